@@ -1,0 +1,476 @@
+/*
+ * FP64 CPU oracle for the force-interpolation adaptive resolution scheme (AdResS).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the CPU baseline of the
+ * benchmark do.  It shares no code, header or constant generator with the HIP
+ * library.  It is deliberately plain: every result is the written-out definition,
+ * summed over *all* other molecules (no neighbour list, no cells, no blocking),
+ * in IEEE double precision, compiled with -ffp-contract=off.
+ *
+ * Paper: "ESPResSo++ 2.0: Advanced methods for multiscale molecular simulation".
+ *   - resolution function lambda(R_alpha): 1 in the atomistic (AT) region, 0 in the
+ *     coarse-grained (CG) region, a smooth squared cosine across the hybrid (HY)
+ *     region, evaluated at each molecule's centre of mass
+ *     (Sec. 2.2 "Force interpolation"; Sec. 2.3 names the squared cosine);
+ *   - Eq. (1): F_ab = l_a l_b F^AT_ab + (1 - l_a l_b) F^CG_ab, with F^AT the sum of
+ *     atom-atom forces between the two molecules and F^CG a force between their
+ *     centres of mass (Sec. 2.2, text following Eq. (1));
+ *   - intramolecular bond terms are not interpolated (Sec. 2.2, last paragraph) and
+ *     are integrated everywhere (Sec. 2.3);
+ *   - force interpolation obeys Newton's third law and has no conserved energy
+ *     (Sec. 2.3, paragraph after Eq. (2)).
+ * Potentials (WCA, FENE, harmonic bonds), sizes and time steps are those of the
+ * synthetic workloads; the readings taken where the paper is silent are listed
+ * at each function.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAX_SITES 8
+
+enum { ORC_OK = 0, ORC_STRETCH = 1, ORC_FENE = 2, ORC_TABLE_RANGE = 4, ORC_NONFINITE = 8 };
+enum { ORC_REGION_AT = 0, ORC_REGION_SLAB = 1, ORC_REGION_SPHERE = 2, ORC_REGION_CG = 3 };
+enum { ORC_CG_WCA = 0, ORC_CG_TABLE = 1, ORC_CG_MLP = 2 };
+enum { ORC_BOND_NONE = 0, ORC_BOND_HARMONIC = 1, ORC_BOND_FENE = 2 };
+
+typedef struct {
+    int32_t n_mol, spm;
+    double box[3];
+    double mass[ORC_MAX_SITES];
+    int32_t region;
+    double center[3], d_at, d_hy;
+    double eps_at, sig_at, rc_at, eps_cg, sig_cg, rc_cg;
+    int32_t cg_kind, bond_kind;
+    double k_bond, r0_bond;
+    int32_t chain_len;
+    double rho_max;
+    /* cubic table of the CG force magnitude: n_knots-1 intervals x {c0,c1,c2,c3} */
+    const float *tab;
+    int32_t tab_n;
+    double tab_lo, tab_hi;
+    /* MLP CG force (FP64 weights, layout W1[H] b1[H] W2[H*H] b2[H] W3[H] b3) */
+    const double *mlp;
+    int32_t mlp_hidden;
+    double mlp_rc, mlp_scale, mlp_taper, mlp_rmin;
+} orc_params;
+
+/* Minimum image of one coordinate difference (periodic orthorhombic box).
+ * Valid for |d| < 1.5 L, which holds for differences of wrapped coordinates. */
+static double orc_mi(double d, double L)
+{
+    if (d > 0.5 * L) d -= L;
+    else if (d < -0.5 * L) d += L;
+    return d;
+}
+
+static double orc_sx(const orc_params *P, const double *x, int dim, int64_t site)
+{
+    int64_t ns = (int64_t)P->n_mol * P->spm;
+    return x[dim * ns + site];
+}
+
+/* Total mass of a molecule, summed left to right over its sites. */
+static double orc_mol_mass(const orc_params *P)
+{
+    double M = 0.0;
+    for (int k = 0; k < P->spm; ++k) M = M + P->mass[k];
+    return M;
+}
+
+/* Centre of mass R_alpha of molecule a (Sec. 2.2: lambda is evaluated at the centre
+ * of mass).  Reading: mass-weighted mean of the minimum-image offsets from site 0,
+ *   R = x0 + ((m1 d1 + m2 d2) + m3 d3) / M,
+ * accumulated left to right, then folded once into [0, L).
+ * Also returns the largest site distance from R (for the stretch check). */
+static void orc_com(const orc_params *P, const double *x, int64_t a, double R[3], double *rho)
+{
+    double M = orc_mol_mass(P);
+    int64_t s0 = a * P->spm;
+    for (int d = 0; d < 3; ++d) {
+        double L = P->box[d];
+        double x0 = orc_sx(P, x, d, s0);
+        double acc = 0.0;
+        for (int k = 1; k < P->spm; ++k)
+            acc = acc + P->mass[k] * orc_mi(orc_sx(P, x, d, s0 + k) - x0, L);
+        double r = x0 + acc / M;
+        if (r >= L) r -= L;
+        else if (r < 0.0) r += L;
+        R[d] = r;
+    }
+    double rmax2 = 0.0;
+    for (int k = 0; k < P->spm; ++k) {
+        double q[3];
+        for (int d = 0; d < 3; ++d) q[d] = orc_mi(orc_sx(P, x, d, s0 + k) - R[d], P->box[d]);
+        double r2 = (q[0] * q[0] + q[1] * q[1]) + q[2] * q[2];
+        if (r2 > rmax2) rmax2 = r2;
+    }
+    *rho = sqrt(rmax2);
+}
+
+/* Resolution function of the distance d from the centre of the AT region
+ * (Sec. 2.2: 1 inside the AT region, 0 in the CG region, smooth in between; Sec. 2.3:
+ * squared cosine).  Reading: w = cos^2(pi (d - d_at) / (2 d_hy)) on d_at < d < d_at + d_hy,
+ * exactly 1 for d <= d_at and exactly 0 for d >= d_at + d_hy. */
+double orc_weight_of_distance(double d, double d_at, double d_hy)
+{
+    if (d <= d_at) return 1.0;
+    if (d >= d_at + d_hy) return 0.0;
+    double c = cos(M_PI * (d - d_at) / (2.0 * d_hy));
+    return c * c;
+}
+
+/* Distance of a centre of mass from the AT region's centre.  Reading: for a slab,
+ * |minimum-image x offset| from the slab's mid-plane; for a sphere, the Euclidean
+ * minimum-image distance from its centre. */
+static double orc_region_distance(const orc_params *P, const double R[3])
+{
+    if (P->region == ORC_REGION_SLAB)
+        return fabs(orc_mi(R[0] - P->center[0], P->box[0]));
+    double q[3];
+    for (int d = 0; d < 3; ++d) q[d] = orc_mi(R[d] - P->center[d], P->box[d]);
+    return sqrt((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]);
+}
+
+static double orc_weight(const orc_params *P, const double R[3])
+{
+    if (P->region == ORC_REGION_AT) return 1.0;
+    if (P->region == ORC_REGION_CG) return 0.0;
+    return orc_weight_of_distance(orc_region_distance(P, R), P->d_at, P->d_hy);
+}
+
+/* Centres of mass (3 x n_mol, SoA), weights (n_mol) and the stretch flag. */
+int orc_weights(const orc_params *P, const double *x, double *com, double *w, double *rho_out)
+{
+    int status = 0;
+    int64_t n = P->n_mol;
+#pragma omp parallel for schedule(static) reduction(| : status)
+    for (int64_t a = 0; a < n; ++a) {
+        double R[3], rho;
+        orc_com(P, x, a, R, &rho);
+        for (int d = 0; d < 3; ++d) com[d * n + a] = R[d];
+        w[a] = orc_weight(P, R);
+        if (rho_out) rho_out[a] = rho;
+        if (P->spm > 1 && rho > P->rho_max) status |= ORC_STRETCH;
+    }
+    return status;
+}
+
+/* Unordered molecule pairs {a < b} whose minimum-image centre-of-mass distance is
+ * below r_list (strict), by brute force over all pairs, in lexicographic order.
+ * The test is r2 < rl2 with r2 = (dx^2 + dy^2) + dz^2 of mi(R_b - R_a).
+ * pairs: 2 x cap int32 (row-major [k][2]).  Returns the pair count (may exceed cap;
+ * only the first cap pairs are written). */
+int64_t orc_pairs(const orc_params *P, const double *com, double rl2, int32_t *pairs, int64_t cap)
+{
+    int64_t n = P->n_mol;
+    int64_t *cnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t a = 0; a < n; ++a) {
+        int64_t c = 0;
+        for (int64_t b = a + 1; b < n; ++b) {
+            double q[3];
+            for (int d = 0; d < 3; ++d) q[d] = orc_mi(com[d * n + b] - com[d * n + a], P->box[d]);
+            double r2 = (q[0] * q[0] + q[1] * q[1]) + q[2] * q[2];
+            if (r2 < rl2) ++c;
+        }
+        cnt[a + 1] = c;
+    }
+    for (int64_t a = 0; a < n; ++a) cnt[a + 1] += cnt[a];
+    int64_t total = cnt[n];
+    if (pairs) {
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t a = 0; a < n; ++a) {
+            int64_t k = cnt[a];
+            for (int64_t b = a + 1; b < n; ++b) {
+                double q[3];
+                for (int d = 0; d < 3; ++d) q[d] = orc_mi(com[d * n + b] - com[d * n + a], P->box[d]);
+                double r2 = (q[0] * q[0] + q[1] * q[1]) + q[2] * q[2];
+                if (r2 < rl2) {
+                    if (k < cap) { pairs[2 * k] = (int32_t)a; pairs[2 * k + 1] = (int32_t)b; }
+                    ++k;
+                }
+            }
+        }
+    }
+    free(cnt);
+    return total;
+}
+
+/* WCA pair term: returns f/r (so the force on the first particle is (f/r) * d with
+ * d = x_first - x_second) and the potential 4 eps (s^12 - s^6) + eps, r2 < rc2. */
+static void orc_wca(double r2, double eps, double sig, double *f_over_r, double *u)
+{
+    double s = (sig * sig) / r2;
+    double s6 = s * s * s;
+    *f_over_r = 24.0 * eps * s6 * (2.0 * s6 - 1.0) / r2;
+    *u = 4.0 * eps * s6 * (s6 - 1.0) + eps;
+}
+
+/* Cubic table of the CG force magnitude: interval k = clamp(floor((r - lo)/h), 0, n-2),
+ * t = (r - lo)/h - k, f = ((c3 t + c2) t + c1) t + c0 with the FP32 coefficients
+ * promoted to FP64.  r < lo raises the table-range flag (reading). */
+double orc_table_eval(const float *tab, int n, double lo, double hi, double r, int *status)
+{
+    double h = (hi - lo) / (double)(n - 1);
+    double u = (r - lo) / h;
+    if (r < lo && status) *status |= ORC_TABLE_RANGE;
+    double kf = floor(u);
+    if (kf < 0.0) kf = 0.0;
+    if (kf > (double)(n - 2)) kf = (double)(n - 2);
+    int k = (int)kf;
+    double t = u - kf;
+    const float *c = tab + 4 * k;
+    return (((double)c[3] * t + (double)c[2]) * t + (double)c[1]) * t + (double)c[0];
+}
+
+static double orc_silu(double z) { return z / (1.0 + exp(-z)); }
+
+/* Learned CG force magnitude (reading of the learned-CG extension):
+ * f(r) = scale * taper(r) * [W3 . silu(W2 silu(W1 x + b1) + b2) + b3], x = r / rc,
+ * taper = 1 below rc - tw, cos^2 ramp to 0 at rc; below r_min the table is used. */
+double orc_mlp_eval(const orc_params *P, double r, int *status)
+{
+    if (r < P->mlp_rmin && P->tab)
+        return orc_table_eval(P->tab, P->tab_n, P->tab_lo, P->tab_hi, r, status);
+    int H = P->mlp_hidden;
+    const double *W1 = P->mlp, *b1 = W1 + H, *W2 = b1 + H, *b2 = W2 + H * H, *W3 = b2 + H, *b3 = W3 + H;
+    double xin = r / P->mlp_rc;
+    double h1[256];
+    for (int k = 0; k < H; ++k) h1[k] = orc_silu(W1[k] * xin + b1[k]);
+    double y = b3[0];
+    for (int o = 0; o < H; ++o) {
+        double z = b2[o];
+        for (int k = 0; k < H; ++k) z += W2[o * H + k] * h1[k];
+        y += W3[o] * orc_silu(z);
+    }
+    double tp = orc_weight_of_distance(r, P->mlp_rc - P->mlp_taper, P->mlp_taper);
+    return P->mlp_scale * tp * y;
+}
+
+/* CG force between centres of mass: returns f/r and the potential (0 for table/MLP). */
+static void orc_cg(const orc_params *P, double r2, double *f_over_r, double *u, int *status)
+{
+    if (P->cg_kind == ORC_CG_WCA) {
+        orc_wca(r2, P->eps_cg, P->sig_cg, f_over_r, u);
+        return;
+    }
+    double r = sqrt(r2);
+    double f = (P->cg_kind == ORC_CG_TABLE)
+                   ? orc_table_eval(P->tab, P->tab_n, P->tab_lo, P->tab_hi, r, status)
+                   : orc_mlp_eval(P, r, status);
+    *f_over_r = f / r;
+    *u = 0.0;
+}
+
+static double orc_norm3(double a, double b, double c) { return sqrt((a * a + b * b) + c * c); }
+
+/* Forces on the sites of molecule a, summed over every other molecule b (no list):
+ *   Eq. (1): ww = w_a w_b;  AT part if ww > 0: ww * sum of atom-atom WCA forces;
+ *   CG part if ww < 1: (1 - ww) * F^CG(R_a - R_b), shared among a's sites by mass
+ *   fraction m_i / M (reading: the paper leaves the distribution to sites open);
+ *   plus the non-interpolated bonded terms.
+ * Writes fa[3][spm], the absolute-sum scale amag[spm] (sum of the magnitudes of all
+ * contributions to each site) and the molecule's half-share of the energies
+ * e[0..2] = U_AT, U_CG, U_bond (each pair term counted half from each side). */
+static int orc_mol_forces(const orc_params *P, const double *x, const double *com, const double *w,
+                          int64_t a, double *fa, double *amag, double e[3])
+{
+    int status = 0;
+    int spm = P->spm;
+    int64_t n = P->n_mol;
+    double M = orc_mol_mass(P);
+    double rcA2 = P->rc_at * P->rc_at, rcC2 = P->rc_cg * P->rc_cg;
+    for (int k = 0; k < 3 * spm; ++k) fa[k] = 0.0;
+    for (int k = 0; k < spm; ++k) amag[k] = 0.0;
+    e[0] = e[1] = e[2] = 0.0;
+    double Ra[3] = {com[a], com[n + a], com[2 * n + a]};
+
+    for (int64_t b = 0; b < n; ++b) {
+        if (b == a) continue;
+        double ww = w[a] * w[b];
+        if (ww > 0.0) {
+            for (int i = 0; i < spm; ++i) {
+                for (int j = 0; j < spm; ++j) {
+                    double d[3];
+                    for (int q = 0; q < 3; ++q)
+                        d[q] = orc_mi(orc_sx(P, x, q, a * spm + i) - orc_sx(P, x, q, b * spm + j), P->box[q]);
+                    double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+                    if (r2 < rcA2) {
+                        double fr, u;
+                        orc_wca(r2, P->eps_at, P->sig_at, &fr, &u);
+                        double c[3] = {ww * fr * d[0], ww * fr * d[1], ww * fr * d[2]};
+                        for (int q = 0; q < 3; ++q) fa[3 * i + q] += c[q];
+                        amag[i] += orc_norm3(c[0], c[1], c[2]);
+                        e[0] += 0.5 * ww * u;
+                    }
+                }
+            }
+        }
+        if (ww < 1.0) {
+            double D[3];
+            for (int q = 0; q < 3; ++q) D[q] = orc_mi(Ra[q] - com[q * n + b], P->box[q]);
+            double r2 = (D[0] * D[0] + D[1] * D[1]) + D[2] * D[2];
+            if (r2 < rcC2) {
+                double fr, u;
+                orc_cg(P, r2, &fr, &u, &status);
+                for (int i = 0; i < spm; ++i) {
+                    double sc = (1.0 - ww) * (P->mass[i] / M) * fr;
+                    double c[3] = {sc * D[0], sc * D[1], sc * D[2]};
+                    for (int q = 0; q < 3; ++q) fa[3 * i + q] += c[q];
+                    amag[i] += orc_norm3(c[0], c[1], c[2]);
+                }
+                e[1] += 0.5 * (1.0 - ww) * u;
+            }
+        }
+    }
+
+    if (P->bond_kind == ORC_BOND_HARMONIC) {
+        /* every pair of sites of the molecule is bonded: U = K/2 (r - b0)^2 */
+        for (int i = 0; i < spm; ++i) {
+            for (int k = 0; k < spm; ++k) {
+                if (k == i) continue;
+                double d[3];
+                for (int q = 0; q < 3; ++q)
+                    d[q] = orc_mi(orc_sx(P, x, q, a * spm + i) - orc_sx(P, x, q, a * spm + k), P->box[q]);
+                double r = orc_norm3(d[0], d[1], d[2]);
+                double fr = -P->k_bond * (r - P->r0_bond) / r;
+                double c[3] = {fr * d[0], fr * d[1], fr * d[2]};
+                for (int q = 0; q < 3; ++q) fa[3 * i + q] += c[q];
+                amag[i] += orc_norm3(c[0], c[1], c[2]);
+                if (k > i) e[2] += 0.5 * P->k_bond * (r - P->r0_bond) * (r - P->r0_bond);
+            }
+        }
+    } else if (P->bond_kind == ORC_BOND_FENE) {
+        /* beads a-1, a, a+1 of one chain (chains are runs of chain_len consecutive
+         * molecules): U = -k R0^2 / 2 * ln(1 - (r / R0)^2) */
+        int64_t chain = a / P->chain_len;
+        for (int side = -1; side <= 1; side += 2) {
+            int64_t b = a + side;
+            if (b < 0 || b >= n || b / P->chain_len != chain) continue;
+            double d[3];
+            for (int q = 0; q < 3; ++q)
+                d[q] = orc_mi(orc_sx(P, x, q, a) - orc_sx(P, x, q, b), P->box[q]);
+            double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+            double R02 = P->r0_bond * P->r0_bond;
+            if (r2 >= R02) { status |= ORC_FENE; continue; }
+            double fr = -P->k_bond / (1.0 - r2 / R02);
+            double c[3] = {fr * d[0], fr * d[1], fr * d[2]};
+            for (int q = 0; q < 3; ++q) fa[q] += c[q];
+            amag[0] += orc_norm3(c[0], c[1], c[2]);
+            e[2] += 0.5 * (-0.5 * P->k_bond * R02 * log(1.0 - r2 / R02));
+        }
+    }
+    for (int k = 0; k < 3 * spm; ++k)
+        if (!isfinite(fa[k])) status |= ORC_NONFINITE;
+    return status;
+}
+
+/* Forces on every site (f: 3 x N_s SoA), absolute-sum scales (amag: N_s) and the
+ * energies e[0..2] = U_AT, U_CG, U_bond.  Returns the status bit mask. */
+int orc_forces(const orc_params *P, const double *x, double *f, double *amag, double *energy)
+{
+    int64_t n = P->n_mol, spm = P->spm, ns = n * spm;
+    double *com = (double *)malloc(sizeof(double) * 3 * n);
+    double *w = (double *)malloc(sizeof(double) * n);
+    double *em = (double *)malloc(sizeof(double) * 3 * n);
+    int status = orc_weights(P, x, com, w, NULL);
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : status)
+    for (int64_t a = 0; a < n; ++a) {
+        double fa[3 * ORC_MAX_SITES], am[ORC_MAX_SITES];
+        status |= orc_mol_forces(P, x, com, w, a, fa, am, em + 3 * a);
+        for (int i = 0; i < spm; ++i) {
+            for (int q = 0; q < 3; ++q) f[q * ns + a * spm + i] = fa[3 * i + q];
+            if (amag) amag[a * spm + i] = am[i];
+        }
+    }
+    if (energy) {
+        energy[0] = energy[1] = energy[2] = 0.0;
+        for (int64_t a = 0; a < n; ++a)
+            for (int k = 0; k < 3; ++k) energy[k] += em[3 * a + k];
+    }
+    free(com); free(w); free(em);
+    return status;
+}
+
+/* Forces on the sites of the selected molecules only (f: [n_sel][3][spm] ... stored as
+ * f[(s * 3 + q) * spm + i]), same definition as orc_forces; O(n_mol) per molecule. */
+int orc_forces_sampled(const orc_params *P, const double *x, const int64_t *sel, int64_t n_sel,
+                       double *f, double *amag)
+{
+    int64_t n = P->n_mol, spm = P->spm;
+    double *com = (double *)malloc(sizeof(double) * 3 * n);
+    double *w = (double *)malloc(sizeof(double) * n);
+    int status = orc_weights(P, x, com, w, NULL);
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : status)
+    for (int64_t s = 0; s < n_sel; ++s) {
+        double fa[3 * ORC_MAX_SITES], am[ORC_MAX_SITES], e[3];
+        status |= orc_mol_forces(P, x, com, w, sel[s], fa, am, e);
+        for (int i = 0; i < spm; ++i) {
+            for (int q = 0; q < 3; ++q) f[(s * 3 + q) * spm + i] = fa[3 * i + q];
+            if (amag) amag[s * spm + i] = am[i];
+        }
+    }
+    free(com); free(w);
+    return status;
+}
+
+double orc_kinetic(const orc_params *P, const double *v)
+{
+    int64_t n = P->n_mol, spm = P->spm, ns = n * spm;
+    double ke = 0.0;
+    for (int64_t s = 0; s < ns; ++s) {
+        double m = P->mass[s % spm];
+        ke += 0.5 * m * ((v[s] * v[s] + v[ns + s] * v[ns + s]) + v[2 * ns + s] * v[2 * ns + s]);
+    }
+    return ke;
+}
+
+/* Velocity Verlet, n_steps of size dt, in place on x, v (f returns F(x_final)):
+ *   v += F dt / (2m); x += v dt; fold each site into [0, L); F = F(x); v += F dt / (2m).
+ * Force interpolation has no conserved energy (Sec. 2.3); energies are diagnostics.
+ * e_out (optional): (n_steps + 1) x 4 rows of U_AT, U_CG, U_bond, KE. */
+int orc_vv(const orc_params *P, double *x, double *v, double *f, double dt, int32_t n_steps,
+           double *e_out)
+{
+    int64_t n = P->n_mol, spm = P->spm, ns = n * spm;
+    double e[3];
+    int status = orc_forces(P, x, f, NULL, e);
+    if (e_out) { e_out[0] = e[0]; e_out[1] = e[1]; e_out[2] = e[2]; e_out[3] = orc_kinetic(P, v); }
+    for (int32_t step = 0; step < n_steps; ++step) {
+        for (int q = 0; q < 3; ++q) {
+            double L = P->box[q];
+            for (int64_t s = 0; s < ns; ++s) {
+                double m = P->mass[s % spm];
+                v[q * ns + s] += f[q * ns + s] * dt / (2.0 * m);
+                double y = x[q * ns + s] + v[q * ns + s] * dt;
+                if (y >= L) y -= L;
+                else if (y < 0.0) y += L;
+                x[q * ns + s] = y;
+            }
+        }
+        status |= orc_forces(P, x, f, NULL, e);
+        for (int q = 0; q < 3; ++q)
+            for (int64_t s = 0; s < ns; ++s)
+                v[q * ns + s] += f[q * ns + s] * dt / (2.0 * P->mass[s % spm]);
+        if (e_out) {
+            double *r = e_out + 4 * (step + 1);
+            r[0] = e[0]; r[1] = e[1]; r[2] = e[2]; r[3] = orc_kinetic(P, v);
+        }
+    }
+    return status;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

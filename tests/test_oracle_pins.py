@@ -1,0 +1,379 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's formulas: they check special values, closed
+forms, invariants, finite-difference gradients of independently computed
+energies, library routines (scipy's periodic k-d tree, NumPy matrix powers) and
+brute force, so that a dropped term, a wrong sign or index or a transposed
+operand in the oracle fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+
+import oracle
+from paper_1806_10841_amd import inputs
+
+EPS = np.finfo(np.float64).eps
+
+
+def _wl(**kw):
+    """A small custom workload (no bonds unless asked)."""
+    base = dict(name="pin", n_mol=2, sites_per_mol=1, box=(20.0, 20.0, 20.0), site_mass=(1.0,),
+                region=inputs.REGION_ALL_AT, center=(10.0, 10.0, 10.0), d_at=2.0, d_hy=3.0,
+                bond_kind=inputs.BOND_NONE, rho_max=0.0)
+    base.update(kw)
+    return inputs.Workload(**base)
+
+
+def _soa(points):
+    return np.ascontiguousarray(np.asarray(points, dtype=np.float64).T)
+
+
+# ---------------------------------------------------------------- resolution function
+class TestWeightFunction:
+    """Sec. 2.2: lambda = 1 in AT, 0 in CG, smooth in HY; Sec. 2.3: squared cosine."""
+
+    @pytest.mark.parametrize("d_at,d_hy", [(4.0, 3.0), (10.0, 5.0), (12.0, 5.0), (0.5, 0.25)])
+    def test_special_values(self, d_at, d_hy):
+        w = lambda d: oracle.weight_of_distance(d, d_at, d_hy)
+        assert w(0.0) == 1.0 and w(d_at) == 1.0
+        assert w(d_at + d_hy) == 0.0 and w(d_at + 2 * d_hy) == 0.0
+        # the midpoint of a squared-cosine ramp is exactly one half (up to cos rounding)
+        assert abs(w(d_at + 0.5 * d_hy) - 0.5) < 4 * EPS
+        # quarter points: cos^2(pi/8) and cos^2(3 pi/8) sum to one
+        assert abs(w(d_at + 0.25 * d_hy) + w(d_at + 0.75 * d_hy) - 1.0) < 8 * EPS
+
+    def test_monotone_and_c1(self):
+        d_at, d_hy = 4.0, 3.0
+        d = np.linspace(d_at - 0.5, d_at + d_hy + 0.5, 4001)
+        w = np.array([oracle.weight_of_distance(q, d_at, d_hy) for q in d])
+        assert np.all(np.diff(w) <= 0.0)
+        # slope at the midpoint of cos^2 over a ramp of width d_hy is -pi / (2 d_hy)
+        h = 1e-6
+        mid = d_at + d_hy / 2
+        slope = (oracle.weight_of_distance(mid + h, d_at, d_hy)
+                 - oracle.weight_of_distance(mid - h, d_at, d_hy)) / (2 * h)
+        assert abs(slope + math.pi / (2 * d_hy)) < 1e-8
+        # C1 at both ends: one-sided slopes vanish (w = 1 - O(h^2), O(h^2))
+        for end, val in ((d_at, 1.0), (d_at + d_hy, 0.0)):
+            for hh in (1e-3, 1e-4):
+                inside = end + hh if val == 1.0 else end - hh
+                assert abs(oracle.weight_of_distance(inside, d_at, d_hy) - val) < 3 * hh * hh
+
+    def test_step_function_limit(self):
+        # d_hy -> 0 gives a sharp interface
+        assert oracle.weight_of_distance(1.0 - 1e-12, 1.0, 0.0) == 1.0
+        assert oracle.weight_of_distance(1.0 + 1e-12, 1.0, 0.0) == 0.0
+
+    def test_slab_and_sphere_through_com(self):
+        """Weights of single-site molecules at chosen positions, periodic slab and sphere."""
+        L = 20.0
+        xs = np.array([10.0, 12.0, 13.5, 15.0, 0.2, 19.9, 6.5, 8.0])
+        pts = np.stack([xs, np.full_like(xs, 3.0), np.full_like(xs, 17.0)], axis=1)
+        wl = _wl(n_mol=len(xs), region=inputs.REGION_SLAB_X)
+        com, w, rho, st = oracle.Model(wl).weights(_soa(pts))
+        assert st == 0
+        np.testing.assert_array_equal(com[0], xs)
+        # |x - 10| = 0, 2, 3.5, 5, 9.8 (through the boundary), 9.9, 3.5, 2
+        assert w[0] == 1.0 and w[1] == 1.0 and w[7] == 1.0
+        assert w[3] == 0.0 and w[4] == 0.0 and w[5] == 0.0
+        assert abs(w[2] - 0.5) < 4 * EPS and abs(w[6] - 0.5) < 4 * EPS
+        # sphere: same distances placed radially along a diagonal
+        u = np.array([1.0, 2.0, 2.0]) / 3.0
+        dist = np.array([0.0, 2.0, 3.5, 5.0 + 1e-9, 6.0])   # 5 itself is rounding-sensitive
+        pts = np.array([10.0, 10.0, 10.0]) + dist[:, None] * u[None, :]
+        wl = _wl(n_mol=len(dist), region=inputs.REGION_SPHERE)
+        _, w, _, _ = oracle.Model(wl).weights(_soa(pts))
+        assert w[0] == 1.0 and w[1] == 1.0 and w[3] == 0.0 and w[4] == 0.0
+        assert abs(w[2] - 0.5) < 1e-14
+
+
+# ---------------------------------------------------------------- centre of mass
+class TestCentreOfMass:
+    def test_straddling_molecule(self):
+        """A 4-site molecule split by the periodic boundary; unequal masses."""
+        L = 10.0
+        pts = [[9.8, 5.0, 5.0], [0.4, 5.0, 5.0], [9.6, 5.5, 5.0], [0.2, 4.5, 5.0]]
+        masses = (1.0, 2.0, 3.0, 2.0)
+        wl = _wl(n_mol=1, sites_per_mol=4, box=(L, L, L), site_mass=masses, rho_max=2.0)
+        com, _, rho, st = oracle.Model(wl).weights(_soa(pts))
+        unwrapped = np.array([9.8, 10.4, 9.6, 10.2])
+        exp_x = np.mod((unwrapped * np.array(masses)).sum() / 8.0, L)
+        assert abs(com[0, 0] - exp_x) < 1e-13
+        assert abs(com[1, 0] - (5.0 + 1.0 * 3 * 0.5 / 8 - 0.5 * 2 / 8)) < 1e-13
+        assert abs(com[2, 0] - 5.0) < 1e-13
+
+    def test_translation_invariance(self):
+        wl = inputs.workload("small_slab")
+        x, _ = inputs.make_state(wl)
+        m = oracle.Model(wl)
+        com0, _, _, _ = m.weights(x)
+        shift = np.array([3.7, -11.2, 40.1])
+        x1 = inputs.wrap_into_box(x + shift[:, None], wl.box)
+        com1, _, _, _ = m.weights(x1)
+        for d in range(3):
+            L = wl.box[d]
+            diff = np.mod(com1[d] - com0[d] - shift[d] + L / 2, L) - L / 2
+            assert np.max(np.abs(diff)) < 1e-12
+
+    def test_stretch_flag(self):
+        wl = _wl(n_mol=1, sites_per_mol=2, site_mass=(1.0, 1.0), rho_max=0.8)
+        # two unit masses 1.7 apart: each site is 0.85 > 0.8 from the centre of mass
+        _, _, rho, st = oracle.Model(wl).weights(_soa([[5, 5, 5], [6.7, 5, 5]]))
+        assert st & oracle.STRETCH and abs(rho[0] - 0.85) < 1e-14
+        _, _, rho, st = oracle.Model(wl).weights(_soa([[5, 5, 5], [6.5, 5, 5]]))
+        assert st == 0 and abs(rho[0] - 0.75) < 1e-14
+
+
+# ---------------------------------------------------------------- pair potentials
+def _two_body(r, **kw):
+    """Force on particle 0 (x component) and total energies for two particles on the x axis."""
+    wl = _wl(**kw)
+    x = _soa([[5.0, 5.0, 5.0], [5.0 + r, 5.0, 5.0]])
+    f, amag, e, st = oracle.Model(wl).forces(x)
+    return f, e, st
+
+
+class TestPairTerms:
+    def test_wca_closed_form(self):
+        f, e, st = _two_body(1.0)
+        assert st == 0
+        assert abs(f[0, 0] + 24.0) < 1e-12 and abs(f[0, 1] - 24.0) < 1e-12   # 24 eps / sigma, repulsive
+        assert abs(e[0] - 1.0) < 1e-12                                         # U(sigma) = eps
+        rc = 2 ** (1 / 6)
+        f, e, _ = _two_body(rc * (1 - 1e-9))
+        assert abs(f[0, 0]) < 1e-6 and abs(e[0]) < 1e-12                      # zero at the cutoff
+        f, e, _ = _two_body(rc * (1 + 1e-12))
+        assert f[0, 0] == 0.0 and e[0] == 0.0
+
+    @pytest.mark.parametrize("kw", [dict(), dict(eps_at=2.0, sig_at=1.3, rc_at=1.3 * 2 ** (1 / 6))])
+    def test_wca_force_is_minus_gradient(self, kw):
+        for r in (0.92, 1.0, 1.05, 1.1):
+            r = r * kw.get("sig_at", 1.0)
+            h = 1e-6
+            _, ep, _ = _two_body(r + h, **kw)
+            _, em, _ = _two_body(r - h, **kw)
+            f, _, _ = _two_body(r, **kw)
+            # particle 1 sits at +r: F_1 = -dU/dr
+            assert abs(f[0, 1] - (-(ep[0] - em[0]) / (2 * h))) < 1e-6 * max(1, abs(f[0, 1]))
+
+    def test_fene_closed_form(self):
+        kw = dict(bond_kind=inputs.BOND_FENE, k_bond=30.0, r0_bond=1.5, chain_len=2)
+        f, e, st = _two_body(1.0, **kw)
+        # FENE at r = 1, R0 = 1.5: 30 * 1 / (1 - 1/2.25) = 54 (attractive); WCA at sigma: 24
+        assert abs(f[0, 1] - (-54.0 + 24.0)) < 1e-11
+        assert abs(e[2] - (-0.5 * 30 * 2.25 * math.log(1 - 1 / 2.25))) < 1e-12
+        for r in (0.9, 1.2, 1.4):
+            h = 1e-6
+            _, ep, _ = _two_body(r + h, **kw)
+            _, em, _ = _two_body(r - h, **kw)
+            f, _, _ = _two_body(r, **kw)
+            assert abs(f[0, 1] + ((ep.sum() - em.sum()) / (2 * h))) < 1e-5 * max(1, abs(f[0, 1]))
+        _, _, st = _two_body(1.5, **kw)
+        assert st & oracle.FENE
+        # beads of different chains are not bonded
+        f, e, _ = _two_body(1.3, bond_kind=inputs.BOND_FENE, k_bond=30.0, r0_bond=1.5, chain_len=1)
+        assert f[0, 0] == 0.0 and e[2] == 0.0
+
+    def test_harmonic_bond(self):
+        wl = _wl(n_mol=1, sites_per_mol=2, site_mass=(1.0, 1.0), bond_kind=inputs.BOND_HARMONIC,
+                 k_bond=400.0, r0_bond=1.0, rho_max=5.0)
+        for r in (0.9, 1.0, 1.13):
+            x = _soa([[5.0, 5.0, 5.0], [5.0 + r, 5.0, 5.0]])
+            f, _, e, _ = oracle.Model(wl).forces(x)
+            assert abs(f[0, 1] - (-400.0 * (r - 1.0))) < 1e-10
+            assert abs(e[2] - 200.0 * (r - 1.0) ** 2) < 1e-10
+
+
+# ---------------------------------------------------------------- pair list
+class TestPairList:
+    @pytest.mark.parametrize("name", ["small_slab", "tiny_slab", "small_cg"])
+    def test_matches_periodic_kdtree(self, name):
+        wl = inputs.workload(name)
+        x, _ = inputs.make_state(wl, seed=123)
+        m = oracle.Model(wl)
+        com, _, _, _ = m.weights(x)
+        rl = m.r_list()
+        mine = m.pairs(com)
+        pts = com.T.copy()
+        tree = cKDTree(pts, boxsize=np.asarray(wl.box))
+        ref = np.array(sorted(tree.query_pairs(rl, output_type="set")), dtype=np.int64)
+        assert len(mine) == len(ref) and len(ref) > 0
+        np.testing.assert_array_equal(mine, ref)
+        # lexicographic, a < b
+        assert np.all(mine[:, 0] < mine[:, 1])
+        key = mine[:, 0].astype(np.int64) * wl.n_mol + mine[:, 1]
+        assert np.all(np.diff(key) > 0)
+
+    def test_list_radius(self):
+        m = oracle.Model(inputs.workload("c2"))
+        assert abs(m.r_list() - (max(2.31 * 2 ** (1 / 6), 2 ** (1 / 6) + 1.6) + 0.3)) < 1e-15
+        m = oracle.Model(inputs.workload("c3"))
+        assert abs(m.r_list() - (2 ** (1 / 6) + 0.3)) < 1e-15
+        m = oracle.Model(inputs.workload("c4"))
+        assert abs(m.r_list() - 3.3) < 1e-15
+
+
+# ---------------------------------------------------------------- Eq. (1) and its limits
+def _energy_grad_check(wl, x, n_check=12, h=1e-6, seed=0):
+    """Central finite differences of the oracle's total potential vs its forces."""
+    m = oracle.Model(wl)
+    f, amag, e, st = m.forces(x)
+    assert st == 0
+    rng = np.random.default_rng(seed)
+    ns = x.shape[1]
+    for _ in range(n_check):
+        q, s = rng.integers(3), rng.integers(ns)
+        xp, xm = x.copy(), x.copy()
+        xp[q, s] += h
+        xm[q, s] -= h
+        ep = m.forces(xp)[2].sum()
+        em = m.forces(xm)[2].sum()
+        fd = -(ep - em) / (2 * h)
+        assert abs(f[q, s] - fd) < 2e-5 * max(1.0, amag[s]), (q, s, f[q, s], fd)
+
+
+class TestLimitsAndEq1:
+    def test_all_at_limit_is_gradient(self):
+        wl = inputs.workload("tiny_slab").with_(region=inputs.REGION_ALL_AT)
+        x, _ = inputs.make_state(wl)
+        _energy_grad_check(wl, x)
+
+    def test_all_cg_limit_is_gradient_with_mass_fractions(self):
+        # unequal masses: the CG force reaches each site with its mass fraction, which is
+        # exactly -dU_CG(R)/dx_i = -(m_i / M) dU/dR
+        wl = inputs.workload("tiny_slab").with_(region=inputs.REGION_ALL_CG, site_mass=(1.0, 2.0, 3.0, 4.0))
+        x, _ = inputs.make_state(wl)
+        _energy_grad_check(wl, x)
+
+    def test_all_cg_net_force_is_com_force(self):
+        """Sum over a molecule's sites = WCA(sigma_cg) between centres of mass."""
+        wl = _wl(n_mol=2, sites_per_mol=4, site_mass=(1.0, 1.0, 1.0, 1.0), region=inputs.REGION_ALL_CG,
+                 rho_max=0.8)
+        rng = np.random.default_rng(3)
+        body = inputs.tetra_positions(np.array([[6.0, 8.0], [6.0, 6.3], [6.0, 6.9]]), rng)
+        f, _, e, st = oracle.Model(wl).forces(body)
+        R0 = body[:, :4].mean(axis=1)
+        R1 = body[:, 4:].mean(axis=1)
+        D = R0 - R1
+        r = np.linalg.norm(D)
+        s6 = (2.31 / r) ** 6
+        fmag = 24 * s6 * (2 * s6 - 1) / r
+        assert r < 2.31 * 2 ** (1 / 6) and fmag > 1.0
+        np.testing.assert_allclose(f[:, :4].sum(axis=1), fmag * D / r, rtol=1e-12, atol=1e-12)
+        # no torque about the centre of mass from the CG part
+        torque = np.cross((body[:, :4] - R0[:, None]).T, f[:, :4].T).sum(axis=0)
+        assert np.max(np.abs(torque)) < 1e-12
+        assert abs(e[1] - (4 * s6 * (s6 - 1) + 1)) < 1e-12
+
+    def test_interpolation_is_affine_in_ww(self):
+        """Eq. (1): two molecules moved together through the hybrid slab; at each position
+        F = ww F_AT + (1 - ww) F_CG with F_AT, F_CG the two limits."""
+        L = 24.0
+        rng = np.random.default_rng(5)
+        body = inputs.tetra_positions(np.array([[0.0, 0.0], [0.0, 1.9], [0.0, 0.4]]), rng)
+        kw = dict(n_mol=2, sites_per_mol=4, site_mass=(1.0, 1.0, 1.0, 1.0), box=(L, L, L),
+                  center=(12.0, 12.0, 12.0), d_at=2.0, d_hy=3.0, rho_max=0.8)
+        seen = set()
+        for xc in np.linspace(12.0, 18.5, 27):
+            x = body + np.array([[xc], [10.0], [10.0]])
+            x = inputs.wrap_into_box(x, (L, L, L))
+            fm, _, _, _ = oracle.Model(_wl(region=inputs.REGION_SLAB_X, **kw)).forces(x)
+            fa, _, _, _ = oracle.Model(_wl(region=inputs.REGION_ALL_AT, **kw)).forces(x)
+            fc, _, _, _ = oracle.Model(_wl(region=inputs.REGION_ALL_CG, **kw)).forces(x)
+            _, w, _, _ = oracle.Model(_wl(region=inputs.REGION_SLAB_X, **kw)).weights(x)
+            ww = w[0] * w[1]
+            seen.add("at" if ww == 1 else "cg" if ww == 0 else "hy")
+            np.testing.assert_allclose(fm, ww * fa + (1 - ww) * fc, rtol=0, atol=1e-12 * np.abs(fa).max())
+        assert seen == {"at", "cg", "hy"}
+
+    def test_newton_third_law_hybrid(self):
+        """Sec. 2.3: force interpolation keeps Newton's third law exactly."""
+        wl = inputs.workload("small_slab")
+        x, _ = inputs.make_state(wl)
+        f, amag, e, st = oracle.Model(wl).forces(x)
+        assert st == 0
+        assert np.all(np.abs(f.sum(axis=1)) < 64 * EPS * amag.sum())
+
+    def test_amag_bounds_force(self):
+        wl = inputs.workload("tiny_slab")
+        x, _ = inputs.make_state(wl)
+        f, amag, _, _ = oracle.Model(wl).forces(x)
+        assert np.all(np.linalg.norm(f, axis=0) <= amag * (1 + 1e-12))
+
+    def test_sampled_equals_full(self):
+        wl = inputs.workload("small_slab")
+        x, _ = inputs.make_state(wl)
+        m = oracle.Model(wl)
+        f, amag, _, _ = m.forces(x)
+        sel = np.array([0, 17, 500, 999])
+        fs, am, _ = m.forces_sampled(x, sel)
+        for k, a in enumerate(sel):
+            np.testing.assert_array_equal(fs[k], f[:, 4 * a:4 * a + 4])
+            np.testing.assert_array_equal(am[k], amag[4 * a:4 * a + 4])
+
+
+# ---------------------------------------------------------------- velocity Verlet
+class TestVelocityVerlet:
+    def test_harmonic_discrete_map(self):
+        """One bond, motion along its axis: VV is the linear map [[1-a/2, dt],[-w2 dt (1-a/4), 1-a/2]]
+        on (q, u) = (r - b0, dr/dt), a = w2 dt^2, w2 = 2K/m (reduced mass m/2)."""
+        K, m, dt, n = 400.0, 1.0, 0.01, 250
+        wl = _wl(n_mol=1, sites_per_mol=2, site_mass=(m, m), bond_kind=inputs.BOND_HARMONIC,
+                 k_bond=K, r0_bond=1.0, rho_max=5.0)
+        q0, u0 = 0.07, -0.3
+        x = _soa([[5.0, 5.0, 5.0], [6.0 + q0, 5.0, 5.0]])
+        v = _soa([[-u0 / 2, 0, 0], [u0 / 2, 0, 0]])
+        xo, vo, _, _, st = oracle.Model(wl).vv(x, v, dt, n)
+        w2 = 2 * K / m
+        a = w2 * dt * dt
+        Mx = np.array([[1 - a / 2, dt], [-w2 * dt * (1 - a / 4), 1 - a / 2]])
+        q, u = np.linalg.matrix_power(Mx, n) @ np.array([q0, u0])
+        assert abs((xo[0, 1] - xo[0, 0] - 1.0) - q) < 1e-11
+        assert abs((vo[0, 1] - vo[0, 0]) - u) < 1e-10
+        # centre of mass does not move
+        assert abs(xo[0].mean() - (5.5 + q0 / 2)) < 1e-12
+
+    def _nve_fluct(self, wl, dt, n):
+        x, v = inputs.make_state(wl)
+        _, _, _, e, st = oracle.Model(wl).vv(x, v, dt, n)
+        tot = e.sum(axis=1)
+        return tot, st
+
+    @pytest.mark.parametrize("region", [inputs.REGION_ALL_AT, inputs.REGION_ALL_CG])
+    def test_nve_limits_dt2(self, region):
+        """Conservative limits (w == 1, w == 0) conserve energy to O(dt^2) under VV."""
+        wl = inputs.workload("tiny_slab").with_(region=region)
+        t1, st = self._nve_fluct(wl, 0.002, 100)
+        t2, _ = self._nve_fluct(wl, 0.001, 200)
+        assert st == 0
+        f1 = np.max(np.abs(t1 - t1[0]))
+        f2 = np.max(np.abs(t2 - t2[0]))
+        assert f1 < 5e-3 * abs(t1[0]) + 1e-2
+        assert 2.5 < f1 / f2 < 6.0, (f1, f2)
+
+    def test_nve_kg_chain(self):
+        wl = inputs.workload("small_kg").with_(n_mol=1000, chain_len=50,
+                                               box=((1000 / 0.85) ** (1 / 3),) * 3)
+        t1, st = self._nve_fluct(wl, 0.002, 50)
+        assert st == 0
+        assert np.max(np.abs(t1 - t1[0])) < 1e-3 * abs(t1[0])
+
+    def test_reversibility(self):
+        wl = inputs.workload("tiny_slab")
+        x, v = inputs.make_state(wl)
+        m = oracle.Model(wl)
+        x1, v1, _, _, _ = m.vv(x, v, 0.005, 40)
+        x2, v2, _, _, _ = m.vv(x1, -v1, 0.005, 40)
+        d = np.mod(x2 - x + 0.5 * wl.box[0], wl.box[0]) - 0.5 * wl.box[0]
+        assert np.max(np.abs(d)) < 1e-9
+        assert np.max(np.abs(v2 + v)) < 1e-8
+
+    def test_momentum_conserved_hybrid(self):
+        wl = inputs.workload("small_slab")
+        x, v = inputs.make_state(wl)
+        _, v1, _, e, st = oracle.Model(wl).vv(x, v, 0.005, 20)
+        assert st == 0
+        assert np.max(np.abs(v1.sum(axis=1) - v.sum(axis=1))) < 1e-10
