@@ -1,0 +1,170 @@
+/*
+ * adres.h -- C ABI of the MI355X (gfx950) adaptive-resolution force-interpolation
+ * library libadres.so.
+ *
+ * The method is the force-interpolation Adaptive Resolution Scheme (AdResS) as
+ * stated in "ESPResSo++ 2.0: Advanced methods for multiscale molecular
+ * simulation", Sec. 2 ("Adaptive resolution simulations"):
+ *   - each molecule alpha carries a resolution value lambda(R_alpha) of its centre
+ *     of mass R_alpha: 1 in the atomistic (AT) region, 0 in the coarse-grained (CG)
+ *     region, smooth across the hybrid (HY) region (Sec. 2.2), a squared cosine
+ *     (Sec. 2.3);
+ *   - the non-bonded force between molecules alpha and beta is Eq. (1):
+ *       F_ab = l_a l_b F^AT_ab + (1 - l_a l_b) F^CG_ab,
+ *     F^AT the sum of atom-atom forces, F^CG a force between centres of mass;
+ *   - intramolecular bonds are not interpolated (Sec. 2.2) and are integrated
+ *     everywhere (Sec. 2.3);
+ *   - neighbours are found with a linked-cell list (Sec. 5, introduction).
+ *
+ * Conventions for every call:
+ *   - Units: lengths in sigma (atom diameter), energies in epsilon, masses in atom
+ *     masses.  Box orthorhombic and periodic, coordinates in [0, L).
+ *   - Arrays named x, v, f are DEVICE pointers to float64 structure-of-arrays of
+ *     shape [3][N_s] (row 0 = x components, row 1 = y, row 2 = z), N_s = n_mol *
+ *     sites_per_mol; molecule a owns sites a*s .. a*s+s-1.  com is [3][n_mol], w is
+ *     [n_mol].  The caller owns these arrays; the library never frees them.
+ *   - The library owns all other state (cell list, neighbour list, Morton-ordered
+ *     copies, tables, network weights, optimiser state).  The caller's site order is
+ *     preserved at the boundary; the Morton order is internal.
+ *   - Work is enqueued on the stream given to adres_create and returns at once,
+ *     except where a call is documented to synchronise (it then waits for that
+ *     stream only).  One context per stream; a context is not thread-safe.
+ *   - Errors: every call returns an adres_status.  Conditions detected on the
+ *     device (non-finite values, a stretched molecule, a broken FENE bond, a table
+ *     lookup below its range) are latched in a device flag word and reported by the
+ *     next synchronising call; adres_last_error gives a message.
+ */
+#ifndef ADRES_H
+#define ADRES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct adres_ctx adres_ctx;
+
+typedef enum {
+    ADRES_OK = 0,
+    ADRES_E_ARG = -1,          /* invalid argument or parameter */
+    ADRES_E_NOMEM = -2,        /* device or host allocation failed */
+    ADRES_E_HIP = -3,          /* a HIP runtime call failed */
+    ADRES_E_BOX = -4,          /* box shorter than twice the list radius */
+    ADRES_E_CAPACITY = -5,     /* neighbour list could not be grown */
+    ADRES_E_STRETCH = -6,      /* a site is farther than rho_max from its centre of mass */
+    ADRES_E_NONFINITE = -7,    /* a force or position is NaN or infinite */
+    ADRES_E_FENE = -8,         /* a FENE bond reached its maximum extension R0 */
+    ADRES_E_TABLE_RANGE = -9,  /* a CG table lookup below the table's first knot */
+    ADRES_E_STATE = -10        /* call out of order (e.g. MLP kind without weights) */
+} adres_status;
+
+enum { ADRES_REGION_ALL_AT = 0, ADRES_REGION_SLAB_X = 1, ADRES_REGION_SPHERE = 2, ADRES_REGION_ALL_CG = 3 };
+enum { ADRES_CG_WCA = 0, ADRES_CG_TABLE = 1, ADRES_CG_MLP = 2, ADRES_CG_MLP_FP8 = 3 };
+enum { ADRES_BOND_NONE = 0, ADRES_BOND_HARMONIC = 1, ADRES_BOND_FENE = 2 };
+
+#define ADRES_MAX_SITES 4
+
+typedef struct {
+    int32_t n_mol;              /* molecules (>= 1) */
+    int32_t sites_per_mol;      /* 1 .. ADRES_MAX_SITES */
+    double  box[3];             /* periodic box lengths */
+    double  site_mass[ADRES_MAX_SITES];
+    int32_t region;             /* ADRES_REGION_*: where the AT region is (Sec. 2.2) */
+    double  center[3];          /* AT region centre (slab: only center[0] is used) */
+    double  d_at, d_hy;         /* AT half-width / radius and hybrid width */
+    double  eps_at, sig_at, rc_at;   /* atom-atom WCA */
+    double  eps_cg, sig_cg, rc_cg;   /* CG centre-of-mass force: WCA parameters and cutoff */
+    int32_t cg_kind;            /* ADRES_CG_* */
+    int32_t bond_kind;          /* ADRES_BOND_* */
+    double  k_bond, r0_bond;    /* harmonic: K, b0;  FENE: k, R0 */
+    int32_t chain_len;          /* FENE: beads per chain (runs of consecutive molecules) */
+    double  r_skin;             /* Verlet skin; the list is rebuilt when a centre of mass
+                                   has moved more than r_skin/2 since the last build */
+    double  rho_max;            /* bound on a site's distance from its centre of mass */
+    int32_t pair_precision;     /* 64: FP64 pair arithmetic; 32: FP32 pair arithmetic on
+                                   FP64-formed displacements, FP64 sums */
+} adres_params;
+
+/* Create a context for one system on the current HIP device.  hip_stream is a
+ * hipStream_t (NULL = default stream).  Validates the parameters (ADRES_E_ARG),
+ * derives the list radius r_list = max(rc_cg, rc_at + 2 rho_max) + r_skin and the
+ * cell grid (ADRES_E_BOX if any box length is below 2 r_list), and allocates the
+ * context's device state.  *out is set only on success. */
+adres_status adres_create(const adres_params *params, void *hip_stream, adres_ctx **out);
+
+/* Release everything the context owns.  Synchronises its stream first.  NULL is a no-op. */
+void adres_destroy(adres_ctx *ctx);
+
+/* Centres of mass and resolution weights (Sec. 2.2, 2.3): com [3][n_mol] and w [n_mol],
+ * device, caller order.  R = x0 + ((m1 d1 + m2 d2) + m3 d3) / M with d_k the
+ * minimum-image offsets of site k from site 0, folded into [0, L); w = 1 for d <= d_at,
+ * cos^2(pi (d - d_at) / (2 d_hy)) inside the hybrid layer, 0 beyond, d the distance of R
+ * from the AT centre (slab: along x).  Asynchronous. */
+adres_status adres_weights(adres_ctx *ctx, const double *x, double *com, double *w);
+
+/* Linked-cell list of the molecules' centres of mass (Sec. 5): cells of edge >= r_list,
+ * ordered along a Morton curve; molecules counted per cell, exclusive-scanned and
+ * scattered, ties inside a cell ordered by caller index.  Reorders the context's
+ * internal copy of the state.  Asynchronous. */
+adres_status adres_build_cells(adres_ctx *ctx, const double *x);
+
+/* Rebuild the cell list for x, then the Verlet list of molecule pairs whose
+ * minimum-image centre-of-mass distance is strictly below r_list.  n_pairs (host,
+ * optional) receives the number of unordered pairs; passing it synchronises.
+ * Synchronises once to check the list capacity (grown and refilled on overflow;
+ * ADRES_E_CAPACITY if growth fails). */
+adres_status adres_build_verlet(adres_ctx *ctx, const double *x, int64_t *n_pairs);
+
+/* Forces of Eq. (1) plus the non-interpolated bonded terms, written to f (device,
+ * caller order).  The atomistic part (ww = w_a w_b > 0) sums WCA over atom pairs with
+ * r < rc_at and weights it by ww; the CG part (ww < 1) is (1 - ww) times the CG force
+ * between centres of mass (r < rc_cg), shared among a molecule's sites by mass
+ * fraction.  energy (device [4], optional): U_AT (ww-weighted), U_CG ((1 - ww)-weighted,
+ * analytic CG only), U_bond, 0.  Builds the lists if none exist and rebuilds them if a
+ * centre of mass moved more than r_skin/2 since the last build; to decide, it
+ * synchronises once before the force kernel is enqueued. */
+adres_status adres_forces(adres_ctx *ctx, const double *x, double *f, double *energy);
+
+/* n_steps of velocity Verlet (v += F dt/2m; x += v dt; fold; F = F(x); v += F dt/2m)
+ * on x, v (device, caller order, updated in place); f receives F(x_final).  The lists
+ * are rebuilt whenever a centre of mass has moved more than r_skin/2.  gamma > 0 adds a
+ * Langevin thermostat at temperature kT with counter-based normal deviates keyed by
+ * (seed, step, site); gamma = 0 is plain NVE.  n_rebuilds (host, optional) receives
+ * the number of list rebuilds.  Synchronises at every rebuild and at the end. */
+adres_status adres_integrate(adres_ctx *ctx, double *x, double *v, double *f, double dt,
+                             int32_t n_steps, double gamma, double kT, uint64_t seed,
+                             int32_t *n_rebuilds);
+
+/* Copy out the current Verlet list as unordered caller-index pairs (a < b), sorted
+ * lexicographically, into pairs_host (host, [cap][2] int32).  *n receives the pair
+ * count even when it exceeds cap.  Synchronises. */
+adres_status adres_get_pairs(adres_ctx *ctx, int32_t *pairs_host, int64_t cap, int64_t *n);
+
+/* Copy out the cell list: cell_start_host [n_cells + 1] (Morton-ordered cells) and
+ * perm_host [n_mol] (caller index of each Morton-ordered slot).  Either may be NULL.
+ * *n_cells receives the cell count.  Synchronises. */
+adres_status adres_get_cells(adres_ctx *ctx, int32_t *cell_start_host, int32_t *perm_host,
+                             int32_t *n_cells);
+
+/* Install a cubic table of the CG force magnitude f(r) (positive = repulsive) on
+ * n_knots equally spaced knots over [r_lo, r_hi]: coef4 (host, float32, [n_knots-1][4])
+ * holds {c0, c1, c2, c3} of interval k, evaluated as ((c3 t + c2) t + c1) t + c0 with
+ * t = (r - r_lo)/h - k.  Copied; used when cg_kind is ADRES_CG_TABLE and as the MLP's
+ * fallback below its r_min.  2 <= n_knots <= 4096. */
+adres_status adres_set_cg_table(adres_ctx *ctx, const float *coef4, int32_t n_knots,
+                                double r_lo, double r_hi);
+
+/* Diagnostic: device time of the force kernels enqueued since the last call, measured
+ * with HIP events on the context's stream when enabled (enable != 0 turns it on, 0 off).
+ * ms (host) receives the summed duration and launches (host) the number of launches.
+ * Synchronises. */
+adres_status adres_kernel_timing(adres_ctx *ctx, int32_t enable, double *ms, int64_t *launches);
+
+/* Message describing the last error of this context (never NULL). */
+const char *adres_last_error(const adres_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADRES_H */

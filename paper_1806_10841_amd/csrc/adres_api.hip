@@ -1,0 +1,591 @@
+// Host side of libadres: context, parameter checks, list-rebuild orchestration
+// and the velocity-Verlet step loop.  Every numerical step runs in the HIP
+// kernels of this directory; the host only allocates, launches and reads the
+// device control word.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "adres_internal.h"
+
+using namespace adres;
+
+struct adres_ctx {
+    adres_params prm{};
+    DevParams P{};
+    Grid G{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    double r_list = 0.0, rl2 = 0.0;
+
+    StateBufs S[2]{};
+    int cur = 0;
+    double *R_ref = nullptr;
+    int *inv_perm = nullptr;
+    int *cell_rank = nullptr, *rank_cell = nullptr;
+    int *count = nullptr, *start = nullptr, *fill = nullptr, *new_from = nullptr;
+    int *nbr = nullptr, *cnt = nullptr;
+    int cap = 0;
+    Ctrl *ctrl = nullptr;
+    Ctrl *ctrl_host = nullptr;
+    double *epart = nullptr;
+    int epart_blocks = 0;
+    float4 *tab = nullptr;
+
+    bool have_state = false;
+    bool list_valid = false;
+    uint64_t step_counter = 0;
+    int last_interval = 8;
+
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    size_t events_used = 0;
+
+    std::string err = "no error";
+};
+
+namespace {
+
+adres_status fail(adres_ctx *c, adres_status st, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return st;
+}
+
+#define HIPCHK(ctx, call)                                                                              \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return fail(ctx, ADRES_E_HIP, std::string(#call " failed: ") + hipGetErrorString(e_));      \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count)
+{
+    return hipMalloc((void **)p, std::max<size_t>(count, 1) * sizeof(T));
+}
+
+uint32_t spread3(uint32_t v)
+{
+    uint32_t r = 0;
+    for (int b = 0; b < 10; ++b) r |= ((v >> b) & 1u) << (3 * b);
+    return r;
+}
+
+// Reads the device control block (synchronises the stream); converts latched error
+// bits into a status and clears them.
+adres_status read_ctrl(adres_ctx *c)
+{
+    HIPCHK(c, hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipGetLastError());
+    int e = c->ctrl_host->err;
+    if (e) {
+        HIPCHK(c, hipMemsetAsync(&c->ctrl->err, 0, sizeof(int), c->stream));
+        if (e & kErrNonFinite) return fail(c, ADRES_E_NONFINITE, "non-finite position or force");
+        if (e & kErrStretch) return fail(c, ADRES_E_STRETCH, "a site is farther than rho_max from its centre of mass");
+        if (e & kErrFene) return fail(c, ADRES_E_FENE, "a FENE bond reached its maximum extension R0");
+        if (e & kErrTableRange) return fail(c, ADRES_E_TABLE_RANGE, "CG table lookup below the first knot");
+    }
+    return ADRES_OK;
+}
+
+adres_status gather(adres_ctx *c, const double *x, const double *v, bool check_disp)
+{
+    launch_gather(c->stream, c->P, x, v, c->S[c->cur], check_disp ? c->R_ref : nullptr, c->ctrl);
+    HIPCHK(c, hipGetLastError());
+    return ADRES_OK;
+}
+
+adres_status resort(adres_ctx *c, bool with_v)
+{
+    const StateBufs &src = c->S[c->cur];
+    const StateBufs &dst = c->S[1 - c->cur];
+    launch_cell_keys(c->stream, c->P, c->G, c->cell_rank, src, c->count);
+    launch_scan_cells(c->stream, c->count, c->G.n_cells, c->start, c->fill);
+    launch_scatter_slots(c->stream, c->P.n_mol, src.key, c->start, c->fill, c->new_from);
+    launch_sort_within_cells(c->stream, c->G.n_cells, c->start, src.perm, c->new_from);
+    launch_permute(c->stream, c->P, c->new_from, src, dst, c->inv_perm, c->R_ref, with_v);
+    HIPCHK(c, hipGetLastError());
+    c->cur = 1 - c->cur;
+    c->list_valid = false;
+    return ADRES_OK;
+}
+
+// Verlet list from the current (sorted) centres; grows the capacity on overflow.
+adres_status build_list(adres_ctx *c)
+{
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        HIPCHK(c, hipMemsetAsync(&c->ctrl->overflow, 0, 2 * sizeof(int), c->stream));
+        launch_list_build(c->stream, c->P, c->G, c->rank_cell, c->cell_rank, c->start, c->S[c->cur], c->rl2,
+                          c->nbr, c->cnt, c->cap, c->ctrl);
+        HIPCHK(c, hipGetLastError());
+        adres_status st = read_ctrl(c);
+        if (st != ADRES_OK) return st;
+        if (!c->ctrl_host->overflow) {
+            c->list_valid = true;
+            return ADRES_OK;
+        }
+        int need = c->ctrl_host->max_count;
+        int new_cap = ((need + need / 4 + 8) + 3) & ~3;
+        HIPCHK(c, hipFree(c->nbr));
+        c->nbr = nullptr;
+        if (dalloc(&c->nbr, (size_t)new_cap * c->P.n_mol) != hipSuccess)
+            return fail(c, ADRES_E_CAPACITY, "could not grow the neighbour list");
+        c->cap = new_cap;
+    }
+    return fail(c, ADRES_E_CAPACITY, "neighbour list capacity did not converge");
+}
+
+ForceArgs force_args(adres_ctx *c)
+{
+    const StateBufs &S = c->S[c->cur];
+    ForceArgs a{};
+    a.P = c->P;
+    a.x = S.x;
+    a.R = S.R;
+    a.w = S.w;
+    a.rho = S.rho;
+    a.nbr = c->nbr;
+    a.cnt = c->cnt;
+    a.cap = c->cap;
+    a.perm = S.perm;
+    a.inv_perm = c->inv_perm;
+    a.ctrl = c->ctrl;
+    return a;
+}
+
+adres_status run_forces(adres_ctx *c, const ForceArgs &a)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        if (c->events_used == c->events.size()) {
+            hipEvent_t p, q;
+            HIPCHK(c, hipEventCreate(&p));
+            HIPCHK(c, hipEventCreate(&q));
+            c->events.emplace_back(p, q);
+        }
+        e0 = c->events[c->events_used].first;
+        e1 = c->events[c->events_used].second;
+        ++c->events_used;
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+    }
+    launch_forces(c->stream, a, c->prm.pair_precision);
+    HIPCHK(c, hipGetLastError());
+    if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
+    return ADRES_OK;
+}
+
+adres_status check_cg_ready(adres_ctx *c)
+{
+    if (c->P.cg_kind == ADRES_CG_TABLE && !c->tab)
+        return fail(c, ADRES_E_STATE, "cg_kind is TABLE but no table was installed");
+    if (c->P.cg_kind == ADRES_CG_MLP || c->P.cg_kind == ADRES_CG_MLP_FP8)
+        return fail(c, ADRES_E_STATE, "MLP CG force requested but no network is installed");
+    return ADRES_OK;
+}
+
+adres_status full_build(adres_ctx *c, const double *x, const double *v)
+{
+    adres_status st = gather(c, x, v, false);
+    if (st != ADRES_OK) return st;
+    st = resort(c, v != nullptr);
+    if (st != ADRES_OK) return st;
+    c->have_state = true;
+    return build_list(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **out)
+{
+    if (!p || !out) return ADRES_E_ARG;
+    const adres_params &q = *p;
+    if (q.n_mol < 1 || q.sites_per_mol < 1 || q.sites_per_mol > ADRES_MAX_SITES) return ADRES_E_ARG;
+    for (int d = 0; d < 3; ++d)
+        if (!(q.box[d] > 0.0) || !std::isfinite(q.box[d])) return ADRES_E_ARG;
+    for (int k = 0; k < q.sites_per_mol; ++k)
+        if (!(q.site_mass[k] > 0.0)) return ADRES_E_ARG;
+    if (q.region < ADRES_REGION_ALL_AT || q.region > ADRES_REGION_ALL_CG) return ADRES_E_ARG;
+    if ((q.region == ADRES_REGION_SLAB_X || q.region == ADRES_REGION_SPHERE) && (q.d_at < 0.0 || q.d_hy < 0.0))
+        return ADRES_E_ARG;
+    if (q.cg_kind < ADRES_CG_WCA || q.cg_kind > ADRES_CG_MLP_FP8) return ADRES_E_ARG;
+    if (q.bond_kind < ADRES_BOND_NONE || q.bond_kind > ADRES_BOND_FENE) return ADRES_E_ARG;
+    if (q.bond_kind == ADRES_BOND_FENE && (q.sites_per_mol != 1 || q.chain_len < 1 || !(q.r0_bond > 0.0)))
+        return ADRES_E_ARG;
+    if (q.region != ADRES_REGION_ALL_CG && !(q.rc_at > 0.0 && q.sig_at > 0.0)) return ADRES_E_ARG;
+    if (q.region != ADRES_REGION_ALL_AT && !(q.rc_cg > 0.0 && q.sig_cg > 0.0)) return ADRES_E_ARG;
+    if (q.r_skin < 0.0 || q.rho_max < 0.0) return ADRES_E_ARG;
+    if (q.sites_per_mol > 1 && !(q.rho_max > 0.0)) return ADRES_E_ARG;
+    if (q.pair_precision != 32 && q.pair_precision != 64) return ADRES_E_ARG;
+
+    adres_ctx *c = new adres_ctx();
+    c->prm = q;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return ADRES_E_HIP;
+    }
+
+    // list radius: largest centre distance at which two molecules can interact, plus skin
+    double r_mol = 0.0;
+    if (q.region != ADRES_REGION_ALL_AT) r_mol = std::max(r_mol, q.rc_cg);
+    if (q.region != ADRES_REGION_ALL_CG) r_mol = std::max(r_mol, q.rc_at + 2.0 * q.rho_max);
+    c->r_list = r_mol + q.r_skin;
+    c->rl2 = c->r_list * c->r_list;
+
+    DevParams &P = c->P;
+    P.n_mol = q.n_mol;
+    P.spm = q.sites_per_mol;
+    P.n_sites = (int64_t)q.n_mol * q.sites_per_mol;
+    P.M = 0.0;
+    for (int k = 0; k < P.spm; ++k) P.M = P.M + q.site_mass[k];
+    for (int k = 0; k < kMaxSites; ++k) {
+        P.mass[k] = k < P.spm ? q.site_mass[k] : 1.0;
+        P.mfrac[k] = k < P.spm ? q.site_mass[k] / P.M : 0.0;
+        P.inv_2m[k] = 1.0 / (2.0 * P.mass[k]);
+    }
+    Grid &G = c->G;
+    G.n_cells = 1;
+    for (int d = 0; d < 3; ++d) {
+        P.box[d] = q.box[d];
+        P.half[d] = 0.5 * q.box[d];
+        P.center[d] = q.center[d];
+        if (q.box[d] < 2.0 * c->r_list) {
+            delete c;
+            return ADRES_E_BOX;
+        }
+        int nd = (int)std::floor(q.box[d] / (c->r_list * (1.0 + 1e-12)));
+        nd = std::max(1, std::min(nd, 1023));
+        G.n[d] = nd;
+        G.inv_len[d] = (double)nd / q.box[d];
+        G.off_lo[d] = nd >= 3 ? -1 : 0;
+        G.off_hi[d] = nd >= 2 ? 1 : 0;
+        G.n_cells *= nd;
+    }
+    P.region = q.region;
+    P.d_at = q.d_at;
+    P.d_hy = q.d_hy;
+    P.d_end = q.d_at + q.d_hy;
+    P.eps_at = q.eps_at;
+    P.sig2_at = q.sig_at * q.sig_at;
+    P.rc_at = q.rc_at;
+    P.rcA2 = q.rc_at * q.rc_at;
+    P.eps_cg = q.eps_cg;
+    P.sig2_cg = q.sig_cg * q.sig_cg;
+    P.rcC2 = q.rc_cg * q.rc_cg;
+    P.cg_kind = q.cg_kind;
+    P.bond_kind = q.bond_kind;
+    P.k_bond = q.k_bond;
+    P.r0_bond = q.r0_bond;
+    P.R02 = q.r0_bond * q.r0_bond;
+    P.chain_len = std::max(1, q.chain_len);
+    P.rho_max = q.rho_max;
+    P.half_skin2 = 0.25 * q.r_skin * q.r_skin;
+
+    // Morton order of the cells
+    std::vector<std::pair<uint32_t, int>> codes(G.n_cells);
+    for (int z = 0; z < G.n[2]; ++z)
+        for (int y = 0; y < G.n[1]; ++y)
+            for (int x = 0; x < G.n[0]; ++x) {
+                int cidx = x + G.n[0] * (y + G.n[1] * z);
+                codes[cidx] = {spread3(x) | (spread3(y) << 1) | (spread3(z) << 2), cidx};
+            }
+    std::sort(codes.begin(), codes.end());
+    std::vector<int> rank(G.n_cells), rcell(G.n_cells);
+    for (int r = 0; r < G.n_cells; ++r) {
+        rank[codes[r].second] = r;
+        rcell[r] = codes[r].second;
+    }
+
+    // neighbour-list capacity: twice the mean count at this density, plus slack
+    double vol = q.box[0] * q.box[1] * q.box[2];
+    double mean = (double)q.n_mol / vol * (4.0 / 3.0) * M_PI * c->rl2 * c->r_list;
+    c->cap = (((int)std::ceil(2.0 * mean) + 16) + 3) & ~3;
+
+    const int n = q.n_mol;
+    const int64_t ns = P.n_sites;
+    bool ok = true;
+    for (int b = 0; b < 2; ++b) {
+        ok = ok && dalloc(&c->S[b].x, 3 * ns) == hipSuccess && dalloc(&c->S[b].v, 3 * ns) == hipSuccess &&
+             dalloc(&c->S[b].R, 3 * (size_t)n) == hipSuccess && dalloc(&c->S[b].w, n) == hipSuccess &&
+             dalloc(&c->S[b].rho, n) == hipSuccess && dalloc(&c->S[b].perm, n) == hipSuccess &&
+             dalloc(&c->S[b].key, n) == hipSuccess;
+    }
+    ok = ok && dalloc(&c->S[0].f, 3 * ns) == hipSuccess;
+    if (ok) c->S[1].f = c->S[0].f;   // forces are recomputed after every reorder
+    ok = ok && dalloc(&c->R_ref, 3 * (size_t)n) == hipSuccess && dalloc(&c->inv_perm, n) == hipSuccess &&
+         dalloc(&c->cell_rank, G.n_cells) == hipSuccess && dalloc(&c->rank_cell, G.n_cells) == hipSuccess &&
+         dalloc(&c->count, G.n_cells) == hipSuccess && dalloc(&c->start, G.n_cells + 1) == hipSuccess &&
+         dalloc(&c->fill, G.n_cells) == hipSuccess && dalloc(&c->new_from, n) == hipSuccess &&
+         dalloc(&c->nbr, (size_t)c->cap * n) == hipSuccess && dalloc(&c->cnt, n) == hipSuccess &&
+         dalloc(&c->ctrl, 1) == hipSuccess;
+    c->epart_blocks = (int)(((int64_t)n * 4 + 255) / 256);
+    ok = ok && dalloc(&c->epart, 3 * (size_t)c->epart_blocks) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&c->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        adres_destroy(c);
+        return ADRES_E_NOMEM;
+    }
+    std::vector<int> ident(n);
+    for (int i = 0; i < n; ++i) ident[i] = i;
+    Ctrl c0{INT_MAX, 0, 0, 0};
+    bool cp = hipMemcpy(c->cell_rank, rank.data(), sizeof(int) * G.n_cells, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(c->rank_cell, rcell.data(), sizeof(int) * G.n_cells, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(c->S[0].perm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(c->S[1].perm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemset(c->count, 0, sizeof(int) * G.n_cells) == hipSuccess &&
+              hipMemcpy(c->ctrl, &c0, sizeof(Ctrl), hipMemcpyHostToDevice) == hipSuccess;
+    if (!cp) {
+        adres_destroy(c);
+        return ADRES_E_HIP;
+    }
+    *out = c;
+    return ADRES_OK;
+}
+
+void adres_destroy(adres_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    else hipDeviceSynchronize();
+    for (int b = 0; b < 2; ++b) {
+        hipFree(c->S[b].x); hipFree(c->S[b].v); hipFree(c->S[b].R); hipFree(c->S[b].w);
+        hipFree(c->S[b].rho); hipFree(c->S[b].perm); hipFree(c->S[b].key);
+    }
+    hipFree(c->S[0].f);
+    hipFree(c->R_ref); hipFree(c->inv_perm); hipFree(c->cell_rank); hipFree(c->rank_cell);
+    hipFree(c->count); hipFree(c->start); hipFree(c->fill); hipFree(c->new_from);
+    hipFree(c->nbr); hipFree(c->cnt); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
+    if (c->ctrl_host) hipHostFree(c->ctrl_host);
+    for (auto &e : c->events) {
+        hipEventDestroy(e.first);
+        hipEventDestroy(e.second);
+    }
+    delete c;
+}
+
+adres_status adres_weights(adres_ctx *c, const double *x, double *com, double *w)
+{
+    if (!c || !x || !com || !w) return fail(c, ADRES_E_ARG, "null argument");
+    launch_weights_caller(c->stream, c->P, x, com, w, c->ctrl);
+    HIPCHK(c, hipGetLastError());
+    return ADRES_OK;
+}
+
+adres_status adres_build_cells(adres_ctx *c, const double *x)
+{
+    if (!c || !x) return fail(c, ADRES_E_ARG, "null argument");
+    adres_status st = gather(c, x, nullptr, false);
+    if (st != ADRES_OK) return st;
+    st = resort(c, false);
+    if (st == ADRES_OK) c->have_state = true;
+    return st;
+}
+
+adres_status adres_build_verlet(adres_ctx *c, const double *x, int64_t *n_pairs)
+{
+    if (!c || !x) return fail(c, ADRES_E_ARG, "null argument");
+    adres_status st = full_build(c, x, nullptr);
+    if (st != ADRES_OK) return st;
+    if (n_pairs) {
+        std::vector<int> h(c->P.n_mol);
+        HIPCHK(c, hipMemcpyAsync(h.data(), c->cnt, sizeof(int) * h.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        int64_t s = 0;
+        for (int v : h) s += v;
+        *n_pairs = s / 2;
+    }
+    return ADRES_OK;
+}
+
+adres_status adres_forces(adres_ctx *c, const double *x, double *f, double *energy)
+{
+    if (!c || !x || !f) return fail(c, ADRES_E_ARG, "null argument");
+    adres_status st = check_cg_ready(c);
+    if (st != ADRES_OK) return st;
+    if (!c->list_valid) {
+        st = full_build(c, x, nullptr);
+        if (st != ADRES_OK) return st;
+    } else {
+        launch_reset_halt(c->stream, c->ctrl);
+        st = gather(c, x, nullptr, true);
+        if (st != ADRES_OK) return st;
+        st = read_ctrl(c);
+        if (st != ADRES_OK) return st;
+        if (c->ctrl_host->halt != INT_MAX) {
+            st = resort(c, false);
+            if (st != ADRES_OK) return st;
+            st = build_list(c);
+            if (st != ADRES_OK) return st;
+        }
+    }
+    ForceArgs a = force_args(c);
+    a.f = f;
+    a.out_perm = c->S[c->cur].perm;
+    a.epart = energy ? c->epart : nullptr;
+    st = run_forces(c, a);
+    if (st != ADRES_OK) return st;
+    if (energy) {
+        launch_energy_reduce(c->stream, c->epart, c->epart_blocks, energy);
+        HIPCHK(c, hipGetLastError());
+    }
+    return ADRES_OK;
+}
+
+adres_status adres_integrate(adres_ctx *c, double *x, double *v, double *f, double dt, int32_t n_steps,
+                             double gamma, double kT, uint64_t seed, int32_t *n_rebuilds)
+{
+    if (!c || !x || !v || !f) return fail(c, ADRES_E_ARG, "null argument");
+    if (n_steps < 0 || !(dt > 0.0) || gamma < 0.0 || (gamma > 0.0 && !(kT >= 0.0)))
+        return fail(c, ADRES_E_ARG, "invalid dt, n_steps, gamma or kT");
+    adres_status st = check_cg_ready(c);
+    if (st != ADRES_OK) return st;
+    st = full_build(c, x, v);
+    if (st != ADRES_OK) return st;
+
+    ForceArgs a0 = force_args(c);
+    a0.f = c->S[c->cur].f;
+    st = run_forces(c, a0);
+    if (st != ADRES_OK) return st;
+
+    int rebuilds = 0;
+    int done = 0;
+    int since = 0;   // steps since the last rebuild
+    while (done < n_steps) {
+        const int chunk = std::min(std::max(2, c->last_interval - since), n_steps - done);
+        launch_reset_halt(c->stream, c->ctrl);
+        for (int k = 0; k < chunk; ++k) {
+            launch_kick_drift(c->stream, c->P, c->S[c->cur], c->R_ref, c->ctrl, k, dt, gamma, kT, seed,
+                              c->step_counter + (uint64_t)(done + k));
+            ForceArgs a = force_args(c);
+            a.f = c->S[c->cur].f;
+            a.v = c->S[c->cur].v;
+            a.dt = dt;
+            a.step = k;
+            a.check_halt = 1;
+            st = run_forces(c, a);
+            if (st != ADRES_OK) return st;
+        }
+        HIPCHK(c, hipGetLastError());
+        st = read_ctrl(c);
+        if (st != ADRES_OK) return st;
+        const int h = c->ctrl_host->halt;
+        if (h == INT_MAX) {
+            done += chunk;
+            since += chunk;
+            continue;
+        }
+        // step h drifted and asked for a rebuild: reorder, rebuild, then finish its force + kick
+        st = resort(c, true);
+        if (st != ADRES_OK) return st;
+        st = build_list(c);
+        if (st != ADRES_OK) return st;
+        ForceArgs a = force_args(c);
+        a.f = c->S[c->cur].f;
+        a.v = c->S[c->cur].v;
+        a.dt = dt;
+        st = run_forces(c, a);
+        if (st != ADRES_OK) return st;
+        ++rebuilds;
+        done += h + 1;
+        c->last_interval = std::max(2, since + h + 1);
+        since = 0;
+    }
+    c->step_counter += (uint64_t)n_steps;
+    launch_scatter_out(c->stream, c->P, c->S[c->cur], x, v, f);
+    HIPCHK(c, hipGetLastError());
+    st = read_ctrl(c);
+    if (n_rebuilds) *n_rebuilds = rebuilds;
+    return st;
+}
+
+adres_status adres_get_pairs(adres_ctx *c, int32_t *pairs_host, int64_t cap, int64_t *n)
+{
+    if (!c || !n || (cap > 0 && !pairs_host)) return fail(c, ADRES_E_ARG, "null argument");
+    if (!c->list_valid) return fail(c, ADRES_E_STATE, "no neighbour list has been built");
+    const int nm = c->P.n_mol;
+    std::vector<int> cnt(nm), perm(nm), nbr((size_t)c->cap * nm);
+    HIPCHK(c, hipMemcpyAsync(cnt.data(), c->cnt, sizeof(int) * nm, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(perm.data(), c->S[c->cur].perm, sizeof(int) * nm, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(nbr.data(), c->nbr, sizeof(int) * nbr.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<std::pair<int, int>> pr;
+    for (int t = 0; t < nm; ++t)
+        for (int k = 0; k < std::min(cnt[t], c->cap); ++k) {
+            int a = perm[t], b = perm[nbr[(size_t)k * nm + t]];
+            if (a < b) pr.emplace_back(a, b);
+        }
+    std::sort(pr.begin(), pr.end());
+    *n = (int64_t)pr.size();
+    for (int64_t i = 0; i < std::min<int64_t>(cap, *n); ++i) {
+        pairs_host[2 * i] = pr[i].first;
+        pairs_host[2 * i + 1] = pr[i].second;
+    }
+    return ADRES_OK;
+}
+
+adres_status adres_get_cells(adres_ctx *c, int32_t *cell_start_host, int32_t *perm_host, int32_t *n_cells)
+{
+    if (!c) return ADRES_E_ARG;
+    if (!c->have_state) return fail(c, ADRES_E_STATE, "no cell list has been built");
+    if (n_cells) *n_cells = c->G.n_cells;
+    if (cell_start_host)
+        HIPCHK(c, hipMemcpyAsync(cell_start_host, c->start, sizeof(int) * (c->G.n_cells + 1), hipMemcpyDeviceToHost,
+                                 c->stream));
+    if (perm_host)
+        HIPCHK(c, hipMemcpyAsync(perm_host, c->S[c->cur].perm, sizeof(int) * c->P.n_mol, hipMemcpyDeviceToHost,
+                                 c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ADRES_OK;
+}
+
+adres_status adres_set_cg_table(adres_ctx *c, const float *coef4, int32_t n_knots, double r_lo, double r_hi)
+{
+    if (!c || !coef4) return fail(c, ADRES_E_ARG, "null argument");
+    if (n_knots < 2 || n_knots > 4096 || !(r_hi > r_lo) || !(r_lo > 0.0))
+        return fail(c, ADRES_E_ARG, "table needs 2..4096 knots on 0 < r_lo < r_hi");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->tab) HIPCHK(c, hipFree(c->tab));
+    c->tab = nullptr;
+    HIPCHK(c, dalloc(&c->tab, (size_t)(n_knots - 1)));
+    HIPCHK(c, hipMemcpy(c->tab, coef4, sizeof(float4) * (n_knots - 1), hipMemcpyHostToDevice));
+    c->P.tab = c->tab;
+    c->P.tab_n = n_knots;
+    c->P.tab_lo = r_lo;
+    c->P.tab_h = (r_hi - r_lo) / (double)(n_knots - 1);
+    return ADRES_OK;
+}
+
+adres_status adres_kernel_timing(adres_ctx *c, int32_t enable, double *ms, int64_t *launches)
+{
+    if (!c) return ADRES_E_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double sum = 0.0;
+    for (size_t i = 0; i < c->events_used; ++i) {
+        float t = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&t, c->events[i].first, c->events[i].second));
+        sum += t;
+    }
+    if (ms) *ms = sum;
+    if (launches) *launches = (int64_t)c->events_used;
+    c->events_used = 0;
+    c->timing = enable != 0;
+    return ADRES_OK;
+}
+
+const char *adres_last_error(const adres_ctx *c)
+{
+    return c ? c->err.c_str() : "null context";
+}
+
+}  // extern "C"

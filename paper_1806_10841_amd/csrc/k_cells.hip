@@ -1,0 +1,229 @@
+// Linked-cell list of molecule centres of mass (Sec. 5, introduction: the
+// linked-cell list behind ESPResSo++'s domain decomposition), rebuilt as a
+// Morton-ordered counting sort on the GPU:
+//   keys (cell -> Morton rank) -> per-cell counts (atomics) -> exclusive scan
+//   (one workgroup, wavefront shuffles) -> scatter -> per-cell insertion sort by
+//   caller index (makes the order a pure function of the positions) -> permute
+//   the state into the new order.
+// and the Verlet list of molecule pairs: every molecule scans the 27 cells around
+// its own (fewer when a dimension has < 3 cells) and keeps the molecules whose
+// minimum-image centre distance is strictly below r_list.  The list is stored
+// column-major (ELL): nbr[k * n_mol + slot], so lanes that handle consecutive
+// slots read consecutive words.
+#include "adres_internal.h"
+
+namespace adres {
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+__global__ __launch_bounds__(kBlock) void k_cell_keys(DevParams P, Grid G, const int *__restrict__ cell_rank,
+                                                      StateBufs S, int *__restrict__ count)
+{
+    int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= P.n_mol) return;
+    const int n = P.n_mol;
+    int cx = cell_coord(S.R[t], G.inv_len[0], G.n[0]);
+    int cy = cell_coord(S.R[n + t], G.inv_len[1], G.n[1]);
+    int cz = cell_coord(S.R[2 * n + t], G.inv_len[2], G.n[2]);
+    int key = cell_rank[cx + G.n[0] * (cy + G.n[1] * cz)];
+    S.key[t] = key;
+    atomicAdd(&count[key], 1);
+}
+
+// Exclusive scan of count[0..n) into start[0..n], one workgroup of 1024 threads:
+// each thread owns a contiguous chunk, chunk sums are scanned with wavefront
+// shuffles and a second pass over the 16 wavefront totals.  Resets count and fill.
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_cells(int *__restrict__ count, int n,
+                                                             int *__restrict__ start, int *__restrict__ fill)
+{
+    __shared__ int wave_tot[kScanThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int chunk = (n + kScanThreads - 1) / kScanThreads;
+    const int lo = min(tid * chunk, n), hi = min(lo + chunk, n);
+    int sum = 0;
+    for (int i = lo; i < hi; ++i) sum += count[i];
+    // inclusive scan within the wavefront
+    int incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) wave_tot[wave] = incl;
+    __syncthreads();
+    if (wave == 0) {
+        int v = lane < kScanThreads / 64 ? wave_tot[lane] : 0;
+        int vi = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            int y = __shfl_up(vi, off, 64);
+            if (lane >= off) vi += y;
+        }
+        if (lane < kScanThreads / 64) wave_tot[lane] = vi - v;   // exclusive wave offsets
+    }
+    __syncthreads();
+    int run = wave_tot[wave] + incl - sum;
+    for (int i = lo; i < hi; ++i) {
+        int c = count[i];
+        start[i] = run;
+        run += c;
+        count[i] = 0;
+        fill[i] = 0;
+    }
+    if (tid == kScanThreads - 1) start[n] = run;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter_slots(int n_mol, const int *__restrict__ key,
+                                                          const int *__restrict__ start, int *__restrict__ fill,
+                                                          int *__restrict__ new_from)
+{
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n_mol) return;
+    int k = key[i];
+    int pos = start[k] + atomicAdd(&fill[k], 1);
+    new_from[pos] = i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort_within_cells(int n_cells, const int *__restrict__ start,
+                                                              const int *__restrict__ perm_old,
+                                                              int *__restrict__ new_from)
+{
+    int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= n_cells) return;
+    int lo = start[c], hi = start[c + 1];
+    for (int i = lo + 1; i < hi; ++i) {
+        int v = new_from[i];
+        int tag = perm_old[v];
+        int j = i - 1;
+        while (j >= lo && perm_old[new_from[j]] > tag) {
+            new_from[j + 1] = new_from[j];
+            --j;
+        }
+        new_from[j + 1] = v;
+    }
+}
+
+template <int SPM>
+__global__ __launch_bounds__(kBlock) void k_permute(DevParams P, const int *__restrict__ new_from, StateBufs src,
+                                                    StateBufs dst, int *__restrict__ inv_perm,
+                                                    double *__restrict__ R_ref, int with_v)
+{
+    int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= P.n_mol) return;
+    const int n = P.n_mol;
+    const int64_t ns = P.n_sites;
+    int i = new_from[t];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+        for (int k = 0; k < SPM; ++k) {
+            dst.x[d * ns + (int64_t)t * SPM + k] = src.x[d * ns + (int64_t)i * SPM + k];
+            if (with_v) dst.v[d * ns + (int64_t)t * SPM + k] = src.v[d * ns + (int64_t)i * SPM + k];
+        }
+        double r = src.R[d * n + i];
+        dst.R[d * n + t] = r;
+        R_ref[d * n + t] = r;
+    }
+    dst.w[t] = src.w[i];
+    dst.rho[t] = src.rho[i];
+    dst.key[t] = src.key[i];
+    int caller = src.perm[i];
+    dst.perm[t] = caller;
+    inv_perm[caller] = t;
+}
+
+__device__ __forceinline__ int wrap_cell(int c, int n)
+{
+    c += n;
+    return c >= n ? (c >= 2 * n ? c - 2 * n : c - n) : c;
+}
+
+__global__ __launch_bounds__(kBlock) void k_list_build(DevParams P, Grid G, const int *__restrict__ rank_cell,
+                                                       const int *__restrict__ cell_rank,
+                                                       const int *__restrict__ start, StateBufs S, double rl2,
+                                                       int *__restrict__ nbr, int *__restrict__ cnt, int cap,
+                                                       Ctrl *ctrl)
+{
+    int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= P.n_mol) return;
+    const int n = P.n_mol;
+    const double Rx = S.R[t], Ry = S.R[n + t], Rz = S.R[2 * n + t];
+    const int c = rank_cell[S.key[t]];
+    const int cx = c % G.n[0], cy = (c / G.n[0]) % G.n[1], cz = c / (G.n[0] * G.n[1]);
+    int k = 0;
+    for (int oz = G.off_lo[2]; oz <= G.off_hi[2]; ++oz) {
+        const int z = wrap_cell(cz + oz, G.n[2]);
+        for (int oy = G.off_lo[1]; oy <= G.off_hi[1]; ++oy) {
+            const int y = wrap_cell(cy + oy, G.n[1]);
+            for (int ox = G.off_lo[0]; ox <= G.off_hi[0]; ++ox) {
+                const int x = wrap_cell(cx + ox, G.n[0]);
+                const int r = cell_rank[x + G.n[0] * (y + G.n[1] * z)];
+                const int hi = start[r + 1];
+                for (int u = start[r]; u < hi; ++u) {
+                    if (u == t) continue;
+                    double dx = mi(S.R[u] - Rx, P.box[0], P.half[0]);
+                    double dy = mi(S.R[n + u] - Ry, P.box[1], P.half[1]);
+                    double dz = mi(S.R[2 * n + u] - Rz, P.box[2], P.half[2]);
+                    if (dist2_exact(dx, dy, dz) < rl2) {
+                        if (k < cap) nbr[(int64_t)k * n + t] = u;
+                        ++k;
+                    }
+                }
+            }
+        }
+    }
+    cnt[t] = k;
+    if (k > cap) {
+        atomicOr(&ctrl->overflow, 1);
+        atomicMax(&ctrl->max_count, k);
+    }
+}
+
+}  // namespace
+
+void launch_cell_keys(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank,
+                      const StateBufs &S, int *count)
+{
+    k_cell_keys<<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, G, cell_rank, S, count);
+}
+
+void launch_scan_cells(hipStream_t s, const int *count, int n_cells, int *start, int *fill)
+{
+    k_scan_cells<<<1, kScanThreads, 0, s>>>(const_cast<int *>(count), n_cells, start, fill);
+}
+
+void launch_scatter_slots(hipStream_t s, int n_mol, const int *key, const int *start, int *fill, int *new_from)
+{
+    k_scatter_slots<<<blocks_for(n_mol), kBlock, 0, s>>>(n_mol, key, start, fill, new_from);
+}
+
+void launch_sort_within_cells(hipStream_t s, int n_cells, const int *start, const int *perm_old, int *new_from)
+{
+    k_sort_within_cells<<<blocks_for(n_cells), kBlock, 0, s>>>(n_cells, start, perm_old, new_from);
+}
+
+void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, const StateBufs &src,
+                    const StateBufs &dst, int *inv_perm, double *R_ref, bool with_v)
+{
+    switch (P.spm) {
+    case 1: k_permute<1><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, new_from, src, dst, inv_perm, R_ref, with_v); break;
+    case 2: k_permute<2><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, new_from, src, dst, inv_perm, R_ref, with_v); break;
+    case 3: k_permute<3><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, new_from, src, dst, inv_perm, R_ref, with_v); break;
+    default: k_permute<4><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, new_from, src, dst, inv_perm, R_ref, with_v); break;
+    }
+}
+
+void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const int *rank_cell,
+                       const int *cell_rank, const int *start, const StateBufs &S, double rl2, int *nbr,
+                       int *cnt, int cap, Ctrl *ctrl)
+{
+    k_list_build<<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, G, rank_cell, cell_rank, start, S, rl2, nbr, cnt, cap,
+                                                       ctrl);
+}
+
+}  // namespace adres

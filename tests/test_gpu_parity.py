@@ -1,0 +1,367 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+Bars (stated per test): centres of mass and neighbour lists bit-exact; weights to
+1e-15 absolute; FP64 forces to 1e-12 and FP32-pair forces to 1e-5, per site
+relative to the oracle's absolute-sum scale A_i (sum of the magnitudes of all
+contributions to site i) and normwise.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1806_10841_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    return torch.device("cuda:0")
+
+
+def _ctx(wl):
+    from paper_1806_10841_amd import binding
+    return binding.Context(wl)
+
+
+def _t(a, dev):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+def assert_forces_close(fg, fo, amag, tol, where=""):
+    err = np.abs(fg - fo).max(axis=0)
+    bad = err > tol * np.maximum(amag, 1e-300)
+    assert not bad.any(), f"{where}: {bad.sum()} sites over tol, worst ratio {(err / np.maximum(amag, 1e-300)).max():.3e}"
+    assert np.linalg.norm(fg - fo) <= tol * np.linalg.norm(fo), where
+
+
+def _morton(cx, cy, cz):
+    def spread(v):
+        r = 0
+        for b in range(10):
+            r |= ((v >> b) & 1) << (3 * b)
+        return r
+    return spread(cx) | (spread(cy) << 1) | (spread(cz) << 2)
+
+
+WORKLOADS_SMALL = ["tiny_slab", "c1", "small_slab", "small_sphere"]
+
+
+@pytest.mark.parametrize("name", WORKLOADS_SMALL + ["small_cg", "small_kg", "c2"])
+def test_weights(dev, name):
+    wl = inputs.workload(name)
+    x, _ = inputs.make_state(wl)
+    com_o, w_o, _, st = oracle.Model(wl).weights(x)
+    ctx = _ctx(wl)
+    com, w = ctx.weights(_t(x, dev))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(com.cpu().numpy(), com_o)            # bit-exact
+    assert np.abs(w.cpu().numpy() - w_o).max() <= 1e-15
+    if wl.region in (inputs.REGION_SLAB_X, inputs.REGION_SPHERE):
+        assert (w_o == 1).any() and (w_o == 0).any() and ((w_o > 0) & (w_o < 1)).any()
+
+
+@pytest.mark.parametrize("name", ["c1", "small_slab", "small_cg", "c2"])
+def test_cell_list_valid(dev, name):
+    """Morton-ordered cell list: a permutation, every molecule in the cell of its centre,
+    cells in Morton order, caller order inside a cell."""
+    wl = inputs.workload(name)
+    x, _ = inputs.make_state(wl)
+    com_o, _, _, _ = oracle.Model(wl).weights(x)
+    ctx = _ctx(wl)
+    ctx.build_cells(_t(x, dev))
+    start, perm = ctx.get_cells()
+    n = wl.n_mol
+    assert sorted(perm.tolist()) == list(range(n))
+    assert start[0] == 0 and start[-1] == n and np.all(np.diff(start) >= 0)
+    rl = oracle.Model(wl).r_list()
+    nc = [int(np.floor(wl.box[d] / (rl * (1 + 1e-12)))) for d in range(3)]
+    cells = np.stack([np.minimum((com_o[d] * (nc[d] / wl.box[d])).astype(np.int64), nc[d] - 1) for d in range(3)])
+    codes = np.array([_morton(*c) for c in cells.T])
+    # rank of each molecule's cell in Morton order
+    order = np.argsort(codes[perm], kind="stable")
+    assert np.all(np.diff(codes[perm]) >= 0), "slots not in Morton order of their cells"
+    same = codes[perm][1:] == codes[perm][:-1]
+    assert np.all(perm[1:][same] > perm[:-1][same]), "caller order inside a cell"
+    del order
+
+
+@pytest.mark.parametrize("name", ["tiny_slab", "c1", "small_slab", "small_sphere", "small_cg", "small_kg", "c2"])
+def test_verlet_pairs_bit_exact(dev, name):
+    wl = inputs.workload(name)
+    x, _ = inputs.make_state(wl)
+    m = oracle.Model(wl)
+    com_o, _, _, _ = m.weights(x)
+    ref = m.pairs(com_o)
+    ctx = _ctx(wl)
+    n = ctx.build_verlet(_t(x, dev))
+    got = ctx.get_pairs()
+    assert n == len(ref) == len(got)
+    np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("name", WORKLOADS_SMALL)
+def test_forces_fp64(dev, name):
+    wl = inputs.workload(name).with_(pair_precision=64)
+    x, _ = inputs.make_state(wl)
+    fo, amag, eo, st = oracle.Model(wl).forces(x)
+    assert st == 0
+    ctx = _ctx(wl)
+    f, e = ctx.forces(_t(x, dev), energy=True)
+    torch.cuda.synchronize()
+    assert_forces_close(f.cpu().numpy(), fo, amag, 1e-12, name)
+    np.testing.assert_allclose(e.cpu().numpy()[:3], eo, rtol=1e-12, atol=1e-12 * np.abs(eo).max())
+
+
+@pytest.mark.parametrize("name", ["small_slab", "small_sphere", "c1"])
+def test_forces_fp32_pairs(dev, name):
+    wl = inputs.workload(name).with_(pair_precision=32)
+    x, _ = inputs.make_state(wl)
+    fo, amag, eo, st = oracle.Model(wl).forces(x)
+    ctx = _ctx(wl)
+    f, e = ctx.forces(_t(x, dev), energy=True)
+    torch.cuda.synchronize()
+    assert_forces_close(f.cpu().numpy(), fo, amag, 1e-5, name)
+    np.testing.assert_allclose(e.cpu().numpy()[:3], eo, rtol=1e-5, atol=1e-5 * np.abs(eo).max())
+
+
+def _sample_by_class(w, per_class, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for mask in (w == 1.0, (w > 0) & (w < 1), w == 0.0):
+        idx = np.flatnonzero(mask)
+        if len(idx):
+            out.append(rng.choice(idx, size=min(per_class, len(idx)), replace=False))
+    return np.sort(np.concatenate(out))
+
+
+def test_forces_c2_full_size_sampled(dev):
+    """64,000 tetrahedra, FP32 pairs: sampled molecules (AT, HY and CG) against the oracle,
+    in the launch configuration the benchmark times; Newton's third law on the whole box."""
+    wl = inputs.workload("c2")
+    x, _ = inputs.make_state(wl)
+    m = oracle.Model(wl)
+    _, w_o, _, _ = m.weights(x)
+    sel = _sample_by_class(w_o, 60, 0)
+    fo, amag, st = m.forces_sampled(x, sel)
+    assert st == 0
+    ctx = _ctx(wl)
+    xt = _t(x, dev)
+    f = ctx.forces(xt).cpu().numpy()
+    fg = np.stack([f[:, 4 * a:4 * a + 4] for a in sel])          # (n_sel, 3, 4)
+    err = np.abs(fg - fo).max(axis=1)                               # (n_sel, 4)
+    assert np.all(err <= 1e-5 * amag), (err / amag).max()
+    assert np.linalg.norm(fg - fo) <= 1e-5 * np.linalg.norm(fo)
+    # Newton's third law (Sec. 2.3): the net force vanishes up to FP32 pair rounding
+    tot = np.abs(f.sum(axis=1))
+    assert np.all(tot <= 1e-5 * np.abs(f).sum(axis=1) / np.sqrt(f.shape[1]))
+
+
+def test_forces_table_cg(dev):
+    """CG force from a 2048-knot cubic table (Hermite fit of the CG WCA built by the oracle)."""
+    from oracle import tables
+    wl = inputs.workload("small_slab").with_(cg_kind=inputs.CG_TABLE, pair_precision=64)
+    coef, lo, hi = tables.hermite_wca_table(wl.sig_cg, wl.eps_cg, wl.rc_cg, 1.5, 3.0, 2048)
+    x, _ = inputs.make_state(wl)
+    fo, amag, _, st = oracle.Model(wl, table=(coef, lo, hi)).forces(x)
+    assert st == 0
+    ctx = _ctx(wl)
+    ctx.set_cg_table(coef, lo, hi)
+    f = ctx.forces(_t(x, dev))
+    torch.cuda.synchronize()
+    assert_forces_close(f.cpu().numpy(), fo, amag, 1e-12, "table fp64")
+    wl32 = wl.with_(pair_precision=32)
+    ctx32 = _ctx(wl32)
+    ctx32.set_cg_table(coef, lo, hi)
+    f32 = ctx32.forces(_t(x, dev))
+    torch.cuda.synchronize()
+    assert_forces_close(f32.cpu().numpy(), fo, amag, 1e-5, "table fp32")
+
+
+def test_forces_deterministic(dev):
+    wl = inputs.workload("c2")
+    x, _ = inputs.make_state(wl)
+    ctx = _ctx(wl)
+    xt = _t(x, dev)
+    f1 = ctx.forces(xt).clone()
+    f2 = ctx.forces(xt).clone()
+    ctx2 = _ctx(wl)
+    f3 = ctx2.forces(xt)
+    assert torch.equal(f1, f2) and torch.equal(f1, f3)
+
+
+def _min_image(d, L):
+    return d - L * np.round(d / L)
+
+
+@pytest.mark.parametrize("name,steps,tol", [("c1", 100, 1e-9), ("tiny_slab", 100, 1e-9),
+                                            ("small_sphere", 40, 1e-9), ("small_kg", 50, 1e-9)])
+def test_integrate_fp64_matches_oracle_vv(dev, name, steps, tol):
+    wl = inputs.workload(name).with_(pair_precision=64)
+    x, v = inputs.make_state(wl)
+    xo, vo, fo, eo, st = oracle.Model(wl).vv(x, v, wl.dt, steps)
+    assert st == 0
+    ctx = _ctx(wl)
+    xt, vt = _t(x, dev), _t(v, dev)
+    ft = torch.empty_like(xt)
+    nreb = ctx.integrate(xt, vt, ft, wl.dt, steps)
+    torch.cuda.synchronize()
+    dx = _min_image(xt.cpu().numpy() - xo, wl.box[0])
+    assert np.abs(dx).max() < tol, np.abs(dx).max()
+    assert np.abs(vt.cpu().numpy() - vo).max() < 100 * tol
+    assert np.abs(ft.cpu().numpy() - fo).max() < 1e4 * tol * max(1.0, np.abs(fo).max())
+    if name == "c1":
+        assert nreb >= 1, "the rebuild path was not exercised"
+
+
+def test_integrate_fp32_pairs_short(dev):
+    """FP32 pair forces, FP64 integration: 10 steps stay within the error the per-step
+    1e-5 force bound allows (|dx| <~ steps^2 dt^2 * 1e-5 * max A / m)."""
+    wl = inputs.workload("small_slab").with_(pair_precision=32)
+    x, v = inputs.make_state(wl)
+    xo, vo, fo, _, _ = oracle.Model(wl).vv(x, v, wl.dt, 10)
+    _, amag, _, _ = oracle.Model(wl).forces(x)
+    ctx = _ctx(wl)
+    xt, vt = _t(x, dev), _t(v, dev)
+    ft = torch.empty_like(xt)
+    ctx.integrate(xt, vt, ft, wl.dt, 10)
+    torch.cuda.synchronize()
+    bound = 10 * 10 * wl.dt * wl.dt * 1e-5 * amag.max()
+    dx = _min_image(xt.cpu().numpy() - xo, wl.box[0])
+    assert np.abs(dx).max() < bound, (np.abs(dx).max(), bound)
+
+
+def test_integrate_c2_momentum_and_rebuilds(dev):
+    """Full-size headline workload: 200 steps, total momentum conserved (Newton's third law,
+    Sec. 2.3), list rebuilt on displacement, no device errors."""
+    wl = inputs.workload("c2")
+    x, v = inputs.make_state(wl)
+    ctx = _ctx(wl)
+    xt, vt = _t(x, dev), _t(v, dev)
+    ft = torch.empty_like(xt)
+    p0 = vt.sum(dim=1).cpu().numpy()
+    nreb = ctx.integrate(xt, vt, ft, wl.dt, 200)
+    torch.cuda.synchronize()
+    p1 = vt.sum(dim=1).cpu().numpy()
+    assert nreb >= 1
+    assert np.abs(p1 - p0).max() < 1e-6 * np.abs(vt.cpu().numpy()).sum(axis=1).max() / 1e3
+    assert torch.isfinite(xt).all() and torch.isfinite(vt).all()
+
+
+def test_langevin_thermostat_temperature(dev):
+    """gamma > 0: the kinetic temperature relaxes to kT (w == 1 tetrahedra)."""
+    wl = inputs.workload("small_slab").with_(region=inputs.REGION_ALL_AT)
+    x, v = inputs.make_state(wl)
+    v = v * 2.0   # start hot: T = 4
+    ctx = _ctx(wl)
+    xt, vt = _t(x, dev), _t(v, dev)
+    ft = torch.empty_like(xt)
+    ctx.integrate(xt, vt, ft, 0.005, 1500, gamma=2.0, kT=1.0, seed=42)
+    temps = []
+    for _ in range(10):
+        ctx.integrate(xt, vt, ft, 0.005, 100, gamma=2.0, kT=1.0, seed=42)
+        ke = 0.5 * (vt ** 2).sum().item()
+        temps.append(2 * ke / (3 * x.shape[1]))
+    assert abs(np.mean(temps) - 1.0) < 0.05, temps
+
+
+# ---------------------------------------------------------------- edge cases and errors
+def test_capacity_growth(dev):
+    """A dense clump overflows the initial list capacity; the list grows and stays exact."""
+    wl = inputs.workload("small_cg")
+    x, _ = inputs.make_state(wl)
+    rng = np.random.default_rng(4)
+    x[:, :300] = 5.0 + rng.uniform(0, 4.0, size=(3, 300))
+    m = oracle.Model(wl)
+    com_o, _, _, _ = m.weights(x)
+    ref = m.pairs(com_o)
+    ctx = _ctx(wl.with_(cg_kind=inputs.CG_WCA))
+    n = ctx.build_verlet(_t(x, dev))
+    np.testing.assert_array_equal(ctx.get_pairs(), ref)
+    assert n == len(ref)
+
+
+def test_error_stretch(dev):
+    from paper_1806_10841_amd import binding
+    wl = inputs.workload("c1")
+    x, _ = inputs.make_state(wl)
+    x[0, 5] += 0.9
+    ctx = _ctx(wl)
+    with pytest.raises(binding.AdresError) as ei:
+        ctx.forces(_t(x, dev))
+        ctx.build_verlet(_t(x, dev))
+    assert ei.value.status == -6
+
+
+def test_error_nonfinite(dev):
+    from paper_1806_10841_amd import binding
+    wl = inputs.workload("c1")
+    x, _ = inputs.make_state(wl)
+    x[1, 17] = np.nan
+    ctx = _ctx(wl)
+    with pytest.raises(binding.AdresError) as ei:
+        ctx.build_verlet(_t(x, dev))
+    assert ei.value.status in (-7, -6)
+
+
+def test_error_fene(dev):
+    from paper_1806_10841_amd import binding
+    wl = inputs.workload("small_kg")
+    x, _ = inputs.make_state(wl)
+    x[0, 1] = x[0, 0] + 1.55 if x[0, 0] + 1.55 < wl.box[0] else x[0, 0] - 1.55
+    x[1, 1], x[2, 1] = x[1, 0], x[2, 0]
+    ctx = _ctx(wl)
+    ctx.forces(_t(x, dev))
+    with pytest.raises(binding.AdresError) as ei:
+        ctx.build_verlet(_t(x, dev))
+    assert ei.value.status == -8
+
+
+def test_error_table_range(dev):
+    from paper_1806_10841_amd import binding
+    from oracle import tables
+    wl = inputs.workload("small_cg").with_(cg_kind=inputs.CG_TABLE, rc_cg=3.0)
+    coef, lo, hi = tables.hermite_wca_table(wl.sig_cg, wl.eps_cg, 2.31 * 2 ** (1 / 6), 2.9, 3.0, 64)
+    x, _ = inputs.make_state(wl)
+    ctx = _ctx(wl)
+    ctx.set_cg_table(coef, lo, hi)
+    ctx.forces(_t(x, dev))
+    with pytest.raises(binding.AdresError) as ei:
+        ctx.build_verlet(_t(x, dev))
+    assert ei.value.status == -9
+
+
+def test_error_table_missing(dev):
+    from paper_1806_10841_amd import binding
+    wl = inputs.workload("small_cg").with_(cg_kind=inputs.CG_TABLE)
+    x, _ = inputs.make_state(wl)
+    ctx = _ctx(wl)
+    with pytest.raises(binding.AdresError) as ei:
+        ctx.forces(_t(x, dev))
+    assert ei.value.status == -10
+
+
+def test_error_box_and_args(dev):
+    from paper_1806_10841_amd import binding
+    with pytest.raises(binding.AdresError) as ei:
+        _ctx(inputs.workload("c1").with_(box=(5.0, 17.1, 17.1)))
+    assert ei.value.status == -4
+    with pytest.raises(binding.AdresError) as ei:
+        _ctx(inputs.workload("c1").with_(pair_precision=16))
+    assert ei.value.status == -1
+
+
+def test_single_molecule_and_two_cells(dev):
+    """Degenerate sizes: one molecule (no pairs) and a box of 2 cells per dimension."""
+    wl = inputs.workload("tiny_slab").with_(n_mol=1, box=(8.6, 8.6, 8.6))
+    x, _ = inputs.make_state(inputs.workload("tiny_slab"))
+    x1 = np.ascontiguousarray(x[:, :4])
+    fo, amag, _, _ = oracle.Model(wl).forces(x1)
+    ctx = _ctx(wl)
+    assert ctx.build_verlet(_t(x1, dev)) == 0
+    f = ctx.forces(_t(x1, dev))
+    torch.cuda.synchronize()
+    assert_forces_close(f.cpu().numpy(), fo, amag, 1e-12, "single molecule")
