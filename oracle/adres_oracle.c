@@ -212,6 +212,15 @@ static void orc_wca(double r2, double eps, double sig, double *f_over_r, double 
     *u = 4.0 * eps * s6 * (s6 - 1.0) + eps;
 }
 
+/* Magnitude scale of a WCA pair term before cancellation: |48 eps s^12| + |24 eps s^6|,
+ * divided by r^2 like f/r (the two terms of the force cancel at the cutoff). */
+static double orc_wca_scale(double r2, double eps, double sig)
+{
+    double s = (sig * sig) / r2;
+    double s6 = s * s * s;
+    return 24.0 * eps * s6 * (2.0 * s6 + 1.0) / r2;
+}
+
 /* Cubic table of the CG force magnitude: interval k = clamp(floor((r - lo)/h), 0, n-2),
  * t = (r - lo)/h - k, f = ((c3 t + c2) t + c1) t + c0 with the FP32 coefficients
  * promoted to FP64.  r < lo raises the table-range flag (reading). */
@@ -227,6 +236,19 @@ double orc_table_eval(const float *tab, int n, double lo, double hi, double r, i
     double t = u - kf;
     const float *c = tab + 4 * k;
     return (((double)c[3] * t + (double)c[2]) * t + (double)c[1]) * t + (double)c[0];
+}
+
+/* Sum of the magnitudes of the four Horner terms of a table lookup. */
+static double orc_table_scale(const float *tab, int n, double lo, double hi, double r)
+{
+    double h = (hi - lo) / (double)(n - 1);
+    double u = (r - lo) / h;
+    double kf = floor(u);
+    if (kf < 0.0) kf = 0.0;
+    if (kf > (double)(n - 2)) kf = (double)(n - 2);
+    double t = u - kf;
+    const float *c = tab + 4 * (int)kf;
+    return fabs((double)c[0]) + fabs((double)c[1] * t) + fabs((double)c[2] * t * t) + fabs((double)c[3] * t * t * t);
 }
 
 static double orc_silu(double z) { return z / (1.0 + exp(-z)); }
@@ -270,14 +292,29 @@ static void orc_cg(const orc_params *P, double r2, double *f_over_r, double *u, 
 
 static double orc_norm3(double a, double b, double c) { return sqrt((a * a + b * b) + c * c); }
 
+/* Term-magnitude scale of the CG force, divided by r like f/r. */
+static double orc_cg_scale(const orc_params *P, double r2, double f_over_r)
+{
+    if (P->cg_kind == ORC_CG_WCA) return orc_wca_scale(r2, P->eps_cg, P->sig_cg);
+    double r = sqrt(r2);
+    if (P->cg_kind == ORC_CG_TABLE) return orc_table_scale(P->tab, P->tab_n, P->tab_lo, P->tab_hi, r) / r;
+    return fabs(f_over_r);
+}
+
 /* Forces on the sites of molecule a, summed over every other molecule b (no list):
  *   Eq. (1): ww = w_a w_b;  AT part if ww > 0: ww * sum of atom-atom WCA forces;
  *   CG part if ww < 1: (1 - ww) * F^CG(R_a - R_b), shared among a's sites by mass
  *   fraction m_i / M (reading: the paper leaves the distribution to sites open);
  *   plus the non-interpolated bonded terms.
- * Writes fa[3][spm], the absolute-sum scale amag[spm] (sum of the magnitudes of all
- * contributions to each site) and the molecule's half-share of the energies
- * e[0..2] = U_AT, U_CG, U_bond (each pair term counted half from each side). */
+ * Writes fa[3][spm], the absolute-sum scale amag[spm] and the molecule's half-share
+ * of the energies e[0..2] = U_AT, U_CG, U_bond (each pair term counted half from
+ * each side).  amag sums, over all contributions to a site, the magnitudes of the
+ * terms each contribution is made of before they cancel: 24 eps s^6 (2 s^6 + 1)/r
+ * for a WCA pair (the two terms cancel at the cutoff), (1 + ww) for the CG share
+ * (1 - ww cancels as ww -> 1), K (r + b0) for a harmonic bond (r - b0 cancels at
+ * rest), the four Horner terms of a table lookup, |f| (1 + r^2/R0^2)/(1 - r^2/R0^2)
+ * for FENE; it bounds the rounding error of any evaluation order of the same
+ * formulas, including sites whose net force is pure rounding noise. */
 static int orc_mol_forces(const orc_params *P, const double *x, const double *com, const double *w,
                           int64_t a, double *fa, double *amag, double e[3])
 {
@@ -306,7 +343,7 @@ static int orc_mol_forces(const orc_params *P, const double *x, const double *co
                         orc_wca(r2, P->eps_at, P->sig_at, &fr, &u);
                         double c[3] = {ww * fr * d[0], ww * fr * d[1], ww * fr * d[2]};
                         for (int q = 0; q < 3; ++q) fa[3 * i + q] += c[q];
-                        amag[i] += orc_norm3(c[0], c[1], c[2]);
+                        amag[i] += ww * orc_wca_scale(r2, P->eps_at, P->sig_at) * sqrt(r2);
                         e[0] += 0.5 * ww * u;
                     }
                 }
@@ -319,11 +356,12 @@ static int orc_mol_forces(const orc_params *P, const double *x, const double *co
             if (r2 < rcC2) {
                 double fr, u;
                 orc_cg(P, r2, &fr, &u, &status);
+                double scale = (1.0 + ww) * orc_cg_scale(P, r2, fr) * sqrt(r2);
                 for (int i = 0; i < spm; ++i) {
                     double sc = (1.0 - ww) * (P->mass[i] / M) * fr;
                     double c[3] = {sc * D[0], sc * D[1], sc * D[2]};
                     for (int q = 0; q < 3; ++q) fa[3 * i + q] += c[q];
-                    amag[i] += orc_norm3(c[0], c[1], c[2]);
+                    amag[i] += (P->mass[i] / M) * scale;
                 }
                 e[1] += 0.5 * (1.0 - ww) * u;
             }
@@ -342,7 +380,7 @@ static int orc_mol_forces(const orc_params *P, const double *x, const double *co
                 double fr = -P->k_bond * (r - P->r0_bond) / r;
                 double c[3] = {fr * d[0], fr * d[1], fr * d[2]};
                 for (int q = 0; q < 3; ++q) fa[3 * i + q] += c[q];
-                amag[i] += orc_norm3(c[0], c[1], c[2]);
+                amag[i] += P->k_bond * (r + P->r0_bond);
                 if (k > i) e[2] += 0.5 * P->k_bond * (r - P->r0_bond) * (r - P->r0_bond);
             }
         }
@@ -362,7 +400,7 @@ static int orc_mol_forces(const orc_params *P, const double *x, const double *co
             double fr = -P->k_bond / (1.0 - r2 / R02);
             double c[3] = {fr * d[0], fr * d[1], fr * d[2]};
             for (int q = 0; q < 3; ++q) fa[q] += c[q];
-            amag[0] += orc_norm3(c[0], c[1], c[2]);
+            amag[0] += orc_norm3(c[0], c[1], c[2]) * (1.0 + r2 / R02) / (1.0 - r2 / R02);
             e[2] += 0.5 * (-0.5 * P->k_bond * R02 * log(1.0 - r2 / R02));
         }
     }

@@ -204,7 +204,7 @@ def workload(name: str) -> Workload:
     if name == "tiny_slab":      # 4^3 tetrahedra, every resolution present
         L = 4 * 2.15
         return Workload("tiny_slab", 64, 4, (L, L, L), tetra_mass, REGION_SLAB_X, (L / 2, L / 2, L / 2),
-                        1.2, 1.5, pair_precision=64, n_steps=20, seed=7)
+                        1.05, 1.5, pair_precision=64, n_steps=20, seed=7)
     if name == "small_slab":     # 10^3 tetrahedra at C2 density
         L = (1000 / 0.1) ** (1.0 / 3.0)
         return Workload("small_slab", 1000, 4, (L, L, L), tetra_mass, REGION_SLAB_X,
