@@ -25,9 +25,12 @@ struct adres_ctx {
     int device = 0;
     double r_list = 0.0, rl2 = 0.0;
 
+    // two buffer sets; positions (x, Rw, rho) and order (v, perm, key) flip independently:
+    // a fused step flips the positions, a reorder flips both.
     StateBufs S[2]{};
-    int cur = 0;
-    double *R_ref = nullptr;
+    int pos = 0, ord = 0;
+    double *f = nullptr;     // forces, Morton order
+    double4 *R_ref = nullptr;
     int *inv_perm = nullptr;
     int *cell_rank = nullptr, *rank_cell = nullptr;
     int *count = nullptr, *start = nullptr, *fill = nullptr, *new_from = nullptr;
@@ -58,6 +61,19 @@ adres_status fail(adres_ctx *c, adres_status st, const std::string &msg)
     if (c) c->err = msg;
     return st;
 }
+
+StateBufs view(const adres_ctx *c, int pos, int ord)
+{
+    StateBufs b;
+    b.x = c->S[pos].x;
+    b.Rw = c->S[pos].Rw;
+    b.rho = c->S[pos].rho;
+    b.v = c->S[ord].v;
+    b.perm = c->S[ord].perm;
+    b.key = c->S[ord].key;
+    return b;
+}
+StateBufs cur(const adres_ctx *c) { return view(c, c->pos, c->ord); }
 
 #define HIPCHK(ctx, call)                                                                              \
     do {                                                                                               \
@@ -99,22 +115,23 @@ adres_status read_ctrl(adres_ctx *c)
 
 adres_status gather(adres_ctx *c, const double *x, const double *v, bool check_disp)
 {
-    launch_gather(c->stream, c->P, x, v, c->S[c->cur], check_disp ? c->R_ref : nullptr, c->ctrl);
+    launch_gather(c->stream, c->P, x, v, cur(c), check_disp ? c->R_ref : nullptr, c->ctrl);
     HIPCHK(c, hipGetLastError());
     return ADRES_OK;
 }
 
 adres_status resort(adres_ctx *c, bool with_v)
 {
-    const StateBufs &src = c->S[c->cur];
-    const StateBufs &dst = c->S[1 - c->cur];
-    launch_cell_keys(c->stream, c->P, c->G, c->cell_rank, src, c->count);
+    const StateBufs src = cur(c);
+    const StateBufs dst = view(c, 1 - c->pos, 1 - c->ord);
+    launch_cell_keys(c->stream, c->P, c->G, c->cell_rank, src.Rw, src.key, c->count);
     launch_scan_cells(c->stream, c->count, c->G.n_cells, c->start, c->fill);
     launch_scatter_slots(c->stream, c->P.n_mol, src.key, c->start, c->fill, c->new_from);
     launch_sort_within_cells(c->stream, c->G.n_cells, c->start, src.perm, c->new_from);
     launch_permute(c->stream, c->P, c->new_from, src, dst, c->inv_perm, c->R_ref, with_v);
     HIPCHK(c, hipGetLastError());
-    c->cur = 1 - c->cur;
+    c->pos = 1 - c->pos;
+    c->ord = 1 - c->ord;
     c->list_valid = false;
     return ADRES_OK;
 }
@@ -124,7 +141,8 @@ adres_status build_list(adres_ctx *c)
 {
     for (int attempt = 0; attempt < 4; ++attempt) {
         HIPCHK(c, hipMemsetAsync(&c->ctrl->overflow, 0, 2 * sizeof(int), c->stream));
-        launch_list_build(c->stream, c->P, c->G, c->rank_cell, c->cell_rank, c->start, c->S[c->cur], c->rl2,
+        const StateBufs b = cur(c);
+        launch_list_build(c->stream, c->P, c->G, c->rank_cell, c->cell_rank, c->start, b.Rw, b.key, c->rl2,
                           c->nbr, c->cnt, c->cap, c->ctrl);
         HIPCHK(c, hipGetLastError());
         adres_status st = read_ctrl(c);
@@ -134,7 +152,7 @@ adres_status build_list(adres_ctx *c)
             return ADRES_OK;
         }
         int need = c->ctrl_host->max_count;
-        int new_cap = ((need + need / 4 + 8) + 3) & ~3;
+        int new_cap = ((need + need / 4 + 8) + 15) & ~15;
         HIPCHK(c, hipFree(c->nbr));
         c->nbr = nullptr;
         if (dalloc(&c->nbr, (size_t)new_cap * c->P.n_mol) != hipSuccess)
@@ -146,12 +164,11 @@ adres_status build_list(adres_ctx *c)
 
 ForceArgs force_args(adres_ctx *c)
 {
-    const StateBufs &S = c->S[c->cur];
+    const StateBufs S = cur(c);
     ForceArgs a{};
     a.P = c->P;
     a.x = S.x;
-    a.R = S.R;
-    a.w = S.w;
+    a.Rw = S.Rw;
     a.rho = S.rho;
     a.nbr = c->nbr;
     a.cnt = c->cnt;
@@ -159,6 +176,7 @@ ForceArgs force_args(adres_ctx *c)
     a.perm = S.perm;
     a.inv_perm = c->inv_perm;
     a.ctrl = c->ctrl;
+    a.mode = kModeForce;
     return a;
 }
 
@@ -310,26 +328,24 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     // neighbour-list capacity: twice the mean count at this density, plus slack
     double vol = q.box[0] * q.box[1] * q.box[2];
     double mean = (double)q.n_mol / vol * (4.0 / 3.0) * M_PI * c->rl2 * c->r_list;
-    c->cap = (((int)std::ceil(2.0 * mean) + 16) + 3) & ~3;
+    c->cap = (((int)std::ceil(2.0 * mean) + 16) + 15) & ~15;
 
     const int n = q.n_mol;
     const int64_t ns = P.n_sites;
     bool ok = true;
     for (int b = 0; b < 2; ++b) {
         ok = ok && dalloc(&c->S[b].x, 3 * ns) == hipSuccess && dalloc(&c->S[b].v, 3 * ns) == hipSuccess &&
-             dalloc(&c->S[b].R, 3 * (size_t)n) == hipSuccess && dalloc(&c->S[b].w, n) == hipSuccess &&
-             dalloc(&c->S[b].rho, n) == hipSuccess && dalloc(&c->S[b].perm, n) == hipSuccess &&
-             dalloc(&c->S[b].key, n) == hipSuccess;
+             dalloc(&c->S[b].Rw, n) == hipSuccess && dalloc(&c->S[b].rho, n) == hipSuccess &&
+             dalloc(&c->S[b].perm, n) == hipSuccess && dalloc(&c->S[b].key, n) == hipSuccess;
     }
-    ok = ok && dalloc(&c->S[0].f, 3 * ns) == hipSuccess;
-    if (ok) c->S[1].f = c->S[0].f;   // forces are recomputed after every reorder
-    ok = ok && dalloc(&c->R_ref, 3 * (size_t)n) == hipSuccess && dalloc(&c->inv_perm, n) == hipSuccess &&
+    ok = ok && dalloc(&c->f, 3 * ns) == hipSuccess;
+    ok = ok && dalloc(&c->R_ref, (size_t)n) == hipSuccess && dalloc(&c->inv_perm, n) == hipSuccess &&
          dalloc(&c->cell_rank, G.n_cells) == hipSuccess && dalloc(&c->rank_cell, G.n_cells) == hipSuccess &&
          dalloc(&c->count, G.n_cells) == hipSuccess && dalloc(&c->start, G.n_cells + 1) == hipSuccess &&
          dalloc(&c->fill, G.n_cells) == hipSuccess && dalloc(&c->new_from, n) == hipSuccess &&
          dalloc(&c->nbr, (size_t)c->cap * n) == hipSuccess && dalloc(&c->cnt, n) == hipSuccess &&
          dalloc(&c->ctrl, 1) == hipSuccess;
-    c->epart_blocks = (int)(((int64_t)n * 4 + 255) / 256);
+    c->epart_blocks = force_blocks(n);
     ok = ok && dalloc(&c->epart, 3 * (size_t)c->epart_blocks) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&c->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) == hipSuccess;
     if (!ok) {
@@ -359,10 +375,10 @@ void adres_destroy(adres_ctx *c)
     if (c->stream) hipStreamSynchronize(c->stream);
     else hipDeviceSynchronize();
     for (int b = 0; b < 2; ++b) {
-        hipFree(c->S[b].x); hipFree(c->S[b].v); hipFree(c->S[b].R); hipFree(c->S[b].w);
+        hipFree(c->S[b].x); hipFree(c->S[b].v); hipFree(c->S[b].Rw);
         hipFree(c->S[b].rho); hipFree(c->S[b].perm); hipFree(c->S[b].key);
     }
-    hipFree(c->S[0].f);
+    hipFree(c->f);
     hipFree(c->R_ref); hipFree(c->inv_perm); hipFree(c->cell_rank); hipFree(c->rank_cell);
     hipFree(c->count); hipFree(c->start); hipFree(c->fill); hipFree(c->new_from);
     hipFree(c->nbr); hipFree(c->cnt); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
@@ -431,7 +447,7 @@ adres_status adres_forces(adres_ctx *c, const double *x, double *f, double *ener
     }
     ForceArgs a = force_args(c);
     a.f = f;
-    a.out_perm = c->S[c->cur].perm;
+    a.out_perm = cur(c).perm;
     a.epart = energy ? c->epart : nullptr;
     st = run_forces(c, a);
     if (st != ADRES_OK) return st;
@@ -453,56 +469,82 @@ adres_status adres_integrate(adres_ctx *c, double *x, double *v, double *f, doub
     st = full_build(c, x, v);
     if (st != ADRES_OK) return st;
 
+    // F(x_0) into the Morton-ordered force buffer
     ForceArgs a0 = force_args(c);
-    a0.f = c->S[c->cur].f;
+    a0.f = c->f;
     st = run_forces(c, a0);
     if (st != ADRES_OK) return st;
 
+    // Kernel g (0 <= g <= n_steps) finishes/starts steps around time g:
+    //   g = 0:            opening kick + drift of step 1 (needs F(x_0))
+    //   0 < g < n_steps:  fused: F(x_g), closing kick of step g, opening kick + drift of step g+1
+    //   g = n_steps:      F(x_N) and the closing kick of the last step
+    // Kernels with g < n_steps drift (positions flip buffers).  They are launched in
+    // chunks; a drift whose centres moved more than skin/2 sets ctrl->halt to its
+    // chunk index and every later kernel of the chunk returns at once.
     int rebuilds = 0;
-    int done = 0;
-    int since = 0;   // steps since the last rebuild
-    while (done < n_steps) {
-        const int chunk = std::min(std::max(2, c->last_interval - since), n_steps - done);
+    int g = n_steps > 0 ? 0 : 1;
+    int since = 0;   // kernels since the last rebuild
+    while (g <= n_steps && n_steps > 0) {
+        const int len = std::min(std::max(2, c->last_interval - since), n_steps + 1 - g);
         launch_reset_halt(c->stream, c->ctrl);
-        for (int k = 0; k < chunk; ++k) {
-            launch_kick_drift(c->stream, c->P, c->S[c->cur], c->R_ref, c->ctrl, k, dt, gamma, kT, seed,
-                              c->step_counter + (uint64_t)(done + k));
-            ForceArgs a = force_args(c);
-            a.f = c->S[c->cur].f;
-            a.v = c->S[c->cur].v;
-            a.dt = dt;
-            a.step = k;
-            a.check_halt = 1;
-            st = run_forces(c, a);
-            if (st != ADRES_OK) return st;
+        int p = c->pos;
+        for (int k = 0; k < len; ++k) {
+            const int gk = g + k;
+            StepArgs sa{dt, gamma, kT, seed, c->step_counter + (uint64_t)gk};
+            const StateBufs in = view(c, p, c->ord), out = view(c, 1 - p, c->ord);
+            if (gk == 0) {
+                launch_kick_drift(c->stream, c->P, in.x, in.v, c->f, out.x, out.Rw, out.rho, c->R_ref, in.perm,
+                                  c->ctrl, k, sa);
+                HIPCHK(c, hipGetLastError());
+            } else {
+                ForceArgs a = force_args(c);
+                a.x = in.x;
+                a.Rw = in.Rw;
+                a.rho = in.rho;
+                a.v = in.v;
+                a.st = sa;
+                a.step = k;
+                a.check_halt = 1;
+                if (gk < n_steps) {
+                    a.mode = kModeStep;
+                    a.x_out = out.x;
+                    a.Rw_out = out.Rw;
+                    a.rho_out = out.rho;
+                    a.R_ref = c->R_ref;
+                } else {
+                    a.mode = kModeClose;
+                    a.f = c->f;
+                }
+                st = run_forces(c, a);
+                if (st != ADRES_OK) return st;
+            }
+            if (gk < n_steps) p = 1 - p;
         }
-        HIPCHK(c, hipGetLastError());
         st = read_ctrl(c);
         if (st != ADRES_OK) return st;
         const int h = c->ctrl_host->halt;
-        if (h == INT_MAX) {
-            done += chunk;
-            since += chunk;
-            continue;
-        }
-        // step h drifted and asked for a rebuild: reorder, rebuild, then finish its force + kick
+        const int ran = h == INT_MAX ? len : h + 1;   // kernels that completed
+        for (int k = 0; k < ran; ++k)
+            if (g + k < n_steps) c->pos = 1 - c->pos;
+        g += ran;
+        since += ran;
+        if (h == INT_MAX) continue;
+        // kernel g-1 drifted and asked for a rebuild: reorder and rebuild the list
         st = resort(c, true);
         if (st != ADRES_OK) return st;
         st = build_list(c);
         if (st != ADRES_OK) return st;
-        ForceArgs a = force_args(c);
-        a.f = c->S[c->cur].f;
-        a.v = c->S[c->cur].v;
-        a.dt = dt;
-        st = run_forces(c, a);
-        if (st != ADRES_OK) return st;
         ++rebuilds;
-        done += h + 1;
-        c->last_interval = std::max(2, since + h + 1);
+        c->last_interval = std::max(2, since);
         since = 0;
     }
+    if (n_steps == 0) {
+        // nothing to integrate: F(x_0) is the answer
+    }
     c->step_counter += (uint64_t)n_steps;
-    launch_scatter_out(c->stream, c->P, c->S[c->cur], x, v, f);
+    const StateBufs fin = cur(c);
+    launch_scatter_out(c->stream, c->P, fin.perm, fin.x, fin.v, c->f, x, v, f);
     HIPCHK(c, hipGetLastError());
     st = read_ctrl(c);
     if (n_rebuilds) *n_rebuilds = rebuilds;
@@ -516,13 +558,13 @@ adres_status adres_get_pairs(adres_ctx *c, int32_t *pairs_host, int64_t cap, int
     const int nm = c->P.n_mol;
     std::vector<int> cnt(nm), perm(nm), nbr((size_t)c->cap * nm);
     HIPCHK(c, hipMemcpyAsync(cnt.data(), c->cnt, sizeof(int) * nm, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(perm.data(), c->S[c->cur].perm, sizeof(int) * nm, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(perm.data(), cur(c).perm, sizeof(int) * nm, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(nbr.data(), c->nbr, sizeof(int) * nbr.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     std::vector<std::pair<int, int>> pr;
     for (int t = 0; t < nm; ++t)
         for (int k = 0; k < std::min(cnt[t], c->cap); ++k) {
-            int a = perm[t], b = perm[nbr[(size_t)k * nm + t]];
+            int a = perm[t], b = perm[nbr[(size_t)t * c->cap + k]];
             if (a < b) pr.emplace_back(a, b);
         }
     std::sort(pr.begin(), pr.end());
@@ -543,7 +585,7 @@ adres_status adres_get_cells(adres_ctx *c, int32_t *cell_start_host, int32_t *pe
         HIPCHK(c, hipMemcpyAsync(cell_start_host, c->start, sizeof(int) * (c->G.n_cells + 1), hipMemcpyDeviceToHost,
                                  c->stream));
     if (perm_host)
-        HIPCHK(c, hipMemcpyAsync(perm_host, c->S[c->cur].perm, sizeof(int) * c->P.n_mol, hipMemcpyDeviceToHost,
+        HIPCHK(c, hipMemcpyAsync(perm_host, cur(c).perm, sizeof(int) * c->P.n_mol, hipMemcpyDeviceToHost,
                                  c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return ADRES_OK;

@@ -139,61 +139,186 @@ __device__ __forceinline__ int cell_coord(double r, double inv_len, int n)
     return s < (double)(n - 1) ? (int)s : n - 1;
 }
 
+// ---------------------------------------------------------------- integrator helpers
+// Philox4x32-10 (Salmon et al., "Parallel random numbers: as easy as 1, 2, 3",
+// SC'11): counter = (step, caller site), key = seed.
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
+        uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
+        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        k0 += W0;
+        k1 += W1;
+    }
+    return c;
+}
+
+// Two standard normal deviates from two 32-bit words (Box-Muller).
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double &n0, double &n1)
+{
+    double u1 = ((double)a + 1.0) * (1.0 / 4294967296.0);   // (0, 1]
+    double u2 = (double)b * (1.0 / 4294967296.0);
+    double r = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincospi(2.0 * u2, &sn, &cs);
+    n0 = r * cs;
+    n1 = r * sn;
+}
+
+// Opening half of a velocity-Verlet step for one site: v += F dt / 2m, then the
+// drift x += v dt folded into [0, L).  With gamma > 0 the drift is split around an
+// exact Ornstein-Uhlenbeck step (BAOAB, Leimkuhler & Matthews 2013):
+//   x += v dt/2;  v = c v + sqrt((1 - c^2) kT / m) N(0,1), c = exp(-gamma dt);  x += v dt/2.
+// Operation order as in the oracle's integrator (no contraction).
+__device__ __forceinline__ void open_and_drift(const DevParams &P, double m, int caller_site, double x[3],
+                                               double v[3], const double F[3], double dt, double gamma,
+                                               double kT, uint64_t seed, uint64_t step_abs)
+{
+#pragma clang fp contract(off)
+    double g[3] = {0.0, 0.0, 0.0};
+    double c_ou = 0.0, s_ou = 0.0;
+    if (gamma > 0.0) {
+        U4 r = philox4x32_10(U4{(uint32_t)step_abs, (uint32_t)(step_abs >> 32), (uint32_t)caller_site, 0u},
+                             (uint32_t)seed, (uint32_t)(seed >> 32));
+        double n3;
+        box_muller(r.x, r.y, g[0], g[1]);
+        box_muller(r.z, r.w, g[2], n3);
+        c_ou = exp(-gamma * dt);
+        s_ou = sqrt((1.0 - c_ou * c_ou) * kT / m);
+    }
+    for (int d = 0; d < 3; ++d) {
+        double vv = v[d] + F[d] * dt / (2.0 * m);
+        double y;
+        if (gamma > 0.0) {
+            y = x[d] + vv * (0.5 * dt);
+            vv = c_ou * vv + s_ou * g[d];
+            y = fold(y + vv * (0.5 * dt), P.box[d]);
+        } else {
+            y = fold(x[d] + vv * dt, P.box[d]);
+        }
+        v[d] = vv;
+        x[d] = y;
+    }
+}
+
+// Closing half-kick v += F dt / 2m (oracle's operation order).
+__device__ __forceinline__ void close_kick(double v[3], const double F[3], double dt, double m)
+{
+#pragma clang fp contract(off)
+    for (int d = 0; d < 3; ++d) v[d] = v[d] + F[d] * dt / (2.0 * m);
+}
+
+// Centre, weight and rho of a molecule at slot t into the packed outputs, with the
+// stretch / non-finite checks and the displacement check against R_ref (which
+// lowers ctrl->halt to halt_value).
+template <int SPM>
+__device__ __forceinline__ void store_molecule(const DevParams &P, const double (&p)[SPM][3], int t,
+                                               double4 *Rw, float *rho, const double4 *R_ref, Ctrl *ctrl,
+                                               int halt_value)
+{
+    double R[3], rh;
+    mol_com<SPM>(P, p, R, rh);
+    const double w = res_weight(P, R);
+    Rw[t] = make_double4(R[0], R[1], R[2], w);
+    rho[t] = (float)rh;
+    bool finite = true;
+#pragma unroll
+    for (int k = 0; k < SPM; ++k) finite = finite && isfinite(p[k][0]) && isfinite(p[k][1]) && isfinite(p[k][2]);
+    if (!finite) atomicOr(&ctrl->err, kErrNonFinite);
+    if (SPM > 1 && rh > P.rho_max) atomicOr(&ctrl->err, kErrStretch);
+    if (R_ref) {
+        const double4 r0 = R_ref[t];
+        double q0 = mi(R[0] - r0.x, P.box[0], P.half[0]);
+        double q1 = mi(R[1] - r0.y, P.box[1], P.half[1]);
+        double q2 = mi(R[2] - r0.z, P.box[2], P.half[2]);
+        if (dist2_exact(q0, q1, q2) > P.half_skin2) atomicMin(&ctrl->halt, halt_value);
+    }
+}
+
 // ---------------------------------------------------------------- launch wrappers
 // All launches are asynchronous on `s`.  Arrays in "sorted" order are indexed by
 // Morton slot; "caller" arrays by the caller's molecule/site index.
 
-struct StateBufs {   // sorted-order state (device)
-    double *x, *v, *f;       // [3][n_sites]
-    double *R;               // [3][n_mol]
-    double *w, *rho;         // [n_mol]
-    int *perm;               // slot -> caller molecule
-    int *key;                // slot -> Morton rank of its cell
+// Morton-ordered state of one configuration: positions, packed centre + weight,
+// rho (largest site distance from the centre), velocities and the order itself.
+struct StateBufs {
+    double *x;        // [3][n_sites]
+    double *v;        // [3][n_sites]
+    double4 *Rw;      // [n_mol] {Rx, Ry, Rz, w}
+    float *rho;       // [n_mol]
+    int *perm;        // slot -> caller molecule
+    int *key;         // slot -> Morton rank of its cell
 };
 
 void launch_weights_caller(hipStream_t s, const DevParams &P, const double *x, double *com, double *w,
                            Ctrl *ctrl);
+// caller x (and v) -> sorted state through S.perm; centres, weights, rho; optional
+// displacement check against R_ref (sets halt = 0)
 void launch_gather(hipStream_t s, const DevParams &P, const double *x_caller, const double *v_caller,
-                   const StateBufs &S, const double *R_ref, Ctrl *ctrl);
-void launch_scatter_out(hipStream_t s, const DevParams &P, const StateBufs &S, double *x_caller,
-                        double *v_caller, double *f_caller);
-void launch_kick_drift(hipStream_t s, const DevParams &P, const StateBufs &S, const double *R_ref,
-                       Ctrl *ctrl, int step, double dt, double gamma, double kT, uint64_t seed,
-                       uint64_t step_abs);
+                   const StateBufs &S, const double4 *R_ref, Ctrl *ctrl);
+void launch_scatter_out(hipStream_t s, const DevParams &P, const int *perm, const double *x, const double *v,
+                        const double *f, double *x_caller, double *v_caller, double *f_caller);
+// opening half-kick + drift of one step from x_in to x_out (new Rw/rho, displacement check)
+struct StepArgs {
+    double dt, gamma, kT;
+    uint64_t seed, step_abs;
+};
+void launch_kick_drift(hipStream_t s, const DevParams &P, const double *x_in, double *v, const double *f,
+                       double *x_out, double4 *Rw_out, float *rho_out, const double4 *R_ref, const int *perm,
+                       Ctrl *ctrl, int step, const StepArgs &st);
 void launch_reset_halt(hipStream_t s, Ctrl *ctrl);
 
 // cell list
 void launch_cell_keys(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank,
-                      const StateBufs &S, int *count);
+                      const double4 *Rw, int *key, int *count);
 void launch_scan_cells(hipStream_t s, const int *count, int n_cells, int *start, int *fill);
 void launch_scatter_slots(hipStream_t s, int n_mol, const int *key, const int *start, int *fill,
                           int *new_from);
 void launch_sort_within_cells(hipStream_t s, int n_cells, const int *start, const int *perm_old,
                               int *new_from);
 void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, const StateBufs &src,
-                    const StateBufs &dst, int *inv_perm, double *R_ref, bool with_v);
+                    const StateBufs &dst, int *inv_perm, double4 *R_ref, bool with_v);
 
-// Verlet list (ELL, column-major: nbr[k * n_mol + slot])
+// Verlet list: ELL, row-major nbr[slot * cap + k]; each row is padded with the
+// row's own slot up to a multiple of 4 entries (cap is a multiple of 4).
 void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const int *rank_cell,
-                       const int *cell_rank, const int *start, const StateBufs &S, double rl2, int *nbr,
-                       int *cnt, int cap, Ctrl *ctrl);
+                       const int *cell_rank, const int *start, const double4 *Rw, const int *key, double rl2,
+                       int *nbr, int *cnt, int cap, Ctrl *ctrl);
 
 // forces
+enum ForceMode : int {
+    kModeForce = 0,   // F(x) only
+    kModeStep = 1,    // F(x_n), closing half-kick of step n, opening half-kick + drift of step n+1
+    kModeClose = 2,   // F(x_n) and the closing half-kick of the last step
+};
 struct ForceArgs {
     DevParams P;
-    const double *x, *R, *w, *rho;
+    const double *x;        // step-n positions (sorted)
+    const double4 *Rw;      // step-n centres + weights
+    const float *rho;
     const int *nbr, *cnt;
     int cap;
     const int *perm, *inv_perm;   // slot -> caller, caller -> slot
-    double *f;                    // output forces
+    int mode;
+    double *f;                    // kModeForce / kModeClose: output forces
     const int *out_perm;          // non-null: write f in caller order via perm
-    double *v;                    // non-null: second half-kick v += f dt / 2m (sorted)
-    double dt;
+    double *v;                    // kModeStep / kModeClose: velocities (in place)
+    double *x_out;                // kModeStep: step n+1 positions, centres, rho
+    double4 *Rw_out;
+    float *rho_out;
+    const double4 *R_ref;
+    StepArgs st;
     Ctrl *ctrl;
     int step, check_halt;
     double *epart;                // non-null: per-block energy partials [blocks][3]
 };
 int launch_forces(hipStream_t s, const ForceArgs &a, int pair_precision);   // returns block count
+int force_blocks(int n_mol);
 void launch_energy_reduce(hipStream_t s, const double *epart, int n_blocks, double *energy);
 
 }  // namespace adres

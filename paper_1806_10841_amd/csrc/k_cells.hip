@@ -8,8 +8,9 @@
 // and the Verlet list of molecule pairs: every molecule scans the 27 cells around
 // its own (fewer when a dimension has < 3 cells) and keeps the molecules whose
 // minimum-image centre distance is strictly below r_list.  The list is stored
-// column-major (ELL): nbr[k * n_mol + slot], so lanes that handle consecutive
-// slots read consecutive words.
+// row-major (ELL): nbr[slot * cap + k]; every row is padded with the row's own
+// slot up to a multiple of 4 so that the force kernel can fetch four entries with
+// one 16-byte load and issue their gathers unconditionally.
 #include "adres_internal.h"
 
 namespace adres {
@@ -20,17 +21,18 @@ constexpr int kBlock = 256;
 inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
 __global__ __launch_bounds__(kBlock) void k_cell_keys(DevParams P, Grid G, const int *__restrict__ cell_rank,
-                                                      StateBufs S, int *__restrict__ count)
+                                                      const double4 *__restrict__ Rw, int *__restrict__ key,
+                                                      int *__restrict__ count)
 {
     int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= P.n_mol) return;
-    const int n = P.n_mol;
-    int cx = cell_coord(S.R[t], G.inv_len[0], G.n[0]);
-    int cy = cell_coord(S.R[n + t], G.inv_len[1], G.n[1]);
-    int cz = cell_coord(S.R[2 * n + t], G.inv_len[2], G.n[2]);
-    int key = cell_rank[cx + G.n[0] * (cy + G.n[1] * cz)];
-    S.key[t] = key;
-    atomicAdd(&count[key], 1);
+    const double4 r = Rw[t];
+    int cx = cell_coord(r.x, G.inv_len[0], G.n[0]);
+    int cy = cell_coord(r.y, G.inv_len[1], G.n[1]);
+    int cz = cell_coord(r.z, G.inv_len[2], G.n[2]);
+    int k = cell_rank[cx + G.n[0] * (cy + G.n[1] * cz)];
+    key[t] = k;
+    atomicAdd(&count[k], 1);
 }
 
 // Exclusive scan of count[0..n) into start[0..n], one workgroup of 1024 threads:
@@ -111,11 +113,10 @@ __global__ __launch_bounds__(kBlock) void k_sort_within_cells(int n_cells, const
 template <int SPM>
 __global__ __launch_bounds__(kBlock) void k_permute(DevParams P, const int *__restrict__ new_from, StateBufs src,
                                                     StateBufs dst, int *__restrict__ inv_perm,
-                                                    double *__restrict__ R_ref, int with_v)
+                                                    double4 *__restrict__ R_ref, int with_v)
 {
     int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= P.n_mol) return;
-    const int n = P.n_mol;
     const int64_t ns = P.n_sites;
     int i = new_from[t];
 #pragma unroll
@@ -125,11 +126,10 @@ __global__ __launch_bounds__(kBlock) void k_permute(DevParams P, const int *__re
             dst.x[d * ns + (int64_t)t * SPM + k] = src.x[d * ns + (int64_t)i * SPM + k];
             if (with_v) dst.v[d * ns + (int64_t)t * SPM + k] = src.v[d * ns + (int64_t)i * SPM + k];
         }
-        double r = src.R[d * n + i];
-        dst.R[d * n + t] = r;
-        R_ref[d * n + t] = r;
     }
-    dst.w[t] = src.w[i];
+    const double4 r = src.Rw[i];
+    dst.Rw[t] = r;
+    R_ref[t] = r;
     dst.rho[t] = src.rho[i];
     dst.key[t] = src.key[i];
     int caller = src.perm[i];
@@ -145,16 +145,17 @@ __device__ __forceinline__ int wrap_cell(int c, int n)
 
 __global__ __launch_bounds__(kBlock) void k_list_build(DevParams P, Grid G, const int *__restrict__ rank_cell,
                                                        const int *__restrict__ cell_rank,
-                                                       const int *__restrict__ start, StateBufs S, double rl2,
+                                                       const int *__restrict__ start, const double4 *__restrict__ Rw,
+                                                       const int *__restrict__ key, double rl2,
                                                        int *__restrict__ nbr, int *__restrict__ cnt, int cap,
                                                        Ctrl *ctrl)
 {
     int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= P.n_mol) return;
-    const int n = P.n_mol;
-    const double Rx = S.R[t], Ry = S.R[n + t], Rz = S.R[2 * n + t];
-    const int c = rank_cell[S.key[t]];
+    const double4 me = Rw[t];
+    const int c = rank_cell[key[t]];
     const int cx = c % G.n[0], cy = (c / G.n[0]) % G.n[1], cz = c / (G.n[0] * G.n[1]);
+    int *row = nbr + (int64_t)t * cap;
     int k = 0;
     for (int oz = G.off_lo[2]; oz <= G.off_hi[2]; ++oz) {
         const int z = wrap_cell(cz + oz, G.n[2]);
@@ -166,11 +167,12 @@ __global__ __launch_bounds__(kBlock) void k_list_build(DevParams P, Grid G, cons
                 const int hi = start[r + 1];
                 for (int u = start[r]; u < hi; ++u) {
                     if (u == t) continue;
-                    double dx = mi(S.R[u] - Rx, P.box[0], P.half[0]);
-                    double dy = mi(S.R[n + u] - Ry, P.box[1], P.half[1]);
-                    double dz = mi(S.R[2 * n + u] - Rz, P.box[2], P.half[2]);
+                    const double4 o = Rw[u];
+                    double dx = mi(o.x - me.x, P.box[0], P.half[0]);
+                    double dy = mi(o.y - me.y, P.box[1], P.half[1]);
+                    double dz = mi(o.z - me.z, P.box[2], P.half[2]);
                     if (dist2_exact(dx, dy, dz) < rl2) {
-                        if (k < cap) nbr[(int64_t)k * n + t] = u;
+                        if (k < cap) row[k] = u;
                         ++k;
                     }
                 }
@@ -181,15 +183,17 @@ __global__ __launch_bounds__(kBlock) void k_list_build(DevParams P, Grid G, cons
     if (k > cap) {
         atomicOr(&ctrl->overflow, 1);
         atomicMax(&ctrl->max_count, k);
+    } else {
+        for (int j = k; j < ((k + 3) & ~3); ++j) row[j] = t;   // padding: the row's own slot
     }
 }
 
 }  // namespace
 
 void launch_cell_keys(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank,
-                      const StateBufs &S, int *count)
+                      const double4 *Rw, int *key, int *count)
 {
-    k_cell_keys<<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, G, cell_rank, S, count);
+    k_cell_keys<<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, G, cell_rank, Rw, key, count);
 }
 
 void launch_scan_cells(hipStream_t s, const int *count, int n_cells, int *start, int *fill)
@@ -208,7 +212,7 @@ void launch_sort_within_cells(hipStream_t s, int n_cells, const int *start, cons
 }
 
 void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, const StateBufs &src,
-                    const StateBufs &dst, int *inv_perm, double *R_ref, bool with_v)
+                    const StateBufs &dst, int *inv_perm, double4 *R_ref, bool with_v)
 {
     switch (P.spm) {
     case 1: k_permute<1><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, new_from, src, dst, inv_perm, R_ref, with_v); break;
@@ -219,11 +223,11 @@ void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, cons
 }
 
 void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const int *rank_cell,
-                       const int *cell_rank, const int *start, const StateBufs &S, double rl2, int *nbr,
-                       int *cnt, int cap, Ctrl *ctrl)
+                       const int *cell_rank, const int *start, const double4 *Rw, const int *key, double rl2,
+                       int *nbr, int *cnt, int cap, Ctrl *ctrl)
 {
-    k_list_build<<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, G, rank_cell, cell_rank, start, S, rl2, nbr, cnt, cap,
-                                                       ctrl);
+    k_list_build<<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, G, rank_cell, cell_rank, start, Rw, key, rl2, nbr, cnt,
+                                                       cap, ctrl);
 }
 
 }  // namespace adres

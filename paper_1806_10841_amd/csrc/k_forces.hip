@@ -3,24 +3,27 @@
 // with F^AT the sum of atom-atom WCA forces between the two molecules and F^CG a
 // force between their centres of mass, shared among a molecule's sites by mass
 // fraction; plus the bonded terms, which are not interpolated (Sec. 2.2, last
-// paragraph).
+// paragraph).  In its step mode the same kernel also finishes velocity Verlet
+// for step n (closing half-kick) and starts step n+1 (opening half-kick, drift,
+// new centre of mass and weight, list-displacement check), so one MD step is one
+// launch.
 //
-// Work mapping (gfx950, wave64): four lanes per home molecule.  Lane q of the
-// group walks neighbour-list entries q, q+4, q+8, ... of its molecule (full list:
-// every pair is seen from both sides, so no atomics and a fixed summation order)
-// and accumulates, in FP64, the force on every site of the home molecule.  The
-// four partial sums are then combined with two butterfly shuffles, after which
-// lane q owns site q: it adds the bonded force, writes F and optionally applies
-// the closing half-kick of velocity Verlet.  A 256-thread workgroup covers 64
-// consecutive Morton slots, i.e. a compact cluster of cells, so neighbour gathers
-// hit the same cache lines across the workgroup.
+// Work mapping (gfx950, wave64): four lanes per home molecule, 16 molecules per
+// wavefront, consecutive Morton slots (a compact cluster of cells) per workgroup.
+// Lane q takes the molecule's list entries in blocks of four (entries 4q..4q+3,
+// then 16 further on): one 16-byte load fetches the four neighbour slots and the
+// four 32-byte {R, w} gathers are issued back to back before any arithmetic, so
+// each lane keeps four independent memory chains in flight (the kernel is bound
+// by gather latency, not by arithmetic).  Every lane accumulates, in FP64, the
+// atom-tile forces on all sites of its molecule and the molecule's total CG force;
+// two butterfly shuffles combine the four lanes; lane q then owns site q.
 //
-// Pair arithmetic in PT (double or float).  In the float variant the displacement
-// is formed in FP64 (minimum image of FP64 coordinates) and rounded once to FP32;
-// everything after that is FP32, and the accumulation is FP64.  Cutoff decisions
-// of the CG part use the FP64 centre distance.  An atom tile is skipped when the
-// centres are farther apart than rc_at + rho_a + rho_b (rho: largest site distance
-// from the centre), which no interacting atom pair can be (triangle inequality).
+// Full (two-sided) list: no atomics, fixed summation order, bit-reproducible.
+// Pair arithmetic in PT (double or float).  In the float variant displacements
+// are formed in FP64 and rounded once; the CG cutoff is decided on the FP64
+// centre distance.  An atom tile is skipped when the centres are farther apart
+// than rc_at + rho_a + rho_b (rho: largest site distance from the centre), which
+// no interacting atom pair can be (triangle inequality).
 #include "adres_internal.h"
 
 namespace adres {
@@ -53,19 +56,11 @@ __device__ __forceinline__ PT table_f(const DevParams &P, double r, Ctrl *ctrl)
     return ((PT(c.w) * t + PT(c.z)) * t + PT(c.y)) * t + PT(c.x);
 }
 
-// Closing half-kick of velocity Verlet, v += F dt / (2m), in the oracle's operation order.
-__device__ __forceinline__ void half_kick(double *v, int64_t ns, int64_t site, const double F[3], double dt,
-                                          double m)
-{
-#pragma clang fp contract(off)
-    for (int d = 0; d < 3; ++d) v[d * ns + site] = v[d * ns + site] + F[d] * dt / (2.0 * m);
-}
-
-template <int SPM, typename PT, bool ENERGY>
+template <int SPM, typename PT, int MODE, bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs a)
 {
     const DevParams &P = a.P;
-    if (a.check_halt && a.step >= a.ctrl->halt) return;
+    if (a.check_halt && a.step > a.ctrl->halt) return;
     const int n = P.n_mol;
     const int64_t ns = P.n_sites;
     const int gid = blockIdx.x * kBlock + threadIdx.x;
@@ -78,71 +73,78 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs a)
     for (int i = 0; i < SPM; ++i)
 #pragma unroll
         for (int d = 0; d < 3; ++d) xi[i][d] = a.x[d * ns + (int64_t)tt * SPM + i];
-    const double Ra0 = a.R[tt], Ra1 = a.R[n + tt], Ra2 = a.R[2 * n + tt];
-    const double wa = a.w[tt], rha = a.rho[tt];
+    const double4 me = a.Rw[tt];
+    const double rha = (double)a.rho[tt];
 
     double acc[SPM][3];
 #pragma unroll
     for (int i = 0; i < SPM; ++i) acc[i][0] = acc[i][1] = acc[i][2] = 0.0;
+    double cg0 = 0.0, cg1 = 0.0, cg2 = 0.0;
     double uat = 0.0, ucg = 0.0, ubond = 0.0;
 
     const PT sig2A = (PT)P.sig2_at, epsA = (PT)P.eps_at, rcA2 = (PT)P.rcA2;
     const PT sig2C = (PT)P.sig2_cg, epsC = (PT)P.eps_cg;
-    const int cnt = valid ? min(a.cnt[tt], a.cap) : 0;
+    const int cnt = valid ? a.cnt[tt] : 0;
+    const int *row = a.nbr + (int64_t)tt * a.cap;
 
-    for (int k = q; k < cnt; k += kLanes) {
-        const int u = a.nbr[(int64_t)k * n + tt];
-        const double ww = wa * a.w[u];
-        const double D0 = mi(Ra0 - a.R[u], P.box[0], P.half[0]);
-        const double D1 = mi(Ra1 - a.R[n + u], P.box[1], P.half[1]);
-        const double D2 = mi(Ra2 - a.R[2 * n + u], P.box[2], P.half[2]);
-        const double r2c = dist2_exact(D0, D1, D2);
-        if (ww > 0.0) {
-            const double bound = P.rc_at + rha + a.rho[u] + 1e-9;
-            if (r2c < bound * bound) {
-                const PT pww = (PT)ww;
+    for (int k0 = 4 * q; k0 < cnt; k0 += 4 * kLanes) {
+        const int4 id4 = *reinterpret_cast<const int4 *>(row + k0);
+        const int us[4] = {id4.x, id4.y, id4.z, id4.w};
+        double4 nb[4];
 #pragma unroll
-                for (int j = 0; j < SPM; ++j) {
-                    const double xj0 = a.x[(int64_t)u * SPM + j];
-                    const double xj1 = a.x[ns + (int64_t)u * SPM + j];
-                    const double xj2 = a.x[2 * ns + (int64_t)u * SPM + j];
+        for (int j = 0; j < 4; ++j) nb[j] = a.Rw[us[j]];   // padding entries are valid slots
 #pragma unroll
-                    for (int i = 0; i < SPM; ++i) {
-                        const PT dx = (PT)mi(xi[i][0] - xj0, P.box[0], P.half[0]);
-                        const PT dy = (PT)mi(xi[i][1] - xj1, P.box[1], P.half[1]);
-                        const PT dz = (PT)mi(xi[i][2] - xj2, P.box[2], P.half[2]);
-                        const PT r2 = (dx * dx + dy * dy) + dz * dz;
-                        if (r2 < rcA2) {
-                            PT uu = PT(0);
-                            const PT c = pww * wca_f_over_r<PT>(r2, sig2A, epsA, uu, ENERGY);
-                            acc[i][0] += (double)(c * dx);
-                            acc[i][1] += (double)(c * dy);
-                            acc[i][2] += (double)(c * dz);
-                            if (ENERGY) uat += 0.5 * ww * (double)uu;
+        for (int j = 0; j < 4; ++j) {
+            if (k0 + j >= cnt) break;
+            const int u = us[j];
+            const double4 o = nb[j];
+            const double ww = me.w * o.w;
+            const double D0 = mi(me.x - o.x, P.box[0], P.half[0]);
+            const double D1 = mi(me.y - o.y, P.box[1], P.half[1]);
+            const double D2 = mi(me.z - o.z, P.box[2], P.half[2]);
+            const double r2c = dist2_exact(D0, D1, D2);
+            if (ww > 0.0) {
+                const double bound = P.rc_at + rha + (double)a.rho[u] + 1e-6;
+                if (r2c < bound * bound) {
+                    const PT pww = (PT)ww;
+#pragma unroll
+                    for (int jj = 0; jj < SPM; ++jj) {
+                        const double xj0 = a.x[(int64_t)u * SPM + jj];
+                        const double xj1 = a.x[ns + (int64_t)u * SPM + jj];
+                        const double xj2 = a.x[2 * ns + (int64_t)u * SPM + jj];
+#pragma unroll
+                        for (int i = 0; i < SPM; ++i) {
+                            const PT dx = (PT)mi(xi[i][0] - xj0, P.box[0], P.half[0]);
+                            const PT dy = (PT)mi(xi[i][1] - xj1, P.box[1], P.half[1]);
+                            const PT dz = (PT)mi(xi[i][2] - xj2, P.box[2], P.half[2]);
+                            const PT r2 = (dx * dx + dy * dy) + dz * dz;
+                            if (r2 < rcA2) {
+                                PT uu = PT(0);
+                                const PT c = pww * wca_f_over_r<PT>(r2, sig2A, epsA, uu, ENERGY);
+                                acc[i][0] += (double)(c * dx);
+                                acc[i][1] += (double)(c * dy);
+                                acc[i][2] += (double)(c * dz);
+                                if (ENERGY) uat += 0.5 * ww * (double)uu;
+                            }
                         }
                     }
                 }
             }
-        }
-        if (ww < 1.0 && r2c < P.rcC2) {
-            PT uu = PT(0);
-            PT fr;
-            if (P.cg_kind == ADRES_CG_WCA) {
-                fr = wca_f_over_r<PT>((PT)r2c, sig2C, epsC, uu, ENERGY);
-            } else {
-                const double r = sqrt(r2c);
-                fr = table_f<PT>(P, r, a.ctrl) / (PT)r;
+            if (ww < 1.0 && r2c < P.rcC2) {
+                PT uu = PT(0);
+                PT fr;
+                if (P.cg_kind == ADRES_CG_WCA) {
+                    fr = wca_f_over_r<PT>((PT)r2c, sig2C, epsC, uu, ENERGY);
+                } else {
+                    const double r = sqrt(r2c);
+                    fr = table_f<PT>(P, r, a.ctrl) / (PT)r;
+                }
+                const PT sc = (PT)(1.0 - ww) * fr;
+                cg0 += (double)(sc * (PT)D0);
+                cg1 += (double)(sc * (PT)D1);
+                cg2 += (double)(sc * (PT)D2);
+                if (ENERGY) ucg += 0.5 * (1.0 - ww) * (double)uu;
             }
-            const PT sc = (PT)(1.0 - ww) * fr;
-            const PT d0 = (PT)D0, d1 = (PT)D1, d2 = (PT)D2;
-#pragma unroll
-            for (int i = 0; i < SPM; ++i) {
-                const PT s = (PT)P.mfrac[i] * sc;
-                acc[i][0] += (double)(s * d0);
-                acc[i][1] += (double)(s * d1);
-                acc[i][2] += (double)(s * d2);
-            }
-            if (ENERGY) ucg += 0.5 * (1.0 - ww) * (double)uu;
         }
     }
 
@@ -156,17 +158,28 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs a)
             v += __shfl_xor(v, 2, kLanes);
             acc[i][d] = v;
         }
+    cg0 += __shfl_xor(cg0, 1, kLanes);
+    cg0 += __shfl_xor(cg0, 2, kLanes);
+    cg1 += __shfl_xor(cg1, 1, kLanes);
+    cg1 += __shfl_xor(cg1, 2, kLanes);
+    cg2 += __shfl_xor(cg2, 1, kLanes);
+    cg2 += __shfl_xor(cg2, 2, kLanes);
 
-    double F[3] = {0.0, 0.0, 0.0};
-    double xq[3] = {0.0, 0.0, 0.0};
+    // lane q owns site q
+    double F[3] = {0.0, 0.0, 0.0}, xq[3] = {0.0, 0.0, 0.0};
+    double mq = 1.0;
 #pragma unroll
     for (int i = 0; i < SPM; ++i)
         if (i == q) {
-            F[0] = acc[i][0]; F[1] = acc[i][1]; F[2] = acc[i][2];
+            const double mf = P.mfrac[i];
+            F[0] = acc[i][0] + mf * cg0;
+            F[1] = acc[i][1] + mf * cg1;
+            F[2] = acc[i][2] + mf * cg2;
             xq[0] = xi[i][0]; xq[1] = xi[i][1]; xq[2] = xi[i][2];
+            mq = P.mass[i];
         }
-
-    if (valid && q < SPM) {
+    const bool owner = valid && q < SPM;
+    if (owner) {
         if (P.bond_kind == ADRES_BOND_HARMONIC) {
 #pragma unroll
             for (int k = 0; k < SPM; ++k) {
@@ -200,11 +213,40 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs a)
             }
         }
         if (!(isfinite(F[0]) && isfinite(F[1]) && isfinite(F[2]))) atomicOr(&a.ctrl->err, kErrNonFinite);
-        const int64_t site = (int64_t)(a.out_perm ? a.out_perm[t] : t) * SPM + q;
-        a.f[site] = F[0];
-        a.f[ns + site] = F[1];
-        a.f[2 * ns + site] = F[2];
-        if (a.v) half_kick(a.v, ns, (int64_t)t * SPM + q, F, a.dt, P.mass[q]);
+    }
+
+    const int64_t site = (int64_t)t * SPM + q;
+    if (MODE == kModeForce) {
+        if (owner) {
+            const int64_t os = a.out_perm ? (int64_t)a.out_perm[t] * SPM + q : site;
+            a.f[os] = F[0];
+            a.f[ns + os] = F[1];
+            a.f[2 * ns + os] = F[2];
+        }
+    } else if (MODE == kModeClose) {
+        if (owner) {
+            double v[3] = {a.v[site], a.v[ns + site], a.v[2 * ns + site]};
+            close_kick(v, F, a.st.dt, mq);
+            a.v[site] = v[0]; a.v[ns + site] = v[1]; a.v[2 * ns + site] = v[2];
+            a.f[site] = F[0]; a.f[ns + site] = F[1]; a.f[2 * ns + site] = F[2];
+        }
+    } else {   // kModeStep
+        double xn[3] = {xq[0], xq[1], xq[2]};
+        if (owner) {
+            double v[3] = {a.v[site], a.v[ns + site], a.v[2 * ns + site]};
+            close_kick(v, F, a.st.dt, mq);
+            const int caller_site = a.st.gamma > 0.0 ? a.perm[t] * SPM + q : 0;
+            open_and_drift(P, mq, caller_site, xn, v, F, a.st.dt, a.st.gamma, a.st.kT, a.st.seed, a.st.step_abs);
+            a.v[site] = v[0]; a.v[ns + site] = v[1]; a.v[2 * ns + site] = v[2];
+            a.x_out[site] = xn[0]; a.x_out[ns + site] = xn[1]; a.x_out[2 * ns + site] = xn[2];
+        }
+        // the molecule's new sites, gathered to every lane of its quad
+        double p[SPM][3];
+#pragma unroll
+        for (int k = 0; k < SPM; ++k)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) p[k][d] = __shfl(xn[d], k, kLanes);
+        if (valid && q == 0) store_molecule<SPM>(P, p, t, a.Rw_out, a.rho_out, a.R_ref, a.ctrl, a.step);
     }
 
     if (ENERGY) {
@@ -247,30 +289,37 @@ __global__ __launch_bounds__(256) void k_energy_reduce(const double *__restrict_
 }
 
 template <int SPM, typename PT>
-void dispatch_energy(hipStream_t s, const ForceArgs &a, int blocks)
+void dispatch_mode(hipStream_t s, const ForceArgs &a, int blocks)
 {
-    if (a.epart)
-        k_forces<SPM, PT, true><<<blocks, kBlock, 0, s>>>(a);
-    else
-        k_forces<SPM, PT, false><<<blocks, kBlock, 0, s>>>(a);
+    switch (a.mode) {
+    case kModeStep: k_forces<SPM, PT, kModeStep, false><<<blocks, kBlock, 0, s>>>(a); break;
+    case kModeClose: k_forces<SPM, PT, kModeClose, false><<<blocks, kBlock, 0, s>>>(a); break;
+    default:
+        if (a.epart)
+            k_forces<SPM, PT, kModeForce, true><<<blocks, kBlock, 0, s>>>(a);
+        else
+            k_forces<SPM, PT, kModeForce, false><<<blocks, kBlock, 0, s>>>(a);
+    }
 }
 
 template <typename PT>
 void dispatch_spm(hipStream_t s, const ForceArgs &a, int blocks)
 {
     switch (a.P.spm) {
-    case 1: dispatch_energy<1, PT>(s, a, blocks); break;
-    case 2: dispatch_energy<2, PT>(s, a, blocks); break;
-    case 3: dispatch_energy<3, PT>(s, a, blocks); break;
-    default: dispatch_energy<4, PT>(s, a, blocks); break;
+    case 1: dispatch_mode<1, PT>(s, a, blocks); break;
+    case 2: dispatch_mode<2, PT>(s, a, blocks); break;
+    case 3: dispatch_mode<3, PT>(s, a, blocks); break;
+    default: dispatch_mode<4, PT>(s, a, blocks); break;
     }
 }
 
 }  // namespace
 
+int force_blocks(int n_mol) { return (int)(((int64_t)n_mol * kLanes + kBlock - 1) / kBlock); }
+
 int launch_forces(hipStream_t s, const ForceArgs &a, int pair_precision)
 {
-    const int blocks = (int)(((int64_t)a.P.n_mol * kLanes + kBlock - 1) / kBlock);
+    const int blocks = force_blocks(a.P.n_mol);
     if (pair_precision == 32)
         dispatch_spm<float>(s, a, blocks);
     else
