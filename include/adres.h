@@ -60,7 +60,7 @@ typedef enum {
 } adres_status;
 
 enum { ADRES_REGION_ALL_AT = 0, ADRES_REGION_SLAB_X = 1, ADRES_REGION_SPHERE = 2, ADRES_REGION_ALL_CG = 3 };
-enum { ADRES_CG_WCA = 0, ADRES_CG_TABLE = 1, ADRES_CG_MLP = 2, ADRES_CG_MLP_FP8 = 3 };
+enum { ADRES_CG_WCA = 0, ADRES_CG_TABLE = 1, ADRES_CG_MLP = 2 };
 enum { ADRES_BOND_NONE = 0, ADRES_BOND_HARMONIC = 1, ADRES_BOND_FENE = 2 };
 
 #define ADRES_MAX_SITES 4
@@ -75,7 +75,7 @@ typedef struct {
     double  d_at, d_hy;         /* AT half-width / radius and hybrid width */
     double  eps_at, sig_at, rc_at;   /* atom-atom WCA */
     double  eps_cg, sig_cg, rc_cg;   /* CG centre-of-mass force: WCA parameters and cutoff */
-    int32_t cg_kind;            /* ADRES_CG_* */
+    int32_t cg_kind;            /* ADRES_CG_*: the CG force between centres of mass */
     int32_t bond_kind;          /* ADRES_BOND_* */
     double  k_bond, r0_bond;    /* harmonic: K, b0;  FENE: k, R0 */
     int32_t chain_len;          /* FENE: beads per chain (runs of consecutive molecules) */
@@ -154,6 +154,25 @@ adres_status adres_get_cells(adres_ctx *ctx, int32_t *cell_start_host, int32_t *
  * fallback below its r_min.  2 <= n_knots <= 4096. */
 adres_status adres_set_cg_table(adres_ctx *ctx, const float *coef4, int32_t n_knots,
                                 double r_lo, double r_hi);
+
+/* Learned CG force (replaces F^CG of Eq. (1) when cg_kind is ADRES_CG_MLP):
+ *   f(r) = scale * taper(r) * [W3 . silu(W2 silu(W1 x + b1) + b2) + b3],  x = r / rc,
+ * silu(z) = z / (1 + e^-z), taper = 1 below rc - taper_width and a cos^2 ramp to 0 at rc,
+ * positive f = repulsive along R_ab / r.  Below r_min the installed cubic table is used
+ * (the fallback).  Hidden width 64: params (host, float32, 4353 values) are
+ * W1[64], b1[64], W2[64*64] (row = output unit), b2[64], W3[64], b3.  Layer 2 runs on
+ * BF16 matrix cores with FP32 accumulation; layers 1 and 3 in FP32.  The values are
+ * copied; n_params must be 4353. */
+adres_status adres_mlp_set(adres_ctx *ctx, const float *params, int32_t n_params, double rc, double scale,
+                           double taper_width, double r_min);
+
+/* Copy the network's current FP32 parameters (e.g. after training) to params (host,
+ * 4353 floats).  Synchronises. */
+adres_status adres_mlp_get(adres_ctx *ctx, float *params, int32_t n_params);
+
+/* Evaluate the installed network (with its taper, cutoff and table fallback) at n
+ * distances: r (device, float64 [n]) -> f (device, float32 [n]).  Asynchronous. */
+adres_status adres_mlp_eval(adres_ctx *ctx, const double *r, float *f, int64_t n);
 
 /* Diagnostic: device time of the force kernels enqueued since the last call, measured
  * with HIP events on the context's stream when enabled (enable != 0 turns it on, 0 off).

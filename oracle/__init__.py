@@ -120,7 +120,7 @@ class Model:
         p.d_at, p.d_hy = wl.d_at, wl.d_hy
         p.eps_at, p.sig_at, p.rc_at = wl.eps_at, wl.sig_at, wl.rc_at
         p.eps_cg, p.sig_cg, p.rc_cg = wl.eps_cg, wl.sig_cg, wl.rc_cg
-        p.cg_kind = {0: 0, 1: 1, 2: 2, 3: 2}[wl.cg_kind]
+        p.cg_kind = wl.cg_kind
         p.bond_kind = wl.bond_kind
         p.k_bond, p.r0_bond = wl.k_bond, wl.r0_bond
         p.chain_len = max(int(wl.chain_len), 1)

@@ -60,6 +60,9 @@ _SIGS = {
     "adres_get_pairs": ([C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
     "adres_get_cells": ([C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)], C.c_int),
     "adres_set_cg_table": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double], C.c_int),
+    "adres_mlp_set": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double], C.c_int),
+    "adres_mlp_get": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
+    "adres_mlp_eval": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64], C.c_int),
     "adres_kernel_timing": ([C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     "adres_last_error": ([C.c_void_p], C.c_char_p),
 }
@@ -199,6 +202,22 @@ class Context:
         assert coef.ndim == 2 and coef.shape[1] == 4
         self._check(self.lib.adres_set_cg_table(self.h, coef.ctypes.data_as(C.c_void_p), coef.shape[0] + 1,
                                                 r_lo, r_hi), "adres_set_cg_table")
+
+    def mlp_set(self, params, rc, scale, taper_width, r_min=0.0):
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self.lib.adres_mlp_set(self.h, params.ctypes.data_as(C.c_void_p), params.size, rc, scale,
+                                           taper_width, r_min), "adres_mlp_set")
+
+    def mlp_get(self):
+        out = np.empty(4353, dtype=np.float32)
+        self._check(self.lib.adres_mlp_get(self.h, out.ctypes.data_as(C.c_void_p), out.size), "adres_mlp_get")
+        return out
+
+    def mlp_eval(self, r):
+        import torch
+        f = torch.empty(r.shape[0], dtype=torch.float32, device=r.device)
+        self._check(self.lib.adres_mlp_eval(self.h, _ptr(r), _ptr(f), r.shape[0]), "adres_mlp_eval")
+        return f
 
     def kernel_timing(self, enable=True):
         ms = C.c_double()

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "adres_internal.h"
+#include "adres_mlp.h"
 
 using namespace adres;
 
@@ -41,6 +42,17 @@ struct adres_ctx {
     double *epart = nullptr;
     int epart_blocks = 0;
     float4 *tab = nullptr;
+
+    // learned CG force
+    float *mlp = nullptr;          // FP32 master parameters (kMlpParams)
+    __bf16 *mlp_w2 = nullptr;      // BF16 copy of W2
+    double mlp_rc = 0.0, mlp_scale = 1.0, mlp_tw = 0.0, mlp_rmin = 0.0;
+    bool have_mlp = false;
+    // half list (every unordered pair once) for per-pair network outputs
+    int *cnt_up = nullptr, *up_off = nullptr, *up_scratch = nullptr, *pid = nullptr;
+    int2 *up_pairs = nullptr;
+    float *f_pair = nullptr;
+    int64_t half_rows_cap = 0, n_up = 0;
 
     bool have_state = false;
     bool list_valid = false;
@@ -136,6 +148,48 @@ adres_status resort(adres_ctx *c, bool with_v)
     return ADRES_OK;
 }
 
+bool is_mlp(const adres_ctx *c) { return c->P.cg_kind >= ADRES_CG_MLP; }
+
+// Every unordered pair of the Verlet list once (t < u) and, for every list entry, the
+// id of its pair; the network is evaluated per pair, so both directions of a pair
+// read the same value (exact Newton's third law).  Synchronises once for the count.
+adres_status build_half_list(adres_ctx *c)
+{
+    const int n = c->P.n_mol;
+    if (c->half_rows_cap < c->cap) {
+        hipFree(c->pid); hipFree(c->up_pairs); hipFree(c->f_pair);
+        c->pid = nullptr; c->up_pairs = nullptr; c->f_pair = nullptr;
+        const size_t cap_pairs = (size_t)n * c->cap / 2 + 16;
+        if (dalloc(&c->pid, (size_t)n * c->cap) != hipSuccess || dalloc(&c->up_pairs, cap_pairs) != hipSuccess ||
+            dalloc(&c->f_pair, cap_pairs) != hipSuccess)
+            return fail(c, ADRES_E_NOMEM, "could not allocate the half list");
+        c->half_rows_cap = c->cap;
+    }
+    launch_half_list(c->stream, n, c->nbr, c->cnt, c->cap, c->cnt_up, c->up_off, c->up_scratch, c->up_pairs, c->pid);
+    HIPCHK(c, hipGetLastError());
+    int total = 0;
+    HIPCHK(c, hipMemcpyAsync(&total, c->up_off + n, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->n_up = total;
+    return ADRES_OK;
+}
+
+MlpDev mlp_dev(const adres_ctx *c)
+{
+    MlpDev M;
+    M.w1 = c->mlp;
+    M.b1 = c->mlp + kHidden;
+    M.w2 = c->mlp + 2 * kHidden;
+    M.b2 = c->mlp + 2 * kHidden + kHidden * kHidden;
+    M.w3 = M.b2 + kHidden;
+    M.w2_bf16 = c->mlp_w2;
+    M.rc = c->mlp_rc;
+    M.scale = c->mlp_scale;
+    M.tw = c->mlp_tw;
+    M.r_min = c->mlp_rmin;
+    return M;
+}
+
 // Verlet list from the current (sorted) centres; grows the capacity on overflow.
 adres_status build_list(adres_ctx *c)
 {
@@ -149,6 +203,7 @@ adres_status build_list(adres_ctx *c)
         if (st != ADRES_OK) return st;
         if (!c->ctrl_host->overflow) {
             c->list_valid = true;
+            if (c->P.cg_kind >= ADRES_CG_MLP) return build_half_list(c);
             return ADRES_OK;
         }
         int need = c->ctrl_host->max_count;
@@ -180,8 +235,15 @@ ForceArgs force_args(adres_ctx *c)
     return a;
 }
 
-adres_status run_forces(adres_ctx *c, const ForceArgs &a)
+adres_status run_forces(adres_ctx *c, ForceArgs a)
 {
+    if (is_mlp(c)) {
+        launch_mlp_forward_pairs(c->stream, mlp_dev(c), c->P, c->up_pairs, a.Rw, c->f_pair, c->n_up, c->ctrl,
+                                 a.check_halt, a.step);
+        HIPCHK(c, hipGetLastError());
+        a.pid = c->pid;
+        a.f_pair = c->f_pair;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
         if (c->events_used == c->events.size()) {
@@ -205,7 +267,7 @@ adres_status check_cg_ready(adres_ctx *c)
 {
     if (c->P.cg_kind == ADRES_CG_TABLE && !c->tab)
         return fail(c, ADRES_E_STATE, "cg_kind is TABLE but no table was installed");
-    if (c->P.cg_kind == ADRES_CG_MLP || c->P.cg_kind == ADRES_CG_MLP_FP8)
+    if (is_mlp(c) && !c->have_mlp)
         return fail(c, ADRES_E_STATE, "MLP CG force requested but no network is installed");
     return ADRES_OK;
 }
@@ -236,7 +298,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     if (q.region < ADRES_REGION_ALL_AT || q.region > ADRES_REGION_ALL_CG) return ADRES_E_ARG;
     if ((q.region == ADRES_REGION_SLAB_X || q.region == ADRES_REGION_SPHERE) && (q.d_at < 0.0 || q.d_hy < 0.0))
         return ADRES_E_ARG;
-    if (q.cg_kind < ADRES_CG_WCA || q.cg_kind > ADRES_CG_MLP_FP8) return ADRES_E_ARG;
+    if (q.cg_kind < ADRES_CG_WCA || q.cg_kind > ADRES_CG_MLP) return ADRES_E_ARG;
     if (q.bond_kind < ADRES_BOND_NONE || q.bond_kind > ADRES_BOND_FENE) return ADRES_E_ARG;
     if (q.bond_kind == ADRES_BOND_FENE && (q.sites_per_mol != 1 || q.chain_len < 1 || !(q.r0_bond > 0.0)))
         return ADRES_E_ARG;
@@ -345,6 +407,8 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
          dalloc(&c->fill, G.n_cells) == hipSuccess && dalloc(&c->new_from, n) == hipSuccess &&
          dalloc(&c->nbr, (size_t)c->cap * n) == hipSuccess && dalloc(&c->cnt, n) == hipSuccess &&
          dalloc(&c->ctrl, 1) == hipSuccess;
+    ok = ok && dalloc(&c->cnt_up, n) == hipSuccess && dalloc(&c->up_off, (size_t)n + 1) == hipSuccess &&
+         dalloc(&c->up_scratch, n) == hipSuccess;
     c->epart_blocks = force_blocks(n);
     ok = ok && dalloc(&c->epart, 3 * (size_t)c->epart_blocks) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&c->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) == hipSuccess;
@@ -360,6 +424,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
               hipMemcpy(c->S[0].perm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->S[1].perm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice) == hipSuccess &&
               hipMemset(c->count, 0, sizeof(int) * G.n_cells) == hipSuccess &&
+              hipMemset(c->cnt_up, 0, sizeof(int) * n) == hipSuccess &&
               hipMemcpy(c->ctrl, &c0, sizeof(Ctrl), hipMemcpyHostToDevice) == hipSuccess;
     if (!cp) {
         adres_destroy(c);
@@ -382,6 +447,8 @@ void adres_destroy(adres_ctx *c)
     hipFree(c->R_ref); hipFree(c->inv_perm); hipFree(c->cell_rank); hipFree(c->rank_cell);
     hipFree(c->count); hipFree(c->start); hipFree(c->fill); hipFree(c->new_from);
     hipFree(c->nbr); hipFree(c->cnt); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
+    hipFree(c->mlp); hipFree(c->mlp_w2); hipFree(c->cnt_up); hipFree(c->up_off); hipFree(c->up_scratch);
+    hipFree(c->pid); hipFree(c->up_pairs); hipFree(c->f_pair);
     if (c->ctrl_host) hipHostFree(c->ctrl_host);
     for (auto &e : c->events) {
         hipEventDestroy(e.first);
@@ -605,6 +672,49 @@ adres_status adres_set_cg_table(adres_ctx *c, const float *coef4, int32_t n_knot
     c->P.tab_n = n_knots;
     c->P.tab_lo = r_lo;
     c->P.tab_h = (r_hi - r_lo) / (double)(n_knots - 1);
+    return ADRES_OK;
+}
+
+adres_status adres_mlp_set(adres_ctx *c, const float *params, int32_t n_params, double rc, double scale,
+                           double taper_width, double r_min)
+{
+    if (!c || !params) return fail(c, ADRES_E_ARG, "null argument");
+    if (n_params != kMlpParams) return fail(c, ADRES_E_ARG, "the network has 4353 parameters (hidden width 64)");
+    if (!(rc > 0.0) || !(taper_width > 0.0) || taper_width > rc || !(r_min >= 0.0) || !std::isfinite(scale))
+        return fail(c, ADRES_E_ARG, "need rc > 0, 0 < taper_width <= rc, r_min >= 0, finite scale");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!c->mlp) {
+        HIPCHK(c, dalloc(&c->mlp, kMlpParams));
+        HIPCHK(c, dalloc(&c->mlp_w2, (size_t)kHidden * kHidden));
+    }
+    HIPCHK(c, hipMemcpy(c->mlp, params, sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
+    launch_mlp_convert(c->stream, c->mlp, c->mlp_w2);
+    HIPCHK(c, hipGetLastError());
+    c->mlp_rc = rc;
+    c->mlp_scale = scale;
+    c->mlp_tw = taper_width;
+    c->mlp_rmin = r_min;
+    c->have_mlp = true;
+    return ADRES_OK;
+}
+
+adres_status adres_mlp_get(adres_ctx *c, float *params, int32_t n_params)
+{
+    if (!c || !params) return fail(c, ADRES_E_ARG, "null argument");
+    if (!c->have_mlp) return fail(c, ADRES_E_STATE, "no network installed");
+    if (n_params != kMlpParams) return fail(c, ADRES_E_ARG, "the network has 4353 parameters");
+    HIPCHK(c, hipMemcpyAsync(params, c->mlp, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ADRES_OK;
+}
+
+adres_status adres_mlp_eval(adres_ctx *c, const double *r, float *f, int64_t n)
+{
+    if (!c || (n > 0 && (!r || !f)) || n < 0) return fail(c, ADRES_E_ARG, "null argument or negative count");
+    if (!c->have_mlp) return fail(c, ADRES_E_STATE, "no network installed");
+    if (n == 0) return ADRES_OK;
+    launch_mlp_forward_r(c->stream, mlp_dev(c), c->P, r, f, n, c->ctrl);
+    HIPCHK(c, hipGetLastError());
     return ADRES_OK;
 }
 

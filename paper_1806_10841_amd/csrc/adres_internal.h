@@ -290,6 +290,10 @@ void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const i
                        const int *cell_rank, const int *start, const double4 *Rw, const int *key, double rl2,
                        int *nbr, int *cnt, int cap, Ctrl *ctrl);
 
+// half list (t < u pairs) + per-entry pair ids; up_off receives n + 1 offsets
+void launch_half_list(hipStream_t s, int n, const int *nbr, const int *cnt, int cap, int *cnt_up, int *up_off,
+                      int *scratch, int2 *pairs, int *pid);
+
 // forces
 enum ForceMode : int {
     kModeForce = 0,   // F(x) only
@@ -316,6 +320,8 @@ struct ForceArgs {
     Ctrl *ctrl;
     int step, check_halt;
     double *epart;                // non-null: per-block energy partials [blocks][3]
+    const int *pid;               // learned CG force: pair id of every list entry
+    const float *f_pair;          //   and the network's f(r) per pair
 };
 int launch_forces(hipStream_t s, const ForceArgs &a, int pair_precision);   // returns block count
 int force_blocks(int n_mol);

@@ -188,7 +188,64 @@ __global__ __launch_bounds__(kBlock) void k_list_build(DevParams P, Grid G, cons
     }
 }
 
+// Half list for per-pair work (the learned CG force): every unordered pair once,
+// as (t, u) with t < u, and for every full-list entry the id of its pair.
+__global__ __launch_bounds__(kBlock) void k_up_count(int n, const int *__restrict__ nbr, const int *__restrict__ cnt,
+                                                     int cap, int *__restrict__ cnt_up)
+{
+    int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n) return;
+    const int *row = nbr + (int64_t)t * cap;
+    int c = 0;
+    for (int k = 0; k < cnt[t]; ++k) c += row[k] > t;
+    cnt_up[t] = c;
+}
+
+__global__ __launch_bounds__(kBlock) void k_up_fill(int n, const int *__restrict__ nbr, const int *__restrict__ cnt,
+                                                    int cap, const int *__restrict__ up_off, int2 *__restrict__ pairs,
+                                                    int *__restrict__ pid)
+{
+    int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n) return;
+    const int *row = nbr + (int64_t)t * cap;
+    int p = up_off[t];
+    for (int k = 0; k < cnt[t]; ++k) {
+        const int u = row[k];
+        if (u > t) {
+            pairs[p] = make_int2(t, u);
+            pid[(int64_t)t * cap + k] = p;
+            ++p;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_up_mirror(int n, const int *__restrict__ nbr, const int *__restrict__ cnt,
+                                                      int cap, int *__restrict__ pid)
+{
+    int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n) return;
+    const int *row = nbr + (int64_t)t * cap;
+    for (int k = 0; k < cnt[t]; ++k) {
+        const int u = row[k];
+        if (u >= t) continue;
+        const int *ru = nbr + (int64_t)u * cap;
+        const int cu = cnt[u];
+        int kk = 0;
+        while (kk < cu && ru[kk] != t) ++kk;   // the list is symmetric: t is in row u
+        pid[(int64_t)t * cap + k] = kk < cu ? pid[(int64_t)u * cap + kk] : 0;
+    }
+}
+
 }  // namespace
+
+void launch_half_list(hipStream_t s, int n, const int *nbr, const int *cnt, int cap, int *cnt_up, int *up_off,
+                      int *scratch, int2 *pairs, int *pid)
+{
+    k_up_count<<<blocks_for(n), kBlock, 0, s>>>(n, nbr, cnt, cap, cnt_up);
+    k_scan_cells<<<1, kScanThreads, 0, s>>>(cnt_up, n, up_off, scratch);
+    k_up_fill<<<blocks_for(n), kBlock, 0, s>>>(n, nbr, cnt, cap, up_off, pairs, pid);
+    k_up_mirror<<<blocks_for(n), kBlock, 0, s>>>(n, nbr, cnt, cap, pid);
+}
 
 void launch_cell_keys(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank,
                       const double4 *Rw, int *key, int *count)

@@ -135,6 +135,8 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs a)
                 PT fr;
                 if (P.cg_kind == ADRES_CG_WCA) {
                     fr = wca_f_over_r<PT>((PT)r2c, sig2C, epsC, uu, ENERGY);
+                } else if (P.cg_kind >= ADRES_CG_MLP) {
+                    fr = (PT)a.f_pair[a.pid[(int64_t)tt * a.cap + k0 + j]] / (PT)sqrt(r2c);
                 } else {
                     const double r = sqrt(r2c);
                     fr = table_f<PT>(P, r, a.ctrl) / (PT)r;
