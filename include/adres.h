@@ -174,6 +174,30 @@ adres_status adres_mlp_get(adres_ctx *ctx, float *params, int32_t n_params);
  * distances: r (device, float64 [n]) -> f (device, float32 [n]).  Asynchronous. */
 adres_status adres_mlp_eval(adres_ctx *ctx, const double *r, float *f, int64_t n);
 
+/* Mapped forces for force matching: the Eq. (1) forces at x (into f, device [3][N_s],
+ * caller order; with region ADRES_REGION_ALL_AT these are the atomistic forces), then
+ * per molecule its centre of mass com [3][n_mol] and the sum of its site forces
+ * f_map [3][n_mol] (intramolecular bond forces cancel in the sum).  Synchronises as
+ * adres_forces does. */
+adres_status adres_map_cg(adres_ctx *ctx, const double *x, double *f, double *com, double *f_map);
+
+/* Force matching of the learned CG force (multiscale coarse-graining, Izvekov & Voth
+ * 2005; the training counterpart of F^CG in Eq. (1)).  The context must describe CG
+ * sites: sites_per_mol = 1, region ADRES_REGION_ALL_CG, cg_kind ADRES_CG_MLP, a network
+ * installed.  com and f_map (device, float64) hold n_frames frames, each [3][n_mol] in
+ * caller order: centres R_I and mapped forces F^map_I.  The prediction is
+ * F_I = sum_J f(r_IJ) (R_I - R_J) / r_IJ over r_IJ < rc (table below r_min), the loss
+ * chi2 = sum_frames sum_I |F_I - F^map_I|^2 / (3 n_frames n_mol).
+ * adres_mlp_fm_grad: loss (host, optional) and its gradient w.r.t. the 4353 parameters
+ * (host float64, optional) at the current parameters; synchronises.
+ * adres_mlp_train_step: the same gradient followed by one Adam step (beta1 0.9, beta2
+ * 0.999, eps 1e-8, learning rate lr > 0) on the FP32 parameters; loss (host, optional)
+ * is the loss before the step; synchronises.  Both rebuild the context's lists per frame. */
+adres_status adres_mlp_fm_grad(adres_ctx *ctx, const double *com, const double *f_map, int32_t n_frames,
+                               double *grad, double *loss);
+adres_status adres_mlp_train_step(adres_ctx *ctx, const double *com, const double *f_map, int32_t n_frames,
+                                  double lr, double *loss);
+
 /* Diagnostic: device time of the force kernels enqueued since the last call, measured
  * with HIP events on the context's stream when enabled (enable != 0 turns it on, 0 off).
  * ms (host) receives the summed duration and launches (host) the number of launches.

@@ -134,9 +134,10 @@ def predicted_forces(params, com, box, rc, scale, tw, H=64, pairs=None, r_min=0.
     return F
 
 
-def fm_loss_and_grad(params, frames, box, rc, scale, tw, H=64, r_min=0.0):
+def fm_loss_and_grad(params, frames, box, rc, scale, tw, H=64, r_min=0.0, table=None):
     """Force-matching loss and its gradient over frames = [(com (3,N), fmap (3,N)), ...].
-    Pairs below r_min (table fallback) carry no gradient."""
+    Pairs below r_min take the table's force (when a table is given) and carry no
+    gradient."""
     n_f = len(frames)
     grad = np.zeros_like(np.asarray(params, dtype=np.float64))
     loss = 0.0
@@ -144,9 +145,9 @@ def fm_loss_and_grad(params, frames, box, rc, scale, tw, H=64, r_min=0.0):
         n = com.shape[1]
         c = 1.0 / (3.0 * n_f * n)
         I, J, r, rhat = pairs_within(com, box, rc)
+        F = predicted_forces(params, com, box, rc, scale, tw, H, pairs=(I, J, r, rhat), r_min=r_min, table=table)
         keep = r >= r_min
         I, J, r, rhat = I[keep], J[keep], r[keep], rhat[:, keep]
-        F = predicted_forces(params, com, box, rc, scale, tw, H, pairs=(I, J, r, rhat))
         e = F - fmap
         loss += c * float((e * e).sum())
         g = 2.0 * c * ((e[:, I] - e[:, J]) * rhat).sum(axis=0)

@@ -63,6 +63,9 @@ _SIGS = {
     "adres_mlp_set": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double], C.c_int),
     "adres_mlp_get": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
     "adres_mlp_eval": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64], C.c_int),
+    "adres_map_cg": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "adres_mlp_fm_grad": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
+    "adres_mlp_train_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_void_p], C.c_int),
     "adres_kernel_timing": ([C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     "adres_last_error": ([C.c_void_p], C.c_char_p),
 }
@@ -218,6 +221,29 @@ class Context:
         f = torch.empty(r.shape[0], dtype=torch.float32, device=r.device)
         self._check(self.lib.adres_mlp_eval(self.h, _ptr(r), _ptr(f), r.shape[0]), "adres_mlp_eval")
         return f
+
+    def map_cg(self, x):
+        """Eq. (1) forces at x, then per molecule (centre of mass, summed force)."""
+        import torch
+        f = torch.empty_like(x)
+        com = torch.empty((3, self.wl.n_mol), dtype=torch.float64, device=x.device)
+        fmap = torch.empty_like(com)
+        self._check(self.lib.adres_map_cg(self.h, _ptr(x), _ptr(f), _ptr(com), _ptr(fmap)), "adres_map_cg")
+        return com, fmap
+
+    def mlp_fm_grad(self, com, fmap):
+        """com, fmap: device float64 tensors (n_frames, 3, n_mol)."""
+        g = np.empty(4353, dtype=np.float64)
+        loss = C.c_double()
+        self._check(self.lib.adres_mlp_fm_grad(self.h, _ptr(com), _ptr(fmap), com.shape[0],
+                                               g.ctypes.data_as(C.c_void_p), C.byref(loss)), "adres_mlp_fm_grad")
+        return loss.value, g
+
+    def mlp_train_step(self, com, fmap, lr):
+        loss = C.c_double()
+        self._check(self.lib.adres_mlp_train_step(self.h, _ptr(com), _ptr(fmap), com.shape[0], lr, C.byref(loss)),
+                    "adres_mlp_train_step")
+        return loss.value
 
     def kernel_timing(self, enable=True):
         ms = C.c_double()

@@ -45,7 +45,11 @@ struct adres_ctx {
 
     // learned CG force
     float *mlp = nullptr;          // FP32 master parameters (kMlpParams)
-    __bf16 *mlp_w2 = nullptr;      // BF16 copy of W2
+    __bf16 *mlp_w2 = nullptr;      // BF16 copy of W2 (kHidden^2) followed by its transpose
+    float *adam_m = nullptr, *adam_v = nullptr;
+    int64_t adam_t = 0;
+    double *grad = nullptr, *loss = nullptr, *res_part = nullptr, *resid = nullptr;
+    float *gpart = nullptr;
     double mlp_rc = 0.0, mlp_scale = 1.0, mlp_tw = 0.0, mlp_rmin = 0.0;
     bool have_mlp = false;
     // half list (every unordered pair once) for per-pair network outputs
@@ -183,6 +187,7 @@ MlpDev mlp_dev(const adres_ctx *c)
     M.b2 = c->mlp + 2 * kHidden + kHidden * kHidden;
     M.w3 = M.b2 + kHidden;
     M.w2_bf16 = c->mlp_w2;
+    M.w2t_bf16 = c->mlp_w2 + kHidden * kHidden;
     M.rc = c->mlp_rc;
     M.scale = c->mlp_scale;
     M.tw = c->mlp_tw;
@@ -449,6 +454,8 @@ void adres_destroy(adres_ctx *c)
     hipFree(c->nbr); hipFree(c->cnt); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
     hipFree(c->mlp); hipFree(c->mlp_w2); hipFree(c->cnt_up); hipFree(c->up_off); hipFree(c->up_scratch);
     hipFree(c->pid); hipFree(c->up_pairs); hipFree(c->f_pair);
+    hipFree(c->adam_m); hipFree(c->adam_v); hipFree(c->grad); hipFree(c->loss); hipFree(c->res_part);
+    hipFree(c->resid); hipFree(c->gpart);
     if (c->ctrl_host) hipHostFree(c->ctrl_host);
     for (auto &e : c->events) {
         hipEventDestroy(e.first);
@@ -685,10 +692,15 @@ adres_status adres_mlp_set(adres_ctx *c, const float *params, int32_t n_params, 
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (!c->mlp) {
         HIPCHK(c, dalloc(&c->mlp, kMlpParams));
-        HIPCHK(c, dalloc(&c->mlp_w2, (size_t)kHidden * kHidden));
+        HIPCHK(c, dalloc(&c->mlp_w2, (size_t)2 * kHidden * kHidden));
+        HIPCHK(c, dalloc(&c->adam_m, kMlpParams));
+        HIPCHK(c, dalloc(&c->adam_v, kMlpParams));
     }
     HIPCHK(c, hipMemcpy(c->mlp, params, sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
-    launch_mlp_convert(c->stream, c->mlp, c->mlp_w2);
+    HIPCHK(c, hipMemset(c->adam_m, 0, sizeof(float) * kMlpParams));
+    HIPCHK(c, hipMemset(c->adam_v, 0, sizeof(float) * kMlpParams));
+    c->adam_t = 0;
+    launch_mlp_convert(c->stream, c->mlp, c->mlp_w2, c->mlp_w2 + kHidden * kHidden);
     HIPCHK(c, hipGetLastError());
     c->mlp_rc = rc;
     c->mlp_scale = scale;
@@ -714,6 +726,92 @@ adres_status adres_mlp_eval(adres_ctx *c, const double *r, float *f, int64_t n)
     if (!c->have_mlp) return fail(c, ADRES_E_STATE, "no network installed");
     if (n == 0) return ADRES_OK;
     launch_mlp_forward_r(c->stream, mlp_dev(c), c->P, r, f, n, c->ctrl);
+    HIPCHK(c, hipGetLastError());
+    return ADRES_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Loss and gradient of force matching over n_frames frames of CG sites (accumulated
+// on the device in c->loss and c->grad).
+adres_status fm_accumulate(adres_ctx *c, const double *com, const double *fmap, int32_t n_frames)
+{
+    if (!com || !fmap || n_frames < 1) return fail(c, ADRES_E_ARG, "need frames of centres and mapped forces");
+    if (c->P.spm != 1 || c->P.region != ADRES_REGION_ALL_CG || !is_mlp(c))
+        return fail(c, ADRES_E_STATE, "force matching needs a context of CG sites (1 site, all CG, MLP kind)");
+    if (!c->have_mlp) return fail(c, ADRES_E_STATE, "no network installed");
+    const int n = c->P.n_mol;
+    if (!c->grad) {
+        const bool ok = dalloc(&c->grad, kMlpParams) == hipSuccess && dalloc(&c->loss, 1) == hipSuccess &&
+                        dalloc(&c->res_part, (size_t)(n + 255) / 256) == hipSuccess &&
+                        dalloc(&c->resid, 3 * (size_t)n) == hipSuccess &&
+                        dalloc(&c->gpart, (size_t)mlp_backward_waves() * kMlpParams) == hipSuccess;
+        if (!ok) return fail(c, ADRES_E_NOMEM, "could not allocate training buffers");
+    }
+    launch_zero(c->stream, c->grad, kMlpParams);
+    launch_zero(c->stream, c->loss, 1);
+    const double cc = 1.0 / (3.0 * (double)n_frames * (double)n);
+    for (int fr = 0; fr < n_frames; ++fr) {
+        const double *x = com + (size_t)fr * 3 * n;
+        const double *fm = fmap + (size_t)fr * 3 * n;
+        adres_status st = full_build(c, x, nullptr);
+        if (st != ADRES_OK) return st;
+        ForceArgs a = force_args(c);
+        a.f = c->f;
+        st = run_forces(c, a);
+        if (st != ADRES_OK) return st;
+        const StateBufs b = cur(c);
+        int n_part = 0;
+        launch_fm_residual(c->stream, n, b.perm, c->f, fm, c->resid, c->res_part, &n_part);
+        launch_loss_accumulate(c->stream, c->res_part, n_part, cc, c->loss);
+        launch_mlp_backward(c->stream, mlp_dev(c), c->P, c->up_pairs, c->n_up, b.Rw, c->resid, 2.0 * cc, c->gpart,
+                            c->grad);
+        HIPCHK(c, hipGetLastError());
+    }
+    return ADRES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+adres_status adres_mlp_fm_grad(adres_ctx *c, const double *com, const double *f_map, int32_t n_frames,
+                               double *grad_host, double *loss_host)
+{
+    if (!c) return ADRES_E_ARG;
+    adres_status st = fm_accumulate(c, com, f_map, n_frames);
+    if (st != ADRES_OK) return st;
+    if (grad_host)
+        HIPCHK(c, hipMemcpyAsync(grad_host, c->grad, sizeof(double) * kMlpParams, hipMemcpyDeviceToHost, c->stream));
+    if (loss_host) HIPCHK(c, hipMemcpyAsync(loss_host, c->loss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    return read_ctrl(c);
+}
+
+adres_status adres_mlp_train_step(adres_ctx *c, const double *com, const double *f_map, int32_t n_frames, double lr,
+                                  double *loss_host)
+{
+    if (!c) return ADRES_E_ARG;
+    if (!(lr > 0.0)) return fail(c, ADRES_E_ARG, "learning rate must be positive");
+    adres_status st = fm_accumulate(c, com, f_map, n_frames);
+    if (st != ADRES_OK) return st;
+    const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+    ++c->adam_t;
+    const double bc1 = 1.0 - std::pow(b1, (double)c->adam_t), bc2 = 1.0 - std::pow(b2, (double)c->adam_t);
+    launch_adam(c->stream, c->mlp, c->adam_m, c->adam_v, c->grad, lr, b1, b2, bc1, bc2, eps);
+    launch_mlp_convert(c->stream, c->mlp, c->mlp_w2, c->mlp_w2 + kHidden * kHidden);
+    HIPCHK(c, hipGetLastError());
+    if (loss_host) HIPCHK(c, hipMemcpyAsync(loss_host, c->loss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    return read_ctrl(c);
+}
+
+adres_status adres_map_cg(adres_ctx *c, const double *x, double *f, double *com, double *f_map)
+{
+    if (!c || !x || !f || !com || !f_map) return fail(c, ADRES_E_ARG, "null argument");
+    adres_status st = adres_forces(c, x, f, nullptr);
+    if (st != ADRES_OK) return st;
+    launch_map_cg(c->stream, c->P, x, f, com, f_map);
     HIPCHK(c, hipGetLastError());
     return ADRES_OK;
 }

@@ -16,7 +16,8 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // (row = output unit) b2[H] W3[H] b3) and the BF16 copy of W2 used by the MFMA.
 struct MlpDev {
     const float *w1, *b1, *w2, *b2, *w3;   // w3[kHidden] is b3
-    const __bf16 *w2_bf16;
+    const __bf16 *w2_bf16;    // W2, row = output unit
+    const __bf16 *w2t_bf16;   // W2 transposed, row = input unit
     double rc, scale, tw, r_min;
 };
 
@@ -24,7 +25,18 @@ void launch_mlp_forward_r(hipStream_t s, const MlpDev &M, const DevParams &P, co
                           Ctrl *ctrl);
 void launch_mlp_forward_pairs(hipStream_t s, const MlpDev &M, const DevParams &P, const int2 *pairs,
                               const double4 *Rw, float *f, int64_t n, Ctrl *ctrl, int check_halt, int step);
-// FP32 master -> BF16 W2 copy
-void launch_mlp_convert(hipStream_t s, const float *params, __bf16 *w2_bf16);
+// FP32 master -> BF16 copies of W2 and of its transpose
+void launch_mlp_convert(hipStream_t s, const float *params, __bf16 *w2_bf16, __bf16 *w2t_bf16);
+
+// force matching
+int mlp_backward_waves();
+void launch_fm_residual(hipStream_t s, int n, const int *perm, const double *F, const double *fmap, double *e,
+                        double *part, int *n_part);
+void launch_loss_accumulate(hipStream_t s, const double *part, int n_part, double c, double *loss);
+void launch_mlp_backward(hipStream_t s, const MlpDev &M, const DevParams &P, const int2 *pairs, int64_t n_pairs,
+                         const double4 *Rw, const double *e, double c2, float *gpart, double *grad);
+void launch_zero(hipStream_t s, double *a, int n);
+void launch_adam(hipStream_t s, float *params, float *m, float *v, const double *grad, double lr, double b1,
+                 double b2, double bc1, double bc2, double eps);
 
 }  // namespace adres

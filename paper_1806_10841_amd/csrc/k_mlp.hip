@@ -164,15 +164,18 @@ void launch_mlp_forward_pairs(hipStream_t s, const MlpDev &M, const DevParams &P
 
 namespace adres {
 namespace {
-__global__ void k_mlp_convert(const float *__restrict__ params, __bf16 *__restrict__ w2)
+__global__ void k_mlp_convert(const float *__restrict__ params, __bf16 *__restrict__ w2, __bf16 *__restrict__ w2t)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < kHidden * kHidden) w2[i] = (__bf16)params[2 * kHidden + i];
+    if (i >= kHidden * kHidden) return;
+    const __bf16 b = (__bf16)params[2 * kHidden + i];
+    w2[i] = b;
+    w2t[(i % kHidden) * kHidden + i / kHidden] = b;
 }
 }  // namespace
 
-void launch_mlp_convert(hipStream_t s, const float *params, __bf16 *w2_bf16)
+void launch_mlp_convert(hipStream_t s, const float *params, __bf16 *w2_bf16, __bf16 *w2t_bf16)
 {
-    k_mlp_convert<<<(kHidden * kHidden + 255) / 256, 256, 0, s>>>(params, w2_bf16);
+    k_mlp_convert<<<(kHidden * kHidden + 255) / 256, 256, 0, s>>>(params, w2_bf16, w2t_bf16);
 }
 }  // namespace adres

@@ -131,6 +131,29 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(DevParams P, const double
     store_molecule<SPM>(P, p, t, Rw_out, rho_out, R_ref, ctrl, step);
 }
 
+// Centre of mass and summed force of every molecule (caller order): the mapping of
+// site forces onto the CG sites used as force-matching targets.
+template <int SPM>
+__global__ __launch_bounds__(kBlock) void k_map_cg(DevParams P, const double *__restrict__ x,
+                                                   const double *__restrict__ f, double *__restrict__ com,
+                                                   double *__restrict__ fmap)
+{
+    int a = blockIdx.x * kBlock + threadIdx.x;
+    if (a >= P.n_mol) return;
+    double p[SPM][3], q[SPM][3];
+    load_sites<SPM>(x, P.n_sites, a, p);
+    load_sites<SPM>(f, P.n_sites, a, q);
+    double R[3], rh;
+    mol_com<SPM>(P, p, R, rh);
+    for (int d = 0; d < 3; ++d) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < SPM; ++k) s += q[k][d];
+        com[(int64_t)d * P.n_mol + a] = R[d];
+        fmap[(int64_t)d * P.n_mol + a] = s;
+    }
+}
+
 __global__ void k_reset_halt(Ctrl *ctrl)
 {
     if (threadIdx.x == 0) ctrl->halt = INT_MAX;
@@ -175,5 +198,10 @@ void launch_kick_drift(hipStream_t s, const DevParams &P, const double *x_in, do
 }
 
 void launch_reset_halt(hipStream_t s, Ctrl *ctrl) { k_reset_halt<<<1, 64, 0, s>>>(ctrl); }
+
+void launch_map_cg(hipStream_t s, const DevParams &P, const double *x, const double *f, double *com, double *fmap)
+{
+    ADRES_SPM_DISPATCH(P.spm, (k_map_cg<S_><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, x, f, com, fmap)));
+}
 
 }  // namespace adres

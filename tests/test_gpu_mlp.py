@@ -91,3 +91,75 @@ def test_integrate_with_learned_cg(dev):
     ctx.integrate(xt, vt, ft, 0.005, 200)
     assert torch.isfinite(xt).all()
     assert np.abs(vt.sum(dim=1).cpu().numpy() - p0).max() < 1e-9 * wl.n_mol
+
+
+def _cg_frames(n_frames, n_side=12, seed=21):
+    """Frames of CG centres (jittered lattice at the workload density) with mapped forces
+    drawn from a smooth pair force plus noise (the gradient test needs no physics)."""
+    L = n_side * (1 / 0.1) ** (1 / 3)
+    box = (L, L, L)
+    rng = np.random.default_rng(seed)
+    coms, fmaps = [], []
+    for _ in range(n_frames):
+        com = inputs.wrap_into_box(inputs.lattice_points((n_side,) * 3, box, rng, jitter=0.5), box)
+        coms.append(com)
+        fmaps.append(rng.normal(size=com.shape) * 3.0)
+    return np.stack(coms), np.stack(fmaps), box
+
+
+def _cg_workload(n, box):
+    return inputs.workload("small_cg").with_(n_mol=n, box=box, center=tuple(b / 2 for b in box),
+                                             cg_kind=inputs.CG_MLP, rc_cg=RC, pair_precision=32)
+
+
+def test_fm_gradient_matches_oracle(dev):
+    """Loss and gradient of force matching (2 frames of 1728 sites) against the FP64 oracle.
+    Bar: 2^-6 normwise for the whole gradient and per parameter block (BF16 rounding of h1,
+    W2 and dz2, each 2^-9 relative, through sums with moderate cancellation)."""
+    coms, fmaps, box = _cg_frames(2)
+    n = coms.shape[2]
+    p32 = inputs.mlp_init(31).astype(np.float32)
+    p = p32.astype(np.float64)
+    frames = [(coms[k], fmaps[k]) for k in range(2)]
+    loss_o, g_o = omlp.fm_loss_and_grad(p, frames, box, RC, SCALE, TW)
+    ctx = _ctx(_cg_workload(n, box))
+    ctx.mlp_set(p32, RC, SCALE, TW, 0.0)
+    loss, g = ctx.mlp_fm_grad(torch.tensor(coms, device=dev), torch.tensor(fmaps, device=dev))
+    assert abs(loss - loss_o) <= 2.0 ** -7 * loss_o
+    assert np.linalg.norm(g - g_o) <= 2.0 ** -6 * np.linalg.norm(g_o)
+    H = 64
+    blocks = {"W1": slice(0, H), "b1": slice(H, 2 * H), "W2": slice(2 * H, 2 * H + H * H),
+              "b2": slice(2 * H + H * H, 3 * H + H * H), "W3": slice(3 * H + H * H, 4 * H + H * H)}
+    for name, sl in blocks.items():
+        assert np.linalg.norm(g[sl] - g_o[sl]) <= 2.0 ** -6 * np.linalg.norm(g_o[sl]) + 1e-12, name
+    assert abs(g[-1] - g_o[-1]) <= 2.0 ** -6 * abs(g_o[-1]) + 2.0 ** -6 * np.abs(g_o).max() * 1e-2
+    # deterministic: a second evaluation gives the same bits
+    loss2, g2 = ctx.mlp_fm_grad(torch.tensor(coms, device=dev), torch.tensor(fmaps, device=dev))
+    assert loss2 == loss and np.array_equal(g2, g)
+
+
+def test_adam_step_matches_oracle(dev):
+    """One Adam step on the device equals the oracle's Adam applied to the device gradient."""
+    coms, fmaps, box = _cg_frames(1, seed=22)
+    n = coms.shape[2]
+    p32 = inputs.mlp_init(32).astype(np.float32)
+    ctx = _ctx(_cg_workload(n, box))
+    ctx.mlp_set(p32, RC, SCALE, TW, 0.0)
+    tc, tf = torch.tensor(coms, device=dev), torch.tensor(fmaps, device=dev)
+    _, g = ctx.mlp_fm_grad(tc, tf)
+    ctx.mlp_train_step(tc, tf, 1e-3)
+    q = ctx.mlp_get().astype(np.float64)
+    ref, _, _ = omlp.adam_step(p32.astype(np.float64), g, np.zeros_like(g), np.zeros_like(g), 1, 1e-3)
+    assert np.abs(q - ref).max() <= 1e-6
+
+
+def test_training_reduces_loss(dev):
+    coms, fmaps, box = _cg_frames(2, seed=23)
+    n = coms.shape[2]
+    # mapped forces that a pair force can represent: the CG WCA force of the frames
+    fm = np.stack([omlp.predicted_forces(inputs.mlp_init(40), c, box, RC, SCALE, TW) for c in coms])
+    ctx = _ctx(_cg_workload(n, box))
+    ctx.mlp_set(inputs.mlp_init(41).astype(np.float32), RC, SCALE, TW, 0.0)
+    tc, tf = torch.tensor(coms, device=dev), torch.tensor(fm, device=dev)
+    losses = [ctx.mlp_train_step(tc, tf, 3e-3) for _ in range(60)]
+    assert losses[-1] < 0.2 * losses[0], (losses[0], losses[-1])
