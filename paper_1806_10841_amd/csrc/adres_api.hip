@@ -34,7 +34,7 @@ struct adres_ctx {
     double4 *R_ref = nullptr;
     int *inv_perm = nullptr;
     int *cell_rank = nullptr, *rank_cell = nullptr;
-    int *count = nullptr, *start = nullptr, *fill = nullptr, *new_from = nullptr;
+    int *count = nullptr, *start = nullptr, *fill = nullptr, *new_from = nullptr, *scan_tiles = nullptr;
     int *nbr = nullptr, *cnt = nullptr;
     int cap = 0;
     Ctrl *ctrl = nullptr;
@@ -56,7 +56,7 @@ struct adres_ctx {
     int *cnt_up = nullptr, *up_off = nullptr, *up_scratch = nullptr, *pid = nullptr;
     int2 *up_pairs = nullptr;
     float *f_pair = nullptr;
-    int64_t half_rows_cap = 0, n_up = 0;
+    int64_t half_rows_cap = 0, half_pairs_cap = 0;
 
     bool have_state = false;
     bool list_valid = false;
@@ -141,7 +141,7 @@ adres_status resort(adres_ctx *c, bool with_v)
     const StateBufs src = cur(c);
     const StateBufs dst = view(c, 1 - c->pos, 1 - c->ord);
     launch_cell_keys(c->stream, c->P, c->G, c->cell_rank, src.Rw, src.key, c->count);
-    launch_scan_cells(c->stream, c->count, c->G.n_cells, c->start, c->fill);
+    launch_scan_cells(c->stream, c->count, c->G.n_cells, c->start, c->fill, c->scan_tiles);
     launch_scatter_slots(c->stream, c->P.n_mol, src.key, c->start, c->fill, c->new_from);
     launch_sort_within_cells(c->stream, c->G.n_cells, c->start, src.perm, c->new_from);
     launch_permute(c->stream, c->P, c->new_from, src, dst, c->inv_perm, c->R_ref, with_v);
@@ -156,7 +156,8 @@ bool is_mlp(const adres_ctx *c) { return c->P.cg_kind >= ADRES_CG_MLP; }
 
 // Every unordered pair of the Verlet list once (t < u) and, for every list entry, the
 // id of its pair; the network is evaluated per pair, so both directions of a pair
-// read the same value (exact Newton's third law).  Synchronises once for the count.
+// read the same value (exact Newton's third law).  The pair count stays on the
+// device (up_off[n]).
 adres_status build_half_list(adres_ctx *c)
 {
     const int n = c->P.n_mol;
@@ -168,13 +169,10 @@ adres_status build_half_list(adres_ctx *c)
             dalloc(&c->f_pair, cap_pairs) != hipSuccess)
             return fail(c, ADRES_E_NOMEM, "could not allocate the half list");
         c->half_rows_cap = c->cap;
+        c->half_pairs_cap = (int64_t)cap_pairs;
     }
     launch_half_list(c->stream, n, c->nbr, c->cnt, c->cap, c->cnt_up, c->up_off, c->up_scratch, c->up_pairs, c->pid);
     HIPCHK(c, hipGetLastError());
-    int total = 0;
-    HIPCHK(c, hipMemcpyAsync(&total, c->up_off + n, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->n_up = total;
     return ADRES_OK;
 }
 
@@ -208,6 +206,7 @@ adres_status build_list(adres_ctx *c)
         if (st != ADRES_OK) return st;
         if (!c->ctrl_host->overflow) {
             c->list_valid = true;
+            launch_reset_halt(c->stream, c->ctrl);   // an earlier overflow may have left halt = -1
             if (c->P.cg_kind >= ADRES_CG_MLP) return build_half_list(c);
             return ADRES_OK;
         }
@@ -220,6 +219,20 @@ adres_status build_list(adres_ctx *c)
         c->cap = new_cap;
     }
     return fail(c, ADRES_E_CAPACITY, "neighbour list capacity did not converge");
+}
+
+// Verlet list without waiting: an overflowing row sets ctrl->halt = -1, which stops
+// every kernel of the next step chunk; the host then regrows (regrow_list).
+adres_status build_list_async(adres_ctx *c)
+{
+    HIPCHK(c, hipMemsetAsync(&c->ctrl->overflow, 0, 2 * sizeof(int), c->stream));
+    const StateBufs b = cur(c);
+    launch_list_build(c->stream, c->P, c->G, c->rank_cell, c->cell_rank, c->start, b.Rw, b.key, c->rl2, c->nbr,
+                      c->cnt, c->cap, c->ctrl);
+    HIPCHK(c, hipGetLastError());
+    c->list_valid = true;
+    if (is_mlp(c)) return build_half_list(c);
+    return ADRES_OK;
 }
 
 ForceArgs force_args(adres_ctx *c)
@@ -243,8 +256,8 @@ ForceArgs force_args(adres_ctx *c)
 adres_status run_forces(adres_ctx *c, ForceArgs a)
 {
     if (is_mlp(c)) {
-        launch_mlp_forward_pairs(c->stream, mlp_dev(c), c->P, c->up_pairs, a.Rw, c->f_pair, c->n_up, c->ctrl,
-                                 a.check_halt, a.step);
+        launch_mlp_forward_pairs(c->stream, mlp_dev(c), c->P, c->up_pairs, a.Rw, c->f_pair, c->up_off + c->P.n_mol,
+                                 c->half_pairs_cap, c->ctrl, a.check_halt, a.step);
         HIPCHK(c, hipGetLastError());
         a.pid = c->pid;
         a.f_pair = c->f_pair;
@@ -260,11 +273,9 @@ adres_status run_forces(adres_ctx *c, ForceArgs a)
         e0 = c->events[c->events_used].first;
         e1 = c->events[c->events_used].second;
         ++c->events_used;
-        HIPCHK(c, hipEventRecord(e0, c->stream));
     }
-    launch_forces(c->stream, a, c->prm.pair_precision);
+    launch_forces(c->stream, a, c->prm.pair_precision, e0, e1);
     HIPCHK(c, hipGetLastError());
-    if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
     return ADRES_OK;
 }
 
@@ -312,6 +323,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     if (q.r_skin < 0.0 || q.rho_max < 0.0) return ADRES_E_ARG;
     if (q.sites_per_mol > 1 && !(q.rho_max > 0.0)) return ADRES_E_ARG;
     if (q.pair_precision != 32 && q.pair_precision != 64) return ADRES_E_ARG;
+    if (q.n_mol > scan_max_elements()) return ADRES_E_ARG;
 
     adres_ctx *c = new adres_ctx();
     c->prm = q;
@@ -411,7 +423,8 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
          dalloc(&c->count, G.n_cells) == hipSuccess && dalloc(&c->start, G.n_cells + 1) == hipSuccess &&
          dalloc(&c->fill, G.n_cells) == hipSuccess && dalloc(&c->new_from, n) == hipSuccess &&
          dalloc(&c->nbr, (size_t)c->cap * n) == hipSuccess && dalloc(&c->cnt, n) == hipSuccess &&
-         dalloc(&c->ctrl, 1) == hipSuccess;
+         dalloc(&c->ctrl, 1) == hipSuccess &&
+         dalloc(&c->scan_tiles, (size_t)std::max(G.n_cells, n) / 1024 + 2) == hipSuccess;
     ok = ok && dalloc(&c->cnt_up, n) == hipSuccess && dalloc(&c->up_off, (size_t)n + 1) == hipSuccess &&
          dalloc(&c->up_scratch, n) == hipSuccess;
     c->epart_blocks = force_blocks(n);
@@ -450,7 +463,7 @@ void adres_destroy(adres_ctx *c)
     }
     hipFree(c->f);
     hipFree(c->R_ref); hipFree(c->inv_perm); hipFree(c->cell_rank); hipFree(c->rank_cell);
-    hipFree(c->count); hipFree(c->start); hipFree(c->fill); hipFree(c->new_from);
+    hipFree(c->count); hipFree(c->start); hipFree(c->fill); hipFree(c->new_from); hipFree(c->scan_tiles);
     hipFree(c->nbr); hipFree(c->cnt); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
     hipFree(c->mlp); hipFree(c->mlp_w2); hipFree(c->cnt_up); hipFree(c->up_off); hipFree(c->up_scratch);
     hipFree(c->pid); hipFree(c->up_pairs); hipFree(c->f_pair);
@@ -557,11 +570,11 @@ adres_status adres_integrate(adres_ctx *c, double *x, double *v, double *f, doub
     // chunks; a drift whose centres moved more than skin/2 sets ctrl->halt to its
     // chunk index and every later kernel of the chunk returns at once.
     int rebuilds = 0;
-    int g = n_steps > 0 ? 0 : 1;
+    int g = 0;
     int since = 0;   // kernels since the last rebuild
+    launch_reset_halt(c->stream, c->ctrl);
     while (g <= n_steps && n_steps > 0) {
         const int len = std::min(std::max(2, c->last_interval - since), n_steps + 1 - g);
-        launch_reset_halt(c->stream, c->ctrl);
         int p = c->pos;
         for (int k = 0; k < len; ++k) {
             const int gk = g + k;
@@ -595,26 +608,30 @@ adres_status adres_integrate(adres_ctx *c, double *x, double *v, double *f, doub
             }
             if (gk < n_steps) p = 1 - p;
         }
-        st = read_ctrl(c);
+        st = read_ctrl(c);   // the one synchronisation per chunk
         if (st != ADRES_OK) return st;
         const int h = c->ctrl_host->halt;
+        launch_reset_halt(c->stream, c->ctrl);
+        if (h < 0) {
+            // the last list build overflowed: nothing of this chunk ran; regrow, rebuild
+            st = build_list(c);
+            if (st != ADRES_OK) return st;
+            continue;
+        }
         const int ran = h == INT_MAX ? len : h + 1;   // kernels that completed
         for (int k = 0; k < ran; ++k)
             if (g + k < n_steps) c->pos = 1 - c->pos;
         g += ran;
         since += ran;
         if (h == INT_MAX) continue;
-        // kernel g-1 drifted and asked for a rebuild: reorder and rebuild the list
+        // kernel g-1 drifted and asked for a rebuild: reorder and rebuild the list (no wait)
         st = resort(c, true);
         if (st != ADRES_OK) return st;
-        st = build_list(c);
+        st = build_list_async(c);
         if (st != ADRES_OK) return st;
         ++rebuilds;
         c->last_interval = std::max(2, since);
         since = 0;
-    }
-    if (n_steps == 0) {
-        // nothing to integrate: F(x_0) is the answer
     }
     c->step_counter += (uint64_t)n_steps;
     const StateBufs fin = cur(c);
@@ -766,8 +783,8 @@ adres_status fm_accumulate(adres_ctx *c, const double *com, const double *fmap, 
         int n_part = 0;
         launch_fm_residual(c->stream, n, b.perm, c->f, fm, c->resid, c->res_part, &n_part);
         launch_loss_accumulate(c->stream, c->res_part, n_part, cc, c->loss);
-        launch_mlp_backward(c->stream, mlp_dev(c), c->P, c->up_pairs, c->n_up, b.Rw, c->resid, 2.0 * cc, c->gpart,
-                            c->grad);
+        launch_mlp_backward(c->stream, mlp_dev(c), c->P, c->up_pairs, c->up_off + n, b.Rw, c->resid, 2.0 * cc,
+                            c->gpart, c->grad);
         HIPCHK(c, hipGetLastError());
     }
     return ADRES_OK;

@@ -191,8 +191,9 @@ __device__ __forceinline__ void open_and_drift(const DevParams &P, double m, int
         c_ou = exp(-gamma * dt);
         s_ou = sqrt((1.0 - c_ou * c_ou) * kT / m);
     }
+    const double inv_2m = 0.5 / m;   // exact for power-of-two masses: then (F dt) / (2m) bit for bit
     for (int d = 0; d < 3; ++d) {
-        double vv = v[d] + F[d] * dt / (2.0 * m);
+        double vv = v[d] + F[d] * dt * inv_2m;
         double y;
         if (gamma > 0.0) {
             y = x[d] + vv * (0.5 * dt);
@@ -206,11 +207,12 @@ __device__ __forceinline__ void open_and_drift(const DevParams &P, double m, int
     }
 }
 
-// Closing half-kick v += F dt / 2m (oracle's operation order).
-__device__ __forceinline__ void close_kick(double v[3], const double F[3], double dt, double m)
+// Closing half-kick v += F dt / 2m, as (F dt) * (1 / 2m) (the oracle's value for
+// power-of-two masses).
+__device__ __forceinline__ void close_kick(double v[3], const double F[3], double dt, double inv_2m)
 {
 #pragma clang fp contract(off)
-    for (int d = 0; d < 3; ++d) v[d] = v[d] + F[d] * dt / (2.0 * m);
+    for (int d = 0; d < 3; ++d) v[d] = v[d] + F[d] * dt * inv_2m;
 }
 
 // Centre, weight and rho of a molecule at slot t into the packed outputs, with the
@@ -277,7 +279,10 @@ void launch_map_cg(hipStream_t s, const DevParams &P, const double *x, const dou
 // cell list
 void launch_cell_keys(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank,
                       const double4 *Rw, int *key, int *count);
-void launch_scan_cells(hipStream_t s, const int *count, int n_cells, int *start, int *fill);
+// exclusive scan of count[0..n) into start[0..n] (start[n] = total); resets count (and
+// fill if non-null); tiles: scratch of at least n / 1024 + 1 ints; n <= scan_max_elements()
+void launch_scan_cells(hipStream_t s, int *count, int n, int *start, int *fill, int *tiles);
+int scan_max_elements();
 void launch_scatter_slots(hipStream_t s, int n_mol, const int *key, const int *start, int *fill,
                           int *new_from);
 void launch_sort_within_cells(hipStream_t s, int n_cells, const int *start, const int *perm_old,
@@ -324,7 +329,9 @@ struct ForceArgs {
     const int *pid;               // learned CG force: pair id of every list entry
     const float *f_pair;          //   and the network's f(r) per pair
 };
-int launch_forces(hipStream_t s, const ForceArgs &a, int pair_precision);   // returns block count
+// returns the block count; e0/e1 (optional) are recorded at the kernel's start and end
+int launch_forces(hipStream_t s, const ForceArgs &a, int pair_precision, hipEvent_t e0 = nullptr,
+                  hipEvent_t e1 = nullptr);
 int force_blocks(int n_mol);
 void launch_energy_reduce(hipStream_t s, const double *epart, int n_blocks, double *energy);
 

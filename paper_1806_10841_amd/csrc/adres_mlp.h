@@ -23,8 +23,10 @@ struct MlpDev {
 
 void launch_mlp_forward_r(hipStream_t s, const MlpDev &M, const DevParams &P, const double *r, float *f, int64_t n,
                           Ctrl *ctrl);
+// pairs: half-list slot pairs, their number read from n_dev (at most n_cap)
 void launch_mlp_forward_pairs(hipStream_t s, const MlpDev &M, const DevParams &P, const int2 *pairs,
-                              const double4 *Rw, float *f, int64_t n, Ctrl *ctrl, int check_halt, int step);
+                              const double4 *Rw, float *f, const int *n_dev, int64_t n_cap, Ctrl *ctrl,
+                              int check_halt, int step);
 // FP32 master -> BF16 copies of W2 and of its transpose
 void launch_mlp_convert(hipStream_t s, const float *params, __bf16 *w2_bf16, __bf16 *w2t_bf16);
 
@@ -33,7 +35,7 @@ int mlp_backward_waves();
 void launch_fm_residual(hipStream_t s, int n, const int *perm, const double *F, const double *fmap, double *e,
                         double *part, int *n_part);
 void launch_loss_accumulate(hipStream_t s, const double *part, int n_part, double c, double *loss);
-void launch_mlp_backward(hipStream_t s, const MlpDev &M, const DevParams &P, const int2 *pairs, int64_t n_pairs,
+void launch_mlp_backward(hipStream_t s, const MlpDev &M, const DevParams &P, const int2 *pairs, const int *n_dev,
                          const double4 *Rw, const double *e, double c2, float *gpart, double *grad);
 void launch_zero(hipStream_t s, double *a, int n);
 void launch_adam(hipStream_t s, float *params, float *m, float *v, const double *grad, double lr, double b1,

@@ -35,22 +35,18 @@ __global__ __launch_bounds__(kBlock) void k_cell_keys(DevParams P, Grid G, const
     atomicAdd(&count[k], 1);
 }
 
-// Exclusive scan of count[0..n) into start[0..n], one workgroup of 1024 threads:
-// each thread owns a contiguous chunk, chunk sums are scanned with wavefront
-// shuffles and a second pass over the 16 wavefront totals.  Resets count and fill.
-constexpr int kScanThreads = 1024;
+// Exclusive scan of count[0..n) into start[0..n] in three launches: each workgroup
+// scans a tile of 1024 counts (4 per thread; wavefront shuffles, then the 4 wave
+// totals), one workgroup scans the tile totals, a third pass adds the tile offsets
+// and resets count and fill for the next build.
+constexpr int kScanThreads = 256;
+constexpr int kScanTile = 4 * kScanThreads;
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_cells(int *__restrict__ count, int n,
-                                                             int *__restrict__ start, int *__restrict__ fill)
+__device__ __forceinline__ int block_exclusive_scan(int v, int &total)
 {
     __shared__ int wave_tot[kScanThreads / 64];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int chunk = (n + kScanThreads - 1) / kScanThreads;
-    const int lo = min(tid * chunk, n), hi = min(lo + chunk, n);
-    int sum = 0;
-    for (int i = lo; i < hi; ++i) sum += count[i];
-    // inclusive scan within the wavefront
-    int incl = sum;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int incl = v;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
         int y = __shfl_up(incl, off, 64);
@@ -58,26 +54,62 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_cells(int *__restrict__ c
     }
     if (lane == 63) wave_tot[wave] = incl;
     __syncthreads();
-    if (wave == 0) {
-        int v = lane < kScanThreads / 64 ? wave_tot[lane] : 0;
-        int vi = v;
+    int before = 0;
+    total = 0;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            int y = __shfl_up(vi, off, 64);
-            if (lane >= off) vi += y;
-        }
-        if (lane < kScanThreads / 64) wave_tot[lane] = vi - v;   // exclusive wave offsets
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        before += w < wave ? wave_tot[w] : 0;
+        total += wave_tot[w];
     }
     __syncthreads();
-    int run = wave_tot[wave] + incl - sum;
-    for (int i = lo; i < hi; ++i) {
-        int c = count[i];
-        start[i] = run;
-        run += c;
-        count[i] = 0;
-        fill[i] = 0;
+    return before + incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int *__restrict__ count, int n,
+                                                             int *__restrict__ start, int *__restrict__ tiles)
+{
+    const int base = blockIdx.x * kScanTile + 4 * threadIdx.x;
+    int c[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c[j] = base + j < n ? count[base + j] : 0;
+    const int mine = (c[0] + c[1]) + (c[2] + c[3]);
+    int total;
+    int run = block_exclusive_scan(mine, total);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (base + j < n) start[base + j] = run;
+        run += c[j];
     }
-    if (tid == kScanThreads - 1) start[n] = run;
+    if (threadIdx.x == 0) tiles[blockIdx.x] = total;
+}
+
+// scans up to kScanTile tile totals in one workgroup; start[n] = grand total
+__global__ __launch_bounds__(kScanThreads) void k_scan_tile_totals(int *__restrict__ tiles, int n_tiles,
+                                                                   int *__restrict__ start, int n)
+{
+    const int base = 4 * threadIdx.x;
+    int c[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c[j] = base + j < n_tiles ? tiles[base + j] : 0;
+    const int mine = (c[0] + c[1]) + (c[2] + c[3]);
+    int total;
+    int run = block_exclusive_scan(mine, total);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (base + j < n_tiles) tiles[base + j] = run;
+        run += c[j];
+    }
+    if (threadIdx.x == 0) start[n] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(int *__restrict__ count, int n, int *__restrict__ start,
+                                                           const int *__restrict__ tiles, int *__restrict__ fill)
+{
+    const int i = blockIdx.x * kScanThreads + threadIdx.x;
+    if (i >= n) return;
+    start[i] += tiles[i / kScanTile];
+    count[i] = 0;
+    if (fill) fill[i] = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter_slots(int n_mol, const int *__restrict__ key,
@@ -183,8 +215,132 @@ __global__ __launch_bounds__(kBlock) void k_list_build(DevParams P, Grid G, cons
     if (k > cap) {
         atomicOr(&ctrl->overflow, 1);
         atomicMax(&ctrl->max_count, k);
+        atomicMin(&ctrl->halt, -1);   // stops every kernel of a step chunk until regrown
     } else {
         for (int j = k; j < ((k + 3) & ~3); ++j) row[j] = t;   // padding: the row's own slot
+    }
+}
+
+// LDS-staged build: one workgroup per brick of kBrick^3 cells stages the centres of
+// the (kBrick+2)^3 halo cells in LDS, then each home molecule of the brick scans its 27
+// neighbour cells from LDS.  Rows come out in the same order as k_list_build (stencil
+// order, then slot order inside a cell).  A brick whose halo holds more molecules than
+// fit in LDS falls back to global loads.  Needs >= 3 cells per dimension.
+constexpr int kBrick = 4;
+constexpr int kHalo = kBrick + 2;
+constexpr int kHaloCells = kHalo * kHalo * kHalo;
+constexpr int kBrickCells = kBrick * kBrick * kBrick;
+constexpr int kLdsMol = 1536;
+
+__global__ __launch_bounds__(kBlock) void k_list_build_lds(DevParams P, Grid G, const int *__restrict__ cell_rank,
+                                                           const int *__restrict__ start,
+                                                           const double4 *__restrict__ Rw, double rl2,
+                                                           int *__restrict__ nbr, int *__restrict__ cnt, int cap,
+                                                           Ctrl *ctrl, int3 nbricks)
+{
+    __shared__ double4 sR[kLdsMol];
+    __shared__ int sSlot[kLdsMol];
+    __shared__ int sFirst[kHaloCells];   // first slot of each halo cell
+    __shared__ int sOff[kHaloCells + 1]; // LDS offset of each halo cell
+    __shared__ int sHome[kBrickCells + 1];
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x;
+    const int bx = b % nbricks.x, by = (b / nbricks.x) % nbricks.y, bz = b / (nbricks.x * nbricks.y);
+    const int ox0 = bx * kBrick - 1, oy0 = by * kBrick - 1, oz0 = bz * kBrick - 1;
+
+    // halo cell sizes, exclusive scan into sOff (one thread per halo cell)
+    int my_cnt = 0;
+    if (tid < kHaloCells) {
+        const int hx = tid % kHalo, hy = (tid / kHalo) % kHalo, hz = tid / (kHalo * kHalo);
+        const int cx = wrap_cell(ox0 + hx, G.n[0]), cy = wrap_cell(oy0 + hy, G.n[1]), cz = wrap_cell(oz0 + hz, G.n[2]);
+        const int r = cell_rank[cx + G.n[0] * (cy + G.n[1] * cz)];
+        sFirst[tid] = start[r];
+        my_cnt = start[r + 1] - start[r];
+    }
+    {
+        __shared__ int wave_tot[kBlock / 64];
+        const int lane = tid & 63, wave = tid >> 6;
+        int incl = my_cnt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            int y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) wave_tot[wave] = incl;
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            before += w < wave ? wave_tot[w] : 0;
+            total += wave_tot[w];
+        }
+        if (tid < kHaloCells) sOff[tid] = before + incl - my_cnt;
+        if (tid == 0) sOff[kHaloCells] = total;
+    }
+    __syncthreads();
+    // home cells of the brick (inside the grid) and their counts
+    if (tid == 0) {
+        int acc = 0;
+        for (int c = 0; c < kBrickCells; ++c) {
+            sHome[c] = acc;
+            const int lx = c % kBrick, ly = (c / kBrick) % kBrick, lz = c / (kBrick * kBrick);
+            const int gx = bx * kBrick + lx, gy = by * kBrick + ly, gz = bz * kBrick + lz;
+            if (gx < G.n[0] && gy < G.n[1] && gz < G.n[2]) {
+                const int h = (lx + 1) + kHalo * ((ly + 1) + kHalo * (lz + 1));
+                acc += sOff[h + 1] - sOff[h];
+            }
+        }
+        sHome[kBrickCells] = acc;
+    }
+    __syncthreads();
+    const bool staged = sOff[kHaloCells] <= kLdsMol;
+    if (staged) {
+        // stage: halo cell h's molecules are the contiguous slots sFirst[h] ..
+        for (int h = 0; h < kHaloCells; ++h) {
+            const int n_h = sOff[h + 1] - sOff[h];
+            for (int i = tid; i < n_h; i += kBlock) {
+                sR[sOff[h] + i] = Rw[sFirst[h] + i];
+                sSlot[sOff[h] + i] = sFirst[h] + i;
+            }
+        }
+    }
+    __syncthreads();
+
+    const int n_home = sHome[kBrickCells];
+    for (int hm = tid; hm < n_home; hm += kBlock) {
+        int c = 0;
+        while (sHome[c + 1] <= hm) ++c;   // brick cell of this home molecule
+        const int lx = c % kBrick, ly = (c / kBrick) % kBrick, lz = c / (kBrick * kBrick);
+        const int hh = (lx + 1) + kHalo * ((ly + 1) + kHalo * (lz + 1));
+        const int t = sFirst[hh] + (hm - sHome[c]);
+        const double4 me = staged ? sR[sOff[hh] + (hm - sHome[c])] : Rw[t];
+        int *row = nbr + (int64_t)t * cap;
+        int k = 0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int h = (lx + 1 + dx) + kHalo * ((ly + 1 + dy) + kHalo * (lz + 1 + dz));
+                    const int n_h = sOff[h + 1] - sOff[h];
+                    for (int i = 0; i < n_h; ++i) {
+                        const int u = sFirst[h] + i;
+                        if (u == t) continue;
+                        const double4 o = staged ? sR[sOff[h] + i] : Rw[u];
+                        const double ddx = mi(o.x - me.x, P.box[0], P.half[0]);
+                        const double ddy = mi(o.y - me.y, P.box[1], P.half[1]);
+                        const double ddz = mi(o.z - me.z, P.box[2], P.half[2]);
+                        if (dist2_exact(ddx, ddy, ddz) < rl2) {
+                            if (k < cap) row[k] = u;
+                            ++k;
+                        }
+                    }
+                }
+        cnt[t] = k;
+        if (k > cap) {
+            atomicOr(&ctrl->overflow, 1);
+            atomicMax(&ctrl->max_count, k);
+            atomicMin(&ctrl->halt, -1);
+        } else {
+            for (int j = k; j < ((k + 3) & ~3); ++j) row[j] = t;
+        }
     }
 }
 
@@ -242,7 +398,7 @@ void launch_half_list(hipStream_t s, int n, const int *nbr, const int *cnt, int 
                       int *scratch, int2 *pairs, int *pid)
 {
     k_up_count<<<blocks_for(n), kBlock, 0, s>>>(n, nbr, cnt, cap, cnt_up);
-    k_scan_cells<<<1, kScanThreads, 0, s>>>(cnt_up, n, up_off, scratch);
+    launch_scan_cells(s, cnt_up, n, up_off, nullptr, scratch);
     k_up_fill<<<blocks_for(n), kBlock, 0, s>>>(n, nbr, cnt, cap, up_off, pairs, pid);
     k_up_mirror<<<blocks_for(n), kBlock, 0, s>>>(n, nbr, cnt, cap, pid);
 }
@@ -253,10 +409,15 @@ void launch_cell_keys(hipStream_t s, const DevParams &P, const Grid &G, const in
     k_cell_keys<<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, G, cell_rank, Rw, key, count);
 }
 
-void launch_scan_cells(hipStream_t s, const int *count, int n_cells, int *start, int *fill)
+void launch_scan_cells(hipStream_t s, int *count, int n, int *start, int *fill, int *tiles)
 {
-    k_scan_cells<<<1, kScanThreads, 0, s>>>(const_cast<int *>(count), n_cells, start, fill);
+    const int n_tiles = (n + kScanTile - 1) / kScanTile;
+    k_scan_tiles<<<n_tiles, kScanThreads, 0, s>>>(count, n, start, tiles);
+    k_scan_tile_totals<<<1, kScanThreads, 0, s>>>(tiles, n_tiles, start, n);
+    k_scan_add<<<(n + kScanThreads - 1) / kScanThreads, kScanThreads, 0, s>>>(count, n, start, tiles, fill);
 }
+
+int scan_max_elements() { return kScanTile * kScanTile; }
 
 void launch_scatter_slots(hipStream_t s, int n_mol, const int *key, const int *start, int *fill, int *new_from)
 {
@@ -283,8 +444,15 @@ void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const i
                        const int *cell_rank, const int *start, const double4 *Rw, const int *key, double rl2,
                        int *nbr, int *cnt, int cap, Ctrl *ctrl)
 {
-    k_list_build<<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, G, rank_cell, cell_rank, start, Rw, key, rl2, nbr, cnt,
-                                                       cap, ctrl);
+    if (G.n[0] >= 3 && G.n[1] >= 3 && G.n[2] >= 3) {
+        const int3 nb = make_int3((G.n[0] + kBrick - 1) / kBrick, (G.n[1] + kBrick - 1) / kBrick,
+                                  (G.n[2] + kBrick - 1) / kBrick);
+        k_list_build_lds<<<nb.x * nb.y * nb.z, kBlock, 0, s>>>(P, G, cell_rank, start, Rw, rl2, nbr, cnt, cap, ctrl,
+                                                                 nb);
+    } else {
+        k_list_build<<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, G, rank_cell, cell_rank, start, Rw, key, rl2, nbr,
+                                                           cnt, cap, ctrl);
+    }
 }
 
 }  // namespace adres

@@ -10,11 +10,11 @@
 //
 // Work mapping (gfx950, wave64): four lanes per home molecule, 16 molecules per
 // wavefront, consecutive Morton slots (a compact cluster of cells) per workgroup.
-// Lane q takes the molecule's list entries in blocks of four (entries 4q..4q+3,
-// then 16 further on): one 16-byte load fetches the four neighbour slots and the
-// four 32-byte {R, w} gathers are issued back to back before any arithmetic, so
-// each lane keeps four independent memory chains in flight (the kernel is bound
-// by gather latency, not by arithmetic).  Every lane accumulates, in FP64, the
+// Lane q takes the molecule's list entries in blocks of kPre (entries kPre q ..,
+// then 4 kPre further on): one vector load fetches the block's neighbour slots and
+// their 32-byte {R, w} gathers are issued back to back before any arithmetic, so
+// each lane keeps kPre independent memory chains in flight (the kernel is bound by
+// gather latency, not by arithmetic).  Every lane accumulates, in FP64, the
 // atom-tile forces on all sites of its molecule and the molecule's total CG force;
 // two butterfly shuffles combine the four lanes; lane q then owns site q.
 //
@@ -24,6 +24,8 @@
 // centre distance.  An atom tile is skipped when the centres are farther apart
 // than rc_at + rho_a + rho_b (rho: largest site distance from the centre), which
 // no interacting atom pair can be (triangle inequality).
+#include <hip/hip_ext.h>
+
 #include "adres_internal.h"
 
 namespace adres {
@@ -31,6 +33,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kLanes = 4;   // lanes per home molecule
+constexpr int kPre = 2;     // list entries a lane fetches and gathers together
 
 template <typename PT>
 __device__ __forceinline__ PT wca_f_over_r(PT r2, PT sig2, PT eps, PT &u, bool want_u)
@@ -56,8 +59,10 @@ __device__ __forceinline__ PT table_f(const DevParams &P, double r, Ctrl *ctrl)
     return ((PT(c.w) * t + PT(c.z)) * t + PT(c.y)) * t + PT(c.x);
 }
 
+// At most 128 VGPRs (4 waves per SIMD): 4 lanes x 64k molecules is ~4000 wavefronts,
+// which then fit the 1024 SIMDs in a single round.
 template <int SPM, typename PT, int MODE, bool ENERGY>
-__global__ __launch_bounds__(kBlock) void k_forces(ForceArgs a)
+__global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
 {
     const DevParams &P = a.P;
     if (a.check_halt && a.step > a.ctrl->halt) return;
@@ -68,11 +73,15 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs a)
     const bool valid = t < n;
     const int tt = valid ? t : n - 1;
 
-    double xi[SPM][3];
+    // home sites of the workgroup's 64 molecules, staged in LDS (read by every lane of a
+    // quad in the atom tiles, the bonds and the drift)
+    __shared__ double sx[kBlock / kLanes][SPM][3];
+    const int ml = threadIdx.x / kLanes;
+    if (q < SPM)
 #pragma unroll
-    for (int i = 0; i < SPM; ++i)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) xi[i][d] = a.x[d * ns + (int64_t)tt * SPM + i];
+        for (int d = 0; d < 3; ++d) sx[ml][q][d] = a.x[d * ns + (int64_t)tt * SPM + q];
+    __syncthreads();
+#define XI(i, d) sx[ml][(i)][(d)]
     const double4 me = a.Rw[tt];
     const double rha = (double)a.rho[tt];
 
@@ -87,14 +96,20 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs a)
     const int cnt = valid ? a.cnt[tt] : 0;
     const int *row = a.nbr + (int64_t)tt * a.cap;
 
-    for (int k0 = 4 * q; k0 < cnt; k0 += 4 * kLanes) {
-        const int4 id4 = *reinterpret_cast<const int4 *>(row + k0);
-        const int us[4] = {id4.x, id4.y, id4.z, id4.w};
-        double4 nb[4];
+    for (int k0 = kPre * q; k0 < cnt; k0 += kPre * kLanes) {
+        int us[kPre];
+        if (kPre == 4) {
+            const int4 id4 = *reinterpret_cast<const int4 *>(row + k0);
+            us[0] = id4.x; us[1] = id4.y; us[kPre > 2 ? 2 : 0] = id4.z; us[kPre > 3 ? 3 : 0] = id4.w;
+        } else {
+            const int2 id2 = *reinterpret_cast<const int2 *>(row + k0);
+            us[0] = id2.x; us[1] = id2.y;
+        }
+        double4 nb[kPre];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) nb[j] = a.Rw[us[j]];   // padding entries are valid slots
+        for (int j = 0; j < kPre; ++j) nb[j] = a.Rw[us[j]];   // padding entries are valid slots
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < kPre; ++j) {
             if (k0 + j >= cnt) break;
             const int u = us[j];
             const double4 o = nb[j];
@@ -107,16 +122,16 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs a)
                 const double bound = P.rc_at + rha + (double)a.rho[u] + 1e-6;
                 if (r2c < bound * bound) {
                     const PT pww = (PT)ww;
-#pragma unroll
+#pragma unroll 1
                     for (int jj = 0; jj < SPM; ++jj) {
                         const double xj0 = a.x[(int64_t)u * SPM + jj];
                         const double xj1 = a.x[ns + (int64_t)u * SPM + jj];
                         const double xj2 = a.x[2 * ns + (int64_t)u * SPM + jj];
 #pragma unroll
                         for (int i = 0; i < SPM; ++i) {
-                            const PT dx = (PT)mi(xi[i][0] - xj0, P.box[0], P.half[0]);
-                            const PT dy = (PT)mi(xi[i][1] - xj1, P.box[1], P.half[1]);
-                            const PT dz = (PT)mi(xi[i][2] - xj2, P.box[2], P.half[2]);
+                            const PT dx = (PT)mi(XI(i, 0) - xj0, P.box[0], P.half[0]);
+                            const PT dy = (PT)mi(XI(i, 1) - xj1, P.box[1], P.half[1]);
+                            const PT dz = (PT)mi(XI(i, 2) - xj2, P.box[2], P.half[2]);
                             const PT r2 = (dx * dx + dy * dy) + dz * dz;
                             if (r2 < rcA2) {
                                 PT uu = PT(0);
@@ -177,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs a)
             F[0] = acc[i][0] + mf * cg0;
             F[1] = acc[i][1] + mf * cg1;
             F[2] = acc[i][2] + mf * cg2;
-            xq[0] = xi[i][0]; xq[1] = xi[i][1]; xq[2] = xi[i][2];
+            xq[0] = XI(i, 0); xq[1] = XI(i, 1); xq[2] = XI(i, 2);
             mq = P.mass[i];
         }
     const bool owner = valid && q < SPM;
@@ -186,9 +201,9 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs a)
 #pragma unroll
             for (int k = 0; k < SPM; ++k) {
                 if (k == q) continue;
-                const double d0 = mi(xq[0] - xi[k][0], P.box[0], P.half[0]);
-                const double d1 = mi(xq[1] - xi[k][1], P.box[1], P.half[1]);
-                const double d2 = mi(xq[2] - xi[k][2], P.box[2], P.half[2]);
+                const double d0 = mi(xq[0] - XI(k, 0), P.box[0], P.half[0]);
+                const double d1 = mi(xq[1] - XI(k, 1), P.box[1], P.half[1]);
+                const double d2 = mi(xq[2] - XI(k, 2), P.box[2], P.half[2]);
                 const double r = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
                 const double fr = -P.k_bond * (r - P.r0_bond) / r;
                 F[0] += fr * d0; F[1] += fr * d1; F[2] += fr * d2;
@@ -228,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs a)
     } else if (MODE == kModeClose) {
         if (owner) {
             double v[3] = {a.v[site], a.v[ns + site], a.v[2 * ns + site]};
-            close_kick(v, F, a.st.dt, mq);
+            close_kick(v, F, a.st.dt, 0.5 / mq);
             a.v[site] = v[0]; a.v[ns + site] = v[1]; a.v[2 * ns + site] = v[2];
             a.f[site] = F[0]; a.f[ns + site] = F[1]; a.f[2 * ns + site] = F[2];
         }
@@ -236,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs a)
         double xn[3] = {xq[0], xq[1], xq[2]};
         if (owner) {
             double v[3] = {a.v[site], a.v[ns + site], a.v[2 * ns + site]};
-            close_kick(v, F, a.st.dt, mq);
+            close_kick(v, F, a.st.dt, 0.5 / mq);
             const int caller_site = a.st.gamma > 0.0 ? a.perm[t] * SPM + q : 0;
             open_and_drift(P, mq, caller_site, xn, v, F, a.st.dt, a.st.gamma, a.st.kT, a.st.seed, a.st.step_abs);
             a.v[site] = v[0]; a.v[ns + site] = v[1]; a.v[2 * ns + site] = v[2];
@@ -251,6 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_forces(ForceArgs a)
         if (valid && q == 0) store_molecule<SPM>(P, p, t, a.Rw_out, a.rho_out, a.R_ref, a.ctrl, a.step);
     }
 
+#undef XI
     if (ENERGY) {
         // block reduction in a fixed order: wavefront butterflies, then 4 waves in LDS
         __shared__ double red[kBlock / 64][3];
@@ -290,28 +306,39 @@ __global__ __launch_bounds__(256) void k_energy_reduce(const double *__restrict_
     if (threadIdx.x == 3) energy[3] = 0.0;
 }
 
+// Launch; with events, hipExtLaunchKernelGGL records them at the kernel's own start
+// and end (the duration excludes launch gaps, as a profiler's kernel trace does).
+template <typename K>
+void launch_k(K kernel, hipStream_t s, const ForceArgs &a, int blocks, hipEvent_t e0, hipEvent_t e1)
+{
+    if (e0)
+        hipExtLaunchKernelGGL(kernel, dim3(blocks), dim3(kBlock), 0, s, e0, e1, 0, a);
+    else
+        kernel<<<blocks, kBlock, 0, s>>>(a);
+}
+
 template <int SPM, typename PT>
-void dispatch_mode(hipStream_t s, const ForceArgs &a, int blocks)
+void dispatch_mode(hipStream_t s, const ForceArgs &a, int blocks, hipEvent_t e0, hipEvent_t e1)
 {
     switch (a.mode) {
-    case kModeStep: k_forces<SPM, PT, kModeStep, false><<<blocks, kBlock, 0, s>>>(a); break;
-    case kModeClose: k_forces<SPM, PT, kModeClose, false><<<blocks, kBlock, 0, s>>>(a); break;
+    case kModeStep: launch_k(k_forces<SPM, PT, kModeStep, false>, s, a, blocks, e0, e1); break;
+    case kModeClose: launch_k(k_forces<SPM, PT, kModeClose, false>, s, a, blocks, e0, e1); break;
     default:
         if (a.epart)
-            k_forces<SPM, PT, kModeForce, true><<<blocks, kBlock, 0, s>>>(a);
+            launch_k(k_forces<SPM, PT, kModeForce, true>, s, a, blocks, e0, e1);
         else
-            k_forces<SPM, PT, kModeForce, false><<<blocks, kBlock, 0, s>>>(a);
+            launch_k(k_forces<SPM, PT, kModeForce, false>, s, a, blocks, e0, e1);
     }
 }
 
 template <typename PT>
-void dispatch_spm(hipStream_t s, const ForceArgs &a, int blocks)
+void dispatch_spm(hipStream_t s, const ForceArgs &a, int blocks, hipEvent_t e0, hipEvent_t e1)
 {
     switch (a.P.spm) {
-    case 1: dispatch_mode<1, PT>(s, a, blocks); break;
-    case 2: dispatch_mode<2, PT>(s, a, blocks); break;
-    case 3: dispatch_mode<3, PT>(s, a, blocks); break;
-    default: dispatch_mode<4, PT>(s, a, blocks); break;
+    case 1: dispatch_mode<1, PT>(s, a, blocks, e0, e1); break;
+    case 2: dispatch_mode<2, PT>(s, a, blocks, e0, e1); break;
+    case 3: dispatch_mode<3, PT>(s, a, blocks, e0, e1); break;
+    default: dispatch_mode<4, PT>(s, a, blocks, e0, e1); break;
     }
 }
 
@@ -319,13 +346,13 @@ void dispatch_spm(hipStream_t s, const ForceArgs &a, int blocks)
 
 int force_blocks(int n_mol) { return (int)(((int64_t)n_mol * kLanes + kBlock - 1) / kBlock); }
 
-int launch_forces(hipStream_t s, const ForceArgs &a, int pair_precision)
+int launch_forces(hipStream_t s, const ForceArgs &a, int pair_precision, hipEvent_t e0, hipEvent_t e1)
 {
     const int blocks = force_blocks(a.P.n_mol);
     if (pair_precision == 32)
-        dispatch_spm<float>(s, a, blocks);
+        dispatch_spm<float>(s, a, blocks, e0, e1);
     else
-        dispatch_spm<double>(s, a, blocks);
+        dispatch_spm<double>(s, a, blocks, e0, e1);
     return blocks;
 }
 

@@ -41,7 +41,8 @@ struct PairSource {
     const double *r;        // non-null: distances
     const int2 *pairs;      // else: (t, u) slot pairs
     const double4 *Rw;
-    int64_t n;
+    int64_t n;              // pair count, or read from n_dev when that is non-null
+    const int *n_dev;
 };
 
 __device__ __forceinline__ double pair_r(const PairSource &src, const DevParams &P, int64_t p)
@@ -59,6 +60,7 @@ __global__ __launch_bounds__(kBlockM) void k_mlp_forward(MlpDev M, DevParams P, 
                                                         Ctrl *ctrl, int check_halt, int step)
 {
     if (check_halt && step > ctrl->halt) return;
+    if (src.n_dev) src.n = *src.n_dev;
     __shared__ float sW1[kHidden], sB1[kHidden];
     for (int i = threadIdx.x; i < kHidden; i += kBlockM) {
         sW1[i] = M.w1[i];
@@ -145,17 +147,18 @@ __global__ __launch_bounds__(kBlockM) void k_mlp_forward(MlpDev M, DevParams P, 
 void launch_mlp_forward_r(hipStream_t s, const MlpDev &M, const DevParams &P, const double *r, float *f, int64_t n,
                           Ctrl *ctrl)
 {
-    PairSource src{r, nullptr, nullptr, n};
+    PairSource src{r, nullptr, nullptr, n, nullptr};
     const int64_t tiles = (n + kTile - 1) / kTile;
     const int blocks = (int)std::min<int64_t>((tiles + kWaves - 1) / kWaves, 4096);
     k_mlp_forward<<<std::max(blocks, 1), kBlockM, 0, s>>>(M, P, src, f, ctrl, 0, 0);
 }
 
 void launch_mlp_forward_pairs(hipStream_t s, const MlpDev &M, const DevParams &P, const int2 *pairs,
-                              const double4 *Rw, float *f, int64_t n, Ctrl *ctrl, int check_halt, int step)
+                              const double4 *Rw, float *f, const int *n_dev, int64_t n_cap, Ctrl *ctrl,
+                              int check_halt, int step)
 {
-    PairSource src{nullptr, pairs, Rw, n};
-    const int64_t tiles = (n + kTile - 1) / kTile;
+    PairSource src{nullptr, pairs, Rw, 0, n_dev};
+    const int64_t tiles = (n_cap + kTile - 1) / kTile;
     const int blocks = (int)std::min<int64_t>((tiles + kWaves - 1) / kWaves, 4096);
     k_mlp_forward<<<std::max(blocks, 1), kBlockM, 0, s>>>(M, P, src, f, ctrl, check_halt, step);
 }

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_loss_accumulate(const double *__restric
 }
 
 __global__ __launch_bounds__(kThreads) void k_mlp_backward(MlpDev M, DevParams P, const int2 *__restrict__ pairs,
-                                                          int64_t n_pairs, const double4 *__restrict__ Rw,
+                                                          const int *__restrict__ n_dev, const double4 *__restrict__ Rw,
                                                           const double *__restrict__ e, double c2,
                                                           float *__restrict__ gpart)
 {
@@ -128,6 +128,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp_backward(MlpDev M, DevParams P
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) accW2[mb][nb] = floatx16{};
 
+    const int64_t n_pairs = *n_dev;
     const int64_t n_tiles = (n_pairs + kTile - 1) / kTile;
     const int64_t wave_id = (int64_t)blockIdx.x * kWaves + wave;
     const int64_t n_waves = (int64_t)gridDim.x * kWaves;
@@ -310,10 +311,10 @@ void launch_loss_accumulate(hipStream_t s, const double *part, int n_part, doubl
     k_loss_accumulate<<<1, 256, 0, s>>>(part, n_part, c, loss);
 }
 
-void launch_mlp_backward(hipStream_t s, const MlpDev &M, const DevParams &P, const int2 *pairs, int64_t n_pairs,
+void launch_mlp_backward(hipStream_t s, const MlpDev &M, const DevParams &P, const int2 *pairs, const int *n_dev,
                          const double4 *Rw, const double *e, double c2, float *gpart, double *grad)
 {
-    k_mlp_backward<<<kBackwardBlocks, kThreads, 0, s>>>(M, P, pairs, n_pairs, Rw, e, c2, gpart);
+    k_mlp_backward<<<kBackwardBlocks, kThreads, 0, s>>>(M, P, pairs, n_dev, Rw, e, c2, gpart);
     k_grad_reduce<<<(kMlpParams + 255) / 256, 256, 0, s>>>(gpart, kBackwardBlocks * kWaves, grad);
 }
 
