@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -38,7 +39,10 @@ struct adres_ctx {
     int *nbr = nullptr, *cnt = nullptr;
     int cap = 0;
     Ctrl *ctrl = nullptr;
-    Ctrl *ctrl_host = nullptr;
+    Ctrl *ctrl_host = nullptr;     // last values read by the host
+    CtrlPub *pub = nullptr;        // host-mapped pinned copy written by k_publish
+    CtrlPub *pub_dev = nullptr;    // its device address
+    unsigned pub_seq = 0;
     double *epart = nullptr;
     int epart_blocks = 0;
     float4 *tab = nullptr;
@@ -111,13 +115,28 @@ uint32_t spread3(uint32_t v)
     return r;
 }
 
-// Reads the device control block (synchronises the stream); converts latched error
-// bits into a status and clears them.
+// Reads the device control block once all work enqueued so far has finished: a
+// one-thread kernel publishes it into host-mapped memory with a sequence number the
+// host polls (cheaper than a copy plus a stream synchronisation).  Converts latched
+// error bits into a status and clears them.
 adres_status read_ctrl(adres_ctx *c)
 {
-    HIPCHK(c, hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const unsigned seq = ++c->pub_seq;
+    launch_publish(c->stream, c->ctrl, c->pub_dev, seq);
     HIPCHK(c, hipGetLastError());
+    const auto t0 = std::chrono::steady_clock::now();
+    for (long spin = 0; __atomic_load_n(&c->pub->seq, __ATOMIC_ACQUIRE) != seq; ++spin) {
+        if ((spin & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(5)) {
+            // something is wrong with the stream: let the runtime report it
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            if (__atomic_load_n(&c->pub->seq, __ATOMIC_ACQUIRE) != seq)
+                return fail(c, ADRES_E_HIP, "control word was not published");
+        }
+    }
+    c->ctrl_host->halt = c->pub->halt;
+    c->ctrl_host->err = c->pub->err;
+    c->ctrl_host->overflow = c->pub->overflow;
+    c->ctrl_host->max_count = c->pub->max_count;
     int e = c->ctrl_host->err;
     if (e) {
         HIPCHK(c, hipMemsetAsync(&c->ctrl->err, 0, sizeof(int), c->stream));
@@ -430,6 +449,11 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     c->epart_blocks = force_blocks(n);
     ok = ok && dalloc(&c->epart, 3 * (size_t)c->epart_blocks) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&c->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&c->pub, sizeof(CtrlPub), hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
+    if (ok) {
+        std::memset(c->pub, 0, sizeof(CtrlPub));
+        ok = hipHostGetDevicePointer((void **)&c->pub_dev, c->pub, 0) == hipSuccess;
+    }
     if (!ok) {
         adres_destroy(c);
         return ADRES_E_NOMEM;
@@ -470,6 +494,7 @@ void adres_destroy(adres_ctx *c)
     hipFree(c->adam_m); hipFree(c->adam_v); hipFree(c->grad); hipFree(c->loss); hipFree(c->res_part);
     hipFree(c->resid); hipFree(c->gpart);
     if (c->ctrl_host) hipHostFree(c->ctrl_host);
+    if (c->pub) hipHostFree(c->pub);
     for (auto &e : c->events) {
         hipEventDestroy(e.first);
         hipEventDestroy(e.second);

@@ -28,6 +28,15 @@ struct Ctrl {
     int max_count;  // longest neighbour-list row seen by the last build
 };
 
+// Copy of the control block in host-mapped pinned memory, published by a one-thread
+// kernel after the work it reports on; the host polls seq instead of synchronising
+// the stream.
+struct CtrlPub {
+    int halt, err, overflow, max_count;
+    unsigned seq;
+    int pad[3];
+};
+
 // Parameters in the form the kernels use (passed by value).
 struct DevParams {
     int n_mol, spm;
@@ -274,6 +283,7 @@ void launch_kick_drift(hipStream_t s, const DevParams &P, const double *x_in, do
                        double *x_out, double4 *Rw_out, float *rho_out, const double4 *R_ref, const int *perm,
                        Ctrl *ctrl, int step, const StepArgs &st);
 void launch_reset_halt(hipStream_t s, Ctrl *ctrl);
+void launch_publish(hipStream_t s, const Ctrl *ctrl, CtrlPub *pub, unsigned seq);
 void launch_map_cg(hipStream_t s, const DevParams &P, const double *x, const double *f, double *com, double *fmap);
 
 // cell list

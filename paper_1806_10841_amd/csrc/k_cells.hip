@@ -239,7 +239,6 @@ __global__ __launch_bounds__(kBlock) void k_list_build_lds(DevParams P, Grid G, 
                                                            Ctrl *ctrl, int3 nbricks)
 {
     __shared__ double4 sR[kLdsMol];
-    __shared__ int sSlot[kLdsMol];
     __shared__ int sFirst[kHaloCells];   // first slot of each halo cell
     __shared__ int sOff[kHaloCells + 1]; // LDS offset of each halo cell
     __shared__ int sHome[kBrickCells + 1];
@@ -294,13 +293,17 @@ __global__ __launch_bounds__(kBlock) void k_list_build_lds(DevParams P, Grid G, 
     __syncthreads();
     const bool staged = sOff[kHaloCells] <= kLdsMol;
     if (staged) {
-        // stage: halo cell h's molecules are the contiguous slots sFirst[h] ..
-        for (int h = 0; h < kHaloCells; ++h) {
-            const int n_h = sOff[h + 1] - sOff[h];
-            for (int i = tid; i < n_h; i += kBlock) {
-                sR[sOff[h] + i] = Rw[sFirst[h] + i];
-                sSlot[sOff[h] + i] = sFirst[h] + i;
+        // stage: LDS entry i belongs to the halo cell h with sOff[h] <= i < sOff[h + 1], whose
+        // molecules are the contiguous slots sFirst[h] ..
+        const int total = sOff[kHaloCells];
+        for (int i = tid; i < total; i += kBlock) {
+            int lo = 0, hi = kHaloCells - 1;   // largest h with sOff[h] <= i
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (sOff[mid] <= i) lo = mid; else hi = mid - 1;
             }
+            const int slot = sFirst[lo] + (i - sOff[lo]);
+            sR[i] = Rw[slot];
         }
     }
     __syncthreads();

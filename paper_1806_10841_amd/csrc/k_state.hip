@@ -154,6 +154,19 @@ __global__ __launch_bounds__(kBlock) void k_map_cg(DevParams P, const double *__
     }
 }
 
+__global__ void k_publish(const Ctrl *__restrict__ ctrl, CtrlPub *pub, unsigned seq)
+{
+    if (threadIdx.x != 0) return;
+    volatile CtrlPub *p = pub;
+    p->halt = ctrl->halt;
+    p->err = ctrl->err;
+    p->overflow = ctrl->overflow;
+    p->max_count = ctrl->max_count;
+    __threadfence_system();
+    p->seq = seq;
+    __threadfence_system();
+}
+
 __global__ void k_reset_halt(Ctrl *ctrl)
 {
     if (threadIdx.x == 0) ctrl->halt = INT_MAX;
@@ -198,6 +211,11 @@ void launch_kick_drift(hipStream_t s, const DevParams &P, const double *x_in, do
 }
 
 void launch_reset_halt(hipStream_t s, Ctrl *ctrl) { k_reset_halt<<<1, 64, 0, s>>>(ctrl); }
+
+void launch_publish(hipStream_t s, const Ctrl *ctrl, CtrlPub *pub, unsigned seq)
+{
+    k_publish<<<1, 64, 0, s>>>(ctrl, pub, seq);
+}
 
 void launch_map_cg(hipStream_t s, const DevParams &P, const double *x, const double *f, double *com, double *fmap)
 {
