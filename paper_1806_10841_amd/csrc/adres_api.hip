@@ -88,6 +88,7 @@ StateBufs view(const adres_ctx *c, int pos, int ord)
     b.x = c->S[pos].x;
     b.Rw = c->S[pos].Rw;
     b.rho = c->S[pos].rho;
+    b.off = c->S[pos].off;
     b.v = c->S[ord].v;
     b.perm = c->S[ord].perm;
     b.key = c->S[ord].key;
@@ -262,6 +263,7 @@ ForceArgs force_args(adres_ctx *c)
     a.x = S.x;
     a.Rw = S.Rw;
     a.rho = S.rho;
+    a.off = S.off;
     a.nbr = c->nbr;
     a.cnt = c->cnt;
     a.cap = c->cap;
@@ -434,6 +436,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     for (int b = 0; b < 2; ++b) {
         ok = ok && dalloc(&c->S[b].x, 3 * ns) == hipSuccess && dalloc(&c->S[b].v, 3 * ns) == hipSuccess &&
              dalloc(&c->S[b].Rw, n) == hipSuccess && dalloc(&c->S[b].rho, n) == hipSuccess &&
+             dalloc(&c->S[b].off, 3 * ns) == hipSuccess &&
              dalloc(&c->S[b].perm, n) == hipSuccess && dalloc(&c->S[b].key, n) == hipSuccess;
     }
     ok = ok && dalloc(&c->f, 3 * ns) == hipSuccess;
@@ -482,7 +485,7 @@ void adres_destroy(adres_ctx *c)
     if (c->stream) hipStreamSynchronize(c->stream);
     else hipDeviceSynchronize();
     for (int b = 0; b < 2; ++b) {
-        hipFree(c->S[b].x); hipFree(c->S[b].v); hipFree(c->S[b].Rw);
+        hipFree(c->S[b].x); hipFree(c->S[b].v); hipFree(c->S[b].Rw); hipFree(c->S[b].off);
         hipFree(c->S[b].rho); hipFree(c->S[b].perm); hipFree(c->S[b].key);
     }
     hipFree(c->f);
@@ -606,14 +609,15 @@ adres_status adres_integrate(adres_ctx *c, double *x, double *v, double *f, doub
             StepArgs sa{dt, gamma, kT, seed, c->step_counter + (uint64_t)gk};
             const StateBufs in = view(c, p, c->ord), out = view(c, 1 - p, c->ord);
             if (gk == 0) {
-                launch_kick_drift(c->stream, c->P, in.x, in.v, c->f, out.x, out.Rw, out.rho, c->R_ref, in.perm,
-                                  c->ctrl, k, sa);
+                launch_kick_drift(c->stream, c->P, in.x, in.v, c->f, out.x, out.Rw, out.rho, out.off, c->R_ref,
+                                  in.perm, c->ctrl, k, sa);
                 HIPCHK(c, hipGetLastError());
             } else {
                 ForceArgs a = force_args(c);
                 a.x = in.x;
                 a.Rw = in.Rw;
                 a.rho = in.rho;
+                a.off = in.off;
                 a.v = in.v;
                 a.st = sa;
                 a.step = k;
@@ -623,6 +627,7 @@ adres_status adres_integrate(adres_ctx *c, double *x, double *v, double *f, doub
                     a.x_out = out.x;
                     a.Rw_out = out.Rw;
                     a.rho_out = out.rho;
+                    a.off_out = out.off;
                     a.R_ref = c->R_ref;
                 } else {
                     a.mode = kModeClose;

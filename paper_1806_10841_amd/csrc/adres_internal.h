@@ -229,14 +229,20 @@ __device__ __forceinline__ void close_kick(double v[3], const double F[3], doubl
 // lowers ctrl->halt to halt_value).
 template <int SPM>
 __device__ __forceinline__ void store_molecule(const DevParams &P, const double (&p)[SPM][3], int t,
-                                               double4 *Rw, float *rho, const double4 *R_ref, Ctrl *ctrl,
-                                               int halt_value)
+                                               double4 *Rw, float *rho, float *off, const double4 *R_ref,
+                                               Ctrl *ctrl, int halt_value)
 {
     double R[3], rh;
     mol_com<SPM>(P, p, R, rh);
     const double w = res_weight(P, R);
     Rw[t] = make_double4(R[0], R[1], R[2], w);
     rho[t] = (float)rh;
+    // FP32 site offsets from the centre (minimum image), for FP32 pair displacements
+#pragma unroll
+    for (int k = 0; k < SPM; ++k)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            off[(int64_t)t * (3 * SPM) + 3 * k + d] = (float)mi(p[k][d] - R[d], P.box[d], P.half[d]);
     bool finite = true;
 #pragma unroll
     for (int k = 0; k < SPM; ++k) finite = finite && isfinite(p[k][0]) && isfinite(p[k][1]) && isfinite(p[k][2]);
@@ -262,6 +268,7 @@ struct StateBufs {
     double *v;        // [3][n_sites]
     double4 *Rw;      // [n_mol] {Rx, Ry, Rz, w}
     float *rho;       // [n_mol]
+    float *off;       // [n_mol][sites][3] FP32 site offsets from the centre
     int *perm;        // slot -> caller molecule
     int *key;         // slot -> Morton rank of its cell
 };
@@ -280,8 +287,8 @@ struct StepArgs {
     uint64_t seed, step_abs;
 };
 void launch_kick_drift(hipStream_t s, const DevParams &P, const double *x_in, double *v, const double *f,
-                       double *x_out, double4 *Rw_out, float *rho_out, const double4 *R_ref, const int *perm,
-                       Ctrl *ctrl, int step, const StepArgs &st);
+                       double *x_out, double4 *Rw_out, float *rho_out, float *off_out, const double4 *R_ref,
+                       const int *perm, Ctrl *ctrl, int step, const StepArgs &st);
 void launch_reset_halt(hipStream_t s, Ctrl *ctrl);
 void launch_publish(hipStream_t s, const Ctrl *ctrl, CtrlPub *pub, unsigned seq);
 void launch_map_cg(hipStream_t s, const DevParams &P, const double *x, const double *f, double *com, double *fmap);
@@ -321,6 +328,7 @@ struct ForceArgs {
     const double *x;        // step-n positions (sorted)
     const double4 *Rw;      // step-n centres + weights
     const float *rho;
+    const float *off;       // step-n FP32 site offsets
     const int *nbr, *cnt;
     int cap;
     const int *perm, *inv_perm;   // slot -> caller, caller -> slot
@@ -331,6 +339,7 @@ struct ForceArgs {
     double *x_out;                // kModeStep: step n+1 positions, centres, rho
     double4 *Rw_out;
     float *rho_out;
+    float *off_out;
     const double4 *R_ref;
     StepArgs st;
     Ctrl *ctrl;

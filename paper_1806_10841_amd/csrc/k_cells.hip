@@ -163,6 +163,8 @@ __global__ __launch_bounds__(kBlock) void k_permute(DevParams P, const int *__re
     dst.Rw[t] = r;
     R_ref[t] = r;
     dst.rho[t] = src.rho[i];
+#pragma unroll
+    for (int j = 0; j < 3 * SPM; ++j) dst.off[(int64_t)t * (3 * SPM) + j] = src.off[(int64_t)i * (3 * SPM) + j];
     dst.key[t] = src.key[i];
     int caller = src.perm[i];
     dst.perm[t] = caller;

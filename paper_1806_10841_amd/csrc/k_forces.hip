@@ -19,9 +19,16 @@
 // two butterfly shuffles combine the four lanes; lane q then owns site q.
 //
 // Full (two-sided) list: no atomics, fixed summation order, bit-reproducible.
-// Pair arithmetic in PT (double or float).  In the float variant displacements
-// are formed in FP64 and rounded once; the CG cutoff is decided on the FP64
-// centre distance.  An atom tile is skipped when the centres are farther apart
+// Pair arithmetic in PT (double or float).  In the float variant an atom-pair
+// displacement is the FP64 centre difference rounded once to FP32 plus the two
+// sites' FP32 offsets from their centres (|offset| < rho_max), which keeps it within
+// a few 1e-7 of the FP64 value without FP64 work per atom pair; the CG cutoff is
+// decided on the FP64 centre distance.  The FP64 variant forms every displacement
+// from FP64 coordinates.
+//
+// Workgroups are mapped XCD by XCD: the hardware deals workgroup b to XCD b mod 8,
+// so logical block ranges are assigned per XCD and every XCD's L2 serves one
+// contiguous stretch of Morton slots (a compact region of space).  An atom tile is skipped when the centres are farther apart
 // than rc_at + rho_a + rho_b (rho: largest site distance from the centre), which
 // no interacting atom pair can be (triangle inequality).
 #include <hip/hip_ext.h>
@@ -34,11 +41,25 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kLanes = 4;   // lanes per home molecule
 constexpr int kPre = 2;     // list entries a lane fetches and gathers together
+constexpr int kXcds = 8;
+
+// logical block of this workgroup: XCD k (= blockIdx mod 8) takes a contiguous range
+__device__ __forceinline__ int xcd_block()
+{
+    const int B = gridDim.x, b = blockIdx.x;
+    const int q = B / kXcds, r = B % kXcds, x = b % kXcds, i = b / kXcds;
+    return x * q + (x < r ? x : r) + i;
+}
+
+template <typename PT>
+__device__ __forceinline__ PT recip(PT x) { return PT(1) / x; }
+template <>
+__device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }   // 1 ulp
 
 template <typename PT>
 __device__ __forceinline__ PT wca_f_over_r(PT r2, PT sig2, PT eps, PT &u, bool want_u)
 {
-    PT inv = PT(1) / r2;
+    PT inv = recip<PT>(r2);
     PT s = sig2 * inv;
     PT s6 = s * s * s;
     if (want_u) u = PT(4) * eps * s6 * (s6 - PT(1)) + eps;
@@ -68,7 +89,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     if (a.check_halt && a.step > a.ctrl->halt) return;
     const int n = P.n_mol;
     const int64_t ns = P.n_sites;
-    const int gid = blockIdx.x * kBlock + threadIdx.x;
+    const int blk = xcd_block();
+    const int gid = blk * kBlock + threadIdx.x;
     const int t = gid / kLanes, q = gid % kLanes;
     const bool valid = t < n;
     const int tt = valid ? t : n - 1;
@@ -84,6 +106,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
 #define XI(i, d) sx[ml][(i)][(d)]
     const double4 me = a.Rw[tt];
     const double rha = (double)a.rho[tt];
+    constexpr bool kOff = sizeof(PT) == 4;   // FP32 displacements from site offsets
+    float hoff[SPM][3];
+    if (kOff) {
+#pragma unroll
+        for (int i = 0; i < SPM; ++i)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) hoff[i][d] = a.off[(int64_t)tt * (3 * SPM) + 3 * i + d];
+    }
 
     double acc[SPM][3];
 #pragma unroll
@@ -122,6 +152,40 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                 const double bound = P.rc_at + rha + (double)a.rho[u] + 1e-6;
                 if (r2c < bound * bound) {
                     const PT pww = (PT)ww;
+                    if constexpr (kOff) {
+                        // displacement of home site i to neighbour site jj: (D + off_i) - off_jj
+                        float no[3 * SPM];
+                        if constexpr (SPM == 4) {   // 48 bytes, 16-byte aligned: three vector loads
+                            const float4 *q4 = reinterpret_cast<const float4 *>(a.off + (int64_t)u * 12);
+                            const float4 o0 = q4[0], o1 = q4[1], o2 = q4[2];
+                            no[0] = o0.x; no[1] = o0.y; no[2] = o0.z; no[3] = o0.w;
+                            no[4] = o1.x; no[5] = o1.y; no[6] = o1.z; no[7] = o1.w;
+                            no[8] = o2.x; no[9] = o2.y; no[10] = o2.z; no[11] = o2.w;
+                        } else {
+#pragma unroll
+                            for (int j2 = 0; j2 < 3 * SPM; ++j2) no[j2] = a.off[(int64_t)u * (3 * SPM) + j2];
+                        }
+                        const float Df0 = (float)D0, Df1 = (float)D1, Df2 = (float)D2;
+#pragma unroll
+                        for (int i = 0; i < SPM; ++i) {
+                            const float e0 = Df0 + hoff[i][0], e1 = Df1 + hoff[i][1], e2 = Df2 + hoff[i][2];
+                            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                            for (int jj = 0; jj < SPM; ++jj) {
+                                const float dx = e0 - no[3 * jj], dy = e1 - no[3 * jj + 1], dz = e2 - no[3 * jj + 2];
+                                const float r2 = (dx * dx + dy * dy) + dz * dz;
+                                if (r2 < (float)rcA2) {
+                                    PT uu = PT(0);
+                                    const PT c = pww * wca_f_over_r<PT>((PT)r2, sig2A, epsA, uu, ENERGY);
+                                    s0 += (double)(c * dx);
+                                    s1 += (double)(c * dy);
+                                    s2 += (double)(c * dz);
+                                    if (ENERGY) uat += 0.5 * ww * (double)uu;
+                                }
+                            }
+                            acc[i][0] += s0; acc[i][1] += s1; acc[i][2] += s2;
+                        }
+                    } else {
 #pragma unroll 1
                     for (int jj = 0; jj < SPM; ++jj) {
                         const double xj0 = a.x[(int64_t)u * SPM + jj];
@@ -142,6 +206,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                                 if (ENERGY) uat += 0.5 * ww * (double)uu;
                             }
                         }
+                    }
                     }
                 }
             }
@@ -263,7 +328,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
         for (int k = 0; k < SPM; ++k)
 #pragma unroll
             for (int d = 0; d < 3; ++d) p[k][d] = __shfl(xn[d], k, kLanes);
-        if (valid && q == 0) store_molecule<SPM>(P, p, t, a.Rw_out, a.rho_out, a.R_ref, a.ctrl, a.step);
+        if (valid && q == 0) store_molecule<SPM>(P, p, t, a.Rw_out, a.rho_out, a.off_out, a.R_ref, a.ctrl, a.step);
     }
 
 #undef XI
@@ -283,7 +348,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
         if (threadIdx.x < 3) {
             double s = 0.0;
             for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
-            a.epart[blockIdx.x * 3 + threadIdx.x] = s;
+            a.epart[blk * 3 + threadIdx.x] = s;
         }
     }
 }

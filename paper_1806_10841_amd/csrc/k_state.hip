@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(DevParams P, const double *__
         load_sites<SPM>(vc, P.n_sites, a, q);
         store_sites<SPM>(S.v, P.n_sites, t, q);
     }
-    store_molecule<SPM>(P, p, t, S.Rw, S.rho, R_ref, ctrl, 0);
+    store_molecule<SPM>(P, p, t, S.Rw, S.rho, S.off, R_ref, ctrl, 0);
 }
 
 template <int SPM>
@@ -104,7 +104,7 @@ template <int SPM>
 __global__ __launch_bounds__(kBlock) void k_kick_drift(DevParams P, const double *__restrict__ x_in,
                                                        double *__restrict__ v, const double *__restrict__ f,
                                                        double *__restrict__ x_out, double4 *__restrict__ Rw_out,
-                                                       float *__restrict__ rho_out,
+                                                       float *__restrict__ rho_out, float *__restrict__ off_out,
                                                        const double4 *__restrict__ R_ref,
                                                        const int *__restrict__ perm, Ctrl *ctrl, int step,
                                                        StepArgs st)
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(DevParams P, const double
             p[k][d] = xx[d];
         }
     }
-    store_molecule<SPM>(P, p, t, Rw_out, rho_out, R_ref, ctrl, step);
+    store_molecule<SPM>(P, p, t, Rw_out, rho_out, off_out, R_ref, ctrl, step);
 }
 
 // Centre of mass and summed force of every molecule (caller order): the mapping of
@@ -203,11 +203,11 @@ void launch_scatter_out(hipStream_t s, const DevParams &P, const int *perm, cons
 }
 
 void launch_kick_drift(hipStream_t s, const DevParams &P, const double *x_in, double *v, const double *f,
-                       double *x_out, double4 *Rw_out, float *rho_out, const double4 *R_ref, const int *perm,
-                       Ctrl *ctrl, int step, const StepArgs &st)
+                       double *x_out, double4 *Rw_out, float *rho_out, float *off_out, const double4 *R_ref,
+                       const int *perm, Ctrl *ctrl, int step, const StepArgs &st)
 {
     ADRES_SPM_DISPATCH(P.spm, (k_kick_drift<S_><<<blocks_for(P.n_mol), kBlock, 0, s>>>(
-                                  P, x_in, v, f, x_out, Rw_out, rho_out, R_ref, perm, ctrl, step, st)));
+                                  P, x_in, v, f, x_out, Rw_out, rho_out, off_out, R_ref, perm, ctrl, step, st)));
 }
 
 void launch_reset_halt(hipStream_t s, Ctrl *ctrl) { k_reset_halt<<<1, 64, 0, s>>>(ctrl); }
