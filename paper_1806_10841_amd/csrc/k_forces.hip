@@ -153,7 +153,6 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                 if (r2c < bound * bound) {
                     const PT pww = (PT)ww;
                     if constexpr (kOff) {
-                        // displacement of home site i to neighbour site jj: (D + off_i) - off_jj
                         float no[3 * SPM];
                         if constexpr (SPM == 4) {   // 48 bytes, 16-byte aligned: three vector loads
                             const float4 *q4 = reinterpret_cast<const float4 *>(a.off + (int64_t)u * 12);
@@ -165,14 +164,17 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
 #pragma unroll
                             for (int j2 = 0; j2 < 3 * SPM; ++j2) no[j2] = a.off[(int64_t)u * (3 * SPM) + j2];
                         }
+                        // D + (off_i - off_jj): the same bits with opposite sign from the
+                        // other molecule's side, so pair forces cancel exactly (Newton's third law)
                         const float Df0 = (float)D0, Df1 = (float)D1, Df2 = (float)D2;
 #pragma unroll
                         for (int i = 0; i < SPM; ++i) {
-                            const float e0 = Df0 + hoff[i][0], e1 = Df1 + hoff[i][1], e2 = Df2 + hoff[i][2];
                             double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
                             for (int jj = 0; jj < SPM; ++jj) {
-                                const float dx = e0 - no[3 * jj], dy = e1 - no[3 * jj + 1], dz = e2 - no[3 * jj + 2];
+                                const float dx = Df0 + (hoff[i][0] - no[3 * jj]);
+                                const float dy = Df1 + (hoff[i][1] - no[3 * jj + 1]);
+                                const float dz = Df2 + (hoff[i][2] - no[3 * jj + 2]);
                                 const float r2 = (dx * dx + dy * dy) + dz * dz;
                                 if (r2 < (float)rcA2) {
                                     PT uu = PT(0);
