@@ -245,7 +245,7 @@ adres_status build_list(adres_ctx *c)
 // every kernel of the next step chunk; the host then regrows (regrow_list).
 adres_status build_list_async(adres_ctx *c)
 {
-    HIPCHK(c, hipMemsetAsync(&c->ctrl->overflow, 0, 2 * sizeof(int), c->stream));
+    // overflow / max_count were cleared by the halt reset launched before the reorder
     const StateBufs b = cur(c);
     launch_list_build(c->stream, c->P, c->G, c->rank_cell, c->cell_rank, c->start, b.Rw, b.key, c->rl2, c->nbr,
                       c->cnt, c->cap, c->ctrl);

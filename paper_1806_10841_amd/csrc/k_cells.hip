@@ -6,8 +6,8 @@
 //   caller index (makes the order a pure function of the positions) -> permute
 //   the state into the new order.
 // and the Verlet list of molecule pairs: every molecule scans the 27 cells around
-// its own (fewer when a dimension has < 3 cells) and keeps the molecules whose
-// minimum-image centre distance is strictly below r_list.  The list is stored
+// its own (fewer when a dimension has < 3 cells), one cell per lane, and keeps the
+// molecules whose minimum-image centre distance is strictly below r_list.  The list is stored
 // row-major (ELL): nbr[slot * cap + k]; every row is padded with the row's own
 // slot up to a multiple of 4 so that the force kernel can fetch four entries with
 // one 16-byte load and issue their gathers unconditionally.
@@ -177,174 +177,78 @@ __device__ __forceinline__ int wrap_cell(int c, int n)
     return c >= n ? (c >= 2 * n ? c - 2 * n : c - n) : c;
 }
 
-__global__ __launch_bounds__(kBlock) void k_list_build(DevParams P, Grid G, const int *__restrict__ rank_cell,
-                                                       const int *__restrict__ cell_rank,
-                                                       const int *__restrict__ start, const double4 *__restrict__ Rw,
-                                                       const int *__restrict__ key, double rl2,
-                                                       int *__restrict__ nbr, int *__restrict__ cnt, int cap,
-                                                       Ctrl *ctrl)
+// Lane-per-cell build: 32 lanes per home molecule, lane c (< 27) scans stencil cell c
+// (stencil order: z, then y, then x offset), counts its matches, a 32-lane exclusive
+// scan gives each lane its write offset, and a second pass writes the matches; rows
+// come out in the same order as a sequential scan (stencil order, then slot order
+// inside a cell).  Offsets outside [off_lo, off_hi] (grids with < 3 cells along a
+// dimension) are skipped so that no cell is visited twice.
+constexpr int kCellLanes = 32;
+
+__global__ __launch_bounds__(kBlock) void k_list_build_cells(DevParams P, Grid G, const int *__restrict__ rank_cell,
+                                                             const int *__restrict__ cell_rank,
+                                                             const int *__restrict__ start,
+                                                             const double4 *__restrict__ Rw,
+                                                             const int *__restrict__ key, double rl2,
+                                                             int *__restrict__ nbr, int *__restrict__ cnt, int cap,
+                                                             Ctrl *ctrl)
 {
-    int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= P.n_mol) return;
-    const double4 me = Rw[t];
-    const int c = rank_cell[key[t]];
+    const int gid = blockIdx.x * kBlock + threadIdx.x;
+    const int t = gid / kCellLanes, lane = gid % kCellLanes;
+    const bool valid = t < P.n_mol;
+    const int tt = valid ? t : P.n_mol - 1;
+    const double4 me = Rw[tt];
+    const int c = rank_cell[key[tt]];
     const int cx = c % G.n[0], cy = (c / G.n[0]) % G.n[1], cz = c / (G.n[0] * G.n[1]);
-    int *row = nbr + (int64_t)t * cap;
-    int k = 0;
-    for (int oz = G.off_lo[2]; oz <= G.off_hi[2]; ++oz) {
-        const int z = wrap_cell(cz + oz, G.n[2]);
-        for (int oy = G.off_lo[1]; oy <= G.off_hi[1]; ++oy) {
-            const int y = wrap_cell(cy + oy, G.n[1]);
-            for (int ox = G.off_lo[0]; ox <= G.off_hi[0]; ++ox) {
-                const int x = wrap_cell(cx + ox, G.n[0]);
-                const int r = cell_rank[x + G.n[0] * (y + G.n[1] * z)];
-                const int hi = start[r + 1];
-                for (int u = start[r]; u < hi; ++u) {
-                    if (u == t) continue;
-                    const double4 o = Rw[u];
-                    double dx = mi(o.x - me.x, P.box[0], P.half[0]);
-                    double dy = mi(o.y - me.y, P.box[1], P.half[1]);
-                    double dz = mi(o.z - me.z, P.box[2], P.half[2]);
-                    if (dist2_exact(dx, dy, dz) < rl2) {
-                        if (k < cap) row[k] = u;
-                        ++k;
-                    }
-                }
-            }
-        }
+    const int oz = lane / 9 - 1, oy = (lane / 3) % 3 - 1, ox = lane % 3 - 1;
+    const bool used = valid && lane < 27 && ox >= G.off_lo[0] && ox <= G.off_hi[0] && oy >= G.off_lo[1] &&
+                      oy <= G.off_hi[1] && oz >= G.off_lo[2] && oz <= G.off_hi[2];
+    int lo = 0, hi = 0;
+    if (used) {
+        const int r = cell_rank[wrap_cell(cx + ox, G.n[0]) +
+                                G.n[0] * (wrap_cell(cy + oy, G.n[1]) + G.n[1] * wrap_cell(cz + oz, G.n[2]))];
+        lo = start[r];
+        hi = start[r + 1];
     }
-    cnt[t] = k;
-    if (k > cap) {
-        atomicOr(&ctrl->overflow, 1);
-        atomicMax(&ctrl->max_count, k);
-        atomicMin(&ctrl->halt, -1);   // stops every kernel of a step chunk until regrown
-    } else {
-        for (int j = k; j < ((k + 3) & ~3); ++j) row[j] = t;   // padding: the row's own slot
+    int mine = 0;
+    for (int u = lo; u < hi; ++u) {
+        if (u == t) continue;
+        const double4 o = Rw[u];
+        const double dx = mi(o.x - me.x, P.box[0], P.half[0]);
+        const double dy = mi(o.y - me.y, P.box[1], P.half[1]);
+        const double dz = mi(o.z - me.z, P.box[2], P.half[2]);
+        mine += dist2_exact(dx, dy, dz) < rl2;
     }
-}
-
-// LDS-staged build: one workgroup per brick of kBrick^3 cells stages the centres of
-// the (kBrick+2)^3 halo cells in LDS, then each home molecule of the brick scans its 27
-// neighbour cells from LDS.  Rows come out in the same order as k_list_build (stencil
-// order, then slot order inside a cell).  A brick whose halo holds more molecules than
-// fit in LDS falls back to global loads.  Needs >= 3 cells per dimension.
-constexpr int kBrick = 4;
-constexpr int kHalo = kBrick + 2;
-constexpr int kHaloCells = kHalo * kHalo * kHalo;
-constexpr int kBrickCells = kBrick * kBrick * kBrick;
-constexpr int kLdsMol = 1536;
-
-__global__ __launch_bounds__(kBlock) void k_list_build_lds(DevParams P, Grid G, const int *__restrict__ cell_rank,
-                                                           const int *__restrict__ start,
-                                                           const double4 *__restrict__ Rw, double rl2,
-                                                           int *__restrict__ nbr, int *__restrict__ cnt, int cap,
-                                                           Ctrl *ctrl, int3 nbricks)
-{
-    __shared__ double4 sR[kLdsMol];
-    __shared__ int sFirst[kHaloCells];   // first slot of each halo cell
-    __shared__ int sOff[kHaloCells + 1]; // LDS offset of each halo cell
-    __shared__ int sHome[kBrickCells + 1];
-    const int tid = threadIdx.x;
-    const int b = blockIdx.x;
-    const int bx = b % nbricks.x, by = (b / nbricks.x) % nbricks.y, bz = b / (nbricks.x * nbricks.y);
-    const int ox0 = bx * kBrick - 1, oy0 = by * kBrick - 1, oz0 = bz * kBrick - 1;
-
-    // halo cell sizes, exclusive scan into sOff (one thread per halo cell)
-    int my_cnt = 0;
-    if (tid < kHaloCells) {
-        const int hx = tid % kHalo, hy = (tid / kHalo) % kHalo, hz = tid / (kHalo * kHalo);
-        const int cx = wrap_cell(ox0 + hx, G.n[0]), cy = wrap_cell(oy0 + hy, G.n[1]), cz = wrap_cell(oz0 + hz, G.n[2]);
-        const int r = cell_rank[cx + G.n[0] * (cy + G.n[1] * cz)];
-        sFirst[tid] = start[r];
-        my_cnt = start[r + 1] - start[r];
-    }
-    {
-        __shared__ int wave_tot[kBlock / 64];
-        const int lane = tid & 63, wave = tid >> 6;
-        int incl = my_cnt;
+    int incl = mine;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            int y = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += y;
-        }
-        if (lane == 63) wave_tot[wave] = incl;
-        __syncthreads();
-        int before = 0, total = 0;
-        for (int w = 0; w < kBlock / 64; ++w) {
-            before += w < wave ? wave_tot[w] : 0;
-            total += wave_tot[w];
-        }
-        if (tid < kHaloCells) sOff[tid] = before + incl - my_cnt;
-        if (tid == 0) sOff[kHaloCells] = total;
+    for (int off = 1; off < kCellLanes; off <<= 1) {
+        const int y = __shfl_up(incl, off, kCellLanes);
+        if (lane >= off) incl += y;
     }
-    __syncthreads();
-    // home cells of the brick (inside the grid) and their counts
-    if (tid == 0) {
-        int acc = 0;
-        for (int c = 0; c < kBrickCells; ++c) {
-            sHome[c] = acc;
-            const int lx = c % kBrick, ly = (c / kBrick) % kBrick, lz = c / (kBrick * kBrick);
-            const int gx = bx * kBrick + lx, gy = by * kBrick + ly, gz = bz * kBrick + lz;
-            if (gx < G.n[0] && gy < G.n[1] && gz < G.n[2]) {
-                const int h = (lx + 1) + kHalo * ((ly + 1) + kHalo * (lz + 1));
-                acc += sOff[h + 1] - sOff[h];
+    const int total = __shfl(incl, kCellLanes - 1, kCellLanes);
+    int *row = nbr + (int64_t)tt * cap;
+    int k = incl - mine;
+    if (mine > 0) {
+        for (int u = lo; u < hi; ++u) {
+            if (u == t) continue;
+            const double4 o = Rw[u];
+            const double dx = mi(o.x - me.x, P.box[0], P.half[0]);
+            const double dy = mi(o.y - me.y, P.box[1], P.half[1]);
+            const double dz = mi(o.z - me.z, P.box[2], P.half[2]);
+            if (dist2_exact(dx, dy, dz) < rl2) {
+                if (k < cap) row[k] = u;
+                ++k;
             }
         }
-        sHome[kBrickCells] = acc;
     }
-    __syncthreads();
-    const bool staged = sOff[kHaloCells] <= kLdsMol;
-    if (staged) {
-        // stage: LDS entry i belongs to the halo cell h with sOff[h] <= i < sOff[h + 1], whose
-        // molecules are the contiguous slots sFirst[h] ..
-        const int total = sOff[kHaloCells];
-        for (int i = tid; i < total; i += kBlock) {
-            int lo = 0, hi = kHaloCells - 1;   // largest h with sOff[h] <= i
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (sOff[mid] <= i) lo = mid; else hi = mid - 1;
-            }
-            const int slot = sFirst[lo] + (i - sOff[lo]);
-            sR[i] = Rw[slot];
-        }
-    }
-    __syncthreads();
-
-    const int n_home = sHome[kBrickCells];
-    for (int hm = tid; hm < n_home; hm += kBlock) {
-        int c = 0;
-        while (sHome[c + 1] <= hm) ++c;   // brick cell of this home molecule
-        const int lx = c % kBrick, ly = (c / kBrick) % kBrick, lz = c / (kBrick * kBrick);
-        const int hh = (lx + 1) + kHalo * ((ly + 1) + kHalo * (lz + 1));
-        const int t = sFirst[hh] + (hm - sHome[c]);
-        const double4 me = staged ? sR[sOff[hh] + (hm - sHome[c])] : Rw[t];
-        int *row = nbr + (int64_t)t * cap;
-        int k = 0;
-        for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int h = (lx + 1 + dx) + kHalo * ((ly + 1 + dy) + kHalo * (lz + 1 + dz));
-                    const int n_h = sOff[h + 1] - sOff[h];
-                    for (int i = 0; i < n_h; ++i) {
-                        const int u = sFirst[h] + i;
-                        if (u == t) continue;
-                        const double4 o = staged ? sR[sOff[h] + i] : Rw[u];
-                        const double ddx = mi(o.x - me.x, P.box[0], P.half[0]);
-                        const double ddy = mi(o.y - me.y, P.box[1], P.half[1]);
-                        const double ddz = mi(o.z - me.z, P.box[2], P.half[2]);
-                        if (dist2_exact(ddx, ddy, ddz) < rl2) {
-                            if (k < cap) row[k] = u;
-                            ++k;
-                        }
-                    }
-                }
-        cnt[t] = k;
-        if (k > cap) {
+    if (valid && lane == kCellLanes - 1) {
+        cnt[t] = total;
+        if (total > cap) {
             atomicOr(&ctrl->overflow, 1);
-            atomicMax(&ctrl->max_count, k);
+            atomicMax(&ctrl->max_count, total);
             atomicMin(&ctrl->halt, -1);
         } else {
-            for (int j = k; j < ((k + 3) & ~3); ++j) row[j] = t;
+            for (int j = total; j < ((total + 3) & ~3); ++j) row[j] = t;   // padding: the row's own slot
         }
     }
 }
@@ -449,15 +353,9 @@ void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const i
                        const int *cell_rank, const int *start, const double4 *Rw, const int *key, double rl2,
                        int *nbr, int *cnt, int cap, Ctrl *ctrl)
 {
-    if (G.n[0] >= 3 && G.n[1] >= 3 && G.n[2] >= 3) {
-        const int3 nb = make_int3((G.n[0] + kBrick - 1) / kBrick, (G.n[1] + kBrick - 1) / kBrick,
-                                  (G.n[2] + kBrick - 1) / kBrick);
-        k_list_build_lds<<<nb.x * nb.y * nb.z, kBlock, 0, s>>>(P, G, cell_rank, start, Rw, rl2, nbr, cnt, cap, ctrl,
-                                                                 nb);
-    } else {
-        k_list_build<<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, G, rank_cell, cell_rank, start, Rw, key, rl2, nbr,
-                                                           cnt, cap, ctrl);
-    }
+    const int blocks = (int)(((int64_t)P.n_mol * kCellLanes + kBlock - 1) / kBlock);
+    k_list_build_cells<<<blocks, kBlock, 0, s>>>(P, G, rank_cell, cell_rank, start, Rw, key, rl2, nbr, cnt, cap,
+                                                 ctrl);
 }
 
 }  // namespace adres

@@ -167,9 +167,15 @@ __global__ void k_publish(const Ctrl *__restrict__ ctrl, CtrlPub *pub, unsigned 
     __threadfence_system();
 }
 
+// clears the halt index and the list-overflow report (a fill kernel, so that no
+// memset node is needed between the launches of a step loop)
 __global__ void k_reset_halt(Ctrl *ctrl)
 {
-    if (threadIdx.x == 0) ctrl->halt = INT_MAX;
+    if (threadIdx.x == 0) {
+        ctrl->halt = INT_MAX;
+        ctrl->overflow = 0;
+        ctrl->max_count = 0;
+    }
 }
 
 }  // namespace
