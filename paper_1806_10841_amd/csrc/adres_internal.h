@@ -94,17 +94,28 @@ __device__ __forceinline__ double dist2_exact(double dx, double dy, double dz)
 // Centre of mass of one molecule from its site coordinates p[k][d]:
 // R = x0 + ((m1 d1 + m2 d2) + m3 d3) / M, folded into [0, L).  Also the largest
 // site distance from R.
+// One coordinate of the centre of mass from the sites' coordinate d.
+template <int SPM>
+__device__ __forceinline__ double com_dim(const DevParams &P, const double (&c)[SPM], int d)
+{
+#pragma clang fp contract(off)
+    const double x0 = c[0];
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 1; k < SPM; ++k) acc = acc + P.mass[k] * mi(c[k] - x0, P.box[d], P.half[d]);
+    return fold(x0 + acc / P.M, P.box[d]);
+}
+
 template <int SPM>
 __device__ __forceinline__ void mol_com(const DevParams &P, const double (&p)[SPM][3], double R[3],
                                         double &rho)
 {
 #pragma clang fp contract(off)
     for (int d = 0; d < 3; ++d) {
-        double x0 = p[0][d];
-        double acc = 0.0;
+        double c[SPM];
 #pragma unroll
-        for (int k = 1; k < SPM; ++k) acc = acc + P.mass[k] * mi(p[k][d] - x0, P.box[d], P.half[d]);
-        R[d] = fold(x0 + acc / P.M, P.box[d]);
+        for (int k = 0; k < SPM; ++k) c[k] = p[k][d];
+        R[d] = com_dim<SPM>(P, c, d);
     }
     double rmax2 = 0.0;
 #pragma unroll

@@ -324,13 +324,47 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
             a.v[site] = v[0]; a.v[ns + site] = v[1]; a.v[2 * ns + site] = v[2];
             a.x_out[site] = xn[0]; a.x_out[ns + site] = xn[1]; a.x_out[2 * ns + site] = xn[2];
         }
-        // the molecule's new sites, gathered to every lane of its quad
-        double p[SPM][3];
+        // new centre, weight, rho and offsets, spread over the quad: lane d < 3 forms
+        // coordinate d of the centre (the operation order of mol_com), lane q < SPM its
+        // own site's offset and distance
+        double col[SPM];
+        const int dd = q < 3 ? q : 0;
 #pragma unroll
-        for (int k = 0; k < SPM; ++k)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) p[k][d] = __shfl(xn[d], k, kLanes);
-        if (valid && q == 0) store_molecule<SPM>(P, p, t, a.Rw_out, a.rho_out, a.off_out, a.R_ref, a.ctrl, a.step);
+        for (int k = 0; k < SPM; ++k) {
+            const double c0 = __shfl(xn[0], k, kLanes), c1 = __shfl(xn[1], k, kLanes), c2 = __shfl(xn[2], k, kLanes);
+            col[k] = dd == 0 ? c0 : (dd == 1 ? c1 : c2);
+        }
+        const double Rd = com_dim<SPM>(P, col, dd);
+        const double R0 = __shfl(Rd, 0, kLanes), R1 = __shfl(Rd, 1, kLanes), R2 = __shfl(Rd, 2, kLanes);
+        double r2 = 0.0;
+        if (owner) {
+            const double o0 = mi(xn[0] - R0, P.box[0], P.half[0]);
+            const double o1 = mi(xn[1] - R1, P.box[1], P.half[1]);
+            const double o2 = mi(xn[2] - R2, P.box[2], P.half[2]);
+            r2 = dist2_exact(o0, o1, o2);
+            float *of = a.off_out + (int64_t)t * (3 * SPM) + 3 * q;
+            of[0] = (float)o0; of[1] = (float)o1; of[2] = (float)o2;
+        }
+        double m2 = r2;
+        {
+            const double y1 = __shfl_xor(m2, 1, kLanes);
+            m2 = y1 > m2 ? y1 : m2;
+            const double y2 = __shfl_xor(m2, 2, kLanes);
+            m2 = y2 > m2 ? y2 : m2;
+        }
+        if (valid && q == 0) {
+            const double R[3] = {R0, R1, R2};
+            const double rh = sqrt(m2);
+            a.Rw_out[t] = make_double4(R0, R1, R2, res_weight(P, R));
+            a.rho_out[t] = (float)rh;
+            if (!(isfinite(R0) && isfinite(R1) && isfinite(R2))) atomicOr(&a.ctrl->err, kErrNonFinite);
+            if (SPM > 1 && rh > P.rho_max) atomicOr(&a.ctrl->err, kErrStretch);
+            const double4 rr = a.R_ref[t];
+            const double q0 = mi(R0 - rr.x, P.box[0], P.half[0]);
+            const double q1 = mi(R1 - rr.y, P.box[1], P.half[1]);
+            const double q2 = mi(R2 - rr.z, P.box[2], P.half[2]);
+            if (dist2_exact(q0, q1, q2) > P.half_skin2) atomicMin(&a.ctrl->halt, a.step);
+        }
     }
 
 #undef XI
