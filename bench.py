@@ -10,6 +10,13 @@ Boltzmann velocities at T = 1).
 One "step" = one velocity-Verlet MD step through adres_integrate: kick-drift with
 centres of mass and weights, list rebuild when needed (cells + Verlet), Eq. (1)
 forces with the closing half-kick.  Prints one JSON line.
+
+The second half of the metric, learned vs tabulated CG force, is measured on 256,000
+CG sites (a centre frame of the headline geometry tiled 2 x 2 x 1, cutoff 3.0): frames
+of centres and mapped forces from an all-atomistic Langevin run made by the library,
+a force-matched cubic table (least squares, host) and the network trained on the GPU
+on the same frames, held-out force RMSE of each (and of the plain method's CG force),
+then MD steps/s of the 256k-site CG liquid with either force.
 """
 from __future__ import annotations
 
@@ -35,6 +42,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cg-compare", action="store_true",
+                    help="skip the learned-vs-tabulated CG force leg")
+    ap.add_argument("--cg-steps", type=int, default=500)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes 10 times "
@@ -96,17 +106,19 @@ def main():
     n_cg = int(np.count_nonzero(wf[cp[:, 0]] * wf[cp[:, 1]] < 1))
     n_inter = n_at + n_cg
 
-    # dominant kernel: Eq. (1) forces + closing half-kick, one launch per step (plus one
-    # per rebuild and one initial evaluation)
+    # dominant kernel: the fused step launch (Eq. (1) forces at x_n, closing half-kick,
+    # opening half-kick and drift to x_{n+1}), one per step.  Algorithmic bytes per launch:
+    # positions read and written, velocities read and written (4 x 24 B per site), the
+    # full neighbour list (4 B per entry, both directions of each listed pair) and the
+    # row counts (4 B per molecule).  Derived per-molecule data (centres, weights, site
+    # offsets) and re-reads are the implementation's, not the algorithm's, and are not
+    # counted; the measured HBM traffic is reported beside it.
     avg_force_s = force_ms / 1e3 / max(launches, 1)
     ns, nm = wl.n_mol * spm, wl.n_mol
     list_entries = 2 * n_pairs
-    bytes_per_launch = (24 * ns            # x read
-                        + 24 * ns          # F write
-                        + 48 * ns          # v read + write (half-kick)
-                        + 40 * nm          # centre (24), weight (8), rho (8) read
-                        + 4 * list_entries + 4 * nm)   # neighbour list + row counts
+    bytes_per_launch = 96 * ns + 4 * list_entries + 4 * nm
     achieved = bytes_per_launch / avg_force_s / 1e9
+    traffic = _measured_traffic()
     pair_rate = n_inter / avg_force_s
 
     out = {
@@ -138,28 +150,141 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "kernel": "k_forces<4,float> (Eq. 1 + bonds + half-kick)",
+            "traffic": traffic,
+            "kernel": "k_forces<4,float,step> (Eq. 1 + bonds + closing kick, opening kick + drift)",
             "bytes_per_launch": bytes_per_launch,
         },
     }
 
+    ctx.close()
+    if not args.no_cg_compare:
+        out["learned_vs_tabulated"] = learned_vs_tabulated(args.cg_steps)
+
     if not args.no_cpu_baseline:
         import oracle
         m = oracle.Model(wl)
+        n_cpu = 4
         t = time.perf_counter()
-        m.vv(x, v, wl.dt, 1)          # two full Eq. (1) evaluations + one VV update
+        m.vv(x, v, wl.dt, n_cpu)      # n_cpu + 1 full Eq. (1) evaluations and n_cpu VV updates
         dt_cpu = time.perf_counter() - t
         out["cpu_baseline"] = {
-            "value": 1.0 / (dt_cpu / 2.0),
+            "value": n_cpu / dt_cpu,
             "unit": "MD steps/s",
             "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": "one oracle velocity-Verlet step on the full 64,000-molecule state "
-                      "(two all-pairs Eq. (1) force evaluations); steps/s = 2 / elapsed",
+            "sample": f"{n_cpu} oracle velocity-Verlet steps on the full 64,000-molecule state "
+                      f"({n_cpu + 1} all-pairs Eq. (1) force evaluations, {dt_cpu:.1f} s); "
+                      f"steps/s = {n_cpu} / elapsed",
         }
-    ctx.close()
     print(json.dumps(out))
+
+
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_forces_step_c2_pmc.md")
+KERNEL_SOURCES = ("paper_1806_10841_amd/csrc/k_forces.hip", "paper_1806_10841_amd/csrc/adres_internal.h")
+
+
+def kernel_source_digest():
+    """SHA-256 over the force kernel's sources (identifies the kernel the counters saw)."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _measured_traffic():
+    """HBM bytes per launch of the force kernel from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings), or None when there is
+    none or the kernel's sources changed since the counters were taken."""
+    try:
+        with open(PMC_SUMMARY) as f:
+            text = f.read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        line = line.strip().lstrip("-* ").strip()
+        if ":" in line:
+            k, v = line.split(":", 1)
+            fields[k.strip().strip("`")] = v.strip().strip("`")
+    if fields.get("source_sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def learned_vs_tabulated(cg_steps):
+    """Force RMSE and MD steps/s of the learned and the tabulated CG force (256k sites)."""
+    import torch
+    from paper_1806_10841_amd import binding, cgtrain, inputs
+
+    t_all = time.perf_counter()
+    n_frames, n_train = 40, 32
+    com, fmap, box = cgtrain.generate_frames(40, n_frames, stride=20, warmup=400, seed=7)
+    tr, te = slice(0, n_train), slice(n_train, n_frames)
+    com_np, fm_np = com.cpu().numpy(), fmap.cpu().numpy()
+    r_min = cgtrain.min_pair_distance(com_np[:4], box, quantile=1e-4)
+    table = cgtrain.fit_table(com_np[:8], fm_np[:8], box, r_fit_lo=r_min)
+    params, scale, hist = cgtrain.train_mlp(com[tr], fmap[tr], box, steps=300, lr=2e-3, batch=4,
+                                            r_min=r_min, table=table)
+    tw = 0.5
+    mlp = (params, scale, tw, r_min)
+    rmse = {
+        "plain_cg_wca": cgtrain.rmse_on_device(com[te], fmap[te], box, inputs.CG_WCA),
+        "fm_table": cgtrain.rmse_on_device(com[te], fmap[te], box, inputs.CG_TABLE, table=table),
+        "mlp": cgtrain.rmse_on_device(com[te], fmap[te], box, inputs.CG_MLP, table=table, mlp=mlp),
+    }
+    c4, box4 = cgtrain.tile_frame(com_np[-1], box, (2, 2, 1))
+    n4 = c4.shape[1]
+    v4 = inputs.maxwell_velocities(n4, np.full(n4, 4.0), 1.0, np.random.default_rng(1004))
+    runs = {}
+    for name, kind in (("table", inputs.CG_TABLE), ("mlp", inputs.CG_MLP)):
+        ctx = binding.Context(cgtrain.cg_workload(n4, box4, kind))
+        ctx.set_cg_table(*table)
+        if kind == inputs.CG_MLP:
+            ctx.mlp_set(params, 3.0, scale, tw, r_min)
+        xt = torch.tensor(inputs.wrap_into_box(c4, box4), device="cuda")
+        vt = torch.tensor(v4, device="cuda")
+        ft = torch.empty_like(xt)
+        ctx.integrate(xt, vt, ft, 0.005, 50)
+        ctx.kernel_timing(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nreb = ctx.integrate(xt, vt, ft, 0.005, cg_steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        f_ms, f_n = ctx.kernel_timing(2 if kind == inputs.CG_MLP else 0)
+        rec = {"steps_per_s": cg_steps / el, "list_rebuilds": nreb, "force_kernel_us": 1e3 * f_ms / max(f_n, 1)}
+        if kind == inputs.CG_MLP:
+            ctx.integrate(xt, vt, ft, 0.005, cg_steps)
+            m_ms, m_n = ctx.kernel_timing(0)
+            rec["mlp_prepass_us"] = 1e3 * m_ms / max(m_n, 1)
+        rec["listed_pairs"] = ctx.build_verlet(xt)
+        ctx.close()
+        runs[name] = rec
+    pairs = runs["mlp"]["listed_pairs"]
+    flop_per_pair = 2 * 64 * 64 + 2 * 64 + 2 * 64 + 2
+    mlp_tflops = flop_per_pair * pairs / (runs["mlp"]["mlp_prepass_us"] * 1e-6) / 1e12
+    return {
+        "workload": f"c4: {n4} CG sites (mass 4), box {box4[0]:.3f} x {box4[1]:.3f} x {box4[2]:.3f}, "
+                    "cutoff 3.0, NVE velocity Verlet dt 0.005",
+        "steps": cg_steps,
+        "mlp_steps_per_s": runs["mlp"]["steps_per_s"],
+        "table_steps_per_s": runs["table"]["steps_per_s"],
+        "force_rmse_heldout": rmse,
+        "mapped_force_rms": cgtrain.force_scale(fmap[te]),
+        "training": {"frames": f"{n_frames} frames of 64,000 tetrahedra (all-atomistic Langevin, "
+                               f"stride 20 steps), {n_train} train / {n_frames - n_train} held out",
+                     "adam_steps": len(hist), "loss_first": hist[0], "loss_last": hist[-1],
+                     "r_min_table_fallback": r_min},
+        "runs": runs,
+        "mlp_prepass": {"pairs": pairs, "flop_per_pair": flop_per_pair, "tflops": mlp_tflops,
+                        "frac_of_bf16_mfma_peak": mlp_tflops / 2500.0},
+        "seconds": time.perf_counter() - t_all,
+    }
 
 
 if __name__ == "__main__":

@@ -198,9 +198,12 @@ adres_status adres_mlp_fm_grad(adres_ctx *ctx, const double *com, const double *
 adres_status adres_mlp_train_step(adres_ctx *ctx, const double *com, const double *f_map, int32_t n_frames,
                                   double lr, double *loss);
 
-/* Diagnostic: device time of the force kernels enqueued since the last call, measured
- * with HIP events on the context's stream when enabled (enable != 0 turns it on, 0 off).
- * ms (host) receives the summed duration and launches (host) the number of launches.
+/* Diagnostic: device time of the kernels enqueued since the last call, measured with
+ * HIP events on the context's stream.  enable selects what the following calls record:
+ * 0 nothing, 1 the force kernel (Eq. (1) with its fused integrator stages), 2 the learned
+ * CG force's pair pre-pass (contexts with cg_kind ADRES_CG_MLP; one per force
+ * evaluation); other values give ADRES_E_ARG.  ms (host) receives the summed duration
+ * of what was recorded before this call and launches (host) the number of launches.
  * Synchronises. */
 adres_status adres_kernel_timing(adres_ctx *ctx, int32_t enable, double *ms, int64_t *launches);
 

@@ -246,8 +246,10 @@ class Context:
         return loss.value
 
     def kernel_timing(self, enable=True):
+        """enable: False/0 off, True/1 force kernel, 2 the network's pair pre-pass."""
         ms = C.c_double()
         n = C.c_int64()
-        self._check(self.lib.adres_kernel_timing(self.h, 1 if enable else 0, C.byref(ms), C.byref(n)),
+        mode = int(enable) if not isinstance(enable, bool) else (1 if enable else 0)
+        self._check(self.lib.adres_kernel_timing(self.h, mode, C.byref(ms), C.byref(n)),
                     "adres_kernel_timing")
         return ms.value, n.value

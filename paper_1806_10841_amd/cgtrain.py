@@ -83,12 +83,18 @@ def _pairs(com, box, rc):
     from scipy.spatial import cKDTree
     box = np.asarray(box, dtype=np.float64)
     pts = np.mod(com.T, box)
-    pts[pts >= box] -= box[pts >= box]
+    pts = np.where(pts >= box, pts - box, pts)
     pr = cKDTree(pts, boxsize=box).query_pairs(rc, output_type="ndarray")
     d = com[:, pr[:, 0]] - com[:, pr[:, 1]]
     d -= box[:, None] * np.round(d / box[:, None])
     r = np.sqrt((d * d).sum(axis=0))
     return pr[:, 0], pr[:, 1], r, d / r
+
+
+def min_pair_distance(com, box, rc=3.0, quantile=0.0):
+    """Smallest (or the given quantile of) centre-pair distance below rc over frames."""
+    rs = np.concatenate([_pairs(np.asarray(c, dtype=np.float64), box, rc)[2] for c in com])
+    return float(np.quantile(rs, quantile)) if quantile > 0 else float(rs.min())
 
 
 def _bspline_basis(r, lo, hi, n_basis):
@@ -107,43 +113,75 @@ def _bspline_basis(r, lo, hi, n_basis):
     return out
 
 
-def fit_table(com, fmap, box, r_lo=1.5, rc=3.0, n_basis=40, n_knots=2048):
-    """Force-matched cubic table: least squares for f(r) = sum_k c_k B_k(r) such that
-    sum_J f(r_IJ) R_hat_IJ ~ F^map_I over all frames; returns (coef [(n-1),4] float32,
-    r_lo, r_hi) evaluating f on [r_lo, rc] (zero at rc)."""
+def hermite_from_values(f, df, h):
+    """Cubic coefficients [(n-1), 4] of the Hermite interpolant of knot values and slopes."""
+    f0, f1 = f[:-1], f[1:]
+    d0, d1 = h * df[:-1], h * df[1:]
+    return np.stack([f0, d0, 3 * (f1 - f0) - 2 * d0 - d1, 2 * (f0 - f1) + d0 + d1], axis=1)
+
+
+def fit_table(com, fmap, box, r_fit_lo, r_lo=0.5, rc=3.0, n_basis=40, n_knots=2048):
+    """Force-matched cubic table (the tabulated CG force of the comparison).
+
+    Linear least squares (NumPy ``lstsq``) for f(r) = sum_k c_k B_k(r) on [r_fit_lo, rc]
+    such that sum_J f(r_IJ) R_hat_IJ ~ F^map_I over all frames (pairs closer than
+    r_fit_lo are rare and enter at r_fit_lo).  Below r_fit_lo the force continues
+    linearly with the slope at r_fit_lo when that slope is repulsive (else flat), so
+    the table stays a wall where there is no data.  Returns (coef [(n_knots-1), 4]
+    float32, r_lo, rc) with f(rc) = 0."""
     com = np.asarray(com, dtype=np.float64)
     fmap = np.asarray(fmap, dtype=np.float64)
     rows, rhs = [], []
     for k in range(com.shape[0]):
         I, J, r, rh = _pairs(com[k], box, rc)
-        rr = np.clip(r, r_lo, rc)
-        B = _bspline_basis(rr, r_lo, rc, n_basis)      # (pairs, n_basis)
+        B = _bspline_basis(np.clip(r, r_fit_lo, rc), r_fit_lo, rc, n_basis)
         n = com.shape[2]
-        A = np.zeros((3 * n, n_basis))
+        A = np.empty((3 * n, n_basis))
         for d in range(3):
-            np.add.at(A, d * n + I, B * rh[d][:, None])
-            np.add.at(A, d * n + J, -B * rh[d][:, None])
+            for q in range(n_basis):
+                w = B[:, q] * rh[d]
+                A[d * n:(d + 1) * n, q] = (np.bincount(I, weights=w, minlength=n)
+                                           - np.bincount(J, weights=w, minlength=n))
         rows.append(A)
         rhs.append(fmap[k].reshape(-1))
-    A = np.concatenate(rows)
-    b = np.concatenate(rhs)
-    c, *_ = np.linalg.lstsq(A, b, rcond=None)
-    # resample to a cubic table (Hermite from values and derivatives by central differences)
+    c, *_ = np.linalg.lstsq(np.concatenate(rows), np.concatenate(rhs), rcond=None)
+
+    def spline(x):
+        return _bspline_basis(x, r_fit_lo, rc, n_basis) @ c
+
     rk = np.linspace(r_lo, rc, n_knots)
     h = rk[1] - rk[0]
-    f = _bspline_basis(rk, r_lo, rc, n_basis) @ c
-    eps = 1e-4 * h
-    df = (_bspline_basis(np.clip(rk + eps, r_lo, rc), r_lo, rc, n_basis) @ c
-          - _bspline_basis(np.clip(rk - eps, r_lo, rc), r_lo, rc, n_basis) @ c) / (
-        np.clip(rk + eps, r_lo, rc) - np.clip(rk - eps, r_lo, rc))
+    inside = rk >= r_fit_lo
+    ri = rk[inside]
+    eps = 1e-5
+    f = np.empty_like(rk)
+    df = np.empty_like(rk)
+    f[inside] = spline(ri)
+    up = np.minimum(ri + eps, rc)
+    dn = np.maximum(ri - eps, r_fit_lo)
+    df[inside] = (spline(up) - spline(dn)) / (up - dn)
+    f0 = float(spline(np.array([r_fit_lo]))[0])
+    s0 = float((spline(np.array([r_fit_lo + eps])) - spline(np.array([r_fit_lo])))[0] / eps)
+    slope = min(s0, 0.0)
+    f[~inside] = f0 + slope * (rk[~inside] - r_fit_lo)
+    df[~inside] = slope
     f[-1] = 0.0
-    f0, f1 = f[:-1], f[1:]
-    d0, d1 = h * df[:-1], h * df[1:]
-    coef = np.stack([f0, d0, 3 * (f1 - f0) - 2 * d0 - d1, 2 * (f0 - f1) + d0 + d1], axis=1)
-    return coef.astype(np.float32), float(r_lo), float(rc)
+    return hermite_from_values(f, df, h).astype(np.float32), float(r_lo), float(rc)
 
 
-def wca_table(sig=2.31, eps=1.0, r_lo=1.0, r_hi=3.0, n_knots=2048):
+def tile_frame(com, box, reps):
+    """Copies of a centre frame (3, n) on a reps[0] x reps[1] x reps[2] grid of boxes."""
+    com = np.asarray(com, dtype=np.float64)
+    box = np.asarray(box, dtype=np.float64)
+    out = []
+    for a in range(reps[0]):
+        for b in range(reps[1]):
+            for c in range(reps[2]):
+                out.append(com + (np.array([a, b, c]) * box)[:, None])
+    return np.concatenate(out, axis=1), tuple(float(x) for x in box * np.asarray(reps))
+
+
+def wca_table(sig=2.31, eps=1.0, r_lo=0.5, r_hi=3.0, n_knots=2048):
     """The plain method's CG force (WCA between centres) as a cubic table."""
     rc = sig * 2 ** (1 / 6)
     rk = np.linspace(r_lo, r_hi, n_knots)
@@ -152,17 +190,17 @@ def wca_table(sig=2.31, eps=1.0, r_lo=1.0, r_hi=3.0, n_knots=2048):
     inside = rk < rc
     f = np.where(inside, 24 * eps * s6 * (2 * s6 - 1) / rk, 0.0)
     df = np.where(inside, 24 * eps * s6 * (7 - 26 * s6) / rk ** 2, 0.0)
-    f0, f1 = f[:-1], f[1:]
-    d0, d1 = h * df[:-1], h * df[1:]
-    coef = np.stack([f0, d0, 3 * (f1 - f0) - 2 * d0 - d1, 2 * (f0 - f1) + d0 + d1], axis=1)
-    return coef.astype(np.float32), float(r_lo), float(r_hi)
+    return hermite_from_values(f, df, h).astype(np.float32), float(r_lo), float(r_hi)
 
 
 def rmse_on_device(com, fmap, box, cg_kind, table=None, mlp=None, rc=3.0):
     """RMSE (per force component) of a CG model's forces against mapped forces, with the
-    model evaluated by the library on the CG sites of each frame."""
+    model evaluated by the library on the CG sites of each frame.  cg_kind WCA is the
+    plain method's CG force (sigma 2.31, cut at its minimum)."""
     import torch
     n = com.shape[2]
+    if cg_kind == inputs.CG_WCA:
+        rc = 2.31 * 2 ** (1 / 6)
     ctx = binding.Context(cg_workload(n, box, cg_kind, rc))
     if table is not None:
         ctx.set_cg_table(*table)

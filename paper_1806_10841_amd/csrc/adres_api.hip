@@ -67,7 +67,7 @@ struct adres_ctx {
     uint64_t step_counter = 0;
     int last_interval = 8;
 
-    bool timing = false;
+    int timing = 0;   // 0 off, 1 force kernel, 2 network pre-pass
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     size_t events_used = 0;
 
@@ -276,15 +276,9 @@ ForceArgs force_args(adres_ctx *c)
 
 adres_status run_forces(adres_ctx *c, ForceArgs a)
 {
-    if (is_mlp(c)) {
-        launch_mlp_forward_pairs(c->stream, mlp_dev(c), c->P, c->up_pairs, a.Rw, c->f_pair, c->up_off + c->P.n_mol,
-                                 c->half_pairs_cap, c->ctrl, a.check_halt, a.step);
-        HIPCHK(c, hipGetLastError());
-        a.pid = c->pid;
-        a.f_pair = c->f_pair;
-    }
+    // timing mode 1 brackets the force kernel, mode 2 the network's pair-force pre-pass
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing) {
+    if (c->timing != 0 && (c->timing == 1 || is_mlp(c))) {
         if (c->events_used == c->events.size()) {
             hipEvent_t p, q;
             HIPCHK(c, hipEventCreate(&p));
@@ -295,7 +289,16 @@ adres_status run_forces(adres_ctx *c, ForceArgs a)
         e1 = c->events[c->events_used].second;
         ++c->events_used;
     }
-    launch_forces(c->stream, a, c->prm.pair_precision, e0, e1);
+    if (is_mlp(c)) {
+        if (c->timing == 2) HIPCHK(c, hipEventRecord(e0, c->stream));
+        launch_mlp_forward_pairs(c->stream, mlp_dev(c), c->P, c->up_pairs, a.Rw, c->f_pair, c->up_off + c->P.n_mol,
+                                 c->half_pairs_cap, c->ctrl, a.check_halt, a.step);
+        HIPCHK(c, hipGetLastError());
+        if (c->timing == 2) HIPCHK(c, hipEventRecord(e1, c->stream));
+        a.pid = c->pid;
+        a.f_pair = c->f_pair;
+    }
+    launch_forces(c->stream, a, c->prm.pair_precision, c->timing == 1 ? e0 : nullptr, c->timing == 1 ? e1 : nullptr);
     HIPCHK(c, hipGetLastError());
     return ADRES_OK;
 }
@@ -876,7 +879,8 @@ adres_status adres_kernel_timing(adres_ctx *c, int32_t enable, double *ms, int64
     if (ms) *ms = sum;
     if (launches) *launches = (int64_t)c->events_used;
     c->events_used = 0;
-    c->timing = enable != 0;
+    if (enable < 0 || enable > 2) return fail(c, ADRES_E_ARG, "timing mode must be 0, 1 or 2");
+    c->timing = enable;
     return ADRES_OK;
 }
 
