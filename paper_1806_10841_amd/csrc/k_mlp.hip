@@ -2,16 +2,18 @@
 // x = r / rc, on gfx950 matrix cores.  It stands in for F^CG of Eq. (1) (Sec. 2.2:
 // a force between centres of mass); below r_min the cubic CG table is used instead.
 //
-// One wavefront evaluates a tile of 32 pairs:
+// One wavefront evaluates a tile of 32 pairs, layer 2 computed transposed
+// (Z2^T = W2 H1^T, output units x pairs) so that every result a lane holds belongs to
+// its own pair:
 //   * layer 1 (rank one in x) in VALU: lane l computes, for pair l % 32, the 32 hidden
 //     units 16 kb + 8 (l / 32) + j (kb = 0..3, j = 0..7), applies silu and writes them
-//     as BF16 straight into the A operands of four MFMA K-blocks;
-//   * layer 2 (32 x 64 x 64) on v_mfma_f32_32x32x16_bf16 with FP32 accumulation; W2
-//     (row = output unit, BF16) is held in registers as the B operands for the whole
-//     kernel (lane l: column l % 32 of N-block nb, K rows 8 (l / 32) .. +7);
-//   * layer 3: lane l owns output unit 32 nb + l % 32 of rows 8 (v / 4) + 4 (l / 32) + v % 4,
-//     multiplies silu(z2) by W3 and the 32 lanes of a half-wavefront add their
-//     products with butterfly shuffles.
+//     as BF16 straight into the B operands (column = pair) of four MFMA K-blocks;
+//   * layer 2 (64 x 64 x 32) on v_mfma_f32_32x32x16_bf16 with FP32 accumulation; W2
+//     (row = output unit, BF16) is held in registers as the A operands for the whole
+//     kernel (lane l: row 32 mb + l % 32 of M-block mb, K columns 16 kb + 8 (l / 32) .. +7);
+//   * layer 3: lane l holds, for pair l % 32, output units 32 mb + 8 (v / 4) + 4 (l / 32)
+//     + v % 4 (v = 0..15), multiplies silu(z2) by W3 and adds the two half-wavefronts'
+//     sums with one exchange.
 // Operand and result lane layouts were checked on the device with a known product.
 #include <algorithm>
 
@@ -23,8 +25,6 @@ namespace {
 constexpr int kTile = 32;
 constexpr int kWaves = 4;
 constexpr int kBlockM = 64 * kWaves;
-
-__device__ __forceinline__ float silu_f(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
 // taper(r) = 1 below rc - tw, cos^2 ramp to 0 at rc (same shape as the resolution function)
 __device__ __forceinline__ float taper_f(float r, float rc, float tw)
@@ -61,83 +61,86 @@ __global__ __launch_bounds__(kBlockM) void k_mlp_forward(MlpDev M, DevParams P, 
 {
     if (check_halt && step > ctrl->halt) return;
     if (src.n_dev) src.n = *src.n_dev;
+    // silu(z) = z / (1 + 2^t) with t = -log2(e) z.  The constants are folded so that each
+    // layer works on t directly: layer 1 forms t1 = (-log2e W1) x + (-log2e b1) and hands
+    // g1 = t1 / (1 + 2^t1) = silu(z1) / (-ln 2) to the matrix cores, whose product with W2
+    // plus (-log2e b2) is then t2 = -log2e z2 (log2e ln 2 = 1); layer 3 adds
+    // (-ln 2 W3) t2 / (1 + 2^t2) = W3 silu(z2).
     __shared__ float sW1[kHidden], sB1[kHidden];
+    __shared__ float sW3[kHidden];
+    constexpr float kLog2e = 1.4426950408889634f, kLn2 = 0.6931471805599453f;
     for (int i = threadIdx.x; i < kHidden; i += kBlockM) {
-        sW1[i] = M.w1[i];
-        sB1[i] = M.b1[i];
+        sW1[i] = -kLog2e * M.w1[i];
+        sB1[i] = -kLog2e * M.b1[i];
+        sW3[i] = -kLn2 * M.w3[i];
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
-    // B operands: W2 rows (output units) 32 nb + col, K columns 16 kb + 8 half .. +7
-    bf16x8 Bop[2][4];
+    // A operands: W2 rows (output units) 32 mb + col, K columns 16 kb + 8 half .. +7
+    bf16x8 Wop[2][4];
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
+    for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb)
-            Bop[nb][kb] = *reinterpret_cast<const bf16x8 *>(M.w2_bf16 + (32 * nb + col) * kHidden + 16 * kb + 8 * half);
-    const float b2u[2] = {M.b2[col], M.b2[32 + col]};
-    const float w3u[2] = {M.w3[col], M.w3[32 + col]};
+            Wop[mb][kb] = *reinterpret_cast<const bf16x8 *>(M.w2_bf16 + (32 * mb + col) * kHidden + 16 * kb + 8 * half);
+    // -log2e b2 of the output units of this lane's result rows (32 mb + 8 (v / 4) + 4 half
+    // + v % 4): the accumulator's initial value
+    floatx16 c2[2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) c2[mb][v] = -kLog2e * M.b2[32 * mb + 8 * (v >> 2) + 4 * half + (v & 3)];
     const float b3 = M.w3[kHidden], inv_rc = 1.0f / (float)M.rc, rcf = (float)M.rc, twf = (float)M.tw, sc = (float)M.scale;
 
     const int64_t n_tiles = (src.n + kTile - 1) / kTile;
     const int64_t wave_id = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
     const int64_t n_waves = (int64_t)gridDim.x * kWaves;
     for (int64_t tile = wave_id; tile < n_tiles; tile += n_waves) {
+        __asm__ volatile("" ::: "memory");   // keep the LDS weight reads inside the loop
         const int64_t p = tile * kTile + col;
         const bool ok = p < src.n;
         const double r = ok ? pair_r(src, P, p) : M.rc;
         const float x = (float)r * inv_rc;
-        bf16x8 A[4];
+        bf16x8 H[4];
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int u = 16 * kb + 8 * half + j;
-                A[kb][j] = (__bf16)silu_f(fmaf(sW1[u], x, sB1[u]));
+                const float t = fmaf(sW1[u], x, sB1[u]);
+                H[kb][j] = (__bf16)(t * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t)));
             }
-        float part[16];
-#pragma unroll
-        for (int v = 0; v < 16; ++v) part[v] = 0.0f;
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-            floatx16 acc = {};
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[kb], Bop[nb][kb], acc, 0, 0, 0);
-#pragma unroll
-            for (int v = 0; v < 16; ++v) part[v] += w3u[nb] * silu_f(acc[v] + b2u[nb]);
-        }
-        // sum over the 32 output units held by the 32 lanes of this half-wavefront
-#pragma unroll
-        for (int v = 0; v < 16; ++v)
-#pragma unroll
-            for (int off = 1; off < 32; off <<= 1) part[v] += __shfl_xor(part[v], off, 32);
-        // lane with col < 16 writes row 8 (col / 4) + 4 half + col % 4
         float y = 0.0f;
 #pragma unroll
-        for (int v = 0; v < 16; ++v)
-            if (v == col) y = part[v];
-        const int row = 8 * (col >> 2) + 4 * half + (col & 3);
-        const double rr = __shfl(r, row, 64);
-        if (col < 16) {
-            const int64_t q = tile * kTile + row;
-            if (q < src.n) {
-                float f;
-                if (rr < M.r_min && P.tab) {
-                    double u = (rr - P.tab_lo) / P.tab_h;
-                    if (rr < P.tab_lo) atomicOr(&ctrl->err, kErrTableRange);
-                    double kf = floor(u);
-                    kf = kf >= 0.0 ? kf : 0.0;
-                    kf = kf > (double)(P.tab_n - 2) ? (double)(P.tab_n - 2) : kf;
-                    const float t = (float)(u - kf);
-                    const float4 c = P.tab[(int)kf];
-                    f = ((c.w * t + c.z) * t + c.y) * t + c.x;
-                } else if (rr >= M.rc) {
-                    f = 0.0f;
-                } else {
-                    f = sc * taper_f((float)rr, rcf, twf) * (y + b3);
-                }
-                out[q] = f;
+        for (int mb = 0; mb < 2; ++mb) {
+            floatx16 acc = c2[mb];
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Wop[mb][kb], H[kb], acc, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const float t = acc[v];
+                const float w = sW3[32 * mb + 8 * (v >> 2) + 4 * half + (v & 3)];
+                y = fmaf(w * t, __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t)), y);
             }
+        }
+        y += __shfl_xor(y, 32, 64);
+        if (half == 0 && ok) {
+            float f;
+            if (r < M.r_min && P.tab) {
+                double u = (r - P.tab_lo) / P.tab_h;
+                if (r < P.tab_lo) atomicOr(&ctrl->err, kErrTableRange);
+                double kf = floor(u);
+                kf = kf >= 0.0 ? kf : 0.0;
+                kf = kf > (double)(P.tab_n - 2) ? (double)(P.tab_n - 2) : kf;
+                const float t = (float)(u - kf);
+                const float4 c = P.tab[(int)kf];
+                f = ((c.w * t + c.z) * t + c.y) * t + c.x;
+            } else if (r >= M.rc) {
+                f = 0.0f;
+            } else {
+                f = sc * taper_f((float)r, rcf, twf) * (y + b3);
+            }
+            out[p] = f;
         }
     }
 }
