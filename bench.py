@@ -45,6 +45,8 @@ def main():
     ap.add_argument("--no-cg-compare", action="store_true",
                     help="skip the learned-vs-tabulated CG force leg")
     ap.add_argument("--cg-steps", type=int, default=500)
+    ap.add_argument("--cg-only", action="store_true",
+                    help="run only the learned-vs-tabulated CG force leg and print its record")
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes 10 times "
@@ -69,6 +71,9 @@ def main():
     from paper_1806_10841_amd import binding, inputs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.cg_only:
+        print(json.dumps({"learned_vs_tabulated": learned_vs_tabulated(args.cg_steps)}))
+        return
     dev = torch.device("cuda:0")
     wl = inputs.workload(args.workload)
     x, v = inputs.make_state(wl)

@@ -54,6 +54,7 @@ struct adres_ctx {
     int64_t adam_t = 0;
     double *grad = nullptr, *loss = nullptr, *res_part = nullptr, *resid = nullptr;
     float *gpart = nullptr;
+    double *gred = nullptr;        // chunk sums of the gradient reduction
     double mlp_rc = 0.0, mlp_scale = 1.0, mlp_tw = 0.0, mlp_rmin = 0.0;
     bool have_mlp = false;
     // half list (every unordered pair once) for per-pair network outputs
@@ -191,6 +192,7 @@ adres_status build_half_list(adres_ctx *c)
         c->half_rows_cap = c->cap;
         c->half_pairs_cap = (int64_t)cap_pairs;
     }
+    if (c->cap > 2048) return fail(c, ADRES_E_CAPACITY, "neighbour rows longer than 2048 entries");
     launch_half_list(c->stream, n, c->nbr, c->cnt, c->cap, c->cnt_up, c->up_off, c->up_scratch, c->up_pairs, c->pid);
     HIPCHK(c, hipGetLastError());
     return ADRES_OK;
@@ -498,7 +500,7 @@ void adres_destroy(adres_ctx *c)
     hipFree(c->mlp); hipFree(c->mlp_w2); hipFree(c->cnt_up); hipFree(c->up_off); hipFree(c->up_scratch);
     hipFree(c->pid); hipFree(c->up_pairs); hipFree(c->f_pair);
     hipFree(c->adam_m); hipFree(c->adam_v); hipFree(c->grad); hipFree(c->loss); hipFree(c->res_part);
-    hipFree(c->resid); hipFree(c->gpart);
+    hipFree(c->resid); hipFree(c->gpart); hipFree(c->gred);
     if (c->ctrl_host) hipHostFree(c->ctrl_host);
     if (c->pub) hipHostFree(c->pub);
     for (auto &e : c->events) {
@@ -797,7 +799,8 @@ adres_status fm_accumulate(adres_ctx *c, const double *com, const double *fmap, 
         const bool ok = dalloc(&c->grad, kMlpParams) == hipSuccess && dalloc(&c->loss, 1) == hipSuccess &&
                         dalloc(&c->res_part, (size_t)(n + 255) / 256) == hipSuccess &&
                         dalloc(&c->resid, 3 * (size_t)n) == hipSuccess &&
-                        dalloc(&c->gpart, (size_t)mlp_backward_waves() * kMlpParams) == hipSuccess;
+                        dalloc(&c->gpart, (size_t)mlp_backward_waves() * kMlpParams) == hipSuccess &&
+                        dalloc(&c->gred, (size_t)mlp_reduce_chunks() * kMlpParams) == hipSuccess;
         if (!ok) return fail(c, ADRES_E_NOMEM, "could not allocate training buffers");
     }
     launch_zero(c->stream, c->grad, kMlpParams);
@@ -817,7 +820,7 @@ adres_status fm_accumulate(adres_ctx *c, const double *com, const double *fmap, 
         launch_fm_residual(c->stream, n, b.perm, c->f, fm, c->resid, c->res_part, &n_part);
         launch_loss_accumulate(c->stream, c->res_part, n_part, cc, c->loss);
         launch_mlp_backward(c->stream, mlp_dev(c), c->P, c->up_pairs, c->up_off + n, b.Rw, c->resid, 2.0 * cc,
-                            c->gpart, c->grad);
+                            c->gpart, c->gred, c->grad);
         HIPCHK(c, hipGetLastError());
     }
     return ADRES_OK;

@@ -32,11 +32,12 @@ void launch_mlp_convert(hipStream_t s, const float *params, __bf16 *w2_bf16, __b
 
 // force matching
 int mlp_backward_waves();
+int mlp_reduce_chunks();   // partial sums of the fixed-order gradient reduction
 void launch_fm_residual(hipStream_t s, int n, const int *perm, const double *F, const double *fmap, double *e,
                         double *part, int *n_part);
 void launch_loss_accumulate(hipStream_t s, const double *part, int n_part, double c, double *loss);
 void launch_mlp_backward(hipStream_t s, const MlpDev &M, const DevParams &P, const int2 *pairs, const int *n_dev,
-                         const double4 *Rw, const double *e, double c2, float *gpart, double *grad);
+                         const double4 *Rw, const double *e, double c2, float *gpart, double *gred, double *grad);
 void launch_zero(hipStream_t s, double *a, int n);
 void launch_adam(hipStream_t s, float *params, float *m, float *v, const double *grad, double lr, double b1,
                  double b2, double bc1, double bc2, double eps);

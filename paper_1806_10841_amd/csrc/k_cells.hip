@@ -255,61 +255,77 @@ __global__ __launch_bounds__(kBlock) void k_list_build_cells(DevParams P, Grid G
 
 // Half list for per-pair work (the learned CG force): every unordered pair once,
 // as (t, u) with t < u, and for every full-list entry the id of its pair.
-__global__ __launch_bounds__(kBlock) void k_up_count(int n, const int *__restrict__ nbr, const int *__restrict__ cnt,
+// Half list for per-pair work (the learned CG force): every unordered listed pair once,
+// as (t, u) with t < u, ordered by t then u, plus for every full-list entry the index of
+// its pair.  Rows are first sorted by neighbour slot (32 lanes per row, rank sort in
+// LDS); then a row's upper neighbours (u > t) are a suffix starting at lb[t] = number of
+// neighbours below t, and the pair of an entry (t, k) is found without search for u > t
+// and by binary search for t in the sorted row u for u < t (the list is symmetric).
+constexpr int kSortRows = kBlock / 32;
+
+__global__ __launch_bounds__(kBlock) void k_sort_rows(int n, int *__restrict__ nbr, const int *__restrict__ cnt,
                                                      int cap, int *__restrict__ cnt_up)
 {
-    int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= n) return;
-    const int *row = nbr + (int64_t)t * cap;
-    int c = 0;
-    for (int k = 0; k < cnt[t]; ++k) c += row[k] > t;
-    cnt_up[t] = c;
-}
-
-__global__ __launch_bounds__(kBlock) void k_up_fill(int n, const int *__restrict__ nbr, const int *__restrict__ cnt,
-                                                    int cap, const int *__restrict__ up_off, int2 *__restrict__ pairs,
-                                                    int *__restrict__ pid)
-{
-    int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= n) return;
-    const int *row = nbr + (int64_t)t * cap;
-    int p = up_off[t];
-    for (int k = 0; k < cnt[t]; ++k) {
-        const int u = row[k];
-        if (u > t) {
-            pairs[p] = make_int2(t, u);
-            pid[(int64_t)t * cap + k] = p;
-            ++p;
-        }
+    extern __shared__ int srow[];   // kSortRows rows of cap entries
+    const int g = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    const int t = blockIdx.x * kSortRows + g;
+    const int c = t < n ? cnt[t] : 0;
+    int *row = nbr + (int64_t)(t < n ? t : 0) * cap;
+    int *sr = srow + g * cap;
+    for (int k = lane; k < c; k += 32) sr[k] = row[k];
+    __syncthreads();
+    int below = 0;
+    for (int k = lane; k < c; k += 32) {
+        const int e = sr[k];
+        int rank = 0;
+        for (int j = 0; j < c; ++j) rank += sr[j] < e;   // entries of a row are distinct
+        row[rank] = e;
+        below += e < t;
     }
+#pragma unroll
+    for (int off = 16; off >= 1; off >>= 1) below += __shfl_xor(below, off, 32);
+    if (t < n && lane == 0) cnt_up[t] = c - below;
 }
 
-__global__ __launch_bounds__(kBlock) void k_up_mirror(int n, const int *__restrict__ nbr, const int *__restrict__ cnt,
-                                                      int cap, int *__restrict__ pid)
+__global__ __launch_bounds__(kBlock) void k_up_entries(int n, const int *__restrict__ nbr, const int *__restrict__ cnt,
+                                                      int cap, const int *__restrict__ up_off, int2 *__restrict__ pairs,
+                                                      int *__restrict__ pid)
 {
-    int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= n) return;
-    const int *row = nbr + (int64_t)t * cap;
-    for (int k = 0; k < cnt[t]; ++k) {
-        const int u = row[k];
-        if (u >= t) continue;
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= (int64_t)n * cap) return;
+    const int t = (int)(e / cap), k = (int)(e - (int64_t)t * cap);
+    const int ct = cnt[t];
+    if (k >= ct) return;
+    const int u = nbr[e];
+    if (u > t) {
+        const int lb = ct - (up_off[t + 1] - up_off[t]);
+        const int p = up_off[t] + k - lb;
+        pairs[p] = make_int2(t, u);
+        pid[e] = p;
+    } else {
         const int *ru = nbr + (int64_t)u * cap;
         const int cu = cnt[u];
-        int kk = 0;
-        while (kk < cu && ru[kk] != t) ++kk;   // the list is symmetric: t is in row u
-        pid[(int64_t)t * cap + k] = kk < cu ? pid[(int64_t)u * cap + kk] : 0;
+        int lo = 0, hi = cu;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ru[mid] < t) lo = mid + 1;
+            else hi = mid;
+        }
+        const int lbu = cu - (up_off[u + 1] - up_off[u]);
+        pid[e] = up_off[u] + lo - lbu;
     }
 }
 
 }  // namespace
 
-void launch_half_list(hipStream_t s, int n, const int *nbr, const int *cnt, int cap, int *cnt_up, int *up_off,
+void launch_half_list(hipStream_t s, int n, int *nbr, const int *cnt, int cap, int *cnt_up, int *up_off,
                       int *scratch, int2 *pairs, int *pid)
 {
-    k_up_count<<<blocks_for(n), kBlock, 0, s>>>(n, nbr, cnt, cap, cnt_up);
+    k_sort_rows<<<(n + kSortRows - 1) / kSortRows, kBlock, (size_t)kSortRows * cap * sizeof(int), s>>>(n, nbr, cnt, cap,
+                                                                                                     cnt_up);
     launch_scan_cells(s, cnt_up, n, up_off, nullptr, scratch);
-    k_up_fill<<<blocks_for(n), kBlock, 0, s>>>(n, nbr, cnt, cap, up_off, pairs, pid);
-    k_up_mirror<<<blocks_for(n), kBlock, 0, s>>>(n, nbr, cnt, cap, pid);
+    const int64_t entries = (int64_t)n * cap;
+    k_up_entries<<<(unsigned)((entries + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, nbr, cnt, cap, up_off, pairs, pid);
 }
 
 void launch_cell_keys(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank,

@@ -261,14 +261,30 @@ __global__ __launch_bounds__(kThreads) void k_mlp_backward(MlpDev M, DevParams P
             }
 }
 
-// grad[i] += sum over waves of gpart[w][i], in wave order (FP64)
-__global__ __launch_bounds__(256) void k_grad_reduce(const float *__restrict__ gpart, int n_waves,
+// grad[i] += sum over waves of gpart[w][i] (FP64) in a fixed order: chunks of
+// kReduceChunk consecutive waves are summed in wave order (k_grad_chunks, one thread per
+// parameter and chunk), then the chunk sums in chunk order (k_grad_finish).
+constexpr int kReduceChunk = 32;
+
+__global__ __launch_bounds__(256) void k_grad_chunks(const float *__restrict__ gpart, int n_waves,
+                                                     double *__restrict__ gred)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= kMlpParams) return;
+    const int w0 = blockIdx.y * kReduceChunk;
+    const int w1 = min(w0 + kReduceChunk, n_waves);
+    double s = 0.0;
+    for (int w = w0; w < w1; ++w) s += (double)gpart[(int64_t)w * kMlpParams + i];
+    gred[(int64_t)blockIdx.y * kMlpParams + i] = s;
+}
+
+__global__ __launch_bounds__(256) void k_grad_finish(const double *__restrict__ gred, int n_chunks,
                                                      double *__restrict__ grad)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= kMlpParams) return;
     double s = 0.0;
-    for (int w = 0; w < n_waves; ++w) s += (double)gpart[(int64_t)w * kMlpParams + i];
+    for (int c = 0; c < n_chunks; ++c) s += gred[(int64_t)c * kMlpParams + i];
     grad[i] += s;
 }
 
@@ -298,6 +314,7 @@ constexpr int kBackwardBlocks = 256;
 }  // namespace
 
 int mlp_backward_waves() { return kBackwardBlocks * kWaves; }
+int mlp_reduce_chunks() { return (kBackwardBlocks * kWaves + kReduceChunk - 1) / kReduceChunk; }
 
 void launch_fm_residual(hipStream_t s, int n, const int *perm, const double *F, const double *fmap, double *e,
                         double *part, int *n_part)
@@ -312,10 +329,13 @@ void launch_loss_accumulate(hipStream_t s, const double *part, int n_part, doubl
 }
 
 void launch_mlp_backward(hipStream_t s, const MlpDev &M, const DevParams &P, const int2 *pairs, const int *n_dev,
-                         const double4 *Rw, const double *e, double c2, float *gpart, double *grad)
+                         const double4 *Rw, const double *e, double c2, float *gpart, double *gred, double *grad)
 {
     k_mlp_backward<<<kBackwardBlocks, kThreads, 0, s>>>(M, P, pairs, n_dev, Rw, e, c2, gpart);
-    k_grad_reduce<<<(kMlpParams + 255) / 256, 256, 0, s>>>(gpart, kBackwardBlocks * kWaves, grad);
+    const int n_waves = kBackwardBlocks * kWaves;
+    const dim3 grid((kMlpParams + 255) / 256, mlp_reduce_chunks());
+    k_grad_chunks<<<grid, 256, 0, s>>>(gpart, n_waves, gred);
+    k_grad_finish<<<(kMlpParams + 255) / 256, 256, 0, s>>>(gred, mlp_reduce_chunks(), grad);
 }
 
 void launch_zero(hipStream_t s, double *a, int n) { k_fill_zero<<<(n + 255) / 256, 256, 0, s>>>(a, n); }
