@@ -202,10 +202,11 @@ adres_status adres_mlp_train_step(adres_ctx *ctx, const double *com, const doubl
  * HIP events on the context's stream.  enable selects what the following calls record:
  * 0 nothing, 1 the force kernel (Eq. (1) with its fused integrator stages), 2 the learned
  * CG force's pair pre-pass (contexts with cg_kind ADRES_CG_MLP; one per force
- * evaluation); other values give ADRES_E_ARG.  ms (host) receives the summed duration
- * of what was recorded before this call and launches (host) the number of launches.
- * Synchronises. */
-adres_status adres_kernel_timing(adres_ctx *ctx, int32_t enable, double *ms, int64_t *launches);
+ * evaluation); every >= 1 records only every every-th such launch (events slow the
+ * launch stream down, so sampling keeps the timed run close to an untimed one).  Other
+ * values give ADRES_E_ARG.  ms (host) receives the summed duration of the launches
+ * recorded before this call and launches (host) their number.  Synchronises. */
+adres_status adres_kernel_timing(adres_ctx *ctx, int32_t enable, int32_t every, double *ms, int64_t *launches);
 
 /* Message describing the last error of this context (never NULL). */
 const char *adres_last_error(const adres_ctx *ctx);

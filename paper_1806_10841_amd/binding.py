@@ -66,7 +66,7 @@ _SIGS = {
     "adres_map_cg": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "adres_mlp_fm_grad": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
     "adres_mlp_train_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_void_p], C.c_int),
-    "adres_kernel_timing": ([C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
+    "adres_kernel_timing": ([C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     "adres_last_error": ([C.c_void_p], C.c_char_p),
 }
 
@@ -245,11 +245,12 @@ class Context:
                     "adres_mlp_train_step")
         return loss.value
 
-    def kernel_timing(self, enable=True):
-        """enable: False/0 off, True/1 force kernel, 2 the network's pair pre-pass."""
+    def kernel_timing(self, enable=True, every=1):
+        """enable: False/0 off, True/1 force kernel, 2 the network's pair pre-pass; every:
+        record every every-th launch.  Returns (ms, launches) recorded since the last call."""
         ms = C.c_double()
         n = C.c_int64()
         mode = int(enable) if not isinstance(enable, bool) else (1 if enable else 0)
-        self._check(self.lib.adres_kernel_timing(self.h, mode, C.byref(ms), C.byref(n)),
+        self._check(self.lib.adres_kernel_timing(self.h, mode, every, C.byref(ms), C.byref(n)),
                     "adres_kernel_timing")
         return ms.value, n.value

@@ -69,6 +69,8 @@ struct adres_ctx {
     int last_interval = 8;
 
     int timing = 0;   // 0 off, 1 force kernel, 2 network pre-pass
+    int timing_every = 1;
+    int64_t timing_count = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     size_t events_used = 0;
 
@@ -278,9 +280,16 @@ ForceArgs force_args(adres_ctx *c)
 
 adres_status run_forces(adres_ctx *c, ForceArgs a)
 {
-    // timing mode 1 brackets the force kernel, mode 2 the network's pair-force pre-pass
+    // timing mode 1 brackets the force kernel, mode 2 the network's pair-force pre-pass;
+    // one launch in timing_every is recorded, picked by a hash of the launch count so that
+    // the sample does not lock onto the rebuild cycle
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool sample = false;
     if (c->timing != 0 && (c->timing == 1 || is_mlp(c))) {
+        const uint32_t h = (uint32_t)(c->timing_count++) * 2654435761u;
+        sample = (h >> 16) % (uint32_t)c->timing_every == 0;
+    }
+    if (sample) {
         if (c->events_used == c->events.size()) {
             hipEvent_t p, q;
             HIPCHK(c, hipEventCreate(&p));
@@ -292,15 +301,16 @@ adres_status run_forces(adres_ctx *c, ForceArgs a)
         ++c->events_used;
     }
     if (is_mlp(c)) {
-        if (c->timing == 2) HIPCHK(c, hipEventRecord(e0, c->stream));
+        if (sample && c->timing == 2) HIPCHK(c, hipEventRecord(e0, c->stream));
         launch_mlp_forward_pairs(c->stream, mlp_dev(c), c->P, c->up_pairs, a.Rw, c->f_pair, c->up_off + c->P.n_mol,
                                  c->half_pairs_cap, c->ctrl, a.check_halt, a.step);
         HIPCHK(c, hipGetLastError());
-        if (c->timing == 2) HIPCHK(c, hipEventRecord(e1, c->stream));
+        if (sample && c->timing == 2) HIPCHK(c, hipEventRecord(e1, c->stream));
         a.pid = c->pid;
         a.f_pair = c->f_pair;
     }
-    launch_forces(c->stream, a, c->prm.pair_precision, c->timing == 1 ? e0 : nullptr, c->timing == 1 ? e1 : nullptr);
+    const bool ev = sample && c->timing == 1;
+    launch_forces(c->stream, a, c->prm.pair_precision, ev ? e0 : nullptr, ev ? e1 : nullptr);
     HIPCHK(c, hipGetLastError());
     return ADRES_OK;
 }
@@ -869,9 +879,10 @@ adres_status adres_map_cg(adres_ctx *c, const double *x, double *f, double *com,
     return ADRES_OK;
 }
 
-adres_status adres_kernel_timing(adres_ctx *c, int32_t enable, double *ms, int64_t *launches)
+adres_status adres_kernel_timing(adres_ctx *c, int32_t enable, int32_t every, double *ms, int64_t *launches)
 {
     if (!c) return ADRES_E_ARG;
+    if (enable < 0 || enable > 2 || every < 1) return fail(c, ADRES_E_ARG, "timing mode must be 0, 1 or 2 and every >= 1");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double sum = 0.0;
     for (size_t i = 0; i < c->events_used; ++i) {
@@ -882,8 +893,9 @@ adres_status adres_kernel_timing(adres_ctx *c, int32_t enable, double *ms, int64
     if (ms) *ms = sum;
     if (launches) *launches = (int64_t)c->events_used;
     c->events_used = 0;
-    if (enable < 0 || enable > 2) return fail(c, ADRES_E_ARG, "timing mode must be 0, 1 or 2");
     c->timing = enable;
+    c->timing_every = every;
+    c->timing_count = 0;
     return ADRES_OK;
 }
 
