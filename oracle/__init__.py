@@ -173,6 +173,27 @@ class Model:
                         out.ctypes.data_as(C.POINTER(C.c_int32)), n)
         return out[:n]
 
+    def neighbours_of(self, com, sel, r_list=None):
+        """Molecules within the list radius of each selected molecule, by brute force over
+        all molecules (NumPy, same arithmetic as the C pair test: minimum image by one
+        conditional shift, r2 = (dx*dx + dy*dy) + dz*dz < r_list^2).  Returns a list of
+        sorted index arrays, one per selected molecule."""
+        com = np.asarray(com, dtype=np.float64)
+        rl = self.r_list() if r_list is None else r_list
+        rl2 = rl * rl
+        out = []
+        for t in np.asarray(sel, dtype=np.int64):
+            d2 = None
+            for k in range(3):
+                L = self.wl.box[k]
+                h = 0.5 * L
+                d = com[k] - com[k, t]
+                d = np.where(d > h, d - L, np.where(d < -h, d + L, d))
+                d2 = d * d if d2 is None else d2 + d * d
+            nb = np.flatnonzero(d2 < rl2)
+            out.append(nb[nb != t])
+        return out
+
     def forces(self, x):
         x = np.ascontiguousarray(x, dtype=np.float64)
         f = np.empty_like(x); amag = np.empty(self.n_sites); e = np.zeros(3)

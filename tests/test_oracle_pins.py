@@ -207,6 +207,18 @@ class TestPairList:
         key = mine[:, 0].astype(np.int64) * wl.n_mol + mine[:, 1]
         assert np.all(np.diff(key) > 0)
 
+    def test_neighbours_of_matches_pair_set(self):
+        """The per-molecule brute force (NumPy) gives the same sets as the C pair list."""
+        wl = inputs.workload("small_slab")
+        x, _ = inputs.make_state(wl, seed=5)
+        m = oracle.Model(wl)
+        com, _, _, _ = m.weights(x)
+        pairs = m.pairs(com)
+        sel = np.array([0, 7, 123, 500, 999])
+        for t, nb in zip(sel, m.neighbours_of(com, sel)):
+            ref = np.sort(np.concatenate([pairs[pairs[:, 0] == t, 1], pairs[pairs[:, 1] == t, 0]]))
+            np.testing.assert_array_equal(nb, ref)
+
     def test_list_radius(self):
         m = oracle.Model(inputs.workload("c2"))
         assert abs(m.r_list() - (max(2.31 * 2 ** (1 / 6), 2 ** (1 / 6) + 1.6) + 0.3)) < 1e-15
