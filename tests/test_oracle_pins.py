@@ -389,3 +389,38 @@ class TestVelocityVerlet:
         _, v1, _, e, st = oracle.Model(wl).vv(x, v, 0.005, 20)
         assert st == 0
         assert np.max(np.abs(v1.sum(axis=1) - v.sum(axis=1))) < 1e-10
+
+
+# ---------------------------------------------------------------- golden closed forms
+def _golden(kind):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "closed_forms.txt")
+    rows = []
+    with open(path) as f:
+        for line in f:
+            parts = line.split()
+            if parts and parts[0] == kind:
+                rows.append([float(v) for v in parts[1:]])
+    assert rows, kind
+    return rows
+
+
+def test_golden_weights():
+    for d_at, d_hy, d, w in _golden("weight"):
+        assert abs(oracle.weight_of_distance(d, d_at, d_hy) - w) <= 1e-15, (d_at, d_hy, d)
+
+
+def test_golden_wca():
+    from oracle import tables
+    for sig, eps, r, f in _golden("wca"):
+        got, _ = tables.wca_force(np.array([r]), sig, eps, sig * 2 ** (1 / 6) * (1 + 1e-12))
+        assert abs(got[0] - f) <= 1e-12 * max(1.0, abs(f)), (sig, eps, r, got[0])
+
+
+def test_golden_tetra_rho():
+    (edge, rho), = _golden("tetra_rho")
+    wl = inputs.workload("c1").with_(n_mol=1, box=(10.0, 10.0, 10.0), center=(5.0, 5.0, 5.0))
+    a = edge / (2.0 * math.sqrt(2.0))
+    verts = np.array([[a, a, a], [a, -a, -a], [-a, a, -a], [-a, -a, a]]) + 5.0
+    _, _, rh, st = oracle.Model(wl).weights(np.ascontiguousarray(verts.T))
+    assert st == 0 and abs(rh[0] - rho) <= 1e-15
