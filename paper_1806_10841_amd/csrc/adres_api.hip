@@ -34,7 +34,7 @@ struct adres_ctx {
     double *f = nullptr;     // forces, Morton order
     double4 *R_ref = nullptr;
     int *inv_perm = nullptr;
-    int *cell_rank = nullptr, *rank_cell = nullptr;
+    int *cell_rank = nullptr;      // Morton rank of every cell (row-major cell index -> rank)
     int *count = nullptr, *start = nullptr, *fill = nullptr, *new_from = nullptr, *scan_tiles = nullptr;
     int *nbr = nullptr, *cnt = nullptr;
     int cap = 0;
@@ -223,8 +223,8 @@ adres_status build_list(adres_ctx *c)
     for (int attempt = 0; attempt < 4; ++attempt) {
         HIPCHK(c, hipMemsetAsync(&c->ctrl->overflow, 0, 2 * sizeof(int), c->stream));
         const StateBufs b = cur(c);
-        launch_list_build(c->stream, c->P, c->G, c->rank_cell, c->cell_rank, c->start, b.Rw, b.key, c->rl2,
-                          c->nbr, c->cnt, c->cap, c->ctrl);
+        launch_list_build(c->stream, c->P, c->G, c->cell_rank, c->start, b.Rw, c->rl2, c->nbr, c->cnt, c->cap,
+                          c->ctrl);
         HIPCHK(c, hipGetLastError());
         adres_status st = read_ctrl(c);
         if (st != ADRES_OK) return st;
@@ -251,8 +251,8 @@ adres_status build_list_async(adres_ctx *c)
 {
     // overflow / max_count were cleared by the halt reset launched before the reorder
     const StateBufs b = cur(c);
-    launch_list_build(c->stream, c->P, c->G, c->rank_cell, c->cell_rank, c->start, b.Rw, b.key, c->rl2, c->nbr,
-                      c->cnt, c->cap, c->ctrl);
+    launch_list_build(c->stream, c->P, c->G, c->cell_rank, c->start, b.Rw, c->rl2, c->nbr, c->cnt, c->cap,
+                      c->ctrl);
     HIPCHK(c, hipGetLastError());
     c->list_valid = true;
     if (is_mlp(c)) return build_half_list(c);
@@ -434,11 +434,8 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
                 codes[cidx] = {spread3(x) | (spread3(y) << 1) | (spread3(z) << 2), cidx};
             }
     std::sort(codes.begin(), codes.end());
-    std::vector<int> rank(G.n_cells), rcell(G.n_cells);
-    for (int r = 0; r < G.n_cells; ++r) {
-        rank[codes[r].second] = r;
-        rcell[r] = codes[r].second;
-    }
+    std::vector<int> rank(G.n_cells);
+    for (int r = 0; r < G.n_cells; ++r) rank[codes[r].second] = r;
 
     // neighbour-list capacity: twice the mean count at this density, plus slack
     double vol = q.box[0] * q.box[1] * q.box[2];
@@ -456,7 +453,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     }
     ok = ok && dalloc(&c->f, 3 * ns) == hipSuccess;
     ok = ok && dalloc(&c->R_ref, (size_t)n) == hipSuccess && dalloc(&c->inv_perm, n) == hipSuccess &&
-         dalloc(&c->cell_rank, G.n_cells) == hipSuccess && dalloc(&c->rank_cell, G.n_cells) == hipSuccess &&
+         dalloc(&c->cell_rank, G.n_cells) == hipSuccess &&
          dalloc(&c->count, G.n_cells) == hipSuccess && dalloc(&c->start, G.n_cells + 1) == hipSuccess &&
          dalloc(&c->fill, G.n_cells) == hipSuccess && dalloc(&c->new_from, n) == hipSuccess &&
          dalloc(&c->nbr, (size_t)c->cap * n) == hipSuccess && dalloc(&c->cnt, n) == hipSuccess &&
@@ -480,7 +477,6 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     for (int i = 0; i < n; ++i) ident[i] = i;
     Ctrl c0{INT_MAX, 0, 0, 0};
     bool cp = hipMemcpy(c->cell_rank, rank.data(), sizeof(int) * G.n_cells, hipMemcpyHostToDevice) == hipSuccess &&
-              hipMemcpy(c->rank_cell, rcell.data(), sizeof(int) * G.n_cells, hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->S[0].perm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->S[1].perm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice) == hipSuccess &&
               hipMemset(c->count, 0, sizeof(int) * G.n_cells) == hipSuccess &&
@@ -504,7 +500,7 @@ void adres_destroy(adres_ctx *c)
         hipFree(c->S[b].rho); hipFree(c->S[b].perm); hipFree(c->S[b].key);
     }
     hipFree(c->f);
-    hipFree(c->R_ref); hipFree(c->inv_perm); hipFree(c->cell_rank); hipFree(c->rank_cell);
+    hipFree(c->R_ref); hipFree(c->inv_perm); hipFree(c->cell_rank);
     hipFree(c->count); hipFree(c->start); hipFree(c->fill); hipFree(c->new_from); hipFree(c->scan_tiles);
     hipFree(c->nbr); hipFree(c->cnt); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
     hipFree(c->mlp); hipFree(c->mlp_w2); hipFree(c->cnt_up); hipFree(c->up_off); hipFree(c->up_scratch);

@@ -320,9 +320,8 @@ void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, cons
 
 // Verlet list: ELL, row-major nbr[slot * cap + k]; each row is padded with the
 // row's own slot up to a multiple of 4 entries (cap is a multiple of 4).
-void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const int *rank_cell,
-                       const int *cell_rank, const int *start, const double4 *Rw, const int *key, double rl2,
-                       int *nbr, int *cnt, int cap, Ctrl *ctrl);
+void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank, const int *start,
+                       const double4 *Rw, double rl2, int *nbr, int *cnt, int cap, Ctrl *ctrl);
 
 // half list (t < u pairs) + per-entry pair ids; up_off receives n + 1 offsets
 void launch_half_list(hipStream_t s, int n, int *nbr, const int *cnt, int cap, int *cnt_up, int *up_off,

@@ -178,18 +178,16 @@ __device__ __forceinline__ int wrap_cell(int c, int n)
 }
 
 // Lane-per-cell build: 32 lanes per home molecule, lane c (< 27) scans stencil cell c
-// (stencil order: z, then y, then x offset), counts its matches, a 32-lane exclusive
-// scan gives each lane its write offset, and a second pass writes the matches; rows
-// come out in the same order as a sequential scan (stencil order, then slot order
-// inside a cell).  Offsets outside [off_lo, off_hi] (grids with < 3 cells along a
-// dimension) are skipped so that no cell is visited twice.
+// (stencil order: z, then y, then x offset) once, keeping its matches as a bit mask over
+// the cell's slots; a 32-lane exclusive scan of the match counts gives each lane its
+// write offset.  Rows come out in the same order as a sequential scan (stencil order,
+// then slot order inside a cell).  Offsets outside [off_lo, off_hi] (grids with < 3
+// cells along a dimension) are skipped so that no cell is visited twice.
 constexpr int kCellLanes = 32;
 
-__global__ __launch_bounds__(kBlock) void k_list_build_cells(DevParams P, Grid G, const int *__restrict__ rank_cell,
-                                                             const int *__restrict__ cell_rank,
+__global__ __launch_bounds__(kBlock) void k_list_build_cells(DevParams P, Grid G, const int *__restrict__ cell_rank,
                                                              const int *__restrict__ start,
-                                                             const double4 *__restrict__ Rw,
-                                                             const int *__restrict__ key, double rl2,
+                                                             const double4 *__restrict__ Rw, double rl2,
                                                              int *__restrict__ nbr, int *__restrict__ cnt, int cap,
                                                              Ctrl *ctrl)
 {
@@ -198,8 +196,10 @@ __global__ __launch_bounds__(kBlock) void k_list_build_cells(DevParams P, Grid G
     const bool valid = t < P.n_mol;
     const int tt = valid ? t : P.n_mol - 1;
     const double4 me = Rw[tt];
-    const int c = rank_cell[key[tt]];
-    const int cx = c % G.n[0], cy = (c / G.n[0]) % G.n[1], cz = c / (G.n[0] * G.n[1]);
+    // the home cell from the centre itself (the cell the last sort put the molecule in)
+    const int cx = cell_coord(me.x, G.inv_len[0], G.n[0]);
+    const int cy = cell_coord(me.y, G.inv_len[1], G.n[1]);
+    const int cz = cell_coord(me.z, G.inv_len[2], G.n[2]);
     const int oz = lane / 9 - 1, oy = (lane / 3) % 3 - 1, ox = lane % 3 - 1;
     const bool used = valid && lane < 27 && ox >= G.off_lo[0] && ox <= G.off_hi[0] && oy >= G.off_lo[1] &&
                       oy <= G.off_hi[1] && oz >= G.off_lo[2] && oz <= G.off_hi[2];
@@ -210,14 +210,27 @@ __global__ __launch_bounds__(kBlock) void k_list_build_cells(DevParams P, Grid G
         lo = start[r];
         hi = start[r + 1];
     }
+    // one pass over the cell's molecules, four centres requested at a time; a cell of at
+    // most 64 molecules keeps its hits as a bit mask, a larger one is scanned again below
+    const bool wide = hi - lo > 64;
+    uint64_t hits = 0;
     int mine = 0;
-    for (int u = lo; u < hi; ++u) {
-        if (u == t) continue;
-        const double4 o = Rw[u];
-        const double dx = mi(o.x - me.x, P.box[0], P.half[0]);
-        const double dy = mi(o.y - me.y, P.box[1], P.half[1]);
-        const double dz = mi(o.z - me.z, P.box[2], P.half[2]);
-        mine += dist2_exact(dx, dy, dz) < rl2;
+    for (int j0 = lo; j0 < hi; j0 += 4) {
+        double4 o[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[j] = Rw[j0 + j < hi ? j0 + j : lo];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int u = j0 + j;
+            if (u >= hi || u == t) continue;
+            const double dx = mi(o[j].x - me.x, P.box[0], P.half[0]);
+            const double dy = mi(o[j].y - me.y, P.box[1], P.half[1]);
+            const double dz = mi(o[j].z - me.z, P.box[2], P.half[2]);
+            if (dist2_exact(dx, dy, dz) < rl2) {
+                ++mine;
+                if (!wide) hits |= 1ull << (u - lo);
+            }
+        }
     }
     int incl = mine;
 #pragma unroll
@@ -228,7 +241,14 @@ __global__ __launch_bounds__(kBlock) void k_list_build_cells(DevParams P, Grid G
     const int total = __shfl(incl, kCellLanes - 1, kCellLanes);
     int *row = nbr + (int64_t)tt * cap;
     int k = incl - mine;
-    if (mine > 0) {
+    if (!wide) {
+        while (hits) {
+            const int j = __builtin_ctzll(hits);
+            hits &= hits - 1;
+            if (k < cap) row[k] = lo + j;
+            ++k;
+        }
+    } else if (mine > 0) {
         for (int u = lo; u < hi; ++u) {
             if (u == t) continue;
             const double4 o = Rw[u];
@@ -253,8 +273,6 @@ __global__ __launch_bounds__(kBlock) void k_list_build_cells(DevParams P, Grid G
     }
 }
 
-// Half list for per-pair work (the learned CG force): every unordered pair once,
-// as (t, u) with t < u, and for every full-list entry the id of its pair.
 // Half list for per-pair work (the learned CG force): every unordered listed pair once,
 // as (t, u) with t < u, ordered by t then u, plus for every full-list entry the index of
 // its pair.  Rows are first sorted by neighbour slot (32 lanes per row, rank sort in
@@ -365,13 +383,11 @@ void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, cons
     }
 }
 
-void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const int *rank_cell,
-                       const int *cell_rank, const int *start, const double4 *Rw, const int *key, double rl2,
-                       int *nbr, int *cnt, int cap, Ctrl *ctrl)
+void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank, const int *start,
+                       const double4 *Rw, double rl2, int *nbr, int *cnt, int cap, Ctrl *ctrl)
 {
     const int blocks = (int)(((int64_t)P.n_mol * kCellLanes + kBlock - 1) / kBlock);
-    k_list_build_cells<<<blocks, kBlock, 0, s>>>(P, G, rank_cell, cell_rank, start, Rw, key, rl2, nbr, cnt, cap,
-                                                 ctrl);
+    k_list_build_cells<<<blocks, kBlock, 0, s>>>(P, G, cell_rank, start, Rw, rl2, nbr, cnt, cap, ctrl);
 }
 
 }  // namespace adres

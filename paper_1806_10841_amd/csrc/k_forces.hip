@@ -98,10 +98,19 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     // home sites of the workgroup's 64 molecules, staged in LDS (read by every lane of a
     // quad in the atom tiles, the bonds and the drift)
     __shared__ double sx[kBlock / kLanes][SPM][3];
+    // velocities and reference centres are only needed after the force loop; staging them
+    // here lets their loads overlap the prologue instead of adding a wait at the end
+    __shared__ double sv[MODE == kModeForce ? 1 : kBlock / kLanes][SPM][3];
+    __shared__ double4 sref[MODE == kModeStep ? kBlock / kLanes : 1];
     const int ml = threadIdx.x / kLanes;
-    if (q < SPM)
+    if (q < SPM) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) sx[ml][q][d] = a.x[d * ns + (int64_t)tt * SPM + q];
+        if (MODE != kModeForce)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) sv[ml][q][d] = a.v[d * ns + (int64_t)tt * SPM + q];
+    }
+    if (MODE == kModeStep && q == 0) sref[ml] = a.R_ref[tt];
     __syncthreads();
 #define XI(i, d) sx[ml][(i)][(d)]
     const double4 me = a.Rw[tt];
@@ -149,7 +158,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
             const double D2 = mi(me.z - o.z, P.box[2], P.half[2]);
             const double r2c = dist2_exact(D0, D1, D2);
             if (ww > 0.0) {
-                const double bound = P.rc_at + rha + (double)a.rho[u] + 1e-6;
+                // no atom pair of the tile can be within the cutoff beyond this centre
+                // distance (every site lies within rho_max of its centre, a checked invariant)
+                const double bound = P.rc_at + rha + P.rho_max + 1e-6;
                 if (r2c < bound * bound) {
                     const PT pww = (PT)ww;
                     if constexpr (kOff) {
@@ -309,7 +320,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
         }
     } else if (MODE == kModeClose) {
         if (owner) {
-            double v[3] = {a.v[site], a.v[ns + site], a.v[2 * ns + site]};
+            double v[3] = {sv[ml][q][0], sv[ml][q][1], sv[ml][q][2]};
             close_kick(v, F, a.st.dt, 0.5 / mq);
             a.v[site] = v[0]; a.v[ns + site] = v[1]; a.v[2 * ns + site] = v[2];
             a.f[site] = F[0]; a.f[ns + site] = F[1]; a.f[2 * ns + site] = F[2];
@@ -317,7 +328,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     } else {   // kModeStep
         double xn[3] = {xq[0], xq[1], xq[2]};
         if (owner) {
-            double v[3] = {a.v[site], a.v[ns + site], a.v[2 * ns + site]};
+            double v[3] = {sv[ml][q][0], sv[ml][q][1], sv[ml][q][2]};
             close_kick(v, F, a.st.dt, 0.5 / mq);
             const int caller_site = a.st.gamma > 0.0 ? a.perm[t] * SPM + q : 0;
             open_and_drift(P, mq, caller_site, xn, v, F, a.st.dt, a.st.gamma, a.st.kT, a.st.seed, a.st.step_abs);
@@ -359,7 +370,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
             a.rho_out[t] = (float)rh;
             if (!(isfinite(R0) && isfinite(R1) && isfinite(R2))) atomicOr(&a.ctrl->err, kErrNonFinite);
             if (SPM > 1 && rh > P.rho_max) atomicOr(&a.ctrl->err, kErrStretch);
-            const double4 rr = a.R_ref[t];
+            const double4 rr = sref[ml];
             const double q0 = mi(R0 - rr.x, P.box[0], P.half[0]);
             const double q1 = mi(R1 - rr.y, P.box[1], P.half[1]);
             const double q2 = mi(R2 - rr.z, P.box[2], P.half[2]);
