@@ -11,6 +11,8 @@
 // row-major (ELL): nbr[slot * cap + k]; every row is padded with the row's own
 // slot up to a multiple of 4 so that the force kernel can fetch four entries with
 // one 16-byte load and issue their gathers unconditionally.
+#include <climits>
+
 #include "adres_internal.h"
 
 namespace adres {
@@ -123,13 +125,36 @@ __global__ __launch_bounds__(kBlock) void k_scatter_slots(int n_mol, const int *
     new_from[pos] = i;
 }
 
+// Molecules of one cell in caller order (the atomic scatter leaves them in arbitrary
+// order).  A cell of at most 16 molecules is loaded into registers at once and every
+// molecule is written to the slot given by its rank (the number of cell mates with a
+// smaller caller index; indices are distinct); larger cells use an insertion sort.
+constexpr int kSortCell = 16;
+
 __global__ __launch_bounds__(kBlock) void k_sort_within_cells(int n_cells, const int *__restrict__ start,
                                                               const int *__restrict__ perm_old,
                                                               int *__restrict__ new_from)
 {
     int c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= n_cells) return;
-    int lo = start[c], hi = start[c + 1];
+    const int lo = start[c], hi = start[c + 1], m = hi - lo;
+    if (m <= 1) return;
+    if (m <= kSortCell) {
+        int v[kSortCell], tag[kSortCell];
+#pragma unroll
+        for (int i = 0; i < kSortCell; ++i) v[i] = i < m ? new_from[lo + i] : 0;
+#pragma unroll
+        for (int i = 0; i < kSortCell; ++i) tag[i] = i < m ? perm_old[v[i]] : INT_MAX;
+#pragma unroll
+        for (int i = 0; i < kSortCell; ++i) {
+            if (i >= m) break;
+            int r = 0;
+#pragma unroll
+            for (int j = 0; j < kSortCell; ++j) r += tag[j] < tag[i];
+            new_from[lo + r] = v[i];
+        }
+        return;
+    }
     for (int i = lo + 1; i < hi; ++i) {
         int v = new_from[i];
         int tag = perm_old[v];
@@ -142,6 +167,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_within_cells(int n_cells, const
     }
 }
 
+// Gathers the state into the new slot order.  All loads are issued before the first
+// store: source and destination are distinct buffers, but the compiler cannot know that
+// and would otherwise wait for every load before the store that follows it.
 template <int SPM>
 __global__ __launch_bounds__(kBlock) void k_permute(DevParams P, const int *__restrict__ new_from, StateBufs src,
                                                     StateBufs dst, int *__restrict__ inv_perm,
@@ -150,23 +178,35 @@ __global__ __launch_bounds__(kBlock) void k_permute(DevParams P, const int *__re
     int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= P.n_mol) return;
     const int64_t ns = P.n_sites;
-    int i = new_from[t];
+    const int i = new_from[t];
+    double xs[3][SPM], vs[3][SPM];
+    float of[3 * SPM];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
+    for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int k = 0; k < SPM; ++k) {
-            dst.x[d * ns + (int64_t)t * SPM + k] = src.x[d * ns + (int64_t)i * SPM + k];
-            if (with_v) dst.v[d * ns + (int64_t)t * SPM + k] = src.v[d * ns + (int64_t)i * SPM + k];
+            xs[d][k] = src.x[d * ns + (int64_t)i * SPM + k];
+            vs[d][k] = with_v ? src.v[d * ns + (int64_t)i * SPM + k] : 0.0;
         }
-    }
+#pragma unroll
+    for (int j = 0; j < 3 * SPM; ++j) of[j] = src.off[(int64_t)i * (3 * SPM) + j];
     const double4 r = src.Rw[i];
+    const float rh = src.rho[i];
+    const int key = src.key[i];
+    const int caller = src.perm[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int k = 0; k < SPM; ++k) {
+            dst.x[d * ns + (int64_t)t * SPM + k] = xs[d][k];
+            if (with_v) dst.v[d * ns + (int64_t)t * SPM + k] = vs[d][k];
+        }
+#pragma unroll
+    for (int j = 0; j < 3 * SPM; ++j) dst.off[(int64_t)t * (3 * SPM) + j] = of[j];
     dst.Rw[t] = r;
     R_ref[t] = r;
-    dst.rho[t] = src.rho[i];
-#pragma unroll
-    for (int j = 0; j < 3 * SPM; ++j) dst.off[(int64_t)t * (3 * SPM) + j] = src.off[(int64_t)i * (3 * SPM) + j];
-    dst.key[t] = src.key[i];
-    int caller = src.perm[i];
+    dst.rho[t] = rh;
+    dst.key[t] = key;
     dst.perm[t] = caller;
     inv_perm[caller] = t;
 }
