@@ -159,6 +159,42 @@ __device__ __forceinline__ int cell_coord(double r, double inv_len, int n)
     return s < (double)(n - 1) ? (int)s : n - 1;
 }
 
+// ---------------------------------------------------------------- lane exchanges
+// Exchanges inside groups of four consecutive lanes by DPP quad permutations (a VALU
+// move, no LDS round trip).  CTRL is the quad_perm selector: lane i of a quad reads lane
+// ((CTRL >> 2 i) & 3) of the same quad.  Every lane of the quad must be active.
+constexpr int kQuadXor1 = 0xB1;   // [1, 0, 3, 2]
+constexpr int kQuadXor2 = 0x4E;   // [2, 3, 0, 1]
+template <int K>
+constexpr int kQuadBcast = 0x55 * K;   // [K, K, K, K]
+
+template <int CTRL>
+__device__ __forceinline__ double quad_perm(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the four lanes of a quad; every lane ends with the same bits
+// ((a + b) + (c + d) with the pairs formed the same way on every lane).
+__device__ __forceinline__ double quad_sum(double v)
+{
+    v += quad_perm<kQuadXor1>(v);
+    return v + quad_perm<kQuadXor2>(v);
+}
+
+// 1/sqrt(x) for x > 0 to FP64 precision: the hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rsqrt_refined(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * (1.5 - hx * y * y);
+    y = y * (1.5 - hx * y * y);
+    return y;
+}
+
 // ---------------------------------------------------------------- integrator helpers
 // Philox4x32-10 (Salmon et al., "Parallel random numbers: as easy as 1, 2, 3",
 // SC'11): counter = (step, caller site), key = seed.
@@ -194,8 +230,9 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double &n0, d
 // drift x += v dt folded into [0, L).  With gamma > 0 the drift is split around an
 // exact Ornstein-Uhlenbeck step (BAOAB, Leimkuhler & Matthews 2013):
 //   x += v dt/2;  v = c v + sqrt((1 - c^2) kT / m) N(0,1), c = exp(-gamma dt);  x += v dt/2.
-// Operation order as in the oracle's integrator (no contraction).
-__device__ __forceinline__ void open_and_drift(const DevParams &P, double m, int caller_site, double x[3],
+// inv_2m = 1 / (2m), precomputed per site (the same bits as 0.5 / m).  Operation order as
+// in the oracle's integrator (no contraction).
+__device__ __forceinline__ void open_and_drift(const DevParams &P, double m, double inv_2m, int caller_site, double x[3],
                                                double v[3], const double F[3], double dt, double gamma,
                                                double kT, uint64_t seed, uint64_t step_abs)
 {
@@ -211,7 +248,6 @@ __device__ __forceinline__ void open_and_drift(const DevParams &P, double m, int
         c_ou = exp(-gamma * dt);
         s_ou = sqrt((1.0 - c_ou * c_ou) * kT / m);
     }
-    const double inv_2m = 0.5 / m;   // exact for power-of-two masses: then (F dt) / (2m) bit for bit
     for (int d = 0; d < 3; ++d) {
         double vv = v[d] + F[d] * dt * inv_2m;
         double y;

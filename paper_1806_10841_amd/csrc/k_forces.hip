@@ -244,25 +244,18 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     }
 
     // combine the four lanes' partial sums (every lane ends with the same bits)
+    static_assert(kLanes == 4, "the quad exchanges below assume four lanes per molecule");
 #pragma unroll
     for (int i = 0; i < SPM; ++i)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            double v = acc[i][d];
-            v += __shfl_xor(v, 1, kLanes);
-            v += __shfl_xor(v, 2, kLanes);
-            acc[i][d] = v;
-        }
-    cg0 += __shfl_xor(cg0, 1, kLanes);
-    cg0 += __shfl_xor(cg0, 2, kLanes);
-    cg1 += __shfl_xor(cg1, 1, kLanes);
-    cg1 += __shfl_xor(cg1, 2, kLanes);
-    cg2 += __shfl_xor(cg2, 1, kLanes);
-    cg2 += __shfl_xor(cg2, 2, kLanes);
+        for (int d = 0; d < 3; ++d) acc[i][d] = quad_sum(acc[i][d]);
+    cg0 = quad_sum(cg0);
+    cg1 = quad_sum(cg1);
+    cg2 = quad_sum(cg2);
 
     // lane q owns site q
     double F[3] = {0.0, 0.0, 0.0}, xq[3] = {0.0, 0.0, 0.0};
-    double mq = 1.0;
+    double mq = 1.0, iq = 0.5;
 #pragma unroll
     for (int i = 0; i < SPM; ++i)
         if (i == q) {
@@ -272,6 +265,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
             F[2] = acc[i][2] + mf * cg2;
             xq[0] = XI(i, 0); xq[1] = XI(i, 1); xq[2] = XI(i, 2);
             mq = P.mass[i];
+            iq = P.inv_2m[i];
         }
     const bool owner = valid && q < SPM;
     if (owner) {
@@ -282,8 +276,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                 const double d0 = mi(xq[0] - XI(k, 0), P.box[0], P.half[0]);
                 const double d1 = mi(xq[1] - XI(k, 1), P.box[1], P.half[1]);
                 const double d2 = mi(xq[2] - XI(k, 2), P.box[2], P.half[2]);
-                const double r = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
-                const double fr = -P.k_bond * (r - P.r0_bond) / r;
+                const double r2b = (d0 * d0 + d1 * d1) + d2 * d2;
+                const double ir = rsqrt_refined(r2b);
+                const double r = r2b * ir;
+                const double fr = -P.k_bond * (r - P.r0_bond) * ir;
                 F[0] += fr * d0; F[1] += fr * d1; F[2] += fr * d2;
                 if (ENERGY && k > q) ubond += 0.5 * P.k_bond * (r - P.r0_bond) * (r - P.r0_bond);
             }
@@ -321,7 +317,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     } else if (MODE == kModeClose) {
         if (owner) {
             double v[3] = {sv[ml][q][0], sv[ml][q][1], sv[ml][q][2]};
-            close_kick(v, F, a.st.dt, 0.5 / mq);
+            close_kick(v, F, a.st.dt, iq);
             a.v[site] = v[0]; a.v[ns + site] = v[1]; a.v[2 * ns + site] = v[2];
             a.f[site] = F[0]; a.f[ns + site] = F[1]; a.f[2 * ns + site] = F[2];
         }
@@ -329,9 +325,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
         double xn[3] = {xq[0], xq[1], xq[2]};
         if (owner) {
             double v[3] = {sv[ml][q][0], sv[ml][q][1], sv[ml][q][2]};
-            close_kick(v, F, a.st.dt, 0.5 / mq);
+            close_kick(v, F, a.st.dt, iq);
             const int caller_site = a.st.gamma > 0.0 ? a.perm[t] * SPM + q : 0;
-            open_and_drift(P, mq, caller_site, xn, v, F, a.st.dt, a.st.gamma, a.st.kT, a.st.seed, a.st.step_abs);
+            open_and_drift(P, mq, iq, caller_site, xn, v, F, a.st.dt, a.st.gamma, a.st.kT, a.st.seed, a.st.step_abs);
             a.v[site] = v[0]; a.v[ns + site] = v[1]; a.v[2 * ns + site] = v[2];
             a.x_out[site] = xn[0]; a.x_out[ns + site] = xn[1]; a.x_out[2 * ns + site] = xn[2];
         }
@@ -340,13 +336,21 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
         // own site's offset and distance
         double col[SPM];
         const int dd = q < 3 ? q : 0;
+        {
+            double b[3][4];
 #pragma unroll
-        for (int k = 0; k < SPM; ++k) {
-            const double c0 = __shfl(xn[0], k, kLanes), c1 = __shfl(xn[1], k, kLanes), c2 = __shfl(xn[2], k, kLanes);
-            col[k] = dd == 0 ? c0 : (dd == 1 ? c1 : c2);
+            for (int d = 0; d < 3; ++d) {
+                b[d][0] = quad_perm<kQuadBcast<0>>(xn[d]);
+                b[d][1] = quad_perm<kQuadBcast<1>>(xn[d]);
+                b[d][2] = quad_perm<kQuadBcast<2>>(xn[d]);
+                b[d][3] = quad_perm<kQuadBcast<3>>(xn[d]);
+            }
+#pragma unroll
+            for (int k = 0; k < SPM; ++k) col[k] = dd == 0 ? b[0][k] : (dd == 1 ? b[1][k] : b[2][k]);
         }
         const double Rd = com_dim<SPM>(P, col, dd);
-        const double R0 = __shfl(Rd, 0, kLanes), R1 = __shfl(Rd, 1, kLanes), R2 = __shfl(Rd, 2, kLanes);
+        const double R0 = quad_perm<kQuadBcast<0>>(Rd), R1 = quad_perm<kQuadBcast<1>>(Rd),
+                     R2 = quad_perm<kQuadBcast<2>>(Rd);
         double r2 = 0.0;
         if (owner) {
             const double o0 = mi(xn[0] - R0, P.box[0], P.half[0]);
@@ -358,9 +362,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
         }
         double m2 = r2;
         {
-            const double y1 = __shfl_xor(m2, 1, kLanes);
+            const double y1 = quad_perm<kQuadXor1>(m2);
             m2 = y1 > m2 ? y1 : m2;
-            const double y2 = __shfl_xor(m2, 2, kLanes);
+            const double y2 = quad_perm<kQuadXor2>(m2);
             m2 = y2 > m2 ? y2 : m2;
         }
         if (valid && q == 0) {

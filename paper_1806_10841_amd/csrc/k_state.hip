@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(DevParams P, const double
         double xx[3] = {x_in[i], x_in[ns + i], x_in[2 * ns + i]};
         double vv[3] = {v[i], v[ns + i], v[2 * ns + i]};
         const double F[3] = {f[i], f[ns + i], f[2 * ns + i]};
-        open_and_drift(P, P.mass[k], caller0 + k, xx, vv, F, st.dt, st.gamma, st.kT, st.seed, st.step_abs);
+        open_and_drift(P, P.mass[k], P.inv_2m[k], caller0 + k, xx, vv, F, st.dt, st.gamma, st.kT, st.seed, st.step_abs);
         for (int d = 0; d < 3; ++d) {
             v[d * ns + i] = vv[d];
             x_out[d * ns + i] = xx[d];

@@ -35,7 +35,10 @@ def assert_forces_close(fg, fo, amag, tol, where=""):
     err = np.abs(fg - fo).max(axis=0)
     bad = err > tol * np.maximum(amag, 1e-300)
     assert not bad.any(), f"{where}: {bad.sum()} sites over tol, worst ratio {(err / np.maximum(amag, 1e-300)).max():.3e}"
-    assert np.linalg.norm(fg - fo) <= tol * np.linalg.norm(fo), where
+    # normwise as well, unless the net forces are themselves rounding noise of their terms
+    # (e.g. bonds at rest length): then only the per-site term-scale bound is meaningful
+    if np.linalg.norm(fo) > 1e-12 * np.linalg.norm(amag):
+        assert np.linalg.norm(fg - fo) <= tol * np.linalg.norm(fo), where
 
 
 def _morton(cx, cy, cz):
