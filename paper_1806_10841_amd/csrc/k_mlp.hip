@@ -25,6 +25,9 @@ namespace {
 constexpr int kTile = 32;
 constexpr int kWaves = 4;
 constexpr int kBlockM = 64 * kWaves;
+constexpr int kQueue = kTile + 64;   // queued pairs per wave: a partial tile plus one window
+
+__device__ __forceinline__ void wave_lds_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
 // taper(r) = 1 below rc - tw, cos^2 ramp to 0 at rc (same shape as the resolution function)
 __device__ __forceinline__ float taper_f(float r, float rc, float tw)
@@ -92,14 +95,20 @@ __global__ __launch_bounds__(kBlockM) void k_mlp_forward(MlpDev M, DevParams P, 
         for (int v = 0; v < 16; ++v) c2[mb][v] = -kLog2e * M.b2[32 * mb + 8 * (v >> 2) + 4 * half + (v & 3)];
     const float b3 = M.w3[kHidden], inv_rc = 1.0f / (float)M.rc, rcf = (float)M.rc, twf = (float)M.tw, sc = (float)M.scale;
 
-    const int64_t n_tiles = (src.n + kTile - 1) / kTile;
-    const int64_t wave_id = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-    const int64_t n_waves = (int64_t)gridDim.x * kWaves;
-    for (int64_t tile = wave_id; tile < n_tiles; tile += n_waves) {
-        __asm__ volatile("" ::: "memory");   // keep the LDS weight reads inside the loop
-        const int64_t p = tile * kTile + col;
-        const bool ok = p < src.n;
-        const double r = ok ? pair_r(src, P, p) : M.rc;
+    // Pairs are read in windows of 64 (one per lane).  A pair below r_min takes the table
+    // and one at or beyond rc is zero, both written at once by its lane; the others are
+    // appended to a per-wave queue in LDS (ballot + prefix count), and the network runs on
+    // full tiles of 32 queued pairs, plus one partial tile at the end.
+    __shared__ double qr[kWaves][kQueue];
+    __shared__ int qp[kWaves][kQueue];
+    const int wv = threadIdx.x >> 6;
+    int q_head = 0, q_len = 0;   // wave-uniform ring-buffer state
+
+    auto run_tile = [&](int count) {
+        // lane col takes queued pair col (both half-wavefronts the same pair)
+        const int slot = (q_head + (col < count ? col : 0)) % kQueue;
+        const double r = col < count ? qr[wv][slot] : M.rc;
+        const int p = qp[wv][slot];
         const float x = (float)r * inv_rc;
         bf16x8 H[4];
 #pragma unroll
@@ -124,8 +133,20 @@ __global__ __launch_bounds__(kBlockM) void k_mlp_forward(MlpDev M, DevParams P, 
             }
         }
         y += __shfl_xor(y, 32, 64);
-        if (half == 0 && ok) {
-            float f;
+        if (half == 0 && col < count) out[p] = sc * taper_f((float)r, rcf, twf) * (y + b3);
+        q_head = (q_head + count) % kQueue;
+        q_len -= count;
+    };
+
+    const int64_t n_win = (src.n + 63) / 64;
+    const int64_t wave_id = (int64_t)blockIdx.x * kWaves + wv;
+    const int64_t n_waves = (int64_t)gridDim.x * kWaves;
+    for (int64_t win = wave_id; win < n_win; win += n_waves) {
+        const int64_t p = win * 64 + lane;
+        const bool ok = p < src.n;
+        const double r = ok ? pair_r(src, P, p) : M.rc;
+        bool net = false;
+        if (ok) {
             if (r < M.r_min && P.tab) {
                 double u = (r - P.tab_lo) / P.tab_h;
                 if (r < P.tab_lo) atomicOr(&ctrl->err, kErrTableRange);
@@ -134,15 +155,29 @@ __global__ __launch_bounds__(kBlockM) void k_mlp_forward(MlpDev M, DevParams P, 
                 kf = kf > (double)(P.tab_n - 2) ? (double)(P.tab_n - 2) : kf;
                 const float t = (float)(u - kf);
                 const float4 c = P.tab[(int)kf];
-                f = ((c.w * t + c.z) * t + c.y) * t + c.x;
+                out[p] = ((c.w * t + c.z) * t + c.y) * t + c.x;
             } else if (r >= M.rc) {
-                f = 0.0f;
+                out[p] = 0.0f;
             } else {
-                f = sc * taper_f((float)r, rcf, twf) * (y + b3);
+                net = true;
             }
-            out[p] = f;
+        }
+        const uint64_t mask = __ballot(net);
+        if (net) {
+            const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+            const int slot = (q_head + q_len + rank) % kQueue;
+            qr[wv][slot] = r;
+            qp[wv][slot] = (int)p;
+        }
+        wave_lds_sync();
+        q_len += __popcll(mask);
+        while (q_len >= kTile) {
+            run_tile(kTile);
+            wave_lds_sync();
         }
     }
+    if (q_len > 0) run_tile(q_len);
 }
 
 }  // namespace
