@@ -147,6 +147,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
         double4 nb[kPre];
 #pragma unroll
         for (int j = 0; j < kPre; ++j) nb[j] = a.Rw[us[j]];   // padding entries are valid slots
+        // CG sites: the learned CG force of each entry's pair, requested with the centres
+        // (pair ids exist for the row's real entries only)
+        float fp[kPre] = {0.0f, 0.0f};
+        if (SPM == 1 && P.cg_kind >= ADRES_CG_MLP) {
+            const int2 pid2 = *reinterpret_cast<const int2 *>(a.pid + (int64_t)tt * a.cap + k0);
+            fp[0] = a.f_pair[pid2.x];
+            if (k0 + 1 < cnt) fp[1] = a.f_pair[pid2.y];
+        }
 #pragma unroll
         for (int j = 0; j < kPre; ++j) {
             if (k0 + j >= cnt) break;
@@ -229,7 +237,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                 if (P.cg_kind == ADRES_CG_WCA) {
                     fr = wca_f_over_r<PT>((PT)r2c, sig2C, epsC, uu, ENERGY);
                 } else if (P.cg_kind >= ADRES_CG_MLP) {
-                    fr = (PT)a.f_pair[a.pid[(int64_t)tt * a.cap + k0 + j]] / (PT)sqrt(r2c);
+                    // the same bits from both sides of the pair (same r2c, same network value)
+                    const float fv = SPM == 1 ? fp[j] : a.f_pair[a.pid[(int64_t)tt * a.cap + k0 + j]];
+                    fr = (PT)fv * (PT)__builtin_amdgcn_rsqf((float)r2c);
                 } else {
                     const double r = sqrt(r2c);
                     fr = table_f<PT>(P, r, a.ctrl) / (PT)r;
