@@ -100,6 +100,7 @@ __device__ __forceinline__ double com_dim(const DevParams &P, const double (&c)[
 {
 #pragma clang fp contract(off)
     const double x0 = c[0];
+    if constexpr (SPM == 1) return fold(x0 + 0.0, P.box[d]);   // x0 + 0 / M without the division
     double acc = 0.0;
 #pragma unroll
     for (int k = 1; k < SPM; ++k) acc = acc + P.mass[k] * mi(c[k] - x0, P.box[d], P.half[d]);

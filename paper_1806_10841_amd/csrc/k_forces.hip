@@ -116,8 +116,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     const double4 me = a.Rw[tt];
     const double rha = (double)a.rho[tt];
     constexpr bool kOff = sizeof(PT) == 4;   // FP32 displacements from site offsets
-    float hoff[SPM][3];
-    if (kOff) {
+    // (a single-site molecule's offset from its centre is exactly zero: no loads or stores)
+    float hoff[SPM][3] = {};
+    if (kOff && SPM > 1) {
 #pragma unroll
         for (int i = 0; i < SPM; ++i)
 #pragma unroll
@@ -181,7 +182,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                             no[8] = o2.x; no[9] = o2.y; no[10] = o2.z; no[11] = o2.w;
                         } else {
 #pragma unroll
-                            for (int j2 = 0; j2 < 3 * SPM; ++j2) no[j2] = a.off[(int64_t)u * (3 * SPM) + j2];
+                            for (int j2 = 0; j2 < 3 * SPM; ++j2)
+                                no[j2] = SPM > 1 ? a.off[(int64_t)u * (3 * SPM) + j2] : 0.0f;
                         }
                         // D + (off_i - off_jj): the same bits with opposite sign from the
                         // other molecule's side, so pair forces cancel exactly (Newton's third law)
@@ -367,8 +369,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
             const double o1 = mi(xn[1] - R1, P.box[1], P.half[1]);
             const double o2 = mi(xn[2] - R2, P.box[2], P.half[2]);
             r2 = dist2_exact(o0, o1, o2);
-            float *of = a.off_out + (int64_t)t * (3 * SPM) + 3 * q;
-            of[0] = (float)o0; of[1] = (float)o1; of[2] = (float)o2;
+            if (SPM > 1) {
+                float *of = a.off_out + (int64_t)t * (3 * SPM) + 3 * q;
+                of[0] = (float)o0; of[1] = (float)o1; of[2] = (float)o2;
+            }
         }
         double m2 = r2;
         {
