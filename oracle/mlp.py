@@ -20,6 +20,13 @@ g_IJ = 2/(3 N_f N) (e_I - e_J) . R_hat_IJ with e = F - F^map.
 
 Parameter layout (float64 vector, H = 64): W1[H], b1[H], W2[H*H] (row = output
 unit), b2[H], W3[H], b3[1].  Written with plain NumPy matmuls, no fusion.
+
+FP8 variant (``forward_fp8``): the second layer's inputs h1 and weights W2 rounded to
+FP8 E4M3 (OCP format: 4 exponent bits, bias 7, 3 mantissa bits, largest finite 448,
+subnormal step 2^-9, round to nearest even) after division by per-tensor scales
+s_w = max|W2| / 448 and s_g = G / 448, with G = 1.01 max(0.2785, max_u |silu(b1_u)|,
+max_u |silu(W1_u + b1_u)|) / ln 2 a bound on |h1| / ln 2 over x in [0, 1] (silu is
+monotone above its minimum -0.27846); the product is scaled back by s_w s_g.
 Pinned by central finite differences and closed-form special cases
 (tests/test_oracle_mlp.py).
 """
@@ -56,6 +63,41 @@ def silu(z):
 def silu_grad(z):
     s = sigmoid(z)
     return s * (1.0 + z * (1.0 - s))
+
+
+def e4m3_round(x):
+    """Round to the nearest FP8 E4M3 (OCP) value, ties to even; |x| <= 448 is required."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.abs(x)
+    with np.errstate(divide="ignore"):
+        e = np.floor(np.log2(np.where(a > 0, a, 1.0)))
+    e = np.maximum(e, -6.0)                  # below 2^-6: subnormals, fixed step 2^-9
+    step = 2.0 ** (e - 3)
+    q = np.round(a / step) * step            # np.round rounds halves to even
+    assert np.all(q <= 448.0), "value beyond the E4M3 range"
+    return np.sign(x) * q
+
+
+def fp8_scales(params, H=64):
+    """(s_w, s_g) of the FP8 variant (see the module docstring)."""
+    W1, b1, W2, b2, W3, b3 = unpack(params, H)
+    g = max(0.2785, float(np.abs(silu(b1)).max()), float(np.abs(silu(W1 + b1)).max()))
+    G = 1.01 * g / np.log(2.0)
+    wmax = float(np.abs(W2).max())
+    return (wmax / 448.0 if wmax > 0 else 1.0), G / 448.0
+
+
+def forward_fp8(params, r, rc, scale, tw, H=64):
+    """f(r) of the FP8 variant: h1 and W2 in E4M3 with per-tensor scales, the rest FP64."""
+    W1, b1, W2, b2, W3, b3 = unpack(params, H)
+    s_w, s_g = fp8_scales(params, H)
+    x = np.asarray(r, dtype=np.float64) / rc
+    h1 = silu(x[:, None] * W1[None, :] + b1[None, :])
+    g = e4m3_round(h1 / np.log(2.0) / s_g)             # the scaled |h1| / ln 2, quantised
+    Wq = e4m3_round(W2 / s_w)
+    z2 = (g @ Wq.T) * (s_w * s_g) * np.log(2.0) + b2[None, :]
+    y = silu(z2) @ W3 + b3[0]
+    return scale * taper(r, rc, tw) * y
 
 
 def taper(r, rc, tw):

@@ -138,3 +138,55 @@ def test_c_oracle_mlp_forces_are_pair_forces():
     assert st == 0
     Fn = mlp.predicted_forces(p, x, wl.box, RC, SCALE, TW)
     np.testing.assert_allclose(f, Fn, rtol=0, atol=1e-12 * np.abs(Fn).max())
+
+
+# ---------------------------------------------------------------- FP8 E4M3 variant
+def _e4m3_codes():
+    """All finite non-negative E4M3 (OCP) values from the bit layout: exponent field e
+    (bias 7), mantissa m; e = 0 is subnormal (m 2^-9); (e, m) = (15, 7) is NaN."""
+    vals = []
+    for e in range(16):
+        for m in range(8):
+            if e == 15 and m == 7:
+                continue
+            vals.append((m / 8.0) * 2.0 ** -6 if e == 0 else (1 + m / 8.0) * 2.0 ** (e - 7))
+    return np.array(sorted(vals))
+
+
+def test_e4m3_round_matches_enumeration():
+    codes = _e4m3_codes()
+    assert codes[-1] == 448.0 and codes[1] == 2.0 ** -9
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.uniform(-448, 448, 2000), rng.uniform(-0.05, 0.05, 2000),
+                        (codes[1:] + codes[:-1]) / 2])          # exact ties
+    got = mlp.e4m3_round(x)
+    for xi, gi in zip(x, got):
+        a = abs(xi)
+        i = np.searchsorted(codes, a)
+        lo, hi = codes[max(i - 1, 0)], codes[min(i, len(codes) - 1)]
+        if a - lo < hi - a:
+            ref = lo
+        elif hi - a < a - lo:
+            ref = hi
+        else:   # tie: the code with an even mantissa (even index in the sorted list)
+            ref = lo if np.searchsorted(codes, lo) % 2 == 0 else hi
+        assert gi == np.copysign(ref, xi), (xi, gi, ref)
+
+
+def test_e4m3_closed_form_values():
+    x = [1.0, 1.0625, 1.1875, 0.1, 448.0, 2.0 ** -9, 7 * 2.0 ** -9, 2.0 ** -10, -2.5]
+    ref = [1.0, 1.0, 1.25, 0.1015625, 448.0, 2.0 ** -9, 7 * 2.0 ** -9, 0.0, -2.5]
+    assert mlp.e4m3_round(x).tolist() == ref
+
+
+def test_forward_fp8_special_cases():
+    p = _params(7)
+    W1, b1, W2, b2, W3, b3 = mlp.unpack(p)
+    r = np.linspace(0.5, 2.9, 50)
+    # W2 = 0: layer 2 sees only its bias, so no quantisation error is possible
+    q = mlp.pack(W1, b1, np.zeros_like(W2), b2, W3, b3)
+    np.testing.assert_allclose(mlp.forward_fp8(q, r, RC, SCALE, TW), mlp.forward(q, r, RC, SCALE, TW),
+                               rtol=1e-13, atol=1e-13)
+    # in general within the E4M3 rounding of two factors (2^-4 each) through silu
+    f8, f = mlp.forward_fp8(p, r, RC, SCALE, TW), mlp.forward(p, r, RC, SCALE, TW)
+    assert np.linalg.norm(f8 - f) <= 0.25 * np.linalg.norm(f)
