@@ -60,7 +60,9 @@ typedef enum {
 } adres_status;
 
 enum { ADRES_REGION_ALL_AT = 0, ADRES_REGION_SLAB_X = 1, ADRES_REGION_SPHERE = 2, ADRES_REGION_ALL_CG = 3 };
-enum { ADRES_CG_WCA = 0, ADRES_CG_TABLE = 1, ADRES_CG_MLP = 2 };
+/* CG force between centres of mass: analytic WCA, cubic table, learned network with layer 2
+ * on BF16 matrix cores, or its FP8 variant (inference only; see adres_mlp_set). */
+enum { ADRES_CG_WCA = 0, ADRES_CG_TABLE = 1, ADRES_CG_MLP = 2, ADRES_CG_MLP_FP8 = 3 };
 enum { ADRES_BOND_NONE = 0, ADRES_BOND_HARMONIC = 1, ADRES_BOND_FENE = 2 };
 
 #define ADRES_MAX_SITES 4
@@ -161,7 +163,12 @@ adres_status adres_set_cg_table(adres_ctx *ctx, const float *coef4, int32_t n_kn
  * positive f = repulsive along R_ab / r.  Below r_min the installed cubic table is used
  * (the fallback).  Hidden width 64: params (host, float32, 4353 values) are
  * W1[64], b1[64], W2[64*64] (row = output unit), b2[64], W3[64], b3.  Layer 2 runs on
- * BF16 matrix cores with FP32 accumulation; layers 1 and 3 in FP32.  The values are
+ * BF16 matrix cores with FP32 accumulation; layers 1 and 3 in FP32.  With cg_kind
+ * ADRES_CG_MLP_FP8 layer 2 runs on FP8 E4M3 (OCP) matrix cores instead: W2 / s_w and
+ * h1 / (s_g ln 2) rounded to E4M3 (nearest even) with per-tensor scales s_w = max|W2| / 448
+ * and s_g = G / 448, G = 1.01 max(0.2785, max_u |silu(b1_u)|, max_u |silu(W1_u + b1_u)|)
+ * / ln 2 (a bound on |h1| / ln 2 for r / rc in [0, 1]), FP32 accumulation; each result
+ * then carries the E4M3 rounding of two factors (relative 2^-4 each).  The values are
  * copied; n_params must be 4353. */
 adres_status adres_mlp_set(adres_ctx *ctx, const float *params, int32_t n_params, double rc, double scale,
                            double taper_width, double r_min);
@@ -201,7 +208,7 @@ adres_status adres_mlp_train_step(adres_ctx *ctx, const double *com, const doubl
 /* Diagnostic: device time of the kernels enqueued since the last call, measured with
  * HIP events on the context's stream.  enable selects what the following calls record:
  * 0 nothing, 1 the force kernel (Eq. (1) with its fused integrator stages), 2 the learned
- * CG force's pair pre-pass (contexts with cg_kind ADRES_CG_MLP; one per force
+ * CG force's pair pre-pass (contexts with a network CG kind; one per force
  * evaluation); every >= 1 records only every every-th such launch (events slow the
  * launch stream down, so sampling keeps the timed run close to an untimed one).  Other
  * values give ADRES_E_ARG.  ms (host) receives the summed duration of the launches

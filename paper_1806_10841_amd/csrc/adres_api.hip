@@ -50,6 +50,8 @@ struct adres_ctx {
     // learned CG force
     float *mlp = nullptr;          // FP32 master parameters (kMlpParams)
     __bf16 *mlp_w2 = nullptr;      // BF16 copy of W2 (kHidden^2) followed by its transpose
+    int *mlp_w2q = nullptr;        // FP8 copy of W2 (kHidden^2 bytes)
+    float *mlp_fp8s = nullptr;     // its scales (3 floats)
     float *adam_m = nullptr, *adam_v = nullptr;
     int64_t adam_t = 0;
     double *grad = nullptr, *loss = nullptr, *res_part = nullptr, *resid = nullptr;
@@ -210,6 +212,9 @@ MlpDev mlp_dev(const adres_ctx *c)
     M.w3 = M.b2 + kHidden;
     M.w2_bf16 = c->mlp_w2;
     M.w2t_bf16 = c->mlp_w2 + kHidden * kHidden;
+    M.w2_fp8 = c->mlp_w2q;
+    M.fp8_scale = c->mlp_fp8s;
+    M.fp8 = c->P.cg_kind == ADRES_CG_MLP_FP8;
     M.rc = c->mlp_rc;
     M.scale = c->mlp_scale;
     M.tw = c->mlp_tw;
@@ -350,7 +355,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     if (q.region < ADRES_REGION_ALL_AT || q.region > ADRES_REGION_ALL_CG) return ADRES_E_ARG;
     if ((q.region == ADRES_REGION_SLAB_X || q.region == ADRES_REGION_SPHERE) && (q.d_at < 0.0 || q.d_hy < 0.0))
         return ADRES_E_ARG;
-    if (q.cg_kind < ADRES_CG_WCA || q.cg_kind > ADRES_CG_MLP) return ADRES_E_ARG;
+    if (q.cg_kind < ADRES_CG_WCA || q.cg_kind > ADRES_CG_MLP_FP8) return ADRES_E_ARG;
     if (q.bond_kind < ADRES_BOND_NONE || q.bond_kind > ADRES_BOND_FENE) return ADRES_E_ARG;
     if (q.bond_kind == ADRES_BOND_FENE && (q.sites_per_mol != 1 || q.chain_len < 1 || !(q.r0_bond > 0.0)))
         return ADRES_E_ARG;
@@ -503,7 +508,7 @@ void adres_destroy(adres_ctx *c)
     hipFree(c->R_ref); hipFree(c->inv_perm); hipFree(c->cell_rank);
     hipFree(c->count); hipFree(c->start); hipFree(c->fill); hipFree(c->new_from); hipFree(c->scan_tiles);
     hipFree(c->nbr); hipFree(c->cnt); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
-    hipFree(c->mlp); hipFree(c->mlp_w2); hipFree(c->cnt_up); hipFree(c->up_off); hipFree(c->up_scratch);
+    hipFree(c->mlp); hipFree(c->mlp_w2); hipFree(c->mlp_w2q); hipFree(c->mlp_fp8s); hipFree(c->cnt_up); hipFree(c->up_off); hipFree(c->up_scratch);
     hipFree(c->pid); hipFree(c->up_pairs); hipFree(c->f_pair);
     hipFree(c->adam_m); hipFree(c->adam_v); hipFree(c->grad); hipFree(c->loss); hipFree(c->res_part);
     hipFree(c->resid); hipFree(c->gpart); hipFree(c->gred);
@@ -751,6 +756,8 @@ adres_status adres_mlp_set(adres_ctx *c, const float *params, int32_t n_params, 
     if (!c->mlp) {
         HIPCHK(c, dalloc(&c->mlp, kMlpParams));
         HIPCHK(c, dalloc(&c->mlp_w2, (size_t)2 * kHidden * kHidden));
+        HIPCHK(c, dalloc(&c->mlp_w2q, (size_t)kHidden * kHidden / 4));
+        HIPCHK(c, dalloc(&c->mlp_fp8s, 4));
         HIPCHK(c, dalloc(&c->adam_m, kMlpParams));
         HIPCHK(c, dalloc(&c->adam_v, kMlpParams));
     }
@@ -759,6 +766,7 @@ adres_status adres_mlp_set(adres_ctx *c, const float *params, int32_t n_params, 
     HIPCHK(c, hipMemset(c->adam_v, 0, sizeof(float) * kMlpParams));
     c->adam_t = 0;
     launch_mlp_convert(c->stream, c->mlp, c->mlp_w2, c->mlp_w2 + kHidden * kHidden);
+    launch_mlp_fp8_prepare(c->stream, c->mlp, c->mlp_w2q, c->mlp_fp8s);
     HIPCHK(c, hipGetLastError());
     c->mlp_rc = rc;
     c->mlp_scale = scale;
@@ -797,7 +805,7 @@ namespace {
 adres_status fm_accumulate(adres_ctx *c, const double *com, const double *fmap, int32_t n_frames)
 {
     if (!com || !fmap || n_frames < 1) return fail(c, ADRES_E_ARG, "need frames of centres and mapped forces");
-    if (c->P.spm != 1 || c->P.region != ADRES_REGION_ALL_CG || !is_mlp(c))
+    if (c->P.spm != 1 || c->P.region != ADRES_REGION_ALL_CG || c->P.cg_kind != ADRES_CG_MLP)
         return fail(c, ADRES_E_STATE, "force matching needs a context of CG sites (1 site, all CG, MLP kind)");
     if (!c->have_mlp) return fail(c, ADRES_E_STATE, "no network installed");
     const int n = c->P.n_mol;

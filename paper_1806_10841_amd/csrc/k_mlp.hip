@@ -59,6 +59,7 @@ __device__ __forceinline__ double pair_r(const PairSource &src, const DevParams 
     return sqrt(dist2_exact(d0, d1, d2));
 }
 
+template <bool FP8>
 __global__ __launch_bounds__(kBlockM) void k_mlp_forward(MlpDev M, DevParams P, PairSource src, float *__restrict__ out,
                                                         Ctrl *ctrl, int check_halt, int step)
 {
@@ -79,20 +80,33 @@ __global__ __launch_bounds__(kBlockM) void k_mlp_forward(MlpDev M, DevParams P, 
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
-    // A operands: W2 rows (output units) 32 mb + col, K columns 16 kb + 8 half .. +7
+    // A operands: W2 rows (output units) 32 mb + col; BF16: K columns 16 kb + 8 half .. +7;
+    // FP8 (32x32x64, one K-block): K columns 32 half .. +31
     bf16x8 Wop[2][4];
+    int32x8 Wq[2];
+    float dq = 1.0f, inv_sg = 1.0f, inv_dq = 1.0f;
+    if constexpr (FP8) {
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+        for (int mb = 0; mb < 2; ++mb)
+            Wq[mb] = *reinterpret_cast<const int32x8 *>(M.w2_fp8 + (32 * mb + col) * (kHidden / 4) + 8 * half);
+        dq = M.fp8_scale[0];
+        inv_sg = M.fp8_scale[1];
+        inv_dq = M.fp8_scale[2];
+    } else {
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb)
-            Wop[mb][kb] = *reinterpret_cast<const bf16x8 *>(M.w2_bf16 + (32 * mb + col) * kHidden + 16 * kb + 8 * half);
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb)
+                Wop[mb][kb] =
+                    *reinterpret_cast<const bf16x8 *>(M.w2_bf16 + (32 * mb + col) * kHidden + 16 * kb + 8 * half);
+    }
     // -log2e b2 of the output units of this lane's result rows (32 mb + 8 (v / 4) + 4 half
-    // + v % 4): the accumulator's initial value
+    // + v % 4): the accumulator's initial value (FP8: in units of the product's scale)
     floatx16 c2[2];
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) c2[mb][v] = -kLog2e * M.b2[32 * mb + 8 * (v >> 2) + 4 * half + (v & 3)];
+        for (int v = 0; v < 16; ++v) c2[mb][v] = -kLog2e * M.b2[32 * mb + 8 * (v >> 2) + 4 * half + (v & 3)] * inv_dq;
     const float b3 = M.w3[kHidden], inv_rc = 1.0f / (float)M.rc, rcf = (float)M.rc, twf = (float)M.tw, sc = (float)M.scale;
 
     // Pairs are read in windows of 64 (one per lane).  A pair below r_min takes the table
@@ -111,23 +125,45 @@ __global__ __launch_bounds__(kBlockM) void k_mlp_forward(MlpDev M, DevParams P, 
         const int p = qp[wv][slot];
         const float x = (float)r * inv_rc;
         bf16x8 H[4];
+        int32x8 Hq;
+        if constexpr (FP8) {
+            // g1 / s_g of input units 32 half + 4 w + e, rounded to E4M3 (nearest even), four per word
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb)
+            for (int w = 0; w < 8; ++w) {
+                float g[4];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int u = 16 * kb + 8 * half + j;
-                const float t = fmaf(sW1[u], x, sB1[u]);
-                H[kb][j] = (__bf16)(t * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t)));
+                for (int e = 0; e < 4; ++e) {
+                    const int u = 32 * half + 4 * w + e;
+                    const float t = fmaf(sW1[u], x, sB1[u]);
+                    g[e] = t * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t)) * inv_sg;
+                }
+                int pk = __builtin_amdgcn_cvt_pk_fp8_f32(g[0], g[1], 0, false);
+                Hq[w] = __builtin_amdgcn_cvt_pk_fp8_f32(g[2], g[3], pk, true);
             }
+        } else {
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int u = 16 * kb + 8 * half + j;
+                    const float t = fmaf(sW1[u], x, sB1[u]);
+                    H[kb][j] = (__bf16)(t * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t)));
+                }
+        }
         float y = 0.0f;
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb) {
             floatx16 acc = c2[mb];
+            if constexpr (FP8) {
+                acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(Wq[mb], Hq, acc, 0, 0, 0, 0, 0, 0);
+            } else {
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Wop[mb][kb], H[kb], acc, 0, 0, 0);
+                for (int kb = 0; kb < 4; ++kb)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Wop[mb][kb], H[kb], acc, 0, 0, 0);
+            }
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                const float t = acc[v];
+                const float t = acc[v] * dq;
                 const float w = sW3[32 * mb + 8 * (v >> 2) + 4 * half + (v & 3)];
                 y = fmaf(w * t, __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t)), y);
             }
@@ -188,7 +224,8 @@ void launch_mlp_forward_r(hipStream_t s, const MlpDev &M, const DevParams &P, co
     PairSource src{r, nullptr, nullptr, n, nullptr};
     const int64_t tiles = (n + kTile - 1) / kTile;
     const int blocks = (int)std::min<int64_t>((tiles + kWaves - 1) / kWaves, 4096);
-    k_mlp_forward<<<std::max(blocks, 1), kBlockM, 0, s>>>(M, P, src, f, ctrl, 0, 0);
+    if (M.fp8) k_mlp_forward<true><<<std::max(blocks, 1), kBlockM, 0, s>>>(M, P, src, f, ctrl, 0, 0);
+    else k_mlp_forward<false><<<std::max(blocks, 1), kBlockM, 0, s>>>(M, P, src, f, ctrl, 0, 0);
 }
 
 void launch_mlp_forward_pairs(hipStream_t s, const MlpDev &M, const DevParams &P, const int2 *pairs,
@@ -198,7 +235,8 @@ void launch_mlp_forward_pairs(hipStream_t s, const MlpDev &M, const DevParams &P
     PairSource src{nullptr, pairs, Rw, 0, n_dev};
     const int64_t tiles = (n_cap + kTile - 1) / kTile;
     const int blocks = (int)std::min<int64_t>((tiles + kWaves - 1) / kWaves, 4096);
-    k_mlp_forward<<<std::max(blocks, 1), kBlockM, 0, s>>>(M, P, src, f, ctrl, check_halt, step);
+    if (M.fp8) k_mlp_forward<true><<<std::max(blocks, 1), kBlockM, 0, s>>>(M, P, src, f, ctrl, check_halt, step);
+    else k_mlp_forward<false><<<std::max(blocks, 1), kBlockM, 0, s>>>(M, P, src, f, ctrl, check_halt, step);
 }
 
 }  // namespace adres
@@ -214,6 +252,52 @@ __global__ void k_mlp_convert(const float *__restrict__ params, __bf16 *__restri
     w2t[(i % kHidden) * kHidden + i / kHidden] = b;
 }
 }  // namespace
+
+// FP8 variant: s_w = max |W2| / 448 and s_g = G / 448 with G = 1.01 max(0.2785,
+// max_u |silu(b1_u)|, max_u |silu(W1_u + b1_u)|) / ln 2, a bound on |h1| / ln 2 for inputs
+// x = r / rc in [0, 1] (silu is monotone above its minimum -0.27846); W2 / s_w rounded to
+// E4M3 (nearest even), row-major, four values per word.  One workgroup.
+__global__ __launch_bounds__(256) void k_mlp_fp8_prepare(const float *__restrict__ params, int *__restrict__ w2q,
+                                                        float *__restrict__ scale)
+{
+    __shared__ float red_w[256], red_g[256];
+    const float *W1 = params, *b1 = params + kHidden, *W2 = params + 2 * kHidden;
+    float wm = 0.0f, gm = 0.0f;
+    for (int i = threadIdx.x; i < kHidden * kHidden; i += 256) wm = fmaxf(wm, fabsf(W2[i]));
+    if (threadIdx.x < kHidden) {
+        const int u = threadIdx.x;
+        const float z0 = b1[u], z1 = W1[u] + b1[u];
+        gm = fmaxf(fabsf(z0 / (1.0f + expf(-z0))), fabsf(z1 / (1.0f + expf(-z1))));
+    }
+    red_w[threadIdx.x] = wm;
+    red_g[threadIdx.x] = gm;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if (threadIdx.x < h) {
+            red_w[threadIdx.x] = fmaxf(red_w[threadIdx.x], red_w[threadIdx.x + h]);
+            red_g[threadIdx.x] = fmaxf(red_g[threadIdx.x], red_g[threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    const float s_w = red_w[0] > 0.0f ? red_w[0] / 448.0f : 1.0f;
+    const float G = 1.01f * fmaxf(0.2785f, red_g[0]) / 0.6931471805599453f;
+    const float s_g = G / 448.0f;
+    const float inv_sw = 1.0f / s_w;
+    for (int k = threadIdx.x; k < kHidden * kHidden / 4; k += 256) {
+        const int pk = __builtin_amdgcn_cvt_pk_fp8_f32(W2[4 * k] * inv_sw, W2[4 * k + 1] * inv_sw, 0, false);
+        w2q[k] = __builtin_amdgcn_cvt_pk_fp8_f32(W2[4 * k + 2] * inv_sw, W2[4 * k + 3] * inv_sw, pk, true);
+    }
+    if (threadIdx.x == 0) {
+        scale[0] = s_w * s_g;
+        scale[1] = 1.0f / s_g;
+        scale[2] = 1.0f / (s_w * s_g);
+    }
+}
+
+void launch_mlp_fp8_prepare(hipStream_t s, const float *params, int *w2_fp8, float *scale)
+{
+    k_mlp_fp8_prepare<<<1, 256, 0, s>>>(params, w2_fp8, scale);
+}
 
 void launch_mlp_convert(hipStream_t s, const float *params, __bf16 *w2_bf16, __bf16 *w2t_bf16)
 {

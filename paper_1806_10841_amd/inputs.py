@@ -39,6 +39,7 @@ REGION_ALL_CG = 3   # w == 0 everywhere (plain coarse-grained MD)
 CG_WCA = 0      # analytic WCA between centres of mass
 CG_TABLE = 1    # cubic-spline table of the CG force
 CG_MLP = 2      # learned MLP, BF16 matrix cores
+CG_MLP_FP8 = 3  # the same network with layer 2 on FP8 E4M3 matrix cores
 
 BOND_NONE = 0
 BOND_HARMONIC = 1   # harmonic bonds between every pair of sites of a molecule

@@ -192,15 +192,17 @@ def test_c5_sphere_table_full_size(dev):
     assert torch.isfinite(xt).all()
 
 
-def test_c5_sphere_learned_cg_full_size(dev):
+@pytest.mark.parametrize("kind,bar", [(inputs.CG_MLP, BF16_NORM), (inputs.CG_MLP_FP8, 2.0 ** -2)])
+def test_c5_sphere_learned_cg_full_size(dev, kind, bar):
     """The same 1,000,000-tetrahedron sphere with the learned CG force between centres (the
-    table as fallback below r_min): sampled AT, HY and CG molecules within the BF16 bar."""
-    wl = inputs.workload("c5").with_(cg_kind=inputs.CG_MLP, rc_cg=RC_MLP)
+    table as fallback below r_min), BF16 or FP8 matrix cores: sampled AT, HY and CG
+    molecules against the FP64 network within the BF16 bar (2^-7) or the FP8 bar (2^-2)."""
+    wl = inputs.workload("c5").with_(cg_kind=kind, rc_cg=RC_MLP)
     x, _ = inputs.make_state(wl)
     table = _c5_table(wl)
     p = inputs.mlp_init(45).astype(np.float32)
     r_min = 1.6
-    m = oracle.Model(wl, table=table, mlp=(p.astype(np.float64), RC_MLP, SCALE, TW, r_min))
+    m = oracle.Model(wl.with_(cg_kind=inputs.CG_MLP), table=table, mlp=(p.astype(np.float64), RC_MLP, SCALE, TW, r_min))
     _, w_o, _, _ = m.weights(x)
     sel = _sample_by_class(w_o, 100, 6)
     fo, _, st = m.forces_sampled(x, sel)
@@ -210,5 +212,5 @@ def test_c5_sphere_learned_cg_full_size(dev):
     ctx.mlp_set(p, RC_MLP, SCALE, TW, r_min)
     f = ctx.forces(_t(x, dev)).cpu().numpy()
     fg = _sampled_forces(f, sel, 4)
-    assert np.linalg.norm(fg - fo) <= BF16_NORM * np.linalg.norm(fo)
+    assert np.linalg.norm(fg - fo) <= bar * np.linalg.norm(fo)
     _newton3(f)

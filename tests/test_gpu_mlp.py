@@ -175,3 +175,52 @@ def test_training_reduces_loss(dev):
     tc, tf = torch.tensor(coms, device=dev), torch.tensor(fm, device=dev)
     losses = [ctx.mlp_train_step(tc, tf, 3e-3) for _ in range(60)]
     assert losses[-1] < 0.2 * losses[0], (losses[0], losses[-1])
+
+
+# ---------------------------------------------------------------- FP8 E4M3 variant
+def _fp8_workload(name="small_cg"):
+    return inputs.workload(name).with_(cg_kind=inputs.CG_MLP_FP8, rc_cg=RC, pair_precision=32)
+
+
+def test_mlp_fp8_eval_matches_oracle(dev):
+    """The FP8 variant against (a) the oracle's definition of it (h1 and W2 rounded to E4M3
+    with the same per-tensor scales, everything else FP64): equal up to FP32 arithmetic and
+    rare rounding-boundary flips, 2^-8 normwise; (b) the FP64 network: the E4M3 rounding of
+    two factors (2^-4 each) through silu, 2^-2 normwise, its RMSE printed."""
+    p32 = inputs.mlp_init(13).astype(np.float32)
+    p = p32.astype(np.float64)
+    r = inputs.random_pair_distances(100003, 0.5, RC, 3)
+    ctx = _ctx(_fp8_workload())
+    ctx.mlp_set(p32, RC, SCALE, TW, 0.0)
+    f = ctx.mlp_eval(torch.tensor(r, device=dev)).cpu().numpy().astype(np.float64)
+    ref8 = omlp.forward_fp8(p, r, RC, SCALE, TW)
+    ref = omlp.forward(p, r, RC, SCALE, TW)
+    print(f"FP8 vs FP64 network: relative RMSE {np.linalg.norm(f - ref) / np.linalg.norm(ref):.4f}")
+    assert np.linalg.norm(f - ref8) <= 2.0 ** -8 * np.linalg.norm(ref8)
+    assert np.linalg.norm(f - ref) <= 2.0 ** -2 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("name", ["small_cg", "small_slab"])
+def test_forces_with_learned_cg_fp8(dev, name):
+    """Eq. (1) with the FP8 network as F^CG against the oracle's FP64 network: 2^-2 normwise
+    (the FP8 bar); Newton's third law exact per pair."""
+    p = inputs.mlp_init(11).astype(np.float32).astype(np.float64)
+    wl = _fp8_workload(name)
+    x, _ = inputs.make_state(wl)
+    fo, _, _, st = oracle.Model(wl.with_(cg_kind=inputs.CG_MLP), mlp=(p, RC, SCALE, TW, 0.0)).forces(x)
+    assert st == 0
+    ctx = _ctx(wl)
+    ctx.mlp_set(p.astype(np.float32), RC, SCALE, TW, 0.0)
+    f = ctx.forces(torch.tensor(x, device=dev)).cpu().numpy()
+    assert np.linalg.norm(f - fo) <= 2.0 ** -2 * np.linalg.norm(fo)
+    assert np.all(np.abs(f.sum(axis=1)) <= 1e-9 * np.abs(f).sum(axis=1))
+
+
+def test_fp8_kind_is_not_trained(dev):
+    from paper_1806_10841_amd import binding
+    coms, fmaps, box = _cg_frames(1, seed=24)
+    wl = _cg_workload(coms.shape[2], box).with_(cg_kind=inputs.CG_MLP_FP8)
+    ctx = _ctx(wl)
+    ctx.mlp_set(inputs.mlp_init(3).astype(np.float32), RC, SCALE, TW, 0.0)
+    with pytest.raises(binding.AdresError):
+        ctx.mlp_train_step(torch.tensor(coms, device=dev), torch.tensor(fmaps, device=dev), 1e-3)
