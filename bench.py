@@ -15,8 +15,9 @@ The second half of the metric, learned vs tabulated CG force, is measured on 256
 CG sites (a centre frame of the headline geometry tiled 2 x 2 x 1, cutoff 3.0): frames
 of centres and mapped forces from an all-atomistic Langevin run made by the library,
 a force-matched cubic table (least squares, host) and the network trained on the GPU
-on the same frames, held-out force RMSE of each (and of the plain method's CG force),
-then MD steps/s of the 256k-site CG liquid with either force.
+on the same frames, held-out force RMSE of each (and of the plain method's CG force and of
+the network's FP8 E4M3 variant), then MD steps/s of the 256k-site CG liquid with the table,
+the network (BF16 matrix cores) and its FP8 variant.
 """
 from __future__ import annotations
 
@@ -242,15 +243,16 @@ def learned_vs_tabulated(cg_steps):
         "plain_cg_wca": cgtrain.rmse_on_device(com[te], fmap[te], box, inputs.CG_WCA),
         "fm_table": cgtrain.rmse_on_device(com[te], fmap[te], box, inputs.CG_TABLE, table=table),
         "mlp": cgtrain.rmse_on_device(com[te], fmap[te], box, inputs.CG_MLP, table=table, mlp=mlp),
+        "mlp_fp8": cgtrain.rmse_on_device(com[te], fmap[te], box, inputs.CG_MLP_FP8, table=table, mlp=mlp),
     }
     c4, box4 = cgtrain.tile_frame(com_np[-1], box, (2, 2, 1))
     n4 = c4.shape[1]
     v4 = inputs.maxwell_velocities(n4, np.full(n4, 4.0), 1.0, np.random.default_rng(1004))
     runs = {}
-    for name, kind in (("table", inputs.CG_TABLE), ("mlp", inputs.CG_MLP)):
+    for name, kind in (("table", inputs.CG_TABLE), ("mlp", inputs.CG_MLP), ("mlp_fp8", inputs.CG_MLP_FP8)):
         ctx = binding.Context(cgtrain.cg_workload(n4, box4, kind))
         ctx.set_cg_table(*table)
-        if kind == inputs.CG_MLP:
+        if kind != inputs.CG_TABLE:
             ctx.mlp_set(params, 3.0, scale, tw, r_min)
         xt = torch.tensor(inputs.wrap_into_box(c4, box4), device="cuda")
         vt = torch.tensor(v4, device="cuda")
@@ -262,9 +264,9 @@ def learned_vs_tabulated(cg_steps):
         nreb = ctx.integrate(xt, vt, ft, 0.005, cg_steps)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        f_ms, f_n = ctx.kernel_timing(2 if kind == inputs.CG_MLP else 0, every=TIMING_EVERY)
+        f_ms, f_n = ctx.kernel_timing(0 if kind == inputs.CG_TABLE else 2, every=TIMING_EVERY)
         rec = {"steps_per_s": cg_steps / el, "list_rebuilds": nreb, "force_kernel_us": 1e3 * f_ms / max(f_n, 1)}
-        if kind == inputs.CG_MLP:
+        if kind != inputs.CG_TABLE:
             ctx.integrate(xt, vt, ft, 0.005, cg_steps)
             m_ms, m_n = ctx.kernel_timing(0)
             rec["mlp_prepass_us"] = 1e3 * m_ms / max(m_n, 1)
@@ -279,6 +281,7 @@ def learned_vs_tabulated(cg_steps):
                     "cutoff 3.0, NVE velocity Verlet dt 0.005",
         "steps": cg_steps,
         "mlp_steps_per_s": runs["mlp"]["steps_per_s"],
+        "mlp_fp8_steps_per_s": runs["mlp_fp8"]["steps_per_s"],
         "table_steps_per_s": runs["table"]["steps_per_s"],
         "force_rmse_heldout": rmse,
         "mapped_force_rms": cgtrain.force_scale(fmap[te]),
