@@ -186,6 +186,7 @@ bool is_mlp(const adres_ctx *c) { return c->P.cg_kind >= ADRES_CG_MLP; }
 adres_status build_half_list(adres_ctx *c)
 {
     const int n = c->P.n_mol;
+    if (c->cap > 2048) return fail(c, ADRES_E_CAPACITY, "neighbour rows longer than 2048 entries");
     if (c->half_rows_cap < c->cap) {
         hipFree(c->pid); hipFree(c->up_pairs); hipFree(c->f_pair);
         c->pid = nullptr; c->up_pairs = nullptr; c->f_pair = nullptr;
@@ -196,8 +197,8 @@ adres_status build_half_list(adres_ctx *c)
         c->half_rows_cap = c->cap;
         c->half_pairs_cap = (int64_t)cap_pairs;
     }
-    if (c->cap > 2048) return fail(c, ADRES_E_CAPACITY, "neighbour rows longer than 2048 entries");
-    launch_half_list(c->stream, n, c->nbr, c->cnt, c->cap, c->cnt_up, c->up_off, c->up_scratch, c->up_pairs, c->pid);
+    launch_half_list(c->stream, n, c->nbr, c->cnt, c->cap, c->cnt_up, c->up_off, c->up_scratch, c->up_pairs,
+                     c->half_pairs_cap, c->pid);
     HIPCHK(c, hipGetLastError());
     return ADRES_OK;
 }

@@ -362,7 +362,7 @@ void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const i
 
 // half list (t < u pairs) + per-entry pair ids; up_off receives n + 1 offsets
 void launch_half_list(hipStream_t s, int n, int *nbr, const int *cnt, int cap, int *cnt_up, int *up_off,
-                      int *scratch, int2 *pairs, int *pid);
+                      int *scratch, int2 *pairs, int64_t pairs_cap, int *pid);
 
 // forces
 enum ForceMode : int {

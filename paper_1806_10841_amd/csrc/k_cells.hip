@@ -327,7 +327,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_rows(int n, int *__restrict__ n
     extern __shared__ int srow[];   // kSortRows rows of cap entries
     const int g = threadIdx.x >> 5, lane = threadIdx.x & 31;
     const int t = blockIdx.x * kSortRows + g;
-    const int c = t < n ? cnt[t] : 0;
+    // a row that overflowed its capacity (count > cap) holds only cap entries; the list is
+    // rebuilt with a larger capacity before anything reads it, so clamping keeps this safe
+    const int c = t < n ? min(cnt[t], cap) : 0;
     int *row = nbr + (int64_t)(t < n ? t : 0) * cap;
     int *sr = srow + g * cap;
     for (int k = lane; k < c; k += 32) sr[k] = row[k];
@@ -347,22 +349,22 @@ __global__ __launch_bounds__(kBlock) void k_sort_rows(int n, int *__restrict__ n
 
 __global__ __launch_bounds__(kBlock) void k_up_entries(int n, const int *__restrict__ nbr, const int *__restrict__ cnt,
                                                       int cap, const int *__restrict__ up_off, int2 *__restrict__ pairs,
-                                                      int *__restrict__ pid)
+                                                      int64_t pairs_cap, int *__restrict__ pid)
 {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= (int64_t)n * cap) return;
     const int t = (int)(e / cap), k = (int)(e - (int64_t)t * cap);
-    const int ct = cnt[t];
+    const int ct = min(cnt[t], cap);   // see k_sort_rows
     if (k >= ct) return;
     const int u = nbr[e];
     if (u > t) {
         const int lb = ct - (up_off[t + 1] - up_off[t]);
         const int p = up_off[t] + k - lb;
-        pairs[p] = make_int2(t, u);
+        if (p < pairs_cap) pairs[p] = make_int2(t, u);   // only an overflowed list can exceed it
         pid[e] = p;
     } else {
         const int *ru = nbr + (int64_t)u * cap;
-        const int cu = cnt[u];
+        const int cu = min(cnt[u], cap);
         int lo = 0, hi = cu;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
@@ -377,13 +379,13 @@ __global__ __launch_bounds__(kBlock) void k_up_entries(int n, const int *__restr
 }  // namespace
 
 void launch_half_list(hipStream_t s, int n, int *nbr, const int *cnt, int cap, int *cnt_up, int *up_off,
-                      int *scratch, int2 *pairs, int *pid)
+                      int *scratch, int2 *pairs, int64_t pairs_cap, int *pid)
 {
     k_sort_rows<<<(n + kSortRows - 1) / kSortRows, kBlock, (size_t)kSortRows * cap * sizeof(int), s>>>(n, nbr, cnt, cap,
                                                                                                      cnt_up);
     launch_scan_cells(s, cnt_up, n, up_off, nullptr, scratch);
     const int64_t entries = (int64_t)n * cap;
-    k_up_entries<<<(unsigned)((entries + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, nbr, cnt, cap, up_off, pairs, pid);
+    k_up_entries<<<(unsigned)((entries + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, nbr, cnt, cap, up_off, pairs, pairs_cap, pid);
 }
 
 void launch_cell_keys(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank,

@@ -44,7 +44,7 @@ struct PairSource {
     const double *r;        // non-null: distances
     const int2 *pairs;      // else: (t, u) slot pairs
     const double4 *Rw;
-    int64_t n;              // pair count, or read from n_dev when that is non-null
+    int64_t n;              // pair count; with n_dev: the capacity, the count read from n_dev
     const int *n_dev;
 };
 
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kBlockM) void k_mlp_forward(MlpDev M, DevParams P, 
                                                         Ctrl *ctrl, int check_halt, int step)
 {
     if (check_halt && step > ctrl->halt) return;
-    if (src.n_dev) src.n = *src.n_dev;
+    if (src.n_dev) src.n = min((int64_t)*src.n_dev, src.n);   // src.n holds the buffer capacity here
     // silu(z) = z / (1 + 2^t) with t = -log2(e) z.  The constants are folded so that each
     // layer works on t directly: layer 1 forms t1 = (-log2e W1) x + (-log2e b1) and hands
     // g1 = t1 / (1 + 2^t1) = silu(z1) / (-ln 2) to the matrix cores, whose product with W2
@@ -232,7 +232,7 @@ void launch_mlp_forward_pairs(hipStream_t s, const MlpDev &M, const DevParams &P
                               const double4 *Rw, float *f, const int *n_dev, int64_t n_cap, Ctrl *ctrl,
                               int check_halt, int step)
 {
-    PairSource src{nullptr, pairs, Rw, 0, n_dev};
+    PairSource src{nullptr, pairs, Rw, n_cap, n_dev};
     const int64_t tiles = (n_cap + kTile - 1) / kTile;
     const int blocks = (int)std::min<int64_t>((tiles + kWaves - 1) / kWaves, 4096);
     if (M.fp8) k_mlp_forward<true><<<std::max(blocks, 1), kBlockM, 0, s>>>(M, P, src, f, ctrl, check_halt, step);
