@@ -50,7 +50,7 @@ typedef enum {
     ADRES_E_ARG = -1,          /* invalid argument or parameter */
     ADRES_E_NOMEM = -2,        /* device or host allocation failed */
     ADRES_E_HIP = -3,          /* a HIP runtime call failed */
-    ADRES_E_BOX = -4,          /* box shorter than twice the list radius */
+    ADRES_E_BOX = -4,          /* box shorter than twice the list radius, or over 2^20 cells */
     ADRES_E_CAPACITY = -5,     /* neighbour list could not be grown */
     ADRES_E_STRETCH = -6,      /* a site is farther than rho_max from its centre of mass */
     ADRES_E_NONFINITE = -7,    /* a force or position is NaN or infinite */
@@ -91,7 +91,8 @@ typedef struct {
 /* Create a context for one system on the current HIP device.  hip_stream is a
  * hipStream_t (NULL = default stream).  Validates the parameters (ADRES_E_ARG),
  * derives the list radius r_list = max(rc_cg, rc_at + 2 rho_max) + r_skin and the
- * cell grid (ADRES_E_BOX if any box length is below 2 r_list), and allocates the
+ * cell grid (ADRES_E_BOX if any box length is below 2 r_list or the grid has more than
+ * 2^20 cells), and allocates the
  * context's device state.  *out is set only on success. */
 adres_status adres_create(const adres_params *params, void *hip_stream, adres_ctx **out);
 

@@ -411,6 +411,10 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
         G.off_hi[d] = nd >= 2 ? 1 : 0;
         G.n_cells *= nd;
     }
+    if (G.n_cells > scan_max_elements()) {   // the cell scan covers at most 2^20 cells
+        delete c;
+        return ADRES_E_BOX;
+    }
     P.region = q.region;
     P.d_at = q.d_at;
     P.d_hy = q.d_hy;
