@@ -37,10 +37,9 @@ __global__ __launch_bounds__(kBlock) void k_cell_keys(DevParams P, Grid G, const
     atomicAdd(&count[k], 1);
 }
 
-// Exclusive scan of count[0..n) into start[0..n] in three launches: each workgroup
-// scans a tile of 1024 counts (4 per thread; wavefront shuffles, then the 4 wave
-// totals), one workgroup scans the tile totals, a third pass adds the tile offsets
-// and resets count and fill for the next build.
+// Exclusive scan of count[0..n) into start[0..n] in two launches: each workgroup scans a
+// tile of 1024 counts (4 per thread; wavefront shuffles, then the 4 wave totals) and
+// records the tile's total; a second pass adds to every tile the totals before it.
 constexpr int kScanThreads = 256;
 constexpr int kScanTile = 4 * kScanThreads;
 
@@ -85,33 +84,32 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int *__restri
     if (threadIdx.x == 0) tiles[blockIdx.x] = total;
 }
 
-// scans up to kScanTile tile totals in one workgroup; start[n] = grand total
-__global__ __launch_bounds__(kScanThreads) void k_scan_tile_totals(int *__restrict__ tiles, int n_tiles,
-                                                                   int *__restrict__ start, int n)
+// Second pass: workgroup T adds the sum of the tile totals before tile T to its tile
+// (each workgroup sums at most kScanTile totals itself), resets count and fill for the
+// next build, and the last workgroup writes start[n], the grand total.
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(int *__restrict__ count, int n, int *__restrict__ start,
+                                                           const int *__restrict__ tiles, int n_tiles,
+                                                           int *__restrict__ fill)
 {
-    const int base = 4 * threadIdx.x;
-    int c[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) c[j] = base + j < n_tiles ? tiles[base + j] : 0;
-    const int mine = (c[0] + c[1]) + (c[2] + c[3]);
-    int total;
-    int run = block_exclusive_scan(mine, total);
+    const int T = blockIdx.x;
+    int part = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        if (base + j < n_tiles) tiles[base + j] = run;
-        run += c[j];
+        const int k = 4 * threadIdx.x + j;
+        part += k < T ? tiles[k] : 0;
     }
-    if (threadIdx.x == 0) start[n] = total;
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_add(int *__restrict__ count, int n, int *__restrict__ start,
-                                                           const int *__restrict__ tiles, int *__restrict__ fill)
-{
-    const int i = blockIdx.x * kScanThreads + threadIdx.x;
-    if (i >= n) return;
-    start[i] += tiles[i / kScanTile];
-    count[i] = 0;
-    if (fill) fill[i] = 0;
+    int before;
+    block_exclusive_scan(part, before);   // before = sum of the totals of tiles 0 .. T-1
+    if (T == n_tiles - 1 && threadIdx.x == 0) start[n] = before + tiles[T];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int i = T * kScanTile + j * kScanThreads + threadIdx.x;
+        if (i < n) {
+            start[i] += before;
+            count[i] = 0;
+            if (fill) fill[i] = 0;
+        }
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter_slots(int n_mol, const int *__restrict__ key,
@@ -192,7 +190,6 @@ __global__ __launch_bounds__(kBlock) void k_permute(DevParams P, const int *__re
     for (int j = 0; j < 3 * SPM; ++j) of[j] = src.off[(int64_t)i * (3 * SPM) + j];
     const double4 r = src.Rw[i];
     const float rh = src.rho[i];
-    const int key = src.key[i];
     const int caller = src.perm[i];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
@@ -206,7 +203,6 @@ __global__ __launch_bounds__(kBlock) void k_permute(DevParams P, const int *__re
     dst.Rw[t] = r;
     R_ref[t] = r;
     dst.rho[t] = rh;
-    dst.key[t] = key;
     dst.perm[t] = caller;
     inv_perm[caller] = t;
 }
@@ -398,8 +394,7 @@ void launch_scan_cells(hipStream_t s, int *count, int n, int *start, int *fill, 
 {
     const int n_tiles = (n + kScanTile - 1) / kScanTile;
     k_scan_tiles<<<n_tiles, kScanThreads, 0, s>>>(count, n, start, tiles);
-    k_scan_tile_totals<<<1, kScanThreads, 0, s>>>(tiles, n_tiles, start, n);
-    k_scan_add<<<(n + kScanThreads - 1) / kScanThreads, kScanThreads, 0, s>>>(count, n, start, tiles, fill);
+    k_scan_add<<<n_tiles, kScanThreads, 0, s>>>(count, n, start, tiles, n_tiles, fill);
 }
 
 int scan_max_elements() { return kScanTile * kScanTile; }
