@@ -42,8 +42,10 @@ def assert_forces_close(fg, fo, amag, tol, where=""):
 
 
 def _morton(cx, cy, cz):
+    """Morton code of cell coordinates (scalars or integer arrays), x in the lowest bit."""
     def spread(v):
-        r = 0
+        v = np.asarray(v, dtype=np.int64)
+        r = np.zeros_like(v)
         for b in range(10):
             r |= ((v >> b) & 1) << (3 * b)
         return r
@@ -53,7 +55,7 @@ def _morton(cx, cy, cz):
 WORKLOADS_SMALL = ["tiny_slab", "c1", "small_slab", "small_sphere"]
 
 
-@pytest.mark.parametrize("name", WORKLOADS_SMALL + ["small_cg", "small_kg", "c2"])
+@pytest.mark.parametrize("name", WORKLOADS_SMALL + ["small_cg", "small_kg", "c2", "c3", "c4", "c5"])
 def test_weights(dev, name):
     wl = inputs.workload(name)
     x, _ = inputs.make_state(wl)
@@ -67,7 +69,7 @@ def test_weights(dev, name):
         assert (w_o == 1).any() and (w_o == 0).any() and ((w_o > 0) & (w_o < 1)).any()
 
 
-@pytest.mark.parametrize("name", ["c1", "small_slab", "small_cg", "c2"])
+@pytest.mark.parametrize("name", ["c1", "small_slab", "small_cg", "c2", "c3", "c4", "c5"])
 def test_cell_list_valid(dev, name):
     """Morton-ordered cell list: a permutation, every molecule in the cell of its centre,
     cells in Morton order, caller order inside a cell."""
@@ -83,7 +85,7 @@ def test_cell_list_valid(dev, name):
     rl = oracle.Model(wl).r_list()
     nc = [int(np.floor(wl.box[d] / (rl * (1 + 1e-12)))) for d in range(3)]
     cells = np.stack([np.minimum((com_o[d] * (nc[d] / wl.box[d])).astype(np.int64), nc[d] - 1) for d in range(3)])
-    codes = np.array([_morton(*c) for c in cells.T])
+    codes = _morton(cells[0], cells[1], cells[2])
     # rank of each molecule's cell in Morton order
     order = np.argsort(codes[perm], kind="stable")
     assert np.all(np.diff(codes[perm]) >= 0), "slots not in Morton order of their cells"
