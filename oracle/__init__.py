@@ -61,6 +61,7 @@ class Params(C.Structure):
         ("mlp", C.POINTER(C.c_double)), ("mlp_hidden", C.c_int32),
         ("mlp_rc", C.c_double), ("mlp_scale", C.c_double), ("mlp_taper", C.c_double),
         ("mlp_rmin", C.c_double),
+        ("scheme", C.c_int32),
     ]
 
 
@@ -125,6 +126,7 @@ class Model:
         p.k_bond, p.r0_bond = wl.k_bond, wl.r0_bond
         p.chain_len = max(int(wl.chain_len), 1)
         p.rho_max = wl.rho_max
+        p.scheme = getattr(wl, "scheme", 0)
         self._keep = []
         if table is not None:
             coef, lo, hi = table

@@ -19,7 +19,12 @@
  *   - intramolecular bond terms are not interpolated (Sec. 2.2, last paragraph) and
  *     are integrated everywhere (Sec. 2.3);
  *   - force interpolation obeys Newton's third law and has no conserved energy
- *     (Sec. 2.3, paragraph after Eq. (2)).
+ *     (Sec. 2.3, paragraph after Eq. (2));
+ *   - potential energy interpolation, Eq. (2) (H-AdResS, Sec. 2.3): the Hamiltonian
+ *     sum_alpha [l_a V^AT_a + (1 - l_a) V^CG_a] plus kinetic (and bond) energy; its forces
+ *     carry the drift term -(V^AT_a - V^CG_a) grad l_a and conserve the energy.  Reading:
+ *     V_a is half of each intermolecular pair potential of molecule a (so that the
+ *     molecules' V add up to the total potential), with the CG potential analytic WCA.
  * Potentials (WCA, FENE, harmonic bonds), sizes and time steps are those of the
  * synthetic workloads; the readings taken where the paper is silent are listed
  * at each function.
@@ -38,6 +43,7 @@ enum { ORC_OK = 0, ORC_STRETCH = 1, ORC_FENE = 2, ORC_TABLE_RANGE = 4, ORC_NONFI
 enum { ORC_REGION_AT = 0, ORC_REGION_SLAB = 1, ORC_REGION_SPHERE = 2, ORC_REGION_CG = 3 };
 enum { ORC_CG_WCA = 0, ORC_CG_TABLE = 1, ORC_CG_MLP = 2 };
 enum { ORC_BOND_NONE = 0, ORC_BOND_HARMONIC = 1, ORC_BOND_FENE = 2 };
+enum { ORC_SCHEME_FORCE = 0, ORC_SCHEME_HAMILTONIAN = 1 };
 
 typedef struct {
     int32_t n_mol, spm;
@@ -58,6 +64,9 @@ typedef struct {
     const double *mlp;
     int32_t mlp_hidden;
     double mlp_rc, mlp_scale, mlp_taper, mlp_rmin;
+    /* ORC_SCHEME_FORCE: force interpolation, Eq. (1); ORC_SCHEME_HAMILTONIAN: potential
+     * energy interpolation, Eq. (2) (H-AdResS) */
+    int32_t scheme;
 } orc_params;
 
 /* Minimum image of one coordinate difference (periodic orthorhombic box).
@@ -135,6 +144,25 @@ static double orc_region_distance(const orc_params *P, const double R[3])
     double q[3];
     for (int d = 0; d < 3; ++d) q[d] = orc_mi(R[d] - P->center[d], P->box[d]);
     return sqrt((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]);
+}
+
+/* Gradient of the weight with respect to the centre of mass (Eq. (2)'s drift needs it):
+ * dw/dd = -(pi / (2 d_hy)) sin(pi (d - d_at) / d_hy) inside the hybrid layer, 0 outside;
+ * grad d = sign of the minimum-image x offset along x (slab) or the unit minimum-image
+ * offset (sphere). */
+static void orc_weight_gradient(const orc_params *P, const double R[3], double g[3])
+{
+    g[0] = g[1] = g[2] = 0.0;
+    if (P->region != ORC_REGION_SLAB && P->region != ORC_REGION_SPHERE) return;
+    double d = orc_region_distance(P, R);
+    if (d <= P->d_at || d >= P->d_at + P->d_hy) return;
+    double dw = -(M_PI / (2.0 * P->d_hy)) * sin(M_PI * (d - P->d_at) / P->d_hy);
+    if (P->region == ORC_REGION_SLAB) {
+        double q = orc_mi(R[0] - P->center[0], P->box[0]);
+        g[0] = q > 0.0 ? dw : -dw;
+        return;
+    }
+    for (int k = 0; k < 3; ++k) g[k] = dw * orc_mi(R[k] - P->center[k], P->box[k]) / d;
 }
 
 static double orc_weight(const orc_params *P, const double R[3])
@@ -303,6 +331,8 @@ static double orc_cg_scale(const orc_params *P, double r2, double f_over_r)
 
 /* Forces on the sites of molecule a, summed over every other molecule b (no list):
  *   Eq. (1): ww = w_a w_b;  AT part if ww > 0: ww * sum of atom-atom WCA forces;
+ *   (Eq. (2) instead: ww = (w_a + w_b) / 2 for both parts, energies w_a V^AT_a and
+ *   (1 - w_a) V^CG_a, and the drift force of a hybrid molecule shared by mass fraction);
  *   CG part if ww < 1: (1 - ww) * F^CG(R_a - R_b), shared among a's sites by mass
  *   fraction m_i / M (reading: the paper leaves the distribution to sites open);
  *   plus the non-interpolated bonded terms.
@@ -327,10 +357,17 @@ static int orc_mol_forces(const orc_params *P, const double *x, const double *co
     for (int k = 0; k < spm; ++k) amag[k] = 0.0;
     e[0] = e[1] = e[2] = 0.0;
     double Ra[3] = {com[a], com[n + a], com[2 * n + a]};
+    const int hamiltonian = P->scheme == ORC_SCHEME_HAMILTONIAN;
+    /* Eq. (2): the molecule's single-molecule potentials V^AT_a, V^CG_a (half of each
+     * intermolecular pair potential, so that the sum over molecules is the total) and
+     * their term scales */
+    double vat = 0.0, vcg = 0.0, avat = 0.0, avcg = 0.0;
 
     for (int64_t b = 0; b < n; ++b) {
         if (b == a) continue;
-        double ww = w[a] * w[b];
+        /* weight of the AT part of the pair force: Eq. (1) w_a w_b; Eq. (2) gives
+         * -grad of (w_a V^AT_a + w_b V^AT_b), i.e. (w_a + w_b) / 2 per pair potential */
+        double ww = hamiltonian ? 0.5 * (w[a] + w[b]) : w[a] * w[b];
         if (ww > 0.0) {
             for (int i = 0; i < spm; ++i) {
                 for (int j = 0; j < spm; ++j) {
@@ -344,7 +381,13 @@ static int orc_mol_forces(const orc_params *P, const double *x, const double *co
                         double c[3] = {ww * fr * d[0], ww * fr * d[1], ww * fr * d[2]};
                         for (int q = 0; q < 3; ++q) fa[3 * i + q] += c[q];
                         amag[i] += ww * orc_wca_scale(r2, P->eps_at, P->sig_at) * sqrt(r2);
-                        e[0] += 0.5 * ww * u;
+                        if (hamiltonian) {
+                            double s6 = pow(P->sig_at * P->sig_at / r2, 3);
+                            vat += 0.5 * u;
+                            avat += 0.5 * (4.0 * P->eps_at * s6 * (s6 + 1.0) + P->eps_at);
+                        } else {
+                            e[0] += 0.5 * ww * u;
+                        }
                     }
                 }
             }
@@ -363,7 +406,28 @@ static int orc_mol_forces(const orc_params *P, const double *x, const double *co
                     for (int q = 0; q < 3; ++q) fa[3 * i + q] += c[q];
                     amag[i] += (P->mass[i] / M) * scale;
                 }
-                e[1] += 0.5 * (1.0 - ww) * u;
+                if (hamiltonian) {
+                    double s6 = pow(P->sig_cg * P->sig_cg / r2, 3);
+                    vcg += 0.5 * u;
+                    avcg += 0.5 * (4.0 * P->eps_cg * s6 * (s6 + 1.0) + P->eps_cg);
+                } else {
+                    e[1] += 0.5 * (1.0 - ww) * u;
+                }
+            }
+        }
+    }
+    if (hamiltonian) {
+        e[0] += w[a] * vat;
+        e[1] += (1.0 - w[a]) * vcg;
+        /* drift force: -(V^AT_a - V^CG_a) grad_x w(R_a); grad_{x_i} R_a = (m_i / M) I */
+        double g[3];
+        orc_weight_gradient(P, Ra, g);
+        double gn = orc_norm3(g[0], g[1], g[2]);
+        if (gn > 0.0) {
+            for (int i = 0; i < spm; ++i) {
+                double mf = P->mass[i] / M;
+                for (int q = 0; q < 3; ++q) fa[3 * i + q] += -(vat - vcg) * g[q] * mf;
+                amag[i] += (avat + avcg) * gn * mf;
             }
         }
     }

@@ -41,6 +41,8 @@ CG_TABLE = 1    # cubic-spline table of the CG force
 CG_MLP = 2      # learned MLP, BF16 matrix cores
 CG_MLP_FP8 = 3  # the same network with layer 2 on FP8 E4M3 matrix cores
 
+SCHEME_FORCE = 0        # force interpolation, Eq. (1)
+SCHEME_HAMILTONIAN = 1  # potential energy interpolation, Eq. (2) (H-AdResS)
 BOND_NONE = 0
 BOND_HARMONIC = 1   # harmonic bonds between every pair of sites of a molecule
 BOND_FENE = 2       # FENE bonds between consecutive beads of a chain
@@ -79,6 +81,7 @@ class Workload:
     gamma: float = 0.0
     kT: float = 1.0
     seed: int = 1000
+    scheme: int = SCHEME_FORCE
 
     def as_dict(self):
         return asdict(self)

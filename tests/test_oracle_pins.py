@@ -424,3 +424,55 @@ def test_golden_tetra_rho():
     verts = np.array([[a, a, a], [a, -a, -a], [-a, a, -a], [-a, -a, a]]) + 5.0
     _, _, rh, st = oracle.Model(wl).weights(np.ascontiguousarray(verts.T))
     assert st == 0 and abs(rh[0] - rho) <= 1e-15
+
+
+# ---------------------------------------------------------------- Eq. (2): H-AdResS
+class TestHamiltonianScheme:
+    """Potential energy interpolation (Eq. (2)): the forces are minus the gradient of the
+    interpolated potential, drift term included, so central differences of the oracle's
+    own energy pin them in the hybrid case; in the w == 1 and w == 0 limits the scheme is
+    force interpolation; and velocity Verlet conserves its energy to O(dt^2) even with a
+    hybrid layer, which force interpolation cannot (Sec. 2.3)."""
+
+    @pytest.mark.parametrize("name", ["tiny_slab", "small_sphere"])
+    def test_forces_are_minus_gradient(self, name):
+        wl = inputs.workload(name).with_(scheme=inputs.SCHEME_HAMILTONIAN)
+        if name == "small_sphere":
+            wl = wl.with_(n_mol=216, box=((216 / 0.1) ** (1 / 3),) * 3, d_at=2.0, d_hy=3.0,
+                          center=(((216 / 0.1) ** (1 / 3)) / 2,) * 3)
+        x, _ = inputs.make_state(wl, seed=11)
+        _, w, _, _ = oracle.Model(wl).weights(x)
+        assert ((w > 0) & (w < 1)).any()
+        _energy_grad_check(wl, x, n_check=16)
+
+    @pytest.mark.parametrize("region", [inputs.REGION_ALL_AT, inputs.REGION_ALL_CG])
+    def test_limits_equal_force_interpolation(self, region):
+        wl = inputs.workload("tiny_slab").with_(region=region)
+        x, _ = inputs.make_state(wl, seed=4)
+        f1, a1, e1, _ = oracle.Model(wl).forces(x)
+        f2, a2, e2, _ = oracle.Model(wl.with_(scheme=inputs.SCHEME_HAMILTONIAN)).forces(x)
+        np.testing.assert_array_equal(f1, f2)
+        np.testing.assert_allclose(e1, e2, rtol=1e-14)
+
+    def test_drift_breaks_newton3_only_in_hybrid_layer(self):
+        wl = inputs.workload("tiny_slab").with_(scheme=inputs.SCHEME_HAMILTONIAN)
+        x, _ = inputs.make_state(wl)
+        m = oracle.Model(wl)
+        f, amag, _, _ = m.forces(x)
+        _, w, _, _ = m.weights(x)
+        hy = (w > 0) & (w < 1)
+        assert hy.any()
+        net = np.abs(f.sum(axis=1)).max()
+        assert net > 1e3 * EPS * amag.sum()
+
+    def test_nve_conserves_energy_with_hybrid_layer(self):
+        wl = inputs.workload("tiny_slab").with_(scheme=inputs.SCHEME_HAMILTONIAN)
+        x, v = inputs.make_state(wl)
+        m = oracle.Model(wl)
+        _, _, _, e1, st = m.vv(x, v, 0.002, 100)
+        _, _, _, e2, _ = m.vv(x, v, 0.001, 200)
+        assert st == 0
+        t1, t2 = e1.sum(axis=1), e2.sum(axis=1)
+        f1, f2 = np.max(np.abs(t1 - t1[0])), np.max(np.abs(t2 - t2[0]))
+        assert f1 < 5e-3 * abs(t1[0]) + 1e-2
+        assert 2.5 < f1 / f2 < 6.0, (f1, f2)
