@@ -49,6 +49,8 @@ def main():
     ap.add_argument("--cg-steps", type=int, default=500)
     ap.add_argument("--cg-only", action="store_true",
                     help="run only the learned-vs-tabulated CG force leg and print its record")
+    ap.add_argument("--no-hamiltonian", action="store_true",
+                    help="skip the potential-energy-interpolation (Eq. (2)) leg")
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes 10 times "
@@ -164,6 +166,8 @@ def main():
     }
 
     ctx.close()
+    if not args.no_hamiltonian:
+        out["hamiltonian_scheme"] = hamiltonian_leg(wl, x, v, args.steps, args.warmup)
     if not args.no_cg_compare:
         out["learned_vs_tabulated"] = learned_vs_tabulated(args.cg_steps)
 
@@ -184,6 +188,48 @@ def main():
                       f"steps/s = {n_cpu} / elapsed",
         }
     print(json.dumps(out))
+
+
+def hamiltonian_leg(wl, x, v, steps, warmup):
+    """The same workload and step with potential energy interpolation (Eq. (2)): pair
+    weights (w_a + w_b) / 2 and the drift force on hybrid molecules.  Reports MD steps/s,
+    the fused step kernel's average duration and the total energy (kinetic + potential)
+    before and after the timed steps (NVE: the scheme conserves it)."""
+    import torch
+    from paper_1806_10841_amd import binding, inputs
+    wh = wl.with_(scheme=inputs.SCHEME_HAMILTONIAN)
+    masses = np.tile(np.asarray(wh.site_mass, dtype=np.float64), wh.n_mol)
+    ctx = binding.Context(wh)
+    xt = torch.tensor(x, device="cuda")
+    vt = torch.tensor(v, device="cuda")
+    ft = torch.empty_like(xt)
+
+    def total_energy():
+        _, e = ctx.forces(xt, energy=True)
+        vv = vt.cpu().numpy()
+        return float(e[:3].sum().item() + 0.5 * np.sum(masses * (vv * vv).sum(axis=0)))
+
+    ctx.integrate(xt, vt, ft, wh.dt, warmup)
+    e0 = total_energy()
+    torch.cuda.synchronize()
+    ctx.kernel_timing(True, every=TIMING_EVERY)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nreb = ctx.integrate(xt, vt, ft, wh.dt, steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    force_ms, launches = ctx.kernel_timing(False)
+    e1 = total_energy()
+    ctx.close()
+    return {
+        "steps_per_s": steps / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "force_kernel_us": force_ms / max(launches, 1) * 1e3,
+        "list_rebuilds": nreb,
+        "total_energy_start": e0,
+        "total_energy_end": e1,
+        "energy_drift_per_molecule": (e1 - e0) / wh.n_mol,
+    }
 
 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_forces_step_c2_pmc.md")

@@ -64,6 +64,9 @@ enum { ADRES_REGION_ALL_AT = 0, ADRES_REGION_SLAB_X = 1, ADRES_REGION_SPHERE = 2
  * on BF16 matrix cores, or its FP8 variant (inference only; see adres_mlp_set). */
 enum { ADRES_CG_WCA = 0, ADRES_CG_TABLE = 1, ADRES_CG_MLP = 2, ADRES_CG_MLP_FP8 = 3 };
 enum { ADRES_BOND_NONE = 0, ADRES_BOND_HARMONIC = 1, ADRES_BOND_FENE = 2 };
+/* Coupling scheme: force interpolation, Eq. (1) (Sec. 2.2), or potential energy
+ * interpolation, Eq. (2) (H-AdResS, Sec. 2.3). */
+enum { ADRES_SCHEME_FORCE = 0, ADRES_SCHEME_HAMILTONIAN = 1 };
 
 #define ADRES_MAX_SITES 4
 
@@ -86,6 +89,15 @@ typedef struct {
     double  rho_max;            /* bound on a site's distance from its centre of mass */
     int32_t pair_precision;     /* 64: FP64 pair arithmetic; 32: FP32 pair arithmetic on
                                    FP64-formed displacements, FP64 sums */
+    int32_t scheme;             /* ADRES_SCHEME_FORCE: pair forces w_a w_b F^AT +
+                                   (1 - w_a w_b) F^CG (Eq. (1)).  ADRES_SCHEME_HAMILTONIAN:
+                                   forces of H = K + sum_a [w_a V^AT_a + (1 - w_a) V^CG_a]
+                                   (Eq. (2)), V_a half of molecule a's intermolecular pair
+                                   potentials: pair weights (w_a + w_b) / 2 and, on hybrid
+                                   molecules, the drift force -(V^AT_a - V^CG_a) grad w_a
+                                   shared by mass fraction; needs cg_kind ADRES_CG_WCA (the
+                                   CG potential).  Energies (adres_forces) are then
+                                   sum_a w_a V^AT_a and sum_a (1 - w_a) V^CG_a. */
 } adres_params;
 
 /* Create a context for one system on the current HIP device.  hip_stream is a

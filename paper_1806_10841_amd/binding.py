@@ -43,6 +43,7 @@ class Params(C.Structure):
         ("chain_len", C.c_int32),
         ("r_skin", C.c_double), ("rho_max", C.c_double),
         ("pair_precision", C.c_int32),
+        ("scheme", C.c_int32),
     ]
 
 
@@ -104,6 +105,7 @@ def params_from(wl) -> Params:
     p.chain_len = wl.chain_len
     p.r_skin, p.rho_max = wl.r_skin, wl.rho_max
     p.pair_precision = wl.pair_precision
+    p.scheme = getattr(wl, "scheme", 0)
     return p
 
 

@@ -365,6 +365,8 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     if (q.r_skin < 0.0 || q.rho_max < 0.0) return ADRES_E_ARG;
     if (q.sites_per_mol > 1 && !(q.rho_max > 0.0)) return ADRES_E_ARG;
     if (q.pair_precision != 32 && q.pair_precision != 64) return ADRES_E_ARG;
+    if (q.scheme != ADRES_SCHEME_FORCE && q.scheme != ADRES_SCHEME_HAMILTONIAN) return ADRES_E_ARG;
+    if (q.scheme == ADRES_SCHEME_HAMILTONIAN && q.cg_kind != ADRES_CG_WCA) return ADRES_E_ARG;
     if (q.n_mol > scan_max_elements()) return ADRES_E_ARG;
 
     adres_ctx *c = new adres_ctx();
@@ -427,6 +429,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     P.sig2_cg = q.sig_cg * q.sig_cg;
     P.rcC2 = q.rc_cg * q.rc_cg;
     P.cg_kind = q.cg_kind;
+    P.scheme = q.scheme;
     P.bond_kind = q.bond_kind;
     P.k_bond = q.k_bond;
     P.r0_bond = q.r0_bond;

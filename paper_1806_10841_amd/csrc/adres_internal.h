@@ -48,6 +48,7 @@ struct DevParams {
     double eps_at, sig2_at, rcA2, rc_at;
     double eps_cg, sig2_cg, rcC2;
     int cg_kind, bond_kind;
+    int scheme;      // ADRES_SCHEME_*
     double k_bond, r0_bond, R02;
     int chain_len;
     double rho_max;
@@ -128,6 +129,35 @@ __device__ __forceinline__ void mol_com(const DevParams &P, const double (&p)[SP
         rmax2 = r2 > rmax2 ? r2 : rmax2;
     }
     rho = sqrt(rmax2);
+}
+
+// Gradient of the resolution weight with respect to the centre of mass (the drift force of
+// Eq. (2)): dw/dd = -(pi / (2 d_hy)) sin(pi (d - d_at) / d_hy) inside the hybrid layer,
+// times the gradient of the distance (sign of the x offset for a slab, the unit offset for
+// a sphere); 0 outside the layer.
+__device__ __forceinline__ void weight_gradient(const DevParams &P, const double4 &R, double g[3])
+{
+    g[0] = g[1] = g[2] = 0.0;
+    if (P.region != ADRES_REGION_SLAB_X && P.region != ADRES_REGION_SPHERE) return;
+    double q0 = mi(R.x - P.center[0], P.box[0], P.half[0]);
+    double d;
+    double q1 = 0.0, q2 = 0.0;
+    if (P.region == ADRES_REGION_SLAB_X) {
+        d = fabs(q0);
+    } else {
+        q1 = mi(R.y - P.center[1], P.box[1], P.half[1]);
+        q2 = mi(R.z - P.center[2], P.box[2], P.half[2]);
+        d = sqrt(dist2_exact(q0, q1, q2));
+    }
+    if (d <= P.d_at || d >= P.d_end) return;
+    const double dw = -(M_PI / (2.0 * P.d_hy)) * sin(M_PI * (d - P.d_at) / P.d_hy);
+    if (P.region == ADRES_REGION_SLAB_X) {
+        g[0] = q0 > 0.0 ? dw : -dw;
+    } else {
+        g[0] = dw * q0 / d;
+        g[1] = dw * q1 / d;
+        g[2] = dw * q2 / d;
+    }
 }
 
 // Resolution weight of a centre of mass (1 in AT, cos^2 ramp in HY, 0 in CG).

@@ -82,7 +82,11 @@ __device__ __forceinline__ PT table_f(const DevParams &P, double r, Ctrl *ctrl)
 
 // At most 128 VGPRs (4 waves per SIMD): 4 lanes x 64k molecules is ~4000 wavefronts,
 // which then fit the 1024 SIMDs in a single round.
-template <int SPM, typename PT, int MODE, bool ENERGY>
+// HAM: potential energy interpolation, Eq. (2): pair weights (w_a + w_b) / 2, the
+// molecule's single-molecule potentials V^AT, V^CG (half of each of its pair potentials)
+// accumulated on hybrid molecules, and their drift force -(V^AT - V^CG) grad w shared by
+// mass fraction.  Otherwise force interpolation, Eq. (1).
+template <int SPM, typename PT, int MODE, bool ENERGY, bool HAM>
 __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
 {
     const DevParams &P = a.P;
@@ -130,6 +134,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     for (int i = 0; i < SPM; ++i) acc[i][0] = acc[i][1] = acc[i][2] = 0.0;
     double cg0 = 0.0, cg1 = 0.0, cg2 = 0.0;
     double uat = 0.0, ucg = 0.0, ubond = 0.0;
+    // Eq. (2): a molecule on which the weight gradient is non-zero needs V^AT and V^CG
+    double gw[3] = {0.0, 0.0, 0.0};
+    if (HAM) weight_gradient(P, me, gw);
+    const bool hy_home = HAM && (gw[0] != 0.0 || gw[1] != 0.0 || gw[2] != 0.0);
+    double vat = 0.0, vcg = 0.0;
 
     const PT sig2A = (PT)P.sig2_at, epsA = (PT)P.eps_at, rcA2 = (PT)P.rcA2;
     const PT sig2C = (PT)P.sig2_cg, epsC = (PT)P.eps_cg;
@@ -161,7 +170,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
             if (k0 + j >= cnt) break;
             const int u = us[j];
             const double4 o = nb[j];
-            const double ww = me.w * o.w;
+            const double ww = HAM ? 0.5 * (me.w + o.w) : me.w * o.w;   // weight of the AT part
             const double D0 = mi(me.x - o.x, P.box[0], P.half[0]);
             const double D1 = mi(me.y - o.y, P.box[1], P.half[1]);
             const double D2 = mi(me.z - o.z, P.box[2], P.half[2]);
@@ -199,11 +208,12 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                                 const float r2 = (dx * dx + dy * dy) + dz * dz;
                                 if (r2 < (float)rcA2) {
                                     PT uu = PT(0);
-                                    const PT c = pww * wca_f_over_r<PT>((PT)r2, sig2A, epsA, uu, ENERGY);
+                                    const PT c = pww * wca_f_over_r<PT>((PT)r2, sig2A, epsA, uu, ENERGY || hy_home);
                                     s0 += (double)(c * dx);
                                     s1 += (double)(c * dy);
                                     s2 += (double)(c * dz);
-                                    if (ENERGY) uat += 0.5 * ww * (double)uu;
+                                    if (ENERGY) uat += 0.5 * (HAM ? me.w : ww) * (double)uu;
+                                    if (HAM) vat += 0.5 * (double)uu;
                                 }
                             }
                             acc[i][0] += s0; acc[i][1] += s1; acc[i][2] += s2;
@@ -222,11 +232,12 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                             const PT r2 = (dx * dx + dy * dy) + dz * dz;
                             if (r2 < rcA2) {
                                 PT uu = PT(0);
-                                const PT c = pww * wca_f_over_r<PT>(r2, sig2A, epsA, uu, ENERGY);
+                                const PT c = pww * wca_f_over_r<PT>(r2, sig2A, epsA, uu, ENERGY || hy_home);
                                 acc[i][0] += (double)(c * dx);
                                 acc[i][1] += (double)(c * dy);
                                 acc[i][2] += (double)(c * dz);
-                                if (ENERGY) uat += 0.5 * ww * (double)uu;
+                                if (ENERGY) uat += 0.5 * (HAM ? me.w : ww) * (double)uu;
+                                if (HAM) vat += 0.5 * (double)uu;
                             }
                         }
                     }
@@ -237,7 +248,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                 PT uu = PT(0);
                 PT fr;
                 if (P.cg_kind == ADRES_CG_WCA) {
-                    fr = wca_f_over_r<PT>((PT)r2c, sig2C, epsC, uu, ENERGY);
+                    fr = wca_f_over_r<PT>((PT)r2c, sig2C, epsC, uu, ENERGY || hy_home);
                 } else if (P.cg_kind >= ADRES_CG_MLP) {
                     // the same bits from both sides of the pair (same r2c, same network value)
                     const float fv = SPM == 1 ? fp[j] : a.f_pair[a.pid[(int64_t)tt * a.cap + k0 + j]];
@@ -250,7 +261,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                 cg0 += (double)(sc * (PT)D0);
                 cg1 += (double)(sc * (PT)D1);
                 cg2 += (double)(sc * (PT)D2);
-                if (ENERGY) ucg += 0.5 * (1.0 - ww) * (double)uu;
+                if (ENERGY) ucg += 0.5 * (HAM ? 1.0 - me.w : 1.0 - ww) * (double)uu;
+                if (HAM) vcg += 0.5 * (double)uu;
             }
         }
     }
@@ -261,6 +273,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     for (int i = 0; i < SPM; ++i)
 #pragma unroll
         for (int d = 0; d < 3; ++d) acc[i][d] = quad_sum(acc[i][d]);
+    if (HAM) {
+        vat = quad_sum(vat);
+        vcg = quad_sum(vcg);
+    }
     cg0 = quad_sum(cg0);
     cg1 = quad_sum(cg1);
     cg2 = quad_sum(cg2);
@@ -275,6 +291,13 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
             F[0] = acc[i][0] + mf * cg0;
             F[1] = acc[i][1] + mf * cg1;
             F[2] = acc[i][2] + mf * cg2;
+            if (hy_home) {
+                // drift force of Eq. (2): -(V^AT - V^CG) grad w(R), grad_x R = m_i / M
+                const double dv = -(vat - vcg) * mf;
+                F[0] += dv * gw[0];
+                F[1] += dv * gw[1];
+                F[2] += dv * gw[2];
+            }
             xq[0] = XI(i, 0); xq[1] = XI(i, 1); xq[2] = XI(i, 2);
             mq = P.mass[i];
             iq = P.inv_2m[i];
@@ -447,28 +470,37 @@ void launch_k(K kernel, hipStream_t s, const ForceArgs &a, int blocks, hipEvent_
         kernel<<<blocks, kBlock, 0, s>>>(a);
 }
 
-template <int SPM, typename PT>
+template <int SPM, typename PT, bool HAM>
 void dispatch_mode(hipStream_t s, const ForceArgs &a, int blocks, hipEvent_t e0, hipEvent_t e1)
 {
     switch (a.mode) {
-    case kModeStep: launch_k(k_forces<SPM, PT, kModeStep, false>, s, a, blocks, e0, e1); break;
-    case kModeClose: launch_k(k_forces<SPM, PT, kModeClose, false>, s, a, blocks, e0, e1); break;
+    case kModeStep: launch_k(k_forces<SPM, PT, kModeStep, false, HAM>, s, a, blocks, e0, e1); break;
+    case kModeClose: launch_k(k_forces<SPM, PT, kModeClose, false, HAM>, s, a, blocks, e0, e1); break;
     default:
         if (a.epart)
-            launch_k(k_forces<SPM, PT, kModeForce, true>, s, a, blocks, e0, e1);
+            launch_k(k_forces<SPM, PT, kModeForce, true, HAM>, s, a, blocks, e0, e1);
         else
-            launch_k(k_forces<SPM, PT, kModeForce, false>, s, a, blocks, e0, e1);
+            launch_k(k_forces<SPM, PT, kModeForce, false, HAM>, s, a, blocks, e0, e1);
     }
+}
+
+template <int SPM, typename PT>
+void dispatch_scheme(hipStream_t s, const ForceArgs &a, int blocks, hipEvent_t e0, hipEvent_t e1)
+{
+    if (a.P.scheme == ADRES_SCHEME_HAMILTONIAN)
+        dispatch_mode<SPM, PT, true>(s, a, blocks, e0, e1);
+    else
+        dispatch_mode<SPM, PT, false>(s, a, blocks, e0, e1);
 }
 
 template <typename PT>
 void dispatch_spm(hipStream_t s, const ForceArgs &a, int blocks, hipEvent_t e0, hipEvent_t e1)
 {
     switch (a.P.spm) {
-    case 1: dispatch_mode<1, PT>(s, a, blocks, e0, e1); break;
-    case 2: dispatch_mode<2, PT>(s, a, blocks, e0, e1); break;
-    case 3: dispatch_mode<3, PT>(s, a, blocks, e0, e1); break;
-    default: dispatch_mode<4, PT>(s, a, blocks, e0, e1); break;
+    case 1: dispatch_scheme<1, PT>(s, a, blocks, e0, e1); break;
+    case 2: dispatch_scheme<2, PT>(s, a, blocks, e0, e1); break;
+    case 3: dispatch_scheme<3, PT>(s, a, blocks, e0, e1); break;
+    default: dispatch_scheme<4, PT>(s, a, blocks, e0, e1); break;
     }
 }
 

@@ -1,0 +1,168 @@
+"""GPU parity of potential energy interpolation (Eq. (2), the Hamiltonian scheme) against
+the FP64 oracle, through the C ABI.
+
+Same bars as force interpolation: FP64 pair forces to 1e-12 and FP32 pair forces to
+1e-5 per site of the oracle's term-scale A_i (which includes the drift force's terms,
+|V^AT| + |V^CG| times |grad w| m_i / M) and normwise; energies to the same relative bar.
+The drift force breaks Newton's third law in the hybrid layer, so no momentum check here;
+what the scheme buys instead is a conserved energy, checked on the GPU's own trajectory.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1806_10841_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+HAM = inputs.SCHEME_HAMILTONIAN
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    return torch.device("cuda:0")
+
+
+def _ctx(wl):
+    from paper_1806_10841_amd import binding
+    return binding.Context(wl)
+
+
+def _t(a, dev):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+def _assert_close(fg, fo, amag, tol, where):
+    err = np.abs(fg - fo).max(axis=0)
+    ratio = (err / np.maximum(amag, 1e-300)).max()
+    assert ratio <= tol, f"{where}: worst ratio {ratio:.3e}"
+    assert np.linalg.norm(fg - fo) <= tol * np.linalg.norm(fo), where
+
+
+def _hybrid_count(wl, x):
+    _, w, _, _ = oracle.Model(wl).weights(x)
+    return int(((w > 0) & (w < 1)).sum())
+
+
+@pytest.mark.parametrize("name", ["tiny_slab", "c1", "small_slab", "small_sphere"])
+def test_forces_fp64(dev, name):
+    wl = inputs.workload(name).with_(pair_precision=64, scheme=HAM)
+    x, _ = inputs.make_state(wl)
+    assert _hybrid_count(wl, x) > 0
+    fo, amag, eo, st = oracle.Model(wl).forces(x)
+    assert st == 0
+    f, e = _ctx(wl).forces(_t(x, dev), energy=True)
+    torch.cuda.synchronize()
+    _assert_close(f.cpu().numpy(), fo, amag, 1e-12, name)
+    np.testing.assert_allclose(e.cpu().numpy()[:3], eo, rtol=1e-12, atol=1e-12 * np.abs(eo).max())
+
+
+@pytest.mark.parametrize("name", ["small_slab", "small_sphere", "c1"])
+def test_forces_fp32_pairs(dev, name):
+    wl = inputs.workload(name).with_(pair_precision=32, scheme=HAM)
+    x, _ = inputs.make_state(wl)
+    fo, amag, eo, st = oracle.Model(wl).forces(x)
+    assert st == 0
+    f, e = _ctx(wl).forces(_t(x, dev), energy=True)
+    torch.cuda.synchronize()
+    _assert_close(f.cpu().numpy(), fo, amag, 1e-5, name)
+    np.testing.assert_allclose(e.cpu().numpy()[:3], eo, rtol=1e-5, atol=1e-5 * np.abs(eo).max())
+
+
+def test_schemes_differ_only_through_the_hybrid_layer(dev):
+    """Both schemes on the same all-AT and all-CG systems give the same forces (the
+    weights are then all 1 or all 0 and Eq. (1) and Eq. (2) coincide); with a hybrid
+    layer they differ."""
+    for region in (inputs.REGION_ALL_AT, inputs.REGION_ALL_CG):
+        wl = inputs.workload("tiny_slab").with_(region=region)
+        x, _ = inputs.make_state(wl, seed=4)
+        f1 = _ctx(wl).forces(_t(x, dev))
+        f2 = _ctx(wl.with_(scheme=HAM)).forces(_t(x, dev))
+        assert torch.equal(f1, f2), region
+    wl = inputs.workload("tiny_slab")
+    x, _ = inputs.make_state(wl)
+    f1 = _ctx(wl).forces(_t(x, dev))
+    f2 = _ctx(wl.with_(scheme=HAM)).forces(_t(x, dev))
+    assert not torch.equal(f1, f2)
+
+
+def test_forces_c2_full_size_sampled(dev):
+    """64,000 tetrahedra with the Hamiltonian scheme, FP32 pairs, in the benchmark's
+    launch configuration: sampled AT, HY and CG molecules against the oracle."""
+    wl = inputs.workload("c2").with_(scheme=HAM)
+    x, _ = inputs.make_state(wl)
+    m = oracle.Model(wl)
+    _, w, _, _ = m.weights(x)
+    rng = np.random.default_rng(3)
+    sel = []
+    for mask in (w == 1.0, (w > 0) & (w < 1), w == 0.0):
+        idx = np.flatnonzero(mask)
+        sel.append(rng.choice(idx, size=min(60, len(idx)), replace=False))
+    sel = np.sort(np.concatenate(sel))
+    fo, amag, st = m.forces_sampled(x, sel)
+    assert st == 0
+    f = _ctx(wl).forces(_t(x, dev)).cpu().numpy()
+    fg = np.stack([f[:, 4 * a:4 * a + 4] for a in sel])
+    err = np.abs(fg - fo).max(axis=1)
+    assert np.all(err <= 1e-5 * amag), (err / amag).max()
+    assert np.linalg.norm(fg - fo) <= 1e-5 * np.linalg.norm(fo)
+
+
+def _min_image(d, L):
+    return d - L * np.round(d / L)
+
+
+@pytest.mark.parametrize("name,steps", [("tiny_slab", 100), ("small_sphere", 40)])
+def test_integrate_fp64_matches_oracle_vv(dev, name, steps):
+    wl = inputs.workload(name).with_(pair_precision=64, scheme=HAM)
+    x, v = inputs.make_state(wl)
+    xo, vo, fo, _, st = oracle.Model(wl).vv(x, v, wl.dt, steps)
+    assert st == 0
+    ctx = _ctx(wl)
+    xt, vt = _t(x, dev), _t(v, dev)
+    ft = torch.empty_like(xt)
+    ctx.integrate(xt, vt, ft, wl.dt, steps)
+    torch.cuda.synchronize()
+    tol = 1e-9
+    assert np.abs(_min_image(xt.cpu().numpy() - xo, wl.box[0])).max() < tol
+    assert np.abs(vt.cpu().numpy() - vo).max() < 100 * tol
+    assert np.abs(ft.cpu().numpy() - fo).max() < 1e4 * tol * max(1.0, np.abs(fo).max())
+
+
+def _gpu_energy_trace(dev, wl, x, v, dt, n_chunks, chunk):
+    """Total energy (kinetic + potential) every ``chunk`` steps of the GPU's own trajectory."""
+    m = oracle.Model(wl)
+    ctx = _ctx(wl)
+    xt, vt = _t(x, dev), _t(v, dev)
+    ft = torch.empty_like(xt)
+    out = []
+    for c in range(n_chunks + 1):
+        if c:
+            ctx.integrate(xt, vt, ft, dt, chunk)
+        _, e = ctx.forces(xt, energy=True)
+        out.append(e[:3].sum().item() + m.kinetic(vt.cpu().numpy()))
+    return np.array(out)
+
+
+def test_nve_energy_conserved_to_dt2_with_hybrid_layer(dev):
+    """Velocity Verlet on the Hamiltonian scheme conserves its energy with an error that
+    falls as dt^2 (halving dt cuts the excursion about four times), hybrid layer included."""
+    wl = inputs.workload("tiny_slab").with_(pair_precision=64, scheme=HAM)
+    x, v = inputs.make_state(wl)
+    t1 = _gpu_energy_trace(dev, wl, x, v, 0.002, 10, 10)
+    t2 = _gpu_energy_trace(dev, wl, x, v, 0.001, 10, 20)
+    f1, f2 = np.abs(t1 - t1[0]).max(), np.abs(t2 - t2[0]).max()
+    assert f1 < 5e-3 * abs(t1[0]) + 1e-2, (f1, t1[0])
+    assert 2.5 < f1 / f2 < 6.0, (f1, f2)
+
+
+def test_scheme_argument_errors(dev):
+    from paper_1806_10841_amd import binding
+    wl = inputs.workload("small_slab").with_(scheme=HAM, cg_kind=inputs.CG_TABLE)
+    with pytest.raises(binding.AdresError):
+        _ctx(wl)
+    with pytest.raises(binding.AdresError):
+        _ctx(inputs.workload("tiny_slab").with_(scheme=2))
