@@ -62,6 +62,8 @@ class Params(C.Structure):
         ("mlp_rc", C.c_double), ("mlp_scale", C.c_double), ("mlp_taper", C.c_double),
         ("mlp_rmin", C.c_double),
         ("scheme", C.c_int32),
+        ("td", C.POINTER(C.c_double)), ("td_n", C.c_int32),
+        ("td_lo", C.c_double), ("td_hi", C.c_double),
     ]
 
 
@@ -93,6 +95,12 @@ def lib():
             L.orc_table_eval.restype = C.c_double
             L.orc_mlp_eval.argtypes = [P, C.c_double, C.POINTER(C.c_int)]
             L.orc_mlp_eval.restype = C.c_double
+            L.orc_density_profile.argtypes = [P, dp, C.c_int32, C.c_double, C.c_double,
+                                              C.POINTER(C.c_int64)]
+            L.orc_density_profile.restype = C.c_int
+            L.orc_tdforce_update.argtypes = [P, dp, C.c_int32, C.c_double, C.c_double,
+                                             C.POINTER(C.c_int64), C.c_int64, C.c_double]
+            L.orc_tdforce_update.restype = None
             L.orc_num_threads.restype = C.c_int
             _lib = L
     return _lib
@@ -107,9 +115,10 @@ class Model:
 
     ``wl`` is any object with the attributes of ``inputs.Workload``.  ``table`` is
     (coef float32 [(n-1), 4], r_lo, r_hi); ``mlp`` is (params float64, rc, scale,
-    taper_width, r_min)."""
+    taper_width, r_min); ``td`` is the correction force (values float64 [n] at the bin
+    centres, lo, hi)."""
 
-    def __init__(self, wl, table=None, mlp=None, hidden=64):
+    def __init__(self, wl, table=None, mlp=None, hidden=64, td=None):
         self.wl = wl
         p = Params()
         p.n_mol, p.spm = wl.n_mol, wl.sites_per_mol
@@ -142,6 +151,13 @@ class Model:
             p.mlp = _dp(prm)
             p.mlp_hidden = hidden
             p.mlp_rc, p.mlp_scale, p.mlp_taper, p.mlp_rmin = rc, scale, taper, rmin
+        if td is not None:
+            F, lo, hi = td
+            F = np.ascontiguousarray(F, dtype=np.float64)
+            self._keep.append(F)
+            p.td = _dp(F)
+            p.td_n = len(F)
+            p.td_lo, p.td_hi = lo, hi
         self.p = p
         self.n_sites = wl.n_mol * wl.sites_per_mol
 
@@ -198,7 +214,7 @@ class Model:
 
     def forces(self, x):
         x = np.ascontiguousarray(x, dtype=np.float64)
-        f = np.empty_like(x); amag = np.empty(self.n_sites); e = np.zeros(3)
+        f = np.empty_like(x); amag = np.empty(self.n_sites); e = np.zeros(4)
         st = lib().orc_forces(C.byref(self.p), _dp(x), _dp(f), _dp(amag), _dp(e))
         return f, amag, e, st
 
@@ -213,13 +229,33 @@ class Model:
         return f, amag, st
 
     def vv(self, x, v, dt, n_steps):
-        """Velocity Verlet; returns (x, v, f, energies[(n_steps+1), 4], status)."""
+        """Velocity Verlet; returns (x, v, f, energies[(n_steps+1), 5], status), the energy
+        columns U_AT, U_CG, U_bond, U_corr, kinetic."""
         x = np.array(x, dtype=np.float64, copy=True)
         v = np.array(v, dtype=np.float64, copy=True)
         f = np.empty_like(x)
-        e = np.zeros((n_steps + 1, 4))
+        e = np.zeros((n_steps + 1, 5))
         st = lib().orc_vv(C.byref(self.p), _dp(x), _dp(v), _dp(f), dt, n_steps, _dp(e))
         return x, v, f, e, st
+
+    def density_profile(self, x, n_bins, lo, hi, counts=None):
+        """Adds the molecules' centre-of-mass distance histogram over [lo, hi) (n_bins equal
+        bins) to ``counts`` (int64, a new zero array if None) and returns it."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        if counts is None:
+            counts = np.zeros(n_bins, dtype=np.int64)
+        st = lib().orc_density_profile(C.byref(self.p), _dp(x), n_bins, lo, hi,
+                                       counts.ctypes.data_as(C.POINTER(C.c_int64)))
+        assert st == 0, st
+        return counts
+
+    def tdforce_update(self, F, lo, hi, counts, n_frames, prefactor):
+        """One refinement step of the correction force values F (returns a new array)."""
+        F = np.array(F, dtype=np.float64, copy=True)
+        counts = np.ascontiguousarray(counts, dtype=np.int64)
+        lib().orc_tdforce_update(C.byref(self.p), _dp(F), len(F), lo, hi,
+                                 counts.ctypes.data_as(C.POINTER(C.c_int64)), n_frames, prefactor)
+        return F
 
     def kinetic(self, v):
         v = np.ascontiguousarray(v, dtype=np.float64)

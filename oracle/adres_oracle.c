@@ -24,7 +24,11 @@
  *     sum_alpha [l_a V^AT_a + (1 - l_a) V^CG_a] plus kinetic (and bond) energy; its forces
  *     carry the drift term -(V^AT_a - V^CG_a) grad l_a and conserve the energy.  Reading:
  *     V_a is half of each intermolecular pair potential of molecule a (so that the
- *     molecules' V add up to the total potential), with the CG potential analytic WCA.
+ *     molecules' V add up to the total potential), with the CG potential analytic WCA;
+ *   - a correction force on the centres of mass along the direction of resolution
+ *     change, to flatten the density profile across the hybrid region: the
+ *     thermodynamic force, built from the density profile and refined iteratively
+ *     (Sec. 2.4).  Readings at orc_td_force and orc_tdforce_update.
  * Potentials (WCA, FENE, harmonic bonds), sizes and time steps are those of the
  * synthetic workloads; the readings taken where the paper is silent are listed
  * at each function.
@@ -67,6 +71,11 @@ typedef struct {
     /* ORC_SCHEME_FORCE: force interpolation, Eq. (1); ORC_SCHEME_HAMILTONIAN: potential
      * energy interpolation, Eq. (2) (H-AdResS) */
     int32_t scheme;
+    /* correction force along the resolution coordinate (Sec. 2.4): td_n values at the
+     * bin centres of [td_lo, td_hi); td_n = 0 means none */
+    const double *td;
+    int32_t td_n;
+    double td_lo, td_hi;
 } orc_params;
 
 /* Minimum image of one coordinate difference (periodic orthorhombic box).
@@ -163,6 +172,61 @@ static void orc_weight_gradient(const orc_params *P, const double R[3], double g
         return;
     }
     for (int k = 0; k < 3; ++k) g[k] = dw * orc_mi(R[k] - P->center[k], P->box[k]) / d;
+}
+
+/* Correction force on a centre of mass (Sec. 2.4) and its potential.  Readings: the
+ * force acts along the gradient of the resolution distance d (slab: the sign of the
+ * minimum-image x offset; sphere: the unit offset from the centre; none at d = 0) with
+ * magnitude F(d) taken from td_n values F_k given at the bin centres
+ * d_k = lo + (k + 1/2) h, h = (hi - lo) / td_n: linear between neighbouring centres, the
+ * end value held from lo to d_0 and from d_{n-1} to hi, zero outside [lo, hi).  Its
+ * potential is U(d) = -integral of F from lo to min(d, hi) (0 below lo), integrated here
+ * piece by piece.  dir receives the unit direction, *u the potential, *scale the sum of
+ * the magnitudes of the table values F depends on (the term scale of the force). */
+static double orc_td_force(const orc_params *P, const double R[3], double dir[3], double *u,
+                           double *scale)
+{
+    dir[0] = dir[1] = dir[2] = 0.0;
+    *u = 0.0;
+    *scale = 0.0;
+    if (P->td_n <= 0 || (P->region != ORC_REGION_SLAB && P->region != ORC_REGION_SPHERE)) return 0.0;
+    double d = orc_region_distance(P, R);
+    if (d > 0.0) {
+        if (P->region == ORC_REGION_SLAB) {
+            dir[0] = orc_mi(R[0] - P->center[0], P->box[0]) > 0.0 ? 1.0 : -1.0;
+        } else {
+            for (int k = 0; k < 3; ++k) dir[k] = orc_mi(R[k] - P->center[k], P->box[k]) / d;
+        }
+    }
+    int n = P->td_n;
+    double lo = P->td_lo, hi = P->td_hi, h = (hi - lo) / n;
+    const double *F = P->td;
+    if (d < lo) return 0.0;
+    /* potential: the pieces [lo, d_0], [d_k, d_k+1] for each k, [d_n-1, hi] clipped at d */
+    double top = d < hi ? d : hi;
+    double integral = 0.0;
+    double c0 = lo + 0.5 * h;
+    integral += F[0] * ((top < c0 ? top : c0) - lo);
+    for (int k = 0; k + 1 < n; ++k) {
+        double a = lo + (k + 0.5) * h, b = lo + (k + 1.5) * h;
+        if (top <= a) break;
+        double e = top < b ? top : b;
+        /* integral of the line through (a, F_k), (b, F_k+1) from a to e */
+        double fa_ = F[k], fe = F[k] + (F[k + 1] - F[k]) * (e - a) / h;
+        integral += 0.5 * (fa_ + fe) * (e - a);
+    }
+    double cn = lo + (n - 0.5) * h;
+    if (top > cn) integral += F[n - 1] * (top - cn);
+    *u = -integral;
+    if (d >= hi) return 0.0;
+    /* force value at d */
+    double t = (d - lo) / h - 0.5;   /* position in units of h from the first centre */
+    if (t <= 0.0) { *scale = fabs(F[0]); return F[0]; }
+    if (t >= n - 1) { *scale = fabs(F[n - 1]); return F[n - 1]; }
+    int k = (int)floor(t);
+    double s = t - k;
+    *scale = fabs(F[k]) + fabs(F[k + 1]);
+    return F[k] * (1.0 - s) + F[k + 1] * s;
 }
 
 static double orc_weight(const orc_params *P, const double R[3])
@@ -346,7 +410,7 @@ static double orc_cg_scale(const orc_params *P, double r2, double f_over_r)
  * for FENE; it bounds the rounding error of any evaluation order of the same
  * formulas, including sites whose net force is pure rounding noise. */
 static int orc_mol_forces(const orc_params *P, const double *x, const double *com, const double *w,
-                          int64_t a, double *fa, double *amag, double e[3])
+                          int64_t a, double *fa, double *amag, double e[4])
 {
     int status = 0;
     int spm = P->spm;
@@ -355,7 +419,7 @@ static int orc_mol_forces(const orc_params *P, const double *x, const double *co
     double rcA2 = P->rc_at * P->rc_at, rcC2 = P->rc_cg * P->rc_cg;
     for (int k = 0; k < 3 * spm; ++k) fa[k] = 0.0;
     for (int k = 0; k < spm; ++k) amag[k] = 0.0;
-    e[0] = e[1] = e[2] = 0.0;
+    e[0] = e[1] = e[2] = e[3] = 0.0;
     double Ra[3] = {com[a], com[n + a], com[2 * n + a]};
     const int hamiltonian = P->scheme == ORC_SCHEME_HAMILTONIAN;
     /* Eq. (2): the molecule's single-molecule potentials V^AT_a, V^CG_a (half of each
@@ -432,6 +496,17 @@ static int orc_mol_forces(const orc_params *P, const double *x, const double *co
         }
     }
 
+    if (P->td_n > 0) {
+        double dir[3], ut, sc;
+        double ft = orc_td_force(P, Ra, dir, &ut, &sc);
+        for (int i = 0; i < spm; ++i) {
+            double mf = P->mass[i] / M;
+            for (int q = 0; q < 3; ++q) fa[3 * i + q] += mf * ft * dir[q];
+            amag[i] += mf * sc;
+        }
+        e[3] += ut;
+    }
+
     if (P->bond_kind == ORC_BOND_HARMONIC) {
         /* every pair of sites of the molecule is bonded: U = K/2 (r - b0)^2 */
         for (int i = 0; i < spm; ++i) {
@@ -474,27 +549,28 @@ static int orc_mol_forces(const orc_params *P, const double *x, const double *co
 }
 
 /* Forces on every site (f: 3 x N_s SoA), absolute-sum scales (amag: N_s) and the
- * energies e[0..2] = U_AT, U_CG, U_bond.  Returns the status bit mask. */
+ * energies e[0..3] = U_AT, U_CG, U_bond, U_corr (the correction force's potential).
+ * Returns the status bit mask. */
 int orc_forces(const orc_params *P, const double *x, double *f, double *amag, double *energy)
 {
     int64_t n = P->n_mol, spm = P->spm, ns = n * spm;
     double *com = (double *)malloc(sizeof(double) * 3 * n);
     double *w = (double *)malloc(sizeof(double) * n);
-    double *em = (double *)malloc(sizeof(double) * 3 * n);
+    double *em = (double *)malloc(sizeof(double) * 4 * n);
     int status = orc_weights(P, x, com, w, NULL);
 #pragma omp parallel for schedule(dynamic, 16) reduction(| : status)
     for (int64_t a = 0; a < n; ++a) {
         double fa[3 * ORC_MAX_SITES], am[ORC_MAX_SITES];
-        status |= orc_mol_forces(P, x, com, w, a, fa, am, em + 3 * a);
+        status |= orc_mol_forces(P, x, com, w, a, fa, am, em + 4 * a);
         for (int i = 0; i < spm; ++i) {
             for (int q = 0; q < 3; ++q) f[q * ns + a * spm + i] = fa[3 * i + q];
             if (amag) amag[a * spm + i] = am[i];
         }
     }
     if (energy) {
-        energy[0] = energy[1] = energy[2] = 0.0;
+        energy[0] = energy[1] = energy[2] = energy[3] = 0.0;
         for (int64_t a = 0; a < n; ++a)
-            for (int k = 0; k < 3; ++k) energy[k] += em[3 * a + k];
+            for (int k = 0; k < 4; ++k) energy[k] += em[4 * a + k];
     }
     free(com); free(w); free(em);
     return status;
@@ -511,7 +587,7 @@ int orc_forces_sampled(const orc_params *P, const double *x, const int64_t *sel,
     int status = orc_weights(P, x, com, w, NULL);
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : status)
     for (int64_t s = 0; s < n_sel; ++s) {
-        double fa[3 * ORC_MAX_SITES], am[ORC_MAX_SITES], e[3];
+        double fa[3 * ORC_MAX_SITES], am[ORC_MAX_SITES], e[4];
         status |= orc_mol_forces(P, x, com, w, sel[s], fa, am, e);
         for (int i = 0; i < spm; ++i) {
             for (int q = 0; q < 3; ++q) f[(s * 3 + q) * spm + i] = fa[3 * i + q];
@@ -536,14 +612,14 @@ double orc_kinetic(const orc_params *P, const double *v)
 /* Velocity Verlet, n_steps of size dt, in place on x, v (f returns F(x_final)):
  *   v += F dt / (2m); x += v dt; fold each site into [0, L); F = F(x); v += F dt / (2m).
  * Force interpolation has no conserved energy (Sec. 2.3); energies are diagnostics.
- * e_out (optional): (n_steps + 1) x 4 rows of U_AT, U_CG, U_bond, KE. */
+ * e_out (optional): (n_steps + 1) x 5 rows of U_AT, U_CG, U_bond, U_corr, KE. */
 int orc_vv(const orc_params *P, double *x, double *v, double *f, double dt, int32_t n_steps,
            double *e_out)
 {
     int64_t n = P->n_mol, spm = P->spm, ns = n * spm;
-    double e[3];
+    double e[4];
     int status = orc_forces(P, x, f, NULL, e);
-    if (e_out) { e_out[0] = e[0]; e_out[1] = e[1]; e_out[2] = e[2]; e_out[3] = orc_kinetic(P, v); }
+    if (e_out) { for (int k = 0; k < 4; ++k) e_out[k] = e[k]; e_out[4] = orc_kinetic(P, v); }
     for (int32_t step = 0; step < n_steps; ++step) {
         for (int q = 0; q < 3; ++q) {
             double L = P->box[q];
@@ -561,11 +637,70 @@ int orc_vv(const orc_params *P, double *x, double *v, double *f, double dt, int3
             for (int64_t s = 0; s < ns; ++s)
                 v[q * ns + s] += f[q * ns + s] * dt / (2.0 * P->mass[s % spm]);
         if (e_out) {
-            double *r = e_out + 4 * (step + 1);
-            r[0] = e[0]; r[1] = e[1]; r[2] = e[2]; r[3] = orc_kinetic(P, v);
+            double *r = e_out + 5 * (step + 1);
+            for (int k = 0; k < 4; ++k) r[k] = e[k];
+            r[4] = orc_kinetic(P, v);
         }
     }
     return status;
+}
+
+/* Density profile along the resolution coordinate (Sec. 2.4): adds to counts[k] the
+ * number of molecules whose centre-of-mass distance d from the AT centre satisfies
+ * lo + k h <= d < lo + (k + 1) h, h = (hi - lo) / n_bins, with the bin index taken as
+ * floor((d - lo) / h) (the top bin also takes a d that rounds to n_bins below hi). */
+int orc_density_profile(const orc_params *P, const double *x, int32_t n_bins, double lo, double hi,
+                        int64_t *counts)
+{
+    int64_t n = P->n_mol;
+    double *com = (double *)malloc(sizeof(double) * 3 * n);
+    double *w = (double *)malloc(sizeof(double) * n);
+    int status = orc_weights(P, x, com, w, NULL);
+    double h = (hi - lo) / n_bins;
+    for (int64_t a = 0; a < n; ++a) {
+        double R[3] = {com[a], com[n + a], com[2 * n + a]};
+        double d = orc_region_distance(P, R);
+        if (d < lo || d >= hi) continue;
+        int64_t k = (int64_t)floor((d - lo) / h);
+        if (k > n_bins - 1) k = n_bins - 1;
+        counts[k] += 1;
+    }
+    free(com); free(w);
+    return status;
+}
+
+/* One refinement of the correction force from a density profile (Sec. 2.4: the force is
+ * built from the distorted density profile and refined iteratively).  Readings: the
+ * number density of bin k is rho_k = counts_k / (n_frames V_k), V_k the bin's volume (slab:
+ * both sides of the mid-plane, 2 h L_y L_z; sphere: the shell 4/3 pi (r_k+1^3 - r_k^3),
+ * r_k = lo + k h); its slope at bin centre k is the central difference
+ * (rho_k+1 - rho_k-1) / (2 h), one-sided at the two end bins, 0 for a single bin; and
+ * the update is F_k <- F_k - prefactor * slope_k (the usual prefactor is
+ * M / (rho_0^2 kappa_T)). */
+void orc_tdforce_update(const orc_params *P, double *F, int32_t n, double lo, double hi,
+                        const int64_t *counts, int64_t n_frames, double prefactor)
+{
+    double h = (hi - lo) / n;
+    double *rho = (double *)malloc(sizeof(double) * n);
+    for (int k = 0; k < n; ++k) {
+        double V;
+        if (P->region == ORC_REGION_SLAB) {
+            V = 2.0 * h * P->box[1] * P->box[2];
+        } else {
+            double r0 = lo + k * h, r1 = lo + (k + 1) * h;
+            V = (4.0 / 3.0) * M_PI * (r1 * r1 * r1 - r0 * r0 * r0);
+        }
+        rho[k] = (double)counts[k] / ((double)n_frames * V);
+    }
+    for (int k = 0; k < n; ++k) {
+        double slope;
+        if (n == 1) slope = 0.0;
+        else if (k == 0) slope = (rho[1] - rho[0]) / h;
+        else if (k == n - 1) slope = (rho[n - 1] - rho[n - 2]) / h;
+        else slope = (rho[k + 1] - rho[k - 1]) / (2.0 * h);
+        F[k] = F[k] - prefactor * slope;
+    }
+    free(rho);
 }
 
 int orc_num_threads(void)

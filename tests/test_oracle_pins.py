@@ -229,9 +229,9 @@ class TestPairList:
 
 
 # ---------------------------------------------------------------- Eq. (1) and its limits
-def _energy_grad_check(wl, x, n_check=12, h=1e-6, seed=0):
+def _energy_grad_check(wl, x, n_check=12, h=1e-6, seed=0, td=None):
     """Central finite differences of the oracle's total potential vs its forces."""
-    m = oracle.Model(wl)
+    m = oracle.Model(wl, td=td)
     f, amag, e, st = m.forces(x)
     assert st == 0
     rng = np.random.default_rng(seed)
@@ -476,3 +476,145 @@ class TestHamiltonianScheme:
         f1, f2 = np.max(np.abs(t1 - t1[0])), np.max(np.abs(t2 - t2[0]))
         assert f1 < 5e-3 * abs(t1[0]) + 1e-2
         assert 2.5 < f1 / f2 < 6.0, (f1, f2)
+
+
+# ---------------------------------------------------------------- correction force (Sec. 2.4)
+class TestCorrectionForce:
+    """The correction (thermodynamic) force along the resolution coordinate: closed forms of
+    its piecewise-linear table and of the potential, the direction (slab sign, sphere
+    unit offset), the mass-fraction split, forces = -grad of the energy including its
+    potential, the density histogram against NumPy's, and the refinement step on density
+    profiles whose slopes are known exactly."""
+
+    LO, HI, N = 2.0, 6.0, 8          # bin centres 2.25, 2.75, ..., 5.75; h = 0.5
+
+    def _single(self, region, R, td, masses=(1.0,)):
+        wl = _wl(n_mol=1, sites_per_mol=len(masses), site_mass=masses, region=region,
+                 rho_max=0.8 if len(masses) > 1 else 0.0)
+        if len(masses) == 1:
+            x = _soa([R])
+        else:
+            rng = np.random.default_rng(5)
+            x = inputs.tetra_positions(np.asarray(R, dtype=np.float64).reshape(3, 1), rng)
+        return oracle.Model(wl, td=td), x
+
+    def test_linear_table_closed_form_slab(self):
+        a, b = 0.7, -0.3
+        h = (self.HI - self.LO) / self.N
+        cent = self.LO + (np.arange(self.N) + 0.5) * h
+        F = a + b * cent
+        d0, dn = cent[0], cent[-1]
+        for d in [0.5, 1.99, 2.0, 2.1, 2.25, 3.1, 4.0, 5.6, 5.75, 5.9, 6.0, 7.5]:
+            for side in (1.0, -1.0):
+                m, x = self._single(inputs.REGION_SLAB_X, (10.0 + side * d, 10.0, 10.0), (F, self.LO, self.HI))
+                f, amag, e, st = m.forces(x)
+                assert st == 0
+                if d < self.LO or d >= self.HI:
+                    val = 0.0
+                elif d <= d0:
+                    val = F[0]
+                elif d >= dn:
+                    val = F[-1]
+                else:
+                    val = a + b * d
+                np.testing.assert_allclose(f[:, 0], [side * val, 0.0, 0.0], atol=1e-14)
+                # potential: -(F_0 (d_0 - lo) + integral of a + b s from d_0, F_n-1 beyond d_n-1)
+                top = min(max(d, self.LO), self.HI)
+                U = 0.0
+                U -= F[0] * (min(top, d0) - self.LO)
+                if top > d0:
+                    t = min(top, dn)
+                    U -= a * (t - d0) + 0.5 * b * (t * t - d0 * d0)
+                if top > dn:
+                    U -= F[-1] * (top - dn)
+                assert abs(e[3] - U) < 1e-13, (d, e[3], U)
+
+    def test_sphere_direction_and_mass_fractions(self):
+        F = np.linspace(1.0, 2.0, self.N)
+        masses = (1.0, 2.0, 3.0, 4.0)
+        rng = np.random.default_rng(2)
+        for _ in range(5):
+            u = rng.normal(size=3); u /= np.linalg.norm(u)
+            d = rng.uniform(self.LO + 0.1, self.HI - 0.1)
+            R = np.array([10.0, 10.0, 10.0]) + d * u
+            m, x = self._single(inputs.REGION_SPHERE, R, (F, self.LO, self.HI), masses)
+            com, _, _, _ = m.weights(x)
+            q = com[:, 0] - 10.0
+            dd = np.linalg.norm(q)
+            f, _, _, st = m.forces(x)
+            assert st == 0
+            # single molecule: no pair or bond forces, only the correction
+            h = (self.HI - self.LO) / self.N
+            val = np.interp(dd, self.LO + (np.arange(self.N) + 0.5) * h, F)
+            for i, mi in enumerate(masses):
+                np.testing.assert_allclose(f[:, i], (mi / 10.0) * val * q / dd, rtol=1e-12, atol=1e-14)
+
+    @pytest.mark.parametrize("scheme", [inputs.SCHEME_FORCE, inputs.SCHEME_HAMILTONIAN])
+    def test_forces_are_minus_gradient_with_correction(self, scheme):
+        # a hybrid slab in the all-AT limit of the pair forces is conservative (FI has no
+        # energy otherwise); with the Hamiltonian scheme the hybrid layer is kept
+        wl = inputs.workload("tiny_slab").with_(scheme=scheme)
+        if scheme == inputs.SCHEME_FORCE:
+            wl = wl.with_(d_at=50.0)
+        rng = np.random.default_rng(8)
+        F = rng.normal(size=12)
+        x, _ = inputs.make_state(wl, seed=11)
+        _energy_grad_check(wl, x, n_check=16, td=(F, 0.3, 3.9))
+
+    def test_zero_table_is_no_correction(self):
+        wl = inputs.workload("tiny_slab")
+        x, _ = inputs.make_state(wl)
+        f0, _, e0, _ = oracle.Model(wl).forces(x)
+        f1, _, e1, _ = oracle.Model(wl, td=(np.zeros(5), 0.5, 3.0)).forces(x)
+        np.testing.assert_array_equal(f0, f1)
+        assert e1[3] == 0.0
+
+    @pytest.mark.parametrize("name", ["small_slab", "small_sphere"])
+    def test_density_histogram_equals_numpy(self, name):
+        wl = inputs.workload(name)
+        x, _ = inputs.make_state(wl)
+        m = oracle.Model(wl)
+        com, _, _, _ = m.weights(x)
+        c = np.asarray(wl.center)[:, None]
+        L = np.asarray(wl.box)[:, None]
+        q = com - c
+        q = q - L * np.round(q / L)
+        d = np.abs(q[0]) if wl.region == inputs.REGION_SLAB_X else np.sqrt((q * q).sum(axis=0))
+        lo, hi, nb = 1.0, 0.5 * wl.box[0] - 0.5, 37
+        counts = m.density_profile(x, nb, lo, hi)
+        ref, _ = np.histogram(d, bins=nb, range=(lo, hi))
+        np.testing.assert_array_equal(counts, ref)
+        # accumulates
+        counts2 = m.density_profile(x, nb, lo, hi, counts.copy())
+        np.testing.assert_array_equal(counts2, 2 * ref)
+
+    def test_update_on_linear_slab_profile(self):
+        wl = inputs.workload("small_slab")
+        m = oracle.Model(wl)
+        n, lo, hi, frames, c = 9, 1.0, 10.0, 7, 0.25
+        h = (hi - lo) / n
+        alpha, beta = 40, 3
+        counts = alpha + beta * np.arange(n)
+        F = np.linspace(-1.0, 1.0, n)
+        V = 2.0 * h * wl.box[1] * wl.box[2]
+        got = m.tdforce_update(F, lo, hi, counts, frames, c)
+        np.testing.assert_allclose(got, F - c * beta / (frames * V * h), rtol=0, atol=1e-14)
+
+    def test_update_on_uniform_sphere_profile(self):
+        # counts proportional to the shell volumes ((k+1)^3 - k^3 for lo = 0): a flat
+        # density, so the update leaves the force unchanged up to rounding
+        wl = inputs.workload("small_sphere")
+        m = oracle.Model(wl)
+        n, lo, hi, frames, c = 10, 0.0, 5.0, 3, 2.0
+        k = np.arange(n)
+        counts = 6 * (3 * k * k + 3 * k + 1)
+        F = np.linspace(0.5, -0.5, n)
+        h = (hi - lo) / n
+        rho = 6 / (frames * (4.0 / 3.0) * np.pi * h ** 3)
+        got = m.tdforce_update(F, lo, hi, counts, frames, c)
+        assert np.abs(got - F).max() <= 1e-12 * c * rho / h
+        # and a density rising by one shell volume's worth per bin moves it by a known slope
+        counts2 = (6 + k) * (3 * k * k + 3 * k + 1)
+        got2 = m.tdforce_update(F, lo, hi, counts2, frames, c)
+        drho = 1 / (frames * (4.0 / 3.0) * np.pi * h ** 3)      # rho_k = (6 + k) drho
+        np.testing.assert_allclose(got2, F - c * drho / h, rtol=1e-12)
