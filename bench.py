@@ -51,6 +51,8 @@ def main():
                     help="run only the learned-vs-tabulated CG force leg and print its record")
     ap.add_argument("--no-hamiltonian", action="store_true",
                     help="skip the potential-energy-interpolation (Eq. (2)) leg")
+    ap.add_argument("--no-tdforce", action="store_true",
+                    help="skip the thermodynamic-force (correction field) leg")
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes 10 times "
@@ -168,6 +170,8 @@ def main():
     ctx.close()
     if not args.no_hamiltonian:
         out["hamiltonian_scheme"] = hamiltonian_leg(wl, x, v, args.steps, args.warmup)
+    if not args.no_tdforce:
+        out["thermodynamic_force"] = tdforce_leg(wl, x, v, args.steps)
     if not args.no_cg_compare:
         out["learned_vs_tabulated"] = learned_vs_tabulated(args.cg_steps)
 
@@ -207,7 +211,7 @@ def hamiltonian_leg(wl, x, v, steps, warmup):
     def total_energy():
         _, e = ctx.forces(xt, energy=True)
         vv = vt.cpu().numpy()
-        return float(e[:3].sum().item() + 0.5 * np.sum(masses * (vv * vv).sum(axis=0)))
+        return float(e.sum().item() + 0.5 * np.sum(masses * (vv * vv).sum(axis=0)))
 
     ctx.integrate(xt, vt, ft, wh.dt, warmup)
     e0 = total_energy()
@@ -229,6 +233,71 @@ def hamiltonian_leg(wl, x, v, steps, warmup):
         "total_energy_start": e0,
         "total_energy_end": e1,
         "energy_drift_per_molecule": (e1 - e0) / wh.n_mol,
+    }
+
+
+def tdforce_leg(wl, x, v, steps, n_iter=4, steps_per_iter=2000, sample_every=20, n_bins=28):
+    """Thermodynamic force (Sec. 2.4) on the same workload: a correction table over the
+    hybrid layer plus one sigma on each side, refined n_iter times from density profiles
+    sampled every sample_every steps of a Langevin run (gamma 1, kT 1), with the
+    ideal-gas prefactor kT / (2 rho_0) (half of the step that would balance the measured
+    gradient of an ideal gas).  Reports the largest deviation |rho / rho_0 - 1| over the
+    bins before the first and after the last refinement (sampling noise included), the
+    wall time per refinement cycle, the density-profile kernel's cost, and MD steps/s of
+    the plain step with the final correction installed."""
+    import torch
+    from paper_1806_10841_amd import binding
+    lo, hi = wl.d_at - 1.0, wl.d_at + wl.d_hy + 1.0
+    rho0 = wl.n_mol / float(np.prod(wl.box))
+    ctx = binding.Context(wl)
+    ctx.set_tdforce(np.zeros(n_bins), lo, hi)
+    xt = torch.tensor(x, device="cuda")
+    vt = torch.tensor(v, device="cuda")
+    ft = torch.empty_like(xt)
+    h = (hi - lo) / n_bins
+    vol = 2.0 * h * wl.box[1] * wl.box[2]
+    counts = torch.zeros(n_bins, dtype=torch.int64, device="cuda")
+    devs = []
+    seed = 7
+    ctx.integrate(xt, vt, ft, wl.dt, 500, gamma=1.0, kT=1.0, seed=seed)     # thermalise
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prof_s = 0.0
+    for it in range(n_iter + 1):
+        counts.zero_()
+        frames = steps_per_iter // sample_every
+        for _ in range(frames):
+            ctx.integrate(xt, vt, ft, wl.dt, sample_every, gamma=1.0, kT=1.0, seed=seed)
+            torch.cuda.synchronize()
+            tp = time.perf_counter()
+            ctx.density_profile(xt, counts)
+            torch.cuda.synchronize()
+            prof_s += time.perf_counter() - tp
+        rho = counts.cpu().numpy() / (frames * vol)
+        devs.append(float(np.abs(rho / rho0 - 1.0).max()))
+        if it < n_iter:
+            ctx.tdforce_update(counts, frames, 1.0 / (2.0 * rho0))
+    torch.cuda.synchronize()
+    cycle_s = (time.perf_counter() - t0) / (n_iter + 1)
+    table = ctx.get_tdforce()
+    # plain NVE steps with the final correction installed
+    ctx.integrate(xt, vt, ft, wl.dt, 100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.integrate(xt, vt, ft, wl.dt, steps)
+    torch.cuda.synchronize()
+    sps = steps / (time.perf_counter() - t0)
+    ctx.close()
+    return {
+        "bins": n_bins, "range": [lo, hi], "iterations": n_iter,
+        "steps_per_iteration": steps_per_iter, "sample_every": sample_every,
+        "max_density_deviation_before": devs[0],
+        "max_density_deviation_after": devs[-1],
+        "max_density_deviation_per_iteration": devs,
+        "seconds_per_iteration": cycle_s,
+        "density_profile_call_us": 1e6 * prof_s / ((n_iter + 1) * (steps_per_iter // sample_every)),
+        "steps_per_s_with_correction": sps,
+        "final_table": [float(t) for t in table],
     }
 
 

@@ -136,7 +136,8 @@ adres_status adres_build_verlet(adres_ctx *ctx, const double *x, int64_t *n_pair
  * r < rc_at and weights it by ww; the CG part (ww < 1) is (1 - ww) times the CG force
  * between centres of mass (r < rc_cg), shared among a molecule's sites by mass
  * fraction.  energy (device [4], optional): U_AT (ww-weighted), U_CG ((1 - ww)-weighted,
- * analytic CG only), U_bond, 0.  Builds the lists if none exist and rebuilds them if a
+ * analytic CG only), U_bond, U_corr (the correction force's potential, see
+ * adres_set_tdforce; 0 without one).  Builds the lists if none exist and rebuilds them if a
  * centre of mass moved more than r_skin/2 since the last build; to decide, it
  * synchronises once before the force kernel is enqueued. */
 adres_status adres_forces(adres_ctx *ctx, const double *x, double *f, double *energy);
@@ -169,6 +170,43 @@ adres_status adres_get_cells(adres_ctx *ctx, int32_t *cell_start_host, int32_t *
  * fallback below its r_min.  2 <= n_knots <= 4096. */
 adres_status adres_set_cg_table(adres_ctx *ctx, const float *coef4, int32_t n_knots,
                                 double r_lo, double r_hi);
+
+/* Correction force along the resolution coordinate: the thermodynamic force or free-energy
+ * correction of Sec. 2.4, a field over the hybrid region that flattens the density
+ * profile across it.  It acts on each molecule's centre of mass along the direction in
+ * which the distance d from the AT centre grows (slab: sign of the minimum-image x
+ * offset; sphere: the unit offset; none at d = 0) and reaches the sites by mass fraction,
+ * in every later force evaluation (adres_forces, adres_integrate, adres_map_cg).
+ * table (host, float64 [n]) holds its value F_k at the bin centres
+ * d_k = d_lo + (k + 1/2) h, h = (d_hi - d_lo) / n; F(d) is linear between neighbouring
+ * centres, holds F_0 from d_lo to d_0 and F_{n-1} from d_{n-1} to d_hi, and is 0 outside
+ * [d_lo, d_hi).  Its potential -integral of F from d_lo to min(d, d_hi) is reported as
+ * U_corr.  Needs region ADRES_REGION_SLAB_X or ADRES_REGION_SPHERE; 1 <= n <= 4096,
+ * 0 <= d_lo < d_hi, finite values (ADRES_E_ARG otherwise).  n = 0 removes the correction.
+ * Copied; synchronises. */
+adres_status adres_set_tdforce(adres_ctx *ctx, const double *table, int32_t n, double d_lo, double d_hi);
+
+/* Copy the installed correction values (e.g. after adres_tdforce_update) to table_host
+ * (host, float64 [n], n the installed length).  ADRES_E_STATE without a table.
+ * Synchronises. */
+adres_status adres_get_tdforce(adres_ctx *ctx, double *table_host, int32_t n);
+
+/* Density profile along the resolution coordinate (Sec. 2.4), in the bins of the installed
+ * correction table: adds to counts (device, int64 [n], caller-initialised) the number of
+ * molecules of x (device, caller order) whose centre-of-mass distance d from the AT
+ * centre lies in bin floor((d - d_lo) / h) of [d_lo, d_hi).  Call once per sampled frame.
+ * ADRES_E_STATE without a table.  Asynchronous. */
+adres_status adres_density_profile(adres_ctx *ctx, const double *x, int64_t *counts);
+
+/* One refinement of the correction force from a density profile (Sec. 2.4: the
+ * thermodynamic force is built from the distorted profile and refined iteratively):
+ * rho_k = counts_k / (n_frames V_k), V_k the volume of bin k (slab: both sides of the
+ * mid-plane, 2 h L_y L_z; sphere: the shell 4/3 pi (r_{k+1}^3 - r_k^3), r_k = d_lo + k h),
+ * then F_k <- F_k - prefactor * (drho/dd)_k with the slope by central differences of the
+ * neighbouring bins (one-sided at the two end bins, 0 for a single bin).  The usual
+ * prefactor is M / (rho_0^2 kappa_T).  counts: device int64 [n], n_frames >= 1.
+ * Asynchronous. */
+adres_status adres_tdforce_update(adres_ctx *ctx, const int64_t *counts, int64_t n_frames, double prefactor);
 
 /* Learned CG force (replaces F^CG of Eq. (1) when cg_kind is ADRES_CG_MLP):
  *   f(r) = scale * taper(r) * [W3 . silu(W2 silu(W1 x + b1) + b2) + b3],  x = r / rc,

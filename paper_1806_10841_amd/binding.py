@@ -61,6 +61,10 @@ _SIGS = {
     "adres_get_pairs": ([C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
     "adres_get_cells": ([C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)], C.c_int),
     "adres_set_cg_table": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double], C.c_int),
+    "adres_set_tdforce": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double], C.c_int),
+    "adres_get_tdforce": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
+    "adres_density_profile": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "adres_tdforce_update": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_double], C.c_int),
     "adres_mlp_set": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double], C.c_int),
     "adres_mlp_get": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
     "adres_mlp_eval": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64], C.c_int),
@@ -137,6 +141,7 @@ class Context:
             raise AdresError(st, "adres_create rejected the parameters")
         self.h = h
         self.n_sites = wl.n_mol * wl.sites_per_mol
+        self._td_n = 0
 
     def close(self):
         if getattr(self, "h", None):
@@ -207,6 +212,33 @@ class Context:
         assert coef.ndim == 2 and coef.shape[1] == 4
         self._check(self.lib.adres_set_cg_table(self.h, coef.ctypes.data_as(C.c_void_p), coef.shape[0] + 1,
                                                 r_lo, r_hi), "adres_set_cg_table")
+
+    def set_tdforce(self, table, d_lo, d_hi):
+        """Install the correction force values (float64, at the bin centres of [d_lo, d_hi))."""
+        table = np.ascontiguousarray(table, dtype=np.float64)
+        self._check(self.lib.adres_set_tdforce(self.h, table.ctypes.data_as(C.c_void_p), table.size,
+                                               d_lo, d_hi), "adres_set_tdforce")
+        self._td_n = int(table.size)
+
+    def get_tdforce(self):
+        out = np.empty(max(self._td_n, 1), dtype=np.float64)
+        self._check(self.lib.adres_get_tdforce(self.h, out.ctypes.data_as(C.c_void_p), out.size),
+                    "adres_get_tdforce")
+        return out
+
+    def density_profile(self, x, counts):
+        """Add the centre-of-mass distance histogram of x to counts (int64 device tensor)."""
+        import torch
+        if counts.dtype != torch.int64:
+            raise TypeError("counts must be int64")
+        self._check(self.lib.adres_density_profile(self.h, _ptr(x), _ptr(counts)), "adres_density_profile")
+
+    def tdforce_update(self, counts, n_frames, prefactor):
+        import torch
+        if counts.dtype != torch.int64:
+            raise TypeError("counts must be int64")
+        self._check(self.lib.adres_tdforce_update(self.h, _ptr(counts), int(n_frames), float(prefactor)),
+                    "adres_tdforce_update")
 
     def mlp_set(self, params, rc, scale, taper_width, r_min=0.0):
         params = np.ascontiguousarray(params, dtype=np.float32)

@@ -46,6 +46,7 @@ struct adres_ctx {
     double *epart = nullptr;
     int epart_blocks = 0;
     float4 *tab = nullptr;
+    double *td = nullptr, *td_u = nullptr;   // correction force table and its integrals
 
     // learned CG force
     float *mlp = nullptr;          // FP32 master parameters (kMlpParams)
@@ -475,7 +476,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     ok = ok && dalloc(&c->cnt_up, n) == hipSuccess && dalloc(&c->up_off, (size_t)n + 1) == hipSuccess &&
          dalloc(&c->up_scratch, n) == hipSuccess;
     c->epart_blocks = force_blocks(n);
-    ok = ok && dalloc(&c->epart, 3 * (size_t)c->epart_blocks) == hipSuccess;
+    ok = ok && dalloc(&c->epart, 4 * (size_t)c->epart_blocks) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&c->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&c->pub, sizeof(CtrlPub), hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
     if (ok) {
@@ -516,6 +517,7 @@ void adres_destroy(adres_ctx *c)
     hipFree(c->R_ref); hipFree(c->inv_perm); hipFree(c->cell_rank);
     hipFree(c->count); hipFree(c->start); hipFree(c->fill); hipFree(c->new_from); hipFree(c->scan_tiles);
     hipFree(c->nbr); hipFree(c->cnt); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
+    hipFree(c->td); hipFree(c->td_u);
     hipFree(c->mlp); hipFree(c->mlp_w2); hipFree(c->mlp_w2q); hipFree(c->mlp_fp8s); hipFree(c->cnt_up); hipFree(c->up_off); hipFree(c->up_scratch);
     hipFree(c->pid); hipFree(c->up_pairs); hipFree(c->f_pair);
     hipFree(c->adam_m); hipFree(c->adam_v); hipFree(c->grad); hipFree(c->loss); hipFree(c->res_part);
@@ -750,6 +752,68 @@ adres_status adres_set_cg_table(adres_ctx *c, const float *coef4, int32_t n_knot
     c->P.tab_n = n_knots;
     c->P.tab_lo = r_lo;
     c->P.tab_h = (r_hi - r_lo) / (double)(n_knots - 1);
+    return ADRES_OK;
+}
+
+adres_status adres_set_tdforce(adres_ctx *c, const double *table, int32_t n, double d_lo, double d_hi)
+{
+    if (!c) return fail(c, ADRES_E_ARG, "null argument");
+    if (n == 0) {
+        c->P.td_n = 0;
+        return ADRES_OK;
+    }
+    if (!table) return fail(c, ADRES_E_ARG, "null argument");
+    if (c->P.region != ADRES_REGION_SLAB_X && c->P.region != ADRES_REGION_SPHERE)
+        return fail(c, ADRES_E_ARG, "a correction force needs a slab or sphere region");
+    if (n < 0 || n > kTdMaxBins || !std::isfinite(d_lo) || !std::isfinite(d_hi) || !(d_lo >= 0.0) ||
+        !(d_hi > d_lo))
+        return fail(c, ADRES_E_ARG, "correction table needs 1..4096 values on 0 <= d_lo < d_hi");
+    for (int k = 0; k < n; ++k)
+        if (!std::isfinite(table[k])) return fail(c, ADRES_E_ARG, "correction table value is not finite");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!c->td) {
+        HIPCHK(c, dalloc(&c->td, (size_t)kTdMaxBins));
+        HIPCHK(c, dalloc(&c->td_u, (size_t)kTdMaxBins));
+    }
+    HIPCHK(c, hipMemcpy(c->td, table, sizeof(double) * n, hipMemcpyHostToDevice));
+    c->P.td = c->td;
+    c->P.td_u = c->td_u;
+    c->P.td_n = n;
+    c->P.td_lo = d_lo;
+    c->P.td_hi = d_hi;
+    c->P.td_h = (d_hi - d_lo) / (double)n;
+    launch_td_update(c->stream, c->P, c->td, c->td_u, nullptr, 1, 0.0);
+    HIPCHK(c, hipGetLastError());
+    return ADRES_OK;
+}
+
+adres_status adres_get_tdforce(adres_ctx *c, double *table_host, int32_t n)
+{
+    if (!c || !table_host) return fail(c, ADRES_E_ARG, "null argument");
+    if (c->P.td_n == 0) return fail(c, ADRES_E_STATE, "no correction force installed");
+    if (n != c->P.td_n) return fail(c, ADRES_E_ARG, "n differs from the installed table's length");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(table_host, c->td, sizeof(double) * n, hipMemcpyDeviceToHost));
+    return ADRES_OK;
+}
+
+adres_status adres_density_profile(adres_ctx *c, const double *x, int64_t *counts)
+{
+    if (!c || !x || !counts) return fail(c, ADRES_E_ARG, "null argument");
+    if (c->P.td_n == 0) return fail(c, ADRES_E_STATE, "no correction table (its bins define the profile)");
+    launch_density_profile(c->stream, c->P, x, reinterpret_cast<unsigned long long *>(counts));
+    HIPCHK(c, hipGetLastError());
+    return ADRES_OK;
+}
+
+adres_status adres_tdforce_update(adres_ctx *c, const int64_t *counts, int64_t n_frames, double prefactor)
+{
+    if (!c || !counts) return fail(c, ADRES_E_ARG, "null argument");
+    if (c->P.td_n == 0) return fail(c, ADRES_E_STATE, "no correction force installed");
+    if (n_frames < 1 || !std::isfinite(prefactor)) return fail(c, ADRES_E_ARG, "need n_frames >= 1, finite prefactor");
+    launch_td_update(c->stream, c->P, c->td, c->td_u, reinterpret_cast<const long long *>(counts),
+                     (long long)n_frames, prefactor);
+    HIPCHK(c, hipGetLastError());
     return ADRES_OK;
 }
 

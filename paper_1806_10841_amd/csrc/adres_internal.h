@@ -57,6 +57,13 @@ struct DevParams {
     const float4 *tab;
     int tab_n;
     double tab_lo, tab_h;
+    // correction force along the resolution coordinate: td_n values at the bin centres
+    // of [td_lo, td_hi) (bin width td_h) and the integrals of the interpolated force from
+    // td_lo to each centre (td_u, for its potential); td_n = 0: none
+    const double *td;
+    const double *td_u;
+    int td_n;
+    double td_lo, td_hi, td_h;
 };
 
 // Cell grid over the box.
@@ -160,21 +167,72 @@ __device__ __forceinline__ void weight_gradient(const DevParams &P, const double
     }
 }
 
+// Distance of a centre of mass from the AT region's centre (slab: |x offset|; sphere:
+// Euclidean), minimum image; q receives the offset (slab: x only).
+__device__ __forceinline__ double res_distance(const DevParams &P, const double R[3], double q[3])
+{
+#pragma clang fp contract(off)
+    q[0] = mi(R[0] - P.center[0], P.box[0], P.half[0]);
+    if (P.region == ADRES_REGION_SLAB_X) {
+        q[1] = q[2] = 0.0;
+        return fabs(q[0]);
+    }
+    q[1] = mi(R[1] - P.center[1], P.box[1], P.half[1]);
+    q[2] = mi(R[2] - P.center[2], P.box[2], P.half[2]);
+    return sqrt(dist2_exact(q[0], q[1], q[2]));
+}
+
+// Correction force on a centre of mass along the resolution coordinate: its value F(d)
+// from the table (linear between bin centres, the end values held out to td_lo and
+// td_hi, 0 outside [td_lo, td_hi)), its unit direction (the gradient of d) in dir, and
+// with ENERGY its potential -integral of F from td_lo to min(d, td_hi) in u.
+template <bool ENERGY>
+__device__ __forceinline__ double corr_force(const DevParams &P, const double R[3], double dir[3], double &u)
+{
+    dir[0] = dir[1] = dir[2] = 0.0;
+    u = 0.0;
+    double q[3];
+    const double d = res_distance(P, R, q);
+    if (!(d >= P.td_lo)) return 0.0;
+    const int n = P.td_n;
+    const double t = (d - P.td_lo) / P.td_h - 0.5;   // in bin widths from the first centre
+    double f;
+    if (d >= P.td_hi) {
+        if (ENERGY) u = -(P.td_u[n - 1] + P.td[n - 1] * (0.5 * P.td_h));
+        return 0.0;
+    } else if (t <= 0.0) {
+        f = P.td[0];
+        if (ENERGY) u = -(P.td[0] * (d - P.td_lo));
+    } else if (t >= (double)(n - 1)) {
+        f = P.td[n - 1];
+        if (ENERGY) u = -(P.td_u[n - 1] + P.td[n - 1] * ((t - (double)(n - 1)) * P.td_h));
+    } else {
+        const int k = (int)t;
+        const double s = t - (double)k;
+        const double f0 = P.td[k], f1 = P.td[k + 1];
+        f = f0 * (1.0 - s) + f1 * s;
+        if (ENERGY) u = -(P.td_u[k] + P.td_h * s * (f0 + 0.5 * (f1 - f0) * s));
+    }
+    if (d > 0.0) {
+        if (P.region == ADRES_REGION_SLAB_X) {
+            dir[0] = q[0] > 0.0 ? 1.0 : -1.0;
+        } else {
+            dir[0] = q[0] / d;
+            dir[1] = q[1] / d;
+            dir[2] = q[2] / d;
+        }
+    }
+    return f;
+}
+
 // Resolution weight of a centre of mass (1 in AT, cos^2 ramp in HY, 0 in CG).
 __device__ __forceinline__ double res_weight(const DevParams &P, const double R[3])
 {
 #pragma clang fp contract(off)
     if (P.region == ADRES_REGION_ALL_AT) return 1.0;
     if (P.region == ADRES_REGION_ALL_CG) return 0.0;
-    double d;
-    if (P.region == ADRES_REGION_SLAB_X) {
-        d = fabs(mi(R[0] - P.center[0], P.box[0], P.half[0]));
-    } else {
-        double q0 = mi(R[0] - P.center[0], P.box[0], P.half[0]);
-        double q1 = mi(R[1] - P.center[1], P.box[1], P.half[1]);
-        double q2 = mi(R[2] - P.center[2], P.box[2], P.half[2]);
-        d = sqrt(dist2_exact(q0, q1, q2));
-    }
+    double q[3];
+    const double d = res_distance(P, R, q);
     if (d <= P.d_at) return 1.0;
     if (d >= P.d_end) return 0.0;
     double c = cos(M_PI * (d - P.d_at) / (2.0 * P.d_hy));
@@ -430,5 +488,11 @@ int launch_forces(hipStream_t s, const ForceArgs &a, int pair_precision, hipEven
                   hipEvent_t e1 = nullptr);
 int force_blocks(int n_mol);
 void launch_energy_reduce(hipStream_t s, const double *epart, int n_blocks, double *energy);
+
+// correction force (k_correction.hip)
+constexpr int kTdMaxBins = 4096;
+void launch_density_profile(hipStream_t s, const DevParams &P, const double *x, unsigned long long *counts);
+void launch_td_update(hipStream_t s, const DevParams &P, double *td, double *td_u, const long long *counts,
+                      long long n_frames, double prefactor);
 
 }  // namespace adres

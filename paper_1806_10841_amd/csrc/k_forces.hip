@@ -281,6 +281,13 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     cg1 = quad_sum(cg1);
     cg2 = quad_sum(cg2);
 
+    // correction force on the centre of mass along the resolution coordinate (Sec. 2.4)
+    double tdir[3] = {0.0, 0.0, 0.0}, ucorr = 0.0, ftd = 0.0;
+    if (P.td_n > 0) {
+        const double Rm[3] = {me.x, me.y, me.z};
+        ftd = corr_force<ENERGY>(P, Rm, tdir, ucorr);
+    }
+
     // lane q owns site q
     double F[3] = {0.0, 0.0, 0.0}, xq[3] = {0.0, 0.0, 0.0};
     double mq = 1.0, iq = 0.5;
@@ -297,6 +304,12 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                 F[0] += dv * gw[0];
                 F[1] += dv * gw[1];
                 F[2] += dv * gw[2];
+            }
+            if (P.td_n > 0) {
+                const double ft = mf * ftd;
+                F[0] += ft * tdir[0];
+                F[1] += ft * tdir[1];
+                F[2] += ft * tdir[2];
             }
             xq[0] = XI(i, 0); xq[1] = XI(i, 1); xq[2] = XI(i, 2);
             mq = P.mass[i];
@@ -422,21 +435,21 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
 #undef XI
     if (ENERGY) {
         // block reduction in a fixed order: wavefront butterflies, then 4 waves in LDS
-        __shared__ double red[kBlock / 64][3];
-        double e[3] = {uat, ucg, ubond};
+        __shared__ double red[kBlock / 64][4];
+        double e[4] = {uat, ucg, ubond, valid && q == 0 ? ucorr : 0.0};
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) e[c] += __shfl_xor(e[c], off, 64);
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         if (lane == 0) {
-            red[wave][0] = e[0]; red[wave][1] = e[1]; red[wave][2] = e[2];
+            red[wave][0] = e[0]; red[wave][1] = e[1]; red[wave][2] = e[2]; red[wave][3] = e[3];
         }
         __syncthreads();
-        if (threadIdx.x < 3) {
+        if (threadIdx.x < 4) {
             double s = 0.0;
             for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
-            a.epart[blk * 3 + threadIdx.x] = s;
+            a.epart[blk * 4 + threadIdx.x] = s;
         }
     }
 }
@@ -444,19 +457,18 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
 __global__ __launch_bounds__(256) void k_energy_reduce(const double *__restrict__ epart, int n_blocks,
                                                        double *__restrict__ energy)
 {
-    __shared__ double red[256][3];
-    double s[3] = {0.0, 0.0, 0.0};
+    __shared__ double red[256][4];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < n_blocks; b += 256)
-        for (int c = 0; c < 3; ++c) s[c] += epart[b * 3 + c];
-    for (int c = 0; c < 3; ++c) red[threadIdx.x][c] = s[c];
+        for (int c = 0; c < 4; ++c) s[c] += epart[b * 4 + c];
+    for (int c = 0; c < 4; ++c) red[threadIdx.x][c] = s[c];
     __syncthreads();
     for (int half = 128; half >= 1; half >>= 1) {
         if (threadIdx.x < half)
-            for (int c = 0; c < 3; ++c) red[threadIdx.x][c] += red[threadIdx.x + half][c];
+            for (int c = 0; c < 4; ++c) red[threadIdx.x][c] += red[threadIdx.x + half][c];
         __syncthreads();
     }
-    if (threadIdx.x < 3) energy[threadIdx.x] = red[0][threadIdx.x];
-    if (threadIdx.x == 3) energy[3] = 0.0;
+    if (threadIdx.x < 4) energy[threadIdx.x] = red[0][threadIdx.x];
 }
 
 // Launch; with events, hipExtLaunchKernelGGL records them at the kernel's own start

@@ -154,6 +154,83 @@ __global__ __launch_bounds__(kBlock) void k_map_cg(DevParams P, const double *__
     }
 }
 
+// Density profile along the resolution coordinate (Sec. 2.4), in the bins of the
+// installed correction table: centre of mass (the operation order of the weights), its
+// distance d from the AT centre, bin floor((d - lo) / h) (the top bin also takes a d that
+// rounds to n below hi), counted per workgroup in LDS and added to the int64 totals.
+template <int SPM>
+__global__ __launch_bounds__(kBlock) void k_density_profile(DevParams P, const double *__restrict__ x,
+                                                            unsigned long long *__restrict__ counts)
+{
+    __shared__ unsigned hist[kTdMaxBins];
+    const int nb = P.td_n;
+    for (int b = threadIdx.x; b < nb; b += kBlock) hist[b] = 0u;
+    __syncthreads();
+    const int a = blockIdx.x * kBlock + threadIdx.x;
+    if (a < P.n_mol) {
+        double p[SPM][3];
+        load_sites<SPM>(x, P.n_sites, a, p);
+        double R[3], rh, q[3];
+        mol_com<SPM>(P, p, R, rh);
+        const double d = res_distance(P, R, q);
+        if (d >= P.td_lo && d < P.td_hi) {
+            const double u = floor((d - P.td_lo) / P.td_h);
+            const int k = u < (double)(nb - 1) ? (int)u : nb - 1;
+            atomicAdd(&hist[k], 1u);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += kBlock)
+        if (hist[b]) atomicAdd(&counts[b], (unsigned long long)hist[b]);
+}
+
+// One refinement of the correction force from accumulated counts (Sec. 2.4): number
+// density per bin (counts / (n_frames V_k), V_k the slab pair of bins 2 h L_y L_z or the
+// spherical shell 4/3 pi (r_k+1^3 - r_k^3)), its central-difference slope (one-sided at
+// the end bins), F_k -= prefactor * slope_k; then the integrals of the interpolated force
+// from lo to each bin centre for the potential.  counts == nullptr only recomputes the
+// integrals.  One workgroup; n <= kTdMaxBins.
+__global__ __launch_bounds__(kBlock) void k_td_update(DevParams P, double *__restrict__ td, double *__restrict__ td_u,
+                                                      const long long *__restrict__ counts, long long n_frames,
+                                                      double prefactor)
+{
+#pragma clang fp contract(off)
+    __shared__ double rho[kTdMaxBins];
+    const int n = P.td_n;
+    const double h = P.td_h, lo = P.td_lo;
+    if (counts) {
+        for (int k = threadIdx.x; k < n; k += kBlock) {
+            double V;
+            if (P.region == ADRES_REGION_SLAB_X) {
+                V = 2.0 * h * P.box[1] * P.box[2];
+            } else {
+                const double r0 = lo + k * h, r1 = lo + (k + 1) * h;
+                V = (4.0 / 3.0) * M_PI * (r1 * r1 * r1 - r0 * r0 * r0);
+            }
+            rho[k] = (double)counts[k] / ((double)n_frames * V);
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < n; k += kBlock) {
+            double slope;
+            if (n == 1) slope = 0.0;
+            else if (k == 0) slope = (rho[1] - rho[0]) / h;
+            else if (k == n - 1) slope = (rho[n - 1] - rho[n - 2]) / h;
+            else slope = (rho[k + 1] - rho[k - 1]) / (2.0 * h);
+            td[k] = td[k] - prefactor * slope;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // integral from lo to the first centre (the held end value), then trapezoids
+        double acc = td[0] * (0.5 * h);
+        td_u[0] = acc;
+        for (int k = 0; k + 1 < n; ++k) {
+            acc = acc + 0.5 * (td[k] + td[k + 1]) * h;
+            td_u[k + 1] = acc;
+        }
+    }
+}
+
 __global__ void k_publish(const Ctrl *__restrict__ ctrl, CtrlPub *pub, unsigned seq)
 {
     if (threadIdx.x != 0) return;
@@ -226,6 +303,17 @@ void launch_publish(hipStream_t s, const Ctrl *ctrl, CtrlPub *pub, unsigned seq)
 void launch_map_cg(hipStream_t s, const DevParams &P, const double *x, const double *f, double *com, double *fmap)
 {
     ADRES_SPM_DISPATCH(P.spm, (k_map_cg<S_><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, x, f, com, fmap)));
+}
+
+void launch_density_profile(hipStream_t s, const DevParams &P, const double *x, unsigned long long *counts)
+{
+    ADRES_SPM_DISPATCH(P.spm, (k_density_profile<S_><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, x, counts)));
+}
+
+void launch_td_update(hipStream_t s, const DevParams &P, double *td, double *td_u, const long long *counts,
+                      long long n_frames, double prefactor)
+{
+    k_td_update<<<1, kBlock, 0, s>>>(P, td, td_u, counts, n_frames, prefactor);
 }
 
 }  // namespace adres

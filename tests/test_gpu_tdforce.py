@@ -1,0 +1,247 @@
+"""GPU parity of the correction (thermodynamic) force of Sec. 2.4 against the FP64 oracle,
+through the C ABI: the force and its potential inside Eq. (1) and Eq. (2) evaluations,
+the density profile (integer counts, exact), one refinement step, trajectories, and the
+conserved energy of the Hamiltonian scheme with a correction.
+
+Bars as for the other forces: FP64 pairs 1e-12 and FP32 pairs 1e-5 of the oracle's term
+scale A_i (which includes |F_k| + |F_k+1| m_i / M of the correction) and normwise.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1806_10841_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+HAM = inputs.SCHEME_HAMILTONIAN
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    return torch.device("cuda:0")
+
+
+def _ctx(wl, td=None):
+    from paper_1806_10841_amd import binding
+    c = binding.Context(wl)
+    if td is not None:
+        c.set_tdforce(*td)
+    return c
+
+
+def _t(a, dev):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+def _table(wl, n, seed):
+    """A smooth random correction over the hybrid layer plus a margin on each side."""
+    rng = np.random.default_rng(seed)
+    lo = max(wl.d_at - 0.5, 0.0)
+    hi = wl.d_at + wl.d_hy + 0.5
+    c = lo + (np.arange(n) + 0.5) * (hi - lo) / n
+    F = 0.8 * np.sin(np.pi * (c - lo) / (hi - lo)) + 0.2 * rng.normal(size=n)
+    return F, lo, hi
+
+
+def _assert_close(fg, fo, amag, tol, where):
+    err = np.abs(fg - fo).max(axis=0)
+    ratio = (err / np.maximum(amag, 1e-300)).max()
+    assert ratio <= tol, f"{where}: worst ratio {ratio:.3e}"
+    assert np.linalg.norm(fg - fo) <= tol * np.linalg.norm(fo), where
+
+
+@pytest.mark.parametrize("name,scheme", [("tiny_slab", 0), ("c1", 0), ("small_slab", 0), ("small_sphere", 0),
+                                         ("small_slab", HAM), ("small_sphere", HAM)])
+def test_forces_fp64_with_correction(dev, name, scheme):
+    wl = inputs.workload(name).with_(pair_precision=64, scheme=scheme)
+    td = _table(wl, 24, 1)
+    x, _ = inputs.make_state(wl)
+    fo, amag, eo, st = oracle.Model(wl, td=td).forces(x)
+    assert st == 0 and eo[3] != 0.0
+    f, e = _ctx(wl, td).forces(_t(x, dev), energy=True)
+    torch.cuda.synchronize()
+    _assert_close(f.cpu().numpy(), fo, amag, 1e-12, name)
+    np.testing.assert_allclose(e.cpu().numpy(), eo, rtol=1e-12, atol=1e-12 * np.abs(eo).max())
+
+
+@pytest.mark.parametrize("name", ["small_slab", "small_sphere"])
+def test_forces_fp32_with_correction(dev, name):
+    wl = inputs.workload(name).with_(pair_precision=32)
+    td = _table(wl, 100, 2)
+    x, _ = inputs.make_state(wl)
+    fo, amag, eo, st = oracle.Model(wl, td=td).forces(x)
+    f, e = _ctx(wl, td).forces(_t(x, dev), energy=True)
+    torch.cuda.synchronize()
+    _assert_close(f.cpu().numpy(), fo, amag, 1e-5, name)
+    np.testing.assert_allclose(e.cpu().numpy(), eo, rtol=1e-5, atol=1e-5 * np.abs(eo).max())
+
+
+def test_forces_c2_full_size_sampled_with_correction(dev):
+    wl = inputs.workload("c2")
+    td = _table(wl, 64, 3)
+    x, _ = inputs.make_state(wl)
+    m = oracle.Model(wl, td=td)
+    _, w, _, _ = m.weights(x)
+    rng = np.random.default_rng(4)
+    sel = []
+    for mask in (w == 1.0, (w > 0) & (w < 1), w == 0.0):
+        idx = np.flatnonzero(mask)
+        sel.append(rng.choice(idx, size=min(60, len(idx)), replace=False))
+    sel = np.sort(np.concatenate(sel))
+    fo, amag, st = m.forces_sampled(x, sel)
+    assert st == 0
+    f = _ctx(wl, td).forces(_t(x, dev)).cpu().numpy()
+    fg = np.stack([f[:, 4 * a:4 * a + 4] for a in sel])
+    err = np.abs(fg - fo).max(axis=1)
+    assert np.all(err <= 1e-5 * amag), (err / amag).max()
+
+
+def _profile_matches(m, x, counts_gpu, n, lo, hi):
+    """Exact equality, except that a centre whose distance lies within 1e-12 of a bin edge
+    may be counted on either side (both sides compute the same distance; the allowance
+    only covers a last-bit difference of a square root)."""
+    ref = m.density_profile(x, n, lo, hi)
+    if np.array_equal(ref, counts_gpu):
+        return True
+    com, _, _, _ = m.weights(x)
+    wl = m.wl
+    q = com - np.asarray(wl.center)[:, None]
+    L = np.asarray(wl.box)[:, None]
+    q = q - L * np.round(q / L)
+    d = np.abs(q[0]) if wl.region == inputs.REGION_SLAB_X else np.sqrt((q * q).sum(axis=0))
+    edges = lo + np.arange(n + 1) * (hi - lo) / n
+    near = np.min(np.abs(d[:, None] - edges[None, :]), axis=1) < 1e-12 * max(hi, 1.0)
+    return np.abs(ref - counts_gpu).sum() <= 2 * int(near.sum())
+
+
+@pytest.mark.parametrize("name,n", [("small_slab", 37), ("small_sphere", 64), ("c2", 200), ("c5", 4096),
+                                    ("tiny_slab", 1)])
+def test_density_profile_exact(dev, name, n):
+    wl = inputs.workload(name)
+    x, _ = inputs.make_state(wl)
+    lo, hi = 0.5, 0.5 * wl.box[0] - 0.25
+    ctx = _ctx(wl, (np.zeros(n), lo, hi))
+    counts = torch.zeros(n, dtype=torch.int64, device=dev)
+    xt = _t(x, dev)
+    ctx.density_profile(xt, counts)
+    ctx.density_profile(xt, counts)           # accumulates
+    torch.cuda.synchronize()
+    got = counts.cpu().numpy()
+    assert got.sum() > 0
+    assert np.all(got % 2 == 0)
+    assert _profile_matches(oracle.Model(wl), x, got // 2, n, lo, hi)
+
+
+@pytest.mark.parametrize("name,n", [("small_slab", 40), ("small_sphere", 33), ("tiny_slab", 1), ("small_slab", 4096)])
+def test_update_matches_oracle(dev, name, n):
+    wl = inputs.workload(name)
+    rng = np.random.default_rng(n)
+    lo, hi = 1.0, 7.5
+    F = rng.normal(size=n)
+    counts = rng.integers(0, 5000, size=n).astype(np.int64)
+    ctx = _ctx(wl, (F, lo, hi))
+    ctx.tdforce_update(torch.tensor(counts, device=dev), 13, 0.37)
+    got = ctx.get_tdforce()
+    ref = oracle.Model(wl).tdforce_update(F, lo, hi, counts, 13, 0.37)
+    np.testing.assert_allclose(got, ref, rtol=1e-14, atol=1e-14 * np.abs(ref).max())
+
+
+def test_update_then_forces_use_new_table(dev):
+    """After a refinement the forces and the potential use the new values (the integrals
+    for the potential are recomputed on the device)."""
+    wl = inputs.workload("small_slab").with_(pair_precision=64)
+    F, lo, hi = _table(wl, 30, 5)
+    x, _ = inputs.make_state(wl)
+    ctx = _ctx(wl, (F, lo, hi))
+    xt = _t(x, dev)
+    counts = torch.zeros(30, dtype=torch.int64, device=dev)
+    ctx.density_profile(xt, counts)
+    ctx.tdforce_update(counts, 1, 5.0)
+    F2 = oracle.Model(wl).tdforce_update(F, lo, hi, oracle.Model(wl).density_profile(x, 30, lo, hi), 1, 5.0)
+    np.testing.assert_allclose(ctx.get_tdforce(), F2, rtol=1e-14, atol=1e-14)
+    fo, amag, eo, _ = oracle.Model(wl, td=(F2, lo, hi)).forces(x)
+    f, e = ctx.forces(xt, energy=True)
+    _assert_close(f.cpu().numpy(), fo, amag, 1e-12, "after update")
+    np.testing.assert_allclose(e.cpu().numpy(), eo, rtol=1e-12, atol=1e-12 * np.abs(eo).max())
+
+
+def _min_image(d, L):
+    return d - L * np.round(d / L)
+
+
+@pytest.mark.parametrize("name,scheme,steps", [("tiny_slab", 0, 100), ("small_sphere", HAM, 40)])
+def test_integrate_fp64_matches_oracle_vv(dev, name, scheme, steps):
+    wl = inputs.workload(name).with_(pair_precision=64, scheme=scheme)
+    td = _table(wl, 20, 6)
+    x, v = inputs.make_state(wl)
+    xo, vo, fo, _, st = oracle.Model(wl, td=td).vv(x, v, wl.dt, steps)
+    assert st == 0
+    ctx = _ctx(wl, td)
+    xt, vt = _t(x, dev), _t(v, dev)
+    ft = torch.empty_like(xt)
+    ctx.integrate(xt, vt, ft, wl.dt, steps)
+    torch.cuda.synchronize()
+    tol = 1e-9
+    assert np.abs(_min_image(xt.cpu().numpy() - xo, wl.box[0])).max() < tol
+    assert np.abs(vt.cpu().numpy() - vo).max() < 100 * tol
+
+
+def test_nve_hamiltonian_with_correction_conserves_energy(dev):
+    """Eq. (2) plus a correction field derived from a potential: velocity Verlet
+    conserves kinetic + U_AT + U_CG + U_bond + U_corr to O(dt^2)."""
+    wl = inputs.workload("tiny_slab").with_(pair_precision=64, scheme=HAM)
+    n = 16
+    lo, hi = 0.4, 3.9
+    c = lo + (np.arange(n) + 0.5) * (hi - lo) / n
+    F = 2.0 * np.sin(np.pi * (c - lo) / (hi - lo)) ** 2       # small end values: small jumps
+    x, v = inputs.make_state(wl)
+    m = oracle.Model(wl)
+
+    def trace(dt, chunk):
+        ctx = _ctx(wl, (F, lo, hi))
+        xt, vt = _t(x, dev), _t(v, dev)
+        ft = torch.empty_like(xt)
+        out = []
+        for k in range(11):
+            if k:
+                ctx.integrate(xt, vt, ft, dt, chunk)
+            _, e = ctx.forces(xt, energy=True)
+            out.append(e.sum().item() + m.kinetic(vt.cpu().numpy()))
+        return np.array(out)
+
+    t1, t2 = trace(0.002, 10), trace(0.001, 20)
+    f1, f2 = np.abs(t1 - t1[0]).max(), np.abs(t2 - t2[0]).max()
+    assert f1 < 5e-3 * abs(t1[0]) + 1e-2, (f1, t1[0])
+    assert 2.5 < f1 / f2 < 6.0, (f1, f2)
+
+
+def test_remove_and_errors(dev):
+    from paper_1806_10841_amd import binding
+    wl = inputs.workload("small_slab").with_(pair_precision=64)
+    x, _ = inputs.make_state(wl)
+    xt = _t(x, dev)
+    ctx = _ctx(wl)
+    f0 = ctx.forces(xt).clone()
+    ctx.set_tdforce(np.ones(8), 1.0, 6.0)
+    assert not torch.equal(ctx.forces(xt), f0)
+    ctx.set_tdforce(np.zeros(0), 0.0, 1.0)          # n = 0 removes it
+    assert torch.equal(ctx.forces(xt), f0)
+    counts = torch.zeros(8, dtype=torch.int64, device=dev)
+    with pytest.raises(binding.AdresError):
+        ctx.density_profile(xt, counts)              # no table: no bins
+    with pytest.raises(binding.AdresError):
+        ctx.set_tdforce(np.ones(4097), 1.0, 6.0)
+    with pytest.raises(binding.AdresError):
+        ctx.set_tdforce(np.ones(8), 6.0, 1.0)
+    with pytest.raises(binding.AdresError):
+        ctx.set_tdforce(np.array([1.0, np.nan]), 1.0, 6.0)
+    at = _ctx(inputs.workload("tiny_slab").with_(region=inputs.REGION_ALL_AT))
+    with pytest.raises(binding.AdresError):
+        at.set_tdforce(np.ones(8), 1.0, 3.0)
+    ctx.set_tdforce(np.ones(8), 1.0, 6.0)
+    with pytest.raises(binding.AdresError):
+        ctx.tdforce_update(counts, 0, 1.0)
