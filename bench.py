@@ -236,12 +236,13 @@ def hamiltonian_leg(wl, x, v, steps, warmup):
     }
 
 
-def tdforce_leg(wl, x, v, steps, n_iter=4, steps_per_iter=2000, sample_every=20, n_bins=28):
+def tdforce_leg(wl, x, v, steps, n_iter=8, steps_per_iter=10000, sample_every=50, n_bins=14,
+                equilibrate=40000):
     """Thermodynamic force (Sec. 2.4) on the same workload: a correction table over the
     hybrid layer plus one sigma on each side, refined n_iter times from density profiles
-    sampled every sample_every steps of a Langevin run (gamma 1, kT 1), with the
-    ideal-gas prefactor kT / (2 rho_0) (half of the step that would balance the measured
-    gradient of an ideal gas).  Reports the largest deviation |rho / rho_0 - 1| over the
+    sampled every sample_every steps of a Langevin run (gamma 1, kT 1) that first melts
+    the lattice start for `equilibrate` steps, with the ideal-gas prefactor kT / rho_0
+    (the force that balances a measured density gradient in an ideal gas).  Reports the largest deviation |rho / rho_0 - 1| over the
     bins before the first and after the last refinement (sampling noise included), the
     wall time per refinement cycle, the density-profile kernel's cost, and MD steps/s of
     the plain step with the final correction installed."""
@@ -257,9 +258,11 @@ def tdforce_leg(wl, x, v, steps, n_iter=4, steps_per_iter=2000, sample_every=20,
     h = (hi - lo) / n_bins
     vol = 2.0 * h * wl.box[1] * wl.box[2]
     counts = torch.zeros(n_bins, dtype=torch.int64, device="cuda")
-    devs = []
+    devs, devs_hy = [], []
+    centres = lo + (np.arange(n_bins) + 0.5) * h
+    hy = (centres > wl.d_at) & (centres < wl.d_at + wl.d_hy)
     seed = 7
-    ctx.integrate(xt, vt, ft, wl.dt, 500, gamma=1.0, kT=1.0, seed=seed)     # thermalise
+    ctx.integrate(xt, vt, ft, wl.dt, equilibrate, gamma=1.0, kT=1.0, seed=seed)   # melt the lattice
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     prof_s = 0.0
@@ -275,8 +278,9 @@ def tdforce_leg(wl, x, v, steps, n_iter=4, steps_per_iter=2000, sample_every=20,
             prof_s += time.perf_counter() - tp
         rho = counts.cpu().numpy() / (frames * vol)
         devs.append(float(np.abs(rho / rho0 - 1.0).max()))
+        devs_hy.append(float(np.abs(rho[hy] / rho0 - 1.0).max()))
         if it < n_iter:
-            ctx.tdforce_update(counts, frames, 1.0 / (2.0 * rho0))
+            ctx.tdforce_update(counts, frames, 1.0 / rho0)
     torch.cuda.synchronize()
     cycle_s = (time.perf_counter() - t0) / (n_iter + 1)
     table = ctx.get_tdforce()
@@ -294,6 +298,8 @@ def tdforce_leg(wl, x, v, steps, n_iter=4, steps_per_iter=2000, sample_every=20,
         "max_density_deviation_before": devs[0],
         "max_density_deviation_after": devs[-1],
         "max_density_deviation_per_iteration": devs,
+        "max_density_deviation_hybrid_bins_per_iteration": devs_hy,
+        "equilibration_steps": equilibrate,
         "seconds_per_iteration": cycle_s,
         "density_profile_call_us": 1e6 * prof_s / ((n_iter + 1) * (steps_per_iter // sample_every)),
         "steps_per_s_with_correction": sps,
