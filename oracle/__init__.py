@@ -95,6 +95,10 @@ def lib():
             L.orc_table_eval.restype = C.c_double
             L.orc_mlp_eval.argtypes = [P, C.c_double, C.POINTER(C.c_int)]
             L.orc_mlp_eval.restype = C.c_double
+            L.orc_forces_part.argtypes = [P, dp, dp, dp, dp, C.c_int]
+            L.orc_forces_part.restype = C.c_int
+            L.orc_respa.argtypes = [P, dp, dp, dp, C.c_double, C.c_int32, C.c_int32, dp]
+            L.orc_respa.restype = C.c_int
             L.orc_density_profile.argtypes = [P, dp, C.c_int32, C.c_double, C.c_double,
                                               C.POINTER(C.c_int64)]
             L.orc_density_profile.restype = C.c_int
@@ -217,6 +221,23 @@ class Model:
         f = np.empty_like(x); amag = np.empty(self.n_sites); e = np.zeros(4)
         st = lib().orc_forces(C.byref(self.p), _dp(x), _dp(f), _dp(amag), _dp(e))
         return f, amag, e, st
+
+    def forces_part(self, x, part):
+        """Forces of one part of the multiple-time-step split: 0 all, 1 fast (atomistic pair
+        part, -V^AT grad w, bonds), 2 slow (CG pair part, +V^CG grad w, correction)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        f = np.empty_like(x); amag = np.empty(self.n_sites); e = np.zeros(4)
+        st = lib().orc_forces_part(C.byref(self.p), _dp(x), _dp(f), _dp(amag), _dp(e), part)
+        return f, amag, e, st
+
+    def respa(self, x, v, dt, n_inner, n_outer):
+        """RESPA with inner step dt; returns (x, v, f_total, energies[(n_outer+1), 5], status)."""
+        x = np.array(x, dtype=np.float64, copy=True)
+        v = np.array(v, dtype=np.float64, copy=True)
+        f = np.empty_like(x)
+        e = np.zeros((n_outer + 1, 5))
+        st = lib().orc_respa(C.byref(self.p), _dp(x), _dp(v), _dp(f), dt, n_inner, n_outer, _dp(e))
+        return x, v, f, e, st
 
     def forces_sampled(self, x, sel):
         """Forces on the sites of molecules ``sel``: returns f (n_sel, 3, spm), amag (n_sel, spm)."""

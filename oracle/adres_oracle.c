@@ -28,7 +28,9 @@
  *   - a correction force on the centres of mass along the direction of resolution
  *     change, to flatten the density profile across the hybrid region: the
  *     thermodynamic force, built from the density profile and refined iteratively
- *     (Sec. 2.4).  Readings at orc_td_force and orc_tdforce_update.
+ *     (Sec. 2.4).  Readings at orc_td_force and orc_tdforce_update;
+ *   - multiple time stepping: the softer CG forces on a longer time step than the
+ *     atomistic ones, by RESPA (Sec. 2.6).  Reading at orc_respa.
  * Potentials (WCA, FENE, harmonic bonds), sizes and time steps are those of the
  * synthetic workloads; the readings taken where the paper is silent are listed
  * at each function.
@@ -48,6 +50,7 @@ enum { ORC_REGION_AT = 0, ORC_REGION_SLAB = 1, ORC_REGION_SPHERE = 2, ORC_REGION
 enum { ORC_CG_WCA = 0, ORC_CG_TABLE = 1, ORC_CG_MLP = 2 };
 enum { ORC_BOND_NONE = 0, ORC_BOND_HARMONIC = 1, ORC_BOND_FENE = 2 };
 enum { ORC_SCHEME_FORCE = 0, ORC_SCHEME_HAMILTONIAN = 1 };
+enum { ORC_PART_ALL = 0, ORC_PART_FAST = 1, ORC_PART_SLOW = 2 };
 
 typedef struct {
     int32_t n_mol, spm;
@@ -409,8 +412,12 @@ static double orc_cg_scale(const orc_params *P, double r2, double f_over_r)
  * rest), the four Horner terms of a table lookup, |f| (1 + r^2/R0^2)/(1 - r^2/R0^2)
  * for FENE; it bounds the rounding error of any evaluation order of the same
  * formulas, including sites whose net force is pure rounding noise. */
+/* part selects the terms for multiple time stepping (Sec. 2.6): ORC_PART_ALL every term;
+ * ORC_PART_FAST the atomistic pair part, the atomistic share -V^AT grad w of the drift and
+ * the bonds; ORC_PART_SLOW the CG pair part, the CG share +V^CG grad w of the drift and the
+ * correction force.  The energies are those of the included terms. */
 static int orc_mol_forces(const orc_params *P, const double *x, const double *com, const double *w,
-                          int64_t a, double *fa, double *amag, double e[4])
+                          int64_t a, double *fa, double *amag, double e[4], int part)
 {
     int status = 0;
     int spm = P->spm;
@@ -432,7 +439,7 @@ static int orc_mol_forces(const orc_params *P, const double *x, const double *co
         /* weight of the AT part of the pair force: Eq. (1) w_a w_b; Eq. (2) gives
          * -grad of (w_a V^AT_a + w_b V^AT_b), i.e. (w_a + w_b) / 2 per pair potential */
         double ww = hamiltonian ? 0.5 * (w[a] + w[b]) : w[a] * w[b];
-        if (ww > 0.0) {
+        if (ww > 0.0 && part != ORC_PART_SLOW) {
             for (int i = 0; i < spm; ++i) {
                 for (int j = 0; j < spm; ++j) {
                     double d[3];
@@ -456,7 +463,7 @@ static int orc_mol_forces(const orc_params *P, const double *x, const double *co
                 }
             }
         }
-        if (ww < 1.0) {
+        if (ww < 1.0 && part != ORC_PART_FAST) {
             double D[3];
             for (int q = 0; q < 3; ++q) D[q] = orc_mi(Ra[q] - com[q * n + b], P->box[q]);
             double r2 = (D[0] * D[0] + D[1] * D[1]) + D[2] * D[2];
@@ -496,7 +503,7 @@ static int orc_mol_forces(const orc_params *P, const double *x, const double *co
         }
     }
 
-    if (P->td_n > 0) {
+    if (P->td_n > 0 && part != ORC_PART_FAST) {
         double dir[3], ut, sc;
         double ft = orc_td_force(P, Ra, dir, &ut, &sc);
         for (int i = 0; i < spm; ++i) {
@@ -507,7 +514,9 @@ static int orc_mol_forces(const orc_params *P, const double *x, const double *co
         e[3] += ut;
     }
 
-    if (P->bond_kind == ORC_BOND_HARMONIC) {
+    if (part == ORC_PART_SLOW) {
+        /* no bonds in the slow part */
+    } else if (P->bond_kind == ORC_BOND_HARMONIC) {
         /* every pair of sites of the molecule is bonded: U = K/2 (r - b0)^2 */
         for (int i = 0; i < spm; ++i) {
             for (int k = 0; k < spm; ++k) {
@@ -551,7 +560,7 @@ static int orc_mol_forces(const orc_params *P, const double *x, const double *co
 /* Forces on every site (f: 3 x N_s SoA), absolute-sum scales (amag: N_s) and the
  * energies e[0..3] = U_AT, U_CG, U_bond, U_corr (the correction force's potential).
  * Returns the status bit mask. */
-int orc_forces(const orc_params *P, const double *x, double *f, double *amag, double *energy)
+int orc_forces_part(const orc_params *P, const double *x, double *f, double *amag, double *energy, int part)
 {
     int64_t n = P->n_mol, spm = P->spm, ns = n * spm;
     double *com = (double *)malloc(sizeof(double) * 3 * n);
@@ -561,7 +570,7 @@ int orc_forces(const orc_params *P, const double *x, double *f, double *amag, do
 #pragma omp parallel for schedule(dynamic, 16) reduction(| : status)
     for (int64_t a = 0; a < n; ++a) {
         double fa[3 * ORC_MAX_SITES], am[ORC_MAX_SITES];
-        status |= orc_mol_forces(P, x, com, w, a, fa, am, em + 4 * a);
+        status |= orc_mol_forces(P, x, com, w, a, fa, am, em + 4 * a, part);
         for (int i = 0; i < spm; ++i) {
             for (int q = 0; q < 3; ++q) f[q * ns + a * spm + i] = fa[3 * i + q];
             if (amag) amag[a * spm + i] = am[i];
@@ -576,6 +585,11 @@ int orc_forces(const orc_params *P, const double *x, double *f, double *amag, do
     return status;
 }
 
+int orc_forces(const orc_params *P, const double *x, double *f, double *amag, double *energy)
+{
+    return orc_forces_part(P, x, f, amag, energy, ORC_PART_ALL);
+}
+
 /* Forces on the sites of the selected molecules only (f: [n_sel][3][spm] ... stored as
  * f[(s * 3 + q) * spm + i]), same definition as orc_forces; O(n_mol) per molecule. */
 int orc_forces_sampled(const orc_params *P, const double *x, const int64_t *sel, int64_t n_sel,
@@ -588,7 +602,7 @@ int orc_forces_sampled(const orc_params *P, const double *x, const int64_t *sel,
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : status)
     for (int64_t s = 0; s < n_sel; ++s) {
         double fa[3 * ORC_MAX_SITES], am[ORC_MAX_SITES], e[4];
-        status |= orc_mol_forces(P, x, com, w, sel[s], fa, am, e);
+        status |= orc_mol_forces(P, x, com, w, sel[s], fa, am, e, ORC_PART_ALL);
         for (int i = 0; i < spm; ++i) {
             for (int q = 0; q < 3; ++q) f[(s * 3 + q) * spm + i] = fa[3 * i + q];
             if (amag) amag[s * spm + i] = am[i];
@@ -642,6 +656,66 @@ int orc_vv(const orc_params *P, double *x, double *v, double *f, double dt, int3
             r[4] = orc_kinetic(P, v);
         }
     }
+    return status;
+}
+
+/* Multiple time stepping (Sec. 2.6): reversible RESPA (Tuckerman, Berne & Martyna 1992)
+ * with the slow part (CG pair forces, the CG share of the drift, the correction force)
+ * on the outer step Dt = n_inner dt and the fast part (atomistic pair forces, the
+ * atomistic share of the drift, bonds) on the inner step dt.  One outer step:
+ *   v += F_slow Dt / (2m);
+ *   n_inner times: v += F_fast dt / (2m); x += v dt (folded); v += F_fast(x) dt / (2m);
+ *   v += F_slow(x) Dt / (2m).
+ * f returns the total force F_fast + F_slow at the final positions.  e_out (optional):
+ * (n_outer + 1) x 5 rows of U_AT, U_CG, U_bond, U_corr, KE after each outer step. */
+int orc_respa(const orc_params *P, double *x, double *v, double *f, double dt, int32_t n_inner,
+              int32_t n_outer, double *e_out)
+{
+    int64_t n = P->n_mol, spm = P->spm, ns = n * spm;
+    double Dt = dt * n_inner;
+    double *ff = (double *)malloc(sizeof(double) * 3 * ns);
+    double *fs = (double *)malloc(sizeof(double) * 3 * ns);
+    double e[4];
+    int status = orc_forces_part(P, x, ff, NULL, NULL, ORC_PART_FAST);
+    status |= orc_forces_part(P, x, fs, NULL, NULL, ORC_PART_SLOW);
+    if (e_out) {
+        status |= orc_forces(P, x, f, NULL, e);
+        for (int k = 0; k < 4; ++k) e_out[k] = e[k];
+        e_out[4] = orc_kinetic(P, v);
+    }
+    for (int32_t o = 0; o < n_outer; ++o) {
+        for (int q = 0; q < 3; ++q)
+            for (int64_t s = 0; s < ns; ++s)
+                v[q * ns + s] += fs[q * ns + s] * Dt / (2.0 * P->mass[s % spm]);
+        for (int32_t j = 0; j < n_inner; ++j) {
+            for (int q = 0; q < 3; ++q) {
+                double L = P->box[q];
+                for (int64_t s = 0; s < ns; ++s) {
+                    v[q * ns + s] += ff[q * ns + s] * dt / (2.0 * P->mass[s % spm]);
+                    double y = x[q * ns + s] + v[q * ns + s] * dt;
+                    if (y >= L) y -= L;
+                    else if (y < 0.0) y += L;
+                    x[q * ns + s] = y;
+                }
+            }
+            status |= orc_forces_part(P, x, ff, NULL, NULL, ORC_PART_FAST);
+            for (int q = 0; q < 3; ++q)
+                for (int64_t s = 0; s < ns; ++s)
+                    v[q * ns + s] += ff[q * ns + s] * dt / (2.0 * P->mass[s % spm]);
+        }
+        status |= orc_forces_part(P, x, fs, NULL, NULL, ORC_PART_SLOW);
+        for (int q = 0; q < 3; ++q)
+            for (int64_t s = 0; s < ns; ++s)
+                v[q * ns + s] += fs[q * ns + s] * Dt / (2.0 * P->mass[s % spm]);
+        if (e_out) {
+            status |= orc_forces(P, x, f, NULL, e);
+            double *r = e_out + 5 * (o + 1);
+            for (int k = 0; k < 4; ++k) r[k] = e[k];
+            r[4] = orc_kinetic(P, v);
+        }
+    }
+    for (int64_t k = 0; k < 3 * ns; ++k) f[k] = ff[k] + fs[k];
+    free(ff); free(fs);
     return status;
 }
 

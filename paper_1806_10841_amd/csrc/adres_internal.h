@@ -479,7 +479,7 @@ struct ForceArgs {
     StepArgs st;
     Ctrl *ctrl;
     int step, check_halt;
-    double *epart;                // non-null: per-block energy partials [blocks][3]
+    double *epart;                // non-null: per-block energy partials [blocks][4]
     const int *pid;               // learned CG force: pair id of every list entry
     const float *f_pair;          //   and the network's f(r) per pair
 };
@@ -489,7 +489,7 @@ int launch_forces(hipStream_t s, const ForceArgs &a, int pair_precision, hipEven
 int force_blocks(int n_mol);
 void launch_energy_reduce(hipStream_t s, const double *epart, int n_blocks, double *energy);
 
-// correction force (k_correction.hip)
+// correction force (k_state.hip)
 constexpr int kTdMaxBins = 4096;
 void launch_density_profile(hipStream_t s, const DevParams &P, const double *x, unsigned long long *counts);
 void launch_td_update(hipStream_t s, const DevParams &P, double *td, double *td_u, const long long *counts,

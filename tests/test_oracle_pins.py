@@ -618,3 +618,74 @@ class TestCorrectionForce:
         got2 = m.tdforce_update(F, lo, hi, counts2, frames, c)
         drho = 1 / (frames * (4.0 / 3.0) * np.pi * h ** 3)      # rho_k = (6 + k) drho
         np.testing.assert_allclose(got2, F - c * drho / h, rtol=1e-12)
+
+
+# ---------------------------------------------------------------- multiple time stepping (Sec. 2.6)
+class TestRespa:
+    """RESPA with the CG part on the outer step: the two parts add up to the full force,
+    each part vanishes where its model is absent, one inner step per outer step is
+    velocity Verlet, the integrator is time-reversible, and with the Hamiltonian scheme
+    it conserves energy to O(dt^2)."""
+
+    @pytest.mark.parametrize("name,scheme,td", [("tiny_slab", 0, False), ("small_sphere", 1, True),
+                                                ("tiny_slab", 1, True)])
+    def test_parts_add_up(self, name, scheme, td):
+        wl = inputs.workload(name).with_(scheme=scheme)
+        if name == "small_sphere":
+            wl = wl.with_(n_mol=216, box=((216 / 0.1) ** (1 / 3),) * 3, d_at=2.0, d_hy=3.0,
+                          center=(((216 / 0.1) ** (1 / 3)) / 2,) * 3)
+        tab = (np.linspace(0.5, -0.5, 9), 0.5, 3.5) if td else None
+        x, _ = inputs.make_state(wl, seed=3)
+        m = oracle.Model(wl, td=tab)
+        f, amag, e, _ = m.forces(x)
+        ff, _, _, _ = m.forces_part(x, 1)
+        fs, _, _, _ = m.forces_part(x, 2)
+        assert np.abs(ff).max() > 0 and np.abs(fs).max() > 0
+        assert np.all(np.abs(ff + fs - f) <= 8 * EPS * amag)
+
+    def test_each_part_vanishes_without_its_model(self):
+        wl = inputs.workload("tiny_slab").with_(region=inputs.REGION_ALL_AT)
+        x, _ = inputs.make_state(wl)
+        fs, _, _, _ = oracle.Model(wl).forces_part(x, 2)
+        assert np.all(fs == 0.0)
+        wl = inputs.workload("tiny_slab").with_(region=inputs.REGION_ALL_CG, bond_kind=inputs.BOND_NONE)
+        ff, _, _, _ = oracle.Model(wl).forces_part(x, 1)
+        assert np.all(ff == 0.0)
+
+    def test_single_inner_step_is_velocity_verlet(self):
+        wl = inputs.workload("tiny_slab")
+        x, v = inputs.make_state(wl)
+        m = oracle.Model(wl)
+        x1, v1, f1, _, _ = m.vv(x, v, wl.dt, 20)
+        x2, v2, f2, _, _ = m.respa(x, v, wl.dt, 1, 20)
+        np.testing.assert_allclose(x2, x1, atol=1e-11)
+        np.testing.assert_allclose(v2, v1, atol=1e-9)
+        np.testing.assert_allclose(f2, f1, atol=1e-7 * np.abs(f1).max())
+        # and a longer outer step is a different integrator
+        x3, _, _, _, _ = m.respa(x, v, wl.dt / 2, 2, 20)
+        x4, _, _, _, _ = m.vv(x, v, wl.dt / 2, 40)
+        assert np.abs(x3 - x4).max() > 1e-9
+
+    def test_time_reversible(self):
+        wl = inputs.workload("tiny_slab").with_(scheme=inputs.SCHEME_HAMILTONIAN)
+        x, v = inputs.make_state(wl)
+        m = oracle.Model(wl)
+        x1, v1, _, _, st = m.respa(x, v, 0.002, 3, 15)
+        assert st == 0
+        x2, v2, _, _, _ = m.respa(x1, -v1, 0.002, 3, 15)
+        d = x2 - x
+        d -= np.asarray(wl.box)[:, None] * np.round(d / np.asarray(wl.box)[:, None])
+        assert np.abs(d).max() < 1e-9
+        assert np.abs(v2 + v).max() < 1e-8
+
+    def test_hamiltonian_energy_error_is_dt2(self):
+        wl = inputs.workload("tiny_slab").with_(scheme=inputs.SCHEME_HAMILTONIAN)
+        x, v = inputs.make_state(wl)
+        m = oracle.Model(wl)
+        _, _, _, e1, st = m.respa(x, v, 0.002, 2, 50)
+        _, _, _, e2, _ = m.respa(x, v, 0.001, 2, 100)
+        assert st == 0
+        t1, t2 = e1.sum(axis=1), e2.sum(axis=1)
+        f1, f2 = np.abs(t1 - t1[0]).max(), np.abs(t2 - t2[0]).max()
+        assert f1 < 5e-3 * abs(t1[0]) + 1e-2
+        assert 2.5 < f1 / f2 < 6.0, (f1, f2)
