@@ -53,6 +53,8 @@ def main():
                     help="skip the potential-energy-interpolation (Eq. (2)) leg")
     ap.add_argument("--no-tdforce", action="store_true",
                     help="skip the thermodynamic-force (correction field) leg")
+    ap.add_argument("--no-respa", action="store_true",
+                    help="skip the multiple-time-stepping (RESPA) leg")
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes 10 times "
@@ -172,6 +174,8 @@ def main():
         out["hamiltonian_scheme"] = hamiltonian_leg(wl, x, v, args.steps, args.warmup)
     if not args.no_tdforce:
         out["thermodynamic_force"] = tdforce_leg(wl, x, v, args.steps)
+    if not args.no_respa:
+        out["respa"] = respa_leg(wl, x, v, args.steps, args.warmup, steps_per_s)
     if not args.no_cg_compare:
         out["learned_vs_tabulated"] = learned_vs_tabulated(args.cg_steps)
 
@@ -234,6 +238,43 @@ def hamiltonian_leg(wl, x, v, steps, warmup):
         "total_energy_end": e1,
         "energy_drift_per_molecule": (e1 - e0) / wh.n_mol,
     }
+
+
+def respa_leg(wl, x, v, steps, warmup, vv_steps_per_s):
+    """Multiple time stepping (Sec. 2.6) on the same workload: the CG part of Eq. (1) on
+    an outer step of n_inner inner steps (dt 0.005), the atomistic part and bonds on every
+    inner step.  Reports inner MD steps/s for n_inner = 2 and 4 (the same simulated time
+    per step as the headline) and the ratio to plain velocity Verlet, with the analytic CG
+    force and with a learned CG force (a randomly initialised network of the library's
+    architecture, scale 1, evaluated on BF16 matrix cores; the network is the costly part
+    that the outer step saves)."""
+    import torch
+    from paper_1806_10841_amd import binding, inputs
+    out = {}
+    for cg in ("wca", "mlp"):
+        wk = wl if cg == "wca" else wl.with_(cg_kind=inputs.CG_MLP)
+        base = vv_steps_per_s if cg == "wca" else None
+        for n_inner in ((2, 4) if cg == "wca" else (1, 2, 4)):
+            ctx = binding.Context(wk)
+            if cg == "mlp":
+                ctx.mlp_set(inputs.mlp_init(12).astype(np.float32), wk.rc_cg, 1.0, 0.5, 0.0)
+            xt = torch.tensor(x, device="cuda")
+            vt = torch.tensor(v, device="cuda")
+            ft = torch.empty_like(xt)
+            ctx.integrate_respa(xt, vt, ft, wk.dt, n_inner, max(warmup // n_inner, 1))
+            torch.cuda.synchronize()
+            n_outer = max(steps // n_inner, 1)
+            t0 = time.perf_counter()
+            nreb = ctx.integrate_respa(xt, vt, ft, wk.dt, n_inner, n_outer)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            ctx.close()
+            sps = n_outer * n_inner / el
+            if base is None:
+                base = sps          # n_inner = 1 of the learned CG force is its VV
+            out[f"{cg}_n_inner_{n_inner}"] = {"inner_steps_per_s": sps, "speedup_vs_vv": sps / base,
+                                              "list_rebuilds": nreb}
+    return out
 
 
 def tdforce_leg(wl, x, v, steps, n_iter=8, steps_per_iter=10000, sample_every=50, n_bins=14,

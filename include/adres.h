@@ -152,6 +152,23 @@ adres_status adres_integrate(adres_ctx *ctx, double *x, double *v, double *f, do
                              int32_t n_steps, double gamma, double kT, uint64_t seed,
                              int32_t *n_rebuilds);
 
+/* Multiple time stepping (Sec. 2.6): reversible RESPA (Tuckerman, Berne & Martyna 1992)
+ * with n_outer outer steps of Dt = n_inner dt.  The slow part -- the CG pair part of the
+ * coupling, the CG share +V^CG grad w of the Hamiltonian scheme's drift and the correction
+ * force -- acts on the outer step; the fast part -- the atomistic pair part, the share
+ * -V^AT grad w of the drift and the bonds -- on the inner step dt.  One outer step:
+ * v += F_slow Dt/2m; n_inner times {v += F_fast dt/2m; x += v dt; fold; v += F_fast(x) dt/2m};
+ * v += F_slow(x) Dt/2m.  The slow part is evaluated once per outer step (the CG pair work
+ * and, for a learned CG force, the network are skipped on the other inner steps).
+ * n_inner = 1 is adres_integrate.  x, v (device, caller order) are updated in place; f
+ * receives the total force at the final positions.  gamma > 0 applies the Langevin
+ * thermostat of adres_integrate at every inner step.  n_rebuilds as for adres_integrate.
+ * ADRES_E_ARG unless n_inner >= 1, n_outer >= 0, n_inner n_outer < 2^31, dt > 0.
+ * Synchronises at every list rebuild and at the end. */
+adres_status adres_integrate_respa(adres_ctx *ctx, double *x, double *v, double *f, double dt,
+                                   int32_t n_inner, int32_t n_outer, double gamma, double kT,
+                                   uint64_t seed, int32_t *n_rebuilds);
+
 /* Copy out the current Verlet list as unordered caller-index pairs (a < b), sorted
  * lexicographically, into pairs_host (host, [cap][2] int32).  *n receives the pair
  * count even when it exceeds cap.  Synchronises. */

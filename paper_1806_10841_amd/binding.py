@@ -58,6 +58,8 @@ _SIGS = {
     "adres_forces": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "adres_integrate": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
                          C.c_double, C.c_double, C.c_uint64, C.POINTER(C.c_int32)], C.c_int),
+    "adres_integrate_respa": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_int32,
+                               C.c_double, C.c_double, C.c_uint64, C.POINTER(C.c_int32)], C.c_int),
     "adres_get_pairs": ([C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
     "adres_get_cells": ([C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)], C.c_int),
     "adres_set_cg_table": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double], C.c_int),
@@ -182,6 +184,13 @@ class Context:
         e = torch.zeros(4, dtype=torch.float64, device=x.device) if energy else None
         self._check(self.lib.adres_forces(self.h, _ptr(x), _ptr(f), _ptr(e)), "adres_forces")
         return (f, e) if energy else f
+
+    def integrate_respa(self, x, v, f, dt, n_inner, n_outer, gamma=0.0, kT=1.0, seed=0):
+        nreb = C.c_int32()
+        st = self.lib.adres_integrate_respa(self.h, _ptr(x), _ptr(v), _ptr(f), dt, n_inner, n_outer, gamma, kT,
+                                            seed, C.byref(nreb))
+        self._check(st, "adres_integrate_respa")
+        return nreb.value
 
     def integrate(self, x, v, f, dt, n_steps, gamma=0.0, kT=1.0, seed=0):
         nreb = C.c_int32()

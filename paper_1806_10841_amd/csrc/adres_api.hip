@@ -282,6 +282,7 @@ ForceArgs force_args(adres_ctx *c)
     a.inv_perm = c->inv_perm;
     a.ctrl = c->ctrl;
     a.mode = kModeForce;
+    a.slow_scale = 1.0;
     return a;
 }
 
@@ -307,12 +308,14 @@ adres_status run_forces(adres_ctx *c, ForceArgs a)
         e1 = c->events[c->events_used].second;
         ++c->events_used;
     }
-    if (is_mlp(c)) {
+    if (is_mlp(c) && a.slow_scale != 0.0) {
         if (sample && c->timing == 2) HIPCHK(c, hipEventRecord(e0, c->stream));
         launch_mlp_forward_pairs(c->stream, mlp_dev(c), c->P, c->up_pairs, a.Rw, c->f_pair, c->up_off + c->P.n_mol,
                                  c->half_pairs_cap, c->ctrl, a.check_halt, a.step);
         HIPCHK(c, hipGetLastError());
         if (sample && c->timing == 2) HIPCHK(c, hipEventRecord(e1, c->stream));
+    }
+    if (is_mlp(c)) {
         a.pid = c->pid;
         a.f_pair = c->f_pair;
     }
@@ -599,20 +602,27 @@ adres_status adres_forces(adres_ctx *c, const double *x, double *f, double *ener
     return ADRES_OK;
 }
 
-adres_status adres_integrate(adres_ctx *c, double *x, double *v, double *f, double dt, int32_t n_steps,
-                             double gamma, double kT, uint64_t seed, int32_t *n_rebuilds)
+namespace {
+
+// Velocity Verlet (n_inner = 1) or RESPA with n_inner inner steps of dt per outer step
+// (n_steps a multiple of n_inner).  In RESPA the half kicks of the slow part at the end
+// of one outer step and the start of the next meet at the same positions, as do the fast
+// part's half kicks at every inner boundary, so every kernel g kicks with
+// F_fast + s_g F_slow: s_g = n_inner at outer boundaries (g a multiple of n_inner), else 0
+// (the slow part is then not computed).  n_inner = 1 gives s_g = 1: plain VV.
+adres_status integrate_impl(adres_ctx *c, double *x, double *v, double *f, double dt, int32_t n_steps,
+                            int32_t n_inner, double gamma, double kT, uint64_t seed, int32_t *n_rebuilds)
 {
-    if (!c || !x || !v || !f) return fail(c, ADRES_E_ARG, "null argument");
-    if (n_steps < 0 || !(dt > 0.0) || gamma < 0.0 || (gamma > 0.0 && !(kT >= 0.0)))
-        return fail(c, ADRES_E_ARG, "invalid dt, n_steps, gamma or kT");
     adres_status st = check_cg_ready(c);
     if (st != ADRES_OK) return st;
     st = full_build(c, x, v);
     if (st != ADRES_OK) return st;
+    auto slow_scale = [n_inner](int g) { return g % n_inner == 0 ? (double)n_inner : 0.0; };
 
     // F(x_0) into the Morton-ordered force buffer
     ForceArgs a0 = force_args(c);
     a0.f = c->f;
+    a0.slow_scale = slow_scale(0);
     st = run_forces(c, a0);
     if (st != ADRES_OK) return st;
 
@@ -648,6 +658,7 @@ adres_status adres_integrate(adres_ctx *c, double *x, double *v, double *f, doub
                 a.st = sa;
                 a.step = k;
                 a.check_halt = 1;
+                a.slow_scale = slow_scale(gk);
                 if (gk < n_steps) {
                     a.mode = kModeStep;
                     a.x_out = out.x;
@@ -690,12 +701,40 @@ adres_status adres_integrate(adres_ctx *c, double *x, double *v, double *f, doub
         since = 0;
     }
     c->step_counter += (uint64_t)n_steps;
+    if (n_inner > 1) {
+        // the closing kernel kicked with F_fast + n_inner F_slow; report the total force
+        ForceArgs af = force_args(c);
+        af.f = c->f;
+        st = run_forces(c, af);
+        if (st != ADRES_OK) return st;
+    }
     const StateBufs fin = cur(c);
     launch_scatter_out(c->stream, c->P, fin.perm, fin.x, fin.v, c->f, x, v, f);
     HIPCHK(c, hipGetLastError());
     st = read_ctrl(c);
     if (n_rebuilds) *n_rebuilds = rebuilds;
     return st;
+}
+
+}  // namespace
+
+adres_status adres_integrate(adres_ctx *c, double *x, double *v, double *f, double dt, int32_t n_steps,
+                             double gamma, double kT, uint64_t seed, int32_t *n_rebuilds)
+{
+    if (!c || !x || !v || !f) return fail(c, ADRES_E_ARG, "null argument");
+    if (n_steps < 0 || !(dt > 0.0) || gamma < 0.0 || (gamma > 0.0 && !(kT >= 0.0)))
+        return fail(c, ADRES_E_ARG, "invalid dt, n_steps, gamma or kT");
+    return integrate_impl(c, x, v, f, dt, n_steps, 1, gamma, kT, seed, n_rebuilds);
+}
+
+adres_status adres_integrate_respa(adres_ctx *c, double *x, double *v, double *f, double dt, int32_t n_inner,
+                                   int32_t n_outer, double gamma, double kT, uint64_t seed, int32_t *n_rebuilds)
+{
+    if (!c || !x || !v || !f) return fail(c, ADRES_E_ARG, "null argument");
+    if (n_inner < 1 || n_outer < 0 || (int64_t)n_inner * n_outer > INT32_MAX || !(dt > 0.0) || gamma < 0.0 ||
+        (gamma > 0.0 && !(kT >= 0.0)))
+        return fail(c, ADRES_E_ARG, "invalid dt, n_inner, n_outer, gamma or kT");
+    return integrate_impl(c, x, v, f, dt, n_inner * n_outer, n_inner, gamma, kT, seed, n_rebuilds);
 }
 
 adres_status adres_get_pairs(adres_ctx *c, int32_t *pairs_host, int64_t cap, int64_t *n)

@@ -482,6 +482,9 @@ struct ForceArgs {
     double *epart;                // non-null: per-block energy partials [blocks][4]
     const int *pid;               // learned CG force: pair id of every list entry
     const float *f_pair;          //   and the network's f(r) per pair
+    // multiple time stepping: the slow part (CG pair part, the CG share of the drift, the
+    // correction force) enters the force with this factor; 0 skips it (inner steps)
+    double slow_scale;
 };
 // returns the block count; e0/e1 (optional) are recorded at the kernel's start and end
 int launch_forces(hipStream_t s, const ForceArgs &a, int pair_precision, hipEvent_t e0 = nullptr,

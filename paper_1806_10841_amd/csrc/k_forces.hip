@@ -144,6 +144,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     const PT sig2C = (PT)P.sig2_cg, epsC = (PT)P.eps_cg;
     const int cnt = valid ? a.cnt[tt] : 0;
     const int *row = a.nbr + (int64_t)tt * a.cap;
+    const bool with_slow = a.slow_scale != 0.0;
 
     for (int k0 = kPre * q; k0 < cnt; k0 += kPre * kLanes) {
         int us[kPre];
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                     }
                 }
             }
-            if (ww < 1.0 && r2c < P.rcC2) {
+            if (with_slow && ww < 1.0 && r2c < P.rcC2) {
                 PT uu = PT(0);
                 PT fr;
                 if (P.cg_kind == ADRES_CG_WCA) {
@@ -283,7 +284,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
 
     // correction force on the centre of mass along the resolution coordinate (Sec. 2.4)
     double tdir[3] = {0.0, 0.0, 0.0}, ucorr = 0.0, ftd = 0.0;
-    if (P.td_n > 0) {
+    if (P.td_n > 0 && with_slow) {
         const double Rm[3] = {me.x, me.y, me.z};
         ftd = corr_force<ENERGY>(P, Rm, tdir, ucorr);
     }
@@ -295,18 +296,19 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     for (int i = 0; i < SPM; ++i)
         if (i == q) {
             const double mf = P.mfrac[i];
-            F[0] = acc[i][0] + mf * cg0;
-            F[1] = acc[i][1] + mf * cg1;
-            F[2] = acc[i][2] + mf * cg2;
+            const double ss = a.slow_scale;
+            F[0] = acc[i][0] + mf * (ss * cg0);
+            F[1] = acc[i][1] + mf * (ss * cg1);
+            F[2] = acc[i][2] + mf * (ss * cg2);
             if (hy_home) {
                 // drift force of Eq. (2): -(V^AT - V^CG) grad w(R), grad_x R = m_i / M
-                const double dv = -(vat - vcg) * mf;
+                const double dv = -(vat - ss * vcg) * mf;
                 F[0] += dv * gw[0];
                 F[1] += dv * gw[1];
                 F[2] += dv * gw[2];
             }
             if (P.td_n > 0) {
-                const double ft = mf * ftd;
+                const double ft = mf * (ss * ftd);
                 F[0] += ft * tdir[0];
                 F[1] += ft * tdir[1];
                 F[2] += ft * tdir[2];
