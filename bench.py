@@ -246,10 +246,10 @@ def respa_leg(wl, x, v, steps, warmup, vv_steps_per_s):
     inner step.  Reports inner MD steps/s for n_inner = 2 and 4 (the same simulated time
     per step as the headline) and the ratio to plain velocity Verlet, with the analytic CG
     force and with a learned CG force (a randomly initialised network of the library's
-    architecture, scale 1, evaluated on BF16 matrix cores; the network is the costly part
-    that the outer step saves)."""
+    architecture, scale 0.3, above r = 2.2 with the plain CG force's table below, evaluated
+    on BF16 matrix cores; the network is the costly part that the outer step saves)."""
     import torch
-    from paper_1806_10841_amd import binding, inputs
+    from paper_1806_10841_amd import binding, cgtrain, inputs
     out = {}
     for cg in ("wca", "mlp"):
         wk = wl if cg == "wca" else wl.with_(cg_kind=inputs.CG_MLP)
@@ -257,7 +257,10 @@ def respa_leg(wl, x, v, steps, warmup, vv_steps_per_s):
         for n_inner in ((2, 4) if cg == "wca" else (1, 2, 4)):
             ctx = binding.Context(wk)
             if cg == "mlp":
-                ctx.mlp_set(inputs.mlp_init(12).astype(np.float32), wk.rc_cg, 1.0, 0.5, 0.0)
+                # the plain CG force as the table below r_min = 2.2 (the repulsive core), the
+                # network from there to the cutoff
+                ctx.set_cg_table(*cgtrain.wca_table())
+                ctx.mlp_set(inputs.mlp_init(12).astype(np.float32), wk.rc_cg, 0.3, 0.3, 2.2)
             xt = torch.tensor(x, device="cuda")
             vt = torch.tensor(v, device="cuda")
             ft = torch.empty_like(xt)
