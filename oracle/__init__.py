@@ -64,6 +64,7 @@ class Params(C.Structure):
         ("scheme", C.c_int32),
         ("td", C.POINTER(C.c_double)), ("td_n", C.c_int32),
         ("td_lo", C.c_double), ("td_hi", C.c_double),
+        ("anchors", C.POINTER(C.c_int32)), ("n_anchors", C.c_int32),
     ]
 
 
@@ -120,9 +121,9 @@ class Model:
     ``wl`` is any object with the attributes of ``inputs.Workload``.  ``table`` is
     (coef float32 [(n-1), 4], r_lo, r_hi); ``mlp`` is (params float64, rc, scale,
     taper_width, r_min); ``td`` is the correction force (values float64 [n] at the bin
-    centres, lo, hi)."""
+    centres, lo, hi); ``anchors`` the anchor molecules of a self-adjusting region."""
 
-    def __init__(self, wl, table=None, mlp=None, hidden=64, td=None):
+    def __init__(self, wl, table=None, mlp=None, hidden=64, td=None, anchors=None):
         self.wl = wl
         p = Params()
         p.n_mol, p.spm = wl.n_mol, wl.sites_per_mol
@@ -162,6 +163,11 @@ class Model:
             p.td = _dp(F)
             p.td_n = len(F)
             p.td_lo, p.td_hi = lo, hi
+        if anchors is not None:
+            an = np.ascontiguousarray(anchors, dtype=np.int32)
+            self._keep.append(an)
+            p.anchors = an.ctypes.data_as(C.POINTER(C.c_int32))
+            p.n_anchors = len(an)
         self.p = p
         self.n_sites = wl.n_mol * wl.sites_per_mol
 

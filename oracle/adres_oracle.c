@@ -30,7 +30,9 @@
  *     thermodynamic force, built from the density profile and refined iteratively
  *     (Sec. 2.4).  Readings at orc_td_force and orc_tdforce_update;
  *   - multiple time stepping: the softer CG forces on a longer time step than the
- *     atomistic ones, by RESPA (Sec. 2.6).  Reading at orc_respa.
+ *     atomistic ones, by RESPA (Sec. 2.6).  Reading at orc_respa;
+ *   - self-adjusting AT regions: spheres around moving anchors whose overlap is the AT
+ *     region (Sec. 2.5), with force interpolation.  Reading at orc_anchor_distance.
  * Potentials (WCA, FENE, harmonic bonds), sizes and time steps are those of the
  * synthetic workloads; the readings taken where the paper is silent are listed
  * at each function.
@@ -46,7 +48,7 @@
 #define ORC_MAX_SITES 8
 
 enum { ORC_OK = 0, ORC_STRETCH = 1, ORC_FENE = 2, ORC_TABLE_RANGE = 4, ORC_NONFINITE = 8 };
-enum { ORC_REGION_AT = 0, ORC_REGION_SLAB = 1, ORC_REGION_SPHERE = 2, ORC_REGION_CG = 3 };
+enum { ORC_REGION_AT = 0, ORC_REGION_SLAB = 1, ORC_REGION_SPHERE = 2, ORC_REGION_CG = 3, ORC_REGION_SPHERES = 4 };
 enum { ORC_CG_WCA = 0, ORC_CG_TABLE = 1, ORC_CG_MLP = 2 };
 enum { ORC_BOND_NONE = 0, ORC_BOND_HARMONIC = 1, ORC_BOND_FENE = 2 };
 enum { ORC_SCHEME_FORCE = 0, ORC_SCHEME_HAMILTONIAN = 1 };
@@ -79,6 +81,10 @@ typedef struct {
     const double *td;
     int32_t td_n;
     double td_lo, td_hi;
+    /* ORC_REGION_SPHERES: the AT region is the union of spheres of radius d_at (hybrid
+     * shell d_hy) around the centres of mass of these molecules (Sec. 2.5) */
+    const int32_t *anchors;
+    int32_t n_anchors;
 } orc_params;
 
 /* Minimum image of one coordinate difference (periodic orthorhombic box).
@@ -240,6 +246,25 @@ static double orc_weight(const orc_params *P, const double R[3])
 }
 
 /* Centres of mass (3 x n_mol, SoA), weights (n_mol) and the stretch flag. */
+/* Self-adjusting AT region (Sec. 2.5): spheres around the current centres of mass of the
+ * anchor molecules, whose overlap forms the AT region.  Reading: a molecule's resolution
+ * distance is its minimum-image distance to the nearest anchor centre, d = min_k |R - R_k|,
+ * and w = w(d); since w falls with d this is the largest of the single-sphere weights (the
+ * union of the spheres).  The anchors move with the simulation, so the region follows. */
+static double orc_anchor_distance(const orc_params *P, const double *com, int64_t a)
+{
+    int64_t n = P->n_mol;
+    double best = INFINITY;
+    for (int32_t k = 0; k < P->n_anchors; ++k) {
+        int64_t b = P->anchors[k];
+        double q[3];
+        for (int d = 0; d < 3; ++d) q[d] = orc_mi(com[d * n + a] - com[d * n + b], P->box[d]);
+        double r2 = (q[0] * q[0] + q[1] * q[1]) + q[2] * q[2];
+        if (r2 < best) best = r2;
+    }
+    return sqrt(best);
+}
+
 int orc_weights(const orc_params *P, const double *x, double *com, double *w, double *rho_out)
 {
     int status = 0;
@@ -249,9 +274,14 @@ int orc_weights(const orc_params *P, const double *x, double *com, double *w, do
         double R[3], rho;
         orc_com(P, x, a, R, &rho);
         for (int d = 0; d < 3; ++d) com[d * n + a] = R[d];
-        w[a] = orc_weight(P, R);
+        if (P->region != ORC_REGION_SPHERES) w[a] = orc_weight(P, R);
         if (rho_out) rho_out[a] = rho;
         if (P->spm > 1 && rho > P->rho_max) status |= ORC_STRETCH;
+    }
+    if (P->region == ORC_REGION_SPHERES) {
+#pragma omp parallel for schedule(static)
+        for (int64_t a = 0; a < n; ++a)
+            w[a] = orc_weight_of_distance(orc_anchor_distance(P, com, a), P->d_at, P->d_hy);
     }
     return status;
 }

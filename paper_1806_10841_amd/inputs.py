@@ -35,6 +35,7 @@ REGION_ALL_AT = 0   # w == 1 everywhere (plain atomistic MD)
 REGION_SLAB_X = 1   # AT slab centred at box centre, normal along x
 REGION_SPHERE = 2   # AT sphere centred at the box centre
 REGION_ALL_CG = 3   # w == 0 everywhere (plain coarse-grained MD)
+REGION_SPHERES = 4  # AT region = union of spheres around the centres of anchor molecules
 
 CG_WCA = 0      # analytic WCA between centres of mass
 CG_TABLE = 1    # cubic-spline table of the CG force
@@ -261,6 +262,12 @@ def make_state(wl: Workload, seed: int | None = None):
     x = wrap_into_box(x, box)
     v = maxwell_velocities(n_sites, masses, wl.kT, rng)
     return np.ascontiguousarray(x), np.ascontiguousarray(v)
+
+
+def anchor_molecules(n_mol, k, seed):
+    """k distinct molecule indices (sorted): the anchors of a self-adjusting AT region."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n_mol, size=k, replace=False)).astype(np.int32)
 
 
 def random_pair_distances(n, r_lo, r_hi, seed):

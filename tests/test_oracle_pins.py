@@ -689,3 +689,62 @@ class TestRespa:
         f1, f2 = np.abs(t1 - t1[0]).max(), np.abs(t2 - t2[0]).max()
         assert f1 < 5e-3 * abs(t1[0]) + 1e-2
         assert 2.5 < f1 / f2 < 6.0, (f1, f2)
+
+
+# ---------------------------------------------------------------- self-adjusting regions (Sec. 2.5)
+class TestAnchorSpheres:
+    """The AT region as the union of spheres around anchor molecules: one anchor is exactly
+    a static sphere centred at its centre of mass, several anchors give the largest of the
+    single-sphere weights, anchors are atomistic, and the region follows the anchors."""
+
+    def _wl(self):
+        return inputs.workload("small_sphere").with_(region=inputs.REGION_SPHERES, d_at=2.5, d_hy=2.0)
+
+    def test_one_anchor_is_a_static_sphere(self):
+        wl = self._wl()
+        x, _ = inputs.make_state(wl)
+        an = np.array([417], dtype=np.int32)
+        m = oracle.Model(wl, anchors=an)
+        com, w, _, st = m.weights(x)
+        assert st == 0
+        ws = wl.with_(region=inputs.REGION_SPHERE, center=tuple(com[:, 417]))
+        com2, w2, _, _ = oracle.Model(ws).weights(x)
+        np.testing.assert_array_equal(w, w2)
+        assert ((w > 0) & (w < 1)).any() and (w == 1).sum() > 1
+        f1, _, e1, _ = m.forces(x)
+        f2, _, e2, _ = oracle.Model(ws).forces(x)
+        np.testing.assert_array_equal(f1, f2)
+
+    def test_several_anchors_take_the_largest_weight(self):
+        wl = self._wl()
+        x, _ = inputs.make_state(wl)
+        an = inputs.anchor_molecules(wl.n_mol, 9, 3)
+        com, w, _, _ = oracle.Model(wl, anchors=an).weights(x)
+        single = []
+        for a in an:
+            ws = wl.with_(region=inputs.REGION_SPHERE, center=tuple(com[:, a]))
+            single.append(oracle.Model(ws).weights(x)[1])
+        np.testing.assert_array_equal(w, np.max(single, axis=0))
+        assert np.all(w[an] == 1.0)
+
+    def test_region_follows_the_anchor(self):
+        wl = self._wl()
+        x, _ = inputs.make_state(wl)
+        an = np.array([100], dtype=np.int32)
+        m = oracle.Model(wl, anchors=an)
+        _, w0, _, _ = m.weights(x)
+        x2 = x.copy()
+        x2[:, 400:404] += np.array([[3.0], [-2.0], [1.0]])      # move anchor 100 (sites 400..403)
+        x2 = inputs.wrap_into_box(x2, wl.box)
+        com2, w2, _, _ = m.weights(x2)
+        ws = wl.with_(region=inputs.REGION_SPHERE, center=tuple(com2[:, 100]))
+        np.testing.assert_array_equal(w2, oracle.Model(ws).weights(x2)[1])
+        assert not np.array_equal(w0, w2)
+
+    def test_newton3_with_anchor_spheres(self):
+        wl = self._wl()
+        x, _ = inputs.make_state(wl)
+        an = inputs.anchor_molecules(wl.n_mol, 5, 1)
+        f, amag, _, st = oracle.Model(wl, anchors=an).forces(x)
+        assert st == 0
+        assert np.all(np.abs(f.sum(axis=1)) <= 64 * EPS * amag.sum())
