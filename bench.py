@@ -55,6 +55,8 @@ def main():
                     help="skip the thermodynamic-force (correction field) leg")
     ap.add_argument("--no-respa", action="store_true",
                     help="skip the multiple-time-stepping (RESPA) leg")
+    ap.add_argument("--no-anchors", action="store_true",
+                    help="skip the self-adjusting (anchor spheres) region leg")
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes 10 times "
@@ -176,6 +178,8 @@ def main():
         out["thermodynamic_force"] = tdforce_leg(wl, x, v, args.steps)
     if not args.no_respa:
         out["respa"] = respa_leg(wl, x, v, args.steps, args.warmup, steps_per_s)
+    if not args.no_anchors:
+        out["self_adjusting_region"] = anchors_leg(wl, x, v, args.steps, args.warmup)
     if not args.no_cg_compare:
         out["learned_vs_tabulated"] = learned_vs_tabulated(args.cg_steps)
 
@@ -238,6 +242,35 @@ def hamiltonian_leg(wl, x, v, steps, warmup):
         "total_energy_end": e1,
         "energy_drift_per_molecule": (e1 - e0) / wh.n_mol,
     }
+
+
+def anchors_leg(wl, x, v, steps, warmup, counts=(16, 256)):
+    """Self-adjusting AT region (Sec. 2.5) on the same molecules: the union of spheres
+    (radius 4, hybrid shell 3) around k anchor molecules that move with the simulation,
+    weights recomputed from the nearest anchor after every step.  MD steps/s per k."""
+    import torch
+    from paper_1806_10841_amd import binding, inputs
+    out = {}
+    for k in counts:
+        wk = wl.with_(region=inputs.REGION_SPHERES, d_at=4.0, d_hy=3.0)
+        ctx = binding.Context(wk)
+        ctx.set_anchors(inputs.anchor_molecules(wk.n_mol, k, 5))
+        xt = torch.tensor(x, device="cuda")
+        vt = torch.tensor(v, device="cuda")
+        ft = torch.empty_like(xt)
+        ctx.integrate(xt, vt, ft, wk.dt, warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nreb = ctx.integrate(xt, vt, ft, wk.dt, steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        _, w = ctx.weights(xt)
+        wn = w.cpu().numpy()
+        ctx.close()
+        out[f"anchors_{k}"] = {"steps_per_s": steps / el, "list_rebuilds": nreb,
+                               "fraction_at": float((wn == 1.0).mean()),
+                               "fraction_hybrid": float(((wn > 0) & (wn < 1)).mean())}
+    return out
 
 
 def respa_leg(wl, x, v, steps, warmup, vv_steps_per_s):

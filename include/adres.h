@@ -59,7 +59,11 @@ typedef enum {
     ADRES_E_STATE = -10        /* call out of order (e.g. MLP kind without weights) */
 } adres_status;
 
-enum { ADRES_REGION_ALL_AT = 0, ADRES_REGION_SLAB_X = 1, ADRES_REGION_SPHERE = 2, ADRES_REGION_ALL_CG = 3 };
+/* ADRES_REGION_SPHERES: a self-adjusting AT region (Sec. 2.5), the union of spheres of radius
+ * d_at (hybrid shell d_hy) around the current centres of mass of anchor molecules chosen with
+ * adres_set_anchors; the region moves with them.  Force interpolation only. */
+enum { ADRES_REGION_ALL_AT = 0, ADRES_REGION_SLAB_X = 1, ADRES_REGION_SPHERE = 2, ADRES_REGION_ALL_CG = 3,
+       ADRES_REGION_SPHERES = 4 };
 /* CG force between centres of mass: analytic WCA, cubic table, learned network with layer 2
  * on BF16 matrix cores, or its FP8 variant (inference only; see adres_mlp_set). */
 enum { ADRES_CG_WCA = 0, ADRES_CG_TABLE = 1, ADRES_CG_MLP = 2, ADRES_CG_MLP_FP8 = 3 };
@@ -75,9 +79,9 @@ typedef struct {
     int32_t sites_per_mol;      /* 1 .. ADRES_MAX_SITES */
     double  box[3];             /* periodic box lengths */
     double  site_mass[ADRES_MAX_SITES];
-    int32_t region;             /* ADRES_REGION_*: where the AT region is (Sec. 2.2) */
+    int32_t region;             /* ADRES_REGION_*: where the AT region is (Sec. 2.2, 2.5) */
     double  center[3];          /* AT region centre (slab: only center[0] is used) */
-    double  d_at, d_hy;         /* AT half-width / radius and hybrid width */
+    double  d_at, d_hy;         /* AT half-width / radius (of each sphere) and hybrid width */
     double  eps_at, sig_at, rc_at;   /* atom-atom WCA */
     double  eps_cg, sig_cg, rc_cg;   /* CG centre-of-mass force: WCA parameters and cutoff */
     int32_t cg_kind;            /* ADRES_CG_*: the CG force between centres of mass */
@@ -224,6 +228,15 @@ adres_status adres_density_profile(adres_ctx *ctx, const double *x, int64_t *cou
  * prefactor is M / (rho_0^2 kappa_T).  counts: device int64 [n], n_frames >= 1.
  * Asynchronous. */
 adres_status adres_tdforce_update(adres_ctx *ctx, const int64_t *counts, int64_t n_frames, double prefactor);
+
+/* Anchors of a self-adjusting AT region (region ADRES_REGION_SPHERES, Sec. 2.5): mols (host,
+ * int32 [k]) are caller molecule indices; each anchor's current centre of mass is the centre
+ * of a sphere, and a molecule's resolution distance is its minimum-image distance to the
+ * nearest anchor centre, d = min_k |R - R_k| (so w is the largest single-sphere weight).
+ * The weights follow the anchors at every step.  1 <= k <= 1024 and 0 <= mols[i] < n_mol
+ * (ADRES_E_ARG otherwise, and for other regions); weights, forces and integration return
+ * ADRES_E_STATE until anchors are set.  Copied; synchronises. */
+adres_status adres_set_anchors(adres_ctx *ctx, const int32_t *mols, int32_t k);
 
 /* Learned CG force (replaces F^CG of Eq. (1) when cg_kind is ADRES_CG_MLP):
  *   f(r) = scale * taper(r) * [W3 . silu(W2 silu(W1 x + b1) + b2) + b3],  x = r / rc,

@@ -64,6 +64,7 @@ _SIGS = {
     "adres_get_cells": ([C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)], C.c_int),
     "adres_set_cg_table": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double], C.c_int),
     "adres_set_tdforce": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double], C.c_int),
+    "adres_set_anchors": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
     "adres_get_tdforce": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
     "adres_density_profile": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "adres_tdforce_update": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_double], C.c_int),
@@ -228,6 +229,12 @@ class Context:
         self._check(self.lib.adres_set_tdforce(self.h, table.ctypes.data_as(C.c_void_p), table.size,
                                                d_lo, d_hi), "adres_set_tdforce")
         self._td_n = int(table.size)
+
+    def set_anchors(self, mols):
+        """Anchor molecules (caller indices) of a self-adjusting AT region."""
+        mols = np.ascontiguousarray(mols, dtype=np.int32)
+        self._check(self.lib.adres_set_anchors(self.h, mols.ctypes.data_as(C.c_void_p), mols.size),
+                    "adres_set_anchors")
 
     def get_tdforce(self):
         out = np.empty(max(self._td_n, 1), dtype=np.float64)

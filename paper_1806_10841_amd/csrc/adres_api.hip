@@ -47,6 +47,7 @@ struct adres_ctx {
     int epart_blocks = 0;
     float4 *tab = nullptr;
     double *td = nullptr, *td_u = nullptr;   // correction force table and its integrals
+    int *anchors = nullptr;                  // anchor molecules of a self-adjusting region
 
     // learned CG force
     float *mlp = nullptr;          // FP32 master parameters (kMlpParams)
@@ -158,6 +159,8 @@ adres_status read_ctrl(adres_ctx *c)
 adres_status gather(adres_ctx *c, const double *x, const double *v, bool check_disp)
 {
     launch_gather(c->stream, c->P, x, v, cur(c), check_disp ? c->R_ref : nullptr, c->ctrl);
+    if (c->P.region == ADRES_REGION_SPHERES)
+        launch_anchor_weights(c->stream, c->P, cur(c).Rw, c->inv_perm, c->ctrl, 0, 0);
     HIPCHK(c, hipGetLastError());
     return ADRES_OK;
 }
@@ -327,6 +330,8 @@ adres_status run_forces(adres_ctx *c, ForceArgs a)
 
 adres_status check_cg_ready(adres_ctx *c)
 {
+    if (c->P.region == ADRES_REGION_SPHERES && c->P.n_anchors == 0)
+        return fail(c, ADRES_E_STATE, "self-adjusting region without anchors (adres_set_anchors)");
     if (c->P.cg_kind == ADRES_CG_TABLE && !c->tab)
         return fail(c, ADRES_E_STATE, "cg_kind is TABLE but no table was installed");
     if (is_mlp(c) && !c->have_mlp)
@@ -357,8 +362,9 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
         if (!(q.box[d] > 0.0) || !std::isfinite(q.box[d])) return ADRES_E_ARG;
     for (int k = 0; k < q.sites_per_mol; ++k)
         if (!(q.site_mass[k] > 0.0)) return ADRES_E_ARG;
-    if (q.region < ADRES_REGION_ALL_AT || q.region > ADRES_REGION_ALL_CG) return ADRES_E_ARG;
-    if ((q.region == ADRES_REGION_SLAB_X || q.region == ADRES_REGION_SPHERE) && (q.d_at < 0.0 || q.d_hy < 0.0))
+    if (q.region < ADRES_REGION_ALL_AT || q.region > ADRES_REGION_SPHERES) return ADRES_E_ARG;
+    if ((q.region == ADRES_REGION_SLAB_X || q.region == ADRES_REGION_SPHERE || q.region == ADRES_REGION_SPHERES) &&
+        (q.d_at < 0.0 || q.d_hy < 0.0))
         return ADRES_E_ARG;
     if (q.cg_kind < ADRES_CG_WCA || q.cg_kind > ADRES_CG_MLP_FP8) return ADRES_E_ARG;
     if (q.bond_kind < ADRES_BOND_NONE || q.bond_kind > ADRES_BOND_FENE) return ADRES_E_ARG;
@@ -371,6 +377,8 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     if (q.pair_precision != 32 && q.pair_precision != 64) return ADRES_E_ARG;
     if (q.scheme != ADRES_SCHEME_FORCE && q.scheme != ADRES_SCHEME_HAMILTONIAN) return ADRES_E_ARG;
     if (q.scheme == ADRES_SCHEME_HAMILTONIAN && q.cg_kind != ADRES_CG_WCA) return ADRES_E_ARG;
+    // moving anchors would add drift forces on the anchors themselves: force interpolation only
+    if (q.scheme == ADRES_SCHEME_HAMILTONIAN && q.region == ADRES_REGION_SPHERES) return ADRES_E_ARG;
     if (q.n_mol > scan_max_elements()) return ADRES_E_ARG;
 
     adres_ctx *c = new adres_ctx();
@@ -496,6 +504,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     bool cp = hipMemcpy(c->cell_rank, rank.data(), sizeof(int) * G.n_cells, hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->S[0].perm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->S[1].perm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(c->inv_perm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice) == hipSuccess &&
               hipMemset(c->count, 0, sizeof(int) * G.n_cells) == hipSuccess &&
               hipMemset(c->cnt_up, 0, sizeof(int) * n) == hipSuccess &&
               hipMemcpy(c->ctrl, &c0, sizeof(Ctrl), hipMemcpyHostToDevice) == hipSuccess;
@@ -520,7 +529,7 @@ void adres_destroy(adres_ctx *c)
     hipFree(c->R_ref); hipFree(c->inv_perm); hipFree(c->cell_rank);
     hipFree(c->count); hipFree(c->start); hipFree(c->fill); hipFree(c->new_from); hipFree(c->scan_tiles);
     hipFree(c->nbr); hipFree(c->cnt); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
-    hipFree(c->td); hipFree(c->td_u);
+    hipFree(c->td); hipFree(c->td_u); hipFree(c->anchors);
     hipFree(c->mlp); hipFree(c->mlp_w2); hipFree(c->mlp_w2q); hipFree(c->mlp_fp8s); hipFree(c->cnt_up); hipFree(c->up_off); hipFree(c->up_scratch);
     hipFree(c->pid); hipFree(c->up_pairs); hipFree(c->f_pair);
     hipFree(c->adam_m); hipFree(c->adam_v); hipFree(c->grad); hipFree(c->loss); hipFree(c->res_part);
@@ -537,7 +546,10 @@ void adres_destroy(adres_ctx *c)
 adres_status adres_weights(adres_ctx *c, const double *x, double *com, double *w)
 {
     if (!c || !x || !com || !w) return fail(c, ADRES_E_ARG, "null argument");
+    if (c->P.region == ADRES_REGION_SPHERES && c->P.n_anchors == 0)
+        return fail(c, ADRES_E_STATE, "self-adjusting region without anchors (adres_set_anchors)");
     launch_weights_caller(c->stream, c->P, x, com, w, c->ctrl);
+    if (c->P.region == ADRES_REGION_SPHERES) launch_anchor_weights_caller(c->stream, c->P, com, w);
     HIPCHK(c, hipGetLastError());
     return ADRES_OK;
 }
@@ -647,6 +659,8 @@ adres_status integrate_impl(adres_ctx *c, double *x, double *v, double *f, doubl
             if (gk == 0) {
                 launch_kick_drift(c->stream, c->P, in.x, in.v, c->f, out.x, out.Rw, out.rho, out.off, c->R_ref,
                                   in.perm, c->ctrl, k, sa);
+                if (c->P.region == ADRES_REGION_SPHERES)
+                    launch_anchor_weights(c->stream, c->P, out.Rw, c->inv_perm, c->ctrl, k, 1);
                 HIPCHK(c, hipGetLastError());
             } else {
                 ForceArgs a = force_args(c);
@@ -672,6 +686,10 @@ adres_status integrate_impl(adres_ctx *c, double *x, double *v, double *f, doubl
                 }
                 st = run_forces(c, a);
                 if (st != ADRES_OK) return st;
+                if (gk < n_steps && c->P.region == ADRES_REGION_SPHERES) {
+                    launch_anchor_weights(c->stream, c->P, out.Rw, c->inv_perm, c->ctrl, k, 1);
+                    HIPCHK(c, hipGetLastError());
+                }
             }
             if (gk < n_steps) p = 1 - p;
         }
@@ -823,6 +841,22 @@ adres_status adres_set_tdforce(adres_ctx *c, const double *table, int32_t n, dou
     c->P.td_h = (d_hi - d_lo) / (double)n;
     launch_td_update(c->stream, c->P, c->td, c->td_u, nullptr, 1, 0.0);
     HIPCHK(c, hipGetLastError());
+    return ADRES_OK;
+}
+
+adres_status adres_set_anchors(adres_ctx *c, const int32_t *mols, int32_t k)
+{
+    if (!c || !mols) return fail(c, ADRES_E_ARG, "null argument");
+    if (c->P.region != ADRES_REGION_SPHERES) return fail(c, ADRES_E_ARG, "anchors need region ADRES_REGION_SPHERES");
+    if (k < 1 || k > kMaxAnchors) return fail(c, ADRES_E_ARG, "1..1024 anchors");
+    for (int i = 0; i < k; ++i)
+        if (mols[i] < 0 || mols[i] >= c->P.n_mol) return fail(c, ADRES_E_ARG, "anchor index out of range");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!c->anchors) HIPCHK(c, dalloc(&c->anchors, (size_t)kMaxAnchors));
+    HIPCHK(c, hipMemcpy(c->anchors, mols, sizeof(int) * k, hipMemcpyHostToDevice));
+    c->P.anchors = c->anchors;
+    c->P.n_anchors = k;
+    c->list_valid = false;   // the weights of the stored state are stale
     return ADRES_OK;
 }
 

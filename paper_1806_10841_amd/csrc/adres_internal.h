@@ -64,6 +64,9 @@ struct DevParams {
     const double *td_u;
     int td_n;
     double td_lo, td_hi, td_h;
+    // self-adjusting region: caller indices of the anchor molecules
+    const int *anchors;
+    int n_anchors;
 };
 
 // Cell grid over the box.
@@ -225,12 +228,25 @@ __device__ __forceinline__ double corr_force(const DevParams &P, const double R[
     return f;
 }
 
-// Resolution weight of a centre of mass (1 in AT, cos^2 ramp in HY, 0 in CG).
+// Resolution weight of a distance from the AT centre (1 up to d_at, cos^2 ramp across
+// the hybrid layer, 0 beyond).
+__device__ __forceinline__ double weight_of_distance(const DevParams &P, double d)
+{
+#pragma clang fp contract(off)
+    if (d <= P.d_at) return 1.0;
+    if (d >= P.d_end) return 0.0;
+    double c = cos(M_PI * (d - P.d_at) / (2.0 * P.d_hy));
+    return c * c;
+}
+
+// Resolution weight of a centre of mass (1 in AT, cos^2 ramp in HY, 0 in CG).  The
+// self-adjusting region's weights need every anchor's centre: they are written by a
+// separate pass (launch_anchor_weights) and this returns a placeholder 0.
 __device__ __forceinline__ double res_weight(const DevParams &P, const double R[3])
 {
 #pragma clang fp contract(off)
     if (P.region == ADRES_REGION_ALL_AT) return 1.0;
-    if (P.region == ADRES_REGION_ALL_CG) return 0.0;
+    if (P.region == ADRES_REGION_ALL_CG || P.region == ADRES_REGION_SPHERES) return 0.0;
     double q[3];
     const double d = res_distance(P, R, q);
     if (d <= P.d_at) return 1.0;
@@ -497,5 +513,13 @@ constexpr int kTdMaxBins = 4096;
 void launch_density_profile(hipStream_t s, const DevParams &P, const double *x, unsigned long long *counts);
 void launch_td_update(hipStream_t s, const DevParams &P, double *td, double *td_u, const long long *counts,
                       long long n_frames, double prefactor);
+
+// self-adjusting region (k_state.hip): weights from the nearest anchor centre, for the
+// Morton-ordered state (Rw in place; anchors located through inv_perm; skipped like the
+// step kernels once a chunk has halted) or for caller-order centres (com [3][n] -> w)
+constexpr int kMaxAnchors = 1024;
+void launch_anchor_weights(hipStream_t s, const DevParams &P, double4 *Rw, const int *inv_perm, Ctrl *ctrl,
+                           int step, int check_halt);
+void launch_anchor_weights_caller(hipStream_t s, const DevParams &P, const double *com, double *w);
 
 }  // namespace adres

@@ -231,6 +231,69 @@ __global__ __launch_bounds__(kBlock) void k_td_update(DevParams P, double *__res
     }
 }
 
+// Self-adjusting AT region (Sec. 2.5): every workgroup stages the anchors' centres in LDS,
+// then each molecule takes the minimum-image distance to the nearest one,
+// d = sqrt(min_k r_k^2), and its weight.  Morton-ordered state: the anchors' slots come
+// from inv_perm and only the w component of Rw is written (centres are read as three
+// scalars, so the stores never overlap a read).
+__global__ __launch_bounds__(kBlock) void k_anchor_weights(DevParams P, double4 *Rw, const int *__restrict__ inv_perm,
+                                                           Ctrl *ctrl, int step, int check_halt)
+{
+#pragma clang fp contract(off)
+    if (check_halt && step > ctrl->halt) return;
+    __shared__ double cen[kMaxAnchors][3];
+    const int K = P.n_anchors;
+    for (int k = threadIdx.x; k < K; k += kBlock) {
+        const double *r = reinterpret_cast<const double *>(Rw + inv_perm[P.anchors[k]]);
+        cen[k][0] = r[0];
+        cen[k][1] = r[1];
+        cen[k][2] = r[2];
+    }
+    __syncthreads();
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= P.n_mol) return;
+    double *me = reinterpret_cast<double *>(Rw + t);
+    const double R0 = me[0], R1 = me[1], R2 = me[2];
+    double best = INFINITY;
+    for (int k = 0; k < K; ++k) {
+        const double q0 = mi(R0 - cen[k][0], P.box[0], P.half[0]);
+        const double q1 = mi(R1 - cen[k][1], P.box[1], P.half[1]);
+        const double q2 = mi(R2 - cen[k][2], P.box[2], P.half[2]);
+        const double r2 = dist2_exact(q0, q1, q2);
+        best = r2 < best ? r2 : best;
+    }
+    me[3] = weight_of_distance(P, sqrt(best));
+}
+
+// The same for caller-order centres com [3][n_mol] into w [n_mol].
+__global__ __launch_bounds__(kBlock) void k_anchor_weights_caller(DevParams P, const double *__restrict__ com,
+                                                                  double *__restrict__ w)
+{
+#pragma clang fp contract(off)
+    __shared__ double cen[kMaxAnchors][3];
+    const int K = P.n_anchors;
+    const int64_t n = P.n_mol;
+    for (int k = threadIdx.x; k < K; k += kBlock) {
+        const int b = P.anchors[k];
+        cen[k][0] = com[b];
+        cen[k][1] = com[n + b];
+        cen[k][2] = com[2 * n + b];
+    }
+    __syncthreads();
+    const int a = blockIdx.x * kBlock + threadIdx.x;
+    if (a >= P.n_mol) return;
+    const double R0 = com[a], R1 = com[n + a], R2 = com[2 * n + a];
+    double best = INFINITY;
+    for (int k = 0; k < K; ++k) {
+        const double q0 = mi(R0 - cen[k][0], P.box[0], P.half[0]);
+        const double q1 = mi(R1 - cen[k][1], P.box[1], P.half[1]);
+        const double q2 = mi(R2 - cen[k][2], P.box[2], P.half[2]);
+        const double r2 = dist2_exact(q0, q1, q2);
+        best = r2 < best ? r2 : best;
+    }
+    w[a] = weight_of_distance(P, sqrt(best));
+}
+
 __global__ void k_publish(const Ctrl *__restrict__ ctrl, CtrlPub *pub, unsigned seq)
 {
     if (threadIdx.x != 0) return;
@@ -314,6 +377,17 @@ void launch_td_update(hipStream_t s, const DevParams &P, double *td, double *td_
                       long long n_frames, double prefactor)
 {
     k_td_update<<<1, kBlock, 0, s>>>(P, td, td_u, counts, n_frames, prefactor);
+}
+
+void launch_anchor_weights(hipStream_t s, const DevParams &P, double4 *Rw, const int *inv_perm, Ctrl *ctrl,
+                           int step, int check_halt)
+{
+    k_anchor_weights<<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, Rw, inv_perm, ctrl, step, check_halt);
+}
+
+void launch_anchor_weights_caller(hipStream_t s, const DevParams &P, const double *com, double *w)
+{
+    k_anchor_weights_caller<<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, com, w);
 }
 
 }  // namespace adres

@@ -1,0 +1,167 @@
+"""GPU parity of the self-adjusting AT region (Sec. 2.5: spheres around anchor molecules
+whose union is the AT region) against the FP64 oracle, through the C ABI.
+
+Bars: weights to 1e-15 absolute (the only new arithmetic is the nearest-anchor distance);
+forces FP64 1e-12 and FP32 1e-5 of A_i; FP64 trajectories 1e-9 in position.  The
+weights of the moving region are checked on the final state of a trajectory too.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1806_10841_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SPH = inputs.REGION_SPHERES
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    return torch.device("cuda:0")
+
+
+def _ctx(wl, anchors):
+    from paper_1806_10841_amd import binding
+    c = binding.Context(wl)
+    c.set_anchors(anchors)
+    return c
+
+
+def _t(a, dev):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+def _wl(name, **kw):
+    base = dict(region=SPH, d_at=2.5, d_hy=2.0)
+    if name == "c2":
+        base = dict(region=SPH, d_at=4.0, d_hy=3.0)
+    base.update(kw)
+    return inputs.workload(name).with_(**base)
+
+
+def _assert_close(fg, fo, amag, tol, where):
+    err = np.abs(fg - fo).max(axis=0)
+    ratio = (err / np.maximum(amag, 1e-300)).max()
+    assert ratio <= tol, f"{where}: worst ratio {ratio:.3e}"
+    assert np.linalg.norm(fg - fo) <= tol * np.linalg.norm(fo), where
+
+
+@pytest.mark.parametrize("name,k", [("small_sphere", 1), ("small_sphere", 9), ("small_sphere", 1024),
+                                    ("c1", 5), ("c2", 300)])
+def test_weights(dev, name, k):
+    wl = _wl(name)
+    an = inputs.anchor_molecules(wl.n_mol, k, k)
+    x, _ = inputs.make_state(wl)
+    com_o, w_o, _, st = oracle.Model(wl, anchors=an).weights(x)
+    assert st == 0 and ((w_o > 0) & (w_o < 1)).any()
+    com, w = _ctx(wl, an).weights(_t(x, dev))
+    np.testing.assert_array_equal(com.cpu().numpy(), com_o)
+    assert np.abs(w.cpu().numpy() - w_o).max() <= 1e-15
+
+
+@pytest.mark.parametrize("name,k,prec", [("small_sphere", 9, 64), ("c1", 5, 64), ("tiny_slab", 3, 64),
+                                         ("small_sphere", 9, 32)])
+def test_forces(dev, name, k, prec):
+    wl = _wl(name, pair_precision=prec)
+    if name == "tiny_slab":
+        wl = wl.with_(d_at=1.0, d_hy=2.0)
+    an = inputs.anchor_molecules(wl.n_mol, k, 2)
+    x, _ = inputs.make_state(wl)
+    fo, amag, eo, st = oracle.Model(wl, anchors=an).forces(x)
+    assert st == 0
+    f, e = _ctx(wl, an).forces(_t(x, dev), energy=True)
+    torch.cuda.synchronize()
+    tol = 1e-12 if prec == 64 else 1e-5
+    _assert_close(f.cpu().numpy(), fo, amag, tol, name)
+    np.testing.assert_allclose(e.cpu().numpy(), eo, rtol=tol, atol=tol * np.abs(eo).max())
+
+
+def _min_image(d, L):
+    return d - L * np.round(d / L)
+
+
+@pytest.mark.parametrize("name,k,steps", [("c1", 5, 100), ("small_sphere", 9, 40)])
+def test_integrate_fp64_matches_oracle_vv(dev, name, k, steps):
+    """The region follows the anchors at every step (trajectory and the final weights)."""
+    wl = _wl(name, pair_precision=64)
+    an = inputs.anchor_molecules(wl.n_mol, k, 7)
+    x, v = inputs.make_state(wl)
+    m = oracle.Model(wl, anchors=an)
+    xo, vo, fo, _, st = m.vv(x, v, wl.dt, steps)
+    assert st == 0
+    ctx = _ctx(wl, an)
+    xt, vt = _t(x, dev), _t(v, dev)
+    ft = torch.empty_like(xt)
+    nreb = ctx.integrate(xt, vt, ft, wl.dt, steps)
+    torch.cuda.synchronize()
+    tol = 1e-9
+    xg = xt.cpu().numpy()
+    assert np.abs(_min_image(xg - xo, wl.box[0])).max() < tol
+    assert np.abs(vt.cpu().numpy() - vo).max() < 100 * tol
+    if name == "c1":
+        assert nreb >= 1
+    _, w_o, _, _ = m.weights(xg)
+    _, w = ctx.weights(xt)
+    assert np.abs(w.cpu().numpy() - w_o).max() <= 1e-15
+
+
+def test_c2_full_size_sampled_and_momentum(dev):
+    """64,000 tetrahedra, 64 anchors, FP32 pairs: sampled molecules of each resolution
+    against the oracle; then 200 steps conserve momentum (force interpolation keeps
+    Newton's third law with any weights)."""
+    wl = _wl("c2")
+    an = inputs.anchor_molecules(wl.n_mol, 64, 5)
+    x, v = inputs.make_state(wl)
+    m = oracle.Model(wl, anchors=an)
+    _, w, _, _ = m.weights(x)
+    rng = np.random.default_rng(6)
+    sel = []
+    for mask in (w == 1.0, (w > 0) & (w < 1), w == 0.0):
+        idx = np.flatnonzero(mask)
+        assert len(idx) > 0
+        sel.append(rng.choice(idx, size=min(60, len(idx)), replace=False))
+    sel = np.sort(np.concatenate(sel))
+    fo, amag, st = m.forces_sampled(x, sel)
+    assert st == 0
+    ctx = _ctx(wl, an)
+    xt, vt = _t(x, dev), _t(v, dev)
+    f = ctx.forces(xt).cpu().numpy()
+    fg = np.stack([f[:, 4 * a:4 * a + 4] for a in sel])
+    err = np.abs(fg - fo).max(axis=1)
+    assert np.all(err <= 1e-5 * amag), (err / amag).max()
+    ft = torch.empty_like(xt)
+    p0 = vt.sum(dim=1).cpu().numpy()
+    nreb = ctx.integrate(xt, vt, ft, wl.dt, 200)
+    torch.cuda.synchronize()
+    assert nreb >= 1
+    p1 = vt.sum(dim=1).cpu().numpy()
+    assert np.abs(p1 - p0).max() < 1e-6 * np.abs(vt.cpu().numpy()).sum(axis=1).max() / 1e3
+
+
+def test_errors(dev):
+    from paper_1806_10841_amd import binding
+    wl = _wl("small_sphere")
+    x, _ = inputs.make_state(wl)
+    xt = _t(x, dev)
+    c = binding.Context(wl)
+    with pytest.raises(binding.AdresError):
+        c.forces(xt)                                   # no anchors yet
+    with pytest.raises(binding.AdresError):
+        c.weights(xt)
+    for bad in (np.zeros(0, np.int32), np.array([wl.n_mol], np.int32), np.array([-1], np.int32),
+                np.arange(1025, dtype=np.int32)):
+        with pytest.raises(binding.AdresError):
+            c.set_anchors(bad)
+    c.set_anchors(np.array([3], np.int32))
+    assert torch.isfinite(c.forces(xt)).all()
+    with pytest.raises(binding.AdresError):            # a correction field needs a slab or sphere
+        c.set_tdforce(np.ones(4), 1.0, 3.0)
+    with pytest.raises(binding.AdresError):
+        binding.Context(wl.with_(scheme=inputs.SCHEME_HAMILTONIAN))
+    s = binding.Context(inputs.workload("small_sphere"))
+    with pytest.raises(binding.AdresError):
+        s.set_anchors(np.array([3], np.int32))
