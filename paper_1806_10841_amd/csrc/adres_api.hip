@@ -48,6 +48,8 @@ struct adres_ctx {
     float4 *tab = nullptr;
     double *td = nullptr, *td_u = nullptr;   // correction force table and its integrals
     int *anchors = nullptr;                  // anchor molecules of a self-adjusting region
+    int *tile_order = nullptr;               // force kernel dispatch order (per list build)
+    unsigned *mcost = nullptr;               // per-molecule cost estimates (list build)
 
     // learned CG force
     float *mlp = nullptr;          // FP32 master parameters (kMlpParams)
@@ -234,12 +236,13 @@ adres_status build_list(adres_ctx *c)
         HIPCHK(c, hipMemsetAsync(&c->ctrl->overflow, 0, 2 * sizeof(int), c->stream));
         const StateBufs b = cur(c);
         launch_list_build(c->stream, c->P, c->G, c->cell_rank, c->start, b.Rw, c->rl2, c->nbr, c->cnt, c->cap,
-                          c->ctrl);
+                          c->mcost, c->ctrl);
         HIPCHK(c, hipGetLastError());
         adres_status st = read_ctrl(c);
         if (st != ADRES_OK) return st;
         if (!c->ctrl_host->overflow) {
             c->list_valid = true;
+            launch_tile_order(c->stream, c->P, c->mcost, c->epart_blocks, c->tile_order);
             launch_reset_halt(c->stream, c->ctrl);   // an earlier overflow may have left halt = -1
             if (c->P.cg_kind >= ADRES_CG_MLP) return build_half_list(c);
             return ADRES_OK;
@@ -262,7 +265,8 @@ adres_status build_list_async(adres_ctx *c)
     // overflow / max_count were cleared by the halt reset launched before the reorder
     const StateBufs b = cur(c);
     launch_list_build(c->stream, c->P, c->G, c->cell_rank, c->start, b.Rw, c->rl2, c->nbr, c->cnt, c->cap,
-                      c->ctrl);
+                      c->mcost, c->ctrl);
+    launch_tile_order(c->stream, c->P, c->mcost, c->epart_blocks, c->tile_order);
     HIPCHK(c, hipGetLastError());
     c->list_valid = true;
     if (is_mlp(c)) return build_half_list(c);
@@ -286,6 +290,7 @@ ForceArgs force_args(adres_ctx *c)
     a.ctrl = c->ctrl;
     a.mode = kModeForce;
     a.slow_scale = 1.0;
+    a.tile_order = c->tile_order;
     return a;
 }
 
@@ -488,6 +493,8 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
          dalloc(&c->up_scratch, n) == hipSuccess;
     c->epart_blocks = force_blocks(n);
     ok = ok && dalloc(&c->epart, 4 * (size_t)c->epart_blocks) == hipSuccess;
+    ok = ok && dalloc(&c->tile_order, (size_t)c->epart_blocks) == hipSuccess &&
+         dalloc(&c->mcost, (size_t)n) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&c->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&c->pub, sizeof(CtrlPub), hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
     if (ok) {
@@ -529,7 +536,7 @@ void adres_destroy(adres_ctx *c)
     hipFree(c->R_ref); hipFree(c->inv_perm); hipFree(c->cell_rank);
     hipFree(c->count); hipFree(c->start); hipFree(c->fill); hipFree(c->new_from); hipFree(c->scan_tiles);
     hipFree(c->nbr); hipFree(c->cnt); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
-    hipFree(c->td); hipFree(c->td_u); hipFree(c->anchors);
+    hipFree(c->td); hipFree(c->td_u); hipFree(c->anchors); hipFree(c->tile_order); hipFree(c->mcost);
     hipFree(c->mlp); hipFree(c->mlp_w2); hipFree(c->mlp_w2q); hipFree(c->mlp_fp8s); hipFree(c->cnt_up); hipFree(c->up_off); hipFree(c->up_scratch);
     hipFree(c->pid); hipFree(c->up_pairs); hipFree(c->f_pair);
     hipFree(c->adam_m); hipFree(c->adam_v); hipFree(c->grad); hipFree(c->loss); hipFree(c->res_part);

@@ -462,7 +462,7 @@ void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, cons
 // Verlet list: ELL, row-major nbr[slot * cap + k]; each row is padded with the
 // row's own slot up to a multiple of 4 entries (cap is a multiple of 4).
 void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank, const int *start,
-                       const double4 *Rw, double rl2, int *nbr, int *cnt, int cap, Ctrl *ctrl);
+                       const double4 *Rw, double rl2, int *nbr, int *cnt, int cap, unsigned *mcost, Ctrl *ctrl);
 
 // half list (t < u pairs) + per-entry pair ids; up_off receives n + 1 offsets
 void launch_half_list(hipStream_t s, int n, int *nbr, const int *cnt, int cap, int *cnt_up, int *up_off,
@@ -501,12 +501,17 @@ struct ForceArgs {
     // multiple time stepping: the slow part (CG pair part, the CG share of the drift, the
     // correction force) enters the force with this factor; 0 skips it (inner steps)
     double slow_scale;
+    // dispatch order of the workgroups (launch_tile_order), or null for the identity
+    const int *tile_order;
 };
 // returns the block count; e0/e1 (optional) are recorded at the kernel's start and end
 int launch_forces(hipStream_t s, const ForceArgs &a, int pair_precision, hipEvent_t e0 = nullptr,
                   hipEvent_t e1 = nullptr);
 int force_blocks(int n_mol);
 void launch_energy_reduce(hipStream_t s, const double *epart, int n_blocks, double *energy);
+
+// workgroup dispatch order of the force kernel, rebuilt with the list (k_cells.hip)
+void launch_tile_order(hipStream_t s, const DevParams &P, const unsigned *mcost, int n_tiles, int *order);
 
 // correction force (k_state.hip)
 constexpr int kTdMaxBins = 4096;

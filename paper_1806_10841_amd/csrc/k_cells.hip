@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kBlock) void k_list_build_cells(DevParams P, Grid G
                                                              const int *__restrict__ start,
                                                              const double4 *__restrict__ Rw, double rl2,
                                                              int *__restrict__ nbr, int *__restrict__ cnt, int cap,
-                                                             Ctrl *ctrl)
+                                                             unsigned *__restrict__ mcost, Ctrl *ctrl)
 {
     const int gid = blockIdx.x * kBlock + threadIdx.x;
     const int t = gid / kCellLanes, lane = gid % kCellLanes;
@@ -299,6 +299,10 @@ __global__ __launch_bounds__(kBlock) void k_list_build_cells(DevParams P, Grid G
     }
     if (valid && lane == kCellLanes - 1) {
         cnt[t] = total;
+        // force-kernel cost estimate of the molecule (k_tile_order): its row, in atom pairs
+        // if it can be atomistic
+        const unsigned heavy = me.w > 0.0 ? (unsigned)(P.spm * P.spm) : 1u;
+        mcost[t] = (unsigned)min(total, cap) * heavy + 4u;
         if (total > cap) {
             atomicOr(&ctrl->overflow, 1);
             atomicMax(&ctrl->max_count, total);
@@ -421,10 +425,91 @@ void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, cons
 }
 
 void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank, const int *start,
-                       const double4 *Rw, double rl2, int *nbr, int *cnt, int cap, Ctrl *ctrl)
+                       const double4 *Rw, double rl2, int *nbr, int *cnt, int cap, unsigned *mcost, Ctrl *ctrl)
 {
     const int blocks = (int)(((int64_t)P.n_mol * kCellLanes + kBlock - 1) / kBlock);
-    k_list_build_cells<<<blocks, kBlock, 0, s>>>(P, G, cell_rank, start, Rw, rl2, nbr, cnt, cap, ctrl);
+    k_list_build_cells<<<blocks, kBlock, 0, s>>>(P, G, cell_rank, start, Rw, rl2, nbr, cnt, cap, mcost, ctrl);
+}
+
+
+namespace {
+
+// Dispatch order of the force kernel's workgroups (longest processing time first): one
+// workgroup per XCD range of tiles (64 molecules each, the force kernel's workgroup).  A
+// tile's cost estimate is the sum over its four wavefronts of the largest per-molecule
+// cost in each (lanes of a wavefront run in lockstep); the list build stores the
+// per-molecule costs (row length, times SPM^2 when the molecule can be atomistic).  Tiles are ranked by falling cost (ties by index) so
+// that the heaviest tiles of an XCD are dispatched first, one per compute unit, instead of
+// piling up on the compute units that receive neighbouring parts of the slab.  Any order
+// is a valid permutation; ranges longer than kTileSortMax keep the identity.
+constexpr int kTileSortMax = 4096;
+constexpr int kTileThreads = 1024;
+
+__global__ __launch_bounds__(kTileThreads) void k_tile_order(int n_mol, const unsigned *__restrict__ mcost, int n_tiles,
+                                                            int *__restrict__ order)
+{
+    __shared__ unsigned tcost[kTileSortMax];
+    __shared__ unsigned long long key[kTileSortMax];
+    const int x = blockIdx.x;
+    const int q = n_tiles / 8, r = n_tiles % 8;
+    const int start = x * q + (x < r ? x : r), len = q + (x < r ? 1 : 0);
+    if (len > kTileSortMax) {
+        for (int i = threadIdx.x; i < len; i += kTileThreads) order[start + i] = start + i;
+        return;
+    }
+    for (int i = threadIdx.x; i < len; i += kTileThreads) tcost[i] = 0u;
+    __syncthreads();
+    // per-molecule costs, 8 independent loads per thread in flight; the largest of each
+    // run of 16 molecules (one force-kernel wavefront) by xor shuffles inside 16-lane
+    // groups, summed per tile with LDS integer atomics (order-independent)
+    const int64_t m0 = (int64_t)start * 64, nm = (int64_t)len * 64;
+    for (int64_t base = 0; base < nm; base += (int64_t)kTileThreads * 8) {
+        unsigned mc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t m = base + (int64_t)u * kTileThreads + threadIdx.x;
+            const int64_t t = m0 + m;
+            mc[u] = m < nm && t < n_mol ? mcost[t] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            unsigned v = mc[u];
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) {
+                const unsigned y = (unsigned)__shfl_xor((int)v, o, 64);
+                v = y > v ? y : v;
+            }
+            const int64_t m = base + (int64_t)u * kTileThreads + threadIdx.x;
+            if ((threadIdx.x & 15) == 0 && m < nm) atomicAdd(&tcost[m / 64], v);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < len; i += kTileThreads)
+        key[i] = ((unsigned long long)tcost[i] << 32) | (unsigned)(~(unsigned)i);
+    for (int i = threadIdx.x; i < len; i += kTileThreads) tcost[i] = 0u;   // now the ranks
+    __syncthreads();
+    // rank of tile i = number of larger keys (keys are distinct), counted by all threads:
+    // C chunks of the j range per tile, partial counts added with LDS atomics
+    const int C = len < kTileThreads ? kTileThreads / len : 1;
+    const int per = (len + C - 1) / C;
+    for (int wk = threadIdx.x; wk < len * C; wk += kTileThreads) {
+        const int i = wk % len, c = wk / len;
+        const unsigned long long k = key[i];
+        const int j0 = c * per, j1 = min(len, j0 + per);
+        unsigned n_gt = 0u;
+#pragma unroll 4
+        for (int j = j0; j < j1; ++j) n_gt += key[j] > k ? 1u : 0u;
+        atomicAdd(&tcost[i], n_gt);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < len; i += kTileThreads) order[start + (int)tcost[i]] = start + i;
+}
+
+}  // namespace
+
+void launch_tile_order(hipStream_t s, const DevParams &P, const unsigned *mcost, int n_tiles, int *order)
+{
+    k_tile_order<<<8, kTileThreads, 0, s>>>(P.n_mol, mcost, n_tiles, order);
 }
 
 }  // namespace adres

@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     if (a.check_halt && a.step > a.ctrl->halt) return;
     const int n = P.n_mol;
     const int64_t ns = P.n_sites;
-    const int blk = xcd_block();
+    const int blk = a.tile_order ? a.tile_order[xcd_block()] : xcd_block();
     const int gid = blk * kBlock + threadIdx.x;
     const int t = gid / kLanes, q = gid % kLanes;
     const bool valid = t < n;
