@@ -246,22 +246,25 @@ def hamiltonian_leg(wl, x, v, steps, warmup):
 
 def anchors_leg(wl, x, v, steps, warmup, counts=(16, 256)):
     """Self-adjusting AT region (Sec. 2.5) on the same molecules: the union of spheres
-    (radius 4, hybrid shell 3) around k anchor molecules that move with the simulation,
-    weights recomputed from the nearest anchor after every step.  MD steps/s per k."""
+    (radius 5, hybrid shell 4) around k anchor molecules that move with the simulation,
+    weights recomputed from the nearest anchor after every step, with the Langevin
+    thermostat (gamma 1, kT 1) that force interpolation needs (Sec. 2.3: no conserved
+    energy; molecules switched to atomistic inside moving spheres otherwise heat up).
+    MD steps/s per k."""
     import torch
     from paper_1806_10841_amd import binding, inputs
     out = {}
     for k in counts:
-        wk = wl.with_(region=inputs.REGION_SPHERES, d_at=4.0, d_hy=3.0)
+        wk = wl.with_(region=inputs.REGION_SPHERES, d_at=5.0, d_hy=4.0)
         ctx = binding.Context(wk)
         ctx.set_anchors(inputs.anchor_molecules(wk.n_mol, k, 5))
         xt = torch.tensor(x, device="cuda")
         vt = torch.tensor(v, device="cuda")
         ft = torch.empty_like(xt)
-        ctx.integrate(xt, vt, ft, wk.dt, warmup)
+        ctx.integrate(xt, vt, ft, wk.dt, warmup, gamma=1.0, kT=1.0, seed=11)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        nreb = ctx.integrate(xt, vt, ft, wk.dt, steps)
+        nreb = ctx.integrate(xt, vt, ft, wk.dt, steps, gamma=1.0, kT=1.0, seed=12)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         _, w = ctx.weights(xt)
