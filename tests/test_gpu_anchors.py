@@ -165,3 +165,20 @@ def test_errors(dev):
     s = binding.Context(inputs.workload("small_sphere"))
     with pytest.raises(binding.AdresError):
         s.set_anchors(np.array([3], np.int32))
+
+
+def test_respa_with_anchor_spheres_matches_oracle(dev):
+    """RESPA (CG part on every second step) with the self-adjusting region: the weights
+    follow the anchors on every inner step, against the oracle's RESPA."""
+    wl = _wl("c1", pair_precision=64)
+    an = inputs.anchor_molecules(wl.n_mol, 5, 7)
+    x, v = inputs.make_state(wl)
+    xo, vo, _, _, st = oracle.Model(wl, anchors=an).respa(x, v, wl.dt / 2, 2, 40)
+    assert st == 0
+    ctx = _ctx(wl, an)
+    xt, vt = _t(x, dev), _t(v, dev)
+    ft = torch.empty_like(xt)
+    ctx.integrate_respa(xt, vt, ft, wl.dt / 2, 2, 40)
+    torch.cuda.synchronize()
+    assert np.abs(_min_image(xt.cpu().numpy() - xo, wl.box[0])).max() < 1e-9
+    assert np.abs(vt.cpu().numpy() - vo).max() < 1e-7
