@@ -474,6 +474,7 @@ def learned_vs_tabulated(cg_steps):
         rec["listed_pairs"] = ctx.build_verlet(xt)
         ctx.close()
         runs[name] = rec
+    c5 = large_heterogeneous(table, params, scale, tw, r_min)
     pairs = runs["mlp"]["listed_pairs"]
     flop_per_pair = 2 * 64 * 64 + 2 * 64 + 2 * 64 + 2
     mlp_tflops = flop_per_pair * pairs / (runs["mlp"]["mlp_prepass_us"] * 1e-6) / 1e12
@@ -493,8 +494,42 @@ def learned_vs_tabulated(cg_steps):
         "runs": runs,
         "mlp_prepass": {"pairs": pairs, "flop_per_pair": flop_per_pair, "tflops": mlp_tflops,
                         "frac_of_bf16_mfma_peak": mlp_tflops / 2500.0},
+        "c5_large_heterogeneous": c5,
         "seconds": time.perf_counter() - t_all,
     }
+
+
+def large_heterogeneous(table, params, scale, tw, r_min, steps=200, warmup=20):
+    """1,000,000 tetrahedra with a spherical AT region (radius 12, hybrid shell 5) in a
+    CG bath, FP32 pairs, NVE velocity Verlet dt 0.005: MD steps/s with the force-matched
+    table, the trained network (BF16 matrix cores) and its FP8 variant as F^CG of Eq. (1),
+    all with the CG cutoff 3.0 the network was trained for."""
+    import torch
+    from paper_1806_10841_amd import binding, inputs
+    wl = inputs.workload("c5").with_(rc_cg=3.0)
+    x, v = inputs.make_state(wl)
+    out = {"workload": f"c5: {wl.n_mol} tetrahedra ({wl.n_mol * 4} atoms), sphere AT 12 + HY 5, CG cutoff 3.0, "
+                       "FP32 pairs, NVE velocity Verlet dt 0.005", "steps": steps}
+    for name, kind in (("table", inputs.CG_TABLE), ("mlp", inputs.CG_MLP), ("mlp_fp8", inputs.CG_MLP_FP8)):
+        ctx = binding.Context(wl.with_(cg_kind=kind))
+        ctx.set_cg_table(*table)
+        if kind != inputs.CG_TABLE:
+            ctx.mlp_set(params, 3.0, scale, tw, r_min)
+        xt = torch.tensor(x, device="cuda")
+        vt = torch.tensor(v, device="cuda")
+        ft = torch.empty_like(xt)
+        ctx.integrate(xt, vt, ft, wl.dt, warmup)
+        ctx.kernel_timing(1, every=TIMING_EVERY)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nreb = ctx.integrate(xt, vt, ft, wl.dt, steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        f_ms, f_n = ctx.kernel_timing(0)
+        ctx.close()
+        out[name] = {"steps_per_s": steps / el, "list_rebuilds": nreb,
+                     "force_kernel_us": 1e3 * f_ms / max(f_n, 1)}
+    return out
 
 
 if __name__ == "__main__":
