@@ -245,3 +245,33 @@ def test_remove_and_errors(dev):
     ctx.set_tdforce(np.ones(8), 1.0, 6.0)
     with pytest.raises(binding.AdresError):
         ctx.tdforce_update(counts, 0, 1.0)
+
+
+@pytest.mark.parametrize("scheme", [0, HAM])
+def test_single_molecule_with_correction_and_respa(dev, scheme):
+    """Degenerate size: one tetrahedron in the hybrid layer (no pairs), both schemes, a
+    correction field: forces (bonds + correction; the drift vanishes with V = 0) and a few
+    RESPA steps against the oracle."""
+    wl = inputs.workload("tiny_slab").with_(n_mol=1, scheme=scheme, pair_precision=64)
+    x, v = inputs.make_state(inputs.workload("tiny_slab"))
+    x1 = np.ascontiguousarray(x[:, 4 * 21:4 * 22])         # molecule 21: 0 < w < 1
+    v1 = np.ascontiguousarray(v[:, 4 * 21:4 * 22])
+    m0 = oracle.Model(wl)
+    com, w, _, _ = m0.weights(x1)
+    assert 0.0 < w[0] < 1.0
+    d = abs(com[0, 0] - wl.center[0])
+    td = (np.linspace(0.3, 1.2, 6), max(d - 1.0, 0.0), d + 1.0)
+    m = oracle.Model(wl, td=td)
+    fo, amag, eo, st = m.forces(x1)
+    assert st == 0 and eo[3] != 0.0
+    ctx = _ctx(wl, td)
+    f, e = ctx.forces(_t(x1, dev), energy=True)
+    torch.cuda.synchronize()
+    _assert_close(f.cpu().numpy(), fo, amag, 1e-12, "single molecule")
+    np.testing.assert_allclose(e.cpu().numpy(), eo, rtol=1e-12, atol=1e-12 * np.abs(eo).max())
+    xo, vo, _, _, _ = m.respa(x1, v1, 0.002, 2, 10)
+    xt, vt = _t(x1, dev), _t(v1, dev)
+    ft = torch.empty_like(xt)
+    ctx.integrate_respa(xt, vt, ft, 0.002, 2, 10)
+    torch.cuda.synchronize()
+    assert np.abs(_min_image(xt.cpu().numpy() - xo, wl.box[0])).max() < 1e-10
