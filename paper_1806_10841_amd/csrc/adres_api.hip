@@ -50,6 +50,7 @@ struct adres_ctx {
     int *anchors = nullptr;                  // anchor molecules of a self-adjusting region
     int *tile_order = nullptr;               // force kernel dispatch order (per list build)
     unsigned *mcost = nullptr;               // per-molecule cost estimates (list build)
+    int *stencil = nullptr;                  // [n_cells][27] neighbour cell ranks (static grid)
 
     // learned CG force
     float *mlp = nullptr;          // FP32 master parameters (kMlpParams)
@@ -235,7 +236,7 @@ adres_status build_list(adres_ctx *c)
     for (int attempt = 0; attempt < 4; ++attempt) {
         HIPCHK(c, hipMemsetAsync(&c->ctrl->overflow, 0, 2 * sizeof(int), c->stream));
         const StateBufs b = cur(c);
-        launch_list_build(c->stream, c->P, c->G, c->cell_rank, c->start, b.Rw, c->rl2, c->nbr, c->cnt, c->cap,
+        launch_list_build(c->stream, c->P, c->G, c->stencil, c->start, b.Rw, c->rl2, c->nbr, c->cnt, c->cap,
                           c->mcost, c->ctrl);
         HIPCHK(c, hipGetLastError());
         adres_status st = read_ctrl(c);
@@ -264,7 +265,7 @@ adres_status build_list_async(adres_ctx *c)
 {
     // overflow / max_count were cleared by the halt reset launched before the reorder
     const StateBufs b = cur(c);
-    launch_list_build(c->stream, c->P, c->G, c->cell_rank, c->start, b.Rw, c->rl2, c->nbr, c->cnt, c->cap,
+    launch_list_build(c->stream, c->P, c->G, c->stencil, c->start, b.Rw, c->rl2, c->nbr, c->cnt, c->cap,
                       c->mcost, c->ctrl);
     launch_tile_order(c->stream, c->P, c->mcost, c->epart_blocks, c->tile_order);
     HIPCHK(c, hipGetLastError());
@@ -472,6 +473,22 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     double mean = (double)q.n_mol / vol * (4.0 / 3.0) * M_PI * c->rl2 * c->r_list;
     c->cap = (((int)std::ceil(2.0 * mean) + 16) + 15) & ~15;
 
+    // the 27 stencil neighbours of every cell, by Morton rank (stencil order z, y, x offset;
+    // offsets outside [off_lo, off_hi] skipped so that small grids visit no cell twice)
+    std::vector<int> stencil((size_t)G.n_cells * 27);
+    for (int r = 0; r < G.n_cells; ++r) {
+        const int cidx = codes[r].second;
+        const int cx = cidx % G.n[0], cy = (cidx / G.n[0]) % G.n[1], cz = cidx / (G.n[0] * G.n[1]);
+        for (int l = 0; l < 27; ++l) {
+            const int oz = l / 9 - 1, oy = (l / 3) % 3 - 1, ox = l % 3 - 1;
+            const bool used = ox >= G.off_lo[0] && ox <= G.off_hi[0] && oy >= G.off_lo[1] && oy <= G.off_hi[1] &&
+                              oz >= G.off_lo[2] && oz <= G.off_hi[2];
+            const int wx = (cx + ox + G.n[0]) % G.n[0], wy = (cy + oy + G.n[1]) % G.n[1],
+                      wz = (cz + oz + G.n[2]) % G.n[2];
+            stencil[(size_t)r * 27 + l] = used ? rank[wx + G.n[0] * (wy + G.n[1] * wz)] : -1;
+        }
+    }
+
     const int n = q.n_mol;
     const int64_t ns = P.n_sites;
     bool ok = true;
@@ -494,7 +511,8 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     c->epart_blocks = force_blocks(n);
     ok = ok && dalloc(&c->epart, 4 * (size_t)c->epart_blocks) == hipSuccess;
     ok = ok && dalloc(&c->tile_order, (size_t)c->epart_blocks) == hipSuccess &&
-         dalloc(&c->mcost, (size_t)n) == hipSuccess;
+         dalloc(&c->mcost, (size_t)n) == hipSuccess &&
+         dalloc(&c->stencil, (size_t)G.n_cells * 27) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&c->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&c->pub, sizeof(CtrlPub), hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
     if (ok) {
@@ -512,6 +530,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
               hipMemcpy(c->S[0].perm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->S[1].perm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->inv_perm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(c->stencil, stencil.data(), sizeof(int) * stencil.size(), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemset(c->count, 0, sizeof(int) * G.n_cells) == hipSuccess &&
               hipMemset(c->cnt_up, 0, sizeof(int) * n) == hipSuccess &&
               hipMemcpy(c->ctrl, &c0, sizeof(Ctrl), hipMemcpyHostToDevice) == hipSuccess;
@@ -536,7 +555,7 @@ void adres_destroy(adres_ctx *c)
     hipFree(c->R_ref); hipFree(c->inv_perm); hipFree(c->cell_rank);
     hipFree(c->count); hipFree(c->start); hipFree(c->fill); hipFree(c->new_from); hipFree(c->scan_tiles);
     hipFree(c->nbr); hipFree(c->cnt); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
-    hipFree(c->td); hipFree(c->td_u); hipFree(c->anchors); hipFree(c->tile_order); hipFree(c->mcost);
+    hipFree(c->td); hipFree(c->td_u); hipFree(c->anchors); hipFree(c->tile_order); hipFree(c->mcost); hipFree(c->stencil);
     hipFree(c->mlp); hipFree(c->mlp_w2); hipFree(c->mlp_w2q); hipFree(c->mlp_fp8s); hipFree(c->cnt_up); hipFree(c->up_off); hipFree(c->up_scratch);
     hipFree(c->pid); hipFree(c->up_pairs); hipFree(c->f_pair);
     hipFree(c->adam_m); hipFree(c->adam_v); hipFree(c->grad); hipFree(c->loss); hipFree(c->res_part);

@@ -461,7 +461,8 @@ void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, cons
 
 // Verlet list: ELL, row-major nbr[slot * cap + k]; each row is padded with the
 // row's own slot up to a multiple of 4 entries (cap is a multiple of 4).
-void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank, const int *start,
+// stencil: rank-major [n_cells][27] neighbour cell ranks, -1 = skipped (fixed at set-up)
+void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const int *stencil, const int *start,
                        const double4 *Rw, double rl2, int *nbr, int *cnt, int cap, unsigned *mcost, Ctrl *ctrl);
 
 // half list (t < u pairs) + per-entry pair ids; up_off receives n + 1 offsets

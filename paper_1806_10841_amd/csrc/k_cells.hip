@@ -207,108 +207,116 @@ __global__ __launch_bounds__(kBlock) void k_permute(DevParams P, const int *__re
     inv_perm[caller] = t;
 }
 
-__device__ __forceinline__ int wrap_cell(int c, int n)
+// Lane h's value broadcast to the whole wavefront (h uniform: a scalar read of the lane).
+__device__ __forceinline__ double read_lane(double v, int h)
 {
-    c += n;
-    return c >= n ? (c >= 2 * n ? c - 2 * n : c - n) : c;
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), h);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), h);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Lane-per-cell build: 32 lanes per home molecule, lane c (< 27) scans stencil cell c
-// (stencil order: z, then y, then x offset) once, keeping its matches as a bit mask over
-// the cell's slots; a 32-lane exclusive scan of the match counts gives each lane its
-// write offset.  Rows come out in the same order as a sequential scan (stencil order,
-// then slot order inside a cell).  Offsets outside [off_lo, off_hi] (grids with < 3
-// cells along a dimension) are skipped so that no cell is visited twice.
-constexpr int kCellLanes = 32;
+// Cell-major build: one wavefront per cell of Morton rank r, four cells per workgroup.  The
+// cell's 27 stencil neighbours come from a table fixed at set-up (rank, or -1 for offsets
+// skipped on grids with fewer than 3 cells along a dimension, so that no cell is visited
+// twice; stencil order z, then y, then x offset); lanes 0..26 fetch their slot ranges and
+// a scan gives every candidate of the stencil an index k (stencil order, then slot order).  Home
+// molecules are taken 64 at a time (lane h holds home h's centre and running row length);
+// candidates 64 at a time (lane = candidate, its cell found by binary search in LDS), each
+// tested against every home of the batch: a ballot gives the hits' positions in the home's
+// row, so rows come out in stencil order, then slot order.  Each candidate centre is
+// loaded once per batch of homes, not once per home molecule.
+constexpr int kCmWaves = 4;
 
-__global__ __launch_bounds__(kBlock) void k_list_build_cells(DevParams P, Grid G, const int *__restrict__ cell_rank,
-                                                             const int *__restrict__ start,
-                                                             const double4 *__restrict__ Rw, double rl2,
-                                                             int *__restrict__ nbr, int *__restrict__ cnt, int cap,
-                                                             unsigned *__restrict__ mcost, Ctrl *ctrl)
+__global__ __launch_bounds__(kBlock) void k_list_build_cm(DevParams P, int n_cells, const int *__restrict__ stencil,
+                                                          const int *__restrict__ start,
+                                                          const double4 *__restrict__ Rw, double rl2,
+                                                          int *__restrict__ nbr, int *__restrict__ cnt, int cap,
+                                                          unsigned *__restrict__ mcost, Ctrl *ctrl)
 {
-    const int gid = blockIdx.x * kBlock + threadIdx.x;
-    const int t = gid / kCellLanes, lane = gid % kCellLanes;
-    const bool valid = t < P.n_mol;
-    const int tt = valid ? t : P.n_mol - 1;
-    const double4 me = Rw[tt];
-    // the home cell from the centre itself (the cell the last sort put the molecule in)
-    const int cx = cell_coord(me.x, G.inv_len[0], G.n[0]);
-    const int cy = cell_coord(me.y, G.inv_len[1], G.n[1]);
-    const int cz = cell_coord(me.z, G.inv_len[2], G.n[2]);
-    const int oz = lane / 9 - 1, oy = (lane / 3) % 3 - 1, ox = lane % 3 - 1;
-    const bool used = valid && lane < 27 && ox >= G.off_lo[0] && ox <= G.off_hi[0] && oy >= G.off_lo[1] &&
-                      oy <= G.off_hi[1] && oz >= G.off_lo[2] && oz <= G.off_hi[2];
-    int lo = 0, hi = 0;
-    if (used) {
-        const int r = cell_rank[wrap_cell(cx + ox, G.n[0]) +
-                                G.n[0] * (wrap_cell(cy + oy, G.n[1]) + G.n[1] * wrap_cell(cz + oz, G.n[2]))];
-        lo = start[r];
-        hi = start[r + 1];
-    }
-    // one pass over the cell's molecules, four centres requested at a time; a cell of at
-    // most 64 molecules keeps its hits as a bit mask, a larger one is scanned again below
-    const bool wide = hi - lo > 64;
-    uint64_t hits = 0;
-    int mine = 0;
-    for (int j0 = lo; j0 < hi; j0 += 4) {
-        double4 o[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) o[j] = Rw[j0 + j < hi ? j0 + j : lo];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int u = j0 + j;
-            if (u >= hi || u == t) continue;
-            const double dx = mi(o[j].x - me.x, P.box[0], P.half[0]);
-            const double dy = mi(o[j].y - me.y, P.box[1], P.half[1]);
-            const double dz = mi(o[j].z - me.z, P.box[2], P.half[2]);
-            if (dist2_exact(dx, dy, dz) < rl2) {
-                ++mine;
-                if (!wide) hits |= 1ull << (u - lo);
-            }
+    __shared__ int s_lo[kCmWaves][32], s_ex[kCmWaves][32];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = blockIdx.x * kCmWaves + wv;
+    if (r >= n_cells) return;   // whole wavefront
+    const int h0 = start[r], h1 = start[r + 1];
+    int lo = 0, c = 0;
+    if (lane < 27) {
+        const int nr = stencil[(int64_t)r * 27 + lane];
+        if (nr >= 0) {
+            lo = start[nr];
+            c = start[nr + 1] - lo;
         }
     }
-    int incl = mine;
+    if (h0 == h1) return;
+    int incl = c;
 #pragma unroll
-    for (int off = 1; off < kCellLanes; off <<= 1) {
-        const int y = __shfl_up(incl, off, kCellLanes);
+    for (int off = 1; off < 32; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
         if (lane >= off) incl += y;
     }
-    const int total = __shfl(incl, kCellLanes - 1, kCellLanes);
-    int *row = nbr + (int64_t)tt * cap;
-    int k = incl - mine;
-    if (!wide) {
-        while (hits) {
-            const int j = __builtin_ctzll(hits);
-            hits &= hits - 1;
-            if (k < cap) row[k] = lo + j;
-            ++k;
-        }
-    } else if (mine > 0) {
-        for (int u = lo; u < hi; ++u) {
-            if (u == t) continue;
-            const double4 o = Rw[u];
-            const double dx = mi(o.x - me.x, P.box[0], P.half[0]);
-            const double dy = mi(o.y - me.y, P.box[1], P.half[1]);
-            const double dz = mi(o.z - me.z, P.box[2], P.half[2]);
-            if (dist2_exact(dx, dy, dz) < rl2) {
-                if (k < cap) row[k] = u;
-                ++k;
+    const int total_c = __shfl(incl, 31, 64);   // lanes 27..31 carry the full sum
+    if (lane < 32) {
+        s_lo[wv][lane] = lo;
+        s_ex[wv][lane] = incl - c;
+    }
+    // lanes of one wavefront read what the others wrote above: LDS operations of a
+    // wavefront complete in order, and this keeps the compiler from moving the reads up
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const unsigned heavy = (unsigned)(P.spm * P.spm);
+    for (int hb = h0; hb < h1; hb += 64) {
+        const int nb = min(64, h1 - hb);
+        double4 hm = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (lane < nb) hm = Rw[hb + lane];
+        int base = 0;   // lane h: entries found so far for home hb + h
+        for (int c0 = 0; c0 < total_c; c0 += 64) {
+            const int k = c0 + lane;
+            const bool vk = k < total_c;
+            int slot = 0;
+            double4 o = make_double4(0.0, 0.0, 0.0, 0.0);
+            if (vk) {
+                // the stencil cell holding candidate k: the largest j with ex_j <= k
+                int a = 0, b = 26;
+                while (a < b) {
+                    const int m = (a + b + 1) >> 1;
+                    if (s_ex[wv][m] <= k) a = m;
+                    else b = m - 1;
+                }
+                slot = s_lo[wv][a] + (k - s_ex[wv][a]);
+                o = Rw[slot];
+            }
+            for (int h = 0; h < nb; ++h) {
+                const double mx = read_lane(hm.x, h), my = read_lane(hm.y, h), mz = read_lane(hm.z, h);
+                const int t = hb + h;
+                bool hit = false;
+                if (vk && slot != t) {
+                    const double dx = mi(o.x - mx, P.box[0], P.half[0]);
+                    const double dy = mi(o.y - my, P.box[1], P.half[1]);
+                    const double dz = mi(o.z - mz, P.box[2], P.half[2]);
+                    hit = dist2_exact(dx, dy, dz) < rl2;
+                }
+                const uint64_t m = __ballot(hit);
+                const int bh = __builtin_amdgcn_readlane(base, h);
+                if (hit) {
+                    const int pos = bh + __popcll(m & ((1ull << lane) - 1ull));
+                    if (pos < cap) nbr[(int64_t)t * cap + pos] = slot;
+                }
+                if (lane == h) base += __popcll(m);
             }
         }
-    }
-    if (valid && lane == kCellLanes - 1) {
-        cnt[t] = total;
-        // force-kernel cost estimate of the molecule (k_tile_order): its row, in atom pairs
-        // if it can be atomistic
-        const unsigned heavy = me.w > 0.0 ? (unsigned)(P.spm * P.spm) : 1u;
-        mcost[t] = (unsigned)min(total, cap) * heavy + 4u;
-        if (total > cap) {
-            atomicOr(&ctrl->overflow, 1);
-            atomicMax(&ctrl->max_count, total);
-            atomicMin(&ctrl->halt, -1);
-        } else {
-            for (int j = total; j < ((total + 3) & ~3); ++j) row[j] = t;   // padding: the row's own slot
+        if (lane < nb) {
+            const int t = hb + lane;
+            const int total = base;
+            cnt[t] = total;
+            mcost[t] = (unsigned)min(total, cap) * (hm.w > 0.0 ? heavy : 1u) + 4u;
+            if (total > cap) {
+                atomicOr(&ctrl->overflow, 1);
+                atomicMax(&ctrl->max_count, total);
+                atomicMin(&ctrl->halt, -1);
+            } else {
+                int *row = nbr + (int64_t)t * cap;
+                for (int j = total; j < ((total + 3) & ~3); ++j) row[j] = t;   // padding: own slot
+            }
         }
     }
 }
@@ -424,11 +432,11 @@ void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, cons
     }
 }
 
-void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank, const int *start,
+void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const int *stencil, const int *start,
                        const double4 *Rw, double rl2, int *nbr, int *cnt, int cap, unsigned *mcost, Ctrl *ctrl)
 {
-    const int blocks = (int)(((int64_t)P.n_mol * kCellLanes + kBlock - 1) / kBlock);
-    k_list_build_cells<<<blocks, kBlock, 0, s>>>(P, G, cell_rank, start, Rw, rl2, nbr, cnt, cap, mcost, ctrl);
+    const int blocks = (G.n_cells + kCmWaves - 1) / kCmWaves;
+    k_list_build_cm<<<blocks, kBlock, 0, s>>>(P, G.n_cells, stencil, start, Rw, rl2, nbr, cnt, cap, mcost, ctrl);
 }
 
 
