@@ -15,6 +15,12 @@
  *   - intramolecular bonds are not interpolated (Sec. 2.2) and are integrated
  *     everywhere (Sec. 2.3);
  *   - neighbours are found with a linked-cell list (Sec. 5, introduction).
+ * Beyond Eq. (1) the library offers potential energy interpolation, Eq. (2) (H-AdResS,
+ * Sec. 2.3: adres_params.scheme), a correction field along the resolution coordinate with
+ * its density profile and refinement (thermodynamic force, Sec. 2.4: adres_set_tdforce),
+ * self-adjusting AT regions made of spheres around moving anchor molecules (Sec. 2.5:
+ * ADRES_REGION_SPHERES) and RESPA multiple time stepping (Sec. 2.6:
+ * adres_integrate_respa).
  *
  * Conventions for every call:
  *   - Units: lengths in sigma (atom diameter), energies in epsilon, masses in atom
