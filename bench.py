@@ -57,6 +57,8 @@ def main():
                     help="skip the multiple-time-stepping (RESPA) leg")
     ap.add_argument("--no-anchors", action="store_true",
                     help="skip the self-adjusting (anchor spheres) region leg")
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the 1M-tetrahedron heterogeneous run inside the learned-CG leg")
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes 10 times "
@@ -82,7 +84,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.cg_only:
-        print(json.dumps({"learned_vs_tabulated": learned_vs_tabulated(args.cg_steps)}))
+        print(json.dumps({"learned_vs_tabulated": learned_vs_tabulated(args.cg_steps, not args.no_c5)}))
         return
     dev = torch.device("cuda:0")
     wl = inputs.workload(args.workload)
@@ -181,7 +183,7 @@ def main():
     if not args.no_anchors:
         out["self_adjusting_region"] = anchors_leg(wl, x, v, args.steps, args.warmup)
     if not args.no_cg_compare:
-        out["learned_vs_tabulated"] = learned_vs_tabulated(args.cg_steps)
+        out["learned_vs_tabulated"] = learned_vs_tabulated(args.cg_steps, not args.no_c5)
 
     if not args.no_cpu_baseline:
         import oracle
@@ -424,7 +426,7 @@ def _measured_traffic():
         return None
 
 
-def learned_vs_tabulated(cg_steps):
+def learned_vs_tabulated(cg_steps, with_c5=True):
     """Force RMSE and MD steps/s of the learned and the tabulated CG force (256k sites)."""
     import torch
     from paper_1806_10841_amd import binding, cgtrain, inputs
@@ -474,7 +476,7 @@ def learned_vs_tabulated(cg_steps):
         rec["listed_pairs"] = ctx.build_verlet(xt)
         ctx.close()
         runs[name] = rec
-    c5 = large_heterogeneous(table, params, scale, tw, r_min)
+    c5 = large_heterogeneous(table, params, scale, tw, r_min) if with_c5 else None
     pairs = runs["mlp"]["listed_pairs"]
     flop_per_pair = 2 * 64 * 64 + 2 * 64 + 2 * 64 + 2
     mlp_tflops = flop_per_pair * pairs / (runs["mlp"]["mlp_prepass_us"] * 1e-6) / 1e12

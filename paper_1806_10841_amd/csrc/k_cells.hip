@@ -222,7 +222,7 @@ __device__ __forceinline__ double read_lane(double v, int h)
 // twice; stencil order z, then y, then x offset); lanes 0..26 fetch their slot ranges and
 // a scan gives every candidate of the stencil an index k (stencil order, then slot order).  Home
 // molecules are taken 64 at a time (lane h holds home h's centre and running row length);
-// candidates 64 at a time (lane = candidate, its cell found by binary search in LDS), each
+// candidates 128 at a time (two per lane, cell found by binary search in LDS), each
 // tested against every home of the batch: a ballot gives the hits' positions in the home's
 // row, so rows come out in stencil order, then slot order.  Each candidate centre is
 // loaded once per batch of homes, not once per home molecule.
@@ -269,39 +269,49 @@ __global__ __launch_bounds__(kBlock) void k_list_build_cm(DevParams P, int n_cel
         double4 hm = make_double4(0.0, 0.0, 0.0, 0.0);
         if (lane < nb) hm = Rw[hb + lane];
         int base = 0;   // lane h: entries found so far for home hb + h
-        for (int c0 = 0; c0 < total_c; c0 += 64) {
-            const int k = c0 + lane;
-            const bool vk = k < total_c;
-            int slot = 0;
-            double4 o = make_double4(0.0, 0.0, 0.0, 0.0);
-            if (vk) {
-                // the stencil cell holding candidate k: the largest j with ex_j <= k
-                int a = 0, b = 26;
-                while (a < b) {
-                    const int m = (a + b + 1) >> 1;
-                    if (s_ex[wv][m] <= k) a = m;
-                    else b = m - 1;
+        // candidates 128 at a time, two per lane, both centres requested before the tests
+        for (int c0 = 0; c0 < total_c; c0 += 128) {
+            int slot[2] = {0, 0};
+            bool vk[2];
+            double4 o[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int k = c0 + 64 * u + lane;
+                vk[u] = k < total_c;
+                o[u] = make_double4(0.0, 0.0, 0.0, 0.0);
+                if (vk[u]) {
+                    // the stencil cell holding candidate k: the largest j with ex_j <= k
+                    int a = 0, b = 26;
+                    while (a < b) {
+                        const int m = (a + b + 1) >> 1;
+                        if (s_ex[wv][m] <= k) a = m;
+                        else b = m - 1;
+                    }
+                    slot[u] = s_lo[wv][a] + (k - s_ex[wv][a]);
+                    o[u] = Rw[slot[u]];
                 }
-                slot = s_lo[wv][a] + (k - s_ex[wv][a]);
-                o = Rw[slot];
             }
             for (int h = 0; h < nb; ++h) {
                 const double mx = read_lane(hm.x, h), my = read_lane(hm.y, h), mz = read_lane(hm.z, h);
                 const int t = hb + h;
-                bool hit = false;
-                if (vk && slot != t) {
-                    const double dx = mi(o.x - mx, P.box[0], P.half[0]);
-                    const double dy = mi(o.y - my, P.box[1], P.half[1]);
-                    const double dz = mi(o.z - mz, P.box[2], P.half[2]);
-                    hit = dist2_exact(dx, dy, dz) < rl2;
+                int bh = __builtin_amdgcn_readlane(base, h);
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    bool hit = false;
+                    if (vk[u] && slot[u] != t) {
+                        const double dx = mi(o[u].x - mx, P.box[0], P.half[0]);
+                        const double dy = mi(o[u].y - my, P.box[1], P.half[1]);
+                        const double dz = mi(o[u].z - mz, P.box[2], P.half[2]);
+                        hit = dist2_exact(dx, dy, dz) < rl2;
+                    }
+                    const uint64_t m = __ballot(hit);
+                    if (hit) {
+                        const int pos = bh + __popcll(m & ((1ull << lane) - 1ull));
+                        if (pos < cap) nbr[(int64_t)t * cap + pos] = slot[u];
+                    }
+                    bh += __popcll(m);
                 }
-                const uint64_t m = __ballot(hit);
-                const int bh = __builtin_amdgcn_readlane(base, h);
-                if (hit) {
-                    const int pos = bh + __popcll(m & ((1ull << lane) - 1ull));
-                    if (pos < cap) nbr[(int64_t)t * cap + pos] = slot;
-                }
-                if (lane == h) base += __popcll(m);
+                if (lane == h) base = bh;
             }
         }
         if (lane < nb) {
