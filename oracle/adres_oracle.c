@@ -191,20 +191,45 @@ static void orc_weight_gradient(const orc_params *P, const double R[3], double g
  * end value held from lo to d_0 and from d_{n-1} to hi, zero outside [lo, hi).  Its
  * potential is U(d) = -integral of F from lo to min(d, hi) (0 below lo), integrated here
  * piece by piece.  dir receives the unit direction, *u the potential, *scale the sum of
- * the magnitudes of the table values F depends on (the term scale of the force). */
-static double orc_td_force(const orc_params *P, const double R[3], double dir[3], double *u,
-                           double *scale)
+ * the magnitudes of the table values F depends on (the term scale of the force).  com
+ * holds all centres of mass (the anchors' for a self-adjusting region). */
+static double orc_td_force(const orc_params *P, const double *com, const double R[3], double dir[3],
+                           double *u, double *scale)
 {
     dir[0] = dir[1] = dir[2] = 0.0;
     *u = 0.0;
     *scale = 0.0;
-    if (P->td_n <= 0 || (P->region != ORC_REGION_SLAB && P->region != ORC_REGION_SPHERE)) return 0.0;
-    double d = orc_region_distance(P, R);
-    if (d > 0.0) {
-        if (P->region == ORC_REGION_SLAB) {
-            dir[0] = orc_mi(R[0] - P->center[0], P->box[0]) > 0.0 ? 1.0 : -1.0;
-        } else {
-            for (int k = 0; k < 3; ++k) dir[k] = orc_mi(R[k] - P->center[k], P->box[k]) / d;
+    if (P->td_n <= 0 ||
+        (P->region != ORC_REGION_SLAB && P->region != ORC_REGION_SPHERE && P->region != ORC_REGION_SPHERES))
+        return 0.0;
+    double d;
+    if (P->region == ORC_REGION_SPHERES) {
+        /* self-adjusting region (Sec. 2.5 with Sec. 2.4).  Reading: the field acts along the
+         * offset from the nearest anchor centre (the first of equally near ones), with the
+         * table of a single sphere; the anchors feel no reaction (an external field) */
+        int64_t n = P->n_mol;
+        double best = INFINITY, qb[3] = {0.0, 0.0, 0.0};
+        for (int32_t k = 0; k < P->n_anchors; ++k) {
+            int64_t b = P->anchors[k];
+            double q[3];
+            for (int c = 0; c < 3; ++c) q[c] = orc_mi(R[c] - com[c * n + b], P->box[c]);
+            double r2 = (q[0] * q[0] + q[1] * q[1]) + q[2] * q[2];
+            if (r2 < best) {
+                best = r2;
+                qb[0] = q[0]; qb[1] = q[1]; qb[2] = q[2];
+            }
+        }
+        d = sqrt(best);
+        if (d > 0.0)
+            for (int k = 0; k < 3; ++k) dir[k] = qb[k] / d;
+    } else {
+        d = orc_region_distance(P, R);
+        if (d > 0.0) {
+            if (P->region == ORC_REGION_SLAB) {
+                dir[0] = orc_mi(R[0] - P->center[0], P->box[0]) > 0.0 ? 1.0 : -1.0;
+            } else {
+                for (int k = 0; k < 3; ++k) dir[k] = orc_mi(R[k] - P->center[k], P->box[k]) / d;
+            }
         }
     }
     int n = P->td_n;
@@ -535,7 +560,7 @@ static int orc_mol_forces(const orc_params *P, const double *x, const double *co
 
     if (P->td_n > 0 && part != ORC_PART_FAST) {
         double dir[3], ut, sc;
-        double ft = orc_td_force(P, Ra, dir, &ut, &sc);
+        double ft = orc_td_force(P, com, Ra, dir, &ut, &sc);
         for (int i = 0; i < spm; ++i) {
             double mf = P->mass[i] / M;
             for (int q = 0; q < 3; ++q) fa[3 * i + q] += mf * ft * dir[q];

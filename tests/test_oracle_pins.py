@@ -748,3 +748,53 @@ class TestAnchorSpheres:
         f, amag, _, st = oracle.Model(wl, anchors=an).forces(x)
         assert st == 0
         assert np.all(np.abs(f.sum(axis=1)) <= 64 * EPS * amag.sum())
+
+    def test_one_anchor_with_correction_is_a_static_sphere(self):
+        wl = self._wl()
+        x, _ = inputs.make_state(wl)
+        an = np.array([417], dtype=np.int32)
+        td = (np.linspace(1.0, -0.5, 10), 1.0, 5.5)
+        m = oracle.Model(wl, anchors=an, td=td)
+        com, _, _, _ = m.weights(x)
+        ws = wl.with_(region=inputs.REGION_SPHERE, center=tuple(com[:, 417]))
+        f1, _, e1, _ = m.forces(x)
+        f2, _, e2, _ = oracle.Model(ws, td=td).forces(x)
+        np.testing.assert_array_equal(f1, f2)
+        np.testing.assert_array_equal(e1, e2)
+        assert e1[3] != 0.0
+
+    def test_correction_points_away_from_the_nearest_anchor(self):
+        # three single-site molecules far apart: anchors 0 and 1, molecule 2 nearer to 1
+        wl = _wl(n_mol=3, region=inputs.REGION_SPHERES, d_at=1.0, d_hy=1.0, box=(30.0, 30.0, 30.0),
+                 center=(15.0, 15.0, 15.0))
+        x = _soa([[5.0, 5.0, 5.0], [20.0, 20.0, 20.0], [22.0, 21.5, 21.5]])   # beyond every pair cutoff
+        F = np.linspace(2.0, 3.0, 8)
+        lo, hi = 0.5, 4.5
+        f, _, e, st = oracle.Model(wl, anchors=np.array([0, 1], np.int32), td=(F, lo, hi)).forces(x)
+        assert st == 0
+        q = x[:, 2] - x[:, 1]
+        d = np.linalg.norm(q)
+        h = (hi - lo) / len(F)
+        val = np.interp(d, lo + (np.arange(len(F)) + 0.5) * h, F)
+        np.testing.assert_allclose(f[:, 2], val * q / d, rtol=1e-12)
+        np.testing.assert_array_equal(f[:, :2], 0.0)    # anchors: d = 0, no reaction
+
+    def test_correction_is_minus_gradient_for_non_anchor_sites(self):
+        # w == 1 everywhere (anchor spheres larger than the box): pair forces are
+        # conservative, the correction is the gradient of U_corr for every non-anchor site
+        wl = inputs.workload("tiny_slab").with_(region=inputs.REGION_SPHERES, d_at=20.0, d_hy=1.0)
+        x, _ = inputs.make_state(wl, seed=3)
+        an = np.array([5, 40], dtype=np.int32)
+        td = (np.random.default_rng(2).normal(size=12), 0.2, 4.0)
+        m = oracle.Model(wl, anchors=an, td=td)
+        f, amag, e, st = m.forces(x)
+        assert st == 0 and e[3] != 0.0
+        rng = np.random.default_rng(0)
+        sites = [s for s in range(x.shape[1]) if s // 4 not in an]
+        for _ in range(16):
+            qd, s = rng.integers(3), int(rng.choice(sites))
+            xp, xm = x.copy(), x.copy()
+            xp[qd, s] += 1e-6
+            xm[qd, s] -= 1e-6
+            fd = -(m.forces(xp)[2].sum() - m.forces(xm)[2].sum()) / 2e-6
+            assert abs(f[qd, s] - fd) < 2e-5 * max(1.0, amag[s]), (qd, s, f[qd, s], fd)
