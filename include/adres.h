@@ -67,7 +67,8 @@ typedef enum {
 
 /* ADRES_REGION_SPHERES: a self-adjusting AT region (Sec. 2.5), the union of spheres of radius
  * d_at (hybrid shell d_hy) around the current centres of mass of anchor molecules chosen with
- * adres_set_anchors; the region moves with them.  Force interpolation only. */
+ * adres_set_anchors; the region moves with them.  Force interpolation only; a correction
+ * field (adres_set_tdforce) acts around the nearest anchor. */
 enum { ADRES_REGION_ALL_AT = 0, ADRES_REGION_SLAB_X = 1, ADRES_REGION_SPHERE = 2, ADRES_REGION_ALL_CG = 3,
        ADRES_REGION_SPHERES = 4 };
 /* CG force between centres of mass: analytic WCA, cubic table, learned network with layer 2
@@ -202,13 +203,17 @@ adres_status adres_set_cg_table(adres_ctx *ctx, const float *coef4, int32_t n_kn
  * correction of Sec. 2.4, a field over the hybrid region that flattens the density
  * profile across it.  It acts on each molecule's centre of mass along the direction in
  * which the distance d from the AT centre grows (slab: sign of the minimum-image x
- * offset; sphere: the unit offset; none at d = 0) and reaches the sites by mass fraction,
+ * offset; sphere: the unit offset; anchor spheres: the unit offset from the nearest anchor
+ * centre, the first of equally near ones, with no reaction on the anchors; none at d = 0)
+ * and reaches the sites by mass fraction,
  * in every later force evaluation (adres_forces, adres_integrate, adres_map_cg).
  * table (host, float64 [n]) holds its value F_k at the bin centres
  * d_k = d_lo + (k + 1/2) h, h = (d_hi - d_lo) / n; F(d) is linear between neighbouring
  * centres, holds F_0 from d_lo to d_0 and F_{n-1} from d_{n-1} to d_hi, and is 0 outside
  * [d_lo, d_hi).  Its potential -integral of F from d_lo to min(d, d_hi) is reported as
- * U_corr.  Needs region ADRES_REGION_SLAB_X or ADRES_REGION_SPHERE; 1 <= n <= 4096,
+ * U_corr.  Needs region ADRES_REGION_SLAB_X, ADRES_REGION_SPHERE or ADRES_REGION_SPHERES
+ * (for the last the table is that of a single sphere, e.g. refined with region
+ * ADRES_REGION_SPHERE and the same d_at, d_hy); 1 <= n <= 4096,
  * 0 <= d_lo < d_hi, finite values (ADRES_E_ARG otherwise).  n = 0 removes the correction.
  * Copied; synchronises. */
 adres_status adres_set_tdforce(adres_ctx *ctx, const double *table, int32_t n, double d_lo, double d_hi);
@@ -222,7 +227,8 @@ adres_status adres_get_tdforce(adres_ctx *ctx, double *table_host, int32_t n);
  * correction table: adds to counts (device, int64 [n], caller-initialised) the number of
  * molecules of x (device, caller order) whose centre-of-mass distance d from the AT
  * centre lies in bin floor((d - d_lo) / h) of [d_lo, d_hi).  Call once per sampled frame.
- * ADRES_E_STATE without a table.  Asynchronous. */
+ * ADRES_E_STATE without a table; ADRES_E_ARG for ADRES_REGION_SPHERES (the bins of a union of
+ * moving spheres have no closed-form volume).  Asynchronous. */
 adres_status adres_density_profile(adres_ctx *ctx, const double *x, int64_t *counts);
 
 /* One refinement of the correction force from a density profile (Sec. 2.4: the
@@ -231,8 +237,8 @@ adres_status adres_density_profile(adres_ctx *ctx, const double *x, int64_t *cou
  * mid-plane, 2 h L_y L_z; sphere: the shell 4/3 pi (r_{k+1}^3 - r_k^3), r_k = d_lo + k h),
  * then F_k <- F_k - prefactor * (drho/dd)_k with the slope by central differences of the
  * neighbouring bins (one-sided at the two end bins, 0 for a single bin).  The usual
- * prefactor is M / (rho_0^2 kappa_T).  counts: device int64 [n], n_frames >= 1.
- * Asynchronous. */
+ * prefactor is M / (rho_0^2 kappa_T).  counts: device int64 [n], n_frames >= 1; not for
+ * ADRES_REGION_SPHERES (ADRES_E_ARG).  Asynchronous. */
 adres_status adres_tdforce_update(adres_ctx *ctx, const int64_t *counts, int64_t n_frames, double prefactor);
 
 /* Anchors of a self-adjusting AT region (region ADRES_REGION_SPHERES, Sec. 2.5): mols (host,

@@ -48,6 +48,7 @@ struct adres_ctx {
     float4 *tab = nullptr;
     double *td = nullptr, *td_u = nullptr;   // correction force table and its integrals
     int *anchors = nullptr;                  // anchor molecules of a self-adjusting region
+    double4 *near = nullptr;                 // offset from the nearest anchor per slot
     int *tile_order = nullptr;               // force kernel dispatch order (per list build)
     unsigned *mcost = nullptr;               // per-molecule cost estimates (list build)
     int *stencil = nullptr;                  // [n_cells][27] neighbour cell ranks (static grid)
@@ -163,7 +164,7 @@ adres_status gather(adres_ctx *c, const double *x, const double *v, bool check_d
 {
     launch_gather(c->stream, c->P, x, v, cur(c), check_disp ? c->R_ref : nullptr, c->ctrl);
     if (c->P.region == ADRES_REGION_SPHERES)
-        launch_anchor_weights(c->stream, c->P, cur(c).Rw, c->inv_perm, c->ctrl, 0, 0);
+        launch_anchor_weights(c->stream, c->P, cur(c).Rw, c->inv_perm, c->ctrl, 0, 0, c->near);
     HIPCHK(c, hipGetLastError());
     return ADRES_OK;
 }
@@ -177,6 +178,9 @@ adres_status resort(adres_ctx *c, bool with_v)
     launch_scatter_slots(c->stream, c->P.n_mol, src.key, c->start, c->fill, c->new_from);
     launch_sort_within_cells(c->stream, c->G.n_cells, c->start, src.perm, c->new_from);
     launch_permute(c->stream, c->P, c->new_from, src, dst, c->inv_perm, c->R_ref, with_v);
+    // the nearest-anchor offsets are per slot: recompute them in the new order
+    if (c->P.region == ADRES_REGION_SPHERES)
+        launch_anchor_weights(c->stream, c->P, dst.Rw, c->inv_perm, c->ctrl, 0, 0, c->near);
     HIPCHK(c, hipGetLastError());
     c->pos = 1 - c->pos;
     c->ord = 1 - c->ord;
@@ -292,6 +296,7 @@ ForceArgs force_args(adres_ctx *c)
     a.mode = kModeForce;
     a.slow_scale = 1.0;
     a.tile_order = c->tile_order;
+    a.near = c->near;
     return a;
 }
 
@@ -513,6 +518,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     ok = ok && dalloc(&c->tile_order, (size_t)c->epart_blocks) == hipSuccess &&
          dalloc(&c->mcost, (size_t)n) == hipSuccess &&
          dalloc(&c->stencil, (size_t)G.n_cells * 27) == hipSuccess;
+    if (q.region == ADRES_REGION_SPHERES) ok = ok && dalloc(&c->near, (size_t)n) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&c->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&c->pub, sizeof(CtrlPub), hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
     if (ok) {
@@ -555,7 +561,7 @@ void adres_destroy(adres_ctx *c)
     hipFree(c->R_ref); hipFree(c->inv_perm); hipFree(c->cell_rank);
     hipFree(c->count); hipFree(c->start); hipFree(c->fill); hipFree(c->new_from); hipFree(c->scan_tiles);
     hipFree(c->nbr); hipFree(c->cnt); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
-    hipFree(c->td); hipFree(c->td_u); hipFree(c->anchors); hipFree(c->tile_order); hipFree(c->mcost); hipFree(c->stencil);
+    hipFree(c->td); hipFree(c->td_u); hipFree(c->anchors); hipFree(c->near); hipFree(c->tile_order); hipFree(c->mcost); hipFree(c->stencil);
     hipFree(c->mlp); hipFree(c->mlp_w2); hipFree(c->mlp_w2q); hipFree(c->mlp_fp8s); hipFree(c->cnt_up); hipFree(c->up_off); hipFree(c->up_scratch);
     hipFree(c->pid); hipFree(c->up_pairs); hipFree(c->f_pair);
     hipFree(c->adam_m); hipFree(c->adam_v); hipFree(c->grad); hipFree(c->loss); hipFree(c->res_part);
@@ -686,7 +692,7 @@ adres_status integrate_impl(adres_ctx *c, double *x, double *v, double *f, doubl
                 launch_kick_drift(c->stream, c->P, in.x, in.v, c->f, out.x, out.Rw, out.rho, out.off, c->R_ref,
                                   in.perm, c->ctrl, k, sa);
                 if (c->P.region == ADRES_REGION_SPHERES)
-                    launch_anchor_weights(c->stream, c->P, out.Rw, c->inv_perm, c->ctrl, k, 1);
+                    launch_anchor_weights(c->stream, c->P, out.Rw, c->inv_perm, c->ctrl, k, 1, c->near);
                 HIPCHK(c, hipGetLastError());
             } else {
                 ForceArgs a = force_args(c);
@@ -713,7 +719,7 @@ adres_status integrate_impl(adres_ctx *c, double *x, double *v, double *f, doubl
                 st = run_forces(c, a);
                 if (st != ADRES_OK) return st;
                 if (gk < n_steps && c->P.region == ADRES_REGION_SPHERES) {
-                    launch_anchor_weights(c->stream, c->P, out.Rw, c->inv_perm, c->ctrl, k, 1);
+                    launch_anchor_weights(c->stream, c->P, out.Rw, c->inv_perm, c->ctrl, k, 1, c->near);
                     HIPCHK(c, hipGetLastError());
                 }
             }
@@ -846,8 +852,9 @@ adres_status adres_set_tdforce(adres_ctx *c, const double *table, int32_t n, dou
         return ADRES_OK;
     }
     if (!table) return fail(c, ADRES_E_ARG, "null argument");
-    if (c->P.region != ADRES_REGION_SLAB_X && c->P.region != ADRES_REGION_SPHERE)
-        return fail(c, ADRES_E_ARG, "a correction force needs a slab or sphere region");
+    if (c->P.region != ADRES_REGION_SLAB_X && c->P.region != ADRES_REGION_SPHERE &&
+        c->P.region != ADRES_REGION_SPHERES)
+        return fail(c, ADRES_E_ARG, "a correction force needs a slab, sphere or anchor-sphere region");
     if (n < 0 || n > kTdMaxBins || !std::isfinite(d_lo) || !std::isfinite(d_hi) || !(d_lo >= 0.0) ||
         !(d_hi > d_lo))
         return fail(c, ADRES_E_ARG, "correction table needs 1..4096 values on 0 <= d_lo < d_hi");
@@ -900,6 +907,8 @@ adres_status adres_density_profile(adres_ctx *c, const double *x, int64_t *count
 {
     if (!c || !x || !counts) return fail(c, ADRES_E_ARG, "null argument");
     if (c->P.td_n == 0) return fail(c, ADRES_E_STATE, "no correction table (its bins define the profile)");
+    if (c->P.region == ADRES_REGION_SPHERES)
+        return fail(c, ADRES_E_ARG, "density profiles need a slab or sphere region (bin volumes)");
     launch_density_profile(c->stream, c->P, x, reinterpret_cast<unsigned long long *>(counts));
     HIPCHK(c, hipGetLastError());
     return ADRES_OK;
@@ -910,6 +919,8 @@ adres_status adres_tdforce_update(adres_ctx *c, const int64_t *counts, int64_t n
     if (!c || !counts) return fail(c, ADRES_E_ARG, "null argument");
     if (c->P.td_n == 0) return fail(c, ADRES_E_STATE, "no correction force installed");
     if (n_frames < 1 || !std::isfinite(prefactor)) return fail(c, ADRES_E_ARG, "need n_frames >= 1, finite prefactor");
+    if (c->P.region == ADRES_REGION_SPHERES)
+        return fail(c, ADRES_E_ARG, "refinement needs a slab or sphere region (bin volumes)");
     launch_td_update(c->stream, c->P, c->td, c->td_u, reinterpret_cast<const long long *>(counts),
                      (long long)n_frames, prefactor);
     HIPCHK(c, hipGetLastError());

@@ -189,13 +189,13 @@ __device__ __forceinline__ double res_distance(const DevParams &P, const double 
 // from the table (linear between bin centres, the end values held out to td_lo and
 // td_hi, 0 outside [td_lo, td_hi)), its unit direction (the gradient of d) in dir, and
 // with ENERGY its potential -integral of F from td_lo to min(d, td_hi) in u.
+// The same from a distance d and the offset q it was measured along (slab: x only).
 template <bool ENERGY>
-__device__ __forceinline__ double corr_force(const DevParams &P, const double R[3], double dir[3], double &u)
+__device__ __forceinline__ double corr_force_dq(const DevParams &P, double d, const double q[3], double dir[3],
+                                                double &u)
 {
     dir[0] = dir[1] = dir[2] = 0.0;
     u = 0.0;
-    double q[3];
-    const double d = res_distance(P, R, q);
     if (!(d >= P.td_lo)) return 0.0;
     const int n = P.td_n;
     const double t = (d - P.td_lo) / P.td_h - 0.5;   // in bin widths from the first centre
@@ -226,6 +226,14 @@ __device__ __forceinline__ double corr_force(const DevParams &P, const double R[
         }
     }
     return f;
+}
+
+template <bool ENERGY>
+__device__ __forceinline__ double corr_force(const DevParams &P, const double R[3], double dir[3], double &u)
+{
+    double q[3];
+    const double d = res_distance(P, R, q);
+    return corr_force_dq<ENERGY>(P, d, q, dir, u);
 }
 
 // Resolution weight of a distance from the AT centre (1 up to d_at, cos^2 ramp across
@@ -504,6 +512,8 @@ struct ForceArgs {
     double slow_scale;
     // dispatch order of the workgroups (launch_tile_order), or null for the identity
     const int *tile_order;
+    // self-adjusting region: offset from the nearest anchor centre and its length per slot
+    const double4 *near;
 };
 // returns the block count; e0/e1 (optional) are recorded at the kernel's start and end
 int launch_forces(hipStream_t s, const ForceArgs &a, int pair_precision, hipEvent_t e0 = nullptr,
@@ -521,11 +531,12 @@ void launch_td_update(hipStream_t s, const DevParams &P, double *td, double *td_
                       long long n_frames, double prefactor);
 
 // self-adjusting region (k_state.hip): weights from the nearest anchor centre, for the
-// Morton-ordered state (Rw in place; anchors located through inv_perm; skipped like the
-// step kernels once a chunk has halted) or for caller-order centres (com [3][n] -> w)
+// Morton-ordered state (Rw in place, and the offset from the nearest anchor with its
+// length into near; anchors located through inv_perm; skipped like the step kernels once
+// a chunk has halted) or for caller-order centres (com [3][n] -> w)
 constexpr int kMaxAnchors = 1024;
 void launch_anchor_weights(hipStream_t s, const DevParams &P, double4 *Rw, const int *inv_perm, Ctrl *ctrl,
-                           int step, int check_halt);
+                           int step, int check_halt, double4 *near);
 void launch_anchor_weights_caller(hipStream_t s, const DevParams &P, const double *com, double *w);
 
 }  // namespace adres

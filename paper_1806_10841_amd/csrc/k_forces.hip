@@ -285,8 +285,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     // correction force on the centre of mass along the resolution coordinate (Sec. 2.4)
     double tdir[3] = {0.0, 0.0, 0.0}, ucorr = 0.0, ftd = 0.0;
     if (P.td_n > 0 && with_slow) {
-        const double Rm[3] = {me.x, me.y, me.z};
-        ftd = corr_force<ENERGY>(P, Rm, tdir, ucorr);
+        if (P.region == ADRES_REGION_SPHERES) {   // along the offset from the nearest anchor
+            const double4 nr = a.near[tt];
+            const double qn[3] = {nr.x, nr.y, nr.z};
+            ftd = corr_force_dq<ENERGY>(P, nr.w, qn, tdir, ucorr);
+        } else {
+            const double Rm[3] = {me.x, me.y, me.z};
+            ftd = corr_force<ENERGY>(P, Rm, tdir, ucorr);
+        }
     }
 
     // lane q owns site q

@@ -237,7 +237,8 @@ __global__ __launch_bounds__(kBlock) void k_td_update(DevParams P, double *__res
 // from inv_perm and only the w component of Rw is written (centres are read as three
 // scalars, so the stores never overlap a read).
 __global__ __launch_bounds__(kBlock) void k_anchor_weights(DevParams P, double4 *Rw, const int *__restrict__ inv_perm,
-                                                           Ctrl *ctrl, int step, int check_halt)
+                                                           Ctrl *ctrl, int step, int check_halt,
+                                                           double4 *__restrict__ near)
 {
 #pragma clang fp contract(off)
     if (check_halt && step > ctrl->halt) return;
@@ -254,15 +255,20 @@ __global__ __launch_bounds__(kBlock) void k_anchor_weights(DevParams P, double4 
     if (t >= P.n_mol) return;
     double *me = reinterpret_cast<double *>(Rw + t);
     const double R0 = me[0], R1 = me[1], R2 = me[2];
-    double best = INFINITY;
+    double best = INFINITY, b0 = 0.0, b1 = 0.0, b2 = 0.0;
     for (int k = 0; k < K; ++k) {
         const double q0 = mi(R0 - cen[k][0], P.box[0], P.half[0]);
         const double q1 = mi(R1 - cen[k][1], P.box[1], P.half[1]);
         const double q2 = mi(R2 - cen[k][2], P.box[2], P.half[2]);
         const double r2 = dist2_exact(q0, q1, q2);
-        best = r2 < best ? r2 : best;
+        if (r2 < best) {   // the first of equally near anchors
+            best = r2;
+            b0 = q0; b1 = q1; b2 = q2;
+        }
     }
-    me[3] = weight_of_distance(P, sqrt(best));
+    const double d = sqrt(best);
+    me[3] = weight_of_distance(P, d);
+    if (near) near[t] = make_double4(b0, b1, b2, d);
 }
 
 // The same for caller-order centres com [3][n_mol] into w [n_mol].
@@ -380,9 +386,9 @@ void launch_td_update(hipStream_t s, const DevParams &P, double *td, double *td_
 }
 
 void launch_anchor_weights(hipStream_t s, const DevParams &P, double4 *Rw, const int *inv_perm, Ctrl *ctrl,
-                           int step, int check_halt)
+                           int step, int check_halt, double4 *near)
 {
-    k_anchor_weights<<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, Rw, inv_perm, ctrl, step, check_halt);
+    k_anchor_weights<<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, Rw, inv_perm, ctrl, step, check_halt, near);
 }
 
 void launch_anchor_weights_caller(hipStream_t s, const DevParams &P, const double *com, double *w)

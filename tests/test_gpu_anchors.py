@@ -158,8 +158,12 @@ def test_errors(dev):
             c.set_anchors(bad)
     c.set_anchors(np.array([3], np.int32))
     assert torch.isfinite(c.forces(xt)).all()
-    with pytest.raises(binding.AdresError):            # a correction field needs a slab or sphere
-        c.set_tdforce(np.ones(4), 1.0, 3.0)
+    c.set_tdforce(np.ones(4), 1.0, 3.0)                 # a correction field is allowed ...
+    counts = torch.zeros(4, dtype=torch.int64, device=dev)
+    with pytest.raises(binding.AdresError):            # ... but no profile (no bin volumes)
+        c.density_profile(xt, counts)
+    with pytest.raises(binding.AdresError):
+        c.tdforce_update(counts, 1, 1.0)
     with pytest.raises(binding.AdresError):
         binding.Context(wl.with_(scheme=inputs.SCHEME_HAMILTONIAN))
     s = binding.Context(inputs.workload("small_sphere"))
@@ -180,5 +184,43 @@ def test_respa_with_anchor_spheres_matches_oracle(dev):
     ft = torch.empty_like(xt)
     ctx.integrate_respa(xt, vt, ft, wl.dt / 2, 2, 40)
     torch.cuda.synchronize()
+    assert np.abs(_min_image(xt.cpu().numpy() - xo, wl.box[0])).max() < 1e-9
+    assert np.abs(vt.cpu().numpy() - vo).max() < 1e-7
+
+
+@pytest.mark.parametrize("name,k,prec", [("small_sphere", 9, 64), ("c1", 5, 64), ("small_sphere", 9, 32)])
+def test_forces_with_correction_around_anchors(dev, name, k, prec):
+    """A correction field around the nearest anchor (Sec. 2.5 with Sec. 2.4): forces and
+    the correction potential against the oracle."""
+    wl = _wl(name, pair_precision=prec)
+    an = inputs.anchor_molecules(wl.n_mol, k, 4)
+    td = (np.linspace(0.8, -0.3, 16), 1.5, 5.0)
+    x, _ = inputs.make_state(wl)
+    fo, amag, eo, st = oracle.Model(wl, anchors=an, td=td).forces(x)
+    assert st == 0 and eo[3] != 0.0
+    c = _ctx(wl, an)
+    c.set_tdforce(*td)
+    f, e = c.forces(_t(x, dev), energy=True)
+    torch.cuda.synchronize()
+    tol = 1e-12 if prec == 64 else 1e-5
+    _assert_close(f.cpu().numpy(), fo, amag, tol, name)
+    np.testing.assert_allclose(e.cpu().numpy(), eo, rtol=tol, atol=tol * np.abs(eo).max())
+
+
+def test_integrate_with_correction_around_anchors(dev):
+    """The nearest-anchor offsets follow the anchors through steps and list rebuilds."""
+    wl = _wl("c1", pair_precision=64)
+    an = inputs.anchor_molecules(wl.n_mol, 5, 7)
+    td = (np.linspace(0.8, -0.3, 16), 1.5, 5.0)
+    x, v = inputs.make_state(wl)
+    xo, vo, _, _, st = oracle.Model(wl, anchors=an, td=td).vv(x, v, wl.dt, 100)
+    assert st == 0
+    c = _ctx(wl, an)
+    c.set_tdforce(*td)
+    xt, vt = _t(x, dev), _t(v, dev)
+    ft = torch.empty_like(xt)
+    nreb = c.integrate(xt, vt, ft, wl.dt, 100)
+    torch.cuda.synchronize()
+    assert nreb >= 1
     assert np.abs(_min_image(xt.cpu().numpy() - xo, wl.box[0])).max() < 1e-9
     assert np.abs(vt.cpu().numpy() - vo).max() < 1e-7
