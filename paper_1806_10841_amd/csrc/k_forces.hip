@@ -82,13 +82,19 @@ __device__ __forceinline__ PT table_f(const DevParams &P, double r, Ctrl *ctrl)
 
 // At most 128 VGPRs (4 waves per SIMD): 4 lanes x 64k molecules is ~4000 wavefronts,
 // which then fit the 1024 SIMDs in a single round.
-// HAM: potential energy interpolation, Eq. (2): pair weights (w_a + w_b) / 2, the
-// molecule's single-molecule potentials V^AT, V^CG (half of each of its pair potentials)
-// accumulated on hybrid molecules, and their drift force -(V^AT - V^CG) grad w shared by
-// mass fraction.  Otherwise force interpolation, Eq. (1).
-template <int SPM, typename PT, int MODE, bool ENERGY, bool HAM>
+// Variants (VAR): kVarForce, force interpolation, Eq. (1); kVarHam, potential energy
+// interpolation, Eq. (2): pair weights (w_a + w_b) / 2, the molecule's single-molecule
+// potentials V^AT, V^CG (half of each of its pair potentials) accumulated on hybrid
+// molecules, and their drift force -(V^AT - V^CG) grad w shared by mass fraction;
+// kVarNear, force interpolation with a correction field around the nearest anchor of a
+// self-adjusting region (its own instantiation, so that the extra load does not weigh on
+// the common kernels' registers).
+enum : int { kVarForce = 0, kVarHam = 1, kVarNear = 2 };
+
+template <int SPM, typename PT, int MODE, bool ENERGY, int VAR>
 __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
 {
+    constexpr bool HAM = VAR == kVarHam;
     const DevParams &P = a.P;
     if (a.check_halt && a.step > a.ctrl->halt) return;
     const int n = P.n_mol;
@@ -282,21 +288,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     cg1 = quad_sum(cg1);
     cg2 = quad_sum(cg2);
 
-    // correction force on the centre of mass along the resolution coordinate (Sec. 2.4)
-    double tdir[3] = {0.0, 0.0, 0.0}, ucorr = 0.0, ftd = 0.0;
-    if (P.td_n > 0 && with_slow) {
-        if (P.region == ADRES_REGION_SPHERES) {   // along the offset from the nearest anchor
-            const double4 nr = a.near[tt];
-            const double qn[3] = {nr.x, nr.y, nr.z};
-            ftd = corr_force_dq<ENERGY>(P, nr.w, qn, tdir, ucorr);
-        } else {
-            const double Rm[3] = {me.x, me.y, me.z};
-            ftd = corr_force<ENERGY>(P, Rm, tdir, ucorr);
-        }
-    }
+    double ucorr = 0.0;   // the correction field's potential (energy only)
 
     // lane q owns site q
     double F[3] = {0.0, 0.0, 0.0}, xq[3] = {0.0, 0.0, 0.0};
+    double mfq = 0.0;   // the lane's site mass fraction
     double mq = 1.0, iq = 0.5;
 #pragma unroll
     for (int i = 0; i < SPM; ++i)
@@ -313,17 +309,32 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                 F[1] += dv * gw[1];
                 F[2] += dv * gw[2];
             }
-            if (P.td_n > 0) {
-                const double ft = mf * (ss * ftd);
-                F[0] += ft * tdir[0];
-                F[1] += ft * tdir[1];
-                F[2] += ft * tdir[2];
-            }
+            mfq = mf;
             xq[0] = XI(i, 0); xq[1] = XI(i, 1); xq[2] = XI(i, 2);
             mq = P.mass[i];
             iq = P.inv_2m[i];
         }
     const bool owner = valid && q < SPM;
+    if (P.td_n > 0 && with_slow && q < SPM) {
+        // correction force on the centre of mass along the resolution coordinate (Sec. 2.4),
+        // shared by mass fraction (evaluated here, after the pair loop, to keep its values
+        // out of the loop's registers)
+        double qd[3], dd;
+        if constexpr (VAR == kVarNear) {   // along the offset from the nearest anchor
+            const double4 nr = a.near[tt];
+            qd[0] = nr.x; qd[1] = nr.y; qd[2] = nr.z;
+            dd = nr.w;
+        } else {
+            const double Rm[3] = {me.x, me.y, me.z};
+            dd = res_distance(P, Rm, qd);
+        }
+        double tdir[3];
+        const double ftd = corr_force_dq<ENERGY>(P, dd, qd, tdir, ucorr);
+        const double ft = mfq * (a.slow_scale * ftd);
+        F[0] += ft * tdir[0];
+        F[1] += ft * tdir[1];
+        F[2] += ft * tdir[2];
+    }
     if (owner) {
         if (P.bond_kind == ADRES_BOND_HARMONIC) {
 #pragma unroll
@@ -490,17 +501,17 @@ void launch_k(K kernel, hipStream_t s, const ForceArgs &a, int blocks, hipEvent_
         kernel<<<blocks, kBlock, 0, s>>>(a);
 }
 
-template <int SPM, typename PT, bool HAM>
+template <int SPM, typename PT, int VAR>
 void dispatch_mode(hipStream_t s, const ForceArgs &a, int blocks, hipEvent_t e0, hipEvent_t e1)
 {
     switch (a.mode) {
-    case kModeStep: launch_k(k_forces<SPM, PT, kModeStep, false, HAM>, s, a, blocks, e0, e1); break;
-    case kModeClose: launch_k(k_forces<SPM, PT, kModeClose, false, HAM>, s, a, blocks, e0, e1); break;
+    case kModeStep: launch_k(k_forces<SPM, PT, kModeStep, false, VAR>, s, a, blocks, e0, e1); break;
+    case kModeClose: launch_k(k_forces<SPM, PT, kModeClose, false, VAR>, s, a, blocks, e0, e1); break;
     default:
         if (a.epart)
-            launch_k(k_forces<SPM, PT, kModeForce, true, HAM>, s, a, blocks, e0, e1);
+            launch_k(k_forces<SPM, PT, kModeForce, true, VAR>, s, a, blocks, e0, e1);
         else
-            launch_k(k_forces<SPM, PT, kModeForce, false, HAM>, s, a, blocks, e0, e1);
+            launch_k(k_forces<SPM, PT, kModeForce, false, VAR>, s, a, blocks, e0, e1);
     }
 }
 
@@ -508,9 +519,11 @@ template <int SPM, typename PT>
 void dispatch_scheme(hipStream_t s, const ForceArgs &a, int blocks, hipEvent_t e0, hipEvent_t e1)
 {
     if (a.P.scheme == ADRES_SCHEME_HAMILTONIAN)
-        dispatch_mode<SPM, PT, true>(s, a, blocks, e0, e1);
+        dispatch_mode<SPM, PT, kVarHam>(s, a, blocks, e0, e1);
+    else if (a.P.region == ADRES_REGION_SPHERES && a.P.td_n > 0)
+        dispatch_mode<SPM, PT, kVarNear>(s, a, blocks, e0, e1);
     else
-        dispatch_mode<SPM, PT, false>(s, a, blocks, e0, e1);
+        dispatch_mode<SPM, PT, kVarForce>(s, a, blocks, e0, e1);
 }
 
 template <typename PT>
