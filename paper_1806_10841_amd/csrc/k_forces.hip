@@ -141,9 +141,15 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     double cg0 = 0.0, cg1 = 0.0, cg2 = 0.0;
     double uat = 0.0, ucg = 0.0, ubond = 0.0;
     // Eq. (2): a molecule on which the weight gradient is non-zero needs V^AT and V^CG
-    double gw[3] = {0.0, 0.0, 0.0};
-    if (HAM) weight_gradient(P, me, gw);
-    const bool hy_home = HAM && (gw[0] != 0.0 || gw[1] != 0.0 || gw[2] != 0.0);
+    // (inside the hybrid layer, where the weight gradient is non-zero; the gradient itself
+    // is formed after the pair loop so that it takes no registers there)
+    bool hy_home = false;
+    if (HAM && (P.region == ADRES_REGION_SLAB_X || P.region == ADRES_REGION_SPHERE)) {
+        const double Rm[3] = {me.x, me.y, me.z};
+        double qh[3];
+        const double dh = res_distance(P, Rm, qh);
+        hy_home = dh > P.d_at && dh < P.d_end;
+    }
     double vat = 0.0, vcg = 0.0;
 
     const PT sig2A = (PT)P.sig2_at, epsA = (PT)P.eps_at, rcA2 = (PT)P.rcA2;
@@ -302,7 +308,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
             F[0] = acc[i][0] + mf * (ss * cg0);
             F[1] = acc[i][1] + mf * (ss * cg1);
             F[2] = acc[i][2] + mf * (ss * cg2);
-            if (hy_home) {
+            if (HAM && hy_home) {
+                double gw[3];
+                weight_gradient(P, me, gw);
                 // drift force of Eq. (2): -(V^AT - V^CG) grad w(R), grad_x R = m_i / M
                 const double dv = -(vat - ss * vcg) * mf;
                 F[0] += dv * gw[0];
