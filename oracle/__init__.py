@@ -104,8 +104,12 @@ def lib():
                                               C.POINTER(C.c_int64)]
             L.orc_density_profile.restype = C.c_int
             L.orc_tdforce_update.argtypes = [P, dp, C.c_int32, C.c_double, C.c_double,
-                                             C.POINTER(C.c_int64), C.c_int64, C.c_double]
+                                             C.POINTER(C.c_int64), C.c_int64, C.c_double,
+                                             C.POINTER(C.c_int64), C.c_int64]
             L.orc_tdforce_update.restype = None
+            L.orc_region_volumes.argtypes = [P, dp, C.c_int64, C.c_uint64, C.c_int32, C.c_double, C.c_double,
+                                             C.POINTER(C.c_int64)]
+            L.orc_region_volumes.restype = C.c_int
             L.orc_num_threads.restype = C.c_int
             _lib = L
     return _lib
@@ -276,13 +280,30 @@ class Model:
         assert st == 0, st
         return counts
 
-    def tdforce_update(self, F, lo, hi, counts, n_frames, prefactor):
-        """One refinement step of the correction force values F (returns a new array)."""
+    def tdforce_update(self, F, lo, hi, counts, n_frames, prefactor, vol_counts=None, n_vol_samples=0):
+        """One refinement step of the correction force values F (returns a new array);
+        with vol_counts the bin volumes are the sampled ones (region_volumes)."""
         F = np.array(F, dtype=np.float64, copy=True)
         counts = np.ascontiguousarray(counts, dtype=np.int64)
+        vp = None
+        if vol_counts is not None:
+            vol_counts = np.ascontiguousarray(vol_counts, dtype=np.int64)
+            vp = vol_counts.ctypes.data_as(C.POINTER(C.c_int64))
         lib().orc_tdforce_update(C.byref(self.p), _dp(F), len(F), lo, hi,
-                                 counts.ctypes.data_as(C.POINTER(C.c_int64)), n_frames, prefactor)
+                                 counts.ctypes.data_as(C.POINTER(C.c_int64)), n_frames, prefactor,
+                                 vp, int(n_vol_samples))
         return F
+
+    def region_volumes(self, x, n_samples, seed, n_bins, lo, hi, counts=None):
+        """Adds the resolution-distance histogram of n_samples uniform points (SplitMix64
+        keyed by seed) to counts (int64, new zeros if None) and returns it."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        if counts is None:
+            counts = np.zeros(n_bins, dtype=np.int64)
+        st = lib().orc_region_volumes(C.byref(self.p), _dp(x), int(n_samples), int(seed) & (2**64 - 1),
+                                      n_bins, lo, hi, counts.ctypes.data_as(C.POINTER(C.c_int64)))
+        assert st == 0, st
+        return counts
 
     def kinetic(self, v):
         v = np.ascontiguousarray(v, dtype=np.float64)

@@ -788,7 +788,60 @@ int orc_density_profile(const orc_params *P, const double *x, int32_t n_bins, do
     double h = (hi - lo) / n_bins;
     for (int64_t a = 0; a < n; ++a) {
         double R[3] = {com[a], com[n + a], com[2 * n + a]};
-        double d = orc_region_distance(P, R);
+        double d = P->region == ORC_REGION_SPHERES ? orc_anchor_distance(P, com, a) : orc_region_distance(P, R);
+        if (d < lo || d >= hi) continue;
+        int64_t k = (int64_t)floor((d - lo) / h);
+        if (k > n_bins - 1) k = n_bins - 1;
+        counts[k] += 1;
+    }
+    free(com); free(w);
+    return status;
+}
+
+/* SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): the output for counter value k of a
+ * stream with key s is the finaliser applied to s + (k + 1) * 0x9E3779B97F4A7C15. */
+static uint64_t orc_splitmix64(uint64_t s, uint64_t k)
+{
+    uint64_t z = s + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* Bin volumes by sampling, for the density profile of a region whose bins have no closed
+ * form (a union of moving spheres, Sec. 2.5 with Sec. 2.4).  Reading: n_samples points
+ * uniform in the box, coordinate c of point i at L_c * u with u = (top 53 bits of
+ * SplitMix64(seed, 3 i + c)) / 2^53; each point is binned by its resolution distance like a
+ * centre of mass (for anchor spheres, the nearest anchor centre of the configuration x).
+ * Adds to counts; V_k is then counts_k / n_samples times the box volume. */
+int orc_region_volumes(const orc_params *P, const double *x, int64_t n_samples, uint64_t seed, int32_t n_bins,
+                       double lo, double hi, int64_t *counts)
+{
+    int64_t n = P->n_mol;
+    double *com = (double *)malloc(sizeof(double) * 3 * n);
+    double *w = (double *)malloc(sizeof(double) * n);
+    int status = orc_weights(P, x, com, w, NULL);
+    double h = (hi - lo) / n_bins;
+    for (int64_t i = 0; i < n_samples; ++i) {
+        double p[3];
+        for (int c = 0; c < 3; ++c) {
+            uint64_t z = orc_splitmix64(seed, 3 * (uint64_t)i + (uint64_t)c);
+            p[c] = P->box[c] * ((double)(z >> 11) * 0x1.0p-53);
+        }
+        double d;
+        if (P->region == ORC_REGION_SPHERES) {
+            double best = INFINITY;
+            for (int32_t k = 0; k < P->n_anchors; ++k) {
+                int64_t b = P->anchors[k];
+                double q[3];
+                for (int c = 0; c < 3; ++c) q[c] = orc_mi(p[c] - com[c * n + b], P->box[c]);
+                double r2 = (q[0] * q[0] + q[1] * q[1]) + q[2] * q[2];
+                if (r2 < best) best = r2;
+            }
+            d = sqrt(best);
+        } else {
+            d = orc_region_distance(P, p);
+        }
         if (d < lo || d >= hi) continue;
         int64_t k = (int64_t)floor((d - lo) / h);
         if (k > n_bins - 1) k = n_bins - 1;
@@ -805,15 +858,24 @@ int orc_density_profile(const orc_params *P, const double *x, int32_t n_bins, do
  * r_k = lo + k h); its slope at bin centre k is the central difference
  * (rho_k+1 - rho_k-1) / (2 h), one-sided at the two end bins, 0 for a single bin; and
  * the update is F_k <- F_k - prefactor * slope_k (the usual prefactor is
- * M / (rho_0^2 kappa_T)). */
+ * M / (rho_0^2 kappa_T)).  With vol_counts the volumes are sampled ones
+ * (orc_region_volumes over n_vol_samples points in total), for any region. */
 void orc_tdforce_update(const orc_params *P, double *F, int32_t n, double lo, double hi,
-                        const int64_t *counts, int64_t n_frames, double prefactor)
+                        const int64_t *counts, int64_t n_frames, double prefactor,
+                        const int64_t *vol_counts, int64_t n_vol_samples)
 {
     double h = (hi - lo) / n;
     double *rho = (double *)malloc(sizeof(double) * n);
     for (int k = 0; k < n; ++k) {
         double V;
-        if (P->region == ORC_REGION_SLAB) {
+        if (vol_counts) {
+            /* sampled volumes (orc_region_volumes); an unsampled bin counts as empty */
+            V = ((double)vol_counts[k] / (double)n_vol_samples) * ((P->box[0] * P->box[1]) * P->box[2]);
+            if (vol_counts[k] == 0) {
+                rho[k] = 0.0;
+                continue;
+            }
+        } else if (P->region == ORC_REGION_SLAB) {
             V = 2.0 * h * P->box[1] * P->box[2];
         } else {
             double r0 = lo + k * h, r1 = lo + (k + 1) * h;

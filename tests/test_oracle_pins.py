@@ -798,3 +798,60 @@ class TestAnchorSpheres:
             xm[qd, s] -= 1e-6
             fd = -(m.forces(xp)[2].sum() - m.forces(xm)[2].sum()) / 2e-6
             assert abs(f[qd, s] - fd) < 2e-5 * max(1.0, amag[s]), (qd, s, f[qd, s], fd)
+
+
+# ---------------------------------------------------------------- sampled bin volumes (Sec. 2.4 + 2.5)
+class TestSampledVolumes:
+    """Bin volumes by uniform sampling (SplitMix64 points) for regions without closed-form
+    bins: they reproduce the exact slab and sphere volumes within binomial error, the
+    anchor-sphere density profile is NumPy's histogram of nearest-anchor distances, and a
+    refinement with sampled volumes has the closed form of a known profile."""
+
+    @pytest.mark.parametrize("region", [inputs.REGION_SLAB_X, inputs.REGION_SPHERE, inputs.REGION_SPHERES])
+    def test_volumes_match_closed_forms(self, region):
+        wl = inputs.workload("small_sphere").with_(region=region)
+        x, _ = inputs.make_state(wl)
+        an = None
+        if region == inputs.REGION_SPHERES:
+            an = np.array([100], np.int32)       # one anchor: its shells are spheres
+        m = oracle.Model(wl, anchors=an)
+        n, lo, hi, N = 12, 0.5, 6.5, 400_000
+        vc = m.region_volumes(x, N, 12345, n, lo, hi)
+        h = (hi - lo) / n
+        r = lo + np.arange(n + 1) * h
+        L = np.asarray(wl.box)
+        if region == inputs.REGION_SLAB_X:
+            V = np.full(n, 2 * h * L[1] * L[2])
+        else:
+            V = 4.0 / 3.0 * np.pi * (r[1:] ** 3 - r[:-1] ** 3)
+        p = V / L.prod()
+        assert np.all(np.abs(vc - N * p) <= 5 * np.sqrt(N * p * (1 - p)) + 1), (vc, N * p)
+        # same seed, same points; another seed, other points
+        np.testing.assert_array_equal(vc, m.region_volumes(x, N, 12345, n, lo, hi))
+        assert not np.array_equal(vc, m.region_volumes(x, N, 54321, n, lo, hi))
+
+    def test_anchor_density_profile_is_histogram_of_nearest_distance(self):
+        wl = inputs.workload("small_sphere").with_(region=inputs.REGION_SPHERES, d_at=2.5, d_hy=2.0)
+        x, _ = inputs.make_state(wl)
+        an = inputs.anchor_molecules(wl.n_mol, 7, 2)
+        m = oracle.Model(wl, anchors=an)
+        com, _, _, _ = m.weights(x)
+        L = np.asarray(wl.box)[:, None, None]
+        q = com[:, :, None] - com[:, an][:, None, :]
+        q = q - L * np.round(q / L)
+        d = np.sqrt((q * q).sum(axis=0)).min(axis=1)
+        n, lo, hi = 20, 0.25, 8.0
+        ref, _ = np.histogram(d, bins=n, range=(lo, hi))
+        np.testing.assert_array_equal(m.density_profile(x, n, lo, hi), ref)
+
+    def test_update_with_uniform_sampled_volumes(self):
+        wl = inputs.workload("small_slab")
+        m = oracle.Model(wl)
+        n, lo, hi, frames, c = 9, 1.0, 10.0, 7, 0.25
+        h = (hi - lo) / n
+        counts = 40 + 3 * np.arange(n)
+        vol = np.full(n, 1000, dtype=np.int64)
+        V = 1000 / 1_000_000 * np.prod(wl.box)
+        F = np.linspace(-1.0, 1.0, n)
+        got = m.tdforce_update(F, lo, hi, counts, frames, c, vol_counts=vol, n_vol_samples=1_000_000)
+        np.testing.assert_allclose(got, F - c * 3 / (frames * V * h), rtol=0, atol=1e-12)
