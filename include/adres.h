@@ -226,10 +226,22 @@ adres_status adres_get_tdforce(adres_ctx *ctx, double *table_host, int32_t n);
 /* Density profile along the resolution coordinate (Sec. 2.4), in the bins of the installed
  * correction table: adds to counts (device, int64 [n], caller-initialised) the number of
  * molecules of x (device, caller order) whose centre-of-mass distance d from the AT
- * centre lies in bin floor((d - d_lo) / h) of [d_lo, d_hi).  Call once per sampled frame.
- * ADRES_E_STATE without a table; ADRES_E_ARG for ADRES_REGION_SPHERES (the bins of a union of
- * moving spheres have no closed-form volume).  Asynchronous. */
+ * centre lies in bin floor((d - d_lo) / h) of [d_lo, d_hi); for ADRES_REGION_SPHERES d is
+ * the distance from the nearest anchor centre of x.  Call once per sampled frame.
+ * ADRES_E_STATE without a table (or without anchors).  Asynchronous. */
 adres_status adres_density_profile(adres_ctx *ctx, const double *x, int64_t *counts);
+
+/* Bin volumes by sampling, for regions whose bins have no closed-form volume (a union of
+ * moving anchor spheres, Sec. 2.5 with Sec. 2.4): adds to vol_counts (device, int64 [n],
+ * caller-initialised) the bins of n_samples points uniform in the box, binned by their
+ * resolution distance like centres of mass (anchor spheres: from the nearest anchor centre
+ * of x, device caller order; x may be NULL for the other regions).  Point i has
+ * coordinate c = L_c * (SplitMix64(seed, 3 i + c) >> 11) * 2^-53, SplitMix64(s, k) the
+ * SplitMix64 finaliser (Steele, Lea and Flood 2014) of s + (k + 1) * 0x9E3779B97F4A7C15.
+ * The volume of bin k is vol_counts_k / n_samples times the box volume.  ADRES_E_STATE
+ * without a table; n_samples >= 1.  Asynchronous. */
+adres_status adres_region_volumes(adres_ctx *ctx, const double *x, int64_t n_samples, uint64_t seed,
+                                  int64_t *vol_counts);
 
 /* One refinement of the correction force from a density profile (Sec. 2.4: the
  * thermodynamic force is built from the distorted profile and refined iteratively):
@@ -238,8 +250,15 @@ adres_status adres_density_profile(adres_ctx *ctx, const double *x, int64_t *cou
  * then F_k <- F_k - prefactor * (drho/dd)_k with the slope by central differences of the
  * neighbouring bins (one-sided at the two end bins, 0 for a single bin).  The usual
  * prefactor is M / (rho_0^2 kappa_T).  counts: device int64 [n], n_frames >= 1; not for
- * ADRES_REGION_SPHERES (ADRES_E_ARG).  Asynchronous. */
+ * ADRES_REGION_SPHERES (ADRES_E_ARG: use adres_tdforce_update_sampled).  Asynchronous. */
 adres_status adres_tdforce_update(adres_ctx *ctx, const int64_t *counts, int64_t n_frames, double prefactor);
+
+/* The same refinement with sampled bin volumes (adres_region_volumes): V_k = vol_counts_k /
+ * n_vol_samples times the box volume, n_vol_samples the points behind vol_counts in total; a
+ * bin no sample fell in counts as empty.  Any region.  counts, vol_counts: device int64 [n].
+ * Asynchronous. */
+adres_status adres_tdforce_update_sampled(adres_ctx *ctx, const int64_t *counts, int64_t n_frames,
+                                          const int64_t *vol_counts, int64_t n_vol_samples, double prefactor);
 
 /* Anchors of a self-adjusting AT region (region ADRES_REGION_SPHERES, Sec. 2.5): mols (host,
  * int32 [k]) are caller molecule indices; each anchor's current centre of mass is the centre

@@ -68,6 +68,9 @@ _SIGS = {
     "adres_get_tdforce": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
     "adres_density_profile": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "adres_tdforce_update": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_double], C.c_int),
+    "adres_region_volumes": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_uint64, C.c_void_p], C.c_int),
+    "adres_tdforce_update_sampled": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_double],
+                                     C.c_int),
     "adres_mlp_set": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double], C.c_int),
     "adres_mlp_get": ([C.c_void_p, C.c_void_p, C.c_int32], C.c_int),
     "adres_mlp_eval": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64], C.c_int),
@@ -255,6 +258,23 @@ class Context:
             raise TypeError("counts must be int64")
         self._check(self.lib.adres_tdforce_update(self.h, _ptr(counts), int(n_frames), float(prefactor)),
                     "adres_tdforce_update")
+
+    def region_volumes(self, x, n_samples, seed, vol_counts):
+        """Add the bins of n_samples uniform points to vol_counts (int64 device tensor)."""
+        import torch
+        if vol_counts.dtype != torch.int64:
+            raise TypeError("vol_counts must be int64")
+        xp = _ptr(x) if x is not None else None
+        self._check(self.lib.adres_region_volumes(self.h, xp, int(n_samples), int(seed) & (2**64 - 1),
+                                                  _ptr(vol_counts)), "adres_region_volumes")
+
+    def tdforce_update_sampled(self, counts, n_frames, vol_counts, n_vol_samples, prefactor):
+        import torch
+        if counts.dtype != torch.int64 or vol_counts.dtype != torch.int64:
+            raise TypeError("counts must be int64")
+        self._check(self.lib.adres_tdforce_update_sampled(self.h, _ptr(counts), int(n_frames), _ptr(vol_counts),
+                                                          int(n_vol_samples), float(prefactor)),
+                    "adres_tdforce_update_sampled")
 
     def mlp_set(self, params, rc, scale, taper_width, r_min=0.0):
         params = np.ascontiguousarray(params, dtype=np.float32)

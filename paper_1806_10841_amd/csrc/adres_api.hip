@@ -49,6 +49,7 @@ struct adres_ctx {
     double *td = nullptr, *td_u = nullptr;   // correction force table and its integrals
     int *anchors = nullptr;                  // anchor molecules of a self-adjusting region
     double4 *near = nullptr;                 // offset from the nearest anchor per slot
+    double *anchor_cen = nullptr;            // anchor centres of a caller configuration [K][3]
     int *tile_order = nullptr;               // force kernel dispatch order (per list build)
     unsigned *mcost = nullptr;               // per-molecule cost estimates (list build)
     int *stencil = nullptr;                  // [n_cells][27] neighbour cell ranks (static grid)
@@ -561,7 +562,7 @@ void adres_destroy(adres_ctx *c)
     hipFree(c->R_ref); hipFree(c->inv_perm); hipFree(c->cell_rank);
     hipFree(c->count); hipFree(c->start); hipFree(c->fill); hipFree(c->new_from); hipFree(c->scan_tiles);
     hipFree(c->nbr); hipFree(c->cnt); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
-    hipFree(c->td); hipFree(c->td_u); hipFree(c->anchors); hipFree(c->near); hipFree(c->tile_order); hipFree(c->mcost); hipFree(c->stencil);
+    hipFree(c->td); hipFree(c->td_u); hipFree(c->anchors); hipFree(c->near); hipFree(c->anchor_cen); hipFree(c->tile_order); hipFree(c->mcost); hipFree(c->stencil);
     hipFree(c->mlp); hipFree(c->mlp_w2); hipFree(c->mlp_w2q); hipFree(c->mlp_fp8s); hipFree(c->cnt_up); hipFree(c->up_off); hipFree(c->up_scratch);
     hipFree(c->pid); hipFree(c->up_pairs); hipFree(c->f_pair);
     hipFree(c->adam_m); hipFree(c->adam_v); hipFree(c->grad); hipFree(c->loss); hipFree(c->res_part);
@@ -872,7 +873,7 @@ adres_status adres_set_tdforce(adres_ctx *c, const double *table, int32_t n, dou
     c->P.td_lo = d_lo;
     c->P.td_hi = d_hi;
     c->P.td_h = (d_hi - d_lo) / (double)n;
-    launch_td_update(c->stream, c->P, c->td, c->td_u, nullptr, 1, 0.0);
+    launch_td_update(c->stream, c->P, c->td, c->td_u, nullptr, 1, 0.0, nullptr, 0);
     HIPCHK(c, hipGetLastError());
     return ADRES_OK;
 }
@@ -885,7 +886,10 @@ adres_status adres_set_anchors(adres_ctx *c, const int32_t *mols, int32_t k)
     for (int i = 0; i < k; ++i)
         if (mols[i] < 0 || mols[i] >= c->P.n_mol) return fail(c, ADRES_E_ARG, "anchor index out of range");
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (!c->anchors) HIPCHK(c, dalloc(&c->anchors, (size_t)kMaxAnchors));
+    if (!c->anchors) {
+        HIPCHK(c, dalloc(&c->anchors, (size_t)kMaxAnchors));
+        HIPCHK(c, dalloc(&c->anchor_cen, (size_t)kMaxAnchors * 3));
+    }
     HIPCHK(c, hipMemcpy(c->anchors, mols, sizeof(int) * k, hipMemcpyHostToDevice));
     c->P.anchors = c->anchors;
     c->P.n_anchors = k;
@@ -907,9 +911,32 @@ adres_status adres_density_profile(adres_ctx *c, const double *x, int64_t *count
 {
     if (!c || !x || !counts) return fail(c, ADRES_E_ARG, "null argument");
     if (c->P.td_n == 0) return fail(c, ADRES_E_STATE, "no correction table (its bins define the profile)");
-    if (c->P.region == ADRES_REGION_SPHERES)
-        return fail(c, ADRES_E_ARG, "density profiles need a slab or sphere region (bin volumes)");
-    launch_density_profile(c->stream, c->P, x, reinterpret_cast<unsigned long long *>(counts));
+    const double *cen = nullptr;
+    if (c->P.region == ADRES_REGION_SPHERES) {
+        if (c->P.n_anchors == 0) return fail(c, ADRES_E_STATE, "self-adjusting region without anchors");
+        launch_anchor_centres(c->stream, c->P, x, c->anchor_cen);
+        cen = c->anchor_cen;
+    }
+    launch_density_profile(c->stream, c->P, x, cen, reinterpret_cast<unsigned long long *>(counts));
+    HIPCHK(c, hipGetLastError());
+    return ADRES_OK;
+}
+
+adres_status adres_region_volumes(adres_ctx *c, const double *x, int64_t n_samples, uint64_t seed,
+                                  int64_t *vol_counts)
+{
+    if (!c || !vol_counts) return fail(c, ADRES_E_ARG, "null argument");
+    if (c->P.td_n == 0) return fail(c, ADRES_E_STATE, "no correction table (its bins define the volumes)");
+    if (n_samples < 1) return fail(c, ADRES_E_ARG, "need n_samples >= 1");
+    const double *cen = nullptr;
+    if (c->P.region == ADRES_REGION_SPHERES) {
+        if (!x) return fail(c, ADRES_E_ARG, "anchor spheres need the configuration x");
+        if (c->P.n_anchors == 0) return fail(c, ADRES_E_STATE, "self-adjusting region without anchors");
+        launch_anchor_centres(c->stream, c->P, x, c->anchor_cen);
+        cen = c->anchor_cen;
+    }
+    launch_region_volumes(c->stream, c->P, cen, (long long)n_samples, (unsigned long long)seed,
+                          reinterpret_cast<unsigned long long *>(vol_counts));
     HIPCHK(c, hipGetLastError());
     return ADRES_OK;
 }
@@ -920,9 +947,23 @@ adres_status adres_tdforce_update(adres_ctx *c, const int64_t *counts, int64_t n
     if (c->P.td_n == 0) return fail(c, ADRES_E_STATE, "no correction force installed");
     if (n_frames < 1 || !std::isfinite(prefactor)) return fail(c, ADRES_E_ARG, "need n_frames >= 1, finite prefactor");
     if (c->P.region == ADRES_REGION_SPHERES)
-        return fail(c, ADRES_E_ARG, "refinement needs a slab or sphere region (bin volumes)");
+        return fail(c, ADRES_E_ARG, "anchor spheres have no closed-form bin volumes: use adres_tdforce_update_sampled");
     launch_td_update(c->stream, c->P, c->td, c->td_u, reinterpret_cast<const long long *>(counts),
-                     (long long)n_frames, prefactor);
+                     (long long)n_frames, prefactor, nullptr, 0);
+    HIPCHK(c, hipGetLastError());
+    return ADRES_OK;
+}
+
+adres_status adres_tdforce_update_sampled(adres_ctx *c, const int64_t *counts, int64_t n_frames,
+                                          const int64_t *vol_counts, int64_t n_vol_samples, double prefactor)
+{
+    if (!c || !counts || !vol_counts) return fail(c, ADRES_E_ARG, "null argument");
+    if (c->P.td_n == 0) return fail(c, ADRES_E_STATE, "no correction force installed");
+    if (n_frames < 1 || n_vol_samples < 1 || !std::isfinite(prefactor))
+        return fail(c, ADRES_E_ARG, "need n_frames >= 1, n_vol_samples >= 1, finite prefactor");
+    launch_td_update(c->stream, c->P, c->td, c->td_u, reinterpret_cast<const long long *>(counts),
+                     (long long)n_frames, prefactor, reinterpret_cast<const long long *>(vol_counts),
+                     (long long)n_vol_samples);
     HIPCHK(c, hipGetLastError());
     return ADRES_OK;
 }

@@ -526,9 +526,15 @@ void launch_tile_order(hipStream_t s, const DevParams &P, const unsigned *mcost,
 
 // correction force (k_state.hip)
 constexpr int kTdMaxBins = 4096;
-void launch_density_profile(hipStream_t s, const DevParams &P, const double *x, unsigned long long *counts);
+// cen: anchor centres [K][3] for ADRES_REGION_SPHERES (else null)
+void launch_density_profile(hipStream_t s, const DevParams &P, const double *x, const double *cen,
+                            unsigned long long *counts);
+void launch_anchor_centres(hipStream_t s, const DevParams &P, const double *x, double *cen);
+void launch_region_volumes(hipStream_t s, const DevParams &P, const double *cen, long long n_samples,
+                           unsigned long long seed, unsigned long long *counts);
+// vol: sampled bin volumes (counts over n_vol points) or null for the closed forms
 void launch_td_update(hipStream_t s, const DevParams &P, double *td, double *td_u, const long long *counts,
-                      long long n_frames, double prefactor);
+                      long long n_frames, double prefactor, const long long *vol, long long n_vol);
 
 // self-adjusting region (k_state.hip): weights from the nearest anchor centre, for the
 // Morton-ordered state (Rw in place, and the offset from the nearest anchor with its

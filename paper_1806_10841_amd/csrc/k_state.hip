@@ -158,13 +158,50 @@ __global__ __launch_bounds__(kBlock) void k_map_cg(DevParams P, const double *__
 // installed correction table: centre of mass (the operation order of the weights), its
 // distance d from the AT centre, bin floor((d - lo) / h) (the top bin also takes a d that
 // rounds to n below hi), counted per workgroup in LDS and added to the int64 totals.
+// Bin index of a resolution distance in the correction table's bins, or -1 outside them.
+__device__ __forceinline__ int td_bin(const DevParams &P, double d)
+{
+    if (!(d >= P.td_lo && d < P.td_hi)) return -1;
+    const double u = floor((d - P.td_lo) / P.td_h);
+    return u < (double)(P.td_n - 1) ? (int)u : P.td_n - 1;
+}
+
+// Distance from the nearest of the K anchor centres staged in LDS (the first of equally
+// near ones).
+__device__ __forceinline__ double nearest_anchor(const DevParams &P, const double (*cen)[3], int K, const double R[3])
+{
+#pragma clang fp contract(off)
+    double best = INFINITY;
+    for (int k = 0; k < K; ++k) {
+        const double q0 = mi(R[0] - cen[k][0], P.box[0], P.half[0]);
+        const double q1 = mi(R[1] - cen[k][1], P.box[1], P.half[1]);
+        const double q2 = mi(R[2] - cen[k][2], P.box[2], P.half[2]);
+        const double r2 = dist2_exact(q0, q1, q2);
+        best = r2 < best ? r2 : best;
+    }
+    return sqrt(best);
+}
+
+// Density profile along the resolution coordinate (Sec. 2.4), in the bins of the
+// installed correction table: centre of mass (the operation order of the weights), its
+// distance d from the AT centre (for anchor spheres: from the nearest anchor centre, given
+// in cen [K][3]), bin floor((d - lo) / h) (the top bin also takes a d that rounds to n
+// below hi), counted per workgroup in LDS and added to the int64 totals.
 template <int SPM>
 __global__ __launch_bounds__(kBlock) void k_density_profile(DevParams P, const double *__restrict__ x,
+                                                            const double *__restrict__ cen,
                                                             unsigned long long *__restrict__ counts)
 {
     __shared__ unsigned hist[kTdMaxBins];
+    __shared__ double scen[kMaxAnchors][3];
     const int nb = P.td_n;
+    const int K = cen ? P.n_anchors : 0;
     for (int b = threadIdx.x; b < nb; b += kBlock) hist[b] = 0u;
+    for (int k = threadIdx.x; k < K; k += kBlock) {
+        scen[k][0] = cen[3 * k];
+        scen[k][1] = cen[3 * k + 1];
+        scen[k][2] = cen[3 * k + 2];
+    }
     __syncthreads();
     const int a = blockIdx.x * kBlock + threadIdx.x;
     if (a < P.n_mol) {
@@ -172,12 +209,72 @@ __global__ __launch_bounds__(kBlock) void k_density_profile(DevParams P, const d
         load_sites<SPM>(x, P.n_sites, a, p);
         double R[3], rh, q[3];
         mol_com<SPM>(P, p, R, rh);
-        const double d = res_distance(P, R, q);
-        if (d >= P.td_lo && d < P.td_hi) {
-            const double u = floor((d - P.td_lo) / P.td_h);
-            const int k = u < (double)(nb - 1) ? (int)u : nb - 1;
-            atomicAdd(&hist[k], 1u);
+        const double d = cen ? nearest_anchor(P, scen, K, R) : res_distance(P, R, q);
+        const int k = td_bin(P, d);
+        if (k >= 0) atomicAdd(&hist[k], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += kBlock)
+        if (hist[b]) atomicAdd(&counts[b], (unsigned long long)hist[b]);
+}
+
+// Centres of mass of the anchor molecules of a caller-order configuration: cen [K][3].
+template <int SPM>
+__global__ void k_anchor_centres(DevParams P, const double *__restrict__ x, double *__restrict__ cen)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P.n_anchors) return;
+    double p[SPM][3];
+    load_sites<SPM>(x, P.n_sites, P.anchors[k], p);
+    double R[3], rh;
+    mol_com<SPM>(P, p, R, rh);
+    cen[3 * k] = R[0];
+    cen[3 * k + 1] = R[1];
+    cen[3 * k + 2] = R[2];
+}
+
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): the finaliser applied to
+// s + (k + 1) * 0x9E3779B97F4A7C15, the output for counter value k of stream key s.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t s, uint64_t k)
+{
+    uint64_t z = s + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Bin volumes by sampling (for bins without closed-form volumes, e.g. a union of moving
+// spheres): point i has coordinate c = L_c * (top 53 bits of SplitMix64(seed, 3 i + c)) / 2^53,
+// binned by its resolution distance like a centre of mass.  Grid-stride over the points,
+// LDS histogram per workgroup, int64 totals.
+__global__ __launch_bounds__(kBlock) void k_region_volumes(DevParams P, const double *__restrict__ cen,
+                                                           long long n_samples, unsigned long long seed,
+                                                           unsigned long long *__restrict__ counts)
+{
+#pragma clang fp contract(off)
+    __shared__ unsigned hist[kTdMaxBins];
+    __shared__ double scen[kMaxAnchors][3];
+    const int nb = P.td_n;
+    const int K = cen ? P.n_anchors : 0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) hist[b] = 0u;
+    for (int k = threadIdx.x; k < K; k += kBlock) {
+        scen[k][0] = cen[3 * k];
+        scen[k][1] = cen[3 * k + 1];
+        scen[k][2] = cen[3 * k + 2];
+    }
+    __syncthreads();
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n_samples;
+         i += (long long)gridDim.x * kBlock) {
+        double pnt[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const uint64_t z = splitmix64(seed, 3ull * (uint64_t)i + (uint64_t)c);
+            pnt[c] = P.box[c] * ((double)(z >> 11) * 0x1.0p-53);
         }
+        double q[3];
+        const double d = cen ? nearest_anchor(P, scen, K, pnt) : res_distance(P, pnt, q);
+        const int k = td_bin(P, d);
+        if (k >= 0) atomicAdd(&hist[k], 1u);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < nb; b += kBlock)
@@ -192,7 +289,8 @@ __global__ __launch_bounds__(kBlock) void k_density_profile(DevParams P, const d
 // integrals.  One workgroup; n <= kTdMaxBins.
 __global__ __launch_bounds__(kBlock) void k_td_update(DevParams P, double *__restrict__ td, double *__restrict__ td_u,
                                                       const long long *__restrict__ counts, long long n_frames,
-                                                      double prefactor)
+                                                      double prefactor, const long long *__restrict__ vol,
+                                                      long long n_vol)
 {
 #pragma clang fp contract(off)
     __shared__ double rho[kTdMaxBins];
@@ -201,7 +299,13 @@ __global__ __launch_bounds__(kBlock) void k_td_update(DevParams P, double *__res
     if (counts) {
         for (int k = threadIdx.x; k < n; k += kBlock) {
             double V;
-            if (P.region == ADRES_REGION_SLAB_X) {
+            if (vol) {   // sampled volumes; an unsampled bin counts as empty
+                V = ((double)vol[k] / (double)n_vol) * ((P.box[0] * P.box[1]) * P.box[2]);
+                if (vol[k] == 0) {
+                    rho[k] = 0.0;
+                    continue;
+                }
+            } else if (P.region == ADRES_REGION_SLAB_X) {
                 V = 2.0 * h * P.box[1] * P.box[2];
             } else {
                 const double r0 = lo + k * h, r1 = lo + (k + 1) * h;
@@ -374,15 +478,29 @@ void launch_map_cg(hipStream_t s, const DevParams &P, const double *x, const dou
     ADRES_SPM_DISPATCH(P.spm, (k_map_cg<S_><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, x, f, com, fmap)));
 }
 
-void launch_density_profile(hipStream_t s, const DevParams &P, const double *x, unsigned long long *counts)
+void launch_density_profile(hipStream_t s, const DevParams &P, const double *x, const double *cen,
+                            unsigned long long *counts)
 {
-    ADRES_SPM_DISPATCH(P.spm, (k_density_profile<S_><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, x, counts)));
+    ADRES_SPM_DISPATCH(P.spm, (k_density_profile<S_><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, x, cen, counts)));
+}
+
+void launch_anchor_centres(hipStream_t s, const DevParams &P, const double *x, double *cen)
+{
+    ADRES_SPM_DISPATCH(P.spm, (k_anchor_centres<S_><<<(P.n_anchors + 63) / 64, 64, 0, s>>>(P, x, cen)));
+}
+
+void launch_region_volumes(hipStream_t s, const DevParams &P, const double *cen, long long n_samples,
+                           unsigned long long seed, unsigned long long *counts)
+{
+    const long long want = (n_samples + kBlock - 1) / kBlock;
+    const int blocks = (int)(want < 2048 ? (want > 0 ? want : 1) : 2048);
+    k_region_volumes<<<blocks, kBlock, 0, s>>>(P, cen, n_samples, seed, counts);
 }
 
 void launch_td_update(hipStream_t s, const DevParams &P, double *td, double *td_u, const long long *counts,
-                      long long n_frames, double prefactor)
+                      long long n_frames, double prefactor, const long long *vol, long long n_vol)
 {
-    k_td_update<<<1, kBlock, 0, s>>>(P, td, td_u, counts, n_frames, prefactor);
+    k_td_update<<<1, kBlock, 0, s>>>(P, td, td_u, counts, n_frames, prefactor, vol, n_vol);
 }
 
 void launch_anchor_weights(hipStream_t s, const DevParams &P, double4 *Rw, const int *inv_perm, Ctrl *ctrl,

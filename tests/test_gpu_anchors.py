@@ -160,10 +160,13 @@ def test_errors(dev):
     assert torch.isfinite(c.forces(xt)).all()
     c.set_tdforce(np.ones(4), 1.0, 3.0)                 # a correction field is allowed ...
     counts = torch.zeros(4, dtype=torch.int64, device=dev)
-    with pytest.raises(binding.AdresError):            # ... but no profile (no bin volumes)
-        c.density_profile(xt, counts)
-    with pytest.raises(binding.AdresError):
+    c.density_profile(xt, counts)                       # ... and a profile ...
+    with pytest.raises(binding.AdresError):            # ... but no closed-form bin volumes
         c.tdforce_update(counts, 1, 1.0)
+    with pytest.raises(binding.AdresError):            # sampled volumes need the configuration
+        c.region_volumes(None, 100, 1, counts)
+    with pytest.raises(binding.AdresError):
+        c.region_volumes(xt, 0, 1, counts)
     with pytest.raises(binding.AdresError):
         binding.Context(wl.with_(scheme=inputs.SCHEME_HAMILTONIAN))
     s = binding.Context(inputs.workload("small_sphere"))
@@ -224,3 +227,44 @@ def test_integrate_with_correction_around_anchors(dev):
     assert nreb >= 1
     assert np.abs(_min_image(xt.cpu().numpy() - xo, wl.box[0])).max() < 1e-9
     assert np.abs(vt.cpu().numpy() - vo).max() < 1e-7
+
+
+def test_anchor_density_profile_and_sampled_volumes_match_oracle(dev):
+    """Density profile by nearest-anchor distance and sampled bin volumes (same SplitMix64
+    points on both sides): integer counts equal to the oracle's; a refinement with them."""
+    wl = _wl("small_sphere")
+    an = inputs.anchor_molecules(wl.n_mol, 9, 3)
+    x, _ = inputs.make_state(wl)
+    n, lo, hi = 20, 0.25, 8.0
+    m = oracle.Model(wl, anchors=an)
+    c = _ctx(wl, an)
+    c.set_tdforce(np.linspace(0.5, -0.5, n), lo, hi)
+    xt = _t(x, dev)
+    counts = torch.zeros(n, dtype=torch.int64, device=dev)
+    c.density_profile(xt, counts)
+    vol = torch.zeros(n, dtype=torch.int64, device=dev)
+    c.region_volumes(xt, 300_000, 99, vol)
+    c.region_volumes(xt, 300_000, 100, vol)
+    torch.cuda.synchronize()
+    ref = m.density_profile(x, n, lo, hi)
+    np.testing.assert_array_equal(counts.cpu().numpy(), ref)
+    vref = m.region_volumes(x, 300_000, 99, n, lo, hi)
+    vref = m.region_volumes(x, 300_000, 100, n, lo, hi, vref)
+    np.testing.assert_array_equal(vol.cpu().numpy(), vref)
+    c.tdforce_update_sampled(counts, 1, vol, 600_000, 0.3)
+    F2 = m.tdforce_update(np.linspace(0.5, -0.5, n), lo, hi, ref, 1, 0.3, vol_counts=vref, n_vol_samples=600_000)
+    np.testing.assert_allclose(c.get_tdforce(), F2, rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("region", [inputs.REGION_SLAB_X, inputs.REGION_SPHERE])
+def test_sampled_volumes_static_regions_match_oracle(dev, region):
+    from paper_1806_10841_amd import binding
+    wl = inputs.workload("small_sphere").with_(region=region)
+    x, _ = inputs.make_state(wl)
+    n, lo, hi = 16, 0.5, 8.5
+    c = binding.Context(wl)
+    c.set_tdforce(np.zeros(n), lo, hi)
+    vol = torch.zeros(n, dtype=torch.int64, device=dev)
+    c.region_volumes(None, 1_000_003, 7, vol)     # ragged: not a multiple of the workgroup
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(vol.cpu().numpy(), oracle.Model(wl).region_volumes(x, 1_000_003, 7, n, lo, hi))
