@@ -72,7 +72,7 @@ def test_respa_fp64_matches_oracle(dev, name, scheme, td, n_inner, n_outer):
         assert nreb >= 1, "the rebuild path was not exercised"
 
 
-@pytest.mark.parametrize("name", ["c1", "small_slab"])
+@pytest.mark.parametrize("name", ["c1", "small_slab", "c2"])
 def test_single_inner_step_is_integrate(dev, name):
     wl = inputs.workload(name)
     x, v = inputs.make_state(wl)
