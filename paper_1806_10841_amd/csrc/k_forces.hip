@@ -96,10 +96,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
 {
     constexpr bool HAM = VAR == kVarHam;
     const DevParams &P = a.P;
-    if (a.check_halt && a.step > a.ctrl->halt) return;
+    const int halt = a.ctrl->halt;
     const int n = P.n_mol;
     const int64_t ns = P.n_sites;
-    const int blk = a.tile_order ? a.tile_order[xcd_block()] : xcd_block();
+    const int slot = xcd_block();
+    const int blk = a.tile_order ? a.tile_order[slot] : slot;
     const int gid = blk * kBlock + threadIdx.x;
     const int t = gid / kLanes, q = gid % kLanes;
     const bool valid = t < n;
@@ -113,16 +114,18 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     __shared__ double sv[MODE == kModeForce ? 1 : kBlock / kLanes][SPM][3];
     __shared__ double4 sref[MODE == kModeStep ? kBlock / kLanes : 1];
     const int ml = threadIdx.x / kLanes;
+    // every load of the molecule's own data (and the halt index) is issued before the
+    // first wait, so that the prologue costs one memory round trip
+    double lx[3] = {0.0, 0.0, 0.0}, lv[3] = {0.0, 0.0, 0.0};
     if (q < SPM) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) sx[ml][q][d] = a.x[d * ns + (int64_t)tt * SPM + q];
+        for (int d = 0; d < 3; ++d) lx[d] = a.x[d * ns + (int64_t)tt * SPM + q];
         if (MODE != kModeForce)
 #pragma unroll
-            for (int d = 0; d < 3; ++d) sv[ml][q][d] = a.v[d * ns + (int64_t)tt * SPM + q];
+            for (int d = 0; d < 3; ++d) lv[d] = a.v[d * ns + (int64_t)tt * SPM + q];
     }
-    if (MODE == kModeStep && q == 0) sref[ml] = a.R_ref[tt];
-    __syncthreads();
-#define XI(i, d) sx[ml][(i)][(d)]
+    double4 lref = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (MODE == kModeStep) lref = a.R_ref[tt];
     const double4 me = a.Rw[tt];
     const double rha = (double)a.rho[tt];
     constexpr bool kOff = sizeof(PT) == 4;   // FP32 displacements from site offsets
@@ -134,6 +137,20 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
 #pragma unroll
             for (int d = 0; d < 3; ++d) hoff[i][d] = a.off[(int64_t)tt * (3 * SPM) + 3 * i + d];
     }
+    const int cnt = valid ? a.cnt[tt] : 0;
+    // the same decision in every wave: only an earlier launch can set halt below this step
+    // (this one sets it to its own step at the lowest), so no workgroup stops at the barrier
+    if (a.check_halt && a.step > halt) return;
+    if (q < SPM) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sx[ml][q][d] = lx[d];
+        if (MODE != kModeForce)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) sv[ml][q][d] = lv[d];
+    }
+    if (MODE == kModeStep && q == 0) sref[ml] = lref;
+    __syncthreads();
+#define XI(i, d) sx[ml][(i)][(d)]
 
     double acc[SPM][3];
 #pragma unroll
@@ -154,7 +171,6 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
 
     const PT sig2A = (PT)P.sig2_at, epsA = (PT)P.eps_at, rcA2 = (PT)P.rcA2;
     const PT sig2C = (PT)P.sig2_cg, epsC = (PT)P.eps_cg;
-    const int cnt = valid ? a.cnt[tt] : 0;
     const int *row = a.nbr + (int64_t)tt * a.cap;
     const bool with_slow = a.slow_scale != 0.0;
 
