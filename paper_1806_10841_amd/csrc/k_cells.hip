@@ -165,46 +165,62 @@ __global__ __launch_bounds__(kBlock) void k_sort_within_cells(int n_cells, const
     }
 }
 
-// Gathers the state into the new slot order.  All loads are issued before the first
-// store: source and destination are distinct buffers, but the compiler cannot know that
-// and would otherwise wait for every load before the store that follows it.
+// Gathers the state into the new slot order, one lane per site (perm_lanes<SPM>() lanes per
+// molecule; lane 0 also moves the per-molecule arrays), so that a rebuild has four times
+// as many independent gathers in flight as with a lane per molecule.  All of a lane's loads
+// are issued before its first store: source and destination are distinct buffers, but the
+// compiler cannot know that and would otherwise wait for every load before the store that
+// follows it.
+template <int SPM>
+constexpr int perm_lanes() { return SPM == 1 ? 1 : (SPM == 2 ? 2 : 4); }
+
 template <int SPM>
 __global__ __launch_bounds__(kBlock) void k_permute(DevParams P, const int *__restrict__ new_from, StateBufs src,
                                                     StateBufs dst, int *__restrict__ inv_perm,
                                                     double4 *__restrict__ R_ref, int with_v)
 {
-    int t = blockIdx.x * kBlock + threadIdx.x;
+    constexpr int L = perm_lanes<SPM>();
+    static_assert(SPM <= L, "one lane per site");
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int t = (int)(g / L), k = (int)(g % L);
     if (t >= P.n_mol) return;
     const int64_t ns = P.n_sites;
     const int i = new_from[t];
-    double xs[3][SPM], vs[3][SPM];
-    float of[3 * SPM];
+    const bool site = k < SPM;
+    const int64_t from = (int64_t)i * SPM + k, to = (int64_t)t * SPM + k;
+    double xs[3] = {0.0, 0.0, 0.0}, vs[3] = {0.0, 0.0, 0.0};
+    float of[3] = {0.0f, 0.0f, 0.0f};
+    if (site) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-        for (int k = 0; k < SPM; ++k) {
-            xs[d][k] = src.x[d * ns + (int64_t)i * SPM + k];
-            vs[d][k] = with_v ? src.v[d * ns + (int64_t)i * SPM + k] : 0.0;
+        for (int d = 0; d < 3; ++d) {
+            xs[d] = src.x[d * ns + from];
+            if (with_v) vs[d] = src.v[d * ns + from];
+            of[d] = src.off[3 * from + d];
         }
+    }
+    double4 r = make_double4(0.0, 0.0, 0.0, 0.0);
+    float rh = 0.0f;
+    int caller = 0;
+    if (k == 0) {
+        r = src.Rw[i];
+        rh = src.rho[i];
+        caller = src.perm[i];
+    }
+    if (site) {
 #pragma unroll
-    for (int j = 0; j < 3 * SPM; ++j) of[j] = src.off[(int64_t)i * (3 * SPM) + j];
-    const double4 r = src.Rw[i];
-    const float rh = src.rho[i];
-    const int caller = src.perm[i];
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-        for (int k = 0; k < SPM; ++k) {
-            dst.x[d * ns + (int64_t)t * SPM + k] = xs[d][k];
-            if (with_v) dst.v[d * ns + (int64_t)t * SPM + k] = vs[d][k];
+        for (int d = 0; d < 3; ++d) {
+            dst.x[d * ns + to] = xs[d];
+            if (with_v) dst.v[d * ns + to] = vs[d];
+            dst.off[3 * to + d] = of[d];
         }
-#pragma unroll
-    for (int j = 0; j < 3 * SPM; ++j) dst.off[(int64_t)t * (3 * SPM) + j] = of[j];
-    dst.Rw[t] = r;
-    R_ref[t] = r;
-    dst.rho[t] = rh;
-    dst.perm[t] = caller;
-    inv_perm[caller] = t;
+    }
+    if (k == 0) {
+        dst.Rw[t] = r;
+        R_ref[t] = r;
+        dst.rho[t] = rh;
+        dst.perm[t] = caller;
+        inv_perm[caller] = t;
+    }
 }
 
 // Lane h's value broadcast to the whole wavefront (h uniform: a scalar read of the lane).
@@ -434,11 +450,12 @@ void launch_sort_within_cells(hipStream_t s, int n_cells, const int *start, cons
 void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, const StateBufs &src,
                     const StateBufs &dst, int *inv_perm, double4 *R_ref, bool with_v)
 {
+    const int64_t n = P.n_mol;
     switch (P.spm) {
-    case 1: k_permute<1><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, new_from, src, dst, inv_perm, R_ref, with_v); break;
-    case 2: k_permute<2><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, new_from, src, dst, inv_perm, R_ref, with_v); break;
-    case 3: k_permute<3><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, new_from, src, dst, inv_perm, R_ref, with_v); break;
-    default: k_permute<4><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, new_from, src, dst, inv_perm, R_ref, with_v); break;
+    case 1: k_permute<1><<<blocks_for(n * perm_lanes<1>()), kBlock, 0, s>>>(P, new_from, src, dst, inv_perm, R_ref, with_v); break;
+    case 2: k_permute<2><<<blocks_for(n * perm_lanes<2>()), kBlock, 0, s>>>(P, new_from, src, dst, inv_perm, R_ref, with_v); break;
+    case 3: k_permute<3><<<blocks_for(n * perm_lanes<3>()), kBlock, 0, s>>>(P, new_from, src, dst, inv_perm, R_ref, with_v); break;
+    default: k_permute<4><<<blocks_for(n * perm_lanes<4>()), kBlock, 0, s>>>(P, new_from, src, dst, inv_perm, R_ref, with_v); break;
     }
 }
 
