@@ -131,11 +131,12 @@ uint32_t spread3(uint32_t v)
 // Reads the device control block once all work enqueued so far has finished: a
 // one-thread kernel publishes it into host-mapped memory with a sequence number the
 // host polls (cheaper than a copy plus a stream synchronisation).  Converts latched
-// error bits into a status and clears them.
-adres_status read_ctrl(adres_ctx *c)
+// error bits into a status and clears them.  With reset_halt the same kernel then clears
+// the device's halt index and overflow report.
+adres_status read_ctrl(adres_ctx *c, bool reset_halt = false)
 {
     const unsigned seq = ++c->pub_seq;
-    launch_publish(c->stream, c->ctrl, c->pub_dev, seq);
+    launch_publish(c->stream, c->ctrl, c->pub_dev, seq, reset_halt);
     HIPCHK(c, hipGetLastError());
     const auto t0 = std::chrono::steady_clock::now();
     for (long spin = 0; __atomic_load_n(&c->pub->seq, __ATOMIC_ACQUIRE) != seq; ++spin) {
@@ -726,10 +727,9 @@ adres_status integrate_impl(adres_ctx *c, double *x, double *v, double *f, doubl
             }
             if (gk < n_steps) p = 1 - p;
         }
-        st = read_ctrl(c);   // the one synchronisation per chunk
+        st = read_ctrl(c, true);   // the one synchronisation per chunk; clears halt
         if (st != ADRES_OK) return st;
         const int h = c->ctrl_host->halt;
-        launch_reset_halt(c->stream, c->ctrl);
         if (h < 0) {
             // the last list build overflowed: nothing of this chunk ran; regrow, rebuild
             st = build_list(c);

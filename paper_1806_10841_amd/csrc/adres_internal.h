@@ -450,7 +450,7 @@ void launch_kick_drift(hipStream_t s, const DevParams &P, const double *x_in, do
                        double *x_out, double4 *Rw_out, float *rho_out, float *off_out, const double4 *R_ref,
                        const int *perm, Ctrl *ctrl, int step, const StepArgs &st);
 void launch_reset_halt(hipStream_t s, Ctrl *ctrl);
-void launch_publish(hipStream_t s, const Ctrl *ctrl, CtrlPub *pub, unsigned seq);
+void launch_publish(hipStream_t s, Ctrl *ctrl, CtrlPub *pub, unsigned seq, bool reset);
 void launch_map_cg(hipStream_t s, const DevParams &P, const double *x, const double *f, double *com, double *fmap);
 
 // cell list

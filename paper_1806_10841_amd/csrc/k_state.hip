@@ -404,7 +404,9 @@ __global__ __launch_bounds__(kBlock) void k_anchor_weights_caller(DevParams P, c
     w[a] = weight_of_distance(P, sqrt(best));
 }
 
-__global__ void k_publish(const Ctrl *__restrict__ ctrl, CtrlPub *pub, unsigned seq)
+// With reset, also clears the halt index and the list-overflow report once they have been
+// copied (what k_reset_halt does), saving the step loop a launch per chunk.
+__global__ void k_publish(Ctrl *__restrict__ ctrl, CtrlPub *pub, unsigned seq, int reset)
 {
     if (threadIdx.x != 0) return;
     volatile CtrlPub *p = pub;
@@ -415,6 +417,11 @@ __global__ void k_publish(const Ctrl *__restrict__ ctrl, CtrlPub *pub, unsigned 
     __threadfence_system();
     p->seq = seq;
     __threadfence_system();
+    if (reset) {
+        ctrl->halt = INT_MAX;
+        ctrl->overflow = 0;
+        ctrl->max_count = 0;
+    }
 }
 
 // clears the halt index and the list-overflow report (a fill kernel, so that no
@@ -468,9 +475,9 @@ void launch_kick_drift(hipStream_t s, const DevParams &P, const double *x_in, do
 
 void launch_reset_halt(hipStream_t s, Ctrl *ctrl) { k_reset_halt<<<1, 64, 0, s>>>(ctrl); }
 
-void launch_publish(hipStream_t s, const Ctrl *ctrl, CtrlPub *pub, unsigned seq)
+void launch_publish(hipStream_t s, Ctrl *ctrl, CtrlPub *pub, unsigned seq, bool reset)
 {
-    k_publish<<<1, 64, 0, s>>>(ctrl, pub, seq);
+    k_publish<<<1, 64, 0, s>>>(ctrl, pub, seq, reset ? 1 : 0);
 }
 
 void launch_map_cg(hipStream_t s, const DevParams &P, const double *x, const double *f, double *com, double *fmap)
