@@ -21,7 +21,8 @@ Workloads (all lengths in units of the atom diameter sigma):
           CG force from a learned MLP or a tabulated cubic spline, cutoff 3.0.
 * ``c5``  1,000,000 tetrahedra (4M atoms), sphere AT radius 12 + hybrid shell 5.
 
-``tiny``-prefixed workloads are scaled-down versions used by the CPU tests.
+``tiny``- and ``small``-prefixed workloads are scaled-down versions used by the tests;
+``small_dumbbell`` and ``small_triangle`` hold 2- and 3-site molecules (unit bonds).
 """
 from __future__ import annotations
 
@@ -155,6 +156,26 @@ def tetra_positions(com, rng):
     return pos.reshape(n * 4, 3).T.copy()
 
 
+def _small_body(spm):
+    """Unit-edge rigid bodies centred at the origin: a dumbbell (2 sites) or an equilateral
+    triangle (3 sites), shape (spm, 3)."""
+    if spm == 2:
+        return np.array([[0.5, 0.0, 0.0], [-0.5, 0.0, 0.0]])
+    if spm == 3:
+        R = 1.0 / math.sqrt(3.0)   # circumradius of the unit triangle
+        return np.array([[0.0, R, 0.0], [-0.5, -0.5 * R, 0.0], [0.5, -0.5 * R, 0.0]])
+    raise ValueError(spm)
+
+
+def body_positions(com, spm, rng):
+    """Sites of randomly oriented dumbbells (spm 2) or triangles (spm 3) around the given
+    centres, com: (3, n_mol).  Returns unwrapped (3, spm*n_mol) site positions."""
+    n = com.shape[1]
+    rot = random_rotations(n, rng)
+    offs = np.einsum("nij,kj->nki", rot, _small_body(spm))
+    return (com.T[:, None, :] + offs).reshape(n * spm, 3).T.copy()
+
+
 def maxwell_velocities(n_sites, masses, kT, rng):
     """Maxwell-Boltzmann velocities at temperature kT with the total momentum removed."""
     m = np.asarray(masses, dtype=np.float64)
@@ -217,6 +238,14 @@ def workload(name: str) -> Workload:
         L = (1728 / 0.1) ** (1.0 / 3.0)
         return Workload("small_sphere", 1728, 4, (L, L, L), tetra_mass, REGION_SPHERE,
                         (L / 2, L / 2, L / 2), 4.0, 3.0, pair_precision=64, n_steps=20, seed=9)
+    if name in ("small_dumbbell", "small_triangle"):   # 2- and 3-site molecules, 10^3
+        # denser than C2 with a narrower CG site (sigma 1.75), so that atom pairs of
+        # neighbouring molecules are inside the WCA cutoff and lattice neighbours interact
+        spm = 2 if name == "small_dumbbell" else 3
+        L = (1000 / 0.15) ** (1.0 / 3.0)
+        return Workload(name, 1000, spm, (L, L, L), (1.0,) * spm, REGION_SLAB_X, (L / 2, L / 2, L / 2),
+                        3.0, 2.0, sig_cg=1.75, rc_cg=WCA_RC * 1.75, pair_precision=64, n_steps=50,
+                        seed=12 + spm)
     if name == "small_kg":
         L = (4000 / 0.85) ** (1.0 / 3.0)
         return Workload("small_kg", 4000, 1, (L, L, L), (1.0,), REGION_ALL_AT, (L / 2, L / 2, L / 2),
@@ -250,6 +279,10 @@ def make_state(wl: Workload, seed: int | None = None):
         dims = _lattice_dims(wl.n_mol, box)
         com = lattice_points(dims, box, rng, jitter=0.05)
         x = tetra_positions(com, rng)
+    elif wl.sites_per_mol in (2, 3):
+        dims = _lattice_dims(wl.n_mol, box)
+        com = lattice_points(dims, box, rng, jitter=0.05)
+        x = body_positions(com, wl.sites_per_mol, rng)
     elif wl.bond_kind == BOND_FENE:
         n = int(math.ceil(wl.n_mol ** (1.0 / 3.0) - 1e-9))
         path = serpentine_path(n)[: wl.n_mol]
