@@ -137,6 +137,7 @@ def main():
     achieved = bytes_per_launch / avg_force_s / 1e9
     traffic = _measured_traffic()
     pair_rate = n_inter / avg_force_s
+    copy_gbs = _copy_bandwidth_gbs(torch)
 
     out = {
         "metric": METRIC,
@@ -170,6 +171,11 @@ def main():
             "traffic": traffic,
             "kernel": "k_forces<4,float,step> (Eq. 1 + bonds + closing kick, opening kick + drift)",
             "bytes_per_launch": bytes_per_launch,
+            # counter bytes over the same time, against the peak (None without counters)
+            "traffic_frac": None if traffic is None else traffic / avg_force_s / 1e9 / HBM_PEAK_GBS,
+            # achievable HBM on this GPU: a plain 1 GiB device copy (read + write bytes)
+            "copy_GBps": copy_gbs,
+            "frac_of_copy": achieved / copy_gbs,
         },
     }
 
@@ -401,6 +407,24 @@ def kernel_source_digest():
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def _copy_bandwidth_gbs(torch, nbytes=1 << 30, reps=10):
+    """Achievable HBM bandwidth: the best of reps device-to-device copies of nbytes,
+    counting the bytes read and written."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) / 1e3)
+    del src, dst
+    return 2 * nbytes / best / 1e9
 
 
 def _measured_traffic():
