@@ -518,7 +518,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     c->epart_blocks = force_blocks(n);
     ok = ok && dalloc(&c->epart, 4 * (size_t)c->epart_blocks) == hipSuccess;
     ok = ok && dalloc(&c->tile_order, (size_t)c->epart_blocks) == hipSuccess &&
-         dalloc(&c->mcost, (size_t)n) == hipSuccess &&
+         dalloc(&c->mcost, ((size_t)n + 15) / 16 * 16) == hipSuccess &&   // whole 16-entry runs
          dalloc(&c->stencil, (size_t)G.n_cells * 27) == hipSuccess;
     if (q.region == ADRES_REGION_SPHERES) ok = ok && dalloc(&c->near, (size_t)n) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&c->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) == hipSuccess;

@@ -479,6 +479,7 @@ namespace {
 // is a valid permutation; ranges longer than kTileSortMax keep the identity.
 constexpr int kTileSortMax = 4096;
 constexpr int kTileThreads = 1024;
+constexpr int kTileRankMax = 512;    // longer ranges are sorted (bitonic) instead of ranked
 
 __global__ __launch_bounds__(kTileThreads) void k_tile_order(int n_mol, const unsigned *__restrict__ mcost, int n_tiles,
                                                             int *__restrict__ order)
@@ -494,50 +495,88 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_order(int n_mol, const un
     }
     for (int i = threadIdx.x; i < len; i += kTileThreads) tcost[i] = 0u;
     __syncthreads();
-    // per-molecule costs, 8 independent loads per thread in flight; the largest of each
-    // run of 16 molecules (one force-kernel wavefront) by xor shuffles inside 16-lane
-    // groups, summed per tile with LDS integer atomics (order-independent)
-    const int64_t m0 = (int64_t)start * 64, nm = (int64_t)len * 64;
-    for (int64_t base = 0; base < nm; base += (int64_t)kTileThreads * 8) {
-        unsigned mc[8];
+    // per-molecule costs in runs of 16 consecutive molecules (one force-kernel wavefront):
+    // each thread reads whole runs as four 16-byte vectors, two runs in flight, and adds the
+    // run's largest cost to its tile's total with an LDS integer atomic (order-independent).
+    // The cost array is padded to a multiple of 16 entries; the address of a run past the
+    // end is moved to the first run, and entries at or beyond n_mol are masked.
+    const int64_t m0 = (int64_t)start * 64;
+    const int n_runs = len * 4;
+    for (int r0 = 0; r0 < n_runs; r0 += 2 * kTileThreads) {
+        uint4 a[2][4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int64_t m = base + (int64_t)u * kTileThreads + threadIdx.x;
-            const int64_t t = m0 + m;
-            mc[u] = m < nm && t < n_mol ? mcost[t] : 0u;
+        for (int u = 0; u < 2; ++u) {
+            const int run = r0 + u * kTileThreads + threadIdx.x;
+            const int64_t t0 = m0 + (int64_t)run * 16;
+            const uint4 *p = reinterpret_cast<const uint4 *>(mcost + (run < n_runs && t0 < n_mol ? t0 : 0));
+#pragma unroll
+            for (int w = 0; w < 4; ++w) a[u][w] = p[w];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            unsigned v = mc[u];
+        for (int u = 0; u < 2; ++u) {
+            const int run = r0 + u * kTileThreads + threadIdx.x;
+            const int64_t t0 = m0 + (int64_t)run * 16;
+            const unsigned e[16] = {a[u][0].x, a[u][0].y, a[u][0].z, a[u][0].w, a[u][1].x, a[u][1].y,
+                                    a[u][1].z, a[u][1].w, a[u][2].x, a[u][2].y, a[u][2].z, a[u][2].w,
+                                    a[u][3].x, a[u][3].y, a[u][3].z, a[u][3].w};
+            unsigned v = 0u;
 #pragma unroll
-            for (int o = 1; o < 16; o <<= 1) {
-                const unsigned y = (unsigned)__shfl_xor((int)v, o, 64);
-                v = y > v ? y : v;
+            for (int k = 0; k < 16; ++k) {
+                const unsigned c = t0 + k < n_mol ? e[k] : 0u;
+                v = c > v ? c : v;
             }
-            const int64_t m = base + (int64_t)u * kTileThreads + threadIdx.x;
-            if ((threadIdx.x & 15) == 0 && m < nm) atomicAdd(&tcost[m / 64], v);
+            if (run < n_runs) atomicAdd(&tcost[run / 4], v);
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < len; i += kTileThreads)
-        key[i] = ((unsigned long long)tcost[i] << 32) | (unsigned)(~(unsigned)i);
-    for (int i = threadIdx.x; i < len; i += kTileThreads) tcost[i] = 0u;   // now the ranks
-    __syncthreads();
-    // rank of tile i = number of larger keys (keys are distinct), counted by all threads:
-    // C chunks of the j range per tile, partial counts added with LDS atomics
-    const int C = len < kTileThreads ? kTileThreads / len : 1;
-    const int per = (len + C - 1) / C;
-    for (int wk = threadIdx.x; wk < len * C; wk += kTileThreads) {
-        const int i = wk % len, c = wk / len;
-        const unsigned long long k = key[i];
-        const int j0 = c * per, j1 = min(len, j0 + per);
-        unsigned n_gt = 0u;
+    // keys (cost, then the lower index first) are distinct and nonzero
+    if (len <= kTileRankMax) {
+        // short ranges: rank of tile i = number of larger keys, counted by all threads in
+        // C chunks of the j range per tile, partial counts added with LDS atomics
+        for (int i = threadIdx.x; i < len; i += kTileThreads)
+            key[i] = ((unsigned long long)tcost[i] << 32) | (unsigned)(~(unsigned)i);
+        for (int i = threadIdx.x; i < len; i += kTileThreads) tcost[i] = 0u;   // now the ranks
+        __syncthreads();
+        const int C = len < kTileThreads ? kTileThreads / len : 1;
+        const int per = (len + C - 1) / C;
+        for (int wk = threadIdx.x; wk < len * C; wk += kTileThreads) {
+            const int i = wk % len, c = wk / len;
+            const unsigned long long k = key[i];
+            const int j0 = c * per, j1 = min(len, j0 + per);
+            unsigned n_gt = 0u;
 #pragma unroll 4
-        for (int j = j0; j < j1; ++j) n_gt += key[j] > k ? 1u : 0u;
-        atomicAdd(&tcost[i], n_gt);
+            for (int j = j0; j < j1; ++j) n_gt += key[j] > k ? 1u : 0u;
+            atomicAdd(&tcost[i], n_gt);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < len; i += kTileThreads) order[start + (int)tcost[i]] = start + i;
+        return;
     }
+    // long ranges: bitonic sort into falling order over a power-of-two padding of zeros
+    // (which sort last), log2(P2) (log2(P2) + 1) / 2 compare-exchange stages
+    int P2 = 1;
+    while (P2 < len) P2 <<= 1;
+    for (int i = threadIdx.x; i < P2; i += kTileThreads)
+        key[i] = i < len ? ((unsigned long long)tcost[i] << 32) | (unsigned)(~(unsigned)i) : 0ull;
     __syncthreads();
-    for (int i = threadIdx.x; i < len; i += kTileThreads) order[start + (int)tcost[i]] = start + i;
+    for (int k = 2; k <= P2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P2; i += kTileThreads) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const unsigned long long a = key[i], b = key[l];
+                    if ((i & k) == 0 ? a < b : a > b) {
+                        key[i] = b;
+                        key[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // position p holds the p-th largest key, whose low word is the complement of its tile
+    for (int p = threadIdx.x; p < len; p += kTileThreads)
+        order[start + p] = start + (int)(~(unsigned)(key[p] & 0xffffffffull));
 }
 
 }  // namespace
