@@ -67,7 +67,7 @@ def main():
                          "(reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU only (no multi-GPU path); --gpus must be 1"}))
         sys.exit(2)
 
     import torch
