@@ -101,16 +101,37 @@ def main():
 
     ctx.integrate(xt, vt, ft, wl.dt, args.warmup)
     torch.cuda.synchronize()
+    x_w, v_w = xt.clone(), vt.clone()   # the timed calls all start from this state
 
-    ctx.kernel_timing(True, every=TIMING_EVERY)   # record every TIMING_EVERY-th force launch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     nreb = ctx.integrate(xt, vt, ft, wl.dt, args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    force_ms, launches = ctx.kernel_timing(False)
     elapsed = t1 - t0
     steps_per_s = args.steps / elapsed
+    x_end, v_end = xt.clone(), vt.clone()
+
+    def rerun(timed_kernel):
+        # the timed call again from the post-warm-up state
+        xt.copy_(x_w)
+        vt.copy_(v_w)
+        if timed_kernel:
+            ctx.kernel_timing(True, every=TIMING_EVERY)   # events on every 8th force launch
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        ctx.integrate(xt, vt, ft, wl.dt, args.steps)
+        torch.cuda.synchronize()
+        return args.steps / (time.perf_counter() - ta)
+
+    # five repeats without events: their median rate (a spread check beside value), then
+    # one with HIP events on the force launches for the kernel's duration (the events slow
+    # the launch stream by a few per cent, so value and the median are taken without them)
+    rates = [rerun(False) for _ in range(5)]
+    rerun(True)
+    force_ms, launches = ctx.kernel_timing(False)
+    xt.copy_(x_end)
+    vt.copy_(v_end)
 
     # workload statistics on the final state (measurement only)
     n_pairs = ctx.build_verlet(xt)
@@ -169,6 +190,8 @@ def main():
         "interacting_pairs_per_eval": {"at_atom_pairs": n_at, "cg_com_pairs": n_cg},
         "listed_molecule_pairs": n_pairs,
         "force_kernel_us": avg_force_s * 1e6,
+        "steps_per_s_median_of_5": float(np.median(rates)),
+        "steps_per_s_of_5": rates,
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
