@@ -189,6 +189,7 @@ def main():
         "pair_interactions_per_s": pair_rate,
         "interacting_pairs_per_eval": {"at_atom_pairs": n_at, "cg_com_pairs": n_cg},
         "listed_molecule_pairs": n_pairs,
+        "listed_pairs_per_s": n_pairs / avg_force_s,   # candidates, beside the interacting rate
         "force_kernel_us": avg_force_s * 1e6,
         "steps_per_s_median_of_5": float(np.median(rates)),
         "steps_per_s_of_5": rates,
