@@ -842,6 +842,7 @@ adres_status adres_set_cg_table(adres_ctx *c, const float *coef4, int32_t n_knot
     c->P.tab_n = n_knots;
     c->P.tab_lo = r_lo;
     c->P.tab_h = (r_hi - r_lo) / (double)(n_knots - 1);
+    c->P.tab_inv_h = (double)(n_knots - 1) / (r_hi - r_lo);
     return ADRES_OK;
 }
 

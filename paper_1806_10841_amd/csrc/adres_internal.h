@@ -56,7 +56,7 @@ struct DevParams {
     // cubic CG table
     const float4 *tab;
     int tab_n;
-    double tab_lo, tab_h;
+    double tab_lo, tab_h, tab_inv_h;
     // correction force along the resolution coordinate: td_n values at the bin centres
     // of [td_lo, td_hi) (bin width td_h) and the integrals of the interpolated force from
     // td_lo to each centre (td_u, for its potential); td_n = 0: none

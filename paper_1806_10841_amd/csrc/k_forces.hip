@@ -66,11 +66,12 @@ __device__ __forceinline__ PT wca_f_over_r(PT r2, PT sig2, PT eps, PT &u, bool w
     return PT(24) * eps * s6 * (PT(2) * s6 - PT(1)) * inv;
 }
 
-// Cubic table of the CG force magnitude; interval and fraction located in FP64.
+// Cubic table of the CG force magnitude; interval and fraction located in FP64 (by a
+// multiplication with the reciprocal knot spacing: within an ulp of the quotient).
 template <typename PT>
 __device__ __forceinline__ PT table_f(const DevParams &P, double r, Ctrl *ctrl)
 {
-    double u = (r - P.tab_lo) / P.tab_h;
+    double u = (r - P.tab_lo) * P.tab_inv_h;
     if (r < P.tab_lo) atomicOr(&ctrl->err, kErrTableRange);
     double kf = floor(u);
     kf = kf >= 0.0 ? kf : 0.0;   // also maps NaN to interval 0
@@ -283,8 +284,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                     const float fv = SPM == 1 ? fp[j] : a.f_pair[a.pid[(int64_t)tt * a.cap + k0 + j]];
                     fr = (PT)fv * (PT)__builtin_amdgcn_rsqf((float)r2c);
                 } else {
-                    const double r = sqrt(r2c);
-                    fr = table_f<PT>(P, r, a.ctrl) / (PT)r;
+                    // r and 1/r from one refined reciprocal square root: no FP64 square
+                    // root or division on the table path
+                    const double ir = rsqrt_refined(r2c);
+                    fr = table_f<PT>(P, r2c * ir, a.ctrl) * (PT)ir;
                 }
                 const PT sc = (PT)(1.0 - ww) * fr;
                 cg0 += (double)(sc * (PT)D0);
