@@ -489,6 +489,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_order(int n_mol, const un
     const int x = blockIdx.x;
     const int q = n_tiles / 8, r = n_tiles % 8;
     const int start = x * q + (x < r ? x : r), len = q + (x < r ? 1 : 0);
+    if (len == 0) return;   // fewer tiles than XCDs: this range is empty
     if (len > kTileSortMax) {
         for (int i = threadIdx.x; i < len; i += kTileThreads) order[start + i] = start + i;
         return;
