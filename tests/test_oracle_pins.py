@@ -410,6 +410,13 @@ def test_golden_weights():
         assert abs(oracle.weight_of_distance(d, d_at, d_hy) - w) <= 1e-15, (d_at, d_hy, d)
 
 
+def test_weight_without_hybrid_layer_is_a_step():
+    # d_hy = 0: exactly 1 up to and including d_at, exactly 0 beyond (no cosine evaluated)
+    for d_at in (0.0, 1.5, 4.0):
+        for d, w in ((0.0, 1.0), (d_at, 1.0), (np.nextafter(d_at, np.inf), 0.0), (d_at + 3.0, 0.0)):
+            assert oracle.weight_of_distance(d, d_at, 0.0) == w, (d_at, d)
+
+
 def test_golden_wca():
     from oracle import tables
     for sig, eps, r, f in _golden("wca"):
