@@ -119,15 +119,41 @@ def params_from(wl) -> Params:
     return p
 
 
-def _ptr(t):
+def _ptr(t, dtype=None, shape=None, min_numel=None, name="tensor"):
+    """Device pointer of a contiguous torch tensor on the GPU, after checking its dtype
+    (a torch dtype) and its exact shape (None entries match any extent) or its least
+    element count: a wrong dtype or extent would make the kernels read or write outside
+    the allocation, so a mismatch raises instead."""
     if t is None:
         return None
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError("expected a CUDA (HIP) torch tensor")
-    if not t.is_contiguous():
-        raise ValueError("tensor must be contiguous")
+        raise TypeError(f"{name}: expected a CUDA (HIP) torch tensor")
+    check_tensor(t, dtype, shape, min_numel, name)
     return C.c_void_p(t.data_ptr())
+
+
+def check_tensor(t, dtype=None, shape=None, min_numel=None, name="tensor"):
+    """The layout checks of _ptr (contiguity, dtype, shape, element count), on any device."""
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if shape is not None:
+        if t.dim() != len(shape) or any(s is not None and s != q for s, q in zip(shape, t.shape)):
+            raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(f"{name}: needs at least {min_numel} elements, got {t.numel()}")
+
+
+def _f64():
+    import torch
+    return torch.float64
+
+
+def _i64():
+    import torch
+    return torch.int64
 
 
 class Context:
@@ -165,20 +191,34 @@ class Context:
             msg = self.lib.adres_last_error(self.h).decode()
             raise AdresError(st, f"{what}: {msg}")
 
+    # -- argument checks ---------------------------------------------------------
+    def _x(self, t, name="x"):
+        """A site array: float64 (3, n_sites)."""
+        return _ptr(t, _f64(), (3, self.n_sites), name=name)
+
+    def _counts(self, t, name="counts"):
+        """A histogram over the installed correction table's bins: int64, 1-D."""
+        return _ptr(t, _i64(), (None,), min_numel=max(self._td_n, 1), name=name)
+
+    def _frames(self, com, fmap):
+        """Frames of centres and mapped forces: float64 (n_frames, 3, n_mol) each."""
+        shape = (com.shape[0] if com.dim() == 3 else -1, 3, self.wl.n_mol)
+        return _ptr(com, _f64(), shape, name="com"), _ptr(fmap, _f64(), shape, name="f_map")
+
     # -- entry points ----------------------------------------------------------
     def weights(self, x):
         import torch
         com = torch.empty((3, self.wl.n_mol), dtype=torch.float64, device=x.device)
         w = torch.empty(self.wl.n_mol, dtype=torch.float64, device=x.device)
-        self._check(self.lib.adres_weights(self.h, _ptr(x), _ptr(com), _ptr(w)), "adres_weights")
+        self._check(self.lib.adres_weights(self.h, self._x(x), _ptr(com), _ptr(w)), "adres_weights")
         return com, w
 
     def build_cells(self, x):
-        self._check(self.lib.adres_build_cells(self.h, _ptr(x)), "adres_build_cells")
+        self._check(self.lib.adres_build_cells(self.h, self._x(x)), "adres_build_cells")
 
     def build_verlet(self, x):
         n = C.c_int64()
-        self._check(self.lib.adres_build_verlet(self.h, _ptr(x), C.byref(n)), "adres_build_verlet")
+        self._check(self.lib.adres_build_verlet(self.h, self._x(x), C.byref(n)), "adres_build_verlet")
         return n.value
 
     def forces(self, x, f=None, energy=False):
@@ -186,20 +226,21 @@ class Context:
         if f is None:
             f = torch.empty_like(x)
         e = torch.zeros(4, dtype=torch.float64, device=x.device) if energy else None
-        self._check(self.lib.adres_forces(self.h, _ptr(x), _ptr(f), _ptr(e)), "adres_forces")
+        self._check(self.lib.adres_forces(self.h, self._x(x), self._x(f, "f"), _ptr(e, _f64(), (4,), name="energy")),
+                    "adres_forces")
         return (f, e) if energy else f
 
     def integrate_respa(self, x, v, f, dt, n_inner, n_outer, gamma=0.0, kT=1.0, seed=0):
         nreb = C.c_int32()
-        st = self.lib.adres_integrate_respa(self.h, _ptr(x), _ptr(v), _ptr(f), dt, n_inner, n_outer, gamma, kT,
-                                            seed, C.byref(nreb))
+        st = self.lib.adres_integrate_respa(self.h, self._x(x), self._x(v, "v"), self._x(f, "f"), dt, n_inner,
+                                            n_outer, gamma, kT, seed, C.byref(nreb))
         self._check(st, "adres_integrate_respa")
         return nreb.value
 
     def integrate(self, x, v, f, dt, n_steps, gamma=0.0, kT=1.0, seed=0):
         nreb = C.c_int32()
-        st = self.lib.adres_integrate(self.h, _ptr(x), _ptr(v), _ptr(f), dt, n_steps, gamma, kT, seed,
-                                      C.byref(nreb))
+        st = self.lib.adres_integrate(self.h, self._x(x), self._x(v, "v"), self._x(f, "f"), dt, n_steps, gamma,
+                                      kT, seed, C.byref(nreb))
         self._check(st, "adres_integrate")
         return nreb.value
 
@@ -247,32 +288,22 @@ class Context:
 
     def density_profile(self, x, counts):
         """Add the centre-of-mass distance histogram of x to counts (int64 device tensor)."""
-        import torch
-        if counts.dtype != torch.int64:
-            raise TypeError("counts must be int64")
-        self._check(self.lib.adres_density_profile(self.h, _ptr(x), _ptr(counts)), "adres_density_profile")
+        self._check(self.lib.adres_density_profile(self.h, self._x(x), self._counts(counts)),
+                    "adres_density_profile")
 
     def tdforce_update(self, counts, n_frames, prefactor):
-        import torch
-        if counts.dtype != torch.int64:
-            raise TypeError("counts must be int64")
-        self._check(self.lib.adres_tdforce_update(self.h, _ptr(counts), int(n_frames), float(prefactor)),
+        self._check(self.lib.adres_tdforce_update(self.h, self._counts(counts), int(n_frames), float(prefactor)),
                     "adres_tdforce_update")
 
     def region_volumes(self, x, n_samples, seed, vol_counts):
         """Add the bins of n_samples uniform points to vol_counts (int64 device tensor)."""
-        import torch
-        if vol_counts.dtype != torch.int64:
-            raise TypeError("vol_counts must be int64")
-        xp = _ptr(x) if x is not None else None
+        xp = self._x(x) if x is not None else None
         self._check(self.lib.adres_region_volumes(self.h, xp, int(n_samples), int(seed) & (2**64 - 1),
-                                                  _ptr(vol_counts)), "adres_region_volumes")
+                                                  self._counts(vol_counts, "vol_counts")), "adres_region_volumes")
 
     def tdforce_update_sampled(self, counts, n_frames, vol_counts, n_vol_samples, prefactor):
-        import torch
-        if counts.dtype != torch.int64 or vol_counts.dtype != torch.int64:
-            raise TypeError("counts must be int64")
-        self._check(self.lib.adres_tdforce_update_sampled(self.h, _ptr(counts), int(n_frames), _ptr(vol_counts),
+        self._check(self.lib.adres_tdforce_update_sampled(self.h, self._counts(counts), int(n_frames),
+                                                          self._counts(vol_counts, "vol_counts"),
                                                           int(n_vol_samples), float(prefactor)),
                     "adres_tdforce_update_sampled")
 
@@ -288,8 +319,9 @@ class Context:
 
     def mlp_eval(self, r):
         import torch
+        rp = _ptr(r, torch.float64, (None,), name="r")
         f = torch.empty(r.shape[0], dtype=torch.float32, device=r.device)
-        self._check(self.lib.adres_mlp_eval(self.h, _ptr(r), _ptr(f), r.shape[0]), "adres_mlp_eval")
+        self._check(self.lib.adres_mlp_eval(self.h, rp, _ptr(f), r.shape[0]), "adres_mlp_eval")
         return f
 
     def map_cg(self, x):
@@ -298,20 +330,22 @@ class Context:
         f = torch.empty_like(x)
         com = torch.empty((3, self.wl.n_mol), dtype=torch.float64, device=x.device)
         fmap = torch.empty_like(com)
-        self._check(self.lib.adres_map_cg(self.h, _ptr(x), _ptr(f), _ptr(com), _ptr(fmap)), "adres_map_cg")
+        self._check(self.lib.adres_map_cg(self.h, self._x(x), _ptr(f), _ptr(com), _ptr(fmap)), "adres_map_cg")
         return com, fmap
 
     def mlp_fm_grad(self, com, fmap):
         """com, fmap: device float64 tensors (n_frames, 3, n_mol)."""
         g = np.empty(4353, dtype=np.float64)
         loss = C.c_double()
-        self._check(self.lib.adres_mlp_fm_grad(self.h, _ptr(com), _ptr(fmap), com.shape[0],
+        com_p, fmap_p = self._frames(com, fmap)
+        self._check(self.lib.adres_mlp_fm_grad(self.h, com_p, fmap_p, com.shape[0],
                                                g.ctypes.data_as(C.c_void_p), C.byref(loss)), "adres_mlp_fm_grad")
         return loss.value, g
 
     def mlp_train_step(self, com, fmap, lr):
         loss = C.c_double()
-        self._check(self.lib.adres_mlp_train_step(self.h, _ptr(com), _ptr(fmap), com.shape[0], lr, C.byref(loss)),
+        com_p, fmap_p = self._frames(com, fmap)
+        self._check(self.lib.adres_mlp_train_step(self.h, com_p, fmap_p, com.shape[0], lr, C.byref(loss)),
                     "adres_mlp_train_step")
         return loss.value
 

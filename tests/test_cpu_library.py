@@ -52,3 +52,30 @@ def test_no_cpu_fallback():
     from paper_1806_10841_amd import inputs
     with pytest.raises(RuntimeError):
         binding.Context(inputs.workload("c1"))
+
+
+def test_binding_refuses_wrong_dtype_or_shape():
+    """The binding checks dtype and extents before any call: a float32 position array, a
+    transposed or short one, a (3, n_mol) array where frames (n_frames, 3, n_mol) are
+    expected, or a histogram shorter than the bins would let the kernels read or write
+    outside the allocation."""
+    torch = pytest.importorskip("torch")
+    chk = binding.check_tensor
+    ok = torch.zeros((3, 8), dtype=torch.float64)
+    chk(ok, torch.float64, (3, 8))
+    with pytest.raises(TypeError):
+        chk(ok.float(), torch.float64, (3, 8))
+    with pytest.raises(ValueError):
+        chk(torch.zeros((8, 3), dtype=torch.float64), torch.float64, (3, 8))
+    with pytest.raises(ValueError):
+        chk(torch.zeros((3, 7), dtype=torch.float64), torch.float64, (3, 8))
+    with pytest.raises(ValueError):
+        chk(ok.t(), torch.float64, (8, 3))                 # not contiguous
+    with pytest.raises(ValueError):
+        chk(torch.zeros((3, 8), dtype=torch.float64), torch.float64, (2, 3, 8))
+    chk(torch.zeros((5, 3, 8), dtype=torch.float64), torch.float64, (5, 3, 8))
+    chk(torch.zeros(14, dtype=torch.int64), torch.int64, (None,), min_numel=14)
+    with pytest.raises(ValueError):
+        chk(torch.zeros(13, dtype=torch.int64), torch.int64, (None,), min_numel=14)
+    with pytest.raises(TypeError):
+        binding._ptr(ok)                                   # a host tensor is refused outright

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
+from _bars import assert_fp32_sites, nonbonded_model
 from paper_1806_10841_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -66,9 +67,10 @@ def test_forces_fp32_pairs(dev, name):
     x, _ = inputs.make_state(wl)
     fo, amag, eo, st = oracle.Model(wl).forces(x)
     assert st == 0
+    _, amag_nb, _, _ = nonbonded_model(wl).forces(x)
     f, e = _ctx(wl).forces(_t(x, dev), energy=True)
     torch.cuda.synchronize()
-    _assert_close(f.cpu().numpy(), fo, amag, 1e-5, name)
+    assert_fp32_sites(f.cpu().numpy(), fo, amag, amag_nb, 1e-5, name)
     np.testing.assert_allclose(e.cpu().numpy(), eo, rtol=1e-5, atol=1e-5 * np.abs(eo).max())
 
 
@@ -104,11 +106,10 @@ def test_forces_c2_full_size_sampled(dev):
     sel = np.sort(np.concatenate(sel))
     fo, amag, st = m.forces_sampled(x, sel)
     assert st == 0
+    _, amag_nb, _ = nonbonded_model(wl).forces_sampled(x, sel)
     f = _ctx(wl).forces(_t(x, dev)).cpu().numpy()
     fg = np.stack([f[:, 4 * a:4 * a + 4] for a in sel])
-    err = np.abs(fg - fo).max(axis=1)
-    assert np.all(err <= 1e-5 * amag), (err / amag).max()
-    assert np.linalg.norm(fg - fo) <= 1e-5 * np.linalg.norm(fo)
+    assert_fp32_sites(fg, fo, amag, amag_nb, 1e-5, "c2 sampled", axis=1)
 
 
 def _min_image(d, L):

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
+from _bars import assert_fp32_sites, nonbonded_model
 from paper_1806_10841_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -126,10 +127,11 @@ def test_forces_fp32_pairs(dev, name):
     wl = inputs.workload(name).with_(pair_precision=32)
     x, _ = inputs.make_state(wl)
     fo, amag, eo, st = oracle.Model(wl).forces(x)
+    _, amag_nb, _, _ = nonbonded_model(wl).forces(x)
     ctx = _ctx(wl)
     f, e = ctx.forces(_t(x, dev), energy=True)
     torch.cuda.synchronize()
-    assert_forces_close(f.cpu().numpy(), fo, amag, 1e-5, name)
+    assert_fp32_sites(f.cpu().numpy(), fo, amag, amag_nb, 1e-5, name)
     np.testing.assert_allclose(e.cpu().numpy(), eo, rtol=1e-5, atol=1e-5 * np.abs(eo).max())
 
 
@@ -153,13 +155,12 @@ def test_forces_c2_full_size_sampled(dev):
     sel = _sample_by_class(w_o, 60, 0)
     fo, amag, st = m.forces_sampled(x, sel)
     assert st == 0
+    _, amag_nb, _ = nonbonded_model(wl).forces_sampled(x, sel)
     ctx = _ctx(wl)
     xt = _t(x, dev)
     f = ctx.forces(xt).cpu().numpy()
     fg = np.stack([f[:, 4 * a:4 * a + 4] for a in sel])          # (n_sel, 3, 4)
-    err = np.abs(fg - fo).max(axis=1)                               # (n_sel, 4)
-    assert np.all(err <= 1e-5 * amag), (err / amag).max()
-    assert np.linalg.norm(fg - fo) <= 1e-5 * np.linalg.norm(fo)
+    assert_fp32_sites(fg, fo, amag, amag_nb, 1e-5, "c2 sampled", axis=1)
     # Newton's third law (Sec. 2.3): every pair term is computed with the same bits and
     # opposite sign from both sides, so the net force is FP64 summation rounding only
     tot = np.abs(f.sum(axis=1))
@@ -184,7 +185,8 @@ def test_forces_table_cg(dev):
     ctx32.set_cg_table(coef, lo, hi)
     f32 = ctx32.forces(_t(x, dev))
     torch.cuda.synchronize()
-    assert_forces_close(f32.cpu().numpy(), fo, amag, 1e-5, "table fp32")
+    _, amag_nb, _, _ = nonbonded_model(wl, table=(coef, lo, hi)).forces(x)
+    assert_fp32_sites(f32.cpu().numpy(), fo, amag, amag_nb, 1e-5, "table fp32")
 
 
 def test_forces_deterministic(dev):
