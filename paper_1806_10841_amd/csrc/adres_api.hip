@@ -38,6 +38,11 @@ struct adres_ctx {
     int *count = nullptr, *start = nullptr, *fill = nullptr, *new_from = nullptr, *scan_tiles = nullptr;
     int *nbr = nullptr, *cnt = nullptr;
     int cap = 0;
+    // tile halos of the force kernel and the rows as local halo indices
+    int *hid = nullptr, *hn = nullptr;
+    uint16_t *lnbr = nullptr;
+    int hcap = 0, lcap = 0;
+    bool rw_stale = false;   // the step kernels moved the positions without storing centres
     Ctrl *ctrl = nullptr;
     Ctrl *ctrl_host = nullptr;     // last values read by the host
     CtrlPub *pub = nullptr;        // host-mapped pinned copy written by k_publish
@@ -99,8 +104,6 @@ StateBufs view(const adres_ctx *c, int pos, int ord)
     StateBufs b;
     b.x = c->S[pos].x;
     b.Rw = c->S[pos].Rw;
-    b.rho = c->S[pos].rho;
-    b.off = c->S[pos].off;
     b.v = c->S[ord].v;
     b.perm = c->S[ord].perm;
     b.key = c->S[ord].key;
@@ -151,6 +154,7 @@ adres_status read_ctrl(adres_ctx *c, bool reset_halt = false)
     c->ctrl_host->err = c->pub->err;
     c->ctrl_host->overflow = c->pub->overflow;
     c->ctrl_host->max_count = c->pub->max_count;
+    c->ctrl_host->max_halo = c->pub->max_halo;
     int e = c->ctrl_host->err;
     if (e) {
         HIPCHK(c, hipMemsetAsync(&c->ctrl->err, 0, sizeof(int), c->stream));
@@ -165,6 +169,7 @@ adres_status read_ctrl(adres_ctx *c, bool reset_halt = false)
 adres_status gather(adres_ctx *c, const double *x, const double *v, bool check_disp)
 {
     launch_gather(c->stream, c->P, x, v, cur(c), check_disp ? c->R_ref : nullptr, c->ctrl);
+    c->rw_stale = false;
     if (c->P.region == ADRES_REGION_SPHERES)
         launch_anchor_weights(c->stream, c->P, cur(c).Rw, c->inv_perm, c->ctrl, 0, 0, c->near);
     HIPCHK(c, hipGetLastError());
@@ -175,6 +180,10 @@ adres_status resort(adres_ctx *c, bool with_v)
 {
     const StateBufs src = cur(c);
     const StateBufs dst = view(c, 1 - c->pos, 1 - c->ord);
+    if (c->rw_stale) {
+        launch_centres(c->stream, c->P, src.x, src.Rw, c->ctrl);
+        c->rw_stale = false;
+    }
     launch_cell_keys(c->stream, c->P, c->G, c->cell_rank, src.Rw, src.key, c->count);
     launch_scan_cells(c->stream, c->count, c->G.n_cells, c->start, c->fill, c->scan_tiles);
     launch_scatter_slots(c->stream, c->P.n_mol, src.key, c->start, c->fill, c->new_from);
@@ -191,6 +200,42 @@ adres_status resort(adres_ctx *c, bool with_v)
 }
 
 bool is_mlp(const adres_ctx *c) { return c->P.cg_kind >= ADRES_CG_MLP; }
+
+// The step kernels store the new centres only when something reads them before the next
+// list build: the network's pair pre-pass and the anchor pass of a self-adjusting region.
+bool keep_centres(const adres_ctx *c) { return is_mlp(c) || c->P.region == ADRES_REGION_SPHERES; }
+
+// Row length of the local-index rows: each lane's quarter holds ceil(cap / 4) entries,
+// rounded up to whole 16-byte loads (8 entries).
+int local_cap(int cap) { return 4 * ((((cap + 3) / 4) + 7) / 8 * 8); }
+
+// (Re)allocates the tile halos for capacity hcap and the local rows for the list capacity.
+adres_status alloc_halo(adres_ctx *c, int hcap)
+{
+    const int tiles = (c->P.n_mol + kHaloTile - 1) / kHaloTile;
+    const int lcap = local_cap(c->cap);
+    if (hcap != c->hcap || !c->hid) {
+        hipFree(c->hid);
+        c->hid = nullptr;
+        if (dalloc(&c->hid, (size_t)tiles * hcap) != hipSuccess)
+            return fail(c, ADRES_E_NOMEM, "could not allocate the tile halos");
+        c->hcap = hcap;
+    }
+    if (lcap != c->lcap || !c->lnbr) {
+        hipFree(c->lnbr);
+        c->lnbr = nullptr;
+        if (dalloc(&c->lnbr, (size_t)lcap * c->P.n_mol) != hipSuccess)
+            return fail(c, ADRES_E_NOMEM, "could not allocate the local rows");
+        c->lcap = lcap;
+    }
+    return ADRES_OK;
+}
+
+void launch_halo(adres_ctx *c)
+{
+    launch_halo_build(c->stream, c->P.n_mol, c->nbr, c->cnt, c->cap, c->hcap, c->lcap, c->hid, c->hn, c->lnbr,
+                      c->ctrl);
+}
 
 // Every unordered pair of the Verlet list once (t < u) and, for every list entry, the
 // id of its pair; the network is evaluated per pair, so both directions of a pair
@@ -236,24 +281,21 @@ MlpDev mlp_dev(const adres_ctx *c)
     return M;
 }
 
-// Verlet list from the current (sorted) centres; grows the capacity on overflow.
+// Verlet list from the current (sorted) centres and the tile halos from it; grows the list
+// and halo capacities on overflow.  The halos are built last: the learned CG force's half
+// list reorders every row, and the local rows must follow the final row order.
 adres_status build_list(adres_ctx *c)
 {
     for (int attempt = 0; attempt < 4; ++attempt) {
-        HIPCHK(c, hipMemsetAsync(&c->ctrl->overflow, 0, 2 * sizeof(int), c->stream));
+        HIPCHK(c, hipMemsetAsync(&c->ctrl->overflow, 0, 3 * sizeof(int), c->stream));
         const StateBufs b = cur(c);
         launch_list_build(c->stream, c->P, c->G, c->stencil, c->start, b.Rw, c->rl2, c->nbr, c->cnt, c->cap,
                           c->mcost, c->ctrl);
         HIPCHK(c, hipGetLastError());
         adres_status st = read_ctrl(c);
         if (st != ADRES_OK) return st;
-        if (!c->ctrl_host->overflow) {
-            c->list_valid = true;
-            launch_tile_order(c->stream, c->P, c->mcost, c->epart_blocks, c->tile_order);
-            launch_reset_halt(c->stream, c->ctrl);   // an earlier overflow may have left halt = -1
-            if (c->P.cg_kind >= ADRES_CG_MLP) return build_half_list(c);
-            return ADRES_OK;
-        }
+        if (!c->ctrl_host->overflow) break;
+        if (attempt == 3) return fail(c, ADRES_E_CAPACITY, "neighbour list capacity did not converge");
         int need = c->ctrl_host->max_count;
         int new_cap = ((need + need / 4 + 8) + 15) & ~15;
         HIPCHK(c, hipFree(c->nbr));
@@ -261,8 +303,36 @@ adres_status build_list(adres_ctx *c)
         if (dalloc(&c->nbr, (size_t)new_cap * c->P.n_mol) != hipSuccess)
             return fail(c, ADRES_E_CAPACITY, "could not grow the neighbour list");
         c->cap = new_cap;
+        st = alloc_halo(c, c->hcap);
+        if (st != ADRES_OK) return st;
     }
-    return fail(c, ADRES_E_CAPACITY, "neighbour list capacity did not converge");
+    launch_tile_order(c->stream, c->P, c->mcost, c->epart_blocks, c->tile_order);
+    if (is_mlp(c)) {
+        adres_status st = build_half_list(c);
+        if (st != ADRES_OK) return st;
+    }
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        launch_halo(c);
+        HIPCHK(c, hipGetLastError());
+        adres_status st = read_ctrl(c);
+        if (st != ADRES_OK) return st;
+        if (!(c->ctrl_host->overflow & 2)) {
+            c->list_valid = true;
+            launch_reset_halt(c->stream, c->ctrl);   // an earlier overflow may have left halt = -1
+            return ADRES_OK;
+        }
+        // a tile's halo outgrew its capacity
+        const int need = c->ctrl_host->max_halo;
+        const int limit = halo_capacity_limit(c->P.spm, c->prm.pair_precision);
+        if (need > limit)
+            return fail(c, ADRES_E_CAPACITY, "a tile's neighbour halo (" + std::to_string(need) +
+                                                 " molecules) exceeds the force kernel's LDS (" +
+                                                 std::to_string(limit) + ")");
+        HIPCHK(c, hipMemsetAsync(&c->ctrl->overflow, 0, 3 * sizeof(int), c->stream));
+        st = alloc_halo(c, std::min(limit, ((need + need / 8 + 16) + 31) & ~31));
+        if (st != ADRES_OK) return st;
+    }
+    return fail(c, ADRES_E_CAPACITY, "tile halo capacity did not converge");
 }
 
 // Verlet list without waiting: an overflowing row sets ctrl->halt = -1, which stops
@@ -276,7 +346,12 @@ adres_status build_list_async(adres_ctx *c)
     launch_tile_order(c->stream, c->P, c->mcost, c->epart_blocks, c->tile_order);
     HIPCHK(c, hipGetLastError());
     c->list_valid = true;
-    if (is_mlp(c)) return build_half_list(c);
+    if (is_mlp(c)) {
+        adres_status st = build_half_list(c);
+        if (st != ADRES_OK) return st;
+    }
+    launch_halo(c);
+    HIPCHK(c, hipGetLastError());
     return ADRES_OK;
 }
 
@@ -287,11 +362,13 @@ ForceArgs force_args(adres_ctx *c)
     a.P = c->P;
     a.x = S.x;
     a.Rw = S.Rw;
-    a.rho = S.rho;
-    a.off = S.off;
-    a.nbr = c->nbr;
     a.cnt = c->cnt;
     a.cap = c->cap;
+    a.hid = c->hid;
+    a.hn = c->hn;
+    a.hcap = c->hcap;
+    a.lnbr = c->lnbr;
+    a.lcap = c->lcap;
     a.perm = S.perm;
     a.inv_perm = c->inv_perm;
     a.ctrl = c->ctrl;
@@ -501,8 +578,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     bool ok = true;
     for (int b = 0; b < 2; ++b) {
         ok = ok && dalloc(&c->S[b].x, 3 * ns) == hipSuccess && dalloc(&c->S[b].v, 3 * ns) == hipSuccess &&
-             dalloc(&c->S[b].Rw, n) == hipSuccess && dalloc(&c->S[b].rho, n) == hipSuccess &&
-             dalloc(&c->S[b].off, 3 * ns) == hipSuccess &&
+             dalloc(&c->S[b].Rw, n) == hipSuccess &&
              dalloc(&c->S[b].perm, n) == hipSuccess && dalloc(&c->S[b].key, n) == hipSuccess;
     }
     ok = ok && dalloc(&c->f, 3 * ns) == hipSuccess;
@@ -517,6 +593,8 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
          dalloc(&c->up_scratch, n) == hipSuccess;
     c->epart_blocks = force_blocks(n);
     ok = ok && dalloc(&c->epart, 4 * (size_t)c->epart_blocks) == hipSuccess;
+    ok = ok && dalloc(&c->hn, (size_t)c->epart_blocks) == hipSuccess;
+    ok = ok && alloc_halo(c, std::min(256, halo_capacity_limit(q.sites_per_mol, q.pair_precision))) == ADRES_OK;
     ok = ok && dalloc(&c->tile_order, (size_t)c->epart_blocks) == hipSuccess &&
          dalloc(&c->mcost, ((size_t)n + 15) / 16 * 16) == hipSuccess &&   // whole 16-entry runs
          dalloc(&c->stencil, (size_t)G.n_cells * 27) == hipSuccess;
@@ -533,7 +611,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     }
     std::vector<int> ident(n);
     for (int i = 0; i < n; ++i) ident[i] = i;
-    Ctrl c0{INT_MAX, 0, 0, 0};
+    Ctrl c0{INT_MAX, 0, 0, 0, 0};
     bool cp = hipMemcpy(c->cell_rank, rank.data(), sizeof(int) * G.n_cells, hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->S[0].perm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->S[1].perm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice) == hipSuccess &&
@@ -556,13 +634,13 @@ void adres_destroy(adres_ctx *c)
     if (c->stream) hipStreamSynchronize(c->stream);
     else hipDeviceSynchronize();
     for (int b = 0; b < 2; ++b) {
-        hipFree(c->S[b].x); hipFree(c->S[b].v); hipFree(c->S[b].Rw); hipFree(c->S[b].off);
-        hipFree(c->S[b].rho); hipFree(c->S[b].perm); hipFree(c->S[b].key);
+        hipFree(c->S[b].x); hipFree(c->S[b].v); hipFree(c->S[b].Rw);
+        hipFree(c->S[b].perm); hipFree(c->S[b].key);
     }
     hipFree(c->f);
     hipFree(c->R_ref); hipFree(c->inv_perm); hipFree(c->cell_rank);
     hipFree(c->count); hipFree(c->start); hipFree(c->fill); hipFree(c->new_from); hipFree(c->scan_tiles);
-    hipFree(c->nbr); hipFree(c->cnt); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
+    hipFree(c->nbr); hipFree(c->cnt); hipFree(c->hid); hipFree(c->hn); hipFree(c->lnbr); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
     hipFree(c->td); hipFree(c->td_u); hipFree(c->anchors); hipFree(c->near); hipFree(c->anchor_cen); hipFree(c->tile_order); hipFree(c->mcost); hipFree(c->stencil);
     hipFree(c->mlp); hipFree(c->mlp_w2); hipFree(c->mlp_w2q); hipFree(c->mlp_fp8s); hipFree(c->cnt_up); hipFree(c->up_off); hipFree(c->up_scratch);
     hipFree(c->pid); hipFree(c->up_pairs); hipFree(c->f_pair);
@@ -691,8 +769,8 @@ adres_status integrate_impl(adres_ctx *c, double *x, double *v, double *f, doubl
             StepArgs sa{dt, gamma, kT, seed, c->step_counter + (uint64_t)gk};
             const StateBufs in = view(c, p, c->ord), out = view(c, 1 - p, c->ord);
             if (gk == 0) {
-                launch_kick_drift(c->stream, c->P, in.x, in.v, c->f, out.x, out.Rw, out.rho, out.off, c->R_ref,
-                                  in.perm, c->ctrl, k, sa);
+                launch_kick_drift(c->stream, c->P, in.x, in.v, c->f, out.x, out.Rw, c->R_ref, in.perm, c->ctrl, k,
+                                  sa);
                 if (c->P.region == ADRES_REGION_SPHERES)
                     launch_anchor_weights(c->stream, c->P, out.Rw, c->inv_perm, c->ctrl, k, 1, c->near);
                 HIPCHK(c, hipGetLastError());
@@ -700,8 +778,6 @@ adres_status integrate_impl(adres_ctx *c, double *x, double *v, double *f, doubl
                 ForceArgs a = force_args(c);
                 a.x = in.x;
                 a.Rw = in.Rw;
-                a.rho = in.rho;
-                a.off = in.off;
                 a.v = in.v;
                 a.st = sa;
                 a.step = k;
@@ -710,10 +786,9 @@ adres_status integrate_impl(adres_ctx *c, double *x, double *v, double *f, doubl
                 if (gk < n_steps) {
                     a.mode = kModeStep;
                     a.x_out = out.x;
-                    a.Rw_out = out.Rw;
-                    a.rho_out = out.rho;
-                    a.off_out = out.off;
+                    a.Rw_out = keep_centres(c) ? out.Rw : nullptr;
                     a.R_ref = c->R_ref;
+                    if (!keep_centres(c)) c->rw_stale = true;
                 } else {
                     a.mode = kModeClose;
                     a.f = c->f;

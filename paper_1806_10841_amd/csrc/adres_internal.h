@@ -24,8 +24,10 @@ enum : int {
 struct Ctrl {
     int halt;       // first step (within the current chunk) that requested a list rebuild
     int err;        // kErr* bits
-    int overflow;   // neighbour list row longer than capacity
+    int overflow;   // bit 0: a neighbour-list row longer than its capacity; bit 1: a tile's
+                    // neighbour halo larger than its capacity
     int max_count;  // longest neighbour-list row seen by the last build
+    int max_halo;   // largest tile halo seen by the last halo build (on overflow)
 };
 
 // Copy of the control block in host-mapped pinned memory, published by a one-thread
@@ -34,7 +36,8 @@ struct Ctrl {
 struct CtrlPub {
     int halt, err, overflow, max_count;
     unsigned seq;
-    int pad[3];
+    int max_halo;
+    int pad[2];
 };
 
 // Parameters in the form the kernels use (passed by value).
@@ -384,25 +387,17 @@ __device__ __forceinline__ void close_kick(double v[3], const double F[3], doubl
     for (int d = 0; d < 3; ++d) v[d] = v[d] + F[d] * dt * inv_2m;
 }
 
-// Centre, weight and rho of a molecule at slot t into the packed outputs, with the
-// stretch / non-finite checks and the displacement check against R_ref (which
-// lowers ctrl->halt to halt_value).
+// Centre and weight of a molecule at slot t into Rw, with the stretch / non-finite
+// checks and the displacement check against R_ref (which lowers ctrl->halt to
+// halt_value).
 template <int SPM>
 __device__ __forceinline__ void store_molecule(const DevParams &P, const double (&p)[SPM][3], int t,
-                                               double4 *Rw, float *rho, float *off, const double4 *R_ref,
-                                               Ctrl *ctrl, int halt_value)
+                                               double4 *Rw, const double4 *R_ref, Ctrl *ctrl, int halt_value)
 {
     double R[3], rh;
     mol_com<SPM>(P, p, R, rh);
     const double w = res_weight(P, R);
     Rw[t] = make_double4(R[0], R[1], R[2], w);
-    rho[t] = (float)rh;
-    // FP32 site offsets from the centre (minimum image), for FP32 pair displacements
-#pragma unroll
-    for (int k = 0; k < SPM; ++k)
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-            off[(int64_t)t * (3 * SPM) + 3 * k + d] = (float)mi(p[k][d] - R[d], P.box[d], P.half[d]);
     bool finite = true;
 #pragma unroll
     for (int k = 0; k < SPM; ++k) finite = finite && isfinite(p[k][0]) && isfinite(p[k][1]) && isfinite(p[k][2]);
@@ -422,13 +417,14 @@ __device__ __forceinline__ void store_molecule(const DevParams &P, const double 
 // Morton slot; "caller" arrays by the caller's molecule/site index.
 
 // Morton-ordered state of one configuration: positions, packed centre + weight,
-// rho (largest site distance from the centre), velocities and the order itself.
+// velocities and the order itself.  The centres are current after a gather, a reorder, the
+// first drift of a step loop and the centres pass; the fused step kernel refreshes them
+// only when something reads them between list builds (the network's pair pre-pass, the
+// weights of a self-adjusting region), since it derives every centre it needs from x.
 struct StateBufs {
     double *x;        // [3][n_sites]
     double *v;        // [3][n_sites]
     double4 *Rw;      // [n_mol] {Rx, Ry, Rz, w}
-    float *rho;       // [n_mol]
-    float *off;       // [n_mol][sites][3] FP32 site offsets from the centre
     int *perm;        // slot -> caller molecule
     int *key;         // slot -> Morton rank of its cell
 };
@@ -447,8 +443,11 @@ struct StepArgs {
     uint64_t seed, step_abs;
 };
 void launch_kick_drift(hipStream_t s, const DevParams &P, const double *x_in, double *v, const double *f,
-                       double *x_out, double4 *Rw_out, float *rho_out, float *off_out, const double4 *R_ref,
-                       const int *perm, Ctrl *ctrl, int step, const StepArgs &st);
+                       double *x_out, double4 *Rw_out, const double4 *R_ref, const int *perm, Ctrl *ctrl, int step,
+                       const StepArgs &st);
+// centres and weights of the sorted state from its positions (before a reorder, when the
+// step kernels have not kept them)
+void launch_centres(hipStream_t s, const DevParams &P, const double *x, double4 *Rw, Ctrl *ctrl);
 void launch_reset_halt(hipStream_t s, Ctrl *ctrl);
 void launch_publish(hipStream_t s, Ctrl *ctrl, CtrlPub *pub, unsigned seq, bool reset);
 void launch_map_cg(hipStream_t s, const DevParams &P, const double *x, const double *f, double *com, double *fmap);
@@ -473,6 +472,20 @@ void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, cons
 void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const int *stencil, const int *start,
                        const double4 *Rw, double rl2, int *nbr, int *cnt, int cap, unsigned *mcost, Ctrl *ctrl);
 
+// Neighbour halo of every force-kernel tile (64 consecutive slots): hid[tile * hcap + l]
+// lists the slots a tile reads, its own 64 first (l < 64, the tile's slot order), then
+// every other slot of its molecules' rows once; hn[tile] is the count.  lnbr holds each row
+// as local halo indices (uint16), entry k of slot t at t * lcap + (k % 4) * (lcap / 4) + k / 4,
+// so lane q of a molecule's quad finds its entries q, q + 4, ... contiguous.  A halo larger
+// than hcap sets overflow bit 1, max_halo and halt = -1.
+constexpr int kHaloTile = 64;
+void launch_halo_build(hipStream_t s, int n_mol, const int *nbr, const int *cnt, int cap, int hcap, int lcap,
+                       int *hid, int *hn, uint16_t *lnbr, Ctrl *ctrl);
+// LDS bytes of the force kernel's halo staging per halo molecule, and the largest halo
+// capacity that fits a workgroup's LDS
+int halo_stride_bytes(int spm, int pair_precision);
+int halo_capacity_limit(int spm, int pair_precision);
+
 // half list (t < u pairs) + per-entry pair ids; up_off receives n + 1 offsets
 void launch_half_list(hipStream_t s, int n, int *nbr, const int *cnt, int cap, int *cnt_up, int *up_off,
                       int *scratch, int2 *pairs, int64_t pairs_cap, int *pid);
@@ -486,20 +499,20 @@ enum ForceMode : int {
 struct ForceArgs {
     DevParams P;
     const double *x;        // step-n positions (sorted)
-    const double4 *Rw;      // step-n centres + weights
-    const float *rho;
-    const float *off;       // step-n FP32 site offsets
-    const int *nbr, *cnt;
-    int cap;
+    const double4 *Rw;      // step-n weights of a self-adjusting region (w only)
+    const int *cnt;         // row lengths
+    int cap;                // row capacity of the slot-indexed list (pair ids)
+    const int *hid, *hn;    // tile halos (launch_halo_build)
+    int hcap;
+    const uint16_t *lnbr;   // rows as local halo indices
+    int lcap;
     const int *perm, *inv_perm;   // slot -> caller, caller -> slot
     int mode;
     double *f;                    // kModeForce / kModeClose: output forces
     const int *out_perm;          // non-null: write f in caller order via perm
     double *v;                    // kModeStep / kModeClose: velocities (in place)
-    double *x_out;                // kModeStep: step n+1 positions, centres, rho
-    double4 *Rw_out;
-    float *rho_out;
-    float *off_out;
+    double *x_out;                // kModeStep: step n+1 positions
+    double4 *Rw_out;              //   and, if non-null, their centres and weights
     const double4 *R_ref;
     StepArgs st;
     Ctrl *ctrl;
@@ -515,7 +528,8 @@ struct ForceArgs {
     // self-adjusting region: offset from the nearest anchor centre and its length per slot
     const double4 *near;
 };
-// returns the block count; e0/e1 (optional) are recorded at the kernel's start and end
+// returns the block count; e0/e1 (optional) are recorded at the kernel's start and end;
+// the launch takes hcap * halo_stride_bytes() bytes of dynamic LDS
 int launch_forces(hipStream_t s, const ForceArgs &a, int pair_precision, hipEvent_t e0 = nullptr,
                   hipEvent_t e1 = nullptr);
 int force_blocks(int n_mol);

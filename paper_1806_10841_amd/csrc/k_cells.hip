@@ -189,21 +189,17 @@ __global__ __launch_bounds__(kBlock) void k_permute(DevParams P, const int *__re
     const bool site = k < SPM;
     const int64_t from = (int64_t)i * SPM + k, to = (int64_t)t * SPM + k;
     double xs[3] = {0.0, 0.0, 0.0}, vs[3] = {0.0, 0.0, 0.0};
-    float of[3] = {0.0f, 0.0f, 0.0f};
     if (site) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             xs[d] = src.x[d * ns + from];
             if (with_v) vs[d] = src.v[d * ns + from];
-            of[d] = src.off[3 * from + d];
         }
     }
     double4 r = make_double4(0.0, 0.0, 0.0, 0.0);
-    float rh = 0.0f;
     int caller = 0;
     if (k == 0) {
         r = src.Rw[i];
-        rh = src.rho[i];
         caller = src.perm[i];
     }
     if (site) {
@@ -211,13 +207,11 @@ __global__ __launch_bounds__(kBlock) void k_permute(DevParams P, const int *__re
         for (int d = 0; d < 3; ++d) {
             dst.x[d * ns + to] = xs[d];
             if (with_v) dst.v[d * ns + to] = vs[d];
-            dst.off[3 * to + d] = of[d];
         }
     }
     if (k == 0) {
         dst.Rw[t] = r;
         R_ref[t] = r;
-        dst.rho[t] = rh;
         dst.perm[t] = caller;
         inv_perm[caller] = t;
     }
@@ -464,6 +458,122 @@ void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const i
 {
     const int blocks = (G.n_cells + kCmWaves - 1) / kCmWaves;
     k_list_build_cm<<<blocks, kBlock, 0, s>>>(P, G.n_cells, stencil, start, Rw, rl2, nbr, cnt, cap, mcost, ctrl);
+}
+
+namespace {
+
+// Neighbour halo of one force-kernel tile (kHaloTile consecutive slots, one workgroup): every
+// slot its molecules' rows reference is entered once into an LDS hash table (open
+// addressing, linear probing); occupied table positions are then numbered in table order
+// after the tile's own slots, which take halo positions 0..kHaloTile-1.  Which position a slot
+// gets depends on the order of the insertions, but nothing computed from the halo does:
+// a row's entries keep their row order, each reading its own molecule's data.  The rows
+// are rewritten as local halo indices, lane q of a quad owning entries q, q + 4, ...
+constexpr int kHaloHash = 2048;   // table positions (a power of two)
+
+__device__ __forceinline__ int halo_hash(int u) { return (int)(((unsigned)u * 2654435761u) >> (32 - 11)); }
+static_assert(kHaloHash == 1 << 11, "hash width");
+
+__global__ __launch_bounds__(kBlock) void k_halo_build(int n_mol, const int *__restrict__ nbr,
+                                                       const int *__restrict__ cnt, int cap, int hcap, int lcap,
+                                                       int *__restrict__ hid, int *__restrict__ hn,
+                                                       uint16_t *__restrict__ lnbr, Ctrl *ctrl)
+{
+    __shared__ int keys[kHaloHash];
+    __shared__ int vals[kHaloHash];
+    __shared__ int wave_tot[kBlock / 64];
+    __shared__ int lost;
+    const int b = blockIdx.x;
+    const int base = b * kHaloTile;
+    const int n_home = min(kHaloTile, n_mol - base);
+    for (int i = threadIdx.x; i < kHaloHash; i += kBlock) keys[i] = -1;
+    if (threadIdx.x == 0) lost = 0;
+    __syncthreads();
+    const int m = threadIdx.x >> 2, q = threadIdx.x & 3;
+    const int t = base + m;
+    // a row that overflowed holds only cap entries; the list is rebuilt before any use
+    const int c = m < n_home ? min(cnt[t], cap) : 0;
+    const int *row = nbr + (int64_t)t * cap;
+    for (int k = q; k < c; k += 4) {
+        const int u = row[k];
+        if ((unsigned)(u - base) < (unsigned)n_home) continue;   // one of the tile's own slots
+        int h = halo_hash(u), probe = 0;
+        for (; probe < kHaloHash; ++probe) {
+            const int prev = atomicCAS(&keys[h], -1, u);
+            if (prev == -1 || prev == u) break;
+            h = (h + 1) & (kHaloHash - 1);
+        }
+        if (probe == kHaloHash) atomicOr(&lost, 1);
+    }
+    __syncthreads();
+    // number the occupied positions: each thread owns kHaloHash / kBlock consecutive ones
+    constexpr int kPer = kHaloHash / kBlock;
+    int occ = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) occ += keys[threadIdx.x * kPer + j] >= 0;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = occ;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wave_tot[wv] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        before += w < wv ? wave_tot[w] : 0;
+        total += wave_tot[w];
+    }
+    int r = kHaloTile + before + incl - occ;
+    int *h_out = hid + (int64_t)b * hcap;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int pos = threadIdx.x * kPer + j;
+        const int key = keys[pos];
+        if (key >= 0) {
+            vals[pos] = r;
+            if (r < hcap) h_out[r] = key;
+            ++r;
+        }
+    }
+    // the tile's own slots first (a short last tile repeats its last slot: never referenced)
+    if (threadIdx.x < kHaloTile) h_out[threadIdx.x] = base + min((int)threadIdx.x, n_home - 1);
+    const int n_halo = lost ? INT_MAX / 2 : kHaloTile + total;
+    if (threadIdx.x == 0) {
+        hn[b] = min(n_halo, hcap);
+        if (n_halo > hcap) {
+            atomicOr(&ctrl->overflow, 2);
+            atomicMax(&ctrl->max_halo, n_halo);
+            atomicMin(&ctrl->halt, -1);
+        }
+    }
+    __syncthreads();
+    if (n_halo > hcap) return;
+    // rows as local halo indices, lane q's entries contiguous in its quarter of the row
+    uint16_t *lrow = lnbr + (int64_t)t * lcap + q * (lcap / 4);
+    for (int k = q; k < c; k += 4) {
+        const int u = row[k];
+        int local;
+        if ((unsigned)(u - base) < (unsigned)n_home) {
+            local = u - base;
+        } else {
+            int h = halo_hash(u);
+            for (int probe = 0; probe < kHaloHash && keys[h] != u; ++probe) h = (h + 1) & (kHaloHash - 1);
+            local = vals[h];
+        }
+        lrow[k >> 2] = (uint16_t)local;
+    }
+}
+
+}  // namespace
+
+void launch_halo_build(hipStream_t s, int n_mol, const int *nbr, const int *cnt, int cap, int hcap, int lcap,
+                       int *hid, int *hn, uint16_t *lnbr, Ctrl *ctrl)
+{
+    const int tiles = (n_mol + kHaloTile - 1) / kHaloTile;
+    k_halo_build<<<tiles, kBlock, 0, s>>>(n_mol, nbr, cnt, cap, hcap, lcap, hid, hn, lnbr, ctrl);
 }
 
 

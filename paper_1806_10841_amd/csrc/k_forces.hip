@@ -5,31 +5,35 @@
 // fraction; plus the bonded terms, which are not interpolated (Sec. 2.2, last
 // paragraph).  In its step mode the same kernel also finishes velocity Verlet
 // for step n (closing half-kick) and starts step n+1 (opening half-kick, drift,
-// new centre of mass and weight, list-displacement check), so one MD step is one
-// launch.
+// new centre of mass and the list-displacement check), so one MD step is one launch.
 //
-// Work mapping (gfx950, wave64): four lanes per home molecule, 16 molecules per
-// wavefront, consecutive Morton slots (a compact cluster of cells) per workgroup.
-// Lane q takes the molecule's list entries in blocks of kPre (entries kPre q ..,
-// then 4 kPre further on): one vector load fetches the block's neighbour slots and
-// their 32-byte {R, w} gathers are issued back to back before any arithmetic, so
-// each lane keeps kPre independent memory chains in flight (the kernel is bound by
-// gather latency, not by arithmetic).  Every lane accumulates, in FP64, the
-// atom-tile forces on all sites of its molecule and the molecule's total CG force;
-// two butterfly shuffles combine the four lanes; lane q then owns site q.
+// Work mapping (gfx950, wave64): a workgroup is a tile of 64 consecutive Morton slots
+// (a compact cluster of cells), four lanes per home molecule.  The tile's neighbour
+// halo -- every molecule its rows reference, its own molecules first -- is staged in
+// LDS: the raw FP64 site coordinates are copied in with coalesced 16-byte (or 8-byte)
+// loads from the positions of step n, then one thread per halo molecule forms its
+// centre of mass, weight, largest site distance and (for FP32 pairs) FP32 site offsets
+// in place.  The pair loop then reads neighbours from LDS only, through rows of local
+// halo indices: a kernel launch has two dependent rounds of global loads (own data and
+// row heads, then the halo) instead of a gather chain per list entry, and no derived
+// per-molecule array is written to or read from memory.  Lane q takes the molecule's
+// entries q, q + 4, ...; every lane accumulates, in FP64, the atom-tile forces on all
+// sites of its molecule and the molecule's total CG force; two butterfly shuffles
+// combine the four lanes; lane q then owns site q.
 //
-// Full (two-sided) list: no atomics, fixed summation order, bit-reproducible.
-// Pair arithmetic in PT (double or float).  In the float variant an atom-pair
-// displacement is the FP64 centre difference rounded once to FP32 plus the two
-// sites' FP32 offsets from their centres (|offset| < rho_max), which keeps it within
-// a few 1e-7 of the FP64 value without FP64 work per atom pair; the CG cutoff is
-// decided on the FP64 centre distance.  The FP64 variant forms every displacement
-// from FP64 coordinates.
+// Full (two-sided) list: no atomics, fixed summation order, bit-reproducible (the order
+// of the halo in LDS does not enter any sum).  Pair arithmetic in PT (double or float).
+// In the float variant an atom-pair displacement is the FP64 centre difference rounded
+// once to FP32 plus the two sites' FP32 offsets from their centres (|offset| < rho_max),
+// which keeps it within a few 1e-7 of the FP64 value without FP64 work per atom pair;
+// the CG cutoff is decided on the FP64 centre distance.  The FP64 variant forms every
+// displacement from FP64 coordinates.
 //
 // Workgroups are mapped XCD by XCD: the hardware deals workgroup b to XCD b mod 8,
 // so logical block ranges are assigned per XCD and every XCD's L2 serves one
-// contiguous stretch of Morton slots (a compact region of space).  An atom tile is skipped when the centres are farther apart
-// than rc_at + rho_a + rho_b (rho: largest site distance from the centre), which
+// contiguous stretch of Morton slots (a compact region of space), where neighbouring
+// tiles' halos overlap.  An atom tile is skipped when the centres are farther apart
+// than rc_at + rho_a + rho_max (rho: largest site distance from the centre), which
 // no interacting atom pair can be (triangle inequality).
 #include <hip/hip_ext.h>
 
@@ -40,8 +44,8 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kLanes = 4;   // lanes per home molecule
-constexpr int kPre = 2;     // list entries a lane fetches and gathers together
 constexpr int kXcds = 8;
+static_assert(kBlock / kLanes == kHaloTile, "a workgroup is one halo tile");
 
 // logical block of this workgroup: XCD k (= blockIdx mod 8) takes a contiguous range
 __device__ __forceinline__ int xcd_block()
@@ -81,6 +85,30 @@ __device__ __forceinline__ PT table_f(const DevParams &P, double r, Ctrl *ctrl)
     return ((PT(c.w) * t + PT(c.z)) * t + PT(c.y)) * t + PT(c.x);
 }
 
+// LDS layout of the staged halo, per halo molecule l at hs + l * kStride:
+//   FP32 pairs: double4 {R, w} at 0, FP32 site offsets from R (float [SPM][3]) at 32, rho
+//     (float) after them; the raw FP64 site coordinates are copied in first at offset 0 and
+//     overwritten in place once the centre is known.
+//   FP64 pairs: double4 {R, w} at 0, rho at 32, raw FP64 site coordinates ([3][SPM]) at 48,
+//     kept for the atom pairs.
+template <int SPM, typename PT>
+struct Stage {
+    static constexpr bool kF32 = sizeof(PT) == 4;
+    static constexpr int r16(int b) { return (b + 15) / 16 * 16; }
+    static constexpr int kRawOff = kF32 ? 0 : 48;
+    static constexpr int kOffOff = 32;
+    static constexpr int kRhoOff = kF32 ? 32 + 12 * SPM : 32;
+    static constexpr int kStride = kF32 ? r16(24 * SPM > 36 + 12 * SPM ? 24 * SPM : 36 + 12 * SPM) : r16(48 + 24 * SPM);
+    // the raw coordinates of one molecule move in 16-byte pieces when a row of its sites is
+    // 16-byte aligned (an even number of sites), else in 8-byte pieces
+    static constexpr bool kPair2 = SPM % 2 == 0;
+    static constexpr int kPieces = kPair2 ? 3 * SPM / 2 : 3 * SPM;
+};
+
+// Static LDS beside the halo: home sites and velocities, reference centres and the energy
+// partials.
+constexpr int kStaticLds = 2 * (kBlock / kLanes) * kMaxSites * 3 * 8 + (kBlock / kLanes) * 32 + 256;
+
 // At most 128 VGPRs (4 waves per SIMD): 4 lanes x 64k molecules is ~4000 wavefronts,
 // which then fit the 1024 SIMDs in a single round.
 // Variants (VAR): kVarForce, force interpolation, Eq. (1); kVarHam, potential energy
@@ -95,7 +123,9 @@ enum : int { kVarForce = 0, kVarHam = 1, kVarNear = 2 };
 template <int SPM, typename PT, int MODE, bool ENERGY, int VAR>
 __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
 {
+    using St = Stage<SPM, PT>;
     constexpr bool HAM = VAR == kVarHam;
+    extern __shared__ __align__(16) unsigned char hs[];   // the tile's staged halo
     const DevParams &P = a.P;
     const int halt = a.ctrl->halt;
     const int n = P.n_mol;
@@ -107,16 +137,16 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     const bool valid = t < n;
     const int tt = valid ? t : n - 1;
 
-    // home sites of the workgroup's 64 molecules, staged in LDS (read by every lane of a
-    // quad in the atom tiles, the bonds and the drift)
+    // the home sites (FP64) for the bonds and the integration; velocities and reference
+    // centres are only needed after the force loop: staging them here lets their loads
+    // overlap the prologue instead of adding a wait at the end
     __shared__ double sx[kBlock / kLanes][SPM][3];
-    // velocities and reference centres are only needed after the force loop; staging them
-    // here lets their loads overlap the prologue instead of adding a wait at the end
     __shared__ double sv[MODE == kModeForce ? 1 : kBlock / kLanes][SPM][3];
     __shared__ double4 sref[MODE == kModeStep ? kBlock / kLanes : 1];
     const int ml = threadIdx.x / kLanes;
-    // every load of the molecule's own data (and the halt index) is issued before the
-    // first wait, so that the prologue costs one memory round trip
+    // every load that does not depend on another (own site, velocity, reference centre, row
+    // length and the first local row entries, the halo count) is issued before the first
+    // wait: the prologue costs one memory round trip, the halo gather a second
     double lx[3] = {0.0, 0.0, 0.0}, lv[3] = {0.0, 0.0, 0.0};
     if (q < SPM) {
 #pragma unroll
@@ -127,21 +157,34 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     }
     double4 lref = make_double4(0.0, 0.0, 0.0, 0.0);
     if (MODE == kModeStep) lref = a.R_ref[tt];
-    const double4 me = a.Rw[tt];
-    const double rha = (double)a.rho[tt];
-    constexpr bool kOff = sizeof(PT) == 4;   // FP32 displacements from site offsets
-    // (a single-site molecule's offset from its centre is exactly zero: no loads or stores)
-    float hoff[SPM][3] = {};
-    if (kOff && SPM > 1) {
-#pragma unroll
-        for (int i = 0; i < SPM; ++i)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) hoff[i][d] = a.off[(int64_t)tt * (3 * SPM) + 3 * i + d];
-    }
-    const int cnt = valid ? a.cnt[tt] : 0;
+    // (a row longer than cap exists only after an overflow, which stops every launch)
+    const int cnt = valid ? min(a.cnt[tt], a.cap) : 0;
+    const int nq = cnt > q ? (cnt - q + 3) >> 2 : 0;   // this lane's entries k = q + 4 i
+    const uint16_t *lrow = a.lnbr + (int64_t)tt * a.lcap + q * (a.lcap >> 2);
+    uint4 ch = make_uint4(0u, 0u, 0u, 0u);
+    if (nq > 0) ch = *reinterpret_cast<const uint4 *>(lrow);
+    const int hn = min(a.hn[blk], a.hcap);
     // the same decision in every wave: only an earlier launch can set halt below this step
-    // (this one sets it to its own step at the lowest), so no workgroup stops at the barrier
+    // (this one sets it to its own step at the lowest), so no workgroup stops at a barrier
     if (a.check_halt && a.step > halt) return;
+
+    // stage A: the raw site coordinates of the halo (the tile's own molecules first), in
+    // coalesced 16- or 8-byte pieces
+    const int *hid = a.hid + (int64_t)blk * a.hcap;
+    for (int idx = threadIdx.x; idx < hn * St::kPieces; idx += kBlock) {
+        const int l = idx / St::kPieces, pc = idx - l * St::kPieces;
+        const int64_t u = hid[l];
+        double *raw = reinterpret_cast<double *>(hs + l * St::kStride + St::kRawOff);
+        if constexpr (St::kPair2) {
+            constexpr int H = SPM / 2;
+            const int d = pc / H, k2 = 2 * (pc - d * H);
+            *reinterpret_cast<double2 *>(raw + d * SPM + k2) =
+                *reinterpret_cast<const double2 *>(a.x + d * ns + u * SPM + k2);
+        } else {
+            const int d = pc / SPM, k = pc - d * SPM;
+            raw[d * SPM + k] = a.x[d * ns + u * SPM + k];
+        }
+    }
     if (q < SPM) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) sx[ml][q][d] = lx[d];
@@ -151,7 +194,56 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     }
     if (MODE == kModeStep && q == 0) sref[ml] = lref;
     __syncthreads();
-#define XI(i, d) sx[ml][(i)][(d)]
+
+    // stage B: centre of mass, weight, rho (and the FP32 site offsets) of every halo
+    // molecule, with the operation order of mol_com, so that every tile derives the same
+    // bits for a molecule
+    for (int l = threadIdx.x; l < hn; l += kBlock) {
+        unsigned char *mrec = hs + l * St::kStride;
+        const double *raw = reinterpret_cast<const double *>(mrec + St::kRawOff);
+        double p[SPM][3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int k = 0; k < SPM; ++k) p[k][d] = raw[d * SPM + k];
+        double R[3], rh;
+        mol_com<SPM>(P, p, R, rh);
+        if constexpr (St::kF32) {
+            float of[3 * SPM];
+#pragma unroll
+            for (int k = 0; k < SPM; ++k)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) of[3 * k + d] = (float)mi(p[k][d] - R[d], P.box[d], P.half[d]);
+            float *od = reinterpret_cast<float *>(mrec + St::kOffOff);
+#pragma unroll
+            for (int j = 0; j < 3 * SPM; ++j) od[j] = of[j];
+        }
+        *reinterpret_cast<double4 *>(mrec) = make_double4(R[0], R[1], R[2], 0.0);
+        *reinterpret_cast<float *>(mrec + St::kRhoOff) = (float)rh;
+    }
+    // the weights in a pass of their own, so that the FP64 cosine's registers do not add to
+    // those of the centre computation (a self-adjusting region's weights come from the
+    // anchor pass)
+    for (int l = threadIdx.x; l < hn; l += kBlock) {
+        double *rw = reinterpret_cast<double *>(hs + l * St::kStride);
+        const double R[3] = {rw[0], rw[1], rw[2]};
+        rw[3] = P.region == ADRES_REGION_SPHERES ? a.Rw[hid[l]].w : res_weight(P, R);
+    }
+    __syncthreads();
+
+    const unsigned char *mine = hs + ml * St::kStride;
+    const double4 me = *reinterpret_cast<const double4 *>(mine);
+    const double rha = (double)*reinterpret_cast<const float *>(mine + St::kRhoOff);
+    constexpr bool kOff = St::kF32;   // FP32 displacements from site offsets
+    float hoff[SPM][3] = {};
+    if constexpr (kOff) {
+        const float *od = reinterpret_cast<const float *>(mine + St::kOffOff);
+#pragma unroll
+        for (int i = 0; i < SPM; ++i)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) hoff[i][d] = od[3 * i + d];
+    }
+#define XI(i, d) (reinterpret_cast<const double *>(mine + St::kRawOff)[(d) * SPM + (i)])
 
     double acc[SPM][3];
 #pragma unroll
@@ -172,132 +264,101 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
 
     const PT sig2A = (PT)P.sig2_at, epsA = (PT)P.eps_at, rcA2 = (PT)P.rcA2;
     const PT sig2C = (PT)P.sig2_cg, epsC = (PT)P.eps_cg;
-    const int *row = a.nbr + (int64_t)tt * a.cap;
     const bool with_slow = a.slow_scale != 0.0;
 
-    for (int k0 = kPre * q; k0 < cnt; k0 += kPre * kLanes) {
-        int us[kPre];
-        if (kPre == 4) {
-            const int4 id4 = *reinterpret_cast<const int4 *>(row + k0);
-            us[0] = id4.x; us[1] = id4.y; us[kPre > 2 ? 2 : 0] = id4.z; us[kPre > 3 ? 3 : 0] = id4.w;
-        } else {
-            const int2 id2 = *reinterpret_cast<const int2 *>(row + k0);
-            us[0] = id2.x; us[1] = id2.y;
-        }
-        double4 nb[kPre];
-#pragma unroll
-        for (int j = 0; j < kPre; ++j) nb[j] = a.Rw[us[j]];   // padding entries are valid slots
-        // CG sites: the learned CG force of each entry's pair, requested with the centres
-        // (pair ids exist for the row's real entries only)
-        float fp[kPre] = {0.0f, 0.0f};
-        if (SPM == 1 && P.cg_kind >= ADRES_CG_MLP) {
-            const int2 pid2 = *reinterpret_cast<const int2 *>(a.pid + (int64_t)tt * a.cap + k0);
-            fp[0] = a.f_pair[pid2.x];
-            if (k0 + 1 < cnt) fp[1] = a.f_pair[pid2.y];
-        }
-#pragma unroll
-        for (int j = 0; j < kPre; ++j) {
-            if (k0 + j >= cnt) break;
-            const int u = us[j];
-            const double4 o = nb[j];
-            const double ww = HAM ? 0.5 * (me.w + o.w) : me.w * o.w;   // weight of the AT part
-            const double D0 = mi(me.x - o.x, P.box[0], P.half[0]);
-            const double D1 = mi(me.y - o.y, P.box[1], P.half[1]);
-            const double D2 = mi(me.z - o.z, P.box[2], P.half[2]);
-            const double r2c = dist2_exact(D0, D1, D2);
-            if (ww > 0.0) {
-                // no atom pair of the tile can be within the cutoff beyond this centre
-                // distance (every site lies within rho_max of its centre, a checked invariant)
-                const double bound = P.rc_at + rha + P.rho_max + 1e-6;
-                if (r2c < bound * bound) {
-                    const PT pww = (PT)ww;
-                    if constexpr (kOff) {
-                        float no[3 * SPM];
-                        if constexpr (SPM == 4) {   // 48 bytes, 16-byte aligned: three vector loads
-                            const float4 *q4 = reinterpret_cast<const float4 *>(a.off + (int64_t)u * 12);
-                            const float4 o0 = q4[0], o1 = q4[1], o2 = q4[2];
-                            no[0] = o0.x; no[1] = o0.y; no[2] = o0.z; no[3] = o0.w;
-                            no[4] = o1.x; no[5] = o1.y; no[6] = o1.z; no[7] = o1.w;
-                            no[8] = o2.x; no[9] = o2.y; no[10] = o2.z; no[11] = o2.w;
-                        } else {
-#pragma unroll
-                            for (int j2 = 0; j2 < 3 * SPM; ++j2)
-                                no[j2] = SPM > 1 ? a.off[(int64_t)u * (3 * SPM) + j2] : 0.0f;
-                        }
-                        // D + (off_i - off_jj): the same bits with opposite sign from the
-                        // other molecule's side, so pair forces cancel exactly (Newton's third law)
-                        const float Df0 = (float)D0, Df1 = (float)D1, Df2 = (float)D2;
-#pragma unroll
-                        for (int i = 0; i < SPM; ++i) {
-                            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-                            for (int jj = 0; jj < SPM; ++jj) {
-                                const float dx = Df0 + (hoff[i][0] - no[3 * jj]);
-                                const float dy = Df1 + (hoff[i][1] - no[3 * jj + 1]);
-                                const float dz = Df2 + (hoff[i][2] - no[3 * jj + 2]);
-                                const float r2 = (dx * dx + dy * dy) + dz * dz;
-                                if (r2 < (float)rcA2) {
-                                    PT uu = PT(0);
-                                    const PT c = pww * wca_f_over_r<PT>((PT)r2, sig2A, epsA, uu, ENERGY || hy_home);
-                                    s0 += (double)(c * dx);
-                                    s1 += (double)(c * dy);
-                                    s2 += (double)(c * dz);
-                                    if (ENERGY) uat += 0.5 * (HAM ? me.w : ww) * (double)uu;
-                                    if (HAM) vat += 0.5 * (double)uu;
-                                }
-                            }
-                            acc[i][0] += s0; acc[i][1] += s1; acc[i][2] += s2;
-                        }
-                    } else {
+    for (int i = 0; i < nq; ++i) {
+        const int j8 = i & 7;
+        if (j8 == 0 && i > 0) ch = *reinterpret_cast<const uint4 *>(lrow + i);   // rows over 32 entries
+        const unsigned wd = j8 < 2 ? ch.x : (j8 < 4 ? ch.y : (j8 < 6 ? ch.z : ch.w));
+        const int l = (int)((wd >> (16 * (j8 & 1))) & 0xffffu);
+        const int k = q + 4 * i;   // the entry's position in the row
+        const unsigned char *nrec = hs + l * St::kStride;
+        const double4 o = *reinterpret_cast<const double4 *>(nrec);
+        const double ww = HAM ? 0.5 * (me.w + o.w) : me.w * o.w;   // weight of the AT part
+        const double D0 = mi(me.x - o.x, P.box[0], P.half[0]);
+        const double D1 = mi(me.y - o.y, P.box[1], P.half[1]);
+        const double D2 = mi(me.z - o.z, P.box[2], P.half[2]);
+        const double r2c = dist2_exact(D0, D1, D2);
+        if (ww > 0.0) {
+            // no atom pair of the tile can be within the cutoff beyond this centre
+            // distance (every site lies within rho_max of its centre, a checked invariant)
+            const double bound = P.rc_at + rha + P.rho_max + 1e-6;
+            if (r2c < bound * bound) {
+                const PT pww = (PT)ww;
+                if constexpr (kOff) {
+                    const float *od = reinterpret_cast<const float *>(nrec + St::kOffOff);
+                    // D + (off_i - off_jj): the same bits with opposite sign from the
+                    // other molecule's side, so pair forces cancel exactly (Newton's third law)
+                    const float Df0 = (float)D0, Df1 = (float)D1, Df2 = (float)D2;
 #pragma unroll 1
                     for (int jj = 0; jj < SPM; ++jj) {
-                        const double xj0 = a.x[(int64_t)u * SPM + jj];
-                        const double xj1 = a.x[ns + (int64_t)u * SPM + jj];
-                        const double xj2 = a.x[2 * ns + (int64_t)u * SPM + jj];
+                        const float n0 = od[3 * jj], n1 = od[3 * jj + 1], n2 = od[3 * jj + 2];
 #pragma unroll
-                        for (int i = 0; i < SPM; ++i) {
-                            const PT dx = (PT)mi(XI(i, 0) - xj0, P.box[0], P.half[0]);
-                            const PT dy = (PT)mi(XI(i, 1) - xj1, P.box[1], P.half[1]);
-                            const PT dz = (PT)mi(XI(i, 2) - xj2, P.box[2], P.half[2]);
-                            const PT r2 = (dx * dx + dy * dy) + dz * dz;
-                            if (r2 < rcA2) {
+                        for (int ii = 0; ii < SPM; ++ii) {
+                            const float dx = Df0 + (hoff[ii][0] - n0);
+                            const float dy = Df1 + (hoff[ii][1] - n1);
+                            const float dz = Df2 + (hoff[ii][2] - n2);
+                            const float r2 = (dx * dx + dy * dy) + dz * dz;
+                            if (r2 < (float)rcA2) {
                                 PT uu = PT(0);
-                                const PT c = pww * wca_f_over_r<PT>(r2, sig2A, epsA, uu, ENERGY || hy_home);
-                                acc[i][0] += (double)(c * dx);
-                                acc[i][1] += (double)(c * dy);
-                                acc[i][2] += (double)(c * dz);
+                                const PT c = pww * wca_f_over_r<PT>((PT)r2, sig2A, epsA, uu, ENERGY || hy_home);
+                                acc[ii][0] += (double)(c * dx);
+                                acc[ii][1] += (double)(c * dy);
+                                acc[ii][2] += (double)(c * dz);
                                 if (ENERGY) uat += 0.5 * (HAM ? me.w : ww) * (double)uu;
                                 if (HAM) vat += 0.5 * (double)uu;
                             }
                         }
                     }
+                } else {
+                    const double *xj = reinterpret_cast<const double *>(nrec + St::kRawOff);
+#pragma unroll 1
+                    for (int jj = 0; jj < SPM; ++jj) {
+                        const double xj0 = xj[jj], xj1 = xj[SPM + jj], xj2 = xj[2 * SPM + jj];
+#pragma unroll
+                        for (int ii = 0; ii < SPM; ++ii) {
+                            const PT dx = (PT)mi(XI(ii, 0) - xj0, P.box[0], P.half[0]);
+                            const PT dy = (PT)mi(XI(ii, 1) - xj1, P.box[1], P.half[1]);
+                            const PT dz = (PT)mi(XI(ii, 2) - xj2, P.box[2], P.half[2]);
+                            const PT r2 = (dx * dx + dy * dy) + dz * dz;
+                            if (r2 < rcA2) {
+                                PT uu = PT(0);
+                                const PT c = pww * wca_f_over_r<PT>(r2, sig2A, epsA, uu, ENERGY || hy_home);
+                                acc[ii][0] += (double)(c * dx);
+                                acc[ii][1] += (double)(c * dy);
+                                acc[ii][2] += (double)(c * dz);
+                                if (ENERGY) uat += 0.5 * (HAM ? me.w : ww) * (double)uu;
+                                if (HAM) vat += 0.5 * (double)uu;
+                            }
+                        }
                     }
                 }
             }
-            if (with_slow && ww < 1.0 && r2c < P.rcC2) {
-                PT uu = PT(0);
-                PT fr;
-                if (P.cg_kind == ADRES_CG_WCA) {
-                    fr = wca_f_over_r<PT>((PT)r2c, sig2C, epsC, uu, ENERGY || hy_home);
-                } else if (P.cg_kind >= ADRES_CG_MLP) {
-                    // the same bits from both sides of the pair (same r2c, same network value)
-                    const float fv = SPM == 1 ? fp[j] : a.f_pair[a.pid[(int64_t)tt * a.cap + k0 + j]];
-                    fr = (PT)fv * (PT)__builtin_amdgcn_rsqf((float)r2c);
-                } else {
-                    // r and 1/r from one refined reciprocal square root: no FP64 square
-                    // root or division on the table path
-                    const double ir = rsqrt_refined(r2c);
-                    fr = table_f<PT>(P, r2c * ir, a.ctrl) * (PT)ir;
-                }
-                const PT sc = (PT)(1.0 - ww) * fr;
-                cg0 += (double)(sc * (PT)D0);
-                cg1 += (double)(sc * (PT)D1);
-                cg2 += (double)(sc * (PT)D2);
-                if (ENERGY) ucg += 0.5 * (HAM ? 1.0 - me.w : 1.0 - ww) * (double)uu;
-                if (HAM) vcg += 0.5 * (double)uu;
+        }
+        if (with_slow && ww < 1.0 && r2c < P.rcC2) {
+            PT uu = PT(0);
+            PT fr;
+            if (P.cg_kind == ADRES_CG_WCA) {
+                fr = wca_f_over_r<PT>((PT)r2c, sig2C, epsC, uu, ENERGY || hy_home);
+            } else if (P.cg_kind >= ADRES_CG_MLP) {
+                // the same bits from both sides of the pair (same r2c, same network value)
+                const float fv = a.f_pair[a.pid[(int64_t)tt * a.cap + k]];
+                fr = (PT)fv * (PT)__builtin_amdgcn_rsqf((float)r2c);
+            } else {
+                // r and 1/r from one refined reciprocal square root: no FP64 square
+                // root or division on the table path
+                const double ir = rsqrt_refined(r2c);
+                fr = table_f<PT>(P, r2c * ir, a.ctrl) * (PT)ir;
             }
+            const PT sc = (PT)(1.0 - ww) * fr;
+            cg0 += (double)(sc * (PT)D0);
+            cg1 += (double)(sc * (PT)D1);
+            cg2 += (double)(sc * (PT)D2);
+            if (ENERGY) ucg += 0.5 * (HAM ? 1.0 - me.w : 1.0 - ww) * (double)uu;
+            if (HAM) vcg += 0.5 * (double)uu;
         }
     }
+#undef XI
 
     // combine the four lanes' partial sums (every lane ends with the same bits)
     static_assert(kLanes == 4, "the quad exchanges below assume four lanes per molecule");
@@ -312,6 +373,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     cg0 = quad_sum(cg0);
     cg1 = quad_sum(cg1);
     cg2 = quad_sum(cg2);
+
+#define XS(k, d) sx[ml][(k)][(d)]
 
     double ucorr = 0.0;   // the correction field's potential (energy only)
 
@@ -337,7 +400,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                 F[2] += dv * gw[2];
             }
             mfq = mf;
-            xq[0] = XI(i, 0); xq[1] = XI(i, 1); xq[2] = XI(i, 2);
+            xq[0] = XS(i, 0); xq[1] = XS(i, 1); xq[2] = XS(i, 2);
             mq = P.mass[i];
             iq = P.inv_2m[i];
         }
@@ -367,9 +430,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
 #pragma unroll
             for (int k = 0; k < SPM; ++k) {
                 if (k == q) continue;
-                const double d0 = mi(xq[0] - XI(k, 0), P.box[0], P.half[0]);
-                const double d1 = mi(xq[1] - XI(k, 1), P.box[1], P.half[1]);
-                const double d2 = mi(xq[2] - XI(k, 2), P.box[2], P.half[2]);
+                const double d0 = mi(xq[0] - XS(k, 0), P.box[0], P.half[0]);
+                const double d1 = mi(xq[1] - XS(k, 1), P.box[1], P.half[1]);
+                const double d2 = mi(xq[2] - XS(k, 2), P.box[2], P.half[2]);
                 const double r2b = (d0 * d0 + d1 * d1) + d2 * d2;
                 const double ir = rsqrt_refined(r2b);
                 const double r = r2b * ir;
@@ -425,9 +488,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
             a.v[site] = v[0]; a.v[ns + site] = v[1]; a.v[2 * ns + site] = v[2];
             a.x_out[site] = xn[0]; a.x_out[ns + site] = xn[1]; a.x_out[2 * ns + site] = xn[2];
         }
-        // new centre, weight, rho and offsets, spread over the quad: lane d < 3 forms
-        // coordinate d of the centre (the operation order of mol_com), lane q < SPM its
-        // own site's offset and distance
+        // new centre (for the displacement check, and stored when something reads it before
+        // the next list build) and rho (for the stretch check), spread over the quad: lane
+        // d < 3 forms coordinate d of the centre (the operation order of mol_com), lane
+        // q < SPM its own site's distance
         double col[SPM];
         const int dd = q < 3 ? q : 0;
         {
@@ -451,10 +515,6 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
             const double o1 = mi(xn[1] - R1, P.box[1], P.half[1]);
             const double o2 = mi(xn[2] - R2, P.box[2], P.half[2]);
             r2 = dist2_exact(o0, o1, o2);
-            if (SPM > 1) {
-                float *of = a.off_out + (int64_t)t * (3 * SPM) + 3 * q;
-                of[0] = (float)o0; of[1] = (float)o1; of[2] = (float)o2;
-            }
         }
         double m2 = r2;
         {
@@ -466,8 +526,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
         if (valid && q == 0) {
             const double R[3] = {R0, R1, R2};
             const double rh = sqrt(m2);
-            a.Rw_out[t] = make_double4(R0, R1, R2, res_weight(P, R));
-            a.rho_out[t] = (float)rh;
+            if (a.Rw_out) a.Rw_out[t] = make_double4(R0, R1, R2, res_weight(P, R));
             if (!(isfinite(R0) && isfinite(R1) && isfinite(R2))) atomicOr(&a.ctrl->err, kErrNonFinite);
             if (SPM > 1 && rh > P.rho_max) atomicOr(&a.ctrl->err, kErrStretch);
             const double4 rr = sref[ml];
@@ -478,7 +537,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
         }
     }
 
-#undef XI
+#undef XS
     if (ENERGY) {
         // block reduction in a fixed order: wavefront butterflies, then 4 waves in LDS
         __shared__ double red[kBlock / 64][4];
@@ -520,25 +579,26 @@ __global__ __launch_bounds__(256) void k_energy_reduce(const double *__restrict_
 // Launch; with events, hipExtLaunchKernelGGL records them at the kernel's own start
 // and end (the duration excludes launch gaps, as a profiler's kernel trace does).
 template <typename K>
-void launch_k(K kernel, hipStream_t s, const ForceArgs &a, int blocks, hipEvent_t e0, hipEvent_t e1)
+void launch_k(K kernel, hipStream_t s, const ForceArgs &a, int blocks, size_t lds, hipEvent_t e0, hipEvent_t e1)
 {
     if (e0)
-        hipExtLaunchKernelGGL(kernel, dim3(blocks), dim3(kBlock), 0, s, e0, e1, 0, a);
+        hipExtLaunchKernelGGL(kernel, dim3(blocks), dim3(kBlock), lds, s, e0, e1, 0, a);
     else
-        kernel<<<blocks, kBlock, 0, s>>>(a);
+        kernel<<<blocks, kBlock, lds, s>>>(a);
 }
 
 template <int SPM, typename PT, int VAR>
 void dispatch_mode(hipStream_t s, const ForceArgs &a, int blocks, hipEvent_t e0, hipEvent_t e1)
 {
+    const size_t lds = (size_t)a.hcap * Stage<SPM, PT>::kStride;
     switch (a.mode) {
-    case kModeStep: launch_k(k_forces<SPM, PT, kModeStep, false, VAR>, s, a, blocks, e0, e1); break;
-    case kModeClose: launch_k(k_forces<SPM, PT, kModeClose, false, VAR>, s, a, blocks, e0, e1); break;
+    case kModeStep: launch_k(k_forces<SPM, PT, kModeStep, false, VAR>, s, a, blocks, lds, e0, e1); break;
+    case kModeClose: launch_k(k_forces<SPM, PT, kModeClose, false, VAR>, s, a, blocks, lds, e0, e1); break;
     default:
         if (a.epart)
-            launch_k(k_forces<SPM, PT, kModeForce, true, VAR>, s, a, blocks, e0, e1);
+            launch_k(k_forces<SPM, PT, kModeForce, true, VAR>, s, a, blocks, lds, e0, e1);
         else
-            launch_k(k_forces<SPM, PT, kModeForce, false, VAR>, s, a, blocks, e0, e1);
+            launch_k(k_forces<SPM, PT, kModeForce, false, VAR>, s, a, blocks, lds, e0, e1);
     }
 }
 
@@ -567,6 +627,30 @@ void dispatch_spm(hipStream_t s, const ForceArgs &a, int blocks, hipEvent_t e0, 
 }  // namespace
 
 int force_blocks(int n_mol) { return (int)(((int64_t)n_mol * kLanes + kBlock - 1) / kBlock); }
+
+namespace {
+template <typename PT>
+int stride_of(int spm)
+{
+    switch (spm) {
+    case 1: return Stage<1, PT>::kStride;
+    case 2: return Stage<2, PT>::kStride;
+    case 3: return Stage<3, PT>::kStride;
+    default: return Stage<4, PT>::kStride;
+    }
+}
+}  // namespace
+
+int halo_stride_bytes(int spm, int pair_precision)
+{
+    return pair_precision == 32 ? stride_of<float>(spm) : stride_of<double>(spm);
+}
+
+// a workgroup's LDS is 64 KiB: the static part and the staged halo share it
+int halo_capacity_limit(int spm, int pair_precision)
+{
+    return (65536 - kStaticLds) / halo_stride_bytes(spm, pair_precision);
+}
 
 int launch_forces(hipStream_t s, const ForceArgs &a, int pair_precision, hipEvent_t e0, hipEvent_t e1)
 {

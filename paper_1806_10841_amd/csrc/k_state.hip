@@ -70,7 +70,24 @@ __global__ __launch_bounds__(kBlock) void k_gather(DevParams P, const double *__
         load_sites<SPM>(vc, P.n_sites, a, q);
         store_sites<SPM>(S.v, P.n_sites, t, q);
     }
-    store_molecule<SPM>(P, p, t, S.Rw, S.rho, S.off, R_ref, ctrl, 0);
+    store_molecule<SPM>(P, p, t, S.Rw, R_ref, ctrl, 0);
+}
+
+// Centres and weights of the sorted state from its positions (no checks: the step kernel
+// that wrote the positions made them).
+template <int SPM>
+__global__ __launch_bounds__(kBlock) void k_centres(DevParams P, const double *__restrict__ x,
+                                                    double4 *__restrict__ Rw)
+{
+    int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= P.n_mol) return;
+    double p[SPM][3];
+    load_sites<SPM>(x, P.n_sites, t, p);
+    double R[3], rh;
+    mol_com<SPM>(P, p, R, rh);
+    // the weight of a self-adjusting region is written by its own pass; keep it
+    const double w = P.region == ADRES_REGION_SPHERES ? Rw[t].w : res_weight(P, R);
+    Rw[t] = make_double4(R[0], R[1], R[2], w);
 }
 
 template <int SPM>
@@ -104,7 +121,6 @@ template <int SPM>
 __global__ __launch_bounds__(kBlock) void k_kick_drift(DevParams P, const double *__restrict__ x_in,
                                                        double *__restrict__ v, const double *__restrict__ f,
                                                        double *__restrict__ x_out, double4 *__restrict__ Rw_out,
-                                                       float *__restrict__ rho_out, float *__restrict__ off_out,
                                                        const double4 *__restrict__ R_ref,
                                                        const int *__restrict__ perm, Ctrl *ctrl, int step,
                                                        StepArgs st)
@@ -128,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(DevParams P, const double
             p[k][d] = xx[d];
         }
     }
-    store_molecule<SPM>(P, p, t, Rw_out, rho_out, off_out, R_ref, ctrl, step);
+    store_molecule<SPM>(P, p, t, Rw_out, R_ref, ctrl, step);
 }
 
 // Centre of mass and summed force of every molecule (caller order): the mapping of
@@ -414,6 +430,7 @@ __global__ void k_publish(Ctrl *__restrict__ ctrl, CtrlPub *pub, unsigned seq, i
     p->err = ctrl->err;
     p->overflow = ctrl->overflow;
     p->max_count = ctrl->max_count;
+    p->max_halo = ctrl->max_halo;
     __threadfence_system();
     p->seq = seq;
     __threadfence_system();
@@ -421,6 +438,7 @@ __global__ void k_publish(Ctrl *__restrict__ ctrl, CtrlPub *pub, unsigned seq, i
         ctrl->halt = INT_MAX;
         ctrl->overflow = 0;
         ctrl->max_count = 0;
+        ctrl->max_halo = 0;
     }
 }
 
@@ -432,6 +450,7 @@ __global__ void k_reset_halt(Ctrl *ctrl)
         ctrl->halt = INT_MAX;
         ctrl->overflow = 0;
         ctrl->max_count = 0;
+        ctrl->max_halo = 0;
     }
 }
 
@@ -466,11 +485,16 @@ void launch_scatter_out(hipStream_t s, const DevParams &P, const int *perm, cons
 }
 
 void launch_kick_drift(hipStream_t s, const DevParams &P, const double *x_in, double *v, const double *f,
-                       double *x_out, double4 *Rw_out, float *rho_out, float *off_out, const double4 *R_ref,
+                       double *x_out, double4 *Rw_out, const double4 *R_ref,
                        const int *perm, Ctrl *ctrl, int step, const StepArgs &st)
 {
     ADRES_SPM_DISPATCH(P.spm, (k_kick_drift<S_><<<blocks_for(P.n_mol), kBlock, 0, s>>>(
-                                  P, x_in, v, f, x_out, Rw_out, rho_out, off_out, R_ref, perm, ctrl, step, st)));
+                                  P, x_in, v, f, x_out, Rw_out, R_ref, perm, ctrl, step, st)));
+}
+
+void launch_centres(hipStream_t s, const DevParams &P, const double *x, double4 *Rw, Ctrl *)
+{
+    ADRES_SPM_DISPATCH(P.spm, (k_centres<S_><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, x, Rw)));
 }
 
 void launch_reset_halt(hipStream_t s, Ctrl *ctrl) { k_reset_halt<<<1, 64, 0, s>>>(ctrl); }
