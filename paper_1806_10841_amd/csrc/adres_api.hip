@@ -492,6 +492,11 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     P.n_sites = (int64_t)q.n_mol * q.sites_per_mol;
     P.M = 0.0;
     for (int k = 0; k < P.spm; ++k) P.M = P.M + q.site_mass[k];
+    {
+        int ex = 0;
+        P.M_pow2 = std::frexp(P.M, &ex) == 0.5 ? 1 : 0;
+        P.inv_M = 1.0 / P.M;
+    }
     for (int k = 0; k < kMaxSites; ++k) {
         P.mass[k] = k < P.spm ? q.site_mass[k] : 1.0;
         P.mfrac[k] = k < P.spm ? q.site_mass[k] / P.M : 0.0;
@@ -502,6 +507,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     for (int d = 0; d < 3; ++d) {
         P.box[d] = q.box[d];
         P.half[d] = 0.5 * q.box[d];
+        P.inv_box[d] = 1.0 / q.box[d];
         P.center[d] = q.center[d];
         if (q.box[d] < 2.0 * c->r_list) {
             delete c;
@@ -594,7 +600,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     c->epart_blocks = force_blocks(n);
     ok = ok && dalloc(&c->epart, 4 * (size_t)c->epart_blocks) == hipSuccess;
     ok = ok && dalloc(&c->hn, (size_t)c->epart_blocks) == hipSuccess;
-    ok = ok && alloc_halo(c, std::min(256, halo_capacity_limit(q.sites_per_mol, q.pair_precision))) == ADRES_OK;
+    ok = ok && alloc_halo(c, std::min(320, halo_capacity_limit(q.sites_per_mol, q.pair_precision))) == ADRES_OK;
     ok = ok && dalloc(&c->tile_order, (size_t)c->epart_blocks) == hipSuccess &&
          dalloc(&c->mcost, ((size_t)n + 15) / 16 * 16) == hipSuccess &&   // whole 16-entry runs
          dalloc(&c->stencil, (size_t)G.n_cells * 27) == hipSuccess;

@@ -44,8 +44,10 @@ struct CtrlPub {
 struct DevParams {
     int n_mol, spm;
     int64_t n_sites;
-    double box[3], half[3];
+    double box[3], half[3], inv_box[3];
     double mass[kMaxSites], mfrac[kMaxSites], inv_2m[kMaxSites], M;
+    double inv_M;    // 1 / M, exact when M is a power of two (then M_pow2 = 1)
+    int M_pow2;
     int region;
     double center[3], d_at, d_hy, d_end;
     double eps_at, sig2_at, rcA2, rc_at;
@@ -85,11 +87,14 @@ struct Grid {
 // The helpers below fix the floating-point operation order (no contraction) so
 // that centres of mass, weights and list distances are reproducible bit for bit.
 
-__device__ __forceinline__ double mi(double d, double L, double half)
+// Minimum image of a coordinate difference |d| < 1.5 L as d - L rint(d / L) (one multiply,
+// one rounding, one fused multiply-add): the single rounding of d -+ L, i.e. the value of
+// adding or subtracting L when |d| > L / 2 and d itself otherwise, except within rounding of
+// |d| = L / 2, where both images are equally near (no cutoff reaches that far: the box is
+// at least twice the list radius).
+__device__ __forceinline__ double mi(double d, double L, double invL)
 {
-    if (d > half) d -= L;
-    else if (d < -half) d += L;
-    return d;
+    return fma(-L, rint(d * invL), d);
 }
 
 __device__ __forceinline__ double fold(double r, double L)
@@ -117,8 +122,9 @@ __device__ __forceinline__ double com_dim(const DevParams &P, const double (&c)[
     if constexpr (SPM == 1) return fold(x0 + 0.0, P.box[d]);   // x0 + 0 / M without the division
     double acc = 0.0;
 #pragma unroll
-    for (int k = 1; k < SPM; ++k) acc = acc + P.mass[k] * mi(c[k] - x0, P.box[d], P.half[d]);
-    return fold(x0 + acc / P.M, P.box[d]);
+    for (int k = 1; k < SPM; ++k) acc = acc + P.mass[k] * mi(c[k] - x0, P.box[d], P.inv_box[d]);
+    // a product with 1 / M is the quotient itself when M is a power of two
+    return fold(x0 + (P.M_pow2 ? acc * P.inv_M : acc / P.M), P.box[d]);
 }
 
 template <int SPM>
@@ -135,9 +141,9 @@ __device__ __forceinline__ void mol_com(const DevParams &P, const double (&p)[SP
     double rmax2 = 0.0;
 #pragma unroll
     for (int k = 0; k < SPM; ++k) {
-        double q0 = mi(p[k][0] - R[0], P.box[0], P.half[0]);
-        double q1 = mi(p[k][1] - R[1], P.box[1], P.half[1]);
-        double q2 = mi(p[k][2] - R[2], P.box[2], P.half[2]);
+        double q0 = mi(p[k][0] - R[0], P.box[0], P.inv_box[0]);
+        double q1 = mi(p[k][1] - R[1], P.box[1], P.inv_box[1]);
+        double q2 = mi(p[k][2] - R[2], P.box[2], P.inv_box[2]);
         double r2 = dist2_exact(q0, q1, q2);
         rmax2 = r2 > rmax2 ? r2 : rmax2;
     }
@@ -152,14 +158,14 @@ __device__ __forceinline__ void weight_gradient(const DevParams &P, const double
 {
     g[0] = g[1] = g[2] = 0.0;
     if (P.region != ADRES_REGION_SLAB_X && P.region != ADRES_REGION_SPHERE) return;
-    double q0 = mi(R.x - P.center[0], P.box[0], P.half[0]);
+    double q0 = mi(R.x - P.center[0], P.box[0], P.inv_box[0]);
     double d;
     double q1 = 0.0, q2 = 0.0;
     if (P.region == ADRES_REGION_SLAB_X) {
         d = fabs(q0);
     } else {
-        q1 = mi(R.y - P.center[1], P.box[1], P.half[1]);
-        q2 = mi(R.z - P.center[2], P.box[2], P.half[2]);
+        q1 = mi(R.y - P.center[1], P.box[1], P.inv_box[1]);
+        q2 = mi(R.z - P.center[2], P.box[2], P.inv_box[2]);
         d = sqrt(dist2_exact(q0, q1, q2));
     }
     if (d <= P.d_at || d >= P.d_end) return;
@@ -178,13 +184,13 @@ __device__ __forceinline__ void weight_gradient(const DevParams &P, const double
 __device__ __forceinline__ double res_distance(const DevParams &P, const double R[3], double q[3])
 {
 #pragma clang fp contract(off)
-    q[0] = mi(R[0] - P.center[0], P.box[0], P.half[0]);
+    q[0] = mi(R[0] - P.center[0], P.box[0], P.inv_box[0]);
     if (P.region == ADRES_REGION_SLAB_X) {
         q[1] = q[2] = 0.0;
         return fabs(q[0]);
     }
-    q[1] = mi(R[1] - P.center[1], P.box[1], P.half[1]);
-    q[2] = mi(R[2] - P.center[2], P.box[2], P.half[2]);
+    q[1] = mi(R[1] - P.center[1], P.box[1], P.inv_box[1]);
+    q[2] = mi(R[2] - P.center[2], P.box[2], P.inv_box[2]);
     return sqrt(dist2_exact(q[0], q[1], q[2]));
 }
 
@@ -405,9 +411,9 @@ __device__ __forceinline__ void store_molecule(const DevParams &P, const double 
     if (SPM > 1 && rh > P.rho_max) atomicOr(&ctrl->err, kErrStretch);
     if (R_ref) {
         const double4 r0 = R_ref[t];
-        double q0 = mi(R[0] - r0.x, P.box[0], P.half[0]);
-        double q1 = mi(R[1] - r0.y, P.box[1], P.half[1]);
-        double q2 = mi(R[2] - r0.z, P.box[2], P.half[2]);
+        double q0 = mi(R[0] - r0.x, P.box[0], P.inv_box[0]);
+        double q1 = mi(R[1] - r0.y, P.box[1], P.inv_box[1]);
+        double q2 = mi(R[2] - r0.z, P.box[2], P.inv_box[2]);
         if (dist2_exact(q0, q1, q2) > P.half_skin2) atomicMin(&ctrl->halt, halt_value);
     }
 }

@@ -309,9 +309,9 @@ __global__ __launch_bounds__(kBlock) void k_list_build_cm(DevParams P, int n_cel
                 for (int u = 0; u < 2; ++u) {
                     bool hit = false;
                     if (vk[u] && slot[u] != t) {
-                        const double dx = mi(o[u].x - mx, P.box[0], P.half[0]);
-                        const double dy = mi(o[u].y - my, P.box[1], P.half[1]);
-                        const double dz = mi(o[u].z - mz, P.box[2], P.half[2]);
+                        const double dx = mi(o[u].x - mx, P.box[0], P.inv_box[0]);
+                        const double dy = mi(o[u].y - my, P.box[1], P.inv_box[1]);
+                        const double dz = mi(o[u].z - mz, P.box[2], P.inv_box[2]);
                         hit = dist2_exact(dx, dy, dz) < rl2;
                     }
                     const uint64_t m = __ballot(hit);
@@ -464,11 +464,11 @@ namespace {
 
 // Neighbour halo of one force-kernel tile (kHaloTile consecutive slots, one workgroup): every
 // slot its molecules' rows reference is entered once into an LDS hash table (open
-// addressing, linear probing); occupied table positions are then numbered in table order
-// after the tile's own slots, which take halo positions 0..kHaloTile-1.  Which position a slot
-// gets depends on the order of the insertions, but nothing computed from the halo does:
-// a row's entries keep their row order, each reading its own molecule's data.  The rows
-// are rewritten as local halo indices, lane q of a quad owning entries q, q + 4, ...
+// addressing, linear probing); the distinct slots are then ranked by value and numbered in
+// slot order after the tile's own slots, which take halo positions 0..kHaloTile-1 (slot
+// order keeps the runs of a cell's molecules together, so that neighbouring lanes of the
+// force kernel's staging read neighbouring addresses).  The rows are rewritten as local
+// halo indices, lane q of a quad owning entries q, q + 4, ...
 constexpr int kHaloHash = 2048;   // table positions (a power of two)
 
 __device__ __forceinline__ int halo_hash(int u) { return (int)(((unsigned)u * 2654435761u) >> (32 - 11)); }
@@ -481,6 +481,7 @@ __global__ __launch_bounds__(kBlock) void k_halo_build(int n_mol, const int *__r
 {
     __shared__ int keys[kHaloHash];
     __shared__ int vals[kHaloHash];
+    __shared__ int dkey[kHaloHash], dpos[kHaloHash];   // the distinct slots, compacted
     __shared__ int wave_tot[kBlock / 64];
     __shared__ int lost;
     const int b = blockIdx.x;
@@ -526,17 +527,27 @@ __global__ __launch_bounds__(kBlock) void k_halo_build(int n_mol, const int *__r
         before += w < wv ? wave_tot[w] : 0;
         total += wave_tot[w];
     }
-    int r = kHaloTile + before + incl - occ;
-    int *h_out = hid + (int64_t)b * hcap;
+    int r = before + incl - occ;
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int pos = threadIdx.x * kPer + j;
         const int key = keys[pos];
         if (key >= 0) {
-            vals[pos] = r;
-            if (r < hcap) h_out[r] = key;
+            dkey[r] = key;
+            dpos[r] = pos;
             ++r;
         }
+    }
+    __syncthreads();
+    // rank of each distinct slot among them (the slots are distinct: ranks are a permutation)
+    int *h_out = hid + (int64_t)b * hcap;
+    for (int j = threadIdx.x; j < total; j += kBlock) {
+        const int key = dkey[j];
+        int rank = 0;
+        for (int i = 0; i < total; ++i) rank += dkey[i] < key;
+        const int lpos = kHaloTile + rank;
+        vals[dpos[j]] = lpos;
+        if (lpos < hcap) h_out[lpos] = key;
     }
     // the tile's own slots first (a short last tile repeats its last slot: never referenced)
     if (threadIdx.x < kHaloTile) h_out[threadIdx.x] = base + min((int)threadIdx.x, n_home - 1);

@@ -86,28 +86,111 @@ __device__ __forceinline__ PT table_f(const DevParams &P, double r, Ctrl *ctrl)
 }
 
 // LDS layout of the staged halo, per halo molecule l at hs + l * kStride:
-//   FP32 pairs: double4 {R, w} at 0, FP32 site offsets from R (float [SPM][3]) at 32, rho
-//     (float) after them; the raw FP64 site coordinates are copied in first at offset 0 and
-//     overwritten in place once the centre is known.
-//   FP64 pairs: double4 {R, w} at 0, rho at 32, raw FP64 site coordinates ([3][SPM]) at 48,
-//     kept for the atom pairs.
+//   FP32 pairs: double4 {R, w} at 0, FP32 site offsets from R (float [SPM][3]) at 32;
+//   FP64 pairs: double4 {R, w} at 0, raw FP64 site coordinates ([3][SPM]) at 32, kept for
+//     the atom pairs.
+// The largest site distance from the centre (rho) is kept for the tile's own molecules only
+// (the atom-tile bound takes the neighbour's from rho_max).
 template <int SPM, typename PT>
 struct Stage {
     static constexpr bool kF32 = sizeof(PT) == 4;
     static constexpr int r16(int b) { return (b + 15) / 16 * 16; }
-    static constexpr int kRawOff = kF32 ? 0 : 48;
+    static constexpr int kRawOff = 32;
     static constexpr int kOffOff = 32;
-    static constexpr int kRhoOff = kF32 ? 32 + 12 * SPM : 32;
-    static constexpr int kStride = kF32 ? r16(24 * SPM > 36 + 12 * SPM ? 24 * SPM : 36 + 12 * SPM) : r16(48 + 24 * SPM);
-    // the raw coordinates of one molecule move in 16-byte pieces when a row of its sites is
-    // 16-byte aligned (an even number of sites), else in 8-byte pieces
-    static constexpr bool kPair2 = SPM % 2 == 0;
-    static constexpr int kPieces = kPair2 ? 3 * SPM / 2 : 3 * SPM;
+    static constexpr int kStride = kF32 ? r16(32 + 12 * SPM) : r16(32 + 24 * SPM);
 };
 
-// Static LDS beside the halo: home sites and velocities, reference centres and the energy
-// partials.
-constexpr int kStaticLds = 2 * (kBlock / kLanes) * kMaxSites * 3 * 8 + (kBlock / kLanes) * 32 + 256;
+// One molecule's FP64 site coordinates p[k][d] from the SoA rows (16-byte loads when the
+// molecule's sites are 16-byte aligned in a row, i.e. an even number of sites).
+template <int SPM>
+__device__ __forceinline__ void load_molecule(const double *__restrict__ x, int64_t ns, int64_t u,
+                                              double (&p)[SPM][3])
+{
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double *row = x + d * ns + u * SPM;
+        if constexpr (SPM % 2 == 0) {
+#pragma unroll
+            for (int k = 0; k < SPM; k += 2) {
+                const double2 v = *reinterpret_cast<const double2 *>(row + k);
+                p[k][d] = v.x;
+                p[k + 1][d] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < SPM; ++k) p[k][d] = row[k];
+        }
+    }
+}
+
+// Whether a molecule with this centre can take part in an atom pair (only then are its FP32
+// site offsets needed): with force interpolation both molecules of the pair have a non-zero
+// weight, so its distance from the AT centre is below d_at + d_hy; with Eq. (2) one of them
+// does, so it lies within that plus the largest centre distance of an atom tile.  A
+// self-adjusting region's weights are not known here: always.
+__device__ __forceinline__ bool maybe_atomistic(const DevParams &P, const double R[3])
+{
+    if (P.region == ADRES_REGION_ALL_CG) return false;
+    if (P.region != ADRES_REGION_SLAB_X && P.region != ADRES_REGION_SPHERE) return true;
+    const double reach = P.scheme == ADRES_SCHEME_HAMILTONIAN ? P.rc_at + 2.0 * P.rho_max + 1e-6 : 0.0;
+    double q[3];
+    return res_distance(P, R, q) < P.d_end + reach;
+}
+
+// Centre of mass and (FP32 pairs) the FP32 site offsets, or (FP64 pairs) the raw site
+// coordinates, of one halo molecule into its LDS record; the weight follows later.  With
+// HOME, also rho (the tile's own molecules: the atom-tile bound takes rho_max for the
+// neighbour).
+template <int SPM, typename PT>
+__device__ __forceinline__ double stage_molecule(const DevParams &P, unsigned char *mrec, const double (&p)[SPM][3],
+                                                 bool home)
+{
+    using St = Stage<SPM, PT>;
+    double R[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double c[SPM];
+#pragma unroll
+        for (int k = 0; k < SPM; ++k) c[k] = p[k][d];
+        R[d] = com_dim<SPM>(P, c, d);
+    }
+    double rh = 0.0;
+    if (home) {   // the operation order of mol_com
+        double rmax2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < SPM; ++k) {
+            const double q0 = mi(p[k][0] - R[0], P.box[0], P.inv_box[0]);
+            const double q1 = mi(p[k][1] - R[1], P.box[1], P.inv_box[1]);
+            const double q2 = mi(p[k][2] - R[2], P.box[2], P.inv_box[2]);
+            const double r2 = dist2_exact(q0, q1, q2);
+            rmax2 = r2 > rmax2 ? r2 : rmax2;
+        }
+        rh = sqrt(rmax2);
+    }
+    if constexpr (St::kF32) {
+        if (SPM > 1 && maybe_atomistic(P, R)) {
+            float *od = reinterpret_cast<float *>(mrec + St::kOffOff);
+#pragma unroll
+            for (int k = 0; k < SPM; ++k)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) od[3 * k + d] = (float)mi(p[k][d] - R[d], P.box[d], P.inv_box[d]);
+        }
+    } else {
+        double *raw = reinterpret_cast<double *>(mrec + St::kRawOff);
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int k = 0; k < SPM; ++k) raw[d * SPM + k] = p[k][d];
+    }
+    double *rw = reinterpret_cast<double *>(mrec);
+    rw[0] = R[0];
+    rw[1] = R[1];
+    rw[2] = R[2];
+    return rh;
+}
+
+// Static LDS beside the halo: home sites, home rho and the energy partials.
+constexpr int kStaticLds = (kBlock / kLanes) * kMaxSites * 3 * 8 + (kBlock / kLanes) * 4 + 256;
 
 // At most 128 VGPRs (4 waves per SIMD): 4 lanes x 64k molecules is ~4000 wavefronts,
 // which then fit the 1024 SIMDs in a single round.
@@ -137,26 +220,20 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     const bool valid = t < n;
     const int tt = valid ? t : n - 1;
 
-    // the home sites (FP64) for the bonds and the integration; velocities and reference
-    // centres are only needed after the force loop: staging them here lets their loads
-    // overlap the prologue instead of adding a wait at the end
+    // the home sites (FP64) for the bonds and the integration, and the home molecules' rho
     __shared__ double sx[kBlock / kLanes][SPM][3];
-    __shared__ double sv[MODE == kModeForce ? 1 : kBlock / kLanes][SPM][3];
-    __shared__ double4 sref[MODE == kModeStep ? kBlock / kLanes : 1];
+    __shared__ float srho[kBlock / kLanes];
     const int ml = threadIdx.x / kLanes;
-    // every load that does not depend on another (own site, velocity, reference centre, row
-    // length and the first local row entries, the halo count) is issued before the first
-    // wait: the prologue costs one memory round trip, the halo gather a second
-    double lx[3] = {0.0, 0.0, 0.0}, lv[3] = {0.0, 0.0, 0.0};
+    // every load that does not depend on another (own site, row length and the first local
+    // row entries, the halo count and the first halo ids) is issued before the first wait:
+    // the prologue costs one memory round trip, the halo gather a second.  Velocities and
+    // the reference centre are requested after the pair loop, which keeps the workgroup's
+    // LDS within a quarter of the compute unit's (four workgroups per compute unit)
+    double lx[3] = {0.0, 0.0, 0.0};
     if (q < SPM) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) lx[d] = a.x[d * ns + (int64_t)tt * SPM + q];
-        if (MODE != kModeForce)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) lv[d] = a.v[d * ns + (int64_t)tt * SPM + q];
     }
-    double4 lref = make_double4(0.0, 0.0, 0.0, 0.0);
-    if (MODE == kModeStep) lref = a.R_ref[tt];
     // (a row longer than cap exists only after an overflow, which stops every launch)
     const int cnt = valid ? min(a.cnt[tt], a.cap) : 0;
     const int nq = cnt > q ? (cnt - q + 3) >> 2 : 0;   // this lane's entries k = q + 4 i
@@ -164,66 +241,45 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     uint4 ch = make_uint4(0u, 0u, 0u, 0u);
     if (nq > 0) ch = *reinterpret_cast<const uint4 *>(lrow);
     const int hn = min(a.hn[blk], a.hcap);
+    // the first two halo molecules of this thread: their slot ids travel with the prologue
+    const int *hid = a.hid + (int64_t)blk * a.hcap;
+    const int la = threadIdx.x, lb = la + kBlock;
+    const int ida = hid[min(la, a.hcap - 1)], idb = hid[min(lb, a.hcap - 1)];
     // the same decision in every wave: only an earlier launch can set halt below this step
     // (this one sets it to its own step at the lowest), so no workgroup stops at a barrier
     if (a.check_halt && a.step > halt) return;
 
-    // stage A: the raw site coordinates of the halo (the tile's own molecules first), in
-    // coalesced 16- or 8-byte pieces
-    const int *hid = a.hid + (int64_t)blk * a.hcap;
-    for (int idx = threadIdx.x; idx < hn * St::kPieces; idx += kBlock) {
-        const int l = idx / St::kPieces, pc = idx - l * St::kPieces;
-        const int64_t u = hid[l];
-        double *raw = reinterpret_cast<double *>(hs + l * St::kStride + St::kRawOff);
-        if constexpr (St::kPair2) {
-            constexpr int H = SPM / 2;
-            const int d = pc / H, k2 = 2 * (pc - d * H);
-            *reinterpret_cast<double2 *>(raw + d * SPM + k2) =
-                *reinterpret_cast<const double2 *>(a.x + d * ns + u * SPM + k2);
-        } else {
-            const int d = pc / SPM, k = pc - d * SPM;
-            raw[d * SPM + k] = a.x[d * ns + u * SPM + k];
-        }
-    }
+    // own sites to LDS first, which frees their registers for the halo's sites
     if (q < SPM) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) sx[ml][q][d] = lx[d];
-        if (MODE != kModeForce)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) sv[ml][q][d] = lv[d];
     }
-    if (MODE == kModeStep && q == 0) sref[ml] = lref;
-    __syncthreads();
 
-    // stage B: centre of mass, weight, rho (and the FP32 site offsets) of every halo
-    // molecule, with the operation order of mol_com, so that every tile derives the same
-    // bits for a molecule
-    for (int l = threadIdx.x; l < hn; l += kBlock) {
-        unsigned char *mrec = hs + l * St::kStride;
-        const double *raw = reinterpret_cast<const double *>(mrec + St::kRawOff);
-        double p[SPM][3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-            for (int k = 0; k < SPM; ++k) p[k][d] = raw[d * SPM + k];
-        double R[3], rh;
-        mol_com<SPM>(P, p, R, rh);
-        if constexpr (St::kF32) {
-            float of[3 * SPM];
-#pragma unroll
-            for (int k = 0; k < SPM; ++k)
-#pragma unroll
-                for (int d = 0; d < 3; ++d) of[3 * k + d] = (float)mi(p[k][d] - R[d], P.box[d], P.half[d]);
-            float *od = reinterpret_cast<float *>(mrec + St::kOffOff);
-#pragma unroll
-            for (int j = 0; j < 3 * SPM; ++j) od[j] = of[j];
+    // stage A: one thread per halo molecule (the tile's own molecules first), two molecules
+    // per thread with all their sites requested before the first use: the halo arrives in
+    // the second dependent round; then the thread forms the molecule's centre of mass and
+    // rho (and the FP32 site offsets) with the operation order of mol_com, so that every
+    // tile derives the same bits for a molecule, and stores them in LDS
+    {
+        // entries at or past the halo count are not written by the halo build: slot 0 instead
+        const int64_t ua = la < hn ? ida : 0, ub = lb < hn ? idb : 0;
+        double pa[SPM][3], pb[SPM][3];
+        load_molecule<SPM>(a.x, ns, ua, pa);
+        if (lb < hn) load_molecule<SPM>(a.x, ns, ub, pb);
+        if (la < hn) {
+            const double rh = stage_molecule<SPM, PT>(P, hs + la * St::kStride, pa, la < kHaloTile);
+            if (la < kHaloTile) srho[la] = (float)rh;
         }
-        *reinterpret_cast<double4 *>(mrec) = make_double4(R[0], R[1], R[2], 0.0);
-        *reinterpret_cast<float *>(mrec + St::kRhoOff) = (float)rh;
+        if (lb < hn) stage_molecule<SPM, PT>(P, hs + lb * St::kStride, pb, false);
     }
-    // the weights in a pass of their own, so that the FP64 cosine's registers do not add to
-    // those of the centre computation (a self-adjusting region's weights come from the
-    // anchor pass)
+    for (int l = 2 * kBlock + threadIdx.x; l < hn; l += kBlock) {   // halos over 512 molecules
+        double pc[SPM][3];
+        load_molecule<SPM>(a.x, ns, hid[l], pc);
+        stage_molecule<SPM, PT>(P, hs + l * St::kStride, pc, false);
+    }
+    // the weights in a pass of their own, by the thread that staged the molecule, so that
+    // the FP64 cosine's registers do not add to those of the centre computation (a
+    // self-adjusting region's weights come from the anchor pass)
     for (int l = threadIdx.x; l < hn; l += kBlock) {
         double *rw = reinterpret_cast<double *>(hs + l * St::kStride);
         const double R[3] = {rw[0], rw[1], rw[2]};
@@ -233,10 +289,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
 
     const unsigned char *mine = hs + ml * St::kStride;
     const double4 me = *reinterpret_cast<const double4 *>(mine);
-    const double rha = (double)*reinterpret_cast<const float *>(mine + St::kRhoOff);
+    const double rha = (double)srho[ml];
     constexpr bool kOff = St::kF32;   // FP32 displacements from site offsets
-    float hoff[SPM][3] = {};
-    if constexpr (kOff) {
+    float hoff[SPM][3] = {};   // (a single site's offset from its centre is exactly zero)
+    if constexpr (kOff && SPM > 1) {
         const float *od = reinterpret_cast<const float *>(mine + St::kOffOff);
 #pragma unroll
         for (int i = 0; i < SPM; ++i)
@@ -275,9 +331,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
         const unsigned char *nrec = hs + l * St::kStride;
         const double4 o = *reinterpret_cast<const double4 *>(nrec);
         const double ww = HAM ? 0.5 * (me.w + o.w) : me.w * o.w;   // weight of the AT part
-        const double D0 = mi(me.x - o.x, P.box[0], P.half[0]);
-        const double D1 = mi(me.y - o.y, P.box[1], P.half[1]);
-        const double D2 = mi(me.z - o.z, P.box[2], P.half[2]);
+        const double D0 = mi(me.x - o.x, P.box[0], P.inv_box[0]);
+        const double D1 = mi(me.y - o.y, P.box[1], P.inv_box[1]);
+        const double D2 = mi(me.z - o.z, P.box[2], P.inv_box[2]);
         const double r2c = dist2_exact(D0, D1, D2);
         if (ww > 0.0) {
             // no atom pair of the tile can be within the cutoff beyond this centre
@@ -287,28 +343,60 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                 const PT pww = (PT)ww;
                 if constexpr (kOff) {
                     const float *od = reinterpret_cast<const float *>(nrec + St::kOffOff);
+                    // a neighbour site's FP32 offset (zero for single-site molecules, not stored)
+                    auto nof = [od](int j) { return SPM > 1 ? od[j] : 0.0f; };
                     // D + (off_i - off_jj): the same bits with opposite sign from the
                     // other molecule's side, so pair forces cancel exactly (Newton's third law)
                     const float Df0 = (float)D0, Df1 = (float)D1, Df2 = (float)D2;
-#pragma unroll 1
+                    const float rcf = (float)rcA2;
+                    // first pass: which of the tile's SPM x SPM atom pairs may be inside the
+                    // cutoff (bit SPM ii + jj); few are, and the lanes of a wavefront disagree.
+                    // The displacement is regrouped as (D - off_jj) + off_i (one subtraction per
+                    // neighbour site) and tested against a cutoff padded by 2^-16 of r^2, far
+                    // more than the few-ulp difference of the two groupings: a superset of the
+                    // pairs inside, which the second pass tests exactly
+                    const float rct = rcf * (1.0f + 1.0f / 65536.0f);
+                    unsigned inside = 0u;
+#pragma unroll
                     for (int jj = 0; jj < SPM; ++jj) {
-                        const float n0 = od[3 * jj], n1 = od[3 * jj + 1], n2 = od[3 * jj + 2];
+                        const float e0 = Df0 - nof(3 * jj), e1 = Df1 - nof(3 * jj + 1),
+                                    e2 = Df2 - nof(3 * jj + 2);
 #pragma unroll
                         for (int ii = 0; ii < SPM; ++ii) {
-                            const float dx = Df0 + (hoff[ii][0] - n0);
-                            const float dy = Df1 + (hoff[ii][1] - n1);
-                            const float dz = Df2 + (hoff[ii][2] - n2);
+                            const float dx = e0 + hoff[ii][0];
+                            const float dy = e1 + hoff[ii][1];
+                            const float dz = e2 + hoff[ii][2];
                             const float r2 = (dx * dx + dy * dy) + dz * dz;
-                            if (r2 < (float)rcA2) {
-                                PT uu = PT(0);
-                                const PT c = pww * wca_f_over_r<PT>((PT)r2, sig2A, epsA, uu, ENERGY || hy_home);
-                                acc[ii][0] += (double)(c * dx);
-                                acc[ii][1] += (double)(c * dy);
-                                acc[ii][2] += (double)(c * dz);
-                                if (ENERGY) uat += 0.5 * (HAM ? me.w : ww) * (double)uu;
-                                if (HAM) vat += 0.5 * (double)uu;
-                            }
+                            inside |= (r2 < rct ? 1u : 0u) << (SPM * ii + jj);
                         }
+                    }
+                    // second pass: the WCA force only for the pairs inside, site by site, so
+                    // that a wavefront runs the force block as often as its busiest lane has
+                    // pairs for that site instead of once per pair position; a site's terms
+                    // against one neighbour molecule (at most SPM) are summed in FP32 first
+#pragma unroll
+                    for (int ii = 0; ii < SPM; ++ii) {
+                        unsigned m = (inside >> (SPM * ii)) & ((1u << SPM) - 1u);
+                        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+                        while (m) {
+                            const int jj = __builtin_ctz(m);
+                            m &= m - 1u;
+                            const float dx = Df0 + (hoff[ii][0] - nof(3 * jj));
+                            const float dy = Df1 + (hoff[ii][1] - nof(3 * jj + 1));
+                            const float dz = Df2 + (hoff[ii][2] - nof(3 * jj + 2));
+                            const float r2 = (dx * dx + dy * dy) + dz * dz;
+                            if (!(r2 < rcf)) continue;
+                            PT uu = PT(0);
+                            const PT c = pww * wca_f_over_r<PT>((PT)r2, sig2A, epsA, uu, ENERGY || hy_home);
+                            s0 += c * dx;
+                            s1 += c * dy;
+                            s2 += c * dz;
+                            if (ENERGY) uat += 0.5 * (HAM ? me.w : ww) * (double)uu;
+                            if (HAM) vat += 0.5 * (double)uu;
+                        }
+                        acc[ii][0] += (double)s0;
+                        acc[ii][1] += (double)s1;
+                        acc[ii][2] += (double)s2;
                     }
                 } else {
                     const double *xj = reinterpret_cast<const double *>(nrec + St::kRawOff);
@@ -317,9 +405,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                         const double xj0 = xj[jj], xj1 = xj[SPM + jj], xj2 = xj[2 * SPM + jj];
 #pragma unroll
                         for (int ii = 0; ii < SPM; ++ii) {
-                            const PT dx = (PT)mi(XI(ii, 0) - xj0, P.box[0], P.half[0]);
-                            const PT dy = (PT)mi(XI(ii, 1) - xj1, P.box[1], P.half[1]);
-                            const PT dz = (PT)mi(XI(ii, 2) - xj2, P.box[2], P.half[2]);
+                            const PT dx = (PT)mi(XI(ii, 0) - xj0, P.box[0], P.inv_box[0]);
+                            const PT dy = (PT)mi(XI(ii, 1) - xj1, P.box[1], P.inv_box[1]);
+                            const PT dz = (PT)mi(XI(ii, 2) - xj2, P.box[2], P.inv_box[2]);
                             const PT r2 = (dx * dx + dy * dy) + dz * dz;
                             if (r2 < rcA2) {
                                 PT uu = PT(0);
@@ -373,6 +461,15 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     cg0 = quad_sum(cg0);
     cg1 = quad_sum(cg1);
     cg2 = quad_sum(cg2);
+
+    // the velocity and the reference centre, requested before the bonds and the correction
+    // field so that their arithmetic covers the load
+    double lv[3] = {0.0, 0.0, 0.0};
+    if (MODE != kModeForce && q < SPM)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) lv[d] = a.v[d * ns + (int64_t)tt * SPM + q];
+    double4 lref = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (MODE == kModeStep && q == 0) lref = a.R_ref[tt];
 
 #define XS(k, d) sx[ml][(k)][(d)]
 
@@ -430,9 +527,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
 #pragma unroll
             for (int k = 0; k < SPM; ++k) {
                 if (k == q) continue;
-                const double d0 = mi(xq[0] - XS(k, 0), P.box[0], P.half[0]);
-                const double d1 = mi(xq[1] - XS(k, 1), P.box[1], P.half[1]);
-                const double d2 = mi(xq[2] - XS(k, 2), P.box[2], P.half[2]);
+                const double d0 = mi(xq[0] - XS(k, 0), P.box[0], P.inv_box[0]);
+                const double d1 = mi(xq[1] - XS(k, 1), P.box[1], P.inv_box[1]);
+                const double d2 = mi(xq[2] - XS(k, 2), P.box[2], P.inv_box[2]);
                 const double r2b = (d0 * d0 + d1 * d1) + d2 * d2;
                 const double ir = rsqrt_refined(r2b);
                 const double r = r2b * ir;
@@ -447,9 +544,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                 const int cb = ca + side;
                 if (cb < 0 || cb >= n || cb / P.chain_len != chain) continue;
                 const int ub = a.inv_perm[cb];
-                const double d0 = mi(xq[0] - a.x[(int64_t)ub * SPM], P.box[0], P.half[0]);
-                const double d1 = mi(xq[1] - a.x[ns + (int64_t)ub * SPM], P.box[1], P.half[1]);
-                const double d2 = mi(xq[2] - a.x[2 * ns + (int64_t)ub * SPM], P.box[2], P.half[2]);
+                const double d0 = mi(xq[0] - a.x[(int64_t)ub * SPM], P.box[0], P.inv_box[0]);
+                const double d1 = mi(xq[1] - a.x[ns + (int64_t)ub * SPM], P.box[1], P.inv_box[1]);
+                const double d2 = mi(xq[2] - a.x[2 * ns + (int64_t)ub * SPM], P.box[2], P.inv_box[2]);
                 const double r2 = (d0 * d0 + d1 * d1) + d2 * d2;
                 if (r2 >= P.R02) {
                     atomicOr(&a.ctrl->err, kErrFene);
@@ -473,7 +570,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
         }
     } else if (MODE == kModeClose) {
         if (owner) {
-            double v[3] = {sv[ml][q][0], sv[ml][q][1], sv[ml][q][2]};
+            double v[3] = {lv[0], lv[1], lv[2]};
             close_kick(v, F, a.st.dt, iq);
             a.v[site] = v[0]; a.v[ns + site] = v[1]; a.v[2 * ns + site] = v[2];
             a.f[site] = F[0]; a.f[ns + site] = F[1]; a.f[2 * ns + site] = F[2];
@@ -481,7 +578,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     } else {   // kModeStep
         double xn[3] = {xq[0], xq[1], xq[2]};
         if (owner) {
-            double v[3] = {sv[ml][q][0], sv[ml][q][1], sv[ml][q][2]};
+            double v[3] = {lv[0], lv[1], lv[2]};
             close_kick(v, F, a.st.dt, iq);
             const int caller_site = a.st.gamma > 0.0 ? a.perm[t] * SPM + q : 0;
             open_and_drift(P, mq, iq, caller_site, xn, v, F, a.st.dt, a.st.gamma, a.st.kT, a.st.seed, a.st.step_abs);
@@ -511,9 +608,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                      R2 = quad_perm<kQuadBcast<2>>(Rd);
         double r2 = 0.0;
         if (owner) {
-            const double o0 = mi(xn[0] - R0, P.box[0], P.half[0]);
-            const double o1 = mi(xn[1] - R1, P.box[1], P.half[1]);
-            const double o2 = mi(xn[2] - R2, P.box[2], P.half[2]);
+            const double o0 = mi(xn[0] - R0, P.box[0], P.inv_box[0]);
+            const double o1 = mi(xn[1] - R1, P.box[1], P.inv_box[1]);
+            const double o2 = mi(xn[2] - R2, P.box[2], P.inv_box[2]);
             r2 = dist2_exact(o0, o1, o2);
         }
         double m2 = r2;
@@ -529,10 +626,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
             if (a.Rw_out) a.Rw_out[t] = make_double4(R0, R1, R2, res_weight(P, R));
             if (!(isfinite(R0) && isfinite(R1) && isfinite(R2))) atomicOr(&a.ctrl->err, kErrNonFinite);
             if (SPM > 1 && rh > P.rho_max) atomicOr(&a.ctrl->err, kErrStretch);
-            const double4 rr = sref[ml];
-            const double q0 = mi(R0 - rr.x, P.box[0], P.half[0]);
-            const double q1 = mi(R1 - rr.y, P.box[1], P.half[1]);
-            const double q2 = mi(R2 - rr.z, P.box[2], P.half[2]);
+            const double4 rr = lref;
+            const double q0 = mi(R0 - rr.x, P.box[0], P.inv_box[0]);
+            const double q1 = mi(R1 - rr.y, P.box[1], P.inv_box[1]);
+            const double q2 = mi(R2 - rr.z, P.box[2], P.inv_box[2]);
             if (dist2_exact(q0, q1, q2) > P.half_skin2) atomicMin(&a.ctrl->halt, a.step);
         }
     }

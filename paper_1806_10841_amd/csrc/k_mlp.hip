@@ -53,9 +53,9 @@ __device__ __forceinline__ double pair_r(const PairSource &src, const DevParams 
     if (src.r) return src.r[p];
     const int2 tu = src.pairs[p];
     const double4 a = src.Rw[tu.x], b = src.Rw[tu.y];
-    const double d0 = mi(a.x - b.x, P.box[0], P.half[0]);
-    const double d1 = mi(a.y - b.y, P.box[1], P.half[1]);
-    const double d2 = mi(a.z - b.z, P.box[2], P.half[2]);
+    const double d0 = mi(a.x - b.x, P.box[0], P.inv_box[0]);
+    const double d1 = mi(a.y - b.y, P.box[1], P.inv_box[1]);
+    const double d2 = mi(a.z - b.z, P.box[2], P.inv_box[2]);
     return sqrt(dist2_exact(d0, d1, d2));
 }
 

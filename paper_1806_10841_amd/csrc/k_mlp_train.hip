@@ -138,9 +138,9 @@ __global__ __launch_bounds__(kThreads) void k_mlp_backward(MlpDev M, DevParams P
         if (p < n_pairs) {
             const int2 tu = pairs[p];
             const double4 a = Rw[tu.x], b = Rw[tu.y];
-            const double d0 = mi(a.x - b.x, P.box[0], P.half[0]);
-            const double d1 = mi(a.y - b.y, P.box[1], P.half[1]);
-            const double d2 = mi(a.z - b.z, P.box[2], P.half[2]);
+            const double d0 = mi(a.x - b.x, P.box[0], P.inv_box[0]);
+            const double d1 = mi(a.y - b.y, P.box[1], P.inv_box[1]);
+            const double d2 = mi(a.z - b.z, P.box[2], P.inv_box[2]);
             const double r = sqrt(dist2_exact(d0, d1, d2));
             x = (float)r * inv_rc;
             if (r < M.rc && r >= M.r_min) {

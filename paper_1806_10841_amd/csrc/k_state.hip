@@ -189,9 +189,9 @@ __device__ __forceinline__ double nearest_anchor(const DevParams &P, const doubl
 #pragma clang fp contract(off)
     double best = INFINITY;
     for (int k = 0; k < K; ++k) {
-        const double q0 = mi(R[0] - cen[k][0], P.box[0], P.half[0]);
-        const double q1 = mi(R[1] - cen[k][1], P.box[1], P.half[1]);
-        const double q2 = mi(R[2] - cen[k][2], P.box[2], P.half[2]);
+        const double q0 = mi(R[0] - cen[k][0], P.box[0], P.inv_box[0]);
+        const double q1 = mi(R[1] - cen[k][1], P.box[1], P.inv_box[1]);
+        const double q2 = mi(R[2] - cen[k][2], P.box[2], P.inv_box[2]);
         const double r2 = dist2_exact(q0, q1, q2);
         best = r2 < best ? r2 : best;
     }
@@ -377,9 +377,9 @@ __global__ __launch_bounds__(kBlock) void k_anchor_weights(DevParams P, double4 
     const double R0 = me[0], R1 = me[1], R2 = me[2];
     double best = INFINITY, b0 = 0.0, b1 = 0.0, b2 = 0.0;
     for (int k = 0; k < K; ++k) {
-        const double q0 = mi(R0 - cen[k][0], P.box[0], P.half[0]);
-        const double q1 = mi(R1 - cen[k][1], P.box[1], P.half[1]);
-        const double q2 = mi(R2 - cen[k][2], P.box[2], P.half[2]);
+        const double q0 = mi(R0 - cen[k][0], P.box[0], P.inv_box[0]);
+        const double q1 = mi(R1 - cen[k][1], P.box[1], P.inv_box[1]);
+        const double q2 = mi(R2 - cen[k][2], P.box[2], P.inv_box[2]);
         const double r2 = dist2_exact(q0, q1, q2);
         if (r2 < best) {   // the first of equally near anchors
             best = r2;
@@ -411,9 +411,9 @@ __global__ __launch_bounds__(kBlock) void k_anchor_weights_caller(DevParams P, c
     const double R0 = com[a], R1 = com[n + a], R2 = com[2 * n + a];
     double best = INFINITY;
     for (int k = 0; k < K; ++k) {
-        const double q0 = mi(R0 - cen[k][0], P.box[0], P.half[0]);
-        const double q1 = mi(R1 - cen[k][1], P.box[1], P.half[1]);
-        const double q2 = mi(R2 - cen[k][2], P.box[2], P.half[2]);
+        const double q0 = mi(R0 - cen[k][0], P.box[0], P.inv_box[0]);
+        const double q1 = mi(R1 - cen[k][1], P.box[1], P.inv_box[1]);
+        const double q2 = mi(R2 - cen[k][2], P.box[2], P.inv_box[2]);
         const double r2 = dist2_exact(q0, q1, q2);
         best = r2 < best ? r2 : best;
     }
