@@ -34,8 +34,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TIMING_EVERY = 8      # HIP events on every 8th force launch (events on all launches slow the stream)
 METRIC = "pair interactions/s + MD steps/s (AdResS 256k sites); learned vs tabulated CG"
+EQUIL_SEED = 20181
+EQUIL_GAMMA = 1.0
 
 
 def main():
@@ -43,6 +44,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--equilibrate", type=int, default=2000,
+                    help="Langevin steps (gamma 1, kT 1, fixed seed) that melt the lattice start "
+                         "before anything is timed; every timed run starts from that state")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cg-compare", action="store_true",
                     help="skip the learned-vs-tabulated CG force leg")
@@ -59,6 +63,8 @@ def main():
                     help="skip the self-adjusting (anchor spheres) region leg")
     ap.add_argument("--no-c5", action="store_true",
                     help="skip the 1M-tetrahedron heterogeneous run inside the learned-CG leg")
+    ap.add_argument("--no-c1-c3", action="store_true",
+                    help="skip the small FP64 workload (C1) and the Kremer-Grest melt (C3) legs")
     ap.add_argument("--workload", default="c2",
                     help="c2 (the headline) or c5 (1,000,000 tetrahedra, spherical AT region); "
                          "the CG force is the analytic WCA between centres")
@@ -71,7 +77,6 @@ def main():
         sys.exit(2)
 
     import torch
-    from scipy.spatial import cKDTree
 
     if args.copy_bytes:
         src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device="cuda")
@@ -82,62 +87,133 @@ def main():
         print(json.dumps({"copy_bytes": args.copy_bytes, "launches": 10}))
         return
 
-    from paper_1806_10841_amd import binding, inputs
+    from paper_1806_10841_amd import inputs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.cg_only:
         print(json.dumps({"learned_vs_tabulated": learned_vs_tabulated(args.cg_steps, not args.no_c5)}))
         return
-    dev = torch.device("cuda:0")
     wl = inputs.workload(args.workload)
     if wl.cg_kind != inputs.CG_WCA:
         # the force-matched table and the network are fitted inside the learned leg only
         wl = wl.with_(cg_kind=inputs.CG_WCA)
     x, v = inputs.make_state(wl)
+    rec = timed_workload(wl, x, v, args.steps, args.warmup, args.equilibrate, gamma=0.0)
+
+    out = {
+        "metric": METRIC,
+        "value": rec["steps_per_s"],
+        "unit": "MD steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": rec["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair arithmetic, f64 sums and integration",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{wl.name}: {wl.n_mol} tetrahedra ({wl.n_mol * wl.sites_per_mol} atoms), "
+                        f"{'x-slab' if wl.region == inputs.REGION_SLAB_X else 'sphere'} AdResS "
+                        f"AT {wl.d_at:g} + HY {wl.d_hy:g}, WCA atoms + WCA CG, harmonic bonds, "
+                        f"NVE velocity Verlet dt {wl.dt:g}; timed from a melted state ({args.equilibrate} "
+                        f"Langevin steps, gamma {EQUIL_GAMMA:g}, kT 1, from the lattice start)",
+            "n_mol": wl.n_mol, "n_sites": wl.n_mol * wl.sites_per_mol, "box": wl.box[0],
+            "list_rebuilds": rec["list_rebuilds"], "equilibration_steps": args.equilibrate,
+        },
+    }
+    for k in ("pair_interactions_per_s", "interacting_pairs_per_eval", "listed_molecule_pairs",
+              "listed_pairs_per_s", "force_kernel_us", "force_kernel_launches_timed",
+              "steps_per_s_median_of_5", "steps_per_s_of_5"):
+        out[k] = rec[k]
+    traffic = _measured_traffic() if wl.name == "c2" else None   # counters were taken on C2
+    avg_s = rec["force_kernel_us"] * 1e-6
+    copy_gbs = _copy_bandwidth_gbs(torch)
+    out["roofline"] = {
+        "bound": "hbm",
+        "achieved": rec["achieved_GBps"],
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": rec["achieved_GBps"] / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "kernel": "k_forces<4,float,step> (Eq. 1 + bonds + closing kick, opening kick + drift)",
+        "bytes_per_launch": rec["bytes_per_launch"],
+        # counter bytes over the same time, against the peak (None without counters)
+        "traffic_frac": None if traffic is None else traffic / avg_s / 1e9 / HBM_PEAK_GBS,
+        # achievable HBM on this GPU: a plain 1 GiB device copy (read + write bytes)
+        "copy_GBps": copy_gbs,
+        "frac_of_copy": rec["achieved_GBps"] / copy_gbs,
+    }
+    x_eq, v_eq = rec.pop("_state")
+
+    if not args.no_c1_c3 and wl.name == "c2":
+        out["c1_fp64_small"] = c1_leg()
+        out["c3_kremer_grest"] = c3_leg(args.steps, args.warmup)
+    if not args.no_hamiltonian:
+        out["hamiltonian_scheme"] = hamiltonian_leg(wl, x_eq, v_eq, args.steps, args.warmup)
+    if not args.no_tdforce:
+        out["thermodynamic_force"] = tdforce_leg(wl, x, v, args.steps)
+    if not args.no_respa:
+        out["respa"] = respa_leg(wl, x_eq, v_eq, args.steps, args.warmup, rec["steps_per_s"])
+    if not args.no_anchors:
+        out["self_adjusting_region"] = anchors_leg(wl, x_eq, v_eq, args.steps, args.warmup)
+    if not args.no_cg_compare:
+        out["learned_vs_tabulated"] = learned_vs_tabulated(args.cg_steps, not args.no_c5)
+
+    if not args.no_cpu_baseline and wl.name == "c2":   # the oracle's all-pairs steps: C2 only
+        out["cpu_baseline"] = cpu_baseline(wl, x_eq, v_eq)
+    print(json.dumps(out))
+
+
+def timed_workload(wl, x, v, steps, warmup, equilibrate, gamma=0.0, kT=1.0, seed=3, eq_gamma=EQUIL_GAMMA):
+    """MD steps/s of adres_integrate on workload wl from a fixed melted state: equilibrate
+    Langevin steps (fixed seed) from (x, v), then warmup untimed steps, then the timed call
+    (and five repeats, and one with HIP events on every force launch) each restarted from the
+    equilibrated state, so that the timed state depends on neither --steps nor --warmup.
+    Also the fused step's average duration, its algorithmic bytes and rate, and the pair
+    counts of the equilibrated state."""
+    import torch
+    from scipy.spatial import cKDTree
+    from paper_1806_10841_amd import binding
     ctx = binding.Context(wl)
-    xt = torch.tensor(x, device=dev)
-    vt = torch.tensor(v, device=dev)
+    xt = torch.tensor(x, device="cuda")
+    vt = torch.tensor(v, device="cuda")
     ft = torch.empty_like(xt)
-
-    ctx.integrate(xt, vt, ft, wl.dt, args.warmup)
+    if equilibrate:
+        ctx.integrate(xt, vt, ft, wl.dt, equilibrate, gamma=eq_gamma, kT=1.0, seed=EQUIL_SEED)
     torch.cuda.synchronize()
-    x_w, v_w = xt.clone(), vt.clone()   # the timed calls all start from this state
-
+    x_eq, v_eq = xt.clone(), vt.clone()
+    ctx.integrate(xt, vt, ft, wl.dt, warmup, gamma=gamma, kT=kT, seed=seed)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    nreb = ctx.integrate(xt, vt, ft, wl.dt, args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    steps_per_s = args.steps / elapsed
-    x_end, v_end = xt.clone(), vt.clone()
 
-    def rerun(timed_kernel):
-        # the timed call again from the post-warm-up state
-        xt.copy_(x_w)
-        vt.copy_(v_w)
-        if timed_kernel:
-            ctx.kernel_timing(True, every=TIMING_EVERY)   # events on every 8th force launch
+    def run(evented):
+        xt.copy_(x_eq)
+        vt.copy_(v_eq)
+        if evented:
+            ctx.kernel_timing(True, every=1)       # events on every force launch
         torch.cuda.synchronize()
-        ta = time.perf_counter()
-        ctx.integrate(xt, vt, ft, wl.dt, args.steps)
+        t0 = time.perf_counter()
+        nreb = ctx.integrate(xt, vt, ft, wl.dt, steps, gamma=gamma, kT=kT, seed=seed)
         torch.cuda.synchronize()
-        return args.steps / (time.perf_counter() - ta)
+        return steps / (time.perf_counter() - t0), nreb
 
+    sps, nreb = run(False)
     # five repeats without events: their median rate (a spread check beside value), then
-    # one with HIP events on the force launches for the kernel's duration (the events slow
+    # one with HIP events on every force launch for the kernel's duration (the events slow
     # the launch stream by a few per cent, so value and the median are taken without them)
-    rates = [rerun(False) for _ in range(5)]
-    rerun(True)
+    rates = [run(False)[0] for _ in range(5)]
+    run(True)
     force_ms, launches = ctx.kernel_timing(False)
-    xt.copy_(x_end)
-    vt.copy_(v_end)
+    avg_s = force_ms / 1e3 / max(launches, 1)
 
-    # workload statistics on the final state (measurement only)
+    # workload statistics of the equilibrated state (measurement only)
+    xt.copy_(x_eq)
     n_pairs = ctx.build_verlet(xt)
     com, w = ctx.weights(xt)
     torch.cuda.synchronize()
     xf, comf, wf = xt.cpu().numpy(), com.cpu().numpy(), w.cpu().numpy()
+    ctx.close()
     box = np.asarray(wl.box)
     spm = wl.sites_per_mol
     pts = np.mod(xf.T, box)
@@ -145,100 +221,140 @@ def main():
     ap_ = cKDTree(pts, boxsize=box).query_pairs(wl.rc_at, output_type="ndarray")
     ma, mb = mol[ap_[:, 0]], mol[ap_[:, 1]]
     n_at = int(np.count_nonzero((ma != mb) & (wf[ma] * wf[mb] > 0)))
-    cp = cKDTree(np.mod(comf.T, box), boxsize=box).query_pairs(wl.rc_cg, output_type="ndarray")
-    n_cg = int(np.count_nonzero(wf[cp[:, 0]] * wf[cp[:, 1]] < 1))
+    n_cg = 0
+    if wl.region != inputs_region_all_at():
+        cp = cKDTree(np.mod(comf.T, box), boxsize=box).query_pairs(wl.rc_cg, output_type="ndarray")
+        n_cg = int(np.count_nonzero(wf[cp[:, 0]] * wf[cp[:, 1]] < 1))
     n_inter = n_at + n_cg
-
     # dominant kernel: the fused step launch (Eq. (1) forces at x_n, closing half-kick,
     # opening half-kick and drift to x_{n+1}), one per step.  Algorithmic bytes per launch:
     # positions read and written, velocities read and written (4 x 24 B per site), the
     # full neighbour list (4 B per entry, both directions of each listed pair) and the
-    # row counts (4 B per molecule).  Derived per-molecule data (centres, weights, site
-    # offsets) and re-reads are the implementation's, not the algorithm's, and are not
-    # counted; the measured HBM traffic is reported beside it.
-    avg_force_s = force_ms / 1e3 / max(launches, 1)
+    # row counts (4 B per molecule).  Derived per-molecule data and re-reads are the
+    # implementation's, not the algorithm's, and are not counted; the measured HBM traffic
+    # is reported beside it.
     ns, nm = wl.n_mol * spm, wl.n_mol
-    list_entries = 2 * n_pairs
-    bytes_per_launch = 96 * ns + 4 * list_entries + 4 * nm
-    achieved = bytes_per_launch / avg_force_s / 1e9
-    traffic = _measured_traffic() if wl.name == "c2" else None   # counters were taken on C2
-    pair_rate = n_inter / avg_force_s
-    copy_gbs = _copy_bandwidth_gbs(torch)
-
-    out = {
-        "metric": METRIC,
-        "value": steps_per_s,
-        "unit": "MD steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32 pair arithmetic, f64 sums and integration",
-        "data": "synthetic",
-        "config": {
-            "workload": f"{wl.name}: {wl.n_mol} tetrahedra ({ns} atoms), "
-                        f"{'x-slab' if wl.region == inputs.REGION_SLAB_X else 'sphere'} AdResS "
-                        f"AT {wl.d_at:g} + HY {wl.d_hy:g}, WCA atoms + WCA CG, harmonic bonds, "
-                        f"NVE velocity Verlet dt {wl.dt:g}",
-            "n_mol": wl.n_mol, "n_sites": ns, "box": wl.box[0], "r_list": None,
-            "list_rebuilds": nreb,
-        },
-        "pair_interactions_per_s": pair_rate,
+    bytes_per_launch = 96 * ns + 4 * 2 * n_pairs + 4 * nm
+    return {
+        "steps_per_s": sps, "ms_per_step": 1e3 / sps, "list_rebuilds": nreb,
+        "steps_per_s_median_of_5": float(np.median(rates)), "steps_per_s_of_5": rates,
+        "force_kernel_us": avg_s * 1e6, "force_kernel_launches_timed": launches,
+        "pair_interactions_per_s": n_inter / avg_s,
         "interacting_pairs_per_eval": {"at_atom_pairs": n_at, "cg_com_pairs": n_cg},
-        "listed_molecule_pairs": n_pairs,
-        "listed_pairs_per_s": n_pairs / avg_force_s,   # candidates, beside the interacting rate
-        "force_kernel_us": avg_force_s * 1e6,
-        "steps_per_s_median_of_5": float(np.median(rates)),
-        "steps_per_s_of_5": rates,
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "kernel": "k_forces<4,float,step> (Eq. 1 + bonds + closing kick, opening kick + drift)",
-            "bytes_per_launch": bytes_per_launch,
-            # counter bytes over the same time, against the peak (None without counters)
-            "traffic_frac": None if traffic is None else traffic / avg_force_s / 1e9 / HBM_PEAK_GBS,
-            # achievable HBM on this GPU: a plain 1 GiB device copy (read + write bytes)
-            "copy_GBps": copy_gbs,
-            "frac_of_copy": achieved / copy_gbs,
-        },
+        "listed_molecule_pairs": n_pairs, "listed_pairs_per_s": n_pairs / avg_s,
+        "bytes_per_launch": bytes_per_launch, "achieved_GBps": bytes_per_launch / avg_s / 1e9,
+        "_state": (x_eq.cpu().numpy(), v_eq.cpu().numpy()),
     }
 
-    ctx.close()
-    if not args.no_hamiltonian:
-        out["hamiltonian_scheme"] = hamiltonian_leg(wl, x, v, args.steps, args.warmup)
-    if not args.no_tdforce:
-        out["thermodynamic_force"] = tdforce_leg(wl, x, v, args.steps)
-    if not args.no_respa:
-        out["respa"] = respa_leg(wl, x, v, args.steps, args.warmup, steps_per_s)
-    if not args.no_anchors:
-        out["self_adjusting_region"] = anchors_leg(wl, x, v, args.steps, args.warmup)
-    if not args.no_cg_compare:
-        out["learned_vs_tabulated"] = learned_vs_tabulated(args.cg_steps, not args.no_c5)
 
-    if not args.no_cpu_baseline and wl.name == "c2":   # the oracle's all-pairs steps: C2 only
-        import oracle
-        m = oracle.Model(wl)
-        n_cpu = 4
+def inputs_region_all_at():
+    from paper_1806_10841_amd import inputs
+    return inputs.REGION_ALL_AT
+
+
+def c1_leg(steps=100, reps=5):
+    """512 tetrahedra, FP64 pairs (latency-bound: about 0.1 MB per evaluation): microseconds
+    per force evaluation (adres_forces, each call synchronised) and per velocity-Verlet step
+    (100-step adres_integrate calls from the lattice start, median of five)."""
+    import torch
+    from paper_1806_10841_amd import binding, inputs
+    wl = inputs.workload("c1")
+    x, v = inputs.make_state(wl)
+    ctx = binding.Context(wl)
+    xt = torch.tensor(x, device="cuda")
+    vt = torch.tensor(v, device="cuda")
+    ft = torch.empty_like(xt)
+    for _ in range(20):
+        ctx.forces(xt, ft)
+    torch.cuda.synchronize()
+    n_eval = 200
+    t0 = time.perf_counter()
+    for _ in range(n_eval):
+        ctx.forces(xt, ft)
+        torch.cuda.synchronize()
+    us_eval = (time.perf_counter() - t0) / n_eval * 1e6
+    ctx.integrate(xt, vt, ft, wl.dt, steps)
+    per = []
+    for _ in range(reps):
+        xt.copy_(torch.tensor(x, device="cuda"))
+        vt.copy_(torch.tensor(v, device="cuda"))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.integrate(xt, vt, ft, wl.dt, steps)
+        torch.cuda.synchronize()
+        per.append((time.perf_counter() - t0) / steps * 1e6)
+    ctx.close()
+    return {"workload": "c1: 512 tetrahedra, x-slab AT 4 + HY 3, FP64 pairs, NVE velocity Verlet dt 0.005",
+            "us_per_force_eval": us_eval, "us_per_step_median_of_5": float(np.median(per)),
+            "us_per_step_of_5": per, "steps": steps}
+
+
+def c3_leg(steps, warmup, equilibrate=500):
+    """1000 Kremer-Grest chains of 200 beads (200,000 beads, density 0.85), FENE + WCA, the
+    plain method (w = 1), Langevin gamma 0.5 kT 1 at dt 0.01, as the workload states; timed
+    from a state equilibrated by the same thermostat."""
+    from paper_1806_10841_amd import inputs
+    wl = inputs.workload("c3")
+    x, v = inputs.make_state(wl)
+    rec = timed_workload(wl, x, v, steps, warmup, equilibrate, gamma=wl.gamma, kT=wl.kT, seed=5,
+                         eq_gamma=wl.gamma)
+    rec.pop("_state")
+    rec["workload"] = (f"c3: {wl.n_mol} beads in chains of {wl.chain_len}, FENE k {wl.k_bond:g} R0 {wl.r0_bond:g} "
+                       f"+ WCA, Langevin gamma {wl.gamma:g} kT {wl.kT:g}, dt {wl.dt:g}")
+    rec["roofline"] = {"bound": "hbm", "achieved": rec["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": rec["achieved_GBps"] / HBM_PEAK_GBS,
+                       "kernel": "k_forces<1,float,step> (WCA + FENE + closing kick, Langevin BAOAB)"}
+    return rec
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(wl, x, v, n_vv=2, n_sample=2000):
+    """The FP64 oracle as it stands (all-pairs Eq. (1) forces, no neighbour list), timed on
+    this host on the equilibrated headline state: one full force evaluation and n_vv
+    velocity-Verlet steps on all threads, and the forces of a sample of molecules on one
+    thread (extrapolated to the whole evaluation)."""
+    import oracle
+    m = oracle.Model(wl)
+    threads = oracle.num_threads()
+    t = time.perf_counter()
+    m.forces(x)
+    t_force = time.perf_counter() - t
+    t = time.perf_counter()
+    m.vv(x, v, wl.dt, n_vv)           # n_vv + 1 full Eq. (1) evaluations and n_vv VV updates
+    t_vv = time.perf_counter() - t
+    sel = np.sort(np.random.default_rng(9).choice(wl.n_mol, n_sample, replace=False))
+    oracle.set_num_threads(1)
+    try:
         t = time.perf_counter()
-        m.vv(x, v, wl.dt, n_cpu)      # n_cpu + 1 full Eq. (1) evaluations and n_cpu VV updates
-        dt_cpu = time.perf_counter() - t
-        out["cpu_baseline"] = {
-            "value": n_cpu / dt_cpu,
-            "unit": "MD steps/s",
-            "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{n_cpu} oracle velocity-Verlet steps on the full 64,000-molecule state "
-                      f"({n_cpu + 1} all-pairs Eq. (1) force evaluations, {dt_cpu:.1f} s); "
-                      f"steps/s = {n_cpu} / elapsed",
-        }
-    print(json.dumps(out))
+        m.forces_sampled(x, sel)
+        t_one = time.perf_counter() - t
+    finally:
+        oracle.set_num_threads(threads)
+    return {
+        "value": n_vv / t_vv,
+        "unit": "MD steps/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{n_vv} oracle velocity-Verlet steps on the full {wl.n_mol}-molecule equilibrated state "
+                  f"({n_vv + 1} all-pairs Eq. (1) force evaluations, {t_vv:.1f} s on {threads} threads); "
+                  f"one more evaluation alone, and the forces of {n_sample} sampled molecules on 1 thread",
+        "cpu_model": _cpu_model(),
+        "host_cpus": os.cpu_count(),
+        "force_eval_s_all_threads": t_force,
+        "force_eval_s_one_thread_extrapolated": t_one * wl.n_mol / n_sample,
+        "one_thread_sample": {"molecules": n_sample, "seconds": t_one},
+    }
 
 
 def hamiltonian_leg(wl, x, v, steps, warmup):
@@ -263,7 +379,7 @@ def hamiltonian_leg(wl, x, v, steps, warmup):
     ctx.integrate(xt, vt, ft, wh.dt, warmup)
     e0 = total_energy()
     torch.cuda.synchronize()
-    ctx.kernel_timing(True, every=TIMING_EVERY)
+    ctx.kernel_timing(True, every=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     nreb = ctx.integrate(xt, vt, ft, wh.dt, steps)
@@ -516,13 +632,13 @@ def learned_vs_tabulated(cg_steps, with_c5=True):
         vt = torch.tensor(v4, device="cuda")
         ft = torch.empty_like(xt)
         ctx.integrate(xt, vt, ft, 0.005, 50)
-        ctx.kernel_timing(1, every=TIMING_EVERY)
+        ctx.kernel_timing(1, every=1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         nreb = ctx.integrate(xt, vt, ft, 0.005, cg_steps)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        f_ms, f_n = ctx.kernel_timing(0 if kind == inputs.CG_TABLE else 2, every=TIMING_EVERY)
+        f_ms, f_n = ctx.kernel_timing(0 if kind == inputs.CG_TABLE else 2, every=1)
         rec = {"steps_per_s": cg_steps / el, "list_rebuilds": nreb, "force_kernel_us": 1e3 * f_ms / max(f_n, 1)}
         if kind != inputs.CG_TABLE:
             ctx.integrate(xt, vt, ft, 0.005, cg_steps)
@@ -576,7 +692,7 @@ def large_heterogeneous(table, params, scale, tw, r_min, steps=200, warmup=20):
         vt = torch.tensor(v, device="cuda")
         ft = torch.empty_like(xt)
         ctx.integrate(xt, vt, ft, wl.dt, warmup)
-        ctx.kernel_timing(1, every=TIMING_EVERY)
+        ctx.kernel_timing(1, every=1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         nreb = ctx.integrate(xt, vt, ft, wl.dt, steps)

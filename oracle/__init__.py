@@ -111,6 +111,8 @@ def lib():
                                              C.POINTER(C.c_int64)]
             L.orc_region_volumes.restype = C.c_int
             L.orc_num_threads.restype = C.c_int
+            L.orc_set_num_threads.argtypes = [C.c_int]
+            L.orc_set_num_threads.restype = None
             _lib = L
     return _lib
 
@@ -329,3 +331,8 @@ def table_eval(coef, lo, hi, r):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    """OpenMP threads of later oracle calls (timing)."""
+    lib().orc_set_num_threads(int(n))

@@ -902,3 +902,13 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Sets the number of OpenMP threads later oracle calls use (timing runs). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
