@@ -153,6 +153,16 @@ adres_status adres_build_verlet(adres_ctx *ctx, const double *x, int64_t *n_pair
  * synchronises once before the force kernel is enqueued. */
 adres_status adres_forces(adres_ctx *ctx, const double *x, double *f, double *energy);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): adres_forces with the same arguments and
+ * results, which itself allocates nothing.  Its energy partials go to a static device array
+ * of the library (one per GPU, 8192 workgroup slots, 256 KiB: at most 524,288 molecules;
+ * larger contexts give ADRES_E_CAPACITY); where adres_forces would grow the neighbour list, a
+ * tile halo or the network's half list, it returns ADRES_E_CAPACITY instead (a call of
+ * adres_forces or adres_build_verlet beforehand sizes them).  Every call on one GPU shares
+ * that array, and calls that overlap on one GPU (other streams or threads) race on it. */
+adres_status adres_forces_noalloc(adres_ctx *ctx, const double *x, double *f, double *energy);
+
 /* n_steps of velocity Verlet (v += F dt/2m; x += v dt; fold; F = F(x); v += F dt/2m)
  * on x, v (device, caller order, updated in place); f receives F(x_final).  The lists
  * are rebuilt whenever a centre of mass has moved more than r_skin/2.  gamma > 0 adds a

@@ -56,6 +56,7 @@ _SIGS = {
     "adres_build_cells": ([C.c_void_p, C.c_void_p], C.c_int),
     "adres_build_verlet": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
     "adres_forces": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "adres_forces_noalloc": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "adres_integrate": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
                          C.c_double, C.c_double, C.c_uint64, C.POINTER(C.c_int32)], C.c_int),
     "adres_integrate_respa": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_int32,
@@ -229,6 +230,13 @@ class Context:
         self._check(self.lib.adres_forces(self.h, self._x(x), self._x(f, "f"), _ptr(e, _f64(), (4,), name="energy")),
                     "adres_forces")
         return (f, e) if energy else f
+
+    def forces_noalloc(self, x, f, energy=None):
+        """adres_forces_noalloc into caller-provided f (and energy [4]); allocates nothing."""
+        self._check(self.lib.adres_forces_noalloc(self.h, self._x(x), self._x(f, "f"),
+                                                  _ptr(energy, _f64(), (4,), name="energy")),
+                    "adres_forces_noalloc")
+        return f
 
     def integrate_respa(self, x, v, f, dt, n_inner, n_outer, gamma=0.0, kT=1.0, seed=0):
         nreb = C.c_int32()

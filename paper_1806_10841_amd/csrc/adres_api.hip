@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -82,6 +83,9 @@ struct adres_ctx {
     uint64_t step_counter = 0;
     int last_interval = 8;
 
+    bool no_alloc = false;   // inside adres_forces_noalloc: capacities may not grow
+    double *scratch_epart = nullptr;   // this device's static energy-partials scratch
+
     int timing = 0;   // 0 off, 1 force kernel, 2 network pre-pass
     int timing_every = 1;
     int64_t timing_count = 0;
@@ -92,6 +96,30 @@ struct adres_ctx {
 };
 
 namespace {
+
+// Energy partials of adres_forces_noalloc (one slot of 4 per force workgroup), in a static
+// device array instead of a context allocation: at most 8192 workgroups, i.e. 524,288
+// molecules (256 KiB).  Each device holds its own copy; its address is taken once per device.
+constexpr int kNoallocBlocks = 8192;
+__device__ __align__(256) double scratch[kNoallocBlocks * 4];
+constexpr int kMaxDevices = 64;
+double *g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mutex;
+
+// The device address of this device's scratch (the current device must be `device`).
+hipError_t scratch_address(int device, double **out)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 adres_status fail(adres_ctx *c, adres_status st, const std::string &msg)
 {
@@ -246,6 +274,8 @@ adres_status build_half_list(adres_ctx *c)
     const int n = c->P.n_mol;
     if (c->cap > 2048) return fail(c, ADRES_E_CAPACITY, "neighbour rows longer than 2048 entries");
     if (c->half_rows_cap < c->cap) {
+        if (c->no_alloc)
+            return fail(c, ADRES_E_CAPACITY, "the half list must grow, which adres_forces_noalloc does not do");
         hipFree(c->pid); hipFree(c->up_pairs); hipFree(c->f_pair);
         c->pid = nullptr; c->up_pairs = nullptr; c->f_pair = nullptr;
         const size_t cap_pairs = (size_t)n * c->cap / 2 + 16;
@@ -296,6 +326,8 @@ adres_status build_list(adres_ctx *c)
         if (st != ADRES_OK) return st;
         if (!c->ctrl_host->overflow) break;
         if (attempt == 3) return fail(c, ADRES_E_CAPACITY, "neighbour list capacity did not converge");
+        if (c->no_alloc)
+            return fail(c, ADRES_E_CAPACITY, "the neighbour list must grow, which adres_forces_noalloc does not do");
         int need = c->ctrl_host->max_count;
         int new_cap = ((need + need / 4 + 8) + 15) & ~15;
         HIPCHK(c, hipFree(c->nbr));
@@ -322,6 +354,8 @@ adres_status build_list(adres_ctx *c)
             return ADRES_OK;
         }
         // a tile's halo outgrew its capacity
+        if (c->no_alloc)
+            return fail(c, ADRES_E_CAPACITY, "a tile halo must grow, which adres_forces_noalloc does not do");
         const int need = c->ctrl_host->max_halo;
         const int limit = halo_capacity_limit(c->P.spm, c->prm.pair_precision);
         if (need > limit)
@@ -386,7 +420,7 @@ adres_status run_forces(adres_ctx *c, ForceArgs a)
     // the sample does not lock onto the rebuild cycle
     hipEvent_t e0 = nullptr, e1 = nullptr;
     bool sample = false;
-    if (c->timing != 0 && (c->timing == 1 || is_mlp(c))) {
+    if (c->timing != 0 && !c->no_alloc && (c->timing == 1 || is_mlp(c))) {
         const uint32_t h = (uint32_t)(c->timing_count++) * 2654435761u;
         sample = (h >> 16) % (uint32_t)c->timing_every == 0;
     }
@@ -475,6 +509,11 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     c->prm = q;
     c->stream = (hipStream_t)hip_stream;
     if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return ADRES_E_HIP;
+    }
+    // the static scratch of adres_forces_noalloc: its address on this device, taken once
+    if (scratch_address(c->device, &c->scratch_epart) != hipSuccess) {
         delete c;
         return ADRES_E_HIP;
     }
@@ -698,9 +737,35 @@ adres_status adres_build_verlet(adres_ctx *c, const double *x, int64_t *n_pairs)
     return ADRES_OK;
 }
 
+namespace {
+
+adres_status forces_impl(adres_ctx *c, const double *x, double *f, double *energy, double *epart);
+
+}  // namespace
+
 adres_status adres_forces(adres_ctx *c, const double *x, double *f, double *energy)
 {
     if (!c || !x || !f) return fail(c, ADRES_E_ARG, "null argument");
+    return forces_impl(c, x, f, energy, c->epart);
+}
+
+adres_status adres_forces_noalloc(adres_ctx *c, const double *x, double *f, double *energy)
+{
+    if (!c || !x || !f) return fail(c, ADRES_E_ARG, "null argument");
+    if (c->epart_blocks > kNoallocBlocks)
+        return fail(c, ADRES_E_CAPACITY, "adres_forces_noalloc takes at most 524288 molecules (" +
+                                             std::to_string(kNoallocBlocks) + " workgroup partials)");
+    if (!c->scratch_epart) return fail(c, ADRES_E_STATE, "no static scratch address for this device");
+    c->no_alloc = true;
+    const adres_status st = forces_impl(c, x, f, energy, c->scratch_epart);
+    c->no_alloc = false;
+    return st;
+}
+
+namespace {
+
+adres_status forces_impl(adres_ctx *c, const double *x, double *f, double *energy, double *epart)
+{
     adres_status st = check_cg_ready(c);
     if (st != ADRES_OK) return st;
     if (!c->list_valid) {
@@ -722,15 +787,17 @@ adres_status adres_forces(adres_ctx *c, const double *x, double *f, double *ener
     ForceArgs a = force_args(c);
     a.f = f;
     a.out_perm = cur(c).perm;
-    a.epart = energy ? c->epart : nullptr;
+    a.epart = energy ? epart : nullptr;
     st = run_forces(c, a);
     if (st != ADRES_OK) return st;
     if (energy) {
-        launch_energy_reduce(c->stream, c->epart, c->epart_blocks, energy);
+        launch_energy_reduce(c->stream, epart, c->epart_blocks, energy);
         HIPCHK(c, hipGetLastError());
     }
     return ADRES_OK;
 }
+
+}  // namespace
 
 namespace {
 
