@@ -157,7 +157,7 @@ def main():
     if not args.no_respa:
         out["respa"] = respa_leg(wl, x_eq, v_eq, args.steps, args.warmup, rec["steps_per_s"])
     if not args.no_anchors:
-        out["self_adjusting_region"] = anchors_leg(wl, x_eq, v_eq, args.steps, args.warmup)
+        out["self_adjusting_region"] = anchors_leg(wl, x, v, args.steps, args.warmup, args.equilibrate)
     if not args.no_cg_compare:
         out["learned_vs_tabulated"] = learned_vs_tabulated(args.cg_steps, not args.no_c5)
 
@@ -399,13 +399,15 @@ def hamiltonian_leg(wl, x, v, steps, warmup):
     }
 
 
-def anchors_leg(wl, x, v, steps, warmup, counts=(16, 256)):
+def anchors_leg(wl, x, v, steps, warmup, equilibrate, counts=(16, 256)):
     """Self-adjusting AT region (Sec. 2.5) on the same molecules: the union of spheres
     (radius 5, hybrid shell 4) around k anchor molecules that move with the simulation,
     weights recomputed from the nearest anchor after every step, with the Langevin
     thermostat (gamma 1, kT 1) that force interpolation needs (Sec. 2.3: no conserved
     energy; molecules switched to atomistic inside moving spheres otherwise heat up).
-    MD steps/s per k."""
+    Started from the lattice (x, v) and melted with its own region for `equilibrate`
+    steps: a state melted with another AT region holds overlapping atoms in what would
+    become atomistic here.  MD steps/s per k."""
     import torch
     from paper_1806_10841_amd import binding, inputs
     out = {}
@@ -416,7 +418,7 @@ def anchors_leg(wl, x, v, steps, warmup, counts=(16, 256)):
         xt = torch.tensor(x, device="cuda")
         vt = torch.tensor(v, device="cuda")
         ft = torch.empty_like(xt)
-        ctx.integrate(xt, vt, ft, wk.dt, warmup, gamma=1.0, kT=1.0, seed=11)
+        ctx.integrate(xt, vt, ft, wk.dt, equilibrate + warmup, gamma=1.0, kT=1.0, seed=11)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         nreb = ctx.integrate(xt, vt, ft, wk.dt, steps, gamma=1.0, kT=1.0, seed=12)
@@ -426,6 +428,7 @@ def anchors_leg(wl, x, v, steps, warmup, counts=(16, 256)):
         wn = w.cpu().numpy()
         ctx.close()
         out[f"anchors_{k}"] = {"steps_per_s": steps / el, "list_rebuilds": nreb,
+                               "equilibration_steps": equilibrate,
                                "fraction_at": float((wn == 1.0).mean()),
                                "fraction_hybrid": float(((wn > 0) & (wn < 1)).mean())}
     return out

@@ -58,7 +58,8 @@ typedef enum {
     ADRES_E_HIP = -3,          /* a HIP runtime call failed */
     ADRES_E_BOX = -4,          /* box shorter than twice the list radius, or over 2^20 cells */
     ADRES_E_CAPACITY = -5,     /* neighbour list could not be grown */
-    ADRES_E_STRETCH = -6,      /* a site is farther than rho_max from its centre of mass */
+    ADRES_E_STRETCH = -6,      /* a site is farther than rho_max + r_skin/2 from its centre
+                                  of mass (no neighbour list can cover it) */
     ADRES_E_NONFINITE = -7,    /* a force or position is NaN or infinite */
     ADRES_E_FENE = -8,         /* a FENE bond reached its maximum extension R0 */
     ADRES_E_TABLE_RANGE = -9,  /* a CG table lookup below the table's first knot */
@@ -97,7 +98,11 @@ typedef struct {
     int32_t chain_len;          /* FENE: beads per chain (runs of consecutive molecules) */
     double  r_skin;             /* Verlet skin; the list is rebuilt when a centre of mass
                                    has moved more than r_skin/2 since the last build */
-    double  rho_max;            /* bound on a site's distance from its centre of mass */
+    double  rho_max;            /* bound on a site's distance from its centre of mass that
+                                   the list radius assumes; a site farther out (thermal
+                                   bond stretch) spends its excess from the molecule's
+                                   r_skin/2 of motion, so the list is rebuilt earlier;
+                                   beyond rho_max + r_skin/2: ADRES_E_STRETCH */
     int32_t pair_precision;     /* 64: FP64 pair arithmetic; 32: FP32 pair arithmetic on
                                    FP64-formed displacements, FP64 sums */
     int32_t scheme;             /* ADRES_SCHEME_FORCE: pair forces w_a w_b F^AT +

@@ -54,6 +54,7 @@ struct adres_ctx {
     float4 *tab = nullptr;
     double *td = nullptr, *td_u = nullptr;   // correction force table and its integrals
     int *anchors = nullptr;                  // anchor molecules of a self-adjusting region
+    int *aslot = nullptr;                    // their slots in the current order
     double4 *near = nullptr;                 // offset from the nearest anchor per slot
     double *anchor_cen = nullptr;            // anchor centres of a caller configuration [K][3]
     int *tile_order = nullptr;               // force kernel dispatch order (per list build)
@@ -187,7 +188,7 @@ adres_status read_ctrl(adres_ctx *c, bool reset_halt = false)
     if (e) {
         HIPCHK(c, hipMemsetAsync(&c->ctrl->err, 0, sizeof(int), c->stream));
         if (e & kErrNonFinite) return fail(c, ADRES_E_NONFINITE, "non-finite position or force");
-        if (e & kErrStretch) return fail(c, ADRES_E_STRETCH, "a site is farther than rho_max from its centre of mass");
+        if (e & kErrStretch) return fail(c, ADRES_E_STRETCH, "a site is farther than rho_max + r_skin/2 from its centre of mass");
         if (e & kErrFene) return fail(c, ADRES_E_FENE, "a FENE bond reached its maximum extension R0");
         if (e & kErrTableRange) return fail(c, ADRES_E_TABLE_RANGE, "CG table lookup below the first knot");
     }
@@ -199,7 +200,7 @@ adres_status gather(adres_ctx *c, const double *x, const double *v, bool check_d
     launch_gather(c->stream, c->P, x, v, cur(c), check_disp ? c->R_ref : nullptr, c->ctrl);
     c->rw_stale = false;
     if (c->P.region == ADRES_REGION_SPHERES)
-        launch_anchor_weights(c->stream, c->P, cur(c).Rw, c->inv_perm, c->ctrl, 0, 0, c->near);
+        launch_anchor_weights(c->stream, c->P, cur(c).Rw, c->inv_perm, c->aslot, 1, c->ctrl, 0, 0, c->near);
     HIPCHK(c, hipGetLastError());
     return ADRES_OK;
 }
@@ -219,7 +220,7 @@ adres_status resort(adres_ctx *c, bool with_v)
     launch_permute(c->stream, c->P, c->new_from, src, dst, c->inv_perm, c->R_ref, with_v);
     // the nearest-anchor offsets are per slot: recompute them in the new order
     if (c->P.region == ADRES_REGION_SPHERES)
-        launch_anchor_weights(c->stream, c->P, dst.Rw, c->inv_perm, c->ctrl, 0, 0, c->near);
+        launch_anchor_weights(c->stream, c->P, dst.Rw, c->inv_perm, c->aslot, 1, c->ctrl, 0, 0, c->near);
     HIPCHK(c, hipGetLastError());
     c->pos = 1 - c->pos;
     c->ord = 1 - c->ord;
@@ -583,6 +584,8 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     P.R02 = q.r0_bond * q.r0_bond;
     P.chain_len = std::max(1, q.chain_len);
     P.rho_max = q.rho_max;
+    P.rho_lim = q.rho_max + 0.5 * q.r_skin;
+    P.half_skin = 0.5 * q.r_skin;
     P.half_skin2 = 0.25 * q.r_skin * q.r_skin;
 
     // Morton order of the cells
@@ -686,7 +689,7 @@ void adres_destroy(adres_ctx *c)
     hipFree(c->R_ref); hipFree(c->inv_perm); hipFree(c->cell_rank);
     hipFree(c->count); hipFree(c->start); hipFree(c->fill); hipFree(c->new_from); hipFree(c->scan_tiles);
     hipFree(c->nbr); hipFree(c->cnt); hipFree(c->hid); hipFree(c->hn); hipFree(c->lnbr); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
-    hipFree(c->td); hipFree(c->td_u); hipFree(c->anchors); hipFree(c->near); hipFree(c->anchor_cen); hipFree(c->tile_order); hipFree(c->mcost); hipFree(c->stencil);
+    hipFree(c->td); hipFree(c->td_u); hipFree(c->anchors); hipFree(c->aslot); hipFree(c->near); hipFree(c->anchor_cen); hipFree(c->tile_order); hipFree(c->mcost); hipFree(c->stencil);
     hipFree(c->mlp); hipFree(c->mlp_w2); hipFree(c->mlp_w2q); hipFree(c->mlp_fp8s); hipFree(c->cnt_up); hipFree(c->up_off); hipFree(c->up_scratch);
     hipFree(c->pid); hipFree(c->up_pairs); hipFree(c->f_pair);
     hipFree(c->adam_m); hipFree(c->adam_v); hipFree(c->grad); hipFree(c->loss); hipFree(c->res_part);
@@ -845,7 +848,7 @@ adres_status integrate_impl(adres_ctx *c, double *x, double *v, double *f, doubl
                 launch_kick_drift(c->stream, c->P, in.x, in.v, c->f, out.x, out.Rw, c->R_ref, in.perm, c->ctrl, k,
                                   sa);
                 if (c->P.region == ADRES_REGION_SPHERES)
-                    launch_anchor_weights(c->stream, c->P, out.Rw, c->inv_perm, c->ctrl, k, 1, c->near);
+                    launch_anchor_weights(c->stream, c->P, out.Rw, c->inv_perm, c->aslot, 0, c->ctrl, k, 1, c->near);
                 HIPCHK(c, hipGetLastError());
             } else {
                 ForceArgs a = force_args(c);
@@ -869,7 +872,7 @@ adres_status integrate_impl(adres_ctx *c, double *x, double *v, double *f, doubl
                 st = run_forces(c, a);
                 if (st != ADRES_OK) return st;
                 if (gk < n_steps && c->P.region == ADRES_REGION_SPHERES) {
-                    launch_anchor_weights(c->stream, c->P, out.Rw, c->inv_perm, c->ctrl, k, 1, c->near);
+                    launch_anchor_weights(c->stream, c->P, out.Rw, c->inv_perm, c->aslot, 0, c->ctrl, k, 1, c->near);
                     HIPCHK(c, hipGetLastError());
                 }
             }
@@ -1037,6 +1040,7 @@ adres_status adres_set_anchors(adres_ctx *c, const int32_t *mols, int32_t k)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (!c->anchors) {
         HIPCHK(c, dalloc(&c->anchors, (size_t)kMaxAnchors));
+        HIPCHK(c, dalloc(&c->aslot, (size_t)kMaxAnchors));
         HIPCHK(c, dalloc(&c->anchor_cen, (size_t)kMaxAnchors * 3));
     }
     HIPCHK(c, hipMemcpy(c->anchors, mols, sizeof(int) * k, hipMemcpyHostToDevice));

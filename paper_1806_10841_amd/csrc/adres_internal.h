@@ -56,8 +56,11 @@ struct DevParams {
     int scheme;      // ADRES_SCHEME_*
     double k_bond, r0_bond, R02;
     int chain_len;
-    double rho_max;
-    double half_skin2;
+    // the list reach assumes every site within rho_max of its centre and leaves r_skin/2 per
+    // molecule for motion; a site farther out spends the same budget (list_stale), up to
+    // rho_lim = rho_max + r_skin/2, the largest distance any list can cover
+    double rho_max, rho_lim;
+    double half_skin, half_skin2;
     // cubic CG table
     const float4 *tab;
     int tab_n;
@@ -393,6 +396,17 @@ __device__ __forceinline__ void close_kick(double v[3], const double F[3], doubl
     for (int d = 0; d < 3; ++d) v[d] = v[d] + F[d] * dt * inv_2m;
 }
 
+// Whether a molecule's list entries may no longer hold every pair in reach: its centre
+// lies sqrt(d2) from where the list was built and its farthest site rh from its centre.
+// The list covers rho_max per site plus r_skin/2 per molecule of motion; a site beyond
+// rho_max takes its excess out of the motion budget.
+__device__ __forceinline__ bool list_stale(const DevParams &P, double d2, double rh)
+{
+    const double ex = rh - P.rho_max;
+    if (!(ex > 0.0)) return d2 > P.half_skin2;
+    return sqrt(d2) + ex > P.half_skin;
+}
+
 // Centre and weight of a molecule at slot t into Rw, with the stretch / non-finite
 // checks and the displacement check against R_ref (which lowers ctrl->halt to
 // halt_value).
@@ -408,13 +422,13 @@ __device__ __forceinline__ void store_molecule(const DevParams &P, const double 
 #pragma unroll
     for (int k = 0; k < SPM; ++k) finite = finite && isfinite(p[k][0]) && isfinite(p[k][1]) && isfinite(p[k][2]);
     if (!finite) atomicOr(&ctrl->err, kErrNonFinite);
-    if (SPM > 1 && rh > P.rho_max) atomicOr(&ctrl->err, kErrStretch);
+    if (SPM > 1 && rh > P.rho_lim) atomicOr(&ctrl->err, kErrStretch);
     if (R_ref) {
         const double4 r0 = R_ref[t];
         double q0 = mi(R[0] - r0.x, P.box[0], P.inv_box[0]);
         double q1 = mi(R[1] - r0.y, P.box[1], P.inv_box[1]);
         double q2 = mi(R[2] - r0.z, P.box[2], P.inv_box[2]);
-        if (dist2_exact(q0, q1, q2) > P.half_skin2) atomicMin(&ctrl->halt, halt_value);
+        if (list_stale(P, dist2_exact(q0, q1, q2), SPM > 1 ? rh : 0.0)) atomicMin(&ctrl->halt, halt_value);
     }
 }
 
@@ -561,8 +575,12 @@ void launch_td_update(hipStream_t s, const DevParams &P, double *td, double *td_
 // length into near; anchors located through inv_perm; skipped like the step kernels once
 // a chunk has halted) or for caller-order centres (com [3][n] -> w)
 constexpr int kMaxAnchors = 1024;
-void launch_anchor_weights(hipStream_t s, const DevParams &P, double4 *Rw, const int *inv_perm, Ctrl *ctrl,
-                           int step, int check_halt, double4 *near);
+constexpr int kAnchorGrid = 16;                                       // anchor cells per axis, at most
+constexpr int kAnchorCells = kAnchorGrid * kAnchorGrid * kAnchorGrid;
+// aslot [n_anchors]: the anchors' slots, refreshed from inv_perm when refresh is set (after
+// every reorder), read otherwise
+void launch_anchor_weights(hipStream_t s, const DevParams &P, double4 *Rw, const int *inv_perm, int *aslot,
+                           int refresh, Ctrl *ctrl, int step, int check_halt, double4 *near);
 void launch_anchor_weights_caller(hipStream_t s, const DevParams &P, const double *com, double *w);
 
 }  // namespace adres

@@ -132,7 +132,7 @@ __device__ __forceinline__ bool maybe_atomistic(const DevParams &P, const double
 {
     if (P.region == ADRES_REGION_ALL_CG) return false;
     if (P.region != ADRES_REGION_SLAB_X && P.region != ADRES_REGION_SPHERE) return true;
-    const double reach = P.scheme == ADRES_SCHEME_HAMILTONIAN ? P.rc_at + 2.0 * P.rho_max + 1e-6 : 0.0;
+    const double reach = P.scheme == ADRES_SCHEME_HAMILTONIAN ? P.rc_at + 2.0 * P.rho_lim + 1e-6 : 0.0;
     double q[3];
     return res_distance(P, R, q) < P.d_end + reach;
 }
@@ -337,8 +337,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
         const double r2c = dist2_exact(D0, D1, D2);
         if (ww > 0.0) {
             // no atom pair of the tile can be within the cutoff beyond this centre
-            // distance (every site lies within rho_max of its centre, a checked invariant)
-            const double bound = P.rc_at + rha + P.rho_max + 1e-6;
+            // distance (every site lies within rho_lim of its centre, a checked invariant)
+            const double bound = P.rc_at + rha + P.rho_lim + 1e-6;
             if (r2c < bound * bound) {
                 const PT pww = (PT)ww;
                 if constexpr (kOff) {
@@ -625,12 +625,12 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
             const double rh = sqrt(m2);
             if (a.Rw_out) a.Rw_out[t] = make_double4(R0, R1, R2, res_weight(P, R));
             if (!(isfinite(R0) && isfinite(R1) && isfinite(R2))) atomicOr(&a.ctrl->err, kErrNonFinite);
-            if (SPM > 1 && rh > P.rho_max) atomicOr(&a.ctrl->err, kErrStretch);
+            if (SPM > 1 && rh > P.rho_lim) atomicOr(&a.ctrl->err, kErrStretch);
             const double4 rr = lref;
             const double q0 = mi(R0 - rr.x, P.box[0], P.inv_box[0]);
             const double q1 = mi(R1 - rr.y, P.box[1], P.inv_box[1]);
             const double q2 = mi(R2 - rr.z, P.box[2], P.inv_box[2]);
-            if (dist2_exact(q0, q1, q2) > P.half_skin2) atomicMin(&a.ctrl->halt, a.step);
+            if (list_stale(P, dist2_exact(q0, q1, q2), SPM > 1 ? rh : 0.0)) atomicMin(&a.ctrl->halt, a.step);
         }
     }
 

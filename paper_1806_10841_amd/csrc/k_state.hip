@@ -5,6 +5,7 @@
 // 64 * s * 8 consecutive bytes of a row per access.
 #include "adres_internal.h"
 
+#include <algorithm>
 #include <climits>
 
 namespace adres {
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void k_weights_caller(DevParams P, const do
 #pragma unroll
     for (int k = 0; k < SPM; ++k) finite = finite && isfinite(p[k][0]) && isfinite(p[k][1]) && isfinite(p[k][2]);
     if (!finite) atomicOr(&ctrl->err, kErrNonFinite);
-    if (SPM > 1 && rh > P.rho_max) atomicOr(&ctrl->err, kErrStretch);
+    if (SPM > 1 && rh > P.rho_lim) atomicOr(&ctrl->err, kErrStretch);
 }
 
 template <int SPM>
@@ -351,41 +352,160 @@ __global__ __launch_bounds__(kBlock) void k_td_update(DevParams P, double *__res
     }
 }
 
-// Self-adjusting AT region (Sec. 2.5): every workgroup stages the anchors' centres in LDS,
-// then each molecule takes the minimum-image distance to the nearest one,
-// d = sqrt(min_k r_k^2), and its weight.  Morton-ordered state: the anchors' slots come
-// from inv_perm and only the w component of Rw is written (centres are read as three
-// scalars, so the stores never overlap a read).
+// Self-adjusting AT region (Sec. 2.5): each molecule's weight from the minimum-image
+// distance to the nearest anchor centre, d = min_k |R - A_k|.  Only distances up to reach
+// (the end of the hybrid shell, or of the correction table if that is longer) change a
+// result: beyond it the weight is 0, the correction force 0 and its potential the table's
+// held value.  Every workgroup bins the anchors' centres in LDS on a grid of cells at least
+// reach wide (nc[d] per axis, at most kAnchorGrid), a counting sort by cell; a molecule
+// then visits the cells within one of its own (all of them along an axis of fewer than
+// three cells), which hold every anchor within reach of it: nine rows of cells, each as
+// at most two runs of consecutive cells, shared by the molecule's four lanes and merged by
+// a quad reduction.  Equally near anchors resolve to the lowest anchor index, so within
+// reach the result is the same, bit for bit, as a search over all anchors in index order;
+// beyond it the distance found is only known to exceed reach (infinite if no anchor was
+// visited).  Morton-ordered state: the anchors' slots (aslot) change only when the state is
+// reordered; a launch with refresh takes them from inv_perm and workgroup 0 stores them
+// for the launches that follow.  Only the w component of Rw is written (centres are read as
+// three scalars, so the stores never overlap a read).  Dynamic LDS: anchor_lds_bytes.
+__device__ __forceinline__ int anchor_cell(double r, double L, double inv_L, int nc)
+{
+    const double u = r - L * floor(r * inv_L);   // wrapped into [0, L] (the cell only has to be
+    const int c = (int)(u * (nc * inv_L));        // the same function for both sides)
+    return c < 0 ? 0 : (c < nc ? c : nc - 1);
+}
+
+constexpr int kAnchorLanes = 4;
+constexpr int kAnchorMols = kBlock / kAnchorLanes;
+
+__host__ __device__ inline size_t anchor_lds_bytes(int K, int n_cells)
+{
+    return (size_t)K * 24 + (size_t)(2 * n_cells + 1) * 4 + (size_t)K * 4 + 16;
+}
+
 __global__ __launch_bounds__(kBlock) void k_anchor_weights(DevParams P, double4 *Rw, const int *__restrict__ inv_perm,
-                                                           Ctrl *ctrl, int step, int check_halt,
-                                                           double4 *__restrict__ near)
+                                                           int *aslot, int refresh, Ctrl *ctrl, int step,
+                                                           int check_halt, double4 *__restrict__ near, int3 nc)
 {
 #pragma clang fp contract(off)
-    if (check_halt && step > ctrl->halt) return;
-    __shared__ double cen[kMaxAnchors][3];
+    extern __shared__ __align__(16) unsigned char als[];
+    __shared__ int wsum[kBlock / 64];
     const int K = P.n_anchors;
+    const int n_cells = nc.x * nc.y * nc.z;
+    double(*cen)[3] = reinterpret_cast<double(*)[3]>(als);
+    int *ccount = reinterpret_cast<int *>(als + (size_t)K * 24);
+    int *cstart = ccount + n_cells;
+    unsigned short *sorted = reinterpret_cast<unsigned short *>(cstart + n_cells + 1);
+    unsigned short *cell_of = sorted + K;
+    const int q = threadIdx.x & (kAnchorLanes - 1);
+    const int t = blockIdx.x * kAnchorMols + threadIdx.x / kAnchorLanes;
+    const bool active = t < P.n_mol;
+    double *me = reinterpret_cast<double *>(Rw + (active ? t : 0));
+    const double R0 = me[0], R1 = me[1], R2 = me[2];
+    const int halt = check_halt ? ctrl->halt : INT_MAX;
+    for (int c = threadIdx.x; c < n_cells; c += kBlock) ccount[c] = 0;
+    __syncthreads();
     for (int k = threadIdx.x; k < K; k += kBlock) {
-        const double *r = reinterpret_cast<const double *>(Rw + inv_perm[P.anchors[k]]);
-        cen[k][0] = r[0];
-        cen[k][1] = r[1];
-        cen[k][2] = r[2];
+        const int sl = refresh ? inv_perm[P.anchors[k]] : aslot[k];
+        if (refresh && blockIdx.x == 0) aslot[k] = sl;
+        const double *r = reinterpret_cast<const double *>(Rw + sl);
+        const double a0 = r[0], a1 = r[1], a2 = r[2];
+        cen[k][0] = a0;
+        cen[k][1] = a1;
+        cen[k][2] = a2;
+        const int c = (anchor_cell(a2, P.box[2], P.inv_box[2], nc.z) * nc.y +
+                       anchor_cell(a1, P.box[1], P.inv_box[1], nc.y)) * nc.x +
+                      anchor_cell(a0, P.box[0], P.inv_box[0], nc.x);
+        cell_of[k] = (unsigned short)c;
+        atomicAdd(&ccount[c], 1);
+    }
+    // the same decision in every workgroup, before a barrier it would skip: only an
+    // earlier launch sets halt
+    if (step > halt) return;
+    __syncthreads();
+    // exclusive scan of the counts: each thread sums a run of consecutive cells
+    {
+        const int run = (n_cells + kBlock - 1) / kBlock;
+        const int c0 = threadIdx.x * run;
+        int s = 0;
+        for (int i = 0; i < run; ++i) s += c0 + i < n_cells ? ccount[c0 + i] : 0;
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        int incl = s;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        int before = incl - s;
+        for (int w = 0; w < wv; ++w) before += wsum[w];
+        for (int i = 0; i < run && c0 + i < n_cells; ++i) {
+            cstart[c0 + i] = before;
+            before += ccount[c0 + i];
+        }
+        if (threadIdx.x == 0) cstart[n_cells] = K;
     }
     __syncthreads();
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= P.n_mol) return;
-    double *me = reinterpret_cast<double *>(Rw + t);
-    const double R0 = me[0], R1 = me[1], R2 = me[2];
+    for (int k = threadIdx.x; k < K; k += kBlock) {
+        const int c = cell_of[k];
+        sorted[cstart[c] + atomicSub(&ccount[c], 1) - 1] = (unsigned short)k;
+    }
+    __syncthreads();
+    // the cells to visit along each axis: c-1, c, c+1 (periodic), or all of a short axis;
+    // along x as at most two runs of consecutive cells
+    const int cx = anchor_cell(R0, P.box[0], P.inv_box[0], nc.x);
+    const int cy = anchor_cell(R1, P.box[1], P.inv_box[1], nc.y);
+    const int cz = anchor_cell(R2, P.box[2], P.inv_box[2], nc.z);
+    int xa, xb, xc = 0, xd = 0;
+    if (nc.x < 3) { xa = 0; xb = nc.x; }
+    else if (cx == 0) { xa = 0; xb = 2; xc = nc.x - 1; xd = nc.x; }
+    else if (cx == nc.x - 1) { xa = nc.x - 2; xb = nc.x; xc = 0; xd = 1; }
+    else { xa = cx - 1; xb = cx + 2; }
+    const int ny = nc.y < 3 ? nc.y : 3, nz = nc.z < 3 ? nc.z : 3;
+    auto nb = [](int c, int n, int i) {   // the i-th visited cell along an axis
+        if (n < 3) return i;
+        const int v = c - 1 + i;
+        return v < 0 ? v + n : (v >= n ? v - n : v);
+    };
     double best = INFINITY, b0 = 0.0, b1 = 0.0, b2 = 0.0;
-    for (int k = 0; k < K; ++k) {
-        const double q0 = mi(R0 - cen[k][0], P.box[0], P.inv_box[0]);
-        const double q1 = mi(R1 - cen[k][1], P.box[1], P.inv_box[1]);
-        const double q2 = mi(R2 - cen[k][2], P.box[2], P.inv_box[2]);
-        const double r2 = dist2_exact(q0, q1, q2);
-        if (r2 < best) {   // the first of equally near anchors
-            best = r2;
-            b0 = q0; b1 = q1; b2 = q2;
+    int bk = INT_MAX;
+    if (active) {
+        for (int r = q; r < 9; r += kAnchorLanes) {   // this lane's rows of the nine
+            const int iz = r / 3, iy = r - 3 * iz;
+            if (iz >= nz || iy >= ny) continue;
+            const int row = (nb(cz, nc.z, iz) * nc.y + nb(cy, nc.y, iy)) * nc.x;
+            for (int h = 0; h < 2; ++h) {
+                if (h && xc == xd) break;
+                const int j0 = cstart[row + (h ? xc : xa)], j1 = cstart[row + (h ? xd : xb)];
+                for (int j = j0; j < j1; ++j) {
+                    const int k = sorted[j];
+                    const double q0 = mi(R0 - cen[k][0], P.box[0], P.inv_box[0]);
+                    const double q1 = mi(R1 - cen[k][1], P.box[1], P.inv_box[1]);
+                    const double q2 = mi(R2 - cen[k][2], P.box[2], P.inv_box[2]);
+                    const double r2 = dist2_exact(q0, q1, q2);
+                    if (r2 < best || (r2 == best && k < bk)) {   // the first of equally near
+                        best = r2;
+                        bk = k;
+                        b0 = q0; b1 = q1; b2 = q2;
+                    }
+                }
+            }
         }
     }
+    // the least (r2, k) of the quad's four lanes, in every lane
+#pragma unroll
+    for (int m = 1; m < kAnchorLanes; m <<= 1) {
+        const double ob = __shfl_xor(best, m), o0 = __shfl_xor(b0, m), o1 = __shfl_xor(b1, m),
+                     o2 = __shfl_xor(b2, m);
+        const int ok = __shfl_xor(bk, m);
+        if (ob < best || (ob == best && ok < bk)) {
+            best = ob;
+            bk = ok;
+            b0 = o0; b1 = o1; b2 = o2;
+        }
+    }
+    if (!active || q != 0) return;
     const double d = sqrt(best);
     me[3] = weight_of_distance(P, d);
     if (near) near[t] = make_double4(b0, b1, b2, d);
@@ -534,10 +654,19 @@ void launch_td_update(hipStream_t s, const DevParams &P, double *td, double *td_
     k_td_update<<<1, kBlock, 0, s>>>(P, td, td_u, counts, n_frames, prefactor, vol, n_vol);
 }
 
-void launch_anchor_weights(hipStream_t s, const DevParams &P, double4 *Rw, const int *inv_perm, Ctrl *ctrl,
-                           int step, int check_halt, double4 *near)
+void launch_anchor_weights(hipStream_t s, const DevParams &P, double4 *Rw, const int *inv_perm, int *aslot,
+                           int refresh, Ctrl *ctrl, int step, int check_halt, double4 *near)
 {
-    k_anchor_weights<<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, Rw, inv_perm, ctrl, step, check_halt, near);
+    // reach: where the weight and the correction force stop changing (the table's end
+    // only while one is installed), padded by 2^-20 of itself; cells at least that wide
+    double reach = P.d_end;
+    if (P.td_n > 0) reach = std::max(reach, P.td_hi);
+    reach *= 1.0 + 0x1p-20;
+    int g[3];
+    for (int d = 0; d < 3; ++d) g[d] = std::max(1, std::min(kAnchorGrid, (int)std::floor(P.box[d] / reach)));
+    const int blocks = (P.n_mol + kAnchorMols - 1) / kAnchorMols;
+    k_anchor_weights<<<blocks, kBlock, anchor_lds_bytes(P.n_anchors, g[0] * g[1] * g[2]), s>>>(
+        P, Rw, inv_perm, aslot, refresh, ctrl, step, check_halt, near, make_int3(g[0], g[1], g[2]));
 }
 
 void launch_anchor_weights_caller(hipStream_t s, const DevParams &P, const double *com, double *w)

@@ -64,6 +64,32 @@ def test_weights(dev, name, k):
     assert np.abs(w.cpu().numpy() - w_o).max() <= 1e-15
 
 
+@pytest.mark.parametrize("d_at,d_hy,clustered", [(6.0, 4.0, False), (9.0, 5.0, False), (2.5, 2.0, True)])
+def test_forces_anchor_grid_shapes(dev, d_at, d_hy, clustered):
+    """The step's nearest-anchor search bins the anchors in cells at least as wide as the
+    hybrid shell's end: two cells per axis (reach 10 in a 25.8 box), a single cell (reach
+    14), and 64 anchors packed around the box centre (the molecules nearest to it, as the
+    atoms of one macromolecule would be), many to a cell.  FP64 forces against the oracle."""
+    wl = _wl("small_sphere", d_at=d_at, d_hy=d_hy)
+    x, _ = inputs.make_state(wl)
+    if clustered:
+        L = wl.box[0]
+        p = x.T.reshape(wl.n_mol, wl.sites_per_mol, 3)
+        d = p - p[:, :1]
+        d -= L * np.round(d / L)
+        com = p[:, 0] + d.mean(axis=1)
+        off = _min_image(com - np.array(wl.center), L)
+        an = np.sort(np.argsort((off ** 2).sum(axis=1))[:64]).astype(np.int32)
+    else:
+        an = inputs.anchor_molecules(wl.n_mol, 9, 2)
+    fo, amag, _, st = oracle.Model(wl, anchors=an).forces(x)
+    _, w_o, _, _ = oracle.Model(wl, anchors=an).weights(x)
+    assert st == 0 and ((w_o > 0) & (w_o < 1)).any()
+    f = _ctx(wl, an).forces(_t(x, dev))
+    torch.cuda.synchronize()
+    _assert_close(f.cpu().numpy(), fo, amag, 1e-12, f"d_at {d_at} clustered {clustered}")
+
+
 @pytest.mark.parametrize("name,k,prec", [("small_sphere", 9, 64), ("c1", 5, 64), ("tiny_slab", 3, 64),
                                          ("small_sphere", 9, 32)])
 def test_forces(dev, name, k, prec):

@@ -72,3 +72,66 @@ def test_setup_refuses(dev, change):
     with pytest.raises(binding.AdresError) as ei:
         _ctx(inputs.workload("tiny_slab").with_(**change))
     assert ei.value.status == -1
+
+
+# ---------------------------------------------------------------- stretched molecules
+def _stretched_pair(rho_a, gap=1.05):
+    """Two unit-edge tetrahedra on a line in a 12-sigma box, a vertex of each pointing at
+    the other, `gap` apart (inside the WCA cutoff 2^(1/6)): molecule A's vertex pushed out
+    along the line until it lies rho_a from A's centre of mass.  With rho_a above rho_max
+    the pair's centre distance exceeds rc_at + rho_B + rho_max, so a kernel that took
+    rho_max as every neighbour's extent would drop the pair on B's side."""
+    r = np.sqrt(3.0 / 8.0)                  # circumradius of the unit-edge tetrahedron
+    p = r * np.sqrt(8.0 / 9.0)
+    body = np.array([[r, 0.0, 0.0]] + [[-r / 3.0, p * np.cos(a), p * np.sin(a)]
+                                        for a in (0.0, 2 * np.pi / 3, 4 * np.pi / 3)])
+    t = (rho_a - r) / 0.75                  # moving one vertex by t moves the centre by t/4
+    a = body.copy()
+    a[0, 0] += t
+    D = gap + 2.0 * r + t                   # B's centre: its vertex at A's vertex + gap
+    b = -body + np.array([D, 0.0, 0.0])
+    sites = np.concatenate([a, b]) + np.array([6.0 - D / 2.0, 6.0, 6.0])
+    wl = inputs.Workload(name="stretched_pair", n_mol=2, sites_per_mol=4, box=(12.0, 12.0, 12.0),
+                         site_mass=(1.0, 1.0, 1.0, 1.0), region=inputs.REGION_ALL_AT,
+                         center=(6.0, 6.0, 6.0), d_at=2.0, d_hy=3.0)
+    return wl, np.ascontiguousarray(sites.T)
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_site_beyond_rho_max_within_the_skin(dev, prec):
+    """A site up to r_skin/2 beyond rho_max is covered (its excess is taken from the skin):
+    forces against the oracle, including the atom pair that only the stretched site reaches;
+    and a short FP64 trajectory of the pair (its rebuilds follow the stretch)."""
+    wl, x = _stretched_pair(0.9)
+    wl = wl.with_(pair_precision=prec)
+    assert wl.rho_max < 0.9 < wl.rho_max + wl.r_skin / 2
+    m = oracle.Model(wl)
+    fo, amag, eo, _ = m.forces(x)
+    # the inter-molecular atom pair is there: without it, A and B feel only their bonds
+    fb, _, _, _ = oracle.Model(wl.with_(eps_at=0.0)).forces(x)
+    assert np.abs(fo - fb).max() > 1.0
+    f, e = _ctx(wl).forces(_t(x, dev), energy=True)
+    torch.cuda.synchronize()
+    tol = 1e-12 if prec == 64 else 1e-5
+    err = np.abs(f.cpu().numpy() - fo).max(axis=0)
+    assert (err <= tol * np.maximum(amag, 1e-300)).all(), err / amag
+    assert np.abs(f.cpu().numpy().sum(axis=1)).max() <= 1e-9 * amag.max()   # Newton's third law
+    if prec == 64:
+        v = np.zeros_like(x)
+        xo, vo, _, _, _ = m.vv(x, v, wl.dt, 40)
+        xt, vt = _t(x, dev), _t(v, dev)
+        ft = torch.empty_like(xt)
+        _ctx(wl).integrate(xt, vt, ft, wl.dt, 40)
+        torch.cuda.synchronize()
+        assert np.abs(_min_image(xt.cpu().numpy() - xo, wl.box[0])).max() < 1e-9
+        assert np.abs(vt.cpu().numpy() - vo).max() < 1e-7
+
+
+def test_site_beyond_the_skin_budget_refused(dev):
+    """Farther than rho_max + r_skin/2 no list can cover the site: ADRES_E_STRETCH."""
+    from paper_1806_10841_amd import binding
+    wl, x = _stretched_pair(1.0)
+    assert 1.0 > wl.rho_max + wl.r_skin / 2
+    with pytest.raises(binding.AdresError) as ei:
+        _ctx(wl).forces(_t(x, dev))
+    assert ei.value.status == -6

@@ -293,10 +293,12 @@ def test_capacity_growth(dev):
 
 
 def test_error_stretch(dev):
+    """A site beyond rho_max + r_skin/2 (0.95): moving it by 2.5 moves it 1.875 from where it
+    was relative to the shifted centre, at least 1.875 - 0.62 from the centre."""
     from paper_1806_10841_amd import binding
     wl = inputs.workload("c1")
     x, _ = inputs.make_state(wl)
-    x[0, 5] += 0.9
+    x[0, 5] += 2.5
     ctx = _ctx(wl)
     with pytest.raises(binding.AdresError) as ei:
         ctx.forces(_t(x, dev))
