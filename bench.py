@@ -474,16 +474,73 @@ def respa_leg(wl, x, v, steps, warmup, vv_steps_per_s):
     return out
 
 
-def tdforce_leg(wl, x, v, steps, n_iter=8, steps_per_iter=10000, sample_every=50, n_bins=14,
-                equilibrate=40000):
+def smooth_counts(counts, width, h):
+    """A binned histogram smoothed with a Gaussian of the given width (bin width h; the
+    weights renormalised where the kernel leaves the table), rounded back to whole counts
+    for the library's update (half a count against ~1e5 per bin).  width 0: unchanged."""
+    counts = np.asarray(counts, dtype=np.int64)
+    if width <= 0:
+        return counts
+    k = np.arange(len(counts))
+    W = np.exp(-0.5 * (((k[:, None] - k[None, :]) * h) / width) ** 2)
+    W /= W.sum(axis=1, keepdims=True)
+    return np.rint(W @ counts.astype(np.float64)).astype(np.int64)
+
+
+def number_fluctuation_s0(frames, box, lo, width, sides=(5, 8, 11, 14, 20)):
+    """Long-wavelength limit of the structure factor, S(0) = rho k_B T kappa_T, from the
+    variance-to-mean ratio of molecule counts in cubes tiling a slab of the box: x in
+    [lo, lo + width) (periodic in x too; lo measured from the box's low corner), all of y
+    and z.  Cubes of side L_y / m for m in `sides` (those that fit at least once across the
+    slab); the ratio S_l approaches S(0) as a / l for a cube of side l (its surface term),
+    so S(0) is the intercept of a least-squares line in 1 / l.  frames: centres (3, n) per
+    frame, any image.  Returns (S0, {l: S_l})."""
+    Lx, Ly, Lz = box
+    out = {}
+    for m in sides:
+        l = Ly / m
+        nx = int(width // l)
+        if nx < 1:
+            continue
+        cnts = []
+        for com in frames:
+            u = (com[0] - lo) % Lx
+            ok = u < nx * l
+            ix = np.floor(u[ok] / l).astype(np.int64)
+            iy = np.floor((com[1][ok] % Ly) / l).astype(np.int64) % m
+            mz = int(round(Lz / l))
+            iz = np.floor((com[2][ok] % Lz) / (Lz / mz)).astype(np.int64) % mz
+            cnts.append(np.bincount((ix * m + iy) * mz + iz, minlength=nx * m * mz))
+        c = np.concatenate(cnts).astype(np.float64)
+        out[l] = float(c.var() / c.mean())
+    ls = np.array(sorted(out))
+    A = np.stack([np.ones_like(ls), 1.0 / ls], axis=1)
+    s0 = float(np.linalg.lstsq(A, np.array([out[l] for l in ls]), rcond=None)[0][0])
+    return s0, out
+
+
+# Refinement schedule of the thermodynamic force: (iterations, prefactor as a fraction of
+# k_B T / (rho_0 S(0)), Gaussian smoothing width of the profile).  The full prefactor cancels
+# the long-wavelength deviation in one step (linear response: an external potential change
+# dU shifts the density by -rho_0 S(k) dU / k_B T at wavenumber k), but a dense liquid's S(k)
+# grows far above S(0) toward its first peak, where that gain would diverge: the coarse phase
+# takes half of it on a profile smoothed over 1.5 sigma, the next ones smaller fractions on
+# finer profiles to remove the layering the coarse phase cannot see.
+TD_SCHEDULE = ((6, 0.5, 1.5), (5, 0.1, 0.5), (5, 0.05, 0.0))
+
+
+def tdforce_leg(wl, x, v, steps, n_bins=14, relax=4000, sample_steps=16000, sample_every=40,
+                equilibrate=40000, s0_frames=100):
     """Thermodynamic force (Sec. 2.4) on the same workload: a correction table over the
-    hybrid layer plus one sigma on each side, refined n_iter times from density profiles
-    sampled every sample_every steps of a Langevin run (gamma 1, kT 1) that first melts
-    the lattice start for `equilibrate` steps, with the ideal-gas prefactor kT / rho_0
-    (the force that balances a measured density gradient in an ideal gas).  Reports the largest deviation |rho / rho_0 - 1| over the
-    bins before the first and after the last refinement (sampling noise included), the
-    wall time per refinement cycle, the density-profile kernel's cost, and MD steps/s of
-    the plain step with the final correction installed."""
+    hybrid layer plus one sigma on each side, refined from density profiles of a Langevin
+    run (gamma 1, kT 1) that first melts the lattice start for `equilibrate` steps.  The
+    prefactor comes from the measured compressibility: S(0) from number fluctuations in the
+    AT and the CG region (the larger, the more compressible phase, sets k_B T / (rho_0 S(0))),
+    then the iterations of TD_SCHEDULE, each `relax` steps after the table change and then
+    `sample_steps` sampled every `sample_every`.  Reports the largest deviation
+    |rho / rho_0 - 1| over all bins and over the hybrid bins per iteration and of a final
+    sample, the wall time per iteration, the density-profile kernel's cost, and MD steps/s
+    of the plain step with the final correction installed."""
     import torch
     from paper_1806_10841_amd import binding
     lo, hi = wl.d_at - 1.0, wl.d_at + wl.d_hy + 1.0
@@ -496,31 +553,56 @@ def tdforce_leg(wl, x, v, steps, n_iter=8, steps_per_iter=10000, sample_every=50
     h = (hi - lo) / n_bins
     vol = 2.0 * h * wl.box[1] * wl.box[2]
     counts = torch.zeros(n_bins, dtype=torch.int64, device="cuda")
-    devs, devs_hy = [], []
     centres = lo + (np.arange(n_bins) + 0.5) * h
     hy = (centres > wl.d_at) & (centres < wl.d_at + wl.d_hy)
     seed = 7
     ctx.integrate(xt, vt, ft, wl.dt, equilibrate, gamma=1.0, kT=1.0, seed=seed)   # melt the lattice
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    prof_s = 0.0
-    for it in range(n_iter + 1):
+    # S(0) of the two phases from frames of the uncorrected run
+    frames = []
+    for k in range(s0_frames):
+        seed += 1
+        ctx.integrate(xt, vt, ft, wl.dt, 50, gamma=1.0, kT=1.0, seed=seed)
+        com, _ = ctx.weights(xt)
+        frames.append(com.cpu().numpy())
+    c0 = wl.center[0]
+    s0_at, sl_at = number_fluctuation_s0(frames, wl.box, c0 - (wl.d_at - 2.0), 2.0 * (wl.d_at - 2.0))
+    cg_lo = c0 + wl.d_at + wl.d_hy + 2.0
+    s0_cg, sl_cg = number_fluctuation_s0(frames, wl.box, cg_lo, wl.box[0] - 2.0 * (wl.d_at + wl.d_hy + 2.0))
+    s0 = max(s0_at, s0_cg)
+    p_full = 1.0 / (rho0 * s0)   # k_B T = 1
+
+    def sample():
+        nonlocal seed
+        seed += 1
+        ctx.integrate(xt, vt, ft, wl.dt, relax, gamma=1.0, kT=1.0, seed=seed)
         counts.zero_()
-        frames = steps_per_iter // sample_every
-        for _ in range(frames):
+        nfr = sample_steps // sample_every
+        for _ in range(nfr):
+            seed += 1
             ctx.integrate(xt, vt, ft, wl.dt, sample_every, gamma=1.0, kT=1.0, seed=seed)
-            torch.cuda.synchronize()
             tp = time.perf_counter()
             ctx.density_profile(xt, counts)
             torch.cuda.synchronize()
-            prof_s += time.perf_counter() - tp
-        rho = counts.cpu().numpy() / (frames * vol)
-        devs.append(float(np.abs(rho / rho0 - 1.0).max()))
-        devs_hy.append(float(np.abs(rho[hy] / rho0 - 1.0).max()))
-        if it < n_iter:
-            ctx.tdforce_update(counts, frames, 1.0 / rho0)
+            prof[0] += time.perf_counter() - tp
+            prof[1] += 1
+        c = counts.cpu().numpy()
+        dev = c / (nfr * vol) / rho0 - 1.0
+        return c, nfr, dev
+
     torch.cuda.synchronize()
-    cycle_s = (time.perf_counter() - t0) / (n_iter + 1)
+    t0 = time.perf_counter()
+    prof = [0.0, 0]
+    devs, devs_hy, iters = [], [], 0
+    for n_it, frac, width in TD_SCHEDULE:
+        for _ in range(n_it):
+            c, nfr, dev = sample()
+            devs.append(float(np.abs(dev).max()))
+            devs_hy.append(float(np.abs(dev[hy]).max()))
+            ctx.tdforce_update(torch.tensor(smooth_counts(c, width, h), device="cuda"), nfr, frac * p_full)
+            iters += 1
+    _, _, dev = sample()   # the profile with the final table
+    torch.cuda.synchronize()
+    cycle_s = (time.perf_counter() - t0) / (iters + 1)
     table = ctx.get_tdforce()
     # plain NVE steps with the final correction installed
     ctx.integrate(xt, vt, ft, wl.dt, 100)
@@ -531,15 +613,22 @@ def tdforce_leg(wl, x, v, steps, n_iter=8, steps_per_iter=10000, sample_every=50
     sps = steps / (time.perf_counter() - t0)
     ctx.close()
     return {
-        "bins": n_bins, "range": [lo, hi], "iterations": n_iter,
-        "steps_per_iteration": steps_per_iter, "sample_every": sample_every,
+        "bins": n_bins, "range": [lo, hi], "hybrid_bins": int(hy.sum()),
+        "s0_at": s0_at, "s0_cg": s0_cg, "s0_by_cube_side_at": {f"{l:.3f}": s for l, s in sl_at.items()},
+        "s0_by_cube_side_cg": {f"{l:.3f}": s for l, s in sl_cg.items()},
+        "prefactor_full": p_full,
+        "schedule": [{"iterations": n, "prefactor": f * p_full, "smoothing_sigma": w} for n, f, w in TD_SCHEDULE],
+        "relax_steps": relax, "sample_steps": sample_steps, "sample_every": sample_every,
         "max_density_deviation_before": devs[0],
-        "max_density_deviation_after": devs[-1],
+        "max_density_deviation_hybrid_bins_before": devs_hy[0],
+        "max_density_deviation_after": float(np.abs(dev).max()),
+        "max_density_deviation_hybrid_bins_after": float(np.abs(dev[hy]).max()),
+        "density_deviation_after": [float(d) for d in dev],
         "max_density_deviation_per_iteration": devs,
         "max_density_deviation_hybrid_bins_per_iteration": devs_hy,
         "equilibration_steps": equilibrate,
         "seconds_per_iteration": cycle_s,
-        "density_profile_call_us": 1e6 * prof_s / ((n_iter + 1) * (steps_per_iter // sample_every)),
+        "density_profile_call_us": 1e6 * prof[0] / max(prof[1], 1),
         "steps_per_s_with_correction": sps,
         "final_table": [float(t) for t in table],
     }

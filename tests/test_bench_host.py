@@ -39,3 +39,44 @@ def test_traffic_follows_the_kernel_digest(monkeypatch):
         assert t is None
     monkeypatch.setattr(bench, "kernel_source_digest", lambda: "0" * 64)
     assert bench._measured_traffic() is None
+
+
+def test_number_fluctuation_s0_of_an_ideal_gas():
+    """Independent uniform points (an ideal gas) have S(0) = 1: the cube estimator and its
+    1/l extrapolation find it within a few percent, in a slab of the box and in one that
+    wraps around the periodic x boundary."""
+    import numpy as np
+    bench = _bench_module()
+    rng = np.random.default_rng(3)
+    L = 86.0
+    frames = [rng.uniform(0.0, L, size=(3, 64000)) for _ in range(20)]
+    s0, per = bench.number_fluctuation_s0(frames, (L, L, L), 30.0, 25.0)
+    assert len(per) >= 3 and abs(s0 - 1.0) < 0.05, (s0, per)
+    s0w, _ = bench.number_fluctuation_s0(frames, (L, L, L), 70.0, 40.0)
+    assert abs(s0w - 1.0) < 0.05
+
+
+def test_number_fluctuation_s0_of_a_lattice_is_small():
+    """A perfect lattice (one point per unit cell, cubes of whole cells) has no number
+    fluctuation at all."""
+    import numpy as np
+    bench = _bench_module()
+    g = np.arange(40, dtype=np.float64) + 0.5
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    com = np.stack([X.ravel(), Y.ravel(), Z.ravel()])
+    s0, per = bench.number_fluctuation_s0([com], (40.0, 40.0, 40.0), 0.0, 40.0, sides=(4, 5, 8))
+    assert max(per.values()) == 0.0 and abs(s0) < 1e-12
+
+
+def test_smooth_counts():
+    """Width 0 leaves the counts alone; a constant profile and the interior of a linear ramp
+    (a symmetric kernel away from the ends) come back unchanged."""
+    import numpy as np
+    bench = _bench_module()
+    c = np.array([5, 9, 2, 7], dtype=np.int64)
+    assert (bench.smooth_counts(c, 0.0, 0.5) == c).all()
+    flat = np.full(14, 100000, dtype=np.int64)
+    assert (bench.smooth_counts(flat, 1.5, 0.5) == flat).all()
+    ramp = 100000 + 1000 * np.arange(40, dtype=np.int64)
+    out = bench.smooth_counts(ramp, 1.0, 0.5)
+    assert np.abs(out[10:30] - ramp[10:30]).max() <= 1
