@@ -209,11 +209,12 @@ adres_status resort(adres_ctx *c, bool with_v)
 {
     const StateBufs src = cur(c);
     const StateBufs dst = view(c, 1 - c->pos, 1 - c->ord);
-    if (c->rw_stale) {
-        launch_centres(c->stream, c->P, src.x, src.Rw, c->ctrl);
+    if (c->rw_stale) {   // the step kernels moved the positions without storing centres
+        launch_centres_keys(c->stream, c->P, c->G, c->cell_rank, src.x, src.Rw, src.key, c->count);
         c->rw_stale = false;
+    } else {
+        launch_cell_keys(c->stream, c->P, c->G, c->cell_rank, src.Rw, src.key, c->count);
     }
-    launch_cell_keys(c->stream, c->P, c->G, c->cell_rank, src.Rw, src.key, c->count);
     launch_scan_cells(c->stream, c->count, c->G.n_cells, c->start, c->fill, c->scan_tiles);
     launch_scatter_slots(c->stream, c->P.n_mol, src.key, c->start, c->fill, c->new_from);
     launch_sort_within_cells(c->stream, c->G.n_cells, c->start, src.perm, c->new_from);
@@ -584,7 +585,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     P.R02 = q.r0_bond * q.r0_bond;
     P.chain_len = std::max(1, q.chain_len);
     P.rho_max = q.rho_max;
-    P.rho_lim = q.rho_max + 0.5 * q.r_skin;
+    P.rho_lim = q.sites_per_mol > 1 ? q.rho_max + 0.5 * q.r_skin : 0.0;   // (a single site is its centre)
     P.half_skin = 0.5 * q.r_skin;
     P.half_skin2 = 0.25 * q.r_skin * q.r_skin;
 

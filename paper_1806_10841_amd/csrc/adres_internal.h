@@ -58,7 +58,8 @@ struct DevParams {
     int chain_len;
     // the list reach assumes every site within rho_max of its centre and leaves r_skin/2 per
     // molecule for motion; a site farther out spends the same budget (list_stale), up to
-    // rho_lim = rho_max + r_skin/2, the largest distance any list can cover
+    // rho_lim = rho_max + r_skin/2, the largest distance any list can cover (0 for
+    // single-site molecules)
     double rho_max, rho_lim;
     double half_skin, half_skin2;
     // cubic CG table
@@ -466,8 +467,9 @@ void launch_kick_drift(hipStream_t s, const DevParams &P, const double *x_in, do
                        double *x_out, double4 *Rw_out, const double4 *R_ref, const int *perm, Ctrl *ctrl, int step,
                        const StepArgs &st);
 // centres and weights of the sorted state from its positions (before a reorder, when the
-// step kernels have not kept them)
-void launch_centres(hipStream_t s, const DevParams &P, const double *x, double4 *Rw, Ctrl *ctrl);
+// step kernels have not kept them) and the cell keys of launch_cell_keys, in one pass
+void launch_centres_keys(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank, const double *x,
+                         double4 *Rw, int *key, int *count);
 void launch_reset_halt(hipStream_t s, Ctrl *ctrl);
 void launch_publish(hipStream_t s, Ctrl *ctrl, CtrlPub *pub, unsigned seq, bool reset);
 void launch_map_cg(hipStream_t s, const DevParams &P, const double *x, const double *f, double *com, double *fmap);

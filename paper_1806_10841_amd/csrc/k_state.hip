@@ -75,10 +75,13 @@ __global__ __launch_bounds__(kBlock) void k_gather(DevParams P, const double *__
 }
 
 // Centres and weights of the sorted state from its positions (no checks: the step kernel
-// that wrote the positions made them).
+// that wrote the positions made them), fused with the cell keys of the reorder that
+// follows (what k_cell_keys derives from Rw): one pass over the positions instead of two.
+// The weight of a self-adjusting region is written by its own pass and kept.
 template <int SPM>
-__global__ __launch_bounds__(kBlock) void k_centres(DevParams P, const double *__restrict__ x,
-                                                    double4 *__restrict__ Rw)
+__global__ __launch_bounds__(kBlock) void k_centres_keys(DevParams P, Grid G, const int *__restrict__ cell_rank,
+                                                         const double *__restrict__ x, double4 *__restrict__ Rw,
+                                                         int *__restrict__ key, int *__restrict__ count)
 {
     int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= P.n_mol) return;
@@ -86,9 +89,14 @@ __global__ __launch_bounds__(kBlock) void k_centres(DevParams P, const double *_
     load_sites<SPM>(x, P.n_sites, t, p);
     double R[3], rh;
     mol_com<SPM>(P, p, R, rh);
-    // the weight of a self-adjusting region is written by its own pass; keep it
     const double w = P.region == ADRES_REGION_SPHERES ? Rw[t].w : res_weight(P, R);
     Rw[t] = make_double4(R[0], R[1], R[2], w);
+    const int cx = cell_coord(R[0], G.inv_len[0], G.n[0]);
+    const int cy = cell_coord(R[1], G.inv_len[1], G.n[1]);
+    const int cz = cell_coord(R[2], G.inv_len[2], G.n[2]);
+    const int k = cell_rank[cx + G.n[0] * (cy + G.n[1] * cz)];
+    key[t] = k;
+    atomicAdd(&count[k], 1);
 }
 
 template <int SPM>
@@ -612,10 +620,13 @@ void launch_kick_drift(hipStream_t s, const DevParams &P, const double *x_in, do
                                   P, x_in, v, f, x_out, Rw_out, R_ref, perm, ctrl, step, st)));
 }
 
-void launch_centres(hipStream_t s, const DevParams &P, const double *x, double4 *Rw, Ctrl *)
+void launch_centres_keys(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank, const double *x,
+                         double4 *Rw, int *key, int *count)
 {
-    ADRES_SPM_DISPATCH(P.spm, (k_centres<S_><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, x, Rw)));
+    ADRES_SPM_DISPATCH(P.spm, (k_centres_keys<S_><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, G, cell_rank, x, Rw,
+                                                                                         key, count)));
 }
+
 
 void launch_reset_halt(hipStream_t s, Ctrl *ctrl) { k_reset_halt<<<1, 64, 0, s>>>(ctrl); }
 
