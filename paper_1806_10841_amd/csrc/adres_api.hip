@@ -42,6 +42,7 @@ struct adres_ctx {
     // tile halos of the force kernel and the rows as local halo indices
     int *hid = nullptr, *hn = nullptr;
     uint16_t *lnbr = nullptr;
+    uint8_t *tperm = nullptr;                // each tile's molecules by falling cost
     int hcap = 0, lcap = 0;
     bool rw_stale = false;   // the step kernels moved the positions without storing centres
     Ctrl *ctrl = nullptr;
@@ -263,8 +264,8 @@ adres_status alloc_halo(adres_ctx *c, int hcap)
 
 void launch_halo(adres_ctx *c)
 {
-    launch_halo_build(c->stream, c->P.n_mol, c->nbr, c->cnt, c->cap, c->hcap, c->lcap, c->hid, c->hn, c->lnbr,
-                      c->ctrl);
+    launch_halo_build(c->stream, c->P.n_mol, c->nbr, c->cnt, c->cap, c->hcap, c->lcap, c->mcost, c->hid, c->hn,
+                      c->lnbr, c->tperm, c->ctrl);
 }
 
 // Every unordered pair of the Verlet list once (t < u) and, for every list entry, the
@@ -405,6 +406,7 @@ ForceArgs force_args(adres_ctx *c)
     a.hcap = c->hcap;
     a.lnbr = c->lnbr;
     a.lcap = c->lcap;
+    a.tperm = c->tperm;
     a.perm = S.perm;
     a.inv_perm = c->inv_perm;
     a.ctrl = c->ctrl;
@@ -643,6 +645,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     c->epart_blocks = force_blocks(n);
     ok = ok && dalloc(&c->epart, 4 * (size_t)c->epart_blocks) == hipSuccess;
     ok = ok && dalloc(&c->hn, (size_t)c->epart_blocks) == hipSuccess;
+    ok = ok && dalloc(&c->tperm, (size_t)c->epart_blocks * kHaloTile) == hipSuccess;
     ok = ok && alloc_halo(c, std::min(320, halo_capacity_limit(q.sites_per_mol, q.pair_precision))) == ADRES_OK;
     ok = ok && dalloc(&c->tile_order, (size_t)c->epart_blocks) == hipSuccess &&
          dalloc(&c->mcost, ((size_t)n + 15) / 16 * 16) == hipSuccess &&   // whole 16-entry runs
@@ -689,7 +692,7 @@ void adres_destroy(adres_ctx *c)
     hipFree(c->f);
     hipFree(c->R_ref); hipFree(c->inv_perm); hipFree(c->cell_rank);
     hipFree(c->count); hipFree(c->start); hipFree(c->fill); hipFree(c->new_from); hipFree(c->scan_tiles);
-    hipFree(c->nbr); hipFree(c->cnt); hipFree(c->hid); hipFree(c->hn); hipFree(c->lnbr); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
+    hipFree(c->nbr); hipFree(c->cnt); hipFree(c->hid); hipFree(c->hn); hipFree(c->lnbr); hipFree(c->tperm); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
     hipFree(c->td); hipFree(c->td_u); hipFree(c->anchors); hipFree(c->aslot); hipFree(c->near); hipFree(c->anchor_cen); hipFree(c->tile_order); hipFree(c->mcost); hipFree(c->stencil);
     hipFree(c->mlp); hipFree(c->mlp_w2); hipFree(c->mlp_w2q); hipFree(c->mlp_fp8s); hipFree(c->cnt_up); hipFree(c->up_off); hipFree(c->up_scratch);
     hipFree(c->pid); hipFree(c->up_pairs); hipFree(c->f_pair);

@@ -499,10 +499,13 @@ void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const i
 // every other slot of its molecules' rows once; hn[tile] is the count.  lnbr holds each row
 // as local halo indices (uint16), entry k of slot t at t * lcap + (k % 4) * (lcap / 4) + k / 4,
 // so lane q of a molecule's quad finds its entries q, q + 4, ... contiguous.  A halo larger
-// than hcap sets overflow bit 1, max_halo and halt = -1.
+// than hcap sets overflow bit 1, max_halo and halt = -1.  tperm[tile * 64 + j] is the tile's
+// j-th molecule by falling cost (mcost from the list build; ties and the empty tail of a
+// short last tile in slot order): the force kernel's thread groups take them in that order,
+// so each wavefront's sixteen molecules have similar row work.
 constexpr int kHaloTile = 64;
 void launch_halo_build(hipStream_t s, int n_mol, const int *nbr, const int *cnt, int cap, int hcap, int lcap,
-                       int *hid, int *hn, uint16_t *lnbr, Ctrl *ctrl);
+                       const unsigned *mcost, int *hid, int *hn, uint16_t *lnbr, uint8_t *tperm, Ctrl *ctrl);
 // LDS bytes of the force kernel's halo staging per halo molecule, and the largest halo
 // capacity that fits a workgroup's LDS
 int halo_stride_bytes(int spm, int pair_precision);
@@ -528,6 +531,7 @@ struct ForceArgs {
     int hcap;
     const uint16_t *lnbr;   // rows as local halo indices
     int lcap;
+    const uint8_t *tperm;   // each tile's molecules by falling cost (launch_halo_build)
     const int *perm, *inv_perm;   // slot -> caller, caller -> slot
     int mode;
     double *f;                    // kModeForce / kModeClose: output forces

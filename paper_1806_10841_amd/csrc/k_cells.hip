@@ -476,20 +476,34 @@ static_assert(kHaloHash == 1 << 11, "hash width");
 
 __global__ __launch_bounds__(kBlock) void k_halo_build(int n_mol, const int *__restrict__ nbr,
                                                        const int *__restrict__ cnt, int cap, int hcap, int lcap,
-                                                       int *__restrict__ hid, int *__restrict__ hn,
-                                                       uint16_t *__restrict__ lnbr, Ctrl *ctrl)
+                                                       const unsigned *__restrict__ mcost, int *__restrict__ hid,
+                                                       int *__restrict__ hn, uint16_t *__restrict__ lnbr,
+                                                       uint8_t *__restrict__ tperm, Ctrl *ctrl)
 {
     __shared__ int keys[kHaloHash];
     __shared__ int vals[kHaloHash];
     __shared__ int dkey[kHaloHash], dpos[kHaloHash];   // the distinct slots, compacted
     __shared__ int wave_tot[kBlock / 64];
     __shared__ int lost;
+    __shared__ unsigned tcost[kHaloTile];
     const int b = blockIdx.x;
     const int base = b * kHaloTile;
     const int n_home = min(kHaloTile, n_mol - base);
     for (int i = threadIdx.x; i < kHaloHash; i += kBlock) keys[i] = -1;
     if (threadIdx.x == 0) lost = 0;
+    // (the tail of a short last tile costs 0: it sorts last; valid costs are at least 4)
+    if (threadIdx.x < kHaloTile) tcost[threadIdx.x] = (int)threadIdx.x < n_home ? mcost[base + threadIdx.x] : 0u;
     __syncthreads();
+    // the tile's molecules by falling cost, ties in slot order
+    if (threadIdx.x < kHaloTile) {
+        const unsigned cme = tcost[threadIdx.x];
+        int rank = 0;
+        for (int j = 0; j < kHaloTile; ++j) {
+            const unsigned o = tcost[j];
+            rank += (o > cme || (o == cme && j < (int)threadIdx.x)) ? 1 : 0;
+        }
+        tperm[(int64_t)b * kHaloTile + rank] = (uint8_t)threadIdx.x;
+    }
     const int m = threadIdx.x >> 2, q = threadIdx.x & 3;
     const int t = base + m;
     // a row that overflowed holds only cap entries; the list is rebuilt before any use
@@ -581,10 +595,10 @@ __global__ __launch_bounds__(kBlock) void k_halo_build(int n_mol, const int *__r
 }  // namespace
 
 void launch_halo_build(hipStream_t s, int n_mol, const int *nbr, const int *cnt, int cap, int hcap, int lcap,
-                       int *hid, int *hn, uint16_t *lnbr, Ctrl *ctrl)
+                       const unsigned *mcost, int *hid, int *hn, uint16_t *lnbr, uint8_t *tperm, Ctrl *ctrl)
 {
     const int tiles = (n_mol + kHaloTile - 1) / kHaloTile;
-    k_halo_build<<<tiles, kBlock, 0, s>>>(n_mol, nbr, cnt, cap, hcap, lcap, hid, hn, lnbr, ctrl);
+    k_halo_build<<<tiles, kBlock, 0, s>>>(n_mol, nbr, cnt, cap, hcap, lcap, mcost, hid, hn, lnbr, tperm, ctrl);
 }
 
 

@@ -215,45 +215,36 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     const int64_t ns = P.n_sites;
     const int slot = xcd_block();
     const int blk = a.tile_order ? a.tile_order[slot] : slot;
-    const int gid = blk * kBlock + threadIdx.x;
-    const int t = gid / kLanes, q = gid % kLanes;
+    const int q = threadIdx.x % kLanes;
+    // the tile's molecules by falling cost: each wavefront's sixteen have similar row work
+    // (ml: the molecule's place in the tile, its LDS record and its slot's offset)
+    const int ml = a.tperm[(int64_t)blk * kHaloTile + threadIdx.x / kLanes];
+    const int t = blk * kHaloTile + ml;
     const bool valid = t < n;
     const int tt = valid ? t : n - 1;
 
     // the home sites (FP64) for the bonds and the integration, and the home molecules' rho
     __shared__ double sx[kBlock / kLanes][SPM][3];
     __shared__ float srho[kBlock / kLanes];
-    const int ml = threadIdx.x / kLanes;
-    // every load that does not depend on another (own site, row length and the first local
-    // row entries, the halo count and the first halo ids) is issued before the first wait:
-    // the prologue costs one memory round trip, the halo gather a second.  Velocities and
-    // the reference centre are requested after the pair loop, which keeps the workgroup's
-    // LDS within a quarter of the compute unit's (four workgroups per compute unit)
-    double lx[3] = {0.0, 0.0, 0.0};
-    if (q < SPM) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) lx[d] = a.x[d * ns + (int64_t)tt * SPM + q];
-    }
+    // every load that does not depend on another (the tile order, the halo count and the
+    // first halo ids, the halt index) is issued before the first wait; the second round
+    // brings the halo's sites (the tile's own molecules first, whose sites also fill sx)
+    // and each molecule's row length and first local-row entries.  Velocities and the
+    // reference centre are requested after the pair loop, which keeps the workgroup's LDS
+    // within a quarter of the compute unit's (four workgroups per compute unit)
+    const int hn = min(a.hn[blk], a.hcap);
+    const int *hid = a.hid + (int64_t)blk * a.hcap;
+    const int la = threadIdx.x, lb = la + kBlock;
+    const int ida = hid[min(la, a.hcap - 1)], idb = hid[min(lb, a.hcap - 1)];
     // (a row longer than cap exists only after an overflow, which stops every launch)
     const int cnt = valid ? min(a.cnt[tt], a.cap) : 0;
     const int nq = cnt > q ? (cnt - q + 3) >> 2 : 0;   // this lane's entries k = q + 4 i
     const uint16_t *lrow = a.lnbr + (int64_t)tt * a.lcap + q * (a.lcap >> 2);
     uint4 ch = make_uint4(0u, 0u, 0u, 0u);
     if (nq > 0) ch = *reinterpret_cast<const uint4 *>(lrow);
-    const int hn = min(a.hn[blk], a.hcap);
-    // the first two halo molecules of this thread: their slot ids travel with the prologue
-    const int *hid = a.hid + (int64_t)blk * a.hcap;
-    const int la = threadIdx.x, lb = la + kBlock;
-    const int ida = hid[min(la, a.hcap - 1)], idb = hid[min(lb, a.hcap - 1)];
     // the same decision in every wave: only an earlier launch can set halt below this step
     // (this one sets it to its own step at the lowest), so no workgroup stops at a barrier
     if (a.check_halt && a.step > halt) return;
-
-    // own sites to LDS first, which frees their registers for the halo's sites
-    if (q < SPM) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) sx[ml][q][d] = lx[d];
-    }
 
     // stage A: one thread per halo molecule (the tile's own molecules first), two molecules
     // per thread with all their sites requested before the first use: the halo arrives in
@@ -266,6 +257,12 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
         double pa[SPM][3], pb[SPM][3];
         load_molecule<SPM>(a.x, ns, ua, pa);
         if (lb < hn) load_molecule<SPM>(a.x, ns, ub, pb);
+        if (la < kHaloTile) {   // one of the tile's own molecules (record la, slot base + la)
+#pragma unroll
+            for (int k = 0; k < SPM; ++k)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) sx[la][k][d] = pa[k][d];
+        }
         if (la < hn) {
             const double rh = stage_molecule<SPM, PT>(P, hs + la * St::kStride, pa, la < kHaloTile);
             if (la < kHaloTile) srho[la] = (float)rh;
