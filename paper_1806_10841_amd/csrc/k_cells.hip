@@ -608,13 +608,28 @@ namespace {
 // workgroup per XCD range of tiles (64 molecules each, the force kernel's workgroup).  A
 // tile's cost estimate is the sum over its four wavefronts of the largest per-molecule
 // cost in each (lanes of a wavefront run in lockstep); the list build stores the
-// per-molecule costs (row length, times SPM^2 when the molecule can be atomistic).  Tiles are ranked by falling cost (ties by index) so
-// that the heaviest tiles of an XCD are dispatched first, one per compute unit, instead of
-// piling up on the compute units that receive neighbouring parts of the slab.  Any order
+// per-molecule costs (row length, times SPM^2 when the molecule can be atomistic).  Tiles are
+// ranked by falling cost (ties by index) within chunks of kTileRound consecutive tiles, so
+// that the heaviest tiles of an XCD round are dispatched first, one per compute unit,
+// instead of piling up on the compute units that receive neighbouring parts of the slab.  Any order
 // is a valid permutation; ranges longer than kTileSortMax keep the identity.
 constexpr int kTileSortMax = 4096;
 constexpr int kTileThreads = 1024;
 constexpr int kTileRankMax = 512;    // longer ranges are sorted (bitonic) instead of ranked
+
+// About as many force workgroups as one XCD holds at once (32 compute units x 4): tiles are
+// ranked by cost within consecutive chunks of this many, so that when a range takes several
+// rounds (large systems) each round stays a compact piece of space whose halos share the
+// XCD's L2, while the heaviest tiles of a round still start first.
+constexpr int kTileRound = 128;
+
+// Sort key of tile i of a range (falling order): its chunk (earlier first), its cost (as
+// summed below, at most 4 x (2048 x 16 + 4) < 2^20), then the lower index; distinct, nonzero.
+__device__ __forceinline__ unsigned long long tile_key(unsigned cost, int i)
+{
+    const unsigned long long chunk = 4095u - (unsigned)(i / kTileRound);   // (i < kTileSortMax)
+    return (chunk << 52) | ((unsigned long long)(cost & 0xFFFFFu) << 32) | (unsigned)(~(unsigned)i);
+}
 
 __global__ __launch_bounds__(kTileThreads) void k_tile_order(int n_mol, const unsigned *__restrict__ mcost, int n_tiles,
                                                             int *__restrict__ order)
@@ -665,12 +680,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_order(int n_mol, const un
         }
     }
     __syncthreads();
-    // keys (cost, then the lower index first) are distinct and nonzero
+    // keys (chunk, cost, then the lower index first) are distinct and nonzero
     if (len <= kTileRankMax) {
         // short ranges: rank of tile i = number of larger keys, counted by all threads in
         // C chunks of the j range per tile, partial counts added with LDS atomics
-        for (int i = threadIdx.x; i < len; i += kTileThreads)
-            key[i] = ((unsigned long long)tcost[i] << 32) | (unsigned)(~(unsigned)i);
+        for (int i = threadIdx.x; i < len; i += kTileThreads) key[i] = tile_key(tcost[i], i);
         for (int i = threadIdx.x; i < len; i += kTileThreads) tcost[i] = 0u;   // now the ranks
         __syncthreads();
         const int C = len < kTileThreads ? kTileThreads / len : 1;
@@ -693,7 +707,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_order(int n_mol, const un
     int P2 = 1;
     while (P2 < len) P2 <<= 1;
     for (int i = threadIdx.x; i < P2; i += kTileThreads)
-        key[i] = i < len ? ((unsigned long long)tcost[i] << 32) | (unsigned)(~(unsigned)i) : 0ull;
+        key[i] = i < len ? tile_key(tcost[i], i) : 0ull;
     __syncthreads();
     for (int k = 2; k <= P2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
