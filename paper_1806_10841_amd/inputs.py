@@ -214,7 +214,7 @@ def workload(name: str) -> Workload:
         return Workload("c3", 200000, 1, (L, L, L), (1.0,), REGION_ALL_AT, (L / 2, L / 2, L / 2),
                         0.0, 0.0, bond_kind=BOND_FENE, k_bond=30.0, r0_bond=1.5, chain_len=200,
                         rho_max=0.0, pair_precision=32, dt=0.01, n_steps=1000,
-                        gamma=0.5, kT=1.0, seed=1003)
+                        gamma=0.5, kT=1.0, seed=1003, r_skin=0.5)   # (no skin stated: a tuning choice)
     if name == "c4":
         L = (64000 / 0.1) ** (1.0 / 3.0)
         return Workload("c4", 256000, 1, (2 * L, 2 * L, L), (4.0,), REGION_ALL_CG,

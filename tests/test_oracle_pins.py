@@ -222,8 +222,8 @@ class TestPairList:
     def test_list_radius(self):
         m = oracle.Model(inputs.workload("c2"))
         assert abs(m.r_list() - (max(2.31 * 2 ** (1 / 6), 2 ** (1 / 6) + 1.6) + 0.3)) < 1e-15
-        m = oracle.Model(inputs.workload("c3"))
-        assert abs(m.r_list() - (2 ** (1 / 6) + 0.3)) < 1e-15
+        m = oracle.Model(inputs.workload("c3"))   # (single beads, skin 0.5)
+        assert abs(m.r_list() - (2 ** (1 / 6) + 0.5)) < 1e-15
         m = oracle.Model(inputs.workload("c4"))
         assert abs(m.r_list() - 3.3) < 1e-15
 
