@@ -224,7 +224,8 @@ def workload(name: str) -> Workload:
     if name == "c5":
         L = (1000000 / 0.1) ** (1.0 / 3.0)
         return Workload("c5", 1000000, 4, (L, L, L), tetra_mass, REGION_SPHERE, (L / 2, L / 2, L / 2),
-                        12.0, 5.0, cg_kind=CG_TABLE, pair_precision=32, n_steps=500, seed=1005)
+                        12.0, 5.0, cg_kind=CG_TABLE, pair_precision=32, n_steps=500, seed=1005,
+                        r_skin=0.5)   # (no skin stated: a tuning choice)
     # scaled-down variants for CPU tests (same physics, fewer molecules)
     if name == "tiny_slab":      # 4^3 tetrahedra, every resolution present
         L = 4 * 2.15
