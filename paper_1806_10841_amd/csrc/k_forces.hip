@@ -367,33 +367,34 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
                             inside |= (r2 < rct ? 1u : 0u) << (SPM * ii + jj);
                         }
                     }
-                    // second pass: the WCA force only for the pairs inside, site by site, so
-                    // that a wavefront runs the force block as often as its busiest lane has
-                    // pairs for that site instead of once per pair position; a site's terms
-                    // against one neighbour molecule (at most SPM) are summed in FP32 first
+                    // second pass: the exact test and the WCA force for the pairs the mask
+                    // kept, in one loop over them (a wavefront runs it as often as its
+                    // busiest lane has pairs), each term added to its site's FP64 sum; my
+                    // site's offset is read from my LDS record by index
+                    const float *myo = reinterpret_cast<const float *>(mine + St::kOffOff);
+                    auto hof = [myo](int j) { return SPM > 1 ? myo[j] : 0.0f; };   // (single site: 0)
+                    unsigned m = inside;
+                    while (m) {
+                        const int b = __builtin_ctz(m);
+                        m &= m - 1u;
+                        const int ii = b / SPM, jj = b % SPM;
+                        const float dx = Df0 + (hof(3 * ii) - nof(3 * jj));
+                        const float dy = Df1 + (hof(3 * ii + 1) - nof(3 * jj + 1));
+                        const float dz = Df2 + (hof(3 * ii + 2) - nof(3 * jj + 2));
+                        const float r2 = (dx * dx + dy * dy) + dz * dz;
+                        if (!(r2 < rcf)) continue;
+                        PT uu = PT(0);
+                        const PT c = pww * wca_f_over_r<PT>((PT)r2, sig2A, epsA, uu, ENERGY || hy_home);
+                        const double vx = (double)(c * dx), vy = (double)(c * dy), vz = (double)(c * dz);
 #pragma unroll
-                    for (int ii = 0; ii < SPM; ++ii) {
-                        unsigned m = (inside >> (SPM * ii)) & ((1u << SPM) - 1u);
-                        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
-                        while (m) {
-                            const int jj = __builtin_ctz(m);
-                            m &= m - 1u;
-                            const float dx = Df0 + (hoff[ii][0] - nof(3 * jj));
-                            const float dy = Df1 + (hoff[ii][1] - nof(3 * jj + 1));
-                            const float dz = Df2 + (hoff[ii][2] - nof(3 * jj + 2));
-                            const float r2 = (dx * dx + dy * dy) + dz * dz;
-                            if (!(r2 < rcf)) continue;
-                            PT uu = PT(0);
-                            const PT c = pww * wca_f_over_r<PT>((PT)r2, sig2A, epsA, uu, ENERGY || hy_home);
-                            s0 += c * dx;
-                            s1 += c * dy;
-                            s2 += c * dz;
-                            if (ENERGY) uat += 0.5 * (HAM ? me.w : ww) * (double)uu;
-                            if (HAM) vat += 0.5 * (double)uu;
-                        }
-                        acc[ii][0] += (double)s0;
-                        acc[ii][1] += (double)s1;
-                        acc[ii][2] += (double)s2;
+                        for (int k2 = 0; k2 < SPM; ++k2)
+                            if (k2 == ii) {
+                                acc[k2][0] += vx;
+                                acc[k2][1] += vy;
+                                acc[k2][2] += vz;
+                            }
+                        if (ENERGY) uat += 0.5 * (HAM ? me.w : ww) * (double)uu;
+                        if (HAM) vat += 0.5 * (double)uu;
                     }
                 } else {
                     const double *xj = reinterpret_cast<const double *>(nrec + St::kRawOff);
