@@ -145,6 +145,12 @@ def main():
         "copy_GBps": copy_gbs,
         "frac_of_copy": rec["achieved_GBps"] / copy_gbs,
     }
+    valu = _measured_valu_insts() if wl.name == "c2" else None
+    # the bound the kernel actually meets: its VALU instructions (counters) at the issue rate
+    # of every SIMD, against the same launch time
+    out["roofline"]["valu_issue"] = None if valu is None else {
+        "wave_instructions_per_launch": valu, "peak_wave_instructions_per_s": VALU_WAVE_INSTS_PER_S,
+        "issue_us": 1e6 * valu / VALU_WAVE_INSTS_PER_S, "frac": valu / VALU_WAVE_INSTS_PER_S / avg_s}
     x_eq, v_eq = rec.pop("_state")
 
     if not args.no_c1_c3 and wl.name == "c2":
@@ -666,10 +672,10 @@ def _copy_bandwidth_gbs(torch, nbytes=1 << 30, reps=10):
     return 2 * nbytes / best / 1e9
 
 
-def _measured_traffic():
-    """HBM bytes per launch of the force kernel from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings), or None when there is
-    none or the kernel's sources changed since the counters were taken."""
+def _pmc_fields():
+    """Fields of the committed rocprofv3 counter summary of the force kernel ("key: value"
+    lines and "| counter | value |" rows), or None when there is none or the kernel's
+    sources changed since the counters were taken."""
     try:
         with open(PMC_SUMMARY) as f:
             text = f.read()
@@ -677,14 +683,42 @@ def _measured_traffic():
         return None
     fields = {}
     for line in text.splitlines():
-        line = line.strip().lstrip("-* ").strip()
+        line = line.strip()
+        if line.startswith("|"):
+            cells = [c.strip() for c in line.strip("|").split("|")]
+            if len(cells) == 2:
+                fields[cells[0]] = cells[1].replace(",", "")
+            continue
+        line = line.lstrip("-* ").strip()
         if ":" in line:
             k, v = line.split(":", 1)
             fields[k.strip().strip("`")] = v.strip().strip("`")
     if fields.get("source_sha256") != kernel_source_digest():
         return None
+    return fields
+
+
+def _measured_traffic():
+    """HBM bytes per launch of the force kernel from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's readings), or None."""
+    fields = _pmc_fields()
     try:
-        return float(fields["traffic_bytes_per_launch"])
+        return float(fields["traffic_bytes_per_launch"]) if fields else None
+    except (KeyError, ValueError):
+        return None
+
+
+# One wave64 VALU instruction issues every 4 cycles per SIMD (16 lanes; packed FP32 is not
+# used, so FP32 and FP64 issue alike): 1,024 SIMDs x 2.4 GHz / 4.
+VALU_WAVE_INSTS_PER_S = 1024 * 2.4e9 / 4
+
+
+def _measured_valu_insts():
+    """VALU wave instructions per launch of the force kernel (SQ_INSTS_VALU) from the
+    committed counter summary, or None."""
+    fields = _pmc_fields()
+    try:
+        return float(fields["SQ_INSTS_VALU"]) if fields else None
     except (KeyError, ValueError):
         return None
 

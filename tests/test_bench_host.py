@@ -39,6 +39,15 @@ def test_traffic_follows_the_kernel_digest(monkeypatch):
         assert t is None
     monkeypatch.setattr(bench, "kernel_source_digest", lambda: "0" * 64)
     assert bench._measured_traffic() is None
+    assert bench._measured_valu_insts() is None
+    # with the digest the counters were taken with, the summary's figures are read: the
+    # traffic above the algorithmic bytes and the VALU instructions of one launch (its table
+    # row, thousands separators removed) equal to the committed row
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: committed[0])
+    assert bench._measured_traffic() > 0
+    row = [ln for ln in text.splitlines() if ln.startswith("| SQ_INSTS_VALU |")]
+    assert len(row) == 1
+    assert bench._measured_valu_insts() == float(row[0].split("|")[2].replace(",", ""))
 
 
 def test_number_fluctuation_s0_of_an_ideal_gas():
