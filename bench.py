@@ -532,7 +532,7 @@ def number_fluctuation_s0(frames, box, lo, width, sides=(5, 8, 11, 14, 20)):
 # grows far above S(0) toward its first peak, where that gain would diverge: the coarse phase
 # takes half of it on a profile smoothed over 1.5 sigma, the next ones smaller fractions on
 # finer profiles to remove the layering the coarse phase cannot see.
-TD_SCHEDULE = ((6, 0.5, 1.5), (5, 0.1, 0.5), (5, 0.05, 0.0))
+TD_SCHEDULE = ((6, 0.5, 1.5), (5, 0.1, 0.5), (8, 0.05, 0.0))
 
 
 def tdforce_leg(wl, x, v, steps, n_bins=14, relax=4000, sample_steps=16000, sample_every=40,

@@ -11,6 +11,7 @@
 // row-major (ELL): nbr[slot * cap + k]; every row is padded with the row's own
 // slot up to a multiple of 4 so that the force kernel can fetch four entries with
 // one 16-byte load and issue their gathers unconditionally.
+#include <algorithm>
 #include <climits>
 
 #include "adres_internal.h"
@@ -217,25 +218,19 @@ __global__ __launch_bounds__(kBlock) void k_permute(DevParams P, const int *__re
     }
 }
 
-// Lane h's value broadcast to the whole wavefront (h uniform: a scalar read of the lane).
-__device__ __forceinline__ double read_lane(double v, int h)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), h);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), h);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
 // Cell-major build: one wavefront per cell of Morton rank r, four cells per workgroup.  The
 // cell's 27 stencil neighbours come from a table fixed at set-up (rank, or -1 for offsets
 // skipped on grids with fewer than 3 cells along a dimension, so that no cell is visited
 // twice; stencil order z, then y, then x offset); lanes 0..26 fetch their slot ranges and
 // a scan gives every candidate of the stencil an index k (stencil order, then slot order).  Home
-// molecules are taken 64 at a time (lane h holds home h's centre and running row length);
-// candidates 128 at a time (two per lane, cell found by binary search in LDS), each
-// tested against every home of the batch: a ballot gives the hits' positions in the home's
-// row, so rows come out in stencil order, then slot order.  Each candidate centre is
-// loaded once per batch of homes, not once per home molecule.
+// molecules are taken 64 at a time (lane h holds home h's running row length, its centre
+// comes from scalar loads, one home ahead); candidates 128 at a time (two per lane, the
+// stencil cell found by a branch-free search of the scanned starts in LDS), each tested
+// against every home of the batch: a ballot gives the hits' positions in the home's row,
+// so rows come out in stencil order, then slot order.  Each candidate centre is loaded once
+// per batch of homes, not once per home molecule.  The kernel is bound by VALU issue: the
+// home's centre and row address are wave-uniform (scalar registers), so that the vector
+// work per (home, candidate) test is the FP64 minimum-image distance and the ballot.
 constexpr int kCmWaves = 4;
 
 __global__ __launch_bounds__(kBlock) void k_list_build_cm(DevParams P, int n_cells, const int *__restrict__ stencil,
@@ -245,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_list_build_cm(DevParams P, int n_cel
                                                           unsigned *__restrict__ mcost, Ctrl *ctrl)
 {
     __shared__ int s_lo[kCmWaves][32], s_ex[kCmWaves][32];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int r = blockIdx.x * kCmWaves + wv;
     if (r >= n_cells) return;   // whole wavefront
     const int h0 = start[r], h1 = start[r + 1];
@@ -267,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_list_build_cm(DevParams P, int n_cel
     const int total_c = __shfl(incl, 31, 64);   // lanes 27..31 carry the full sum
     if (lane < 32) {
         s_lo[wv][lane] = lo;
-        s_ex[wv][lane] = incl - c;
+        s_ex[wv][lane] = incl - c;   // entries 27..31 hold total_c: above every candidate index
     }
     // lanes of one wavefront read what the others wrote above: LDS operations of a
     // wavefront complete in order, and this keeps the compiler from moving the reads up
@@ -276,8 +271,6 @@ __global__ __launch_bounds__(kBlock) void k_list_build_cm(DevParams P, int n_cel
     const unsigned heavy = (unsigned)(P.spm * P.spm);
     for (int hb = h0; hb < h1; hb += 64) {
         const int nb = min(64, h1 - hb);
-        double4 hm = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (lane < nb) hm = Rw[hb + lane];
         int base = 0;   // lane h: entries found so far for home hb + h
         // candidates 128 at a time, two per lane, both centres requested before the tests
         for (int c0 = 0; c0 < total_c; c0 += 128) {
@@ -288,22 +281,20 @@ __global__ __launch_bounds__(kBlock) void k_list_build_cm(DevParams P, int n_cel
             for (int u = 0; u < 2; ++u) {
                 const int k = c0 + 64 * u + lane;
                 vk[u] = k < total_c;
+                // the stencil cell holding candidate k: the largest j with ex_j <= k (ex_0 = 0)
+                int j = 0;
+#pragma unroll
+                for (int step = 16; step >= 1; step >>= 1) j += s_ex[wv][j + step] <= k ? step : 0;
+                slot[u] = s_lo[wv][j] + (k - s_ex[wv][j]);
                 o[u] = make_double4(0.0, 0.0, 0.0, 0.0);
-                if (vk[u]) {
-                    // the stencil cell holding candidate k: the largest j with ex_j <= k
-                    int a = 0, b = 26;
-                    while (a < b) {
-                        const int m = (a + b + 1) >> 1;
-                        if (s_ex[wv][m] <= k) a = m;
-                        else b = m - 1;
-                    }
-                    slot[u] = s_lo[wv][a] + (k - s_ex[wv][a]);
-                    o[u] = Rw[slot[u]];
-                }
+                if (vk[u]) o[u] = Rw[slot[u]];
             }
+            double4 nx = Rw[hb];   // the next home's centre (uniform: scalar loads)
             for (int h = 0; h < nb; ++h) {
-                const double mx = read_lane(hm.x, h), my = read_lane(hm.y, h), mz = read_lane(hm.z, h);
+                const double mx = nx.x, my = nx.y, mz = nx.z;
+                if (h + 1 < nb) nx = Rw[hb + h + 1];
                 const int t = hb + h;
+                int *row = nbr + (int64_t)t * cap;
                 int bh = __builtin_amdgcn_readlane(base, h);
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
@@ -314,10 +305,11 @@ __global__ __launch_bounds__(kBlock) void k_list_build_cm(DevParams P, int n_cel
                         const double dz = mi(o[u].z - mz, P.box[2], P.inv_box[2]);
                         hit = dist2_exact(dx, dy, dz) < rl2;
                     }
-                    const uint64_t m = __ballot(hit);
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
                     if (hit) {
-                        const int pos = bh + __popcll(m & ((1ull << lane) - 1ull));
-                        if (pos < cap) nbr[(int64_t)t * cap + pos] = slot[u];
+                        const unsigned pos = (unsigned)bh + __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                                                       __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                        if (pos < (unsigned)cap) row[pos] = slot[u];
                     }
                     bh += __popcll(m);
                 }
@@ -328,7 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_list_build_cm(DevParams P, int n_cel
             const int t = hb + lane;
             const int total = base;
             cnt[t] = total;
-            mcost[t] = (unsigned)min(total, cap) * (hm.w > 0.0 ? heavy : 1u) + 4u;
+            mcost[t] = (unsigned)min(total, cap) * (Rw[t].w > 0.0 ? heavy : 1u) + 4u;
             if (total > cap) {
                 atomicOr(&ctrl->overflow, 1);
                 atomicMax(&ctrl->max_count, total);
@@ -468,63 +460,125 @@ namespace {
 // slot order after the tile's own slots, which take halo positions 0..kHaloTile-1 (slot
 // order keeps the runs of a cell's molecules together, so that neighbouring lanes of the
 // force kernel's staging read neighbouring addresses).  The rows are rewritten as local
-// halo indices, lane q of a quad owning entries q, q + 4, ...
-constexpr int kHaloHash = 2048;   // table positions (a power of two)
+// halo indices, lane q of a quad owning entries q, q + 4, ...  The kernel is bound by the
+// latency of its dependent chains (row loads, hash probes): a lane takes its entries in
+// groups of kHaloGroup, each group's loads, first probes and lookups issued together, and
+// keeps its first group in registers for the second pass.  The table takes 6 bytes a
+// position (4-byte key, 2-byte halo position) and the compacted list 8 bytes a distinct
+// slot (at most hcap - kHaloTile).  Its size is a power of two in [kBlock, kHaloHashMax]:
+// a grid that one round of workgroups covers (four per compute unit) is bound by one
+// workgroup's latency and takes the largest table (fewest collisions, hence the shortest
+// probe chains); a larger grid is bound by how many workgroups a compute unit holds and
+// takes the smallest table with at most half of its positions filled.
+constexpr int kHaloHashMin = kBlock;   // table positions: a power of two in [kBlock, kHaloHashMax]
+constexpr int kHaloHashMax = 2048;
+constexpr int kHaloGroup = 4;          // row entries per lane in flight together
 
-__device__ __forceinline__ int halo_hash(int u) { return (int)(((unsigned)u * 2654435761u) >> (32 - 11)); }
-static_assert(kHaloHash == 1 << 11, "hash width");
+__device__ __forceinline__ int halo_hash(int u, int shift) { return (int)(((unsigned)u * 2654435761u) >> shift); }
+
+// Inserts u, whose first probe returned prev, by linear probing from there.
+__device__ __forceinline__ void halo_insert_rest(int *keys, int mask, int shift, int u, int prev, int *lost)
+{
+    if (prev == -1 || prev == u) return;
+    int h = halo_hash(u, shift), probe = 1;
+#pragma unroll 1
+    for (; probe <= mask; ++probe) {
+        h = (h + 1) & mask;
+        const int p = atomicCAS(&keys[h], -1, u);
+        if (p == -1 || p == u) break;
+    }
+    if (probe > mask) atomicOr(lost, 1);
+}
+
+// Table position of u (present), given the key found at its first probe position.
+__device__ __forceinline__ int halo_find(const int *keys, int mask, int shift, int u, int first)
+{
+    int h = halo_hash(u, shift);
+    if (first == u) return h;
+#pragma unroll 1
+    for (int probe = 1; probe <= mask; ++probe) {
+        h = (h + 1) & mask;
+        if (keys[h] == u) break;
+    }
+    return h;
+}
+
+// log2 of the table size for a halo capacity hcap and a grid of `tiles` workgroups on
+// n_cu compute units
+int halo_table_log2(int hcap, int tiles, int n_cu)
+{
+    int lg = 0;
+    if (n_cu > 0 && tiles <= 4 * n_cu) {
+        while ((1 << lg) < kHaloHashMax) ++lg;
+        return lg;
+    }
+    while ((1 << lg) < kHaloHashMin || ((1 << lg) < 2 * (hcap - kHaloTile) && (1 << lg) < kHaloHashMax)) ++lg;
+    return lg;
+}
 
 __global__ __launch_bounds__(kBlock) void k_halo_build(int n_mol, const int *__restrict__ nbr,
                                                        const int *__restrict__ cnt, int cap, int hcap, int lcap,
-                                                       const unsigned *__restrict__ mcost, int *__restrict__ hid,
+                                                       int lg, const unsigned *__restrict__ mcost, int *__restrict__ hid,
                                                        int *__restrict__ hn, uint16_t *__restrict__ lnbr,
                                                        uint8_t *__restrict__ tperm, Ctrl *ctrl)
 {
-    __shared__ int keys[kHaloHash];
-    __shared__ int vals[kHaloHash];
-    __shared__ int dkey[kHaloHash], dpos[kHaloHash];   // the distinct slots, compacted
+    // keys and vals by table position, then the distinct slots compacted (key, position):
+    // room for the hcap - kHaloTile a halo may hold (more overflow the capacity)
+    extern __shared__ int tab[];
+    const int T = 1 << lg, mask = T - 1, shift = 32 - lg, D = hcap - kHaloTile;
+    int *keys = tab, *dkey = tab + T, *dpos = tab + T + D;
+    uint16_t *vals = reinterpret_cast<uint16_t *>(tab + T + 2 * D);   // halo positions (< hcap)
     __shared__ int wave_tot[kBlock / 64];
     __shared__ int lost;
     __shared__ unsigned tcost[kHaloTile];
     const int b = blockIdx.x;
     const int base = b * kHaloTile;
     const int n_home = min(kHaloTile, n_mol - base);
-    for (int i = threadIdx.x; i < kHaloHash; i += kBlock) keys[i] = -1;
-    if (threadIdx.x == 0) lost = 0;
     // (the tail of a short last tile costs 0: it sorts last; valid costs are at least 4)
-    if (threadIdx.x < kHaloTile) tcost[threadIdx.x] = (int)threadIdx.x < n_home ? mcost[base + threadIdx.x] : 0u;
+    const unsigned my_cost = (int)threadIdx.x < n_home ? mcost[base + threadIdx.x] : 0u;
+    const int m = threadIdx.x >> 2, q = threadIdx.x & 3;
+    const int t = base + m;
+    // a row that overflowed holds only cap entries; the list is rebuilt before any use
+    const int c = m < n_home ? min(cnt[t], cap) : 0;
+    const int per = c > q ? (c - q + 3) >> 2 : 0;   // lane q's entries k = q + 4 i, i < per
+    const int *row = nbr + (int64_t)t * cap + q;
+    auto own = [base, n_home](int v) { return (unsigned)(v - base) < (unsigned)n_home; };
+    int u0[kHaloGroup];   // the first group, kept for the second pass
+#pragma unroll
+    for (int i = 0; i < kHaloGroup; ++i) u0[i] = i < per ? row[4 * i] : base;
+
+    for (int i = threadIdx.x; i < T; i += kBlock) keys[i] = -1;
+    if (threadIdx.x == 0) lost = 0;
+    if (threadIdx.x < kHaloTile) tcost[threadIdx.x] = my_cost;
     __syncthreads();
     // the tile's molecules by falling cost, ties in slot order
     if (threadIdx.x < kHaloTile) {
         const unsigned cme = tcost[threadIdx.x];
         int rank = 0;
+#pragma unroll 8
         for (int j = 0; j < kHaloTile; ++j) {
             const unsigned o = tcost[j];
             rank += (o > cme || (o == cme && j < (int)threadIdx.x)) ? 1 : 0;
         }
         tperm[(int64_t)b * kHaloTile + rank] = (uint8_t)threadIdx.x;
     }
-    const int m = threadIdx.x >> 2, q = threadIdx.x & 3;
-    const int t = base + m;
-    // a row that overflowed holds only cap entries; the list is rebuilt before any use
-    const int c = m < n_home ? min(cnt[t], cap) : 0;
-    const int *row = nbr + (int64_t)t * cap;
-    for (int k = q; k < c; k += 4) {
-        const int u = row[k];
-        if ((unsigned)(u - base) < (unsigned)n_home) continue;   // one of the tile's own slots
-        int h = halo_hash(u), probe = 0;
-        for (; probe < kHaloHash; ++probe) {
-            const int prev = atomicCAS(&keys[h], -1, u);
-            if (prev == -1 || prev == u) break;
-            h = (h + 1) & (kHaloHash - 1);
-        }
-        if (probe == kHaloHash) atomicOr(&lost, 1);
+    // insertion, a group at a time: its first probes back to back, then the rare collisions
+    // (entries past the row's length are the tile's own first slot: skipped as own)
+    for (int i0 = 0; i0 < per; i0 += kHaloGroup) {
+        int v[kHaloGroup], prev[kHaloGroup];
+#pragma unroll
+        for (int i = 0; i < kHaloGroup; ++i) v[i] = i0 == 0 ? u0[i] : (i0 + i < per ? row[4 * (i0 + i)] : base);
+#pragma unroll
+        for (int i = 0; i < kHaloGroup; ++i)
+            prev[i] = own(v[i]) ? -1 : atomicCAS(&keys[halo_hash(v[i], shift)], -1, v[i]);
+#pragma unroll
+        for (int i = 0; i < kHaloGroup; ++i)
+            if (!own(v[i])) halo_insert_rest(keys, mask, shift, v[i], prev[i], &lost);
     }
     __syncthreads();
-    // number the occupied positions: each thread owns kHaloHash / kBlock consecutive ones
-    constexpr int kPer = kHaloHash / kBlock;
+    // number the occupied positions: each thread owns T / kBlock consecutive ones
+    const int kPer = T / kBlock;
     int occ = 0;
-#pragma unroll
     for (int j = 0; j < kPer; ++j) occ += keys[threadIdx.x * kPer + j] >= 0;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int incl = occ;
@@ -542,30 +596,35 @@ __global__ __launch_bounds__(kBlock) void k_halo_build(int n_mol, const int *__r
         total += wave_tot[w];
     }
     int r = before + incl - occ;
-#pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int pos = threadIdx.x * kPer + j;
         const int key = keys[pos];
         if (key >= 0) {
-            dkey[r] = key;
-            dpos[r] = pos;
+            if (r < D) {
+                dkey[r] = key;
+                dpos[r] = pos;
+            }
             ++r;
         }
     }
     __syncthreads();
-    // rank of each distinct slot among them (the slots are distinct: ranks are a permutation)
+    // rank of each distinct slot among them (the slots are distinct: ranks are a permutation);
+    // a halo over the capacity is only reported (the capacity grows, the halos are rebuilt)
     int *h_out = hid + (int64_t)b * hcap;
-    for (int j = threadIdx.x; j < total; j += kBlock) {
+    for (int j = threadIdx.x; j < (total > D ? 0 : total); j += kBlock) {
         const int key = dkey[j];
         int rank = 0;
+#pragma unroll 8
         for (int i = 0; i < total; ++i) rank += dkey[i] < key;
         const int lpos = kHaloTile + rank;
-        vals[dpos[j]] = lpos;
+        vals[dpos[j]] = (uint16_t)lpos;
         if (lpos < hcap) h_out[lpos] = key;
     }
     // the tile's own slots first (a short last tile repeats its last slot: never referenced)
     if (threadIdx.x < kHaloTile) h_out[threadIdx.x] = base + min((int)threadIdx.x, n_home - 1);
-    const int n_halo = lost ? INT_MAX / 2 : kHaloTile + total;
+    // a full table held more than T distinct slots: report T + 1 of them, so that the
+    // capacity (and with it the table) grows
+    const int n_halo = kHaloTile + (lost ? T + 1 : total);
     if (threadIdx.x == 0) {
         hn[b] = min(n_halo, hcap);
         if (n_halo > hcap) {
@@ -576,19 +635,26 @@ __global__ __launch_bounds__(kBlock) void k_halo_build(int n_mol, const int *__r
     }
     __syncthreads();
     if (n_halo > hcap) return;
-    // rows as local halo indices, lane q's entries contiguous in its quarter of the row
+    // rows as local halo indices, lane q's entries contiguous in its quarter of the row, a
+    // group's lookups issued together and its entries stored as one 8-byte word (the
+    // quarter is a multiple of 8 entries long and 16-byte aligned; entries past the row's
+    // length are never read)
     uint16_t *lrow = lnbr + (int64_t)t * lcap + q * (lcap / 4);
-    for (int k = q; k < c; k += 4) {
-        const int u = row[k];
-        int local;
-        if ((unsigned)(u - base) < (unsigned)n_home) {
-            local = u - base;
-        } else {
-            int h = halo_hash(u);
-            for (int probe = 0; probe < kHaloHash && keys[h] != u; ++probe) h = (h + 1) & (kHaloHash - 1);
-            local = vals[h];
-        }
-        lrow[k >> 2] = (uint16_t)local;
+    static_assert(kHaloGroup == 4, "a group is stored as one 8-byte word");
+    for (int i0 = 0; i0 < per; i0 += kHaloGroup) {
+        int v[kHaloGroup], first[kHaloGroup];
+#pragma unroll
+        for (int i = 0; i < kHaloGroup; ++i) v[i] = i0 == 0 ? u0[i] : (i0 + i < per ? row[4 * (i0 + i)] : base);
+#pragma unroll
+        for (int i = 0; i < kHaloGroup; ++i) first[i] = own(v[i]) ? 0 : keys[halo_hash(v[i], shift)];
+        unsigned loc[kHaloGroup];
+#pragma unroll
+        for (int i = 0; i < kHaloGroup; ++i)
+            loc[i] = own(v[i]) ? (unsigned)(v[i] - base) : (unsigned)vals[halo_find(keys, mask, shift, v[i], first[i])];
+        uint2 pk;
+        pk.x = (loc[0] & 0xFFFFu) | (loc[1] << 16);
+        pk.y = (loc[2] & 0xFFFFu) | (loc[3] << 16);
+        *reinterpret_cast<uint2 *>(lrow + i0) = pk;
     }
 }
 
@@ -598,7 +664,13 @@ void launch_halo_build(hipStream_t s, int n_mol, const int *nbr, const int *cnt,
                        const unsigned *mcost, int *hid, int *hn, uint16_t *lnbr, uint8_t *tperm, Ctrl *ctrl)
 {
     const int tiles = (n_mol + kHaloTile - 1) / kHaloTile;
-    k_halo_build<<<tiles, kBlock, 0, s>>>(n_mol, nbr, cnt, cap, hcap, lcap, mcost, hid, hn, lnbr, tperm, ctrl);
+    int dev = 0, n_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        n_cu = 0;
+    const int lg = halo_table_log2(hcap, tiles, n_cu);
+    const size_t lds = ((size_t)6 << lg) + (size_t)8 * (hcap - kHaloTile);
+    k_halo_build<<<tiles, kBlock, lds, s>>>(n_mol, nbr, cnt, cap, hcap, lcap, lg, mcost, hid, hn, lnbr, tperm, ctrl);
 }
 
 

@@ -135,3 +135,28 @@ def test_site_beyond_the_skin_budget_refused(dev):
     with pytest.raises(binding.AdresError) as ei:
         _ctx(wl).forces(_t(x, dev))
     assert ei.value.status == -6
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_rows_longer_than_64_entries(dev, prec):
+    """A 3-sigma skin on the CG melt gives every molecule 70-91 listed neighbours: the list
+    build, the tile halos (whose rows past 64 entries take the path for grown capacities)
+    and the force kernel's long rows against the oracle (list bit-exact, forces to the
+    precision's bar of A_i)."""
+    wl = inputs.workload("small_cg").with_(cg_kind=inputs.CG_WCA, r_skin=3.0, pair_precision=prec)
+    x, _ = inputs.make_state(wl)
+    m = oracle.Model(wl)
+    com_o, _, _, _ = m.weights(x)
+    ref = m.pairs(com_o)
+    counts = np.bincount(ref.ravel(), minlength=wl.n_mol)
+    assert counts.min() > 64
+    ctx = _ctx(wl)
+    assert ctx.build_verlet(_t(x, dev)) == len(ref)
+    np.testing.assert_array_equal(ctx.get_pairs(), ref)
+    fo, amag, eo, _ = m.forces(x)
+    f, e = ctx.forces(_t(x, dev), energy=True)
+    torch.cuda.synchronize()
+    tol = 1e-12 if prec == 64 else 1e-5
+    err = np.abs(f.cpu().numpy() - fo).max(axis=0)
+    assert (err <= tol * np.maximum(amag, 1e-300)).all(), (err / amag).max()
+    np.testing.assert_allclose(e.cpu().numpy(), eo, rtol=tol, atol=tol * np.abs(eo).max())
