@@ -59,6 +59,8 @@ struct adres_ctx {
     double4 *near = nullptr;                 // offset from the nearest anchor per slot
     double *anchor_cen = nullptr;            // anchor centres of a caller configuration [K][3]
     int *tile_order = nullptr;               // force kernel dispatch order (per list build)
+    int *tile_pos = nullptr;                 // its inverse: each tile's dispatch position
+    int *hcnt = nullptr;                     // row lengths in dispatch order (halo build)
     unsigned *mcost = nullptr;               // per-molecule cost estimates (list build)
     int *stencil = nullptr;                  // [n_cells][27] neighbour cell ranks (static grid)
 
@@ -264,8 +266,8 @@ adres_status alloc_halo(adres_ctx *c, int hcap)
 
 void launch_halo(adres_ctx *c)
 {
-    launch_halo_build(c->stream, c->P.n_mol, c->nbr, c->cnt, c->cap, c->hcap, c->lcap, c->mcost, c->hid, c->hn,
-                      c->lnbr, c->tperm, c->ctrl);
+    launch_halo_build(c->stream, c->P.n_mol, c->nbr, c->cnt, c->cap, c->hcap, c->lcap, c->mcost, c->tile_pos,
+                      c->hid, c->hn, c->hcnt, c->lnbr, c->tperm, c->ctrl);
 }
 
 // Every unordered pair of the Verlet list once (t < u) and, for every list entry, the
@@ -341,7 +343,7 @@ adres_status build_list(adres_ctx *c)
         st = alloc_halo(c, c->hcap);
         if (st != ADRES_OK) return st;
     }
-    launch_tile_order(c->stream, c->P, c->mcost, c->epart_blocks, c->tile_order);
+    launch_tile_order(c->stream, c->P, c->mcost, c->epart_blocks, c->tile_order, c->tile_pos);
     if (is_mlp(c)) {
         adres_status st = build_half_list(c);
         if (st != ADRES_OK) return st;
@@ -380,7 +382,7 @@ adres_status build_list_async(adres_ctx *c)
     const StateBufs b = cur(c);
     launch_list_build(c->stream, c->P, c->G, c->stencil, c->start, b.Rw, c->rl2, c->nbr, c->cnt, c->cap,
                       c->mcost, c->ctrl);
-    launch_tile_order(c->stream, c->P, c->mcost, c->epart_blocks, c->tile_order);
+    launch_tile_order(c->stream, c->P, c->mcost, c->epart_blocks, c->tile_order, c->tile_pos);
     HIPCHK(c, hipGetLastError());
     c->list_valid = true;
     if (is_mlp(c)) {
@@ -399,7 +401,6 @@ ForceArgs force_args(adres_ctx *c)
     a.P = c->P;
     a.x = S.x;
     a.Rw = S.Rw;
-    a.cnt = c->cnt;
     a.cap = c->cap;
     a.hid = c->hid;
     a.hn = c->hn;
@@ -407,6 +408,7 @@ ForceArgs force_args(adres_ctx *c)
     a.lnbr = c->lnbr;
     a.lcap = c->lcap;
     a.tperm = c->tperm;
+    a.hcnt = c->hcnt;
     a.perm = S.perm;
     a.inv_perm = c->inv_perm;
     a.ctrl = c->ctrl;
@@ -647,6 +649,8 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     ok = ok && dalloc(&c->hn, (size_t)c->epart_blocks) == hipSuccess;
     ok = ok && dalloc(&c->tperm, (size_t)c->epart_blocks * kHaloTile) == hipSuccess;
     ok = ok && alloc_halo(c, std::min(320, halo_capacity_limit(q.sites_per_mol, q.pair_precision))) == ADRES_OK;
+    ok = ok && dalloc(&c->tile_pos, (size_t)c->epart_blocks) == hipSuccess &&
+         dalloc(&c->hcnt, (size_t)c->epart_blocks * kHaloTile) == hipSuccess;
     ok = ok && dalloc(&c->tile_order, (size_t)c->epart_blocks) == hipSuccess &&
          dalloc(&c->mcost, ((size_t)n + 15) / 16 * 16) == hipSuccess &&   // whole 16-entry runs
          dalloc(&c->stencil, (size_t)G.n_cells * 27) == hipSuccess;
@@ -693,7 +697,7 @@ void adres_destroy(adres_ctx *c)
     hipFree(c->R_ref); hipFree(c->inv_perm); hipFree(c->cell_rank);
     hipFree(c->count); hipFree(c->start); hipFree(c->fill); hipFree(c->new_from); hipFree(c->scan_tiles);
     hipFree(c->nbr); hipFree(c->cnt); hipFree(c->hid); hipFree(c->hn); hipFree(c->lnbr); hipFree(c->tperm); hipFree(c->ctrl); hipFree(c->epart); hipFree(c->tab);
-    hipFree(c->td); hipFree(c->td_u); hipFree(c->anchors); hipFree(c->aslot); hipFree(c->near); hipFree(c->anchor_cen); hipFree(c->tile_order); hipFree(c->mcost); hipFree(c->stencil);
+    hipFree(c->td); hipFree(c->td_u); hipFree(c->anchors); hipFree(c->aslot); hipFree(c->near); hipFree(c->anchor_cen); hipFree(c->tile_order); hipFree(c->tile_pos); hipFree(c->hcnt); hipFree(c->mcost); hipFree(c->stencil);
     hipFree(c->mlp); hipFree(c->mlp_w2); hipFree(c->mlp_w2q); hipFree(c->mlp_fp8s); hipFree(c->cnt_up); hipFree(c->up_off); hipFree(c->up_scratch);
     hipFree(c->pid); hipFree(c->up_pairs); hipFree(c->f_pair);
     hipFree(c->adam_m); hipFree(c->adam_v); hipFree(c->grad); hipFree(c->loss); hipFree(c->res_part);

@@ -494,18 +494,22 @@ void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, cons
 void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const int *stencil, const int *start,
                        const double4 *Rw, double rl2, int *nbr, int *cnt, int cap, unsigned *mcost, Ctrl *ctrl);
 
-// Neighbour halo of every force-kernel tile (64 consecutive slots): hid[tile * hcap + l]
-// lists the slots a tile reads, its own 64 first (l < 64, the tile's slot order), then
-// every other slot of its molecules' rows once; hn[tile] is the count.  lnbr holds each row
-// as local halo indices (uint16), entry k of slot t at t * lcap + (k % 4) * (lcap / 4) + k / 4,
-// so lane q of a molecule's quad finds its entries q, q + 4, ... contiguous.  A halo larger
-// than hcap sets overflow bit 1, max_halo and halt = -1.  tperm[tile * 64 + j] is the tile's
-// j-th molecule by falling cost (mcost from the list build; ties and the empty tail of a
-// short last tile in slot order): the force kernel's thread groups take them in that order,
-// so each wavefront's sixteen molecules have similar row work.
+// Neighbour halo of every force-kernel tile (64 consecutive slots), stored at the tile's
+// dispatch position p = tile_pos[tile] (launch_tile_order), so that the force kernel's
+// workgroup p finds it without first reading which tile it runs: hid[p * hcap + l] lists
+// the slots the tile reads, its own 64 first (l < 64, the tile's slot order), then every
+// other slot of its molecules' rows once; hn[p] is the count.  tperm[p * 64 + j] is the
+// tile's j-th molecule by falling cost (mcost from the list build; ties and the empty tail
+// of a short last tile in slot order): the force kernel's thread group j takes it, so each
+// wavefront's sixteen molecules have similar row work.  Row j of the dispatch-ordered rows
+// (r = p * 64 + j) is that molecule's: hcnt[r] its length (0 for the empty tail) and lnbr
+// its entries as local halo indices (uint16), entry k at r * lcap + (k % 4) * (lcap / 4) +
+// k / 4, so that lane q of the quad finds its entries q, q + 4, ... contiguous.  A halo
+// larger than hcap sets overflow bit 1, max_halo and halt = -1.
 constexpr int kHaloTile = 64;
 void launch_halo_build(hipStream_t s, int n_mol, const int *nbr, const int *cnt, int cap, int hcap, int lcap,
-                       const unsigned *mcost, int *hid, int *hn, uint16_t *lnbr, uint8_t *tperm, Ctrl *ctrl);
+                       const unsigned *mcost, const int *tile_pos, int *hid, int *hn, int *hcnt, uint16_t *lnbr,
+                       uint8_t *tperm, Ctrl *ctrl);
 // LDS bytes of the force kernel's halo staging per halo molecule, and the largest halo
 // capacity that fits a workgroup's LDS
 int halo_stride_bytes(int spm, int pair_precision);
@@ -525,13 +529,15 @@ struct ForceArgs {
     DevParams P;
     const double *x;        // step-n positions (sorted)
     const double4 *Rw;      // step-n weights of a self-adjusting region (w only)
-    const int *cnt;         // row lengths
     int cap;                // row capacity of the slot-indexed list (pair ids)
-    const int *hid, *hn;    // tile halos (launch_halo_build)
+    // tile halos, cost order and rows as local halo indices, all at the dispatch position
+    // (launch_halo_build)
+    const int *hid, *hn;
     int hcap;
-    const uint16_t *lnbr;   // rows as local halo indices
+    const int *hcnt;
+    const uint16_t *lnbr;
     int lcap;
-    const uint8_t *tperm;   // each tile's molecules by falling cost (launch_halo_build)
+    const uint8_t *tperm;
     const int *perm, *inv_perm;   // slot -> caller, caller -> slot
     int mode;
     double *f;                    // kModeForce / kModeClose: output forces
@@ -549,7 +555,7 @@ struct ForceArgs {
     // multiple time stepping: the slow part (CG pair part, the CG share of the drift, the
     // correction force) enters the force with this factor; 0 skips it (inner steps)
     double slow_scale;
-    // dispatch order of the workgroups (launch_tile_order), or null for the identity
+    // dispatch order of the workgroups (launch_tile_order): the tile workgroup p runs
     const int *tile_order;
     // self-adjusting region: offset from the nearest anchor centre and its length per slot
     const double4 *near;
@@ -561,8 +567,9 @@ int launch_forces(hipStream_t s, const ForceArgs &a, int pair_precision, hipEven
 int force_blocks(int n_mol);
 void launch_energy_reduce(hipStream_t s, const double *epart, int n_blocks, double *energy);
 
-// workgroup dispatch order of the force kernel, rebuilt with the list (k_cells.hip)
-void launch_tile_order(hipStream_t s, const DevParams &P, const unsigned *mcost, int n_tiles, int *order);
+// workgroup dispatch order of the force kernel, rebuilt with the list (k_cells.hip):
+// order[p] is the tile dispatched as workgroup p, pos[tile] its inverse
+void launch_tile_order(hipStream_t s, const DevParams &P, const unsigned *mcost, int n_tiles, int *order, int *pos);
 
 // correction force (k_state.hip)
 constexpr int kTdMaxBins = 4096;

@@ -518,9 +518,11 @@ int halo_table_log2(int hcap, int tiles, int n_cu)
 
 __global__ __launch_bounds__(kBlock) void k_halo_build(int n_mol, const int *__restrict__ nbr,
                                                        const int *__restrict__ cnt, int cap, int hcap, int lcap,
-                                                       int lg, const unsigned *__restrict__ mcost, int *__restrict__ hid,
-                                                       int *__restrict__ hn, uint16_t *__restrict__ lnbr,
-                                                       uint8_t *__restrict__ tperm, Ctrl *ctrl)
+                                                       int lg, const unsigned *__restrict__ mcost,
+                                                       const int *__restrict__ tile_pos, int *__restrict__ hid,
+                                                       int *__restrict__ hn, int *__restrict__ hcnt,
+                                                       uint16_t *__restrict__ lnbr, uint8_t *__restrict__ tperm,
+                                                       Ctrl *ctrl)
 {
     // keys and vals by table position, then the distinct slots compacted (key, position):
     // room for the hcap - kHaloTile a halo may hold (more overflow the capacity)
@@ -531,7 +533,9 @@ __global__ __launch_bounds__(kBlock) void k_halo_build(int n_mol, const int *__r
     __shared__ int wave_tot[kBlock / 64];
     __shared__ int lost;
     __shared__ unsigned tcost[kHaloTile];
+    __shared__ int trank[kHaloTile];   // each molecule's place in the cost order
     const int b = blockIdx.x;
+    const int pb = tile_pos[b];   // the dispatch position, where the outputs go
     const int base = b * kHaloTile;
     const int n_home = min(kHaloTile, n_mol - base);
     // (the tail of a short last tile costs 0: it sorts last; valid costs are at least 4)
@@ -560,7 +564,8 @@ __global__ __launch_bounds__(kBlock) void k_halo_build(int n_mol, const int *__r
             const unsigned o = tcost[j];
             rank += (o > cme || (o == cme && j < (int)threadIdx.x)) ? 1 : 0;
         }
-        tperm[(int64_t)b * kHaloTile + rank] = (uint8_t)threadIdx.x;
+        tperm[(int64_t)pb * kHaloTile + rank] = (uint8_t)threadIdx.x;
+        trank[threadIdx.x] = rank;
     }
     // insertion, a group at a time: its first probes back to back, then the rare collisions
     // (entries past the row's length are the tile's own first slot: skipped as own)
@@ -610,7 +615,7 @@ __global__ __launch_bounds__(kBlock) void k_halo_build(int n_mol, const int *__r
     __syncthreads();
     // rank of each distinct slot among them (the slots are distinct: ranks are a permutation);
     // a halo over the capacity is only reported (the capacity grows, the halos are rebuilt)
-    int *h_out = hid + (int64_t)b * hcap;
+    int *h_out = hid + (int64_t)pb * hcap;
     for (int j = threadIdx.x; j < (total > D ? 0 : total); j += kBlock) {
         const int key = dkey[j];
         int rank = 0;
@@ -626,7 +631,7 @@ __global__ __launch_bounds__(kBlock) void k_halo_build(int n_mol, const int *__r
     // capacity (and with it the table) grows
     const int n_halo = kHaloTile + (lost ? T + 1 : total);
     if (threadIdx.x == 0) {
-        hn[b] = min(n_halo, hcap);
+        hn[pb] = min(n_halo, hcap);
         if (n_halo > hcap) {
             atomicOr(&ctrl->overflow, 2);
             atomicMax(&ctrl->max_halo, n_halo);
@@ -639,7 +644,9 @@ __global__ __launch_bounds__(kBlock) void k_halo_build(int n_mol, const int *__r
     // group's lookups issued together and its entries stored as one 8-byte word (the
     // quarter is a multiple of 8 entries long and 16-byte aligned; entries past the row's
     // length are never read)
-    uint16_t *lrow = lnbr + (int64_t)t * lcap + q * (lcap / 4);
+    const int64_t rrow = (int64_t)pb * kHaloTile + trank[m];   // the row's dispatch-ordered place
+    if (q == 0) hcnt[rrow] = c;
+    uint16_t *lrow = lnbr + rrow * lcap + q * (lcap / 4);
     static_assert(kHaloGroup == 4, "a group is stored as one 8-byte word");
     for (int i0 = 0; i0 < per; i0 += kHaloGroup) {
         int v[kHaloGroup], first[kHaloGroup];
@@ -661,7 +668,8 @@ __global__ __launch_bounds__(kBlock) void k_halo_build(int n_mol, const int *__r
 }  // namespace
 
 void launch_halo_build(hipStream_t s, int n_mol, const int *nbr, const int *cnt, int cap, int hcap, int lcap,
-                       const unsigned *mcost, int *hid, int *hn, uint16_t *lnbr, uint8_t *tperm, Ctrl *ctrl)
+                       const unsigned *mcost, const int *tile_pos, int *hid, int *hn, int *hcnt, uint16_t *lnbr,
+                       uint8_t *tperm, Ctrl *ctrl)
 {
     const int tiles = (n_mol + kHaloTile - 1) / kHaloTile;
     int dev = 0, n_cu = 0;
@@ -670,7 +678,8 @@ void launch_halo_build(hipStream_t s, int n_mol, const int *nbr, const int *cnt,
         n_cu = 0;
     const int lg = halo_table_log2(hcap, tiles, n_cu);
     const size_t lds = ((size_t)6 << lg) + (size_t)8 * (hcap - kHaloTile);
-    k_halo_build<<<tiles, kBlock, lds, s>>>(n_mol, nbr, cnt, cap, hcap, lcap, lg, mcost, hid, hn, lnbr, tperm, ctrl);
+    k_halo_build<<<tiles, kBlock, lds, s>>>(n_mol, nbr, cnt, cap, hcap, lcap, lg, mcost, tile_pos, hid, hn, hcnt, lnbr,
+                                            tperm, ctrl);
 }
 
 
@@ -704,7 +713,7 @@ __device__ __forceinline__ unsigned long long tile_key(unsigned cost, int i)
 }
 
 __global__ __launch_bounds__(kTileThreads) void k_tile_order(int n_mol, const unsigned *__restrict__ mcost, int n_tiles,
-                                                            int *__restrict__ order)
+                                                            int *__restrict__ order, int *__restrict__ pos)
 {
     __shared__ unsigned tcost[kTileSortMax];
     __shared__ unsigned long long key[kTileSortMax];
@@ -713,7 +722,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_order(int n_mol, const un
     const int start = x * q + (x < r ? x : r), len = q + (x < r ? 1 : 0);
     if (len == 0) return;   // fewer tiles than XCDs: this range is empty
     if (len > kTileSortMax) {
-        for (int i = threadIdx.x; i < len; i += kTileThreads) order[start + i] = start + i;
+        for (int i = threadIdx.x; i < len; i += kTileThreads) order[start + i] = pos[start + i] = start + i;
         return;
     }
     for (int i = threadIdx.x; i < len; i += kTileThreads) tcost[i] = 0u;
@@ -771,7 +780,10 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_order(int n_mol, const un
             atomicAdd(&tcost[i], n_gt);
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < len; i += kTileThreads) order[start + (int)tcost[i]] = start + i;
+        for (int i = threadIdx.x; i < len; i += kTileThreads) {
+            order[start + (int)tcost[i]] = start + i;
+            pos[start + i] = start + (int)tcost[i];
+        }
         return;
     }
     // long ranges: bitonic sort into falling order over a power-of-two padding of zeros
@@ -797,15 +809,18 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_order(int n_mol, const un
         }
     }
     // position p holds the p-th largest key, whose low word is the complement of its tile
-    for (int p = threadIdx.x; p < len; p += kTileThreads)
-        order[start + p] = start + (int)(~(unsigned)(key[p] & 0xffffffffull));
+    for (int p = threadIdx.x; p < len; p += kTileThreads) {
+        const int i = (int)(~(unsigned)(key[p] & 0xffffffffull));
+        order[start + p] = start + i;
+        pos[start + i] = start + p;
+    }
 }
 
 }  // namespace
 
-void launch_tile_order(hipStream_t s, const DevParams &P, const unsigned *mcost, int n_tiles, int *order)
+void launch_tile_order(hipStream_t s, const DevParams &P, const unsigned *mcost, int n_tiles, int *order, int *pos)
 {
-    k_tile_order<<<8, kTileThreads, 0, s>>>(P.n_mol, mcost, n_tiles, order);
+    k_tile_order<<<8, kTileThreads, 0, s>>>(P.n_mol, mcost, n_tiles, order, pos);
 }
 
 }  // namespace adres

@@ -213,12 +213,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     const int halt = a.ctrl->halt;
     const int n = P.n_mol;
     const int64_t ns = P.n_sites;
-    const int slot = xcd_block();
-    const int blk = a.tile_order ? a.tile_order[slot] : slot;
+    const int slot = xcd_block();   // the dispatch position: the tile's halo, rows and cost order
+    const int blk = a.tile_order[slot];   // the tile (its molecules' slots)
     const int q = threadIdx.x % kLanes;
     // the tile's molecules by falling cost: each wavefront's sixteen have similar row work
-    // (ml: the molecule's place in the tile, its LDS record and its slot's offset)
-    const int ml = a.tperm[(int64_t)blk * kHaloTile + threadIdx.x / kLanes];
+    // (ml: the molecule's place in the tile, its LDS record and its slot's offset; its row
+    // is the thread group's row of the dispatch-ordered rows)
+    const int64_t row = (int64_t)slot * kHaloTile + threadIdx.x / kLanes;
+    const int ml = a.tperm[row];
     const int t = blk * kHaloTile + ml;
     const bool valid = t < n;
     const int tt = valid ? t : n - 1;
@@ -226,20 +228,22 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
     // the home sites (FP64) for the bonds and the integration, and the home molecules' rho
     __shared__ double sx[kBlock / kLanes][SPM][3];
     __shared__ float srho[kBlock / kLanes];
-    // every load that does not depend on another (the tile order, the halo count and the
-    // first halo ids, the halt index) is issued before the first wait; the second round
-    // brings the halo's sites (the tile's own molecules first, whose sites also fill sx)
-    // and each molecule's row length and first local-row entries.  Velocities and the
-    // reference centre are requested after the pair loop, which keeps the workgroup's LDS
-    // within a quarter of the compute unit's (four workgroups per compute unit)
-    const int hn = min(a.hn[blk], a.hcap);
-    const int *hid = a.hid + (int64_t)blk * a.hcap;
+    // every load that does not depend on another (the tile, the halo count and the first
+    // halo ids, each molecule's row length and first local-row entries, the halt index: all
+    // stored at the dispatch position) is issued before the first wait; the second round
+    // brings the halo's sites (the tile's own molecules first, whose sites also fill sx).
+    // Velocities and the reference centre are requested after the pair loop, which keeps
+    // the workgroup's LDS within a quarter of the compute unit's (four workgroups per
+    // compute unit)
+    const int hn = min(a.hn[slot], a.hcap);
+    const int *hid = a.hid + (int64_t)slot * a.hcap;
     const int la = threadIdx.x, lb = la + kBlock;
     const int ida = hid[min(la, a.hcap - 1)], idb = hid[min(lb, a.hcap - 1)];
-    // (a row longer than cap exists only after an overflow, which stops every launch)
-    const int cnt = valid ? min(a.cnt[tt], a.cap) : 0;
+    // (a row longer than cap exists only after an overflow, which stops every launch; the
+    // empty tail of a short last tile has length 0)
+    const int cnt = min(a.hcnt[row], a.cap);
     const int nq = cnt > q ? (cnt - q + 3) >> 2 : 0;   // this lane's entries k = q + 4 i
-    const uint16_t *lrow = a.lnbr + (int64_t)tt * a.lcap + q * (a.lcap >> 2);
+    const uint16_t *lrow = a.lnbr + row * a.lcap + q * (a.lcap >> 2);
     uint4 ch = make_uint4(0u, 0u, 0u, 0u);
     if (nq > 0) ch = *reinterpret_cast<const uint4 *>(lrow);
     // the same decision in every wave: only an earlier launch can set halt below this step
