@@ -339,7 +339,9 @@ adres_status adres_mlp_train_step(adres_ctx *ctx, const double *com, const doubl
  * evaluation); every >= 1 records only every every-th such launch (events slow the
  * launch stream down, so sampling keeps the timed run close to an untimed one).  Other
  * values give ADRES_E_ARG.  ms (host) receives the summed duration of the launches
- * recorded before this call and launches (host) their number.  Synchronises. */
+ * recorded before this call and launches (host) their number; a launch of adres_integrate
+ * that returned at once, because an earlier kernel of its step chunk asked for a list
+ * rebuild (or a list overflow stopped the chunk), is not counted.  Synchronises. */
 adres_status adres_kernel_timing(adres_ctx *ctx, int32_t enable, int32_t every, double *ms, int64_t *launches);
 
 /* Message describing the last error of this context (never NULL). */

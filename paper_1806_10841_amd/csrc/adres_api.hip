@@ -95,6 +95,11 @@ struct adres_ctx {
     int64_t timing_count = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     size_t events_used = 0;
+    // per recorded launch: its kernel's index within the step chunk (-1 outside the step
+    // loop), and whether it returned at once (an earlier kernel of its chunk asked for a
+    // rebuild, or a list overflow stopped the chunk): such launches are not counted
+    std::vector<int> event_k;
+    std::vector<char> event_skip;
 
     std::string err = "no error";
 };
@@ -168,10 +173,17 @@ uint32_t spread3(uint32_t v)
 // host polls (cheaper than a copy plus a stream synchronisation).  Converts latched
 // error bits into a status and clears them.  With reset_halt the same kernel then clears
 // the device's halt index and overflow report.
-adres_status read_ctrl(adres_ctx *c, bool reset_halt = false)
+// The publication is launched and waited for separately by the step loop, which enqueues
+// more work between the two.
+unsigned publish_ctrl(adres_ctx *c, bool reset_halt, int len_drift = 0)
 {
     const unsigned seq = ++c->pub_seq;
-    launch_publish(c->stream, c->ctrl, c->pub_dev, seq, reset_halt);
+    launch_publish(c->stream, c->ctrl, c->pub_dev, seq, reset_halt, len_drift);
+    return seq;
+}
+
+adres_status wait_ctrl(adres_ctx *c, unsigned seq)
+{
     HIPCHK(c, hipGetLastError());
     const auto t0 = std::chrono::steady_clock::now();
     for (long spin = 0; __atomic_load_n(&c->pub->seq, __ATOMIC_ACQUIRE) != seq; ++spin) {
@@ -198,6 +210,11 @@ adres_status read_ctrl(adres_ctx *c, bool reset_halt = false)
     return ADRES_OK;
 }
 
+adres_status read_ctrl(adres_ctx *c, bool reset_halt = false)
+{
+    return wait_ctrl(c, publish_ctrl(c, reset_halt));
+}
+
 adres_status gather(adres_ctx *c, const double *x, const double *v, bool check_disp)
 {
     launch_gather(c->stream, c->P, x, v, cur(c), check_disp ? c->R_ref : nullptr, c->ctrl);
@@ -208,27 +225,41 @@ adres_status gather(adres_ctx *c, const double *x, const double *v, bool check_d
     return ADRES_OK;
 }
 
-adres_status resort(adres_ctx *c, bool with_v)
+// Morton reorder: the launches (guarded by go when non-null: a rebuild enqueued before the
+// host knows whether it is needed) and the host's bookkeeping once it has run
+void enqueue_resort(adres_ctx *c, bool with_v, const int *go)
 {
     const StateBufs src = cur(c);
     const StateBufs dst = view(c, 1 - c->pos, 1 - c->ord);
-    if (c->rw_stale) {   // the step kernels moved the positions without storing centres
-        launch_centres_keys(c->stream, c->P, c->G, c->cell_rank, src.x, src.Rw, src.key, c->count);
-        c->rw_stale = false;
-    } else {
-        launch_cell_keys(c->stream, c->P, c->G, c->cell_rank, src.Rw, src.key, c->count);
-    }
-    launch_scan_cells(c->stream, c->count, c->G.n_cells, c->start, c->fill, c->scan_tiles);
-    launch_scatter_slots(c->stream, c->P.n_mol, src.key, c->start, c->fill, c->new_from);
-    launch_sort_within_cells(c->stream, c->G.n_cells, c->start, src.perm, c->new_from);
-    launch_permute(c->stream, c->P, c->new_from, src, dst, c->inv_perm, c->R_ref, with_v);
+    // (each position-reading kernel also gets the other position buffer, which a guarded
+    // rebuild reads instead when the chunk's positions sit there: Ctrl::fix)
+    if (c->rw_stale)   // the step kernels moved the positions without storing centres
+        launch_centres_keys(c->stream, c->P, c->G, c->cell_rank, src.x, src.Rw, src.key, c->count, go, dst.x,
+                            dst.Rw);
+    else
+        launch_cell_keys(c->stream, c->P, c->G, c->cell_rank, src.Rw, src.key, c->count, go, dst.Rw);
+    launch_scan_cells(c->stream, c->count, c->G.n_cells, c->start, c->fill, c->scan_tiles, go);
+    launch_scatter_slots(c->stream, c->P.n_mol, src.key, c->start, c->fill, c->new_from, go);
+    launch_sort_within_cells(c->stream, c->G.n_cells, c->start, src.perm, c->new_from, go);
+    launch_permute(c->stream, c->P, c->new_from, src, dst, c->inv_perm, c->R_ref, with_v, go);
     // the nearest-anchor offsets are per slot: recompute them in the new order
     if (c->P.region == ADRES_REGION_SPHERES)
-        launch_anchor_weights(c->stream, c->P, dst.Rw, c->inv_perm, c->aslot, 1, c->ctrl, 0, 0, c->near);
-    HIPCHK(c, hipGetLastError());
+        launch_anchor_weights(c->stream, c->P, dst.Rw, c->inv_perm, c->aslot, 1, c->ctrl, 0, 0, c->near, go, src.Rw);
+}
+
+void commit_resort(adres_ctx *c)
+{
+    c->rw_stale = false;
     c->pos = 1 - c->pos;
     c->ord = 1 - c->ord;
     c->list_valid = false;
+}
+
+adres_status resort(adres_ctx *c, bool with_v)
+{
+    enqueue_resort(c, with_v, nullptr);
+    HIPCHK(c, hipGetLastError());
+    commit_resort(c);
     return ADRES_OK;
 }
 
@@ -264,10 +295,10 @@ adres_status alloc_halo(adres_ctx *c, int hcap)
     return ADRES_OK;
 }
 
-void launch_halo(adres_ctx *c)
+void launch_halo(adres_ctx *c, const int *go = nullptr)
 {
     launch_halo_build(c->stream, c->P.n_mol, c->nbr, c->cnt, c->cap, c->hcap, c->lcap, c->mcost, c->tile_pos,
-                      c->hid, c->hn, c->hcnt, c->lnbr, c->tperm, c->ctrl);
+                      c->hid, c->hn, c->hcnt, c->lnbr, c->tperm, c->ctrl, go);
 }
 
 // Every unordered pair of the Verlet list once (t < u) and, for every list entry, the
@@ -375,22 +406,37 @@ adres_status build_list(adres_ctx *c)
 }
 
 // Verlet list without waiting: an overflowing row sets ctrl->halt = -1, which stops
-// every kernel of the next step chunk; the host then regrows (regrow_list).
-adres_status build_list_async(adres_ctx *c)
+// every kernel of the next step chunk; the host then regrows (regrow_list).  With go, the
+// launches are guarded (see enqueue_resort) and the half list reuses its allocation, which
+// only a synchronous regrow enlarges.
+adres_status enqueue_list(adres_ctx *c, const int *go)
 {
     // overflow / max_count were cleared by the halt reset launched before the reorder
     const StateBufs b = cur(c);
     launch_list_build(c->stream, c->P, c->G, c->stencil, c->start, b.Rw, c->rl2, c->nbr, c->cnt, c->cap,
-                      c->mcost, c->ctrl);
-    launch_tile_order(c->stream, c->P, c->mcost, c->epart_blocks, c->tile_order, c->tile_pos);
+                      c->mcost, c->ctrl, go, view(c, 1 - c->pos, c->ord).Rw);
+    launch_tile_order(c->stream, c->P, c->mcost, c->epart_blocks, c->tile_order, c->tile_pos, go);
     HIPCHK(c, hipGetLastError());
-    c->list_valid = true;
     if (is_mlp(c)) {
-        adres_status st = build_half_list(c);
-        if (st != ADRES_OK) return st;
+        if (go) {
+            if (c->half_rows_cap < c->cap) return fail(c, ADRES_E_STATE, "half list smaller than the list");
+            launch_half_list(c->stream, c->P.n_mol, c->nbr, c->cnt, c->cap, c->cnt_up, c->up_off, c->up_scratch,
+                             c->up_pairs, c->half_pairs_cap, c->pid, go);
+        } else {
+            adres_status st = build_half_list(c);
+            if (st != ADRES_OK) return st;
+        }
     }
-    launch_halo(c);
+    launch_halo(c, go);
     HIPCHK(c, hipGetLastError());
+    return ADRES_OK;
+}
+
+adres_status build_list_async(adres_ctx *c)
+{
+    adres_status st = enqueue_list(c, nullptr);
+    if (st != ADRES_OK) return st;
+    c->list_valid = true;
     return ADRES_OK;
 }
 
@@ -437,8 +483,14 @@ adres_status run_forces(adres_ctx *c, ForceArgs a)
             HIPCHK(c, hipEventCreate(&q));
             c->events.emplace_back(p, q);
         }
+        if (c->event_k.size() < c->events.size()) {
+            c->event_k.resize(c->events.size());
+            c->event_skip.resize(c->events.size());
+        }
         e0 = c->events[c->events_used].first;
         e1 = c->events[c->events_used].second;
+        c->event_k[c->events_used] = a.check_halt ? a.step : -1;
+        c->event_skip[c->events_used] = 0;
         ++c->events_used;
     }
     if (is_mlp(c) && a.slow_scale != 0.0) {
@@ -667,7 +719,7 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     }
     std::vector<int> ident(n);
     for (int i = 0; i < n; ++i) ident[i] = i;
-    Ctrl c0{INT_MAX, 0, 0, 0, 0};
+    Ctrl c0{INT_MAX, 0, 0, 0, 0, 0, 0};
     bool cp = hipMemcpy(c->cell_rank, rank.data(), sizeof(int) * G.n_cells, hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->S[0].perm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->S[1].perm, ident.data(), sizeof(int) * n, hipMemcpyHostToDevice) == hipSuccess &&
@@ -844,10 +896,15 @@ adres_status integrate_impl(adres_ctx *c, double *x, double *v, double *f, doubl
     int rebuilds = 0;
     int g = 0;
     int since = 0;   // kernels since the last rebuild
+    const int *go = &c->ctrl->go;
     launch_reset_halt(c->stream, c->ctrl);
     while (g <= n_steps && n_steps > 0) {
-        const int len = std::min(std::max(2, c->last_interval - since), n_steps + 1 - g);
+        // one kernel past the expected rebuild: a chunk without one costs a rebuild's worth of
+        // guarded launches that return at once, one past it only a kernel that does
+        const int len = std::min(std::max(2, c->last_interval - since) + 1, n_steps + 1 - g);
         int p = c->pos;
+        int len_drift = 0;
+        const size_t ev0 = c->events_used;   // this chunk's timed launches start here
         for (int k = 0; k < len; ++k) {
             const int gk = g + k;
             StepArgs sa{dt, gamma, kT, seed, c->step_counter + (uint64_t)gk};
@@ -884,11 +941,41 @@ adres_status integrate_impl(adres_ctx *c, double *x, double *v, double *f, doubl
                     HIPCHK(c, hipGetLastError());
                 }
             }
-            if (gk < n_steps) p = 1 - p;
+            if (gk < n_steps) {
+                p = 1 - p;
+                ++len_drift;
+            }
         }
-        st = read_ctrl(c, true);   // the one synchronisation per chunk; clears halt
+        // The chunk's publication (which also clears halt), then, without waiting for it, a
+        // reorder + list rebuild that runs only if a drift asked for one (Ctrl::go): the GPU
+        // goes on while the host reads the publication.  The rebuild is enqueued as if every
+        // drift ran (positions in buffer p); if an odd number did not, its kernels read the
+        // other buffer (Ctrl::fix).  The host keeps the rebuild's bookkeeping only if it ran.
+        const unsigned seq = publish_ctrl(c, true, len_drift);
+        c->pos = p;
+        const int pos0 = c->pos, ord0 = c->ord;
+        const bool stale0 = c->rw_stale, valid0 = c->list_valid;
+        enqueue_resort(c, true, go);
+        commit_resort(c);
+        st = enqueue_list(c, go);
+        if (st != ADRES_OK) return st;
+        c->list_valid = true;
+        st = wait_ctrl(c, seq);   // the one synchronisation per chunk
         if (st != ADRES_OK) return st;
         const int h = c->ctrl_host->halt;
+        for (size_t i = ev0; i < c->events_used; ++i)
+            if (c->event_k[i] >= 0 && (h < 0 || (h != INT_MAX && c->event_k[i] > h))) c->event_skip[i] = 1;
+        // the drifts that ran, and whether the positions sit in the other buffer (as on the device)
+        const int ran_drift = h == INT_MAX ? len_drift : (h < 0 ? 0 : std::min(h + 1, len_drift));
+        const int fix = (len_drift - ran_drift) & 1;
+        if (h < 0 || h == INT_MAX) {   // the rebuild did not run
+            c->pos = pos0 ^ fix;
+            c->ord = ord0;
+            c->rw_stale = stale0;
+            c->list_valid = valid0;
+        } else {
+            c->pos = pos0 ^ fix ^ 1;   // the reorder wrote the buffer its source was not in
+        }
         if (h < 0) {
             // the last list build overflowed: nothing of this chunk ran; regrow, rebuild
             st = build_list(c);
@@ -896,16 +983,10 @@ adres_status integrate_impl(adres_ctx *c, double *x, double *v, double *f, doubl
             continue;
         }
         const int ran = h == INT_MAX ? len : h + 1;   // kernels that completed
-        for (int k = 0; k < ran; ++k)
-            if (g + k < n_steps) c->pos = 1 - c->pos;
         g += ran;
         since += ran;
         if (h == INT_MAX) continue;
-        // kernel g-1 drifted and asked for a rebuild: reorder and rebuild the list (no wait)
-        st = resort(c, true);
-        if (st != ADRES_OK) return st;
-        st = build_list_async(c);
-        if (st != ADRES_OK) return st;
+        // kernel g-1 drifted, asked for a rebuild, and the rebuild ran
         ++rebuilds;
         c->last_interval = std::max(2, since);
         since = 0;
@@ -1273,13 +1354,16 @@ adres_status adres_kernel_timing(adres_ctx *c, int32_t enable, int32_t every, do
     if (enable < 0 || enable > 2 || every < 1) return fail(c, ADRES_E_ARG, "timing mode must be 0, 1 or 2 and every >= 1");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double sum = 0.0;
+    int64_t counted = 0;
     for (size_t i = 0; i < c->events_used; ++i) {
+        if (c->event_skip[i]) continue;
         float t = 0.0f;
         HIPCHK(c, hipEventElapsedTime(&t, c->events[i].first, c->events[i].second));
         sum += t;
+        ++counted;
     }
     if (ms) *ms = sum;
-    if (launches) *launches = (int64_t)c->events_used;
+    if (launches) *launches = counted;
     c->events_used = 0;
     c->timing = enable;
     c->timing_every = every;

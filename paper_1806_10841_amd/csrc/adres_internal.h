@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "adres.h"
@@ -28,7 +29,14 @@ struct Ctrl {
                     // neighbour halo larger than its capacity
     int max_count;  // longest neighbour-list row seen by the last build
     int max_halo;   // largest tile halo seen by the last halo build (on overflow)
+    // set by the publication that ends a step chunk: go = a drift asked for a rebuild (the
+    // rebuild enqueued behind the chunk runs; else its kernels return at once); fix = the
+    // positions sit in the other buffer than the one the host assumed, because an odd
+    // number of the chunk's drifts did not run (the rebuild's kernels then exchange the two
+    // position buffers; a guarded kernel finds fix right after go)
+    int go, fix;
 };
+static_assert(offsetof(Ctrl, fix) == offsetof(Ctrl, go) + sizeof(int), "fix follows go");
 
 // Copy of the control block in host-mapped pinned memory, published by a one-thread
 // kernel after the work it reports on; the host polls seq instead of synchronising
@@ -469,30 +477,34 @@ void launch_kick_drift(hipStream_t s, const DevParams &P, const double *x_in, do
 // centres and weights of the sorted state from its positions (before a reorder, when the
 // step kernels have not kept them) and the cell keys of launch_cell_keys, in one pass
 void launch_centres_keys(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank, const double *x,
-                         double4 *Rw, int *key, int *count);
+                         double4 *Rw, int *key, int *count, const int *go = nullptr, const double *x_alt = nullptr,
+                         double4 *Rw_alt = nullptr);
 void launch_reset_halt(hipStream_t s, Ctrl *ctrl);
-void launch_publish(hipStream_t s, Ctrl *ctrl, CtrlPub *pub, unsigned seq, bool reset);
+// len_drift: the drifting kernels of the step chunk the publication ends (0 elsewhere)
+void launch_publish(hipStream_t s, Ctrl *ctrl, CtrlPub *pub, unsigned seq, bool reset, int len_drift = 0);
 void launch_map_cg(hipStream_t s, const DevParams &P, const double *x, const double *f, double *com, double *fmap);
 
 // cell list
 void launch_cell_keys(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank,
-                      const double4 *Rw, int *key, int *count);
+                      const double4 *Rw, int *key, int *count, const int *go = nullptr,
+                      const double4 *Rw_alt = nullptr);
 // exclusive scan of count[0..n) into start[0..n] (start[n] = total); resets count (and
 // fill if non-null); tiles: scratch of at least n / 1024 + 1 ints; n <= scan_max_elements()
-void launch_scan_cells(hipStream_t s, int *count, int n, int *start, int *fill, int *tiles);
+void launch_scan_cells(hipStream_t s, int *count, int n, int *start, int *fill, int *tiles, const int *go = nullptr);
 int scan_max_elements();
 void launch_scatter_slots(hipStream_t s, int n_mol, const int *key, const int *start, int *fill,
-                          int *new_from);
+                          int *new_from, const int *go = nullptr);
 void launch_sort_within_cells(hipStream_t s, int n_cells, const int *start, const int *perm_old,
-                              int *new_from);
+                              int *new_from, const int *go = nullptr);
 void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, const StateBufs &src,
-                    const StateBufs &dst, int *inv_perm, double4 *R_ref, bool with_v);
+                    const StateBufs &dst, int *inv_perm, double4 *R_ref, bool with_v, const int *go = nullptr);
 
 // Verlet list: ELL, row-major nbr[slot * cap + k]; each row is padded with the
 // row's own slot up to a multiple of 4 entries (cap is a multiple of 4).
 // stencil: rank-major [n_cells][27] neighbour cell ranks, -1 = skipped (fixed at set-up)
 void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const int *stencil, const int *start,
-                       const double4 *Rw, double rl2, int *nbr, int *cnt, int cap, unsigned *mcost, Ctrl *ctrl);
+                       const double4 *Rw, double rl2, int *nbr, int *cnt, int cap, unsigned *mcost, Ctrl *ctrl,
+                       const int *go = nullptr, const double4 *Rw_alt = nullptr);
 
 // Neighbour halo of every force-kernel tile (64 consecutive slots), stored at the tile's
 // dispatch position p = tile_pos[tile] (launch_tile_order), so that the force kernel's
@@ -509,7 +521,7 @@ void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const i
 constexpr int kHaloTile = 64;
 void launch_halo_build(hipStream_t s, int n_mol, const int *nbr, const int *cnt, int cap, int hcap, int lcap,
                        const unsigned *mcost, const int *tile_pos, int *hid, int *hn, int *hcnt, uint16_t *lnbr,
-                       uint8_t *tperm, Ctrl *ctrl);
+                       uint8_t *tperm, Ctrl *ctrl, const int *go = nullptr);
 // LDS bytes of the force kernel's halo staging per halo molecule, and the largest halo
 // capacity that fits a workgroup's LDS
 int halo_stride_bytes(int spm, int pair_precision);
@@ -517,7 +529,7 @@ int halo_capacity_limit(int spm, int pair_precision);
 
 // half list (t < u pairs) + per-entry pair ids; up_off receives n + 1 offsets
 void launch_half_list(hipStream_t s, int n, int *nbr, const int *cnt, int cap, int *cnt_up, int *up_off,
-                      int *scratch, int2 *pairs, int64_t pairs_cap, int *pid);
+                      int *scratch, int2 *pairs, int64_t pairs_cap, int *pid, const int *go = nullptr);
 
 // forces
 enum ForceMode : int {
@@ -569,7 +581,7 @@ void launch_energy_reduce(hipStream_t s, const double *epart, int n_blocks, doub
 
 // workgroup dispatch order of the force kernel, rebuilt with the list (k_cells.hip):
 // order[p] is the tile dispatched as workgroup p, pos[tile] its inverse
-void launch_tile_order(hipStream_t s, const DevParams &P, const unsigned *mcost, int n_tiles, int *order, int *pos);
+void launch_tile_order(hipStream_t s, const DevParams &P, const unsigned *mcost, int n_tiles, int *order, int *pos, const int *go = nullptr);
 
 // correction force (k_state.hip)
 constexpr int kTdMaxBins = 4096;
@@ -593,7 +605,8 @@ constexpr int kAnchorCells = kAnchorGrid * kAnchorGrid * kAnchorGrid;
 // aslot [n_anchors]: the anchors' slots, refreshed from inv_perm when refresh is set (after
 // every reorder), read otherwise
 void launch_anchor_weights(hipStream_t s, const DevParams &P, double4 *Rw, const int *inv_perm, int *aslot,
-                           int refresh, Ctrl *ctrl, int step, int check_halt, double4 *near);
+                           int refresh, Ctrl *ctrl, int step, int check_halt, double4 *near, const int *go = nullptr,
+                           double4 *Rw_alt = nullptr);
 void launch_anchor_weights_caller(hipStream_t s, const DevParams &P, const double *com, double *w);
 
 }  // namespace adres

@@ -23,10 +23,14 @@ constexpr int kBlock = 256;
 
 inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
-__global__ __launch_bounds__(kBlock) void k_cell_keys(DevParams P, Grid G, const int *__restrict__ cell_rank,
+__global__ __launch_bounds__(kBlock) void k_cell_keys(const int *__restrict__ go, DevParams P, Grid G, const int *__restrict__ cell_rank,
                                                       const double4 *__restrict__ Rw, int *__restrict__ key,
-                                                      int *__restrict__ count)
+                                                      int *__restrict__ count, const double4 *__restrict__ Rw_alt)
 {
+    if (go && *go == 0) return;   // a guarded rebuild that was not asked for
+    // (go points at Ctrl::go, followed by Ctrl::fix: the chunk's positions sit in the other buffer)
+    const bool sw = go && go[1] != 0;
+    if (sw) Rw = Rw_alt;
     int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= P.n_mol) return;
     const double4 r = Rw[t];
@@ -67,9 +71,10 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int &total)
     return before + incl - v;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int *__restrict__ count, int n,
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int *__restrict__ go, const int *__restrict__ count, int n,
                                                              int *__restrict__ start, int *__restrict__ tiles)
 {
+    if (go && *go == 0) return;   // a guarded rebuild that was not asked for
     const int base = blockIdx.x * kScanTile + 4 * threadIdx.x;
     int c[4];
 #pragma unroll
@@ -88,10 +93,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int *__restri
 // Second pass: workgroup T adds the sum of the tile totals before tile T to its tile
 // (each workgroup sums at most kScanTile totals itself), resets count and fill for the
 // next build, and the last workgroup writes start[n], the grand total.
-__global__ __launch_bounds__(kScanThreads) void k_scan_add(int *__restrict__ count, int n, int *__restrict__ start,
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(const int *__restrict__ go, int *__restrict__ count, int n, int *__restrict__ start,
                                                            const int *__restrict__ tiles, int n_tiles,
                                                            int *__restrict__ fill)
 {
+    if (go && *go == 0) return;   // a guarded rebuild that was not asked for
     const int T = blockIdx.x;
     int part = 0;
 #pragma unroll
@@ -113,10 +119,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(int *__restrict__ cou
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter_slots(int n_mol, const int *__restrict__ key,
+__global__ __launch_bounds__(kBlock) void k_scatter_slots(const int *__restrict__ go, int n_mol, const int *__restrict__ key,
                                                           const int *__restrict__ start, int *__restrict__ fill,
                                                           int *__restrict__ new_from)
 {
+    if (go && *go == 0) return;   // a guarded rebuild that was not asked for
     int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n_mol) return;
     int k = key[i];
@@ -130,10 +137,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter_slots(int n_mol, const int *
 // smaller caller index; indices are distinct); larger cells use an insertion sort.
 constexpr int kSortCell = 16;
 
-__global__ __launch_bounds__(kBlock) void k_sort_within_cells(int n_cells, const int *__restrict__ start,
+__global__ __launch_bounds__(kBlock) void k_sort_within_cells(const int *__restrict__ go, int n_cells, const int *__restrict__ start,
                                                               const int *__restrict__ perm_old,
                                                               int *__restrict__ new_from)
 {
+    if (go && *go == 0) return;   // a guarded rebuild that was not asked for
     int c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= n_cells) return;
     const int lo = start[c], hi = start[c + 1], m = hi - lo;
@@ -176,10 +184,17 @@ template <int SPM>
 constexpr int perm_lanes() { return SPM == 1 ? 1 : (SPM == 2 ? 2 : 4); }
 
 template <int SPM>
-__global__ __launch_bounds__(kBlock) void k_permute(DevParams P, const int *__restrict__ new_from, StateBufs src,
+__global__ __launch_bounds__(kBlock) void k_permute(const int *__restrict__ go, DevParams P, const int *__restrict__ new_from, StateBufs src,
                                                     StateBufs dst, int *__restrict__ inv_perm,
                                                     double4 *__restrict__ R_ref, int with_v)
 {
+    if (go && *go == 0) return;   // a guarded rebuild that was not asked for
+    // (go points at Ctrl::go, followed by Ctrl::fix: the chunk's positions sit in the other buffer)
+    const bool sw = go && go[1] != 0;
+    if (sw) {   // the source positions are in the destination's buffer and the other way round
+        double *tx = src.x; src.x = dst.x; dst.x = tx;
+        double4 *tr = src.Rw; src.Rw = dst.Rw; dst.Rw = tr;
+    }
     constexpr int L = perm_lanes<SPM>();
     static_assert(SPM <= L, "one lane per site");
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -233,12 +248,17 @@ __global__ __launch_bounds__(kBlock) void k_permute(DevParams P, const int *__re
 // work per (home, candidate) test is the FP64 minimum-image distance and the ballot.
 constexpr int kCmWaves = 4;
 
-__global__ __launch_bounds__(kBlock) void k_list_build_cm(DevParams P, int n_cells, const int *__restrict__ stencil,
+__global__ __launch_bounds__(kBlock) void k_list_build_cm(const int *__restrict__ go, DevParams P, int n_cells, const int *__restrict__ stencil,
                                                           const int *__restrict__ start,
                                                           const double4 *__restrict__ Rw, double rl2,
                                                           int *__restrict__ nbr, int *__restrict__ cnt, int cap,
-                                                          unsigned *__restrict__ mcost, Ctrl *ctrl)
+                                                          unsigned *__restrict__ mcost, Ctrl *ctrl,
+                                                          const double4 *__restrict__ Rw_alt)
 {
+    if (go && *go == 0) return;   // a guarded rebuild that was not asked for
+    // (go points at Ctrl::go, followed by Ctrl::fix: the chunk's positions sit in the other buffer)
+    const bool sw = go && go[1] != 0;
+    if (sw) Rw = Rw_alt;
     __shared__ int s_lo[kCmWaves][32], s_ex[kCmWaves][32];
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int r = blockIdx.x * kCmWaves + wv;
@@ -341,9 +361,10 @@ __global__ __launch_bounds__(kBlock) void k_list_build_cm(DevParams P, int n_cel
 // and by binary search for t in the sorted row u for u < t (the list is symmetric).
 constexpr int kSortRows = kBlock / 32;
 
-__global__ __launch_bounds__(kBlock) void k_sort_rows(int n, int *__restrict__ nbr, const int *__restrict__ cnt,
+__global__ __launch_bounds__(kBlock) void k_sort_rows(const int *__restrict__ go, int n, int *__restrict__ nbr, const int *__restrict__ cnt,
                                                      int cap, int *__restrict__ cnt_up)
 {
+    if (go && *go == 0) return;   // a guarded rebuild that was not asked for
     extern __shared__ int srow[];   // kSortRows rows of cap entries
     const int g = threadIdx.x >> 5, lane = threadIdx.x & 31;
     const int t = blockIdx.x * kSortRows + g;
@@ -367,10 +388,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_rows(int n, int *__restrict__ n
     if (t < n && lane == 0) cnt_up[t] = c - below;
 }
 
-__global__ __launch_bounds__(kBlock) void k_up_entries(int n, const int *__restrict__ nbr, const int *__restrict__ cnt,
+__global__ __launch_bounds__(kBlock) void k_up_entries(const int *__restrict__ go, int n, const int *__restrict__ nbr, const int *__restrict__ cnt,
                                                       int cap, const int *__restrict__ up_off, int2 *__restrict__ pairs,
                                                       int64_t pairs_cap, int *__restrict__ pid)
 {
+    if (go && *go == 0) return;   // a guarded rebuild that was not asked for
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= (int64_t)n * cap) return;
     const int t = (int)(e / cap), k = (int)(e - (int64_t)t * cap);
@@ -399,57 +421,58 @@ __global__ __launch_bounds__(kBlock) void k_up_entries(int n, const int *__restr
 }  // namespace
 
 void launch_half_list(hipStream_t s, int n, int *nbr, const int *cnt, int cap, int *cnt_up, int *up_off,
-                      int *scratch, int2 *pairs, int64_t pairs_cap, int *pid)
+                      int *scratch, int2 *pairs, int64_t pairs_cap, int *pid, const int *go)
 {
-    k_sort_rows<<<(n + kSortRows - 1) / kSortRows, kBlock, (size_t)kSortRows * cap * sizeof(int), s>>>(n, nbr, cnt, cap,
+    k_sort_rows<<<(n + kSortRows - 1) / kSortRows, kBlock, (size_t)kSortRows * cap * sizeof(int), s>>>(go, n, nbr, cnt, cap,
                                                                                                      cnt_up);
-    launch_scan_cells(s, cnt_up, n, up_off, nullptr, scratch);
+    launch_scan_cells(s, cnt_up, n, up_off, nullptr, scratch, go);
     const int64_t entries = (int64_t)n * cap;
-    k_up_entries<<<(unsigned)((entries + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, nbr, cnt, cap, up_off, pairs, pairs_cap, pid);
+    k_up_entries<<<(unsigned)((entries + kBlock - 1) / kBlock), kBlock, 0, s>>>(go, n, nbr, cnt, cap, up_off, pairs, pairs_cap, pid);
 }
 
 void launch_cell_keys(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank,
-                      const double4 *Rw, int *key, int *count)
+                      const double4 *Rw, int *key, int *count, const int *go, const double4 *Rw_alt)
 {
-    k_cell_keys<<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, G, cell_rank, Rw, key, count);
+    k_cell_keys<<<blocks_for(P.n_mol), kBlock, 0, s>>>(go, P, G, cell_rank, Rw, key, count, Rw_alt);
 }
 
-void launch_scan_cells(hipStream_t s, int *count, int n, int *start, int *fill, int *tiles)
+void launch_scan_cells(hipStream_t s, int *count, int n, int *start, int *fill, int *tiles, const int *go)
 {
     const int n_tiles = (n + kScanTile - 1) / kScanTile;
-    k_scan_tiles<<<n_tiles, kScanThreads, 0, s>>>(count, n, start, tiles);
-    k_scan_add<<<n_tiles, kScanThreads, 0, s>>>(count, n, start, tiles, n_tiles, fill);
+    k_scan_tiles<<<n_tiles, kScanThreads, 0, s>>>(go, count, n, start, tiles);
+    k_scan_add<<<n_tiles, kScanThreads, 0, s>>>(go, count, n, start, tiles, n_tiles, fill);
 }
 
 int scan_max_elements() { return kScanTile * kScanTile; }
 
-void launch_scatter_slots(hipStream_t s, int n_mol, const int *key, const int *start, int *fill, int *new_from)
+void launch_scatter_slots(hipStream_t s, int n_mol, const int *key, const int *start, int *fill, int *new_from, const int *go)
 {
-    k_scatter_slots<<<blocks_for(n_mol), kBlock, 0, s>>>(n_mol, key, start, fill, new_from);
+    k_scatter_slots<<<blocks_for(n_mol), kBlock, 0, s>>>(go, n_mol, key, start, fill, new_from);
 }
 
-void launch_sort_within_cells(hipStream_t s, int n_cells, const int *start, const int *perm_old, int *new_from)
+void launch_sort_within_cells(hipStream_t s, int n_cells, const int *start, const int *perm_old, int *new_from, const int *go)
 {
-    k_sort_within_cells<<<blocks_for(n_cells), kBlock, 0, s>>>(n_cells, start, perm_old, new_from);
+    k_sort_within_cells<<<blocks_for(n_cells), kBlock, 0, s>>>(go, n_cells, start, perm_old, new_from);
 }
 
 void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, const StateBufs &src,
-                    const StateBufs &dst, int *inv_perm, double4 *R_ref, bool with_v)
+                    const StateBufs &dst, int *inv_perm, double4 *R_ref, bool with_v, const int *go)
 {
     const int64_t n = P.n_mol;
     switch (P.spm) {
-    case 1: k_permute<1><<<blocks_for(n * perm_lanes<1>()), kBlock, 0, s>>>(P, new_from, src, dst, inv_perm, R_ref, with_v); break;
-    case 2: k_permute<2><<<blocks_for(n * perm_lanes<2>()), kBlock, 0, s>>>(P, new_from, src, dst, inv_perm, R_ref, with_v); break;
-    case 3: k_permute<3><<<blocks_for(n * perm_lanes<3>()), kBlock, 0, s>>>(P, new_from, src, dst, inv_perm, R_ref, with_v); break;
-    default: k_permute<4><<<blocks_for(n * perm_lanes<4>()), kBlock, 0, s>>>(P, new_from, src, dst, inv_perm, R_ref, with_v); break;
+    case 1: k_permute<1><<<blocks_for(n * perm_lanes<1>()), kBlock, 0, s>>>(go, P, new_from, src, dst, inv_perm, R_ref, with_v); break;
+    case 2: k_permute<2><<<blocks_for(n * perm_lanes<2>()), kBlock, 0, s>>>(go, P, new_from, src, dst, inv_perm, R_ref, with_v); break;
+    case 3: k_permute<3><<<blocks_for(n * perm_lanes<3>()), kBlock, 0, s>>>(go, P, new_from, src, dst, inv_perm, R_ref, with_v); break;
+    default: k_permute<4><<<blocks_for(n * perm_lanes<4>()), kBlock, 0, s>>>(go, P, new_from, src, dst, inv_perm, R_ref, with_v); break;
     }
 }
 
 void launch_list_build(hipStream_t s, const DevParams &P, const Grid &G, const int *stencil, const int *start,
-                       const double4 *Rw, double rl2, int *nbr, int *cnt, int cap, unsigned *mcost, Ctrl *ctrl)
+                       const double4 *Rw, double rl2, int *nbr, int *cnt, int cap, unsigned *mcost, Ctrl *ctrl, const int *go,
+                       const double4 *Rw_alt)
 {
     const int blocks = (G.n_cells + kCmWaves - 1) / kCmWaves;
-    k_list_build_cm<<<blocks, kBlock, 0, s>>>(P, G.n_cells, stencil, start, Rw, rl2, nbr, cnt, cap, mcost, ctrl);
+    k_list_build_cm<<<blocks, kBlock, 0, s>>>(go, P, G.n_cells, stencil, start, Rw, rl2, nbr, cnt, cap, mcost, ctrl, Rw_alt);
 }
 
 namespace {
@@ -516,7 +539,7 @@ int halo_table_log2(int hcap, int tiles, int n_cu)
     return lg;
 }
 
-__global__ __launch_bounds__(kBlock) void k_halo_build(int n_mol, const int *__restrict__ nbr,
+__global__ __launch_bounds__(kBlock) void k_halo_build(const int *__restrict__ go, int n_mol, const int *__restrict__ nbr,
                                                        const int *__restrict__ cnt, int cap, int hcap, int lcap,
                                                        int lg, const unsigned *__restrict__ mcost,
                                                        const int *__restrict__ tile_pos, int *__restrict__ hid,
@@ -524,6 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_halo_build(int n_mol, const int *__r
                                                        uint16_t *__restrict__ lnbr, uint8_t *__restrict__ tperm,
                                                        Ctrl *ctrl)
 {
+    if (go && *go == 0) return;   // a guarded rebuild that was not asked for
     // keys and vals by table position, then the distinct slots compacted (key, position):
     // room for the hcap - kHaloTile a halo may hold (more overflow the capacity)
     extern __shared__ int tab[];
@@ -669,7 +693,7 @@ __global__ __launch_bounds__(kBlock) void k_halo_build(int n_mol, const int *__r
 
 void launch_halo_build(hipStream_t s, int n_mol, const int *nbr, const int *cnt, int cap, int hcap, int lcap,
                        const unsigned *mcost, const int *tile_pos, int *hid, int *hn, int *hcnt, uint16_t *lnbr,
-                       uint8_t *tperm, Ctrl *ctrl)
+                       uint8_t *tperm, Ctrl *ctrl, const int *go)
 {
     const int tiles = (n_mol + kHaloTile - 1) / kHaloTile;
     int dev = 0, n_cu = 0;
@@ -678,7 +702,7 @@ void launch_halo_build(hipStream_t s, int n_mol, const int *nbr, const int *cnt,
         n_cu = 0;
     const int lg = halo_table_log2(hcap, tiles, n_cu);
     const size_t lds = ((size_t)6 << lg) + (size_t)8 * (hcap - kHaloTile);
-    k_halo_build<<<tiles, kBlock, lds, s>>>(n_mol, nbr, cnt, cap, hcap, lcap, lg, mcost, tile_pos, hid, hn, hcnt, lnbr,
+    k_halo_build<<<tiles, kBlock, lds, s>>>(go, n_mol, nbr, cnt, cap, hcap, lcap, lg, mcost, tile_pos, hid, hn, hcnt, lnbr,
                                             tperm, ctrl);
 }
 
@@ -712,9 +736,10 @@ __device__ __forceinline__ unsigned long long tile_key(unsigned cost, int i)
     return (chunk << 52) | ((unsigned long long)(cost & 0xFFFFFu) << 32) | (unsigned)(~(unsigned)i);
 }
 
-__global__ __launch_bounds__(kTileThreads) void k_tile_order(int n_mol, const unsigned *__restrict__ mcost, int n_tiles,
+__global__ __launch_bounds__(kTileThreads) void k_tile_order(const int *__restrict__ go, int n_mol, const unsigned *__restrict__ mcost, int n_tiles,
                                                             int *__restrict__ order, int *__restrict__ pos)
 {
+    if (go && *go == 0) return;   // a guarded rebuild that was not asked for
     __shared__ unsigned tcost[kTileSortMax];
     __shared__ unsigned long long key[kTileSortMax];
     const int x = blockIdx.x;
@@ -818,9 +843,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_order(int n_mol, const un
 
 }  // namespace
 
-void launch_tile_order(hipStream_t s, const DevParams &P, const unsigned *mcost, int n_tiles, int *order, int *pos)
+void launch_tile_order(hipStream_t s, const DevParams &P, const unsigned *mcost, int n_tiles, int *order, int *pos, const int *go)
 {
-    k_tile_order<<<8, kTileThreads, 0, s>>>(P.n_mol, mcost, n_tiles, order, pos);
+    k_tile_order<<<8, kTileThreads, 0, s>>>(go, P.n_mol, mcost, n_tiles, order, pos);
 }
 
 }  // namespace adres

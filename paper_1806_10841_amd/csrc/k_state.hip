@@ -79,10 +79,18 @@ __global__ __launch_bounds__(kBlock) void k_gather(DevParams P, const double *__
 // follows (what k_cell_keys derives from Rw): one pass over the positions instead of two.
 // The weight of a self-adjusting region is written by its own pass and kept.
 template <int SPM>
-__global__ __launch_bounds__(kBlock) void k_centres_keys(DevParams P, Grid G, const int *__restrict__ cell_rank,
+__global__ __launch_bounds__(kBlock) void k_centres_keys(const int *__restrict__ go, DevParams P, Grid G, const int *__restrict__ cell_rank,
                                                          const double *__restrict__ x, double4 *__restrict__ Rw,
-                                                         int *__restrict__ key, int *__restrict__ count)
+                                                         int *__restrict__ key, int *__restrict__ count,
+                                                         const double *__restrict__ x_alt, double4 *__restrict__ Rw_alt)
 {
+    if (go && *go == 0) return;   // a guarded rebuild that was not asked for
+    // (go points at Ctrl::go, followed by Ctrl::fix: the chunk's positions sit in the other buffer)
+    const bool sw = go && go[1] != 0;
+    if (sw) {
+        x = x_alt;
+        Rw = Rw_alt;
+    }
     int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= P.n_mol) return;
     double p[SPM][3];
@@ -391,11 +399,16 @@ __host__ __device__ inline size_t anchor_lds_bytes(int K, int n_cells)
     return (size_t)K * 24 + (size_t)(2 * n_cells + 1) * 4 + (size_t)K * 4 + 16;
 }
 
-__global__ __launch_bounds__(kBlock) void k_anchor_weights(DevParams P, double4 *Rw, const int *__restrict__ inv_perm,
+__global__ __launch_bounds__(kBlock) void k_anchor_weights(const int *__restrict__ go, DevParams P, double4 *Rw, const int *__restrict__ inv_perm,
                                                            int *aslot, int refresh, Ctrl *ctrl, int step,
-                                                           int check_halt, double4 *__restrict__ near, int3 nc)
+                                                           int check_halt, double4 *__restrict__ near, int3 nc,
+                                                           double4 *Rw_alt)
 {
 #pragma clang fp contract(off)
+    if (go && *go == 0) return;   // a guarded rebuild that was not asked for
+    // (go points at Ctrl::go, followed by Ctrl::fix: the chunk's positions sit in the other buffer)
+    const bool sw = go && go[1] != 0;
+    if (sw) Rw = Rw_alt;
     extern __shared__ __align__(16) unsigned char als[];
     __shared__ int wsum[kBlock / 64];
     const int K = P.n_anchors;
@@ -550,7 +563,7 @@ __global__ __launch_bounds__(kBlock) void k_anchor_weights_caller(DevParams P, c
 
 // With reset, also clears the halt index and the list-overflow report once they have been
 // copied (what k_reset_halt does), saving the step loop a launch per chunk.
-__global__ void k_publish(Ctrl *__restrict__ ctrl, CtrlPub *pub, unsigned seq, int reset)
+__global__ void k_publish(Ctrl *__restrict__ ctrl, CtrlPub *pub, unsigned seq, int reset, int len_drift)
 {
     if (threadIdx.x != 0) return;
     volatile CtrlPub *p = pub;
@@ -563,12 +576,19 @@ __global__ void k_publish(Ctrl *__restrict__ ctrl, CtrlPub *pub, unsigned seq, i
     p->seq = seq;
     __threadfence_system();
     if (reset) {
+        // the chunk's drifts that ran: all, none (a list overflow stopped the chunk), or up to
+        // and including the one that asked for the rebuild
+        const int h = ctrl->halt;
+        const int ran = h == INT_MAX ? len_drift : (h < 0 ? 0 : min(h + 1, len_drift));
+        ctrl->go = (h >= 0 && h != INT_MAX) ? 1 : 0;
+        ctrl->fix = (len_drift - ran) & 1;
         ctrl->halt = INT_MAX;
         ctrl->overflow = 0;
         ctrl->max_count = 0;
         ctrl->max_halo = 0;
     }
 }
+
 
 // clears the halt index and the list-overflow report (a fill kernel, so that no
 // memset node is needed between the launches of a step loop)
@@ -621,18 +641,18 @@ void launch_kick_drift(hipStream_t s, const DevParams &P, const double *x_in, do
 }
 
 void launch_centres_keys(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank, const double *x,
-                         double4 *Rw, int *key, int *count)
+                         double4 *Rw, int *key, int *count, const int *go, const double *x_alt, double4 *Rw_alt)
 {
-    ADRES_SPM_DISPATCH(P.spm, (k_centres_keys<S_><<<blocks_for(P.n_mol), kBlock, 0, s>>>(P, G, cell_rank, x, Rw,
-                                                                                         key, count)));
+    ADRES_SPM_DISPATCH(P.spm, (k_centres_keys<S_><<<blocks_for(P.n_mol), kBlock, 0, s>>>(go, P, G, cell_rank, x, Rw,
+                                                                                         key, count, x_alt, Rw_alt)));
 }
 
 
 void launch_reset_halt(hipStream_t s, Ctrl *ctrl) { k_reset_halt<<<1, 64, 0, s>>>(ctrl); }
 
-void launch_publish(hipStream_t s, Ctrl *ctrl, CtrlPub *pub, unsigned seq, bool reset)
+void launch_publish(hipStream_t s, Ctrl *ctrl, CtrlPub *pub, unsigned seq, bool reset, int len_drift)
 {
-    k_publish<<<1, 64, 0, s>>>(ctrl, pub, seq, reset ? 1 : 0);
+    k_publish<<<1, 64, 0, s>>>(ctrl, pub, seq, reset ? 1 : 0, len_drift);
 }
 
 void launch_map_cg(hipStream_t s, const DevParams &P, const double *x, const double *f, double *com, double *fmap)
@@ -666,7 +686,8 @@ void launch_td_update(hipStream_t s, const DevParams &P, double *td, double *td_
 }
 
 void launch_anchor_weights(hipStream_t s, const DevParams &P, double4 *Rw, const int *inv_perm, int *aslot,
-                           int refresh, Ctrl *ctrl, int step, int check_halt, double4 *near)
+                           int refresh, Ctrl *ctrl, int step, int check_halt, double4 *near, const int *go,
+                           double4 *Rw_alt)
 {
     // reach: where the weight and the correction force stop changing (the table's end
     // only while one is installed), padded by 2^-20 of itself; cells at least that wide
@@ -677,7 +698,7 @@ void launch_anchor_weights(hipStream_t s, const DevParams &P, double4 *Rw, const
     for (int d = 0; d < 3; ++d) g[d] = std::max(1, std::min(kAnchorGrid, (int)std::floor(P.box[d] / reach)));
     const int blocks = (P.n_mol + kAnchorMols - 1) / kAnchorMols;
     k_anchor_weights<<<blocks, kBlock, anchor_lds_bytes(P.n_anchors, g[0] * g[1] * g[2]), s>>>(
-        P, Rw, inv_perm, aslot, refresh, ctrl, step, check_halt, near, make_int3(g[0], g[1], g[2]));
+        go, P, Rw, inv_perm, aslot, refresh, ctrl, step, check_halt, near, make_int3(g[0], g[1], g[2]), Rw_alt);
 }
 
 void launch_anchor_weights_caller(hipStream_t s, const DevParams &P, const double *com, double *w)
