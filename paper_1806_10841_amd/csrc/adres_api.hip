@@ -186,19 +186,27 @@ adres_status wait_ctrl(adres_ctx *c, unsigned seq)
 {
     HIPCHK(c, hipGetLastError());
     const auto t0 = std::chrono::steady_clock::now();
-    for (long spin = 0; __atomic_load_n(&c->pub->seq, __ATOMIC_ACQUIRE) != seq; ++spin) {
+    int v[kPubFields];
+    auto published = [c, seq, &v]() {
+        for (int i = 0; i < kPubFields; ++i) {
+            const unsigned long long w = __atomic_load_n(&c->pub->w[i], __ATOMIC_ACQUIRE);
+            if ((unsigned)(w >> 32) != seq) return false;
+            v[i] = (int)(unsigned)w;
+        }
+        return true;
+    };
+    for (long spin = 0; !published(); ++spin) {
         if ((spin & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(5)) {
             // something is wrong with the stream: let the runtime report it
             HIPCHK(c, hipStreamSynchronize(c->stream));
-            if (__atomic_load_n(&c->pub->seq, __ATOMIC_ACQUIRE) != seq)
-                return fail(c, ADRES_E_HIP, "control word was not published");
+            if (!published()) return fail(c, ADRES_E_HIP, "control word was not published");
         }
     }
-    c->ctrl_host->halt = c->pub->halt;
-    c->ctrl_host->err = c->pub->err;
-    c->ctrl_host->overflow = c->pub->overflow;
-    c->ctrl_host->max_count = c->pub->max_count;
-    c->ctrl_host->max_halo = c->pub->max_halo;
+    c->ctrl_host->halt = v[kPubHalt];
+    c->ctrl_host->err = v[kPubErr];
+    c->ctrl_host->overflow = v[kPubOverflow];
+    c->ctrl_host->max_count = v[kPubMaxCount];
+    c->ctrl_host->max_halo = v[kPubMaxHalo];
     int e = c->ctrl_host->err;
     if (e) {
         HIPCHK(c, hipMemsetAsync(&c->ctrl->err, 0, sizeof(int), c->stream));

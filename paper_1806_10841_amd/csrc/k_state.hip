@@ -566,15 +566,11 @@ __global__ __launch_bounds__(kBlock) void k_anchor_weights_caller(DevParams P, c
 __global__ void k_publish(Ctrl *__restrict__ ctrl, CtrlPub *pub, unsigned seq, int reset, int len_drift)
 {
     if (threadIdx.x != 0) return;
-    volatile CtrlPub *p = pub;
-    p->halt = ctrl->halt;
-    p->err = ctrl->err;
-    p->overflow = ctrl->overflow;
-    p->max_count = ctrl->max_count;
-    p->max_halo = ctrl->max_halo;
-    __threadfence_system();
-    p->seq = seq;
-    __threadfence_system();
+    const int v[kPubFields] = {ctrl->halt, ctrl->err, ctrl->overflow, ctrl->max_count, ctrl->max_halo};
+#pragma unroll
+    for (int i = 0; i < kPubFields; ++i)
+        __hip_atomic_store(&pub->w[i], ((unsigned long long)seq << 32) | (unsigned)v[i], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
     if (reset) {
         // the chunk's drifts that ran: all, none (a list overflow stopped the chunk), or up to
         // and including the one that asked for the rebuild
