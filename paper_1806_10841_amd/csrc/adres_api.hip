@@ -968,8 +968,11 @@ adres_status integrate_impl(adres_ctx *c, double *x, double *v, double *f, doubl
         st = enqueue_list(c, go);
         if (st != ADRES_OK) return st;
         c->list_valid = true;
-        st = wait_ctrl(c, seq);   // the one synchronisation per chunk
-        if (st != ADRES_OK) return st;
+        // the one synchronisation per chunk; on an error latched by the chunk the fields are
+        // still read, so that the context's buffers stay where the device left them
+        st = wait_ctrl(c, seq);
+        if (st != ADRES_OK && __atomic_load_n(&c->pub->w[kPubHalt], __ATOMIC_ACQUIRE) >> 32 != seq) return st;
+        const adres_status chunk_st = st;
         const int h = c->ctrl_host->halt;
         for (size_t i = ev0; i < c->events_used; ++i)
             if (c->event_k[i] >= 0 && (h < 0 || (h != INT_MAX && c->event_k[i] > h))) c->event_skip[i] = 1;
@@ -984,6 +987,7 @@ adres_status integrate_impl(adres_ctx *c, double *x, double *v, double *f, doubl
         } else {
             c->pos = pos0 ^ fix ^ 1;   // the reorder wrote the buffer its source was not in
         }
+        if (chunk_st != ADRES_OK) return chunk_st;
         if (h < 0) {
             // the last list build overflowed: nothing of this chunk ran; regrow, rebuild
             st = build_list(c);
