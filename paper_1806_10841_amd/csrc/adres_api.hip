@@ -246,9 +246,9 @@ void enqueue_resort(adres_ctx *c, bool with_v, const int *go)
                             dst.Rw);
     else
         launch_cell_keys(c->stream, c->P, c->G, c->cell_rank, src.Rw, src.key, c->count, go, dst.Rw);
-    launch_scan_cells(c->stream, c->count, c->G.n_cells, c->start, c->fill, c->scan_tiles, go);
-    launch_scatter_slots(c->stream, c->P.n_mol, src.key, c->start, c->fill, c->new_from, go);
-    launch_sort_within_cells(c->stream, c->G.n_cells, c->start, src.perm, c->new_from, go);
+    launch_scatter_slots(c->stream, c->P.n_mol, c->G.n_cells, src.key, c->count, c->start, c->fill, c->scan_tiles,
+                         c->new_from, go);
+    launch_sort_within_cells(c->stream, c->G.n_cells, c->start, src.perm, c->new_from, c->count, go);
     launch_permute(c->stream, c->P, c->new_from, src, dst, c->inv_perm, c->R_ref, with_v, go);
     // the nearest-anchor offsets are per slot: recompute them in the new order
     if (c->P.region == ADRES_REGION_SPHERES)

@@ -492,10 +492,15 @@ void launch_cell_keys(hipStream_t s, const DevParams &P, const Grid &G, const in
 // fill if non-null); tiles: scratch of at least n / 1024 + 1 ints; n <= scan_max_elements()
 void launch_scan_cells(hipStream_t s, int *count, int n, int *start, int *fill, int *tiles, const int *go = nullptr);
 int scan_max_elements();
-void launch_scatter_slots(hipStream_t s, int n_mol, const int *key, const int *start, int *fill,
-                          int *new_from, const int *go = nullptr);
-void launch_sort_within_cells(hipStream_t s, int n_cells, const int *start, const int *perm_old,
-                              int *new_from, const int *go = nullptr);
+// the cell sort after the keys pass: counts (in place) scanned per tile of 1024 cells, the
+// cells' starts start[0..n_cells] and every molecule's slot in new_from (cell order, arbitrary
+// within a cell); fill cleared here; tiles: scratch of at least n_cells / 1024 + 1 ints;
+// n_cells <= scan_max_elements()
+void launch_scatter_slots(hipStream_t s, int n_mol, int n_cells, const int *key, int *count, int *start, int *fill,
+                          int *tiles, int *new_from, const int *go = nullptr);
+// caller order within each cell; clears the counts for the next build
+void launch_sort_within_cells(hipStream_t s, int n_cells, const int *start, const int *perm_old, int *new_from,
+                              int *count, const int *go = nullptr);
 void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, const StateBufs &src,
                     const StateBufs &dst, int *inv_perm, double4 *R_ref, bool with_v, const int *go = nullptr);
 

@@ -119,15 +119,59 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(const int *__restrict
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter_slots(const int *__restrict__ go, int n_mol, const int *__restrict__ key,
-                                                          const int *__restrict__ start, int *__restrict__ fill,
-                                                          int *__restrict__ new_from)
+// The cell sort's scan in one pass plus the scatter: k_scan_local leaves each tile of 1024
+// cells its in-tile exclusive prefix (in place of the counts) and its total, and clears the
+// fill counters; k_scatter_slots then scans the tile totals in every workgroup (at most
+// kScanTile of them), writes the cells' global starts and places every molecule at its
+// cell's start plus an atomic fill index (the order within a cell is fixed afterwards by
+// k_sort_within_cells, which also clears the counts for the next build).
+__global__ __launch_bounds__(kScanThreads) void k_scan_local(const int *__restrict__ go, int *__restrict__ count, int n,
+                                                             int *__restrict__ tiles, int *__restrict__ fill)
 {
     if (go && *go == 0) return;   // a guarded rebuild that was not asked for
-    int i = blockIdx.x * kBlock + threadIdx.x;
+    const int base = blockIdx.x * kScanTile + 4 * threadIdx.x;
+    int c[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c[j] = base + j < n ? count[base + j] : 0;
+    const int mine = (c[0] + c[1]) + (c[2] + c[3]);
+    int total;
+    int run = block_exclusive_scan(mine, total);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (base + j < n) {
+            count[base + j] = run;
+            fill[base + j] = 0;
+        }
+        run += c[j];
+    }
+    if (threadIdx.x == 0) tiles[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter_slots(const int *__restrict__ go, int n_mol, const int *__restrict__ key,
+                                                          const int *__restrict__ lstart, const int *__restrict__ tiles,
+                                                          int n_tiles, int n_cells, int *__restrict__ start,
+                                                          int *__restrict__ fill, int *__restrict__ new_from)
+{
+    if (go && *go == 0) return;   // a guarded rebuild that was not asked for
+    static_assert(kBlock == kScanThreads, "the tile totals are scanned by the whole workgroup");
+    __shared__ int toff[kScanTile];
+    int tt[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tt[j] = 4 * (int)threadIdx.x + j < n_tiles ? tiles[4 * threadIdx.x + j] : 0;
+    int total;
+    int run = block_exclusive_scan((tt[0] + tt[1]) + (tt[2] + tt[3]), total);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        toff[4 * threadIdx.x + j] = run;
+        run += tt[j];
+    }
+    __syncthreads();
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n_cells) start[i] = lstart[i] + toff[i / kScanTile];
+    else if (i == n_cells) start[i] = total;
     if (i >= n_mol) return;
-    int k = key[i];
-    int pos = start[k] + atomicAdd(&fill[k], 1);
+    const int k = key[i];
+    const int pos = lstart[k] + toff[k / kScanTile] + atomicAdd(&fill[k], 1);
     new_from[pos] = i;
 }
 
@@ -139,11 +183,12 @@ constexpr int kSortCell = 16;
 
 __global__ __launch_bounds__(kBlock) void k_sort_within_cells(const int *__restrict__ go, int n_cells, const int *__restrict__ start,
                                                               const int *__restrict__ perm_old,
-                                                              int *__restrict__ new_from)
+                                                              int *__restrict__ new_from, int *__restrict__ count)
 {
     if (go && *go == 0) return;   // a guarded rebuild that was not asked for
     int c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= n_cells) return;
+    count[c] = 0;   // (the in-tile prefixes of k_scan_local: cleared for the next build)
     const int lo = start[c], hi = start[c + 1], m = hi - lo;
     if (m <= 1) return;
     if (m <= kSortCell) {
@@ -445,14 +490,19 @@ void launch_scan_cells(hipStream_t s, int *count, int n, int *start, int *fill, 
 
 int scan_max_elements() { return kScanTile * kScanTile; }
 
-void launch_scatter_slots(hipStream_t s, int n_mol, const int *key, const int *start, int *fill, int *new_from, const int *go)
+void launch_scatter_slots(hipStream_t s, int n_mol, int n_cells, const int *key, int *count, int *start, int *fill,
+                          int *tiles, int *new_from, const int *go)
 {
-    k_scatter_slots<<<blocks_for(n_mol), kBlock, 0, s>>>(go, n_mol, key, start, fill, new_from);
+    const int n_tiles = (n_cells + kScanTile - 1) / kScanTile;
+    k_scan_local<<<n_tiles, kScanThreads, 0, s>>>(go, count, n_cells, tiles, fill);
+    k_scatter_slots<<<blocks_for(std::max(n_mol, n_cells + 1)), kBlock, 0, s>>>(go, n_mol, key, count, tiles, n_tiles,
+                                                                               n_cells, start, fill, new_from);
 }
 
-void launch_sort_within_cells(hipStream_t s, int n_cells, const int *start, const int *perm_old, int *new_from, const int *go)
+void launch_sort_within_cells(hipStream_t s, int n_cells, const int *start, const int *perm_old, int *new_from,
+                              int *count, const int *go)
 {
-    k_sort_within_cells<<<blocks_for(n_cells), kBlock, 0, s>>>(go, n_cells, start, perm_old, new_from);
+    k_sort_within_cells<<<blocks_for(n_cells), kBlock, 0, s>>>(go, n_cells, start, perm_old, new_from, count);
 }
 
 void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, const StateBufs &src,
