@@ -171,14 +171,13 @@ uint32_t spread3(uint32_t v)
 // Reads the device control block once all work enqueued so far has finished: a
 // one-thread kernel publishes it into host-mapped memory with a sequence number the
 // host polls (cheaper than a copy plus a stream synchronisation).  Converts latched
-// error bits into a status and clears them.  With reset_halt the same kernel then clears
-// the device's halt index and overflow report.
-// The publication is launched and waited for separately by the step loop, which enqueues
-// more work between the two.
-unsigned publish_ctrl(adres_ctx *c, bool reset_halt, int len_drift = 0)
+// error bits into a status and clears them.
+// The step loop has the first launch of the rebuild behind each chunk publish instead
+// (ChainHead) and waits for it after enqueueing the rest of the rebuild.
+unsigned publish_ctrl(adres_ctx *c)
 {
     const unsigned seq = ++c->pub_seq;
-    launch_publish(c->stream, c->ctrl, c->pub_dev, seq, reset_halt, len_drift);
+    launch_publish(c->stream, c->ctrl, c->pub_dev, seq);
     return seq;
 }
 
@@ -218,9 +217,9 @@ adres_status wait_ctrl(adres_ctx *c, unsigned seq)
     return ADRES_OK;
 }
 
-adres_status read_ctrl(adres_ctx *c, bool reset_halt = false)
+adres_status read_ctrl(adres_ctx *c)
 {
-    return wait_ctrl(c, publish_ctrl(c, reset_halt));
+    return wait_ctrl(c, publish_ctrl(c));
 }
 
 adres_status gather(adres_ctx *c, const double *x, const double *v, bool check_disp)
@@ -234,8 +233,9 @@ adres_status gather(adres_ctx *c, const double *x, const double *v, bool check_d
 }
 
 // Morton reorder: the launches (guarded by go when non-null: a rebuild enqueued before the
-// host knows whether it is needed) and the host's bookkeeping once it has run
-void enqueue_resort(adres_ctx *c, bool with_v, const int *go)
+// host knows whether it is needed; head: the publication of the step chunk before it, taken
+// by the first launch, which then also stores go) and the host's bookkeeping once it has run
+void enqueue_resort(adres_ctx *c, bool with_v, const int *go, const ChainHead &head = ChainHead{})
 {
     const StateBufs src = cur(c);
     const StateBufs dst = view(c, 1 - c->pos, 1 - c->ord);
@@ -243,13 +243,14 @@ void enqueue_resort(adres_ctx *c, bool with_v, const int *go)
     // rebuild reads instead when the chunk's positions sit there: Ctrl::fix)
     if (c->rw_stale)   // the step kernels moved the positions without storing centres
         launch_centres_keys(c->stream, c->P, c->G, c->cell_rank, src.x, src.Rw, src.key, c->count, go, dst.x,
-                            dst.Rw);
+                            dst.Rw, head);
     else
-        launch_cell_keys(c->stream, c->P, c->G, c->cell_rank, src.Rw, src.key, c->count, go, dst.Rw);
+        launch_cell_keys(c->stream, c->P, c->G, c->cell_rank, src.Rw, src.key, c->count, go, dst.Rw, head);
+    // (after a head, the scan's launch clears the halt index and the list reports it published)
     launch_scatter_slots(c->stream, c->P.n_mol, c->G.n_cells, src.key, c->count, c->start, c->fill, c->scan_tiles,
-                         c->new_from, go);
-    launch_sort_within_cells(c->stream, c->G.n_cells, c->start, src.perm, c->new_from, c->count, go);
-    launch_permute(c->stream, c->P, c->new_from, src, dst, c->inv_perm, c->R_ref, with_v, go);
+                         c->new_from, go, head.ctrl);
+    launch_sort_permute(c->stream, c->P, c->G.n_cells, c->start, c->new_from, c->count, src, dst, c->inv_perm,
+                        c->R_ref, with_v, go);
     // the nearest-anchor offsets are per slot: recompute them in the new order
     if (c->P.region == ADRES_REGION_SPHERES)
         launch_anchor_weights(c->stream, c->P, dst.Rw, c->inv_perm, c->aslot, 1, c->ctrl, 0, 0, c->near, go, src.Rw);
@@ -954,16 +955,16 @@ adres_status integrate_impl(adres_ctx *c, double *x, double *v, double *f, doubl
                 ++len_drift;
             }
         }
-        // The chunk's publication (which also clears halt), then, without waiting for it, a
-        // reorder + list rebuild that runs only if a drift asked for one (Ctrl::go): the GPU
+        // A reorder + list rebuild that runs only if a drift asked for one (Ctrl::go), whose
+        // first launch publishes the chunk's control word (its second clears halt): the GPU
         // goes on while the host reads the publication.  The rebuild is enqueued as if every
         // drift ran (positions in buffer p); if an odd number did not, its kernels read the
         // other buffer (Ctrl::fix).  The host keeps the rebuild's bookkeeping only if it ran.
-        const unsigned seq = publish_ctrl(c, true, len_drift);
+        const unsigned seq = ++c->pub_seq;
         c->pos = p;
         const int pos0 = c->pos, ord0 = c->ord;
         const bool stale0 = c->rw_stale, valid0 = c->list_valid;
-        enqueue_resort(c, true, go);
+        enqueue_resort(c, true, go, ChainHead{c->ctrl, c->pub_dev, seq, len_drift});
         commit_resort(c);
         st = enqueue_list(c, go);
         if (st != ADRES_OK) return st;

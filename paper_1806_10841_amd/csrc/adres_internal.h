@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <limits.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -47,6 +48,46 @@ enum CtrlPubField : int { kPubHalt, kPubErr, kPubOverflow, kPubMaxCount, kPubMax
 struct CtrlPub {
     unsigned long long w[8];
 };
+
+// The publication of a step chunk, taken by the first kernel of the guarded rebuild that
+// is enqueued behind the chunk (one launch less per chunk).  ctrl == nullptr: none.
+struct ChainHead {
+    Ctrl *ctrl;
+    CtrlPub *pub;
+    unsigned seq;
+    int len_drift;   // the chunk's drifting kernels
+};
+
+// In that first kernel: every workgroup derives go and fix from the halt index (which no
+// kernel of the rebuild writes before the next one clears it); workgroup 0 publishes the
+// fields and stores go and fix for the later kernels of the rebuild.  Without a head, go
+// and fix are read from where the publication stored them (go == nullptr: an unguarded
+// launch).  Returns go.
+__device__ __forceinline__ bool chain_go(const ChainHead &head, const int *go, bool &fix)
+{
+    if (head.ctrl) {
+        Ctrl *c = head.ctrl;
+        const int h = c->halt;
+        // the chunk's drifts that ran: all, none (a list overflow stopped the chunk), or up
+        // to and including the one that asked for the rebuild
+        const int ran = h == INT_MAX ? head.len_drift : (h < 0 ? 0 : min(h + 1, head.len_drift));
+        const int g = (h >= 0 && h != INT_MAX) ? 1 : 0;
+        const int f = (head.len_drift - ran) & 1;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            const int v[kPubFields] = {h, c->err, c->overflow, c->max_count, c->max_halo};
+#pragma unroll
+            for (int i = 0; i < kPubFields; ++i)
+                __hip_atomic_store(&head.pub->w[i], ((unsigned long long)head.seq << 32) | (unsigned)v[i],
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            c->go = g;
+            c->fix = f;
+        }
+        fix = f != 0;
+        return g != 0;
+    }
+    fix = go && go[1] != 0;
+    return !go || go[0] != 0;
+}
 
 // Parameters in the form the kernels use (passed by value).
 struct DevParams {
@@ -476,18 +517,19 @@ void launch_kick_drift(hipStream_t s, const DevParams &P, const double *x_in, do
                        const StepArgs &st);
 // centres and weights of the sorted state from its positions (before a reorder, when the
 // step kernels have not kept them) and the cell keys of launch_cell_keys, in one pass
+// (head: the step chunk's publication, see ChainHead)
 void launch_centres_keys(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank, const double *x,
                          double4 *Rw, int *key, int *count, const int *go = nullptr, const double *x_alt = nullptr,
-                         double4 *Rw_alt = nullptr);
+                         double4 *Rw_alt = nullptr, const ChainHead &head = ChainHead{});
 void launch_reset_halt(hipStream_t s, Ctrl *ctrl);
-// len_drift: the drifting kernels of the step chunk the publication ends (0 elsewhere)
-void launch_publish(hipStream_t s, Ctrl *ctrl, CtrlPub *pub, unsigned seq, bool reset, int len_drift = 0);
+// the control block's fields into host-mapped memory, tagged with seq (see CtrlPub)
+void launch_publish(hipStream_t s, Ctrl *ctrl, CtrlPub *pub, unsigned seq);
 void launch_map_cg(hipStream_t s, const DevParams &P, const double *x, const double *f, double *com, double *fmap);
 
 // cell list
 void launch_cell_keys(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank,
                       const double4 *Rw, int *key, int *count, const int *go = nullptr,
-                      const double4 *Rw_alt = nullptr);
+                      const double4 *Rw_alt = nullptr, const ChainHead &head = ChainHead{});
 // exclusive scan of count[0..n) into start[0..n] (start[n] = total); resets count (and
 // fill if non-null); tiles: scratch of at least n / 1024 + 1 ints; n <= scan_max_elements()
 void launch_scan_cells(hipStream_t s, int *count, int n, int *start, int *fill, int *tiles, const int *go = nullptr);
@@ -495,14 +537,15 @@ int scan_max_elements();
 // the cell sort after the keys pass: counts (in place) scanned per tile of 1024 cells, the
 // cells' starts start[0..n_cells] and every molecule's slot in new_from (cell order, arbitrary
 // within a cell); fill cleared here; tiles: scratch of at least n_cells / 1024 + 1 ints;
-// n_cells <= scan_max_elements()
+// n_cells <= scan_max_elements().  reset: a control block whose halt index and list reports
+// are cleared (whether or not go is set), after a chain head published them.
 void launch_scatter_slots(hipStream_t s, int n_mol, int n_cells, const int *key, int *count, int *start, int *fill,
-                          int *tiles, int *new_from, const int *go = nullptr);
-// caller order within each cell; clears the counts for the next build
-void launch_sort_within_cells(hipStream_t s, int n_cells, const int *start, const int *perm_old, int *new_from,
-                              int *count, const int *go = nullptr);
-void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, const StateBufs &src,
-                    const StateBufs &dst, int *inv_perm, double4 *R_ref, bool with_v, const int *go = nullptr);
+                          int *tiles, int *new_from, const int *go = nullptr, Ctrl *reset = nullptr);
+// caller order within each cell, then the state gathered into the new slot order; clears
+// the counts for the next build
+void launch_sort_permute(hipStream_t s, const DevParams &P, int n_cells, const int *start, int *new_from,
+                         int *count, const StateBufs &src, const StateBufs &dst, int *inv_perm, double4 *R_ref,
+                         bool with_v, const int *go = nullptr);
 
 // Verlet list: ELL, row-major nbr[slot * cap + k]; each row is padded with the
 // row's own slot up to a multiple of 4 entries (cap is a multiple of 4).

@@ -25,11 +25,11 @@ inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
 __global__ __launch_bounds__(kBlock) void k_cell_keys(const int *__restrict__ go, DevParams P, Grid G, const int *__restrict__ cell_rank,
                                                       const double4 *__restrict__ Rw, int *__restrict__ key,
-                                                      int *__restrict__ count, const double4 *__restrict__ Rw_alt)
+                                                      int *__restrict__ count, const double4 *__restrict__ Rw_alt,
+                                                      ChainHead head)
 {
-    if (go && *go == 0) return;   // a guarded rebuild that was not asked for
-    // (go points at Ctrl::go, followed by Ctrl::fix: the chunk's positions sit in the other buffer)
-    const bool sw = go && go[1] != 0;
+    bool sw;   // the chunk's positions sit in the other buffer
+    if (!chain_go(head, go, sw)) return;   // a guarded rebuild that was not asked for
     if (sw) Rw = Rw_alt;
     int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= P.n_mol) return;
@@ -124,10 +124,17 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(const int *__restrict
 // fill counters; k_scatter_slots then scans the tile totals in every workgroup (at most
 // kScanTile of them), writes the cells' global starts and places every molecule at its
 // cell's start plus an atomic fill index (the order within a cell is fixed afterwards by
-// k_sort_within_cells, which also clears the counts for the next build).
+// k_sort_permute, which also clears the counts for the next build).
 __global__ __launch_bounds__(kScanThreads) void k_scan_local(const int *__restrict__ go, int *__restrict__ count, int n,
-                                                             int *__restrict__ tiles, int *__restrict__ fill)
+                                                             int *__restrict__ tiles, int *__restrict__ fill,
+                                                             Ctrl *__restrict__ reset)
 {
+    if (reset && blockIdx.x == 0 && threadIdx.x == 0) {   // published by the kernel before
+        reset->halt = INT_MAX;
+        reset->overflow = 0;
+        reset->max_count = 0;
+        reset->max_halo = 0;
+    }
     if (go && *go == 0) return;   // a guarded rebuild that was not asked for
     const int base = blockIdx.x * kScanTile + 4 * threadIdx.x;
     int c[4];
@@ -175,21 +182,23 @@ __global__ __launch_bounds__(kBlock) void k_scatter_slots(const int *__restrict_
     new_from[pos] = i;
 }
 
-// Molecules of one cell in caller order (the atomic scatter leaves them in arbitrary
-// order).  A cell of at most 16 molecules is loaded into registers at once and every
+// Caller order within each cell (the atomic scatter leaves the molecules of a cell in
+// arbitrary order), then the state gathered into the new slot order, in one launch: the
+// slots of a cell depend on that cell alone, so a workgroup takes kSortCells consecutive
+// cells, its first wavefront orders them (a thread per cell) and the whole workgroup then
+// moves the molecules of their slot range.
+// Ordering: a cell of at most 16 molecules is loaded into registers at once and every
 // molecule is written to the slot given by its rank (the number of cell mates with a
 // smaller caller index; indices are distinct); larger cells use an insertion sort.
+// Moving: one lane per site (perm_lanes<SPM>() lanes per molecule; lane 0 also moves the
+// per-molecule arrays), all of a lane's loads issued before its first store (source and
+// destination are distinct buffers, which the compiler cannot know).
 constexpr int kSortCell = 16;
+constexpr int kSortCells = 64;
 
-__global__ __launch_bounds__(kBlock) void k_sort_within_cells(const int *__restrict__ go, int n_cells, const int *__restrict__ start,
-                                                              const int *__restrict__ perm_old,
-                                                              int *__restrict__ new_from, int *__restrict__ count)
+__device__ __forceinline__ void sort_cell(int lo, int hi, const int *__restrict__ perm_old, int *__restrict__ new_from)
 {
-    if (go && *go == 0) return;   // a guarded rebuild that was not asked for
-    int c = blockIdx.x * kBlock + threadIdx.x;
-    if (c >= n_cells) return;
-    count[c] = 0;   // (the in-tile prefixes of k_scan_local: cleared for the next build)
-    const int lo = start[c], hi = start[c + 1], m = hi - lo;
+    const int m = hi - lo;
     if (m <= 1) return;
     if (m <= kSortCell) {
         int v[kSortCell], tag[kSortCell];
@@ -219,62 +228,66 @@ __global__ __launch_bounds__(kBlock) void k_sort_within_cells(const int *__restr
     }
 }
 
-// Gathers the state into the new slot order, one lane per site (perm_lanes<SPM>() lanes per
-// molecule; lane 0 also moves the per-molecule arrays), so that a rebuild has four times
-// as many independent gathers in flight as with a lane per molecule.  All of a lane's loads
-// are issued before its first store: source and destination are distinct buffers, but the
-// compiler cannot know that and would otherwise wait for every load before the store that
-// follows it.
 template <int SPM>
 constexpr int perm_lanes() { return SPM == 1 ? 1 : (SPM == 2 ? 2 : 4); }
 
 template <int SPM>
-__global__ __launch_bounds__(kBlock) void k_permute(const int *__restrict__ go, DevParams P, const int *__restrict__ new_from, StateBufs src,
-                                                    StateBufs dst, int *__restrict__ inv_perm,
-                                                    double4 *__restrict__ R_ref, int with_v)
+__global__ __launch_bounds__(kBlock) void k_sort_permute(const int *__restrict__ go, DevParams P, int n_cells,
+                                                         const int *__restrict__ start, int *__restrict__ new_from,
+                                                         int *__restrict__ count, StateBufs src, StateBufs dst,
+                                                         int *__restrict__ inv_perm, double4 *__restrict__ R_ref,
+                                                         int with_v)
 {
     if (go && *go == 0) return;   // a guarded rebuild that was not asked for
     // (go points at Ctrl::go, followed by Ctrl::fix: the chunk's positions sit in the other buffer)
-    const bool sw = go && go[1] != 0;
-    if (sw) {   // the source positions are in the destination's buffer and the other way round
+    if (go && go[1] != 0) {   // the source positions are in the destination's buffer and the other way round
         double *tx = src.x; src.x = dst.x; dst.x = tx;
         double4 *tr = src.Rw; src.Rw = dst.Rw; dst.Rw = tr;
     }
+    const int c0 = blockIdx.x * kSortCells;
+    const int c1 = min(c0 + kSortCells, n_cells);
+    if (threadIdx.x < kSortCells && c0 + (int)threadIdx.x < c1) {
+        const int c = c0 + threadIdx.x;
+        count[c] = 0;   // (the in-tile prefixes of k_scan_local: cleared for the next build)
+        sort_cell(start[c], start[c + 1], src.perm, new_from);
+    }
+    __syncthreads();   // the workgroup's own global stores are visible to it after the barrier
     constexpr int L = perm_lanes<SPM>();
     static_assert(SPM <= L, "one lane per site");
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int t = (int)(g / L), k = (int)(g % L);
-    if (t >= P.n_mol) return;
+    const int lo = start[c0], hi = start[c1];
     const int64_t ns = P.n_sites;
-    const int i = new_from[t];
-    const bool site = k < SPM;
-    const int64_t from = (int64_t)i * SPM + k, to = (int64_t)t * SPM + k;
-    double xs[3] = {0.0, 0.0, 0.0}, vs[3] = {0.0, 0.0, 0.0};
-    if (site) {
+    for (int64_t g = (int64_t)lo * L + threadIdx.x; g < (int64_t)hi * L; g += kBlock) {
+        const int t = (int)(g / L), k = (int)(g % L);
+        const int i = new_from[t];
+        const bool site = k < SPM;
+        const int64_t from = (int64_t)i * SPM + k, to = (int64_t)t * SPM + k;
+        double xs[3] = {0.0, 0.0, 0.0}, vs[3] = {0.0, 0.0, 0.0};
+        if (site) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            xs[d] = src.x[d * ns + from];
-            if (with_v) vs[d] = src.v[d * ns + from];
+            for (int d = 0; d < 3; ++d) {
+                xs[d] = src.x[d * ns + from];
+                if (with_v) vs[d] = src.v[d * ns + from];
+            }
         }
-    }
-    double4 r = make_double4(0.0, 0.0, 0.0, 0.0);
-    int caller = 0;
-    if (k == 0) {
-        r = src.Rw[i];
-        caller = src.perm[i];
-    }
-    if (site) {
+        double4 r = make_double4(0.0, 0.0, 0.0, 0.0);
+        int caller = 0;
+        if (k == 0) {
+            r = src.Rw[i];
+            caller = src.perm[i];
+        }
+        if (site) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            dst.x[d * ns + to] = xs[d];
-            if (with_v) dst.v[d * ns + to] = vs[d];
+            for (int d = 0; d < 3; ++d) {
+                dst.x[d * ns + to] = xs[d];
+                if (with_v) dst.v[d * ns + to] = vs[d];
+            }
         }
-    }
-    if (k == 0) {
-        dst.Rw[t] = r;
-        R_ref[t] = r;
-        dst.perm[t] = caller;
-        inv_perm[caller] = t;
+        if (k == 0) {
+            dst.Rw[t] = r;
+            R_ref[t] = r;
+            dst.perm[t] = caller;
+            inv_perm[caller] = t;
+        }
     }
 }
 
@@ -476,9 +489,10 @@ void launch_half_list(hipStream_t s, int n, int *nbr, const int *cnt, int cap, i
 }
 
 void launch_cell_keys(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank,
-                      const double4 *Rw, int *key, int *count, const int *go, const double4 *Rw_alt)
+                      const double4 *Rw, int *key, int *count, const int *go, const double4 *Rw_alt,
+                      const ChainHead &head)
 {
-    k_cell_keys<<<blocks_for(P.n_mol), kBlock, 0, s>>>(go, P, G, cell_rank, Rw, key, count, Rw_alt);
+    k_cell_keys<<<blocks_for(P.n_mol), kBlock, 0, s>>>(go, P, G, cell_rank, Rw, key, count, Rw_alt, head);
 }
 
 void launch_scan_cells(hipStream_t s, int *count, int n, int *start, int *fill, int *tiles, const int *go)
@@ -491,29 +505,25 @@ void launch_scan_cells(hipStream_t s, int *count, int n, int *start, int *fill, 
 int scan_max_elements() { return kScanTile * kScanTile; }
 
 void launch_scatter_slots(hipStream_t s, int n_mol, int n_cells, const int *key, int *count, int *start, int *fill,
-                          int *tiles, int *new_from, const int *go)
+                          int *tiles, int *new_from, const int *go, Ctrl *reset)
 {
     const int n_tiles = (n_cells + kScanTile - 1) / kScanTile;
-    k_scan_local<<<n_tiles, kScanThreads, 0, s>>>(go, count, n_cells, tiles, fill);
+    k_scan_local<<<n_tiles, kScanThreads, 0, s>>>(go, count, n_cells, tiles, fill, reset);
     k_scatter_slots<<<blocks_for(std::max(n_mol, n_cells + 1)), kBlock, 0, s>>>(go, n_mol, key, count, tiles, n_tiles,
                                                                                n_cells, start, fill, new_from);
 }
 
-void launch_sort_within_cells(hipStream_t s, int n_cells, const int *start, const int *perm_old, int *new_from,
-                              int *count, const int *go)
+void launch_sort_permute(hipStream_t s, const DevParams &P, int n_cells, const int *start, int *new_from,
+                         int *count, const StateBufs &src, const StateBufs &dst, int *inv_perm, double4 *R_ref,
+                         bool with_v, const int *go)
 {
-    k_sort_within_cells<<<blocks_for(n_cells), kBlock, 0, s>>>(go, n_cells, start, perm_old, new_from, count);
-}
-
-void launch_permute(hipStream_t s, const DevParams &P, const int *new_from, const StateBufs &src,
-                    const StateBufs &dst, int *inv_perm, double4 *R_ref, bool with_v, const int *go)
-{
-    const int64_t n = P.n_mol;
+    const int nb = (n_cells + kSortCells - 1) / kSortCells;
+    const int v = with_v ? 1 : 0;
     switch (P.spm) {
-    case 1: k_permute<1><<<blocks_for(n * perm_lanes<1>()), kBlock, 0, s>>>(go, P, new_from, src, dst, inv_perm, R_ref, with_v); break;
-    case 2: k_permute<2><<<blocks_for(n * perm_lanes<2>()), kBlock, 0, s>>>(go, P, new_from, src, dst, inv_perm, R_ref, with_v); break;
-    case 3: k_permute<3><<<blocks_for(n * perm_lanes<3>()), kBlock, 0, s>>>(go, P, new_from, src, dst, inv_perm, R_ref, with_v); break;
-    default: k_permute<4><<<blocks_for(n * perm_lanes<4>()), kBlock, 0, s>>>(go, P, new_from, src, dst, inv_perm, R_ref, with_v); break;
+    case 1: k_sort_permute<1><<<nb, kBlock, 0, s>>>(go, P, n_cells, start, new_from, count, src, dst, inv_perm, R_ref, v); break;
+    case 2: k_sort_permute<2><<<nb, kBlock, 0, s>>>(go, P, n_cells, start, new_from, count, src, dst, inv_perm, R_ref, v); break;
+    case 3: k_sort_permute<3><<<nb, kBlock, 0, s>>>(go, P, n_cells, start, new_from, count, src, dst, inv_perm, R_ref, v); break;
+    default: k_sort_permute<4><<<nb, kBlock, 0, s>>>(go, P, n_cells, start, new_from, count, src, dst, inv_perm, R_ref, v); break;
     }
 }
 

@@ -82,11 +82,11 @@ template <int SPM>
 __global__ __launch_bounds__(kBlock) void k_centres_keys(const int *__restrict__ go, DevParams P, Grid G, const int *__restrict__ cell_rank,
                                                          const double *__restrict__ x, double4 *__restrict__ Rw,
                                                          int *__restrict__ key, int *__restrict__ count,
-                                                         const double *__restrict__ x_alt, double4 *__restrict__ Rw_alt)
+                                                         const double *__restrict__ x_alt, double4 *__restrict__ Rw_alt,
+                                                         ChainHead head)
 {
-    if (go && *go == 0) return;   // a guarded rebuild that was not asked for
-    // (go points at Ctrl::go, followed by Ctrl::fix: the chunk's positions sit in the other buffer)
-    const bool sw = go && go[1] != 0;
+    bool sw;   // the chunk's positions sit in the other buffer
+    if (!chain_go(head, go, sw)) return;   // a guarded rebuild that was not asked for
     if (sw) {
         x = x_alt;
         Rw = Rw_alt;
@@ -561,9 +561,7 @@ __global__ __launch_bounds__(kBlock) void k_anchor_weights_caller(DevParams P, c
     w[a] = weight_of_distance(P, sqrt(best));
 }
 
-// With reset, also clears the halt index and the list-overflow report once they have been
-// copied (what k_reset_halt does), saving the step loop a launch per chunk.
-__global__ void k_publish(Ctrl *__restrict__ ctrl, CtrlPub *pub, unsigned seq, int reset, int len_drift)
+__global__ void k_publish(Ctrl *__restrict__ ctrl, CtrlPub *pub, unsigned seq)
 {
     if (threadIdx.x != 0) return;
     const int v[kPubFields] = {ctrl->halt, ctrl->err, ctrl->overflow, ctrl->max_count, ctrl->max_halo};
@@ -571,18 +569,6 @@ __global__ void k_publish(Ctrl *__restrict__ ctrl, CtrlPub *pub, unsigned seq, i
     for (int i = 0; i < kPubFields; ++i)
         __hip_atomic_store(&pub->w[i], ((unsigned long long)seq << 32) | (unsigned)v[i], __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_SYSTEM);
-    if (reset) {
-        // the chunk's drifts that ran: all, none (a list overflow stopped the chunk), or up to
-        // and including the one that asked for the rebuild
-        const int h = ctrl->halt;
-        const int ran = h == INT_MAX ? len_drift : (h < 0 ? 0 : min(h + 1, len_drift));
-        ctrl->go = (h >= 0 && h != INT_MAX) ? 1 : 0;
-        ctrl->fix = (len_drift - ran) & 1;
-        ctrl->halt = INT_MAX;
-        ctrl->overflow = 0;
-        ctrl->max_count = 0;
-        ctrl->max_halo = 0;
-    }
 }
 
 
@@ -637,18 +623,20 @@ void launch_kick_drift(hipStream_t s, const DevParams &P, const double *x_in, do
 }
 
 void launch_centres_keys(hipStream_t s, const DevParams &P, const Grid &G, const int *cell_rank, const double *x,
-                         double4 *Rw, int *key, int *count, const int *go, const double *x_alt, double4 *Rw_alt)
+                         double4 *Rw, int *key, int *count, const int *go, const double *x_alt, double4 *Rw_alt,
+                         const ChainHead &head)
 {
     ADRES_SPM_DISPATCH(P.spm, (k_centres_keys<S_><<<blocks_for(P.n_mol), kBlock, 0, s>>>(go, P, G, cell_rank, x, Rw,
-                                                                                         key, count, x_alt, Rw_alt)));
+                                                                                         key, count, x_alt, Rw_alt,
+                                                                                         head)));
 }
 
 
 void launch_reset_halt(hipStream_t s, Ctrl *ctrl) { k_reset_halt<<<1, 64, 0, s>>>(ctrl); }
 
-void launch_publish(hipStream_t s, Ctrl *ctrl, CtrlPub *pub, unsigned seq, bool reset, int len_drift)
+void launch_publish(hipStream_t s, Ctrl *ctrl, CtrlPub *pub, unsigned seq)
 {
-    k_publish<<<1, 64, 0, s>>>(ctrl, pub, seq, reset ? 1 : 0, len_drift);
+    k_publish<<<1, 64, 0, s>>>(ctrl, pub, seq);
 }
 
 void launch_map_cg(hipStream_t s, const DevParams &P, const double *x, const double *f, double *com, double *fmap)
