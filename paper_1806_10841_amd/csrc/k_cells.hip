@@ -194,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_slots(const int *__restrict_
 // per-molecule arrays), all of a lane's loads issued before its first store (source and
 // destination are distinct buffers, which the compiler cannot know).
 constexpr int kSortCell = 16;
-constexpr int kSortCells = 64;
+constexpr int kSortCells = 32;
 
 __device__ __forceinline__ void sort_cell(int lo, int hi, const int *__restrict__ perm_old, int *__restrict__ new_from)
 {
