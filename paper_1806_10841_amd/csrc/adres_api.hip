@@ -47,7 +47,7 @@ struct adres_ctx {
     bool rw_stale = false;   // the step kernels moved the positions without storing centres
     Ctrl *ctrl = nullptr;
     Ctrl *ctrl_host = nullptr;     // last values read by the host
-    CtrlPub *pub = nullptr;        // host-mapped pinned copy written by k_publish
+    CtrlPub *pub = nullptr;        // host-mapped pinned copy (k_publish, or a rebuild's first kernel)
     CtrlPub *pub_dev = nullptr;    // its device address
     unsigned pub_seq = 0;
     double *epart = nullptr;

@@ -39,9 +39,9 @@ struct Ctrl {
 };
 static_assert(offsetof(Ctrl, fix) == offsetof(Ctrl, go) + sizeof(int), "fix follows go");
 
-// Copy of the control block in host-mapped pinned memory, published by a one-thread
-// kernel after the work it reports on; the host polls it instead of synchronising the
-// stream.  Each word holds the publication's sequence number (high half) with one field
+// Copy of the control block in host-mapped pinned memory, published after the work it
+// reports on (by a one-thread kernel, or by the first kernel of a rebuild: ChainHead); the
+// host polls it instead of synchronising the stream.  Each word holds the publication's sequence number (high half) with one field
 // (low half) and is written with one 8-byte store, so that the host takes the fields once
 // every word carries the sequence number it waits for: no fence orders the stores.
 enum CtrlPubField : int { kPubHalt, kPubErr, kPubOverflow, kPubMaxCount, kPubMaxHalo, kPubFields };

@@ -1,16 +1,17 @@
 // Linked-cell list of molecule centres of mass (Sec. 5, introduction: the
 // linked-cell list behind ESPResSo++'s domain decomposition), rebuilt as a
 // Morton-ordered counting sort on the GPU:
-//   keys (cell -> Morton rank) -> per-cell counts (atomics) -> exclusive scan
-//   (one workgroup, wavefront shuffles) -> scatter -> per-cell insertion sort by
-//   caller index (makes the order a pure function of the positions) -> permute
-//   the state into the new order.
-// and the Verlet list of molecule pairs: every molecule scans the 27 cells around
-// its own (fewer when a dimension has < 3 cells), one cell per lane, and keeps the
-// molecules whose minimum-image centre distance is strictly below r_list.  The list is stored
-// row-major (ELL): nbr[slot * cap + k]; every row is padded with the row's own
-// slot up to a multiple of 4 so that the force kernel can fetch four entries with
-// one 16-byte load and issue their gathers unconditionally.
+//   keys (cell -> Morton rank) -> per-cell counts (atomics) -> exclusive scan (each
+//   tile of 1024 cells in place, the tile totals by every workgroup of the scatter)
+//   -> scatter -> per-cell order by caller index (makes the order a pure function of
+//   the positions), fused with the move of the state into the new order.
+// The Verlet list of molecule pairs is built cell by cell: a wavefront takes a cell's
+// molecules as homes and the molecules of the 27 cells around it (fewer when a
+// dimension has < 3 cells) as candidates, and keeps those whose minimum-image centre
+// distance is strictly below r_list.  The list is stored row-major (ELL):
+// nbr[slot * cap + k]; every row is padded with the row's own slot up to a multiple
+// of 4.  The tile halos and the dispatch order of the force kernel's tiles are built
+// from it at the end of this file.
 #include <algorithm>
 #include <climits>
 
