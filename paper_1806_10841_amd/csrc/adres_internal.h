@@ -111,6 +111,11 @@ struct DevParams {
     // single-site molecules)
     double rho_max, rho_lim;
     double half_skin, half_skin2;
+    // With force interpolation (Eq. 1) a pair with a zero-weight partner interacts only
+    // through the CG cutoff, whatever the partner's motion budget: a molecule of weight zero
+    // at the step its motion is checked may move (r_list - r_c,CG)/2 (squared here; equal to
+    // half_skin2 where that is not larger: other schemes, regions or cutoffs)
+    double cg_budget2;
     // cubic CG table
     const float4 *tab;
     int tab_n;

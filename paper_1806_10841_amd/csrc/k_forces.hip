@@ -632,7 +632,16 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
             const double q0 = mi(R0 - rr.x, P.box[0], P.inv_box[0]);
             const double q1 = mi(R1 - rr.y, P.box[1], P.inv_box[1]);
             const double q2 = mi(R2 - rr.z, P.box[2], P.inv_box[2]);
-            if (list_stale(P, dist2_exact(q0, q1, q2), SPM > 1 ? rh : 0.0)) atomicMin(&a.ctrl->halt, a.step);
+            const double d2 = dist2_exact(q0, q1, q2);
+            bool stale = list_stale(P, d2, SPM > 1 ? rh : 0.0);
+            // (rare) a molecule that the next evaluation gives weight zero (its distance from
+            // the AT region past the hybrid layer's end, with a margin far above the last
+            // bits) has the CG cutoff's budget instead, which is at least the skin's
+            if (stale && P.cg_budget2 > P.half_skin2) {
+                double qd[3];
+                if (res_distance(P, R, qd) > P.d_end + 1e-9) stale = d2 > P.cg_budget2;
+            }
+            if (stale) atomicMin(&a.ctrl->halt, a.step);
         }
     }
 
