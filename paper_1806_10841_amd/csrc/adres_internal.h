@@ -111,11 +111,14 @@ struct DevParams {
     // single-site molecules)
     double rho_max, rho_lim;
     double half_skin, half_skin2;
-    // With force interpolation (Eq. 1) a pair with a zero-weight partner interacts only
-    // through the CG cutoff, whatever the partner's motion budget: a molecule of weight zero
-    // at the step its motion is checked may move (r_list - r_c,CG)/2 (squared here; equal to
-    // half_skin2 where that is not larger: other schemes, regions or cutoffs)
-    double cg_budget2;
+    // How far a molecule's centre may move from where the list was built (list_stale): a pair
+    // stays listed while neither molecule exceeds its budget.  cg_half = (r_list - r_c,CG)/2
+    // keeps the CG cutoff between centres covered; at_half = rho_max + r_skin/2, less the
+    // molecule's current extent, keeps its atom pairs covered (each is 1e300 where the model
+    // has no such part).  With force interpolation and a static region (w0_cg) a molecule of
+    // weight zero at the step being checked has no atom pairs and takes cg_half alone.
+    double cg_half, at_half;
+    int w0_cg;
     // cubic CG table
     const float4 *tab;
     int tab_n;
@@ -453,13 +456,16 @@ __device__ __forceinline__ void close_kick(double v[3], const double F[3], doubl
 
 // Whether a molecule's list entries may no longer hold every pair in reach: its centre
 // lies sqrt(d2) from where the list was built and its farthest site rh from its centre.
-// The list covers rho_max per site plus r_skin/2 per molecule of motion; a site beyond
-// rho_max takes its excess out of the motion budget.
+// An unlisted pair started at least r_list apart, so its centres are now at least r_list
+// minus the two displacements apart, and its sites that less the two extents: the CG part
+// is out of reach while each displacement is within cg_half, the atom pairs while each
+// displacement plus extent is within at_half (r_list >= r_c,AT + 2 rho_max + r_skin).  A
+// compact molecule (extent below rho_max) thus moves further than r_skin/2, one with a
+// site beyond rho_max less far.
 __device__ __forceinline__ bool list_stale(const DevParams &P, double d2, double rh)
 {
-    const double ex = rh - P.rho_max;
-    if (!(ex > 0.0)) return d2 > P.half_skin2;
-    return sqrt(d2) + ex > P.half_skin;
+    const double b = fmin(P.cg_half, P.at_half - rh);
+    return !(b >= 0.0) || d2 > b * b;
 }
 
 // Centre and weight of a molecule at slot t into Rw, with the stretch / non-finite

@@ -636,10 +636,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_forces(ForceArgs a)
             bool stale = list_stale(P, d2, SPM > 1 ? rh : 0.0);
             // (rare) a molecule that the next evaluation gives weight zero (its distance from
             // the AT region past the hybrid layer's end, with a margin far above the last
-            // bits) has the CG cutoff's budget instead, which is at least the skin's
-            if (stale && P.cg_budget2 > P.half_skin2) {
+            // bits) has the CG cutoff's budget alone, which is at least list_stale's
+            if (stale && P.w0_cg) {
                 double qd[3];
-                if (res_distance(P, R, qd) > P.d_end + 1e-9) stale = d2 > P.cg_budget2;
+                if (res_distance(P, R, qd) > P.d_end + 1e-9) stale = d2 > P.cg_half * P.cg_half;
             }
             if (stale) atomicMin(&a.ctrl->halt, a.step);
         }
