@@ -97,11 +97,16 @@ typedef struct {
     double  k_bond, r0_bond;    /* harmonic: K, b0;  FENE: k, R0 */
     int32_t chain_len;          /* FENE: beads per chain (runs of consecutive molecules) */
     double  r_skin;             /* Verlet skin; the list is rebuilt when a centre of mass
-                                   has moved more than r_skin/2 since the last build */
+                                   has moved further than its budget since the last build:
+                                   min((r_list - rc_cg)/2, rho_max + r_skin/2 - the
+                                   molecule's current extent; in the step loop the CG
+                                   part alone for a molecule of weight zero with force
+                                   interpolation and a static region), at least r_skin/2
+                                   for a molecule within rho_max */
     double  rho_max;            /* bound on a site's distance from its centre of mass that
                                    the list radius assumes; a site farther out (thermal
                                    bond stretch) spends its excess from the molecule's
-                                   r_skin/2 of motion, so the list is rebuilt earlier;
+                                   motion budget, so the list is rebuilt earlier;
                                    beyond rho_max + r_skin/2: ADRES_E_STRETCH */
     int32_t pair_precision;     /* 64: FP64 pair arithmetic; 32: FP32 pair arithmetic on
                                    FP64-formed displacements, FP64 sums */
@@ -154,7 +159,7 @@ adres_status adres_build_verlet(adres_ctx *ctx, const double *x, int64_t *n_pair
  * fraction.  energy (device [4], optional): U_AT (ww-weighted), U_CG ((1 - ww)-weighted,
  * analytic CG only), U_bond, U_corr (the correction force's potential, see
  * adres_set_tdforce; 0 without one).  Builds the lists if none exist and rebuilds them if a
- * centre of mass moved more than r_skin/2 since the last build; to decide, it
+ * centre of mass moved further than its budget (see r_skin) since the last build; to decide, it
  * synchronises once before the force kernel is enqueued. */
 adres_status adres_forces(adres_ctx *ctx, const double *x, double *f, double *energy);
 
@@ -170,7 +175,8 @@ adres_status adres_forces_noalloc(adres_ctx *ctx, const double *x, double *f, do
 
 /* n_steps of velocity Verlet (v += F dt/2m; x += v dt; fold; F = F(x); v += F dt/2m)
  * on x, v (device, caller order, updated in place); f receives F(x_final).  The lists
- * are rebuilt whenever a centre of mass has moved more than r_skin/2.  gamma > 0 adds a
+ * are rebuilt whenever a centre of mass has moved further than its budget (see r_skin).
+ * gamma > 0 adds a
  * Langevin thermostat at temperature kT with counter-based normal deviates keyed by
  * (seed, step, site); gamma = 0 is plain NVE.  n_rebuilds (host, optional) receives
  * the number of list rebuilds.  Synchronises at every rebuild and at the end. */
