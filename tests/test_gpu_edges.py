@@ -137,6 +137,76 @@ def test_site_beyond_the_skin_budget_refused(dev):
     assert ei.value.status == -6
 
 
+# ------------------------------------------------------------ the list's motion budget
+def _approaching_pair(kind):
+    """Two unit-edge tetrahedra whose centres start 0.02 beyond r_list on a line (the first
+    list does not hold the pair) and move head-on at 2 sigma/tau each, so that they come into
+    reach one step after each has moved as far as its motion budget allows:
+    'atom': all-atomistic, a vertex of each pointing at the other; the atom pair is in reach
+    once the vertices are rc_at apart, and each molecule may move rho_max + r_skin/2 minus
+    its extent (0.338 sigma for the undistorted tetrahedron, more than r_skin/2);
+    'cg': force interpolation, the pair far outside a slab AT region (weight zero); the CG
+    force is in reach once the centres are rc_cg apart, and each may move
+    (r_list - rc_cg)/2 (0.215 sigma)."""
+    r = np.sqrt(3.0 / 8.0)                  # circumradius of the unit-edge tetrahedron
+    p = r * np.sqrt(8.0 / 9.0)
+    body = np.array([[r, 0.0, 0.0]] + [[-r / 3.0, p * np.cos(a), p * np.sin(a)]
+                                        for a in (0.0, 2 * np.pi / 3, 4 * np.pi / 3)])
+    if kind == "atom":
+        wl = inputs.Workload(name="approaching_atoms", n_mol=2, sites_per_mol=4, box=(12.0, 12.0, 12.0),
+                             site_mass=(1.0, 1.0, 1.0, 1.0), region=inputs.REGION_ALL_AT,
+                             center=(6.0, 6.0, 6.0), d_at=2.0, d_hy=3.0)
+        r_list = wl.rc_at + 2.0 * wl.rho_max + wl.r_skin
+        axis = 0
+        first = wl.rho_max + wl.r_skin / 2 - r        # a molecule's budget
+        reach = wl.rc_at + 2.0 * r                     # centre distance of the first atom pair
+    else:
+        wl = inputs.Workload(name="approaching_cg", n_mol=2, sites_per_mol=4, box=(12.0, 12.0, 12.0),
+                             site_mass=(1.0, 1.0, 1.0, 1.0), region=inputs.REGION_SLAB_X,
+                             center=(0.0, 6.0, 6.0), d_at=1.0, d_hy=1.0)
+        r_list = max(wl.rc_cg, wl.rc_at + 2.0 * wl.rho_max) + wl.r_skin
+        axis = 1
+        first = (r_list - wl.rc_cg) / 2
+        reach = wl.rc_cg
+    D = r_list + 0.02
+    a = body.copy()
+    b = -body
+    a[:, axis], a[:, 0] = body[:, 0].copy(), body[:, axis].copy()
+    b[:, axis], b[:, 0] = -body[:, 0].copy(), -body[:, axis].copy()
+    off = np.zeros(3)
+    off[axis] = D
+    sites = np.concatenate([a, b + off]) + np.array([6.0, 6.0, 6.0]) - off / 2
+    vel = np.zeros_like(sites)
+    vel[:4, axis] = 2.0
+    vel[4:, axis] = -2.0
+    return wl, np.ascontiguousarray(sites.T), np.ascontiguousarray(vel.T), D, first, reach
+
+
+@pytest.mark.parametrize("kind", ["atom", "cg"])
+def test_motion_budget_rebuilds_before_reach(dev, kind):
+    """A molecule may move further than r_skin/2 when it is compact (atom pairs) or of weight
+    zero (CG force only); the pair below comes into reach one step after the budget runs out,
+    so an FP64 trajectory through the contact matches the oracle's (which builds no list) only
+    if the step loop rebuilt the list in time."""
+    wl, x, v, D, first, reach = _approaching_pair(kind)
+    step = 2.0 * wl.dt                               # each centre's motion per step
+    k_budget = int(np.floor(first / step)) + 1       # first step past the budget
+    k_reach = int(np.floor((D - reach) / (2 * step))) + 1   # first step in reach
+    assert first > wl.r_skin / 2 and k_reach == k_budget + 1, (first, k_budget, k_reach)
+    n = k_reach + 15
+    m = oracle.Model(wl)
+    xo, vo, fo, _, st = m.vv(x, v, wl.dt, n)
+    assert st == 0
+    assert np.abs(vo - v).max() > 1e-3              # the pair did interact
+    xt, vt = _t(x, dev), _t(v, dev)
+    ft = torch.empty_like(xt)
+    nreb = _ctx(wl).integrate(xt, vt, ft, wl.dt, n)
+    torch.cuda.synchronize()
+    assert nreb >= 1
+    assert np.abs(_min_image(xt.cpu().numpy() - xo, wl.box[0])).max() < 1e-9
+    assert np.abs(vt.cpu().numpy() - vo).max() < 1e-7
+
+
 @pytest.mark.parametrize("prec", [64, 32])
 def test_rows_longer_than_64_entries(dev, prec):
     """A 3-sigma skin on the CG melt gives every molecule 70-91 listed neighbours: the list
