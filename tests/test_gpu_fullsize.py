@@ -97,6 +97,37 @@ def test_c2_integrate_matches_oracle_vv(dev):
     _newton3(ft.cpu().numpy())
 
 
+@pytest.mark.parametrize("n", [61, 97])
+def test_c2_forces_from_a_list_in_use(dev, n):
+    """The closing forces F(x_n) of an n-step run come from the list of its last rebuild,
+    after the molecules have moved up to their motion budgets since (more than r_skin/2 for
+    compact molecules and for those of weight zero): sampled AT, HY and CG molecules and the
+    molecules that moved furthest, within 1e-5 A_i of the oracle's forces at the same
+    positions (the oracle builds no list)."""
+    wl = inputs.workload("c2")
+    x, v = inputs.make_state(wl)
+    ctx = _ctx(wl)
+    xt, vt = _t(x, dev), _t(v, dev)
+    ft = torch.empty_like(xt)
+    nreb = ctx.integrate(xt, vt, ft, wl.dt, n)
+    torch.cuda.synchronize()
+    assert nreb >= 2
+    xn = xt.cpu().numpy()
+    m = oracle.Model(wl)
+    com_o, w_o, _, st = m.weights(xn)
+    assert st == 0
+    com_0, _, _, _ = m.weights(x)
+    moved = com_o - com_0
+    moved -= np.asarray(wl.box)[:, None] * np.round(moved / np.asarray(wl.box)[:, None])
+    far = np.argsort(np.linalg.norm(moved, axis=0))[-60:]
+    sel = np.unique(np.concatenate([_sample_by_class(w_o, 80, n), far]))
+    fo, amag, st = m.forces_sampled(xn, sel)
+    assert st == 0
+    fg = _sampled_forces(ft.cpu().numpy(), sel, 4)
+    _, amag_nb, _ = nonbonded_model(wl).forces_sampled(xn, sel)
+    assert_fp32_sites(fg, fo, amag, amag_nb, 1e-5, f"c2 after {n} steps", axis=1)
+
+
 def test_c3_kremer_grest_full_size(dev):
     """200,000 beads in FENE chains of 200: sampled neighbour sets bit-exact, sampled forces
     (WCA + FENE) within 1e-5 A_i, Newton's third law; 20 NVE steps conserve momentum and a
