@@ -652,7 +652,6 @@ adres_status adres_create(const adres_params *p, void *hip_stream, adres_ctx **o
     P.rho_max = q.rho_max;
     P.rho_lim = q.sites_per_mol > 1 ? q.rho_max + 0.5 * q.r_skin : 0.0;   // (a single site is its centre)
     P.half_skin = 0.5 * q.r_skin;
-    P.half_skin2 = 0.25 * q.r_skin * q.r_skin;
     P.cg_half = q.region != ADRES_REGION_ALL_AT ? 0.5 * (c->r_list - q.rc_cg) : 1e300;
     P.at_half = q.region != ADRES_REGION_ALL_CG ? q.rho_max + P.half_skin : 1e300;
     P.w0_cg = q.scheme == ADRES_SCHEME_FORCE && (q.region == ADRES_REGION_SLAB_X || q.region == ADRES_REGION_SPHERE);

@@ -41,9 +41,10 @@ static_assert(offsetof(Ctrl, fix) == offsetof(Ctrl, go) + sizeof(int), "fix foll
 
 // Copy of the control block in host-mapped pinned memory, published after the work it
 // reports on (by a one-thread kernel, or by the first kernel of a rebuild: ChainHead); the
-// host polls it instead of synchronising the stream.  Each word holds the publication's sequence number (high half) with one field
-// (low half) and is written with one 8-byte store, so that the host takes the fields once
-// every word carries the sequence number it waits for: no fence orders the stores.
+// host polls it instead of synchronising the stream.  Each word holds the publication's
+// sequence number (high half) with one field (low half) and is written with one 8-byte
+// store, so that the host takes the fields once every word carries the sequence number it
+// waits for: no fence orders the stores.
 enum CtrlPubField : int { kPubHalt, kPubErr, kPubOverflow, kPubMaxCount, kPubMaxHalo, kPubFields };
 struct CtrlPub {
     unsigned long long w[8];
@@ -105,12 +106,12 @@ struct DevParams {
     int scheme;      // ADRES_SCHEME_*
     double k_bond, r0_bond, R02;
     int chain_len;
-    // the list reach assumes every site within rho_max of its centre and leaves r_skin/2 per
-    // molecule for motion; a site farther out spends the same budget (list_stale), up to
-    // rho_lim = rho_max + r_skin/2, the largest distance any list can cover (0 for
-    // single-site molecules)
+    // the list reach assumes every site within rho_max of its centre and leaves at least
+    // r_skin/2 per molecule for motion; a site farther out spends part of that budget
+    // (list_stale), up to rho_lim = rho_max + r_skin/2, the largest distance any list can
+    // cover (0 for single-site molecules)
     double rho_max, rho_lim;
-    double half_skin, half_skin2;
+    double half_skin;
     // How far a molecule's centre may move from where the list was built (list_stale): a pair
     // stays listed while neither molecule exceeds its budget.  cg_half = (r_list - r_c,CG)/2
     // keeps the CG cutoff between centres covered; at_half = rho_max + r_skin/2, less the
